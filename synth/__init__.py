@@ -1,0 +1,339 @@
+"""Seeded synthetic inputs for the OMPDart data-flow solve.
+
+This package only produces inputs (structured CFGs with host/device blocks,
+read/write bitmaps, call graphs, request arrival times) and the plain
+container that carries them.  It holds none of the analysis arithmetic: the
+oracle and the GPU library both consume what it returns.
+
+Workload recipes (all seeded from ``MASTER_SEED``):
+
+* ``c1``  one procedure, 64 user blocks, loop depth <= 3, 30 % device blocks,
+  32 variables, read p=0.2, write p=0.1.
+* ``c2``  one procedure, 16,384 user blocks, loop depth <= 6, 40 % device
+  blocks, 1 % of loops made irreducible, 2,048 variables, p=0.05 / 0.02.
+* ``c3``  4,096 procedures, user blocks log-uniform in [16, 8192], variables
+  log-uniform in [32, 4096], otherwise as ``c1``.
+* ``c4``  a program of 2,000 procedures (see ``program``).
+* ``c5``  a Poisson stream of ``c2``-shaped requests (see ``poisson_arrivals``).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+import threading
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gen.c")
+_SO = os.path.join(_HERE, "libsynth.so")
+
+MASTER_SEED = 240613881
+MASK64 = (1 << 64) - 1
+
+KIND_NORMAL, KIND_BACK, KIND_LOOP_ENTRY = 0, 1, 2
+HOST, DEVICE = 0, 1
+
+
+def build() -> str:
+    """Compile the generator with gcc (always recompiles)."""
+    tmp = _SO + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _SO)
+    return _SO
+
+
+_lib_lock = threading.Lock()
+_lib_handle = None
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("n_user", ctypes.c_int32),
+        ("n_vars", ctypes.c_int32),
+        ("max_loop_depth", ctypes.c_int32),
+        ("n_call_sites", ctypes.c_int32),
+        ("device_frac", ctypes.c_double),
+        ("irr_loop_frac", ctypes.c_double),
+        ("thr_read", ctypes.c_uint32),
+        ("thr_write", ctypes.c_uint32),
+    ]
+
+
+def _lib():
+    global _lib_handle
+    with _lib_lock:
+        if _lib_handle is None:
+            if not os.path.exists(_SO):
+                build()
+            lib = ctypes.CDLL(_SO)
+            lib.synth_splitmix64.restype = ctypes.c_uint64
+            lib.synth_splitmix64.argtypes = [ctypes.c_uint64]
+            lib.synth_log_uniform_int.restype = ctypes.c_int64
+            lib.synth_log_uniform_int.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64]
+            lib.synth_cfg_edges.restype = ctypes.c_int64
+            lib.synth_cfg_edges.argtypes = [ctypes.c_uint64, ctypes.POINTER(_Params)]
+            vp = ctypes.c_void_p
+            lib.synth_cfg_fill.restype = ctypes.c_int
+            lib.synth_cfg_fill.argtypes = [ctypes.c_uint64, ctypes.POINTER(_Params), vp, vp, vp, vp, vp, vp, vp, vp]
+            _lib_handle = lib
+        return _lib_handle
+
+
+def splitmix64(x: int) -> int:
+    return int(_lib().synth_splitmix64(ctypes.c_uint64(x & MASK64)))
+
+
+def config_seed(k: int) -> int:
+    return splitmix64(MASTER_SEED ^ k)
+
+
+def item_seed(k: int, i: int) -> int:
+    return splitmix64((config_seed(k) + i) & MASK64)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def words(n_vars: int) -> int:
+    return (n_vars + 63) // 64
+
+
+def var_mask(n_vars: int) -> np.ndarray:
+    """[words] mask of the valid variable bits."""
+    wd = words(n_vars)
+    m = np.full(wd, np.uint64(MASK64), dtype=np.uint64)
+    if n_vars % 64 and wd:
+        m[-1] = np.uint64((1 << (n_vars % 64)) - 1)
+    return m
+
+
+@dataclass
+class CFG:
+    """One procedure: successor CSR, edge kinds, block spaces and R/W bitmaps.
+
+    ``n_blocks`` includes the access-free HOST blocks ``entry`` and ``exit``.
+    Bit v of word (v >> 6) of row b of ``R``/``W`` is the access of
+    variable v in block b.  Boundary vectors left ``None`` take the defaults:
+    everything valid on the host and nothing on the device at ENTRY, and
+    every variable live on the host (none on the device) after EXIT.
+    """
+
+    n_blocks: int
+    n_vars: int
+    succ_ptr: np.ndarray
+    succ_idx: np.ndarray
+    edge_kind: np.ndarray
+    space: np.ndarray
+    R: np.ndarray
+    W: np.ndarray
+    entry: int = 0
+    exit: int = -1
+    entry_valid_h: Optional[np.ndarray] = None
+    entry_valid_d: Optional[np.ndarray] = None
+    exit_live_h: Optional[np.ndarray] = None
+    exit_live_d: Optional[np.ndarray] = None
+    loop_depth: Optional[np.ndarray] = None
+    call_blocks: Optional[np.ndarray] = None
+    seed: Optional[int] = None
+
+    def __post_init__(self):
+        if self.exit < 0:
+            self.exit = self.n_blocks - 1
+
+    @property
+    def n_edges(self) -> int:
+        return int(self.succ_idx.shape[0])
+
+    @property
+    def wd(self) -> int:
+        return words(self.n_vars)
+
+    @property
+    def facts(self) -> int:
+        return (self.n_blocks - 2) * self.n_vars
+
+    def boundary(self) -> Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+        """(entry_valid_h, entry_valid_d, exit_live_h, exit_live_d) with defaults filled."""
+        m = var_mask(self.n_vars)
+        z = np.zeros(self.wd, dtype=np.uint64)
+        evh = m.copy() if self.entry_valid_h is None else np.ascontiguousarray(self.entry_valid_h, dtype=np.uint64)
+        evd = z.copy() if self.entry_valid_d is None else np.ascontiguousarray(self.entry_valid_d, dtype=np.uint64)
+        lxh = m.copy() if self.exit_live_h is None else np.ascontiguousarray(self.exit_live_h, dtype=np.uint64)
+        lxd = z.copy() if self.exit_live_d is None else np.ascontiguousarray(self.exit_live_d, dtype=np.uint64)
+        return evh, evd, lxh, lxd
+
+    def preds(self) -> List[List[Tuple[int, int]]]:
+        """Per block: list of (pred block, successor-CSR edge id)."""
+        out: List[List[Tuple[int, int]]] = [[] for _ in range(self.n_blocks)]
+        for p in range(self.n_blocks):
+            for e in range(int(self.succ_ptr[p]), int(self.succ_ptr[p + 1])):
+                out[int(self.succ_idx[e])].append((p, e))
+        return out
+
+
+def make_cfg(seed: int, n_user: int, n_vars: int, max_loop_depth: int, device_frac: float,
+             irr_loop_frac: float = 0.0, p_read: float = 0.2, p_write: float = 0.1,
+             n_call_sites: int = 0, with_bits: bool = True) -> CFG:
+    """Generate one structured CFG (deterministic in every argument)."""
+    p = _Params(n_user, n_vars, max_loop_depth, n_call_sites, device_frac, irr_loop_frac,
+                int(round(p_read * 65536)), int(round(p_write * 65536)))
+    lib = _lib()
+    ne = int(lib.synth_cfg_edges(ctypes.c_uint64(seed & MASK64), ctypes.byref(p)))
+    if ne < 0:
+        raise ValueError("bad generator parameters")
+    nb = n_user + 2
+    wd = words(n_vars)
+    succ_ptr = np.zeros(nb + 1, dtype=np.int32)
+    succ_idx = np.zeros(max(ne, 1), dtype=np.int32)[:ne]
+    kind = np.zeros(max(ne, 1), dtype=np.uint8)[:ne]
+    space = np.zeros(nb, dtype=np.uint8)
+    ldepth = np.zeros(nb, dtype=np.int32)
+    R = np.zeros((nb, wd), dtype=np.uint64)
+    W = np.zeros((nb, wd), dtype=np.uint64)
+    calls = np.zeros(max(n_call_sites, 1), dtype=np.int32)
+    nc = lib.synth_cfg_fill(ctypes.c_uint64(seed & MASK64), ctypes.byref(p), _ptr(succ_ptr), _ptr(succ_idx),
+                            _ptr(kind), _ptr(space), _ptr(R) if with_bits else None,
+                            _ptr(W) if with_bits else None, _ptr(ldepth), _ptr(calls))
+    if nc < 0:
+        raise ValueError("generator failed")
+    return CFG(n_blocks=nb, n_vars=n_vars, succ_ptr=succ_ptr, succ_idx=succ_idx, edge_kind=kind,
+               space=space, R=R, W=W, loop_depth=ldepth, call_blocks=calls[:nc].copy(), seed=seed)
+
+
+# --------------------------------------------------------------------------
+# the five workloads
+# --------------------------------------------------------------------------
+C1 = dict(n_user=64, n_vars=32, max_loop_depth=3, device_frac=0.30, irr_loop_frac=0.0, p_read=0.2, p_write=0.1)
+C2 = dict(n_user=16384, n_vars=2048, max_loop_depth=6, device_frac=0.40, irr_loop_frac=0.01,
+          p_read=0.05, p_write=0.02)
+C3_BLOCKS = (16, 8192)
+C3_VARS = (32, 4096)
+C3_COUNT = 4096
+
+
+def c1(i: int = 0) -> CFG:
+    """Config 1 (i = 0 is the benchmark instance; others feed the parity sweep)."""
+    return make_cfg(item_seed(1, i), **C1)
+
+
+def c2(i: int = 0) -> CFG:
+    return make_cfg(item_seed(2, i), **C2)
+
+
+def c3_sizes(n: int = C3_COUNT) -> Tuple[np.ndarray, np.ndarray]:
+    """(user blocks, variables) of the first n items of config 3."""
+    lib = _lib()
+    nu = np.zeros(n, dtype=np.int64)
+    nv = np.zeros(n, dtype=np.int64)
+    for i in range(n):
+        s = item_seed(3, i)
+        nu[i] = lib.synth_log_uniform_int(ctypes.c_uint64(splitmix64(s ^ 0xB10C5)), C3_BLOCKS[0], C3_BLOCKS[1])
+        nv[i] = lib.synth_log_uniform_int(ctypes.c_uint64(splitmix64(s ^ 0x7A125)), C3_VARS[0], C3_VARS[1])
+    return nu, nv
+
+
+def c3_item(i: int, n_user: Optional[int] = None, n_vars: Optional[int] = None) -> CFG:
+    if n_user is None or n_vars is None:
+        nu, nv = c3_sizes(i + 1)
+        n_user, n_vars = int(nu[i]), int(nv[i])
+    prm = dict(C1)
+    prm.update(n_user=int(n_user), n_vars=int(n_vars))
+    return make_cfg(item_seed(3, i), **prm)
+
+
+def c3(n: int = C3_COUNT, threads: int = 0, indices: Optional[Sequence[int]] = None) -> List[CFG]:
+    """Items of config 3, generated in parallel threads (the C code releases the GIL)."""
+    nu, nv = c3_sizes(n if indices is None else max(indices) + 1)
+    idx = list(range(n)) if indices is None else list(indices)
+    threads = threads or min(16, os.cpu_count() or 4)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lambda i: c3_item(i, int(nu[i]), int(nv[i])), idx))
+
+
+def c5_request(i: int) -> CFG:
+    """Request i of the serving stream: a config-2-shaped CFG with its own seed."""
+    return make_cfg(item_seed(5, i), **C2)
+
+
+def poisson_arrivals(rate_per_s: float, n: int, seed: int) -> np.ndarray:
+    """Arrival times (s) of a Poisson stream of n requests at the given rate."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, size=n))
+
+
+def from_edges(blocks: Sequence[Tuple[int, Sequence[int], Sequence[int]]],
+               edges: Sequence[Tuple[int, int, int]], n_vars: int) -> Tuple[CFG, np.ndarray]:
+    """Hand-built CFG.
+
+    ``blocks``: per block (space, read vars, written vars); block 0 is ENTRY and
+    the last block is EXIT.  ``edges``: (src, dst, kind) in any order.
+    Returns the CFG and, for each input edge, its id in successor-CSR order
+    (edges are grouped by source, keeping the given order within a source).
+    """
+    nb = len(blocks)
+    wd = words(n_vars)
+    order = sorted(range(len(edges)), key=lambda k: (edges[k][0], k))
+    csr_pos = np.zeros(len(edges), dtype=np.int64)
+    succ_idx = np.zeros(len(edges), dtype=np.int32)
+    kind = np.zeros(len(edges), dtype=np.uint8)
+    ptr = np.zeros(nb + 1, dtype=np.int32)
+    for pos, k in enumerate(order):
+        s, d, kd = edges[k]
+        csr_pos[k] = pos
+        succ_idx[pos] = d
+        kind[pos] = kd
+        ptr[s + 1] += 1
+    ptr = np.cumsum(ptr).astype(np.int32)
+    space = np.array([b[0] for b in blocks], dtype=np.uint8)
+    R = np.zeros((nb, wd), dtype=np.uint64)
+    W = np.zeros((nb, wd), dtype=np.uint64)
+    for b, (_, rd, wr) in enumerate(blocks):
+        for v in rd:
+            R[b, v >> 6] |= np.uint64(1 << (v & 63))
+        for v in wr:
+            W[b, v >> 6] |= np.uint64(1 << (v & 63))
+    return CFG(n_blocks=nb, n_vars=n_vars, succ_ptr=ptr, succ_idx=succ_idx, edge_kind=kind,
+               space=space, R=R, W=W), csr_pos
+
+
+def random_dag(seed: int, n_blocks: int, n_vars: int, p_extra: float = 0.3, p_dev: float = 0.4,
+               p_read: float = 0.3, p_write: float = 0.2, p_loop_entry: float = 0.0) -> CFG:
+    """Small random acyclic CFG (unstructured).  Every block has a
+    predecessor of lower id and a successor of higher id, so every block is
+    reachable from ENTRY (0) and reaches EXIT (n_blocks - 1).  Optionally
+    marks random edges LOOP_ENTRY to stress the loop rule of the placement."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nb = n_blocks
+    E = set()
+    for i in range(1, nb - 1):
+        E.add((int(rng.integers(0, i)), i))
+        E.add((i, int(rng.integers(i + 1, nb))))
+    for i in range(0, nb - 1):
+        for j in range(i + 1, nb):
+            if rng.random() < p_extra / max(1, nb - i - 1) * 2:
+                if not (i == 0 and j == nb - 1):
+                    E.add((i, j))
+    if not any(s == 0 for (s, _) in E):
+        E.add((0, nb - 1))
+    edges = []
+    for (s, d) in sorted(E):
+        k = KIND_LOOP_ENTRY if (d != nb - 1 and rng.random() < p_loop_entry) else KIND_NORMAL
+        edges.append((s, d, k))
+    blocks = []
+    for b in range(nb):
+        if b == 0 or b == nb - 1:
+            blocks.append((HOST, [], []))
+            continue
+        sp = DEVICE if rng.random() < p_dev else HOST
+        rd = [v for v in range(n_vars) if rng.random() < p_read]
+        wr = [v for v in range(n_vars) if rng.random() < p_write]
+        blocks.append((sp, rd, wr))
+    cfg, _ = from_edges(blocks, edges, n_vars)
+    return cfg

@@ -1,0 +1,289 @@
+"""Independent checkers that pin the oracle (no code shared with it).
+
+* ``mop_nu`` / ``mop_valid``: meet-over-all-paths by explicit path
+  enumeration on acyclic CFGs.  The data-flow problems are gen/kill, hence
+  distributive, so the fixed point must equal the MOP solution.
+* ``reach_after_dev`` / ``reach_before_dev``: boolean transitive closure.
+* ``simulate_paths``: random walks with per-variable version counters in each
+  memory space; every read must see the latest version and every copy must
+  read from a space that holds it.
+* ``check_invariants``: static safety, completeness and exclusivity.
+
+Variables are handled as Python integers of n_vars bits, so every check is
+written per path, not per word.
+"""
+from __future__ import annotations
+
+from collections import deque
+from typing import Dict, List, Sequence, Tuple
+
+import numpy as np
+
+KIND_LOOP_ENTRY = 2
+
+
+def row_int(row: np.ndarray) -> int:
+    v = 0
+    for w, x in enumerate(row.tolist()):
+        v |= int(x) << (64 * w)
+    return v
+
+
+def int_row(v: int, wd: int) -> np.ndarray:
+    return np.array([(v >> (64 * w)) & ((1 << 64) - 1) for w in range(wd)], dtype=np.uint64)
+
+
+def rows_int(a: np.ndarray) -> List[int]:
+    return [row_int(a[i]) for i in range(a.shape[0])]
+
+
+class View:
+    """Big-int view of a CFG for path-level checks."""
+
+    def __init__(self, cfg):
+        self.cfg = cfg
+        self.nb = cfg.n_blocks
+        self.full = (1 << cfg.n_vars) - 1
+        self.R = rows_int(cfg.R.reshape(cfg.n_blocks, cfg.wd))
+        self.W = rows_int(cfg.W.reshape(cfg.n_blocks, cfg.wd))
+        evh, evd, lxh, lxd = cfg.boundary()
+        self.ev = [row_int(evh), row_int(evd)]
+        self.lx = [row_int(lxh), row_int(lxd)]
+        self.space = [int(x) for x in cfg.space]
+        self.succ: List[List[Tuple[int, int]]] = [[] for _ in range(self.nb)]
+        for p in range(self.nb):
+            for e in range(int(cfg.succ_ptr[p]), int(cfg.succ_ptr[p + 1])):
+                self.succ[p].append((int(cfg.succ_idx[e]), e))
+        self.entry, self.exit = cfg.entry, cfg.exit
+
+    def use(self, s: int, b: int) -> int:
+        if b == self.exit:
+            return self.lx[s]
+        return self.R[b] if self.space[b] == s else 0
+
+    def paths_from(self, b: int) -> List[List[Tuple[int, int]]]:
+        """All paths b -> EXIT as lists of (block, edge taken from it; -1 at EXIT)."""
+        out = []
+
+        def rec(x, acc):
+            if x == self.exit:
+                out.append(acc + [(x, -1)])
+                return
+            for (q, e) in self.succ[x]:
+                rec(q, acc + [(x, e)])
+        rec(b, [])
+        return out
+
+    def paths_to(self, q: int) -> List[List[Tuple[int, int]]]:
+        """All paths ENTRY -> q as lists of (block, edge that entered it; -1 at ENTRY)."""
+        out = []
+
+        def rec(x, acc):
+            if x == q:
+                out.append(acc)
+                return
+            for (y, e) in self.succ[x]:
+                rec(y, acc + [(y, e)])
+        rec(self.entry, [(self.entry, -1)])
+        return out
+
+
+def mop_nu(cfg) -> Tuple[List[int], List[int]]:
+    """Next use per space: some path from b to EXIT reads v in s before any
+    write of v (reads of a block precede its writes), or reaches EXIT without
+    a write while v is live in s after the region."""
+    V = View(cfg)
+    res = [[0] * V.nb, [0] * V.nb]
+    for b in range(V.nb):
+        for path in V.paths_from(b):
+            for s in (0, 1):
+                live, alive = 0, V.full
+                for (x, _) in path:
+                    live |= alive & V.use(s, x)
+                    if x != V.exit:
+                        alive &= ~V.W[x]
+                res[s][b] |= live
+    return res[0], res[1]
+
+
+def mop_valid(cfg, gen_entry: Sequence[List[int]], gen_edge: Sequence[Dict[int, int]]) -> Tuple[List[int], List[int]]:
+    """Must-validity at block entry over every ENTRY->q path.
+
+    Along a path the copy in space s is valid after a write in s, stale after
+    a write in the other space, and made valid by the gens: ``gen_entry[s][b]``
+    just before block b and ``gen_edge[s][e]`` on edge e.  At ENTRY the
+    validity is the boundary.
+    """
+    V = View(cfg)
+    res = [[V.full] * V.nb, [V.full] * V.nb]
+    for q in range(V.nb):
+        for path in V.paths_to(q):
+            for s in (0, 1):
+                val = None
+                for i, (x, e) in enumerate(path):
+                    if i == 0:
+                        val = V.ev[s]
+                    else:
+                        val = val | gen_edge[s].get(e, 0) | gen_entry[s][x]
+                    if x == q:
+                        break
+                    w = V.W[x]
+                    val = (val | w) if V.space[x] == s else (val & ~w)
+                res[s][q] &= val
+    return res[0], res[1]
+
+
+def closure(cfg) -> np.ndarray:
+    """reach[a, b] = b is reachable from a by a path of >= 0 edges."""
+    nb = cfg.n_blocks
+    M = np.eye(nb, dtype=bool)
+    for p in range(nb):
+        for e in range(int(cfg.succ_ptr[p]), int(cfg.succ_ptr[p + 1])):
+            M[p, int(cfg.succ_idx[e])] = True
+    for k in range(nb):
+        M = M | (M[:, k:k + 1] & M[k:k + 1, :])
+    return M
+
+
+def reach_labels(cfg) -> Tuple[np.ndarray, np.ndarray]:
+    M = closure(cfg)
+    dev = np.asarray(cfg.space) == 1
+    after = (M[dev, :].any(axis=0)).astype(np.uint8)
+    before = (M[:, dev].any(axis=1)).astype(np.uint8)
+    return after, before
+
+
+def check_invariants(cfg, res) -> List[str]:
+    """Static checks of a placement (empty list = all hold).
+
+    safety:       a copy into s on p->q needs o valid at the end of p
+                  (after copies placed on p's own entry); a copy before q
+                  needs o valid on every in-edge.
+    completeness: every read (and the liveness after EXIT) is valid.
+    exclusivity:  never a copy into both spaces at one location.
+    """
+    V = View(cfg)
+    nb = V.nb
+    wd = cfg.wd
+    errs = []
+    avf = [rows_int(res["avf_h"]), rows_int(res["avf_d"])]
+    ie = [rows_int(res["ins_entry_h"]), rows_int(res["ins_entry_d"])]
+    ig = [rows_int(res["ins_edge_h"].reshape(-1, wd)) if cfg.n_edges else [],
+          rows_int(res["ins_edge_d"].reshape(-1, wd)) if cfg.n_edges else []]
+
+    def out_valid(s, b):
+        w = V.W[b]
+        return (avf[s][b] | w) if V.space[b] == s else (avf[s][b] & ~w)
+
+    preds = cfg.preds()
+    for p in range(nb):
+        for (q, e) in V.succ[p]:
+            for s in (0, 1):
+                o = 1 - s
+                if ig[s][e] & ~out_valid(o, p):
+                    errs.append("safety edge %d space %d" % (e, s))
+                if ig[0][e] & ig[1][e]:
+                    errs.append("exclusive edge %d" % e)
+    for q in range(nb):
+        for s in (0, 1):
+            o = 1 - s
+            if ie[s][q]:
+                src = V.full
+                for (p, e) in preds[q]:
+                    src &= out_valid(o, p) | ig[o][e]
+                if q == V.entry:
+                    src = V.ev[o]
+                if ie[s][q] & ~src:
+                    errs.append("safety entry %d space %d" % (q, s))
+            if V.use(s, q) & ~avf[s][q]:
+                errs.append("completeness block %d space %d" % (q, s))
+        if ie[0][q] & ie[1][q]:
+            errs.append("exclusive entry %d" % q)
+    return errs
+
+
+def simulate_paths(cfg, res, walks: int, seed: int, cap_factor: int = 50) -> Tuple[List[str], float]:
+    """Random-path soundness check of a placement.
+
+    Each walk picks successors uniformly (loops run a geometric number of
+    times, including zero), is capped at cap_factor * n_blocks steps and
+    then finishes along a shortest path to EXIT.  Versions: a write in x
+    makes ``ver += 1; ver_x = ver``; a copy into s asserts ``ver_o == ver``
+    and sets ``ver_s = ver``; a read in x asserts ``ver_x == ver``; at EXIT
+    the live spaces must hold ``ver``.  Returns (errors, copies per walk).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nb, nv, wd = cfg.n_blocks, cfg.n_vars, cfg.wd
+    V = View(cfg)
+
+    def bits(v: int) -> np.ndarray:
+        return np.array([(v >> i) & 1 for i in range(nv)], dtype=bool)
+
+    R = [bits(x) for x in V.R]
+    Wb = [bits(x) for x in V.W]
+    ie = [[bits(x) for x in rows_int(res["ins_entry_h"])], [bits(x) for x in rows_int(res["ins_entry_d"])]]
+    ig = [[bits(x) for x in rows_int(res["ins_edge_h"].reshape(-1, wd))] if cfg.n_edges else [],
+          [bits(x) for x in rows_int(res["ins_edge_d"].reshape(-1, wd))] if cfg.n_edges else []]
+    ev = [bits(V.ev[0]), bits(V.ev[1])]
+    lx = [bits(V.lx[0]), bits(V.lx[1])]
+    # distance to EXIT for the finishing leg
+    dist = [-1] * nb
+    dist[V.exit] = 0
+    rev: List[List[int]] = [[] for _ in range(nb)]
+    for p in range(nb):
+        for (q, _) in V.succ[p]:
+            rev[q].append(p)
+    dq = deque([V.exit])
+    while dq:
+        q = dq.popleft()
+        for p in rev[q]:
+            if dist[p] < 0:
+                dist[p] = dist[q] + 1
+                dq.append(p)
+    errs: List[str] = []
+    copies = 0
+    for wk in range(walks):
+        ver = np.zeros(nv, dtype=np.int64)
+        vs = [np.where(ev[0], 0, -1).astype(np.int64), np.where(ev[1], 0, -1).astype(np.int64)]
+
+        def copy(mask, s, where):
+            nonlocal copies
+            if not mask.any():
+                return
+            o = 1 - s
+            bad = mask & (vs[o] != ver)
+            if bad.any():
+                errs.append("walk %d: stale copy source into space %d at %s, vars %s" % (wk, s, where, np.nonzero(bad)[0][:4].tolist()))
+            vs[s] = np.where(mask, ver, vs[s])
+            copies += int(mask.sum())
+
+        b = V.entry
+        steps = 0
+        while True:
+            for s in (0, 1):
+                copy(ie[s][b], s, "entry %d" % b)
+            if b == V.exit:
+                for s in (0, 1):
+                    bad = lx[s] & (vs[s] != ver)
+                    if bad.any():
+                        errs.append("walk %d: stale live-out in space %d, vars %s" % (wk, s, np.nonzero(bad)[0][:4].tolist()))
+                break
+            x = V.space[b]
+            bad = R[b] & (vs[x] != ver)
+            if bad.any():
+                errs.append("walk %d: stale read in block %d space %d, vars %s" % (wk, b, x, np.nonzero(bad)[0][:4].tolist()))
+            if Wb[b].any():
+                ver = ver + Wb[b].astype(np.int64)
+                vs[x] = np.where(Wb[b], ver, vs[x])
+            steps += 1
+            succ = V.succ[b]
+            if steps < cap_factor * nb:
+                q, e = succ[int(rng.integers(len(succ)))]
+            else:
+                q, e = min(succ, key=lambda t: dist[t[0]])
+            for s in (0, 1):
+                copy(ig[s][e], s, "edge %d" % e)
+            b = q
+        if len(errs) > 20:
+            break
+    return errs, copies / max(walks, 1)
