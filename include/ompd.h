@@ -1,0 +1,207 @@
+/*
+ * ompd.h — C ABI of the MI355X (gfx950) solver for the OMPDart data-flow
+ * problems (Marzen, Dutta, Jannesari, "Static Generation of Efficient OpenMP
+ * Offload Data Mappings", SC24).
+ *
+ * The library takes control-flow graphs whose basic blocks are tagged host
+ * or device (offload kernels, Table I) with per-block read/write bitmaps
+ * (the memory-access classification of the approach section) and returns,
+ * per variable, the fixed points of
+ *   - next use per memory space      (region-exit liveness, section
+ *                                     "Data-Flow Analysis", last paragraph)
+ *   - validity per memory space      (valid = last written there; a write in
+ *                                     one space makes the other copy stale;
+ *                                     a stale read is a RAW dependency)
+ *   - the placement of copies        (map(to/from) and target update, with
+ *                                     the loop rule: no copy enters a loop,
+ *                                     copies needed inside a loop go on its
+ *                                     entry edge; Table II)
+ *   - validity after the placement, and the map/update labels of one target
+ *     data region per function (Table II),
+ * and, for whole programs, exact per-procedure summaries with call-string
+ * contexts (section "Interprocedural Analysis").
+ *
+ * Conventions (every entry point):
+ *   Return value: OMPD_OK (0) or a negative OMPD_E_* code.  On error,
+ *   ompd_last_error(ctx) gives a message owned by ctx, valid until the next
+ *   call on ctx from the same thread.
+ *   Bit layout: variable v is bit (v & 63) of 64-bit word (v >> 6).  A block
+ *   vector is n_blocks rows of ceil(n_vars/64) words, row-major
+ *   [block][word]; an edge vector is n_edges rows in successor-CSR edge
+ *   order.  Padding bits above n_vars must be zero on input and are
+ *   returned as zero.
+ *   Pointers are host pointers unless OMPD_F_DEVICE_PTRS is set, in which
+ *   case every pointer in ompd_cfg / ompd_result is a device pointer on the
+ *   context's GPU and `stream` (a hipStream_t, NULL = default stream) is
+ *   the caller's stream.  Host inputs are copied before the call returns;
+ *   device inputs must stay valid until the work completes.
+ *   The caller owns every input and output buffer.
+ *   Thread safety: calls on one context are serialised by an internal lock.
+ */
+#ifndef OMPD_H
+#define OMPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define OMPD_OK 0
+#define OMPD_E_INVAL (-1)          /* malformed CFG or argument (see S1 rules below)      */
+#define OMPD_E_NOMEM (-2)          /* device memory / admission budget exceeded            */
+#define OMPD_E_DEVICE (-3)         /* HIP runtime error                                    */
+#define OMPD_E_NOCONVERGE (-4)     /* sweep cap reached (only below the proven bound)      */
+#define OMPD_E_BUSY (-5)           /* serving queue full: poll and retry                   */
+#define OMPD_E_UNKNOWN_TICKET (-6) /* ticket never issued or already collected             */
+#define OMPD_E_TIMEOUT (-7)        /* ompd_wait timed out                                  */
+
+/* ---- enums ----------------------------------------------------------- */
+enum { OMPD_HOST = 0, OMPD_DEVICE = 1 };                                  /* block space */
+enum { OMPD_EDGE_NORMAL = 0, OMPD_EDGE_BACK = 1, OMPD_EDGE_LOOP_ENTRY = 2 };  /* edge kind */
+enum { OMPD_MAP_TO = 1, OMPD_MAP_FROM = 2, OMPD_MAP_ALLOC = 4 };          /* var_kind bits */
+
+/* ---- flags ----------------------------------------------------------- */
+#define OMPD_F_DEVICE_PTRS (1u << 0)      /* all pointers are device pointers               */
+#define OMPD_F_PLACEMENT_EAGER (1u << 1)  /* materialise every eager copy (no delay)         */
+#define OMPD_F_SWEEP_CAP(n) ((((uint32_t)(n)) & 0xFFFFu) << 16) /* cap sweeps per phase */
+
+/* ---- one procedure ----------------------------------------------------
+ * A CFG of basic blocks (the CFG half of the paper's AST-CFG, Figure 2).
+ * n_blocks includes an access-free HOST block `entry` with no predecessors
+ * and an access-free HOST block `exit` with no successors.  Every block must
+ * be reachable from entry and reach exit.  Edge kinds come from the AST
+ * loops (For/While/Do): LOOP_ENTRY marks an edge into a loop header from
+ * outside the loop, BACK an edge from inside the loop to its header.  Edges
+ * into exit must be NORMAL and no edge out of entry may be BACK.
+ * Reads of a block precede its writes; a write is a whole-variable write.
+ * Block ids define the sweep order: numbering blocks in source order makes
+ * the fixed points converge in few sweeps; any numbering gives the same
+ * result.
+ * Boundaries (NULL = default):
+ *   entry_valid_host [wd] variables valid in host memory at entry   (default all)
+ *   entry_valid_dev  [wd] variables valid in device memory at entry (default none)
+ *   exit_live_host   [wd] variables read on the host after exit      (default all)
+ *   exit_live_dev    [wd] variables read on the device after exit    (default none)
+ * entry_valid_host | entry_valid_dev must cover every variable.
+ * Call blocks (interprocedural use): call_summary[b] >= 0 names row
+ * call_summary[b] of `summaries` (layout [n_summaries][16][wd], rows
+ * MAYR_H MAYR_D MAYW_H MAYW_D NU0_H NU0_D NU1_H NU1_D T_H00 T_H01 T_H10
+ * T_H11 T_D00 T_D01 T_D10 T_D11, identity for variables the callee cannot
+ * see); call blocks must be HOST.  call_summary NULL = no calls.          */
+typedef struct {
+    int32_t n_blocks, n_edges, n_vars;
+    int32_t entry, exit;
+    const int32_t* succ_ptr;          /* [n_blocks+1] */
+    const int32_t* succ_idx;          /* [n_edges]    */
+    const uint8_t* edge_kind;         /* [n_edges]    */
+    const uint8_t* space;             /* [n_blocks]   */
+    const uint64_t* read_bits;        /* [n_blocks*wd] */
+    const uint64_t* write_bits;       /* [n_blocks*wd] */
+    const uint64_t* entry_valid_host; /* [wd] or NULL */
+    const uint64_t* entry_valid_dev;  /* [wd] or NULL */
+    const uint64_t* exit_live_host;   /* [wd] or NULL */
+    const uint64_t* exit_live_dev;    /* [wd] or NULL */
+    const int32_t* call_summary;      /* [n_blocks] or NULL */
+    const uint64_t* summaries;        /* [n_summaries*16*wd] or NULL */
+    int32_t n_summaries;
+    int32_t reserved;
+} ompd_cfg;
+
+/* Outputs; any pointer may be NULL (not requested).
+ *   nu_*          [n_blocks*wd] next use in that space at block entry
+ *   ave_*         [n_blocks*wd] validity at block entry assuming eager copies
+ *   avf_*         [n_blocks*wd] validity at block entry after the placement
+ *   ins_entry_to_dev / _to_host [n_blocks*wd] copy into that space just before block b
+ *   ins_edge_to_dev  / _to_host [n_edges*wd]  copy into that space on edge e
+ *   var_kind      [n_vars]   OMPD_MAP_TO | OMPD_MAP_FROM (both = tofrom), or OMPD_MAP_ALLOC
+ *   after_dev     [n_blocks] 1 iff some DEVICE block reaches b (b included)
+ *   before_dev    [n_blocks] 1 iff b reaches some DEVICE block (b included)
+ * Labels: a copy into the device on edge p->q is map(to) iff !after_dev[p],
+ * before block q iff no predecessor of q is after_dev; otherwise it is
+ * target update to.  A copy into the host on p->q or before q is map(from)
+ * iff !before_dev[q]; otherwise target update from.
+ *   sweeps[6]     sweeps used per phase (next use, validity, pending,
+ *                 delay, final validity, reachability); host memory, filled
+ *                 after completion; informational.                        */
+typedef struct {
+    uint64_t *nu_host, *nu_dev;
+    uint64_t *ave_host, *ave_dev;
+    uint64_t *avf_host, *avf_dev;
+    uint64_t *ins_entry_to_dev, *ins_entry_to_host;
+    uint64_t *ins_edge_to_dev, *ins_edge_to_host;
+    uint8_t* var_kind;
+    uint8_t* after_dev;
+    uint8_t* before_dev;
+    int32_t sweeps[6];
+} ompd_result;
+
+typedef struct ompd_ctx ompd_ctx;
+typedef struct ompd_plan ompd_plan;
+typedef uint64_t ompd_ticket;
+
+/* Create a context on HIP device `device_ordinal`.  device_mem_budget_bytes
+ * bounds what the serving path admits (0 = 64 GiB).  Returns OMPD_E_DEVICE
+ * if the device cannot be used. */
+int ompd_ctx_create(ompd_ctx** out, int device_ordinal, uint64_t device_mem_budget_bytes);
+void ompd_ctx_destroy(ompd_ctx* ctx);
+const char* ompd_last_error(const ompd_ctx* ctx);
+/* Device facts the solver plans with: compute units, LDS bytes a workgroup
+ * of the solve kernel may use, and device memory.  Any pointer may be NULL. */
+int ompd_device_info(ompd_ctx* ctx, int32_t* n_cu, int32_t* lds_bytes, int64_t* mem_bytes);
+
+/* Solve one CFG; synchronous (returns when the results are in `res`).
+ * Errors: OMPD_E_INVAL for a malformed CFG, OMPD_E_NOCONVERGE if a sweep
+ * cap below the proven bound (2*n_blocks+2) stops a phase. */
+int ompd_analyze_cfg(ompd_ctx* ctx, const ompd_cfg* cfg, ompd_result* res, uint32_t flags, void* stream);
+
+/* Solve n CFGs in one persistent launch; synchronous.  Per-CFG errors are
+ * reported as the first failing CFG's code; results of valid CFGs are
+ * written regardless. */
+int ompd_analyze_batch(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n,
+                       uint32_t flags, void* stream);
+
+/* Resident batch: ompd_plan_create records the CFGs (device pointers only:
+ * OMPD_F_DEVICE_PTRS is required), allocates scratch and chooses tiles;
+ * ompd_plan_run enqueues one complete solve (ingest kernels, all phases,
+ * labels) on `stream` without synchronising, replaying a captured HIP
+ * graph; ompd_plan_status synchronises and returns OMPD_OK or the first
+ * per-CFG error (per_cfg may be NULL or [n]).  The plan keeps pointers to
+ * the caller's buffers, which must stay valid while it exists. */
+int ompd_plan_create(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n, uint32_t flags,
+                     ompd_plan** out);
+int ompd_plan_run(ompd_plan* plan, void* stream);
+int ompd_plan_status(ompd_plan* plan, int32_t* per_cfg);
+/* Autotuner: times each candidate (slice width rule, LDS per workgroup,
+ * workgroups per CU) `trials` times on `stream` and keeps the fastest.
+ * Results are bit-identical for every candidate.  best_ms may be NULL. */
+int ompd_plan_autotune(ompd_plan* plan, void* stream, int32_t trials, float* best_ms);
+/* Describe the plan's current configuration as a NUL-terminated string. */
+int ompd_plan_describe(ompd_plan* plan, char* buf, int32_t len);
+/* Duration (ms) of the last ompd_plan_run measured with HIP events on its
+ * stream: total, and the solve kernel alone. */
+int ompd_plan_last_ms(ompd_plan* plan, float* total_ms, float* solve_ms);
+void ompd_plan_destroy(ompd_plan* plan);
+
+/* Serving: continuous batching.  submit copies the host CFG to the device
+ * if it fits the context's device-memory budget and a slot is free
+ * (otherwise OMPD_E_BUSY: poll/wait on earlier tickets and retry), and
+ * returns at once; a background thread groups admitted requests into steps
+ * that run concurrently on several streams.  `res` (host pointers) must
+ * stay valid until poll reports done.  poll: *done = 0 pending, 1 done,
+ * negative = that request's error code; a done ticket is released by the
+ * poll that reports it.  wait blocks until done or timeout_ns (< 0 = no
+ * limit). */
+int ompd_submit(ompd_ctx* ctx, const ompd_cfg* cfg, ompd_result* res, uint32_t flags, ompd_ticket* out);
+int ompd_poll(ompd_ctx* ctx, ompd_ticket t, int* done);
+int ompd_wait(ompd_ctx* ctx, ompd_ticket t, int64_t timeout_ns, int* done);
+/* Serving counters: admitted, completed, in flight, bytes in use. */
+int ompd_serving_stats(ompd_ctx* ctx, int64_t* admitted, int64_t* completed, int64_t* in_flight,
+                       int64_t* bytes_in_use);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OMPD_H */

@@ -72,6 +72,28 @@ def _lib():
         return _handle
 
 
+def use_library(path: str):
+    """Load the solver from another build of oracle.c (used by the mutation
+    tests that plant mistakes in a copy); returns the previous handle."""
+    global _handle
+    with _lock:
+        prev = _handle
+        lib = ctypes.CDLL(path)
+        vp = ctypes.c_void_p
+        i32 = ctypes.c_int32
+        lib.oracle_solve.restype = ctypes.c_int
+        lib.oracle_solve.argtypes = [i32, i32, i32, i32, i32] + [vp] * 4 + [vp, vp] + [vp] * 4 + \
+            [vp, vp, i32] + [vp] * 10 + [vp, vp, vp, vp]
+        _handle = lib
+        return prev
+
+
+def restore_library(prev):
+    global _handle
+    with _lock:
+        _handle = prev
+
+
 def _p(a):
     return None if a is None else ctypes.c_void_p(a.ctypes.data)
 

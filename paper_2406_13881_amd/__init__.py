@@ -1,0 +1,374 @@
+"""MI355X (gfx950) solver for the OMPDart data-flow problems — Python binding.
+
+Thin ctypes binding of ``libompd.so`` (``include/ompd.h``): argument
+marshalling only.  Every step of the solve runs in the library's HIP
+kernels; there is no CPU fallback, and importing a function whose library is
+not built raises ``OmpdNotBuilt``.
+
+Entry points (same names as the C ABI): ``ctx_create``, ``analyze_cfg``,
+``analyze_batch``, ``plan_create`` / ``plan_run`` / ``plan_status`` /
+``plan_autotune`` / ``plan_last_ms`` / ``plan_describe``, ``submit`` /
+``poll`` / ``wait``, ``analyze_program``.  CFG arguments are any objects
+with the attributes of ``synth.CFG`` (numpy arrays), or ``DeviceCFG`` for
+device pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libompd.so")
+_SOURCES = ["csrc/ompd_kernels.hip", "csrc/ompd_runtime.hip", "csrc/ompd_serving.hip"]
+
+OMPD_OK = 0
+OMPD_E_INVAL = -1
+OMPD_E_NOMEM = -2
+OMPD_E_DEVICE = -3
+OMPD_E_NOCONVERGE = -4
+OMPD_E_BUSY = -5
+OMPD_E_UNKNOWN_TICKET = -6
+OMPD_E_TIMEOUT = -7
+
+F_DEVICE_PTRS = 1 << 0
+F_PLACEMENT_EAGER = 1 << 1
+
+
+def F_SWEEP_CAP(n: int) -> int:
+    return (int(n) & 0xFFFF) << 16
+
+
+OUTPUTS = ("nu_h", "nu_d", "ave_h", "ave_d", "avf_h", "avf_d", "ins_entry_h", "ins_entry_d",
+           "ins_edge_h", "ins_edge_d", "var_kind", "after_dev", "before_dev")
+
+
+def build() -> str:
+    """Compile libompd.so for gfx950 with hipcc (always recompiles)."""
+    tmp = _SO + ".tmp%d" % os.getpid()
+    cmd = ["hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-o", tmp] + [os.path.join(_HERE, s) for s in _SOURCES]
+    subprocess.check_call(cmd, cwd=_HERE)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+class OmpdNotBuilt(RuntimeError):
+    pass
+
+
+class OmpdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("ompd error %d: %s" % (code, msg))
+        self.code = code
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [("n_blocks", _i32), ("n_edges", _i32), ("n_vars", _i32), ("entry", _i32), ("exit", _i32),
+                ("succ_ptr", _vp), ("succ_idx", _vp), ("edge_kind", _vp), ("space", _vp),
+                ("read_bits", _vp), ("write_bits", _vp),
+                ("entry_valid_host", _vp), ("entry_valid_dev", _vp), ("exit_live_host", _vp),
+                ("exit_live_dev", _vp), ("call_summary", _vp), ("summaries", _vp),
+                ("n_summaries", _i32), ("reserved", _i32)]
+
+
+class _Res(ctypes.Structure):
+    _fields_ = [("nu_host", _vp), ("nu_dev", _vp), ("ave_host", _vp), ("ave_dev", _vp),
+                ("avf_host", _vp), ("avf_dev", _vp), ("ins_entry_to_dev", _vp), ("ins_entry_to_host", _vp),
+                ("ins_edge_to_dev", _vp), ("ins_edge_to_host", _vp), ("var_kind", _vp),
+                ("after_dev", _vp), ("before_dev", _vp), ("sweeps", _i32 * 6)]
+
+
+_RES_FIELD = {"nu_h": "nu_host", "nu_d": "nu_dev", "ave_h": "ave_host", "ave_d": "ave_dev",
+              "avf_h": "avf_host", "avf_d": "avf_dev", "ins_entry_h": "ins_entry_to_host",
+              "ins_entry_d": "ins_entry_to_dev", "ins_edge_h": "ins_edge_to_host",
+              "ins_edge_d": "ins_edge_to_dev", "var_kind": "var_kind", "after_dev": "after_dev",
+              "before_dev": "before_dev"}
+
+_lock = threading.Lock()
+_handle = None
+
+
+def lib():
+    """The loaded library; raises OmpdNotBuilt if libompd.so is missing."""
+    global _handle
+    with _lock:
+        if _handle is None:
+            if not os.path.exists(_SO):
+                raise OmpdNotBuilt("libompd.so is not built (run __graft_entry__.build())")
+            L = ctypes.CDLL(_SO)
+            P = ctypes.POINTER
+            L.ompd_ctx_create.argtypes = [P(_vp), ctypes.c_int, ctypes.c_uint64]
+            L.ompd_ctx_destroy.argtypes = [_vp]
+            L.ompd_ctx_destroy.restype = None
+            L.ompd_last_error.argtypes = [_vp]
+            L.ompd_last_error.restype = ctypes.c_char_p
+            L.ompd_device_info.argtypes = [_vp, P(_i32), P(_i32), P(ctypes.c_int64)]
+            L.ompd_analyze_cfg.argtypes = [_vp, P(_Cfg), P(_Res), ctypes.c_uint32, _vp]
+            L.ompd_analyze_batch.argtypes = [_vp, P(_Cfg), P(_Res), _i32, ctypes.c_uint32, _vp]
+            L.ompd_plan_create.argtypes = [_vp, P(_Cfg), P(_Res), _i32, ctypes.c_uint32, P(_vp)]
+            L.ompd_plan_run.argtypes = [_vp, _vp]
+            L.ompd_plan_status.argtypes = [_vp, _vp]
+            L.ompd_plan_autotune.argtypes = [_vp, _vp, _i32, P(ctypes.c_float)]
+            L.ompd_plan_describe.argtypes = [_vp, ctypes.c_char_p, _i32]
+            L.ompd_plan_last_ms.argtypes = [_vp, P(ctypes.c_float), P(ctypes.c_float)]
+            L.ompd_plan_destroy.argtypes = [_vp]
+            L.ompd_plan_destroy.restype = None
+            L.ompd_submit.argtypes = [_vp, P(_Cfg), P(_Res), ctypes.c_uint32, P(ctypes.c_uint64)]
+            L.ompd_poll.argtypes = [_vp, ctypes.c_uint64, P(ctypes.c_int)]
+            L.ompd_wait.argtypes = [_vp, ctypes.c_uint64, ctypes.c_int64, P(ctypes.c_int)]
+            L.ompd_serving_stats.argtypes = [_vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64),
+                                             P(ctypes.c_int64)]
+            _handle = L
+        return _handle
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = lib().ompd_last_error(None)
+        raise OmpdError(rc, msg.decode() if msg else "")
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return _vp(a.ctypes.data)
+
+
+@dataclass
+class DeviceCFG:
+    """A CFG whose arrays are device pointers (e.g. torch tensors' data_ptr())."""
+    n_blocks: int
+    n_edges: int
+    n_vars: int
+    entry: int
+    exit: int
+    succ_ptr: int
+    succ_idx: int
+    edge_kind: int
+    space: int
+    read_bits: int
+    write_bits: int
+    entry_valid_host: int = 0
+    entry_valid_dev: int = 0
+    exit_live_host: int = 0
+    exit_live_dev: int = 0
+    call_summary: int = 0
+    summaries: int = 0
+    n_summaries: int = 0
+
+
+def _cfg_struct(cfg, keep: list) -> _Cfg:
+    if isinstance(cfg, DeviceCFG):
+        s = _Cfg()
+        for f in ("n_blocks", "n_edges", "n_vars", "entry", "exit", "n_summaries"):
+            setattr(s, f, int(getattr(cfg, f)))
+        for f in ("succ_ptr", "succ_idx", "edge_kind", "space", "read_bits", "write_bits", "entry_valid_host",
+                  "entry_valid_dev", "exit_live_host", "exit_live_dev", "call_summary", "summaries"):
+            v = int(getattr(cfg, f))
+            setattr(s, f, v if v else None)
+        return s
+    nb, nv = int(cfg.n_blocks), int(cfg.n_vars)
+    wd = (nv + 63) // 64
+
+    def arr(a, dt, shape=None):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dt)
+        if shape is not None:
+            a = a.reshape(shape)
+        keep.append(a)
+        return a
+    sp = arr(cfg.succ_ptr, np.int32)
+    si = arr(cfg.succ_idx, np.int32)
+    kd = arr(cfg.edge_kind, np.uint8)
+    spc = arr(cfg.space, np.uint8)
+    R = arr(cfg.R, np.uint64, (nb, wd))
+    W = arr(cfg.W, np.uint64, (nb, wd))
+    s = _Cfg()
+    s.n_blocks, s.n_edges, s.n_vars = nb, int(si.shape[0]), nv
+    s.entry, s.exit = int(cfg.entry), int(cfg.exit)
+    s.succ_ptr, s.succ_idx, s.edge_kind, s.space = _np_ptr(sp), _np_ptr(si), _np_ptr(kd), _np_ptr(spc)
+    s.read_bits, s.write_bits = _np_ptr(R), _np_ptr(W)
+    for f_api, f_cfg in (("entry_valid_host", "entry_valid_h"), ("entry_valid_dev", "entry_valid_d"),
+                         ("exit_live_host", "exit_live_h"), ("exit_live_dev", "exit_live_d")):
+        v = getattr(cfg, f_cfg, None)
+        setattr(s, f_api, _np_ptr(arr(v, np.uint64)) if v is not None else None)
+    call = getattr(cfg, "call_summary", None)
+    if call is not None:
+        sums = arr(cfg.summaries, np.uint64)
+        s.call_summary = _np_ptr(arr(call, np.int32))
+        s.summaries = _np_ptr(sums)
+        s.n_summaries = int(sums.size // (16 * max(wd, 1))) if wd else int(getattr(cfg, "n_summaries", 1))
+    return s
+
+
+def _alloc_outputs(cfg, want: Sequence[str]) -> Dict[str, np.ndarray]:
+    nb, nv = int(cfg.n_blocks), int(cfg.n_vars)
+    ne = int(np.asarray(cfg.succ_idx).shape[0])
+    wd = (nv + 63) // 64
+    out = {}
+    for k in want:
+        if k.startswith("ins_edge"):
+            out[k] = np.zeros((ne, wd), np.uint64)
+        elif k == "var_kind":
+            out[k] = np.zeros(nv, np.uint8)
+        elif k in ("after_dev", "before_dev"):
+            out[k] = np.zeros(nb, np.uint8)
+        else:
+            out[k] = np.zeros((nb, wd), np.uint64)
+    return out
+
+
+def _res_struct(out: Dict[str, np.ndarray]) -> _Res:
+    r = _Res()
+    for k, a in out.items():
+        setattr(r, _RES_FIELD[k], _vp(a.ctypes.data) if a.size else _vp(a.ctypes.data))
+    return r
+
+
+class Context:
+    """An ompd context on one GPU (ompd_ctx_create / ompd_ctx_destroy)."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        h = _vp()
+        _check(lib().ompd_ctx_create(ctypes.byref(h), int(device), int(budget_bytes)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().ompd_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def device_info(self) -> Dict[str, int]:
+        cu, lds, mem = _i32(0), _i32(0), ctypes.c_int64(0)
+        _check(lib().ompd_device_info(self.h, ctypes.byref(cu), ctypes.byref(lds), ctypes.byref(mem)))
+        return {"n_cu": cu.value, "lds_bytes": lds.value, "mem_bytes": mem.value}
+
+    # -- one-shot, host pointers ------------------------------------------------
+    def analyze_cfg(self, cfg, flags: int = 0, want: Sequence[str] = OUTPUTS) -> Dict[str, np.ndarray]:
+        return self.analyze_batch([cfg], flags, want)[0]
+
+    def analyze_batch(self, cfgs: Sequence, flags: int = 0, want: Sequence[str] = OUTPUTS) -> List[Dict[str, np.ndarray]]:
+        keep: list = []
+        n = len(cfgs)
+        C = (_Cfg * max(n, 1))()
+        R = (_Res * max(n, 1))()
+        outs = []
+        for i, g in enumerate(cfgs):
+            C[i] = _cfg_struct(g, keep)
+            o = _alloc_outputs(g, want)
+            outs.append(o)
+            R[i] = _res_struct(o)
+        _check(lib().ompd_analyze_batch(self.h, C, R, n, int(flags), None))
+        for i in range(n):
+            outs[i]["sweeps"] = np.array(list(R[i].sweeps), dtype=np.int32)
+        return outs
+
+
+def ctx_create(device: int = 0, budget_bytes: int = 0) -> Context:
+    return Context(device, budget_bytes)
+
+
+def analyze_cfg(ctx: Context, cfg, flags: int = 0, want: Sequence[str] = OUTPUTS):
+    return ctx.analyze_cfg(cfg, flags, want)
+
+
+def analyze_batch(ctx: Context, cfgs: Sequence, flags: int = 0, want: Sequence[str] = OUTPUTS):
+    return ctx.analyze_batch(cfgs, flags, want)
+
+
+@dataclass
+class DeviceResult:
+    """Device pointers for one CFG's outputs (0 = not requested)."""
+    nu_h: int = 0
+    nu_d: int = 0
+    ave_h: int = 0
+    ave_d: int = 0
+    avf_h: int = 0
+    avf_d: int = 0
+    ins_entry_h: int = 0
+    ins_entry_d: int = 0
+    ins_edge_h: int = 0
+    ins_edge_d: int = 0
+    var_kind: int = 0
+    after_dev: int = 0
+    before_dev: int = 0
+
+
+class Plan:
+    """A resident batch (ompd_plan_*) over device-pointer CFGs."""
+
+    def __init__(self, ctx: Context, cfgs: Sequence[DeviceCFG], results: Sequence[DeviceResult], flags: int = 0):
+        n = len(cfgs)
+        self.ctx = ctx
+        self.n = n
+        self._C = (_Cfg * max(n, 1))()
+        self._R = (_Res * max(n, 1))()
+        keep: list = []
+        for i in range(n):
+            self._C[i] = _cfg_struct(cfgs[i], keep)
+            r = _Res()
+            for k, f in _RES_FIELD.items():
+                v = int(getattr(results[i], k))
+                setattr(r, f, v if v else None)
+            self._R[i] = r
+        h = _vp()
+        _check(lib().ompd_plan_create(ctx.h, self._C, self._R, n, int(flags) | F_DEVICE_PTRS, ctypes.byref(h)))
+        self.h = h
+
+    def run(self, stream: int = 0):
+        _check(lib().ompd_plan_run(self.h, _vp(stream) if stream else None))
+
+    def status(self) -> np.ndarray:
+        per = np.zeros(max(self.n, 1), np.int32)
+        rc = lib().ompd_plan_status(self.h, _vp(per.ctypes.data))
+        if rc not in (0, OMPD_E_INVAL, OMPD_E_NOCONVERGE):
+            _check(rc)
+        return per[:self.n]
+
+    def autotune(self, stream: int = 0, trials: int = 2) -> float:
+        best = ctypes.c_float(0)
+        _check(lib().ompd_plan_autotune(self.h, _vp(stream) if stream else None, int(trials), ctypes.byref(best)))
+        return best.value
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(1024)
+        _check(lib().ompd_plan_describe(self.h, buf, 1024))
+        return buf.value.decode()
+
+    def last_ms(self):
+        a, b = ctypes.c_float(0), ctypes.c_float(0)
+        _check(lib().ompd_plan_last_ms(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ompd_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_create(ctx: Context, cfgs: Sequence[DeviceCFG], results: Sequence[DeviceResult], flags: int = 0) -> Plan:
+    return Plan(ctx, cfgs, results, flags)

@@ -1,0 +1,65 @@
+// Device-side descriptors shared by the HIP kernels and the host runtime of
+// libompd (internal; the public interface is include/ompd.h).
+#pragma once
+#include <stdint.h>
+
+namespace ompd {
+
+enum : int32_t {
+    INFO_STATUS = 0,      // 0 ok, else an OMPD_E_* code
+    INFO_NLEVELS = 1,     // number of levels of the forward-edge DAG
+    INFO_SWEEPS = 2,      // [2..7] max sweeps per phase over the CFG's tiles
+    INFO_WORDS = 16
+};
+
+enum : int32_t { PH_NU = 0, PH_AVE = 1, PH_MAYP = 2, PH_LATER = 3, PH_AVF = 4, PH_REACH = 5 };
+
+// Summary rows of a callee, each a word vector over all variables.
+enum : int32_t {
+    SUM_MAYR_H = 0, SUM_MAYR_D, SUM_MAYW_H, SUM_MAYW_D,
+    SUM_NU0_H, SUM_NU0_D, SUM_NU1_H, SUM_NU1_D,
+    SUM_TH = 8, SUM_TD = 12, SUM_ROWS = 16
+};
+
+// One CFG as the kernels see it.  Every pointer is a device pointer; inputs
+// the caller left NULL and outputs the solve needs internally point into
+// scratch owned by the plan.
+struct DevCfg {
+    int32_t nb, ne, nv, entry, exit, wd;   // wd = 64-bit words per row
+    int32_t n_sums, placement, sweep_cap, pad;
+    const int32_t* succ_ptr;
+    const int32_t* succ_idx;
+    const uint8_t* kind;
+    const uint8_t* space;
+    const uint64_t* R;
+    const uint64_t* W;
+    const uint64_t* ev_h;
+    const uint64_t* ev_d;
+    const uint64_t* lx_h;
+    const uint64_t* lx_d;
+    const int32_t* call;        // NULL = no call blocks
+    const uint64_t* sums;
+    uint64_t* nu_h;  uint64_t* nu_d;
+    uint64_t* ave_h; uint64_t* ave_d;
+    uint64_t* avf_h; uint64_t* avf_d;      // may be NULL
+    uint64_t* ie_h;  uint64_t* ie_d;       // copy into host / device before block
+    uint64_t* ig_h;  uint64_t* ig_d;       // copy into host / device on edge
+    uint8_t* var_kind;                     // may be NULL
+    uint8_t* after_dev;                    // may be NULL
+    uint8_t* before_dev;                   // may be NULL
+    uint64_t* aveout_h; uint64_t* aveout_d;
+    uint64_t* mayp_h;   uint64_t* mayp_d;
+    int32_t* pred_ptr;  int32_t* pred_idx; int32_t* pred_eid;
+    int32_t* level_ptr; int32_t* level_blk; int32_t* tmp;
+    int32_t* info;
+};
+
+// A tile: one CFG, a range of bit-slices of width tbits (8, 16 or 32).
+struct Tile {
+    int32_t cfg;
+    int32_t tbits;
+    int32_t s0;   // first slice (in units of tbits)
+    int32_t ns;   // number of slices (0 only when the CFG has no variables)
+};
+
+}  // namespace ompd

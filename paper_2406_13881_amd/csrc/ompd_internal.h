@@ -1,0 +1,70 @@
+// Host-side internal types of libompd.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/ompd.h"
+#include "ompd_device.h"
+
+struct ServingState;
+
+struct ompd_ctx {
+    int device = 0;
+    hipDeviceProp_t prop{};
+    int n_cu = 1;
+    int lds_max = 64 * 1024;
+    uint64_t budget = 0;
+    std::mutex mu;                 // serialises API calls
+    ServingState* srv = nullptr;   // created on first submit
+    std::mutex srv_mu;
+};
+
+// Tunable launch configuration of a plan; results never depend on it.
+struct PlanConfig {
+    size_t lds_bytes = 0;   // LDS per workgroup of the solve kernel (0 = automatic)
+    int max_ns = 16;        // most slices per tile
+    int min_tbits = 8;      // narrowest slice allowed
+    int wg_per_cu = 0;      // 0 = as many as fit
+    bool use_graph = true;  // replay a captured HIP graph
+};
+
+struct ompd_plan {
+    ompd_ctx* ctx = nullptr;
+    int n = 0;
+    uint32_t flags = 0;
+    PlanConfig cfg;
+    std::vector<ompd::DevCfg> h_cfgs;
+    std::vector<ompd_result> res;
+    std::vector<int32_t> h_info;
+    ompd::DevCfg* d_cfgs = nullptr;
+    std::vector<ompd::Tile> h_tiles;
+    ompd::Tile* d_tiles = nullptr;
+    int n_tiles = 0;
+    int32_t* d_counter = nullptr;
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    int max_nb = 2;
+    size_t lds_solve = 0, lds_prep = 0;
+    int grid_solve = 1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t last_stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+};
+
+int ompd_fail(int code, const std::string& msg);
+size_t ompd_tile_lds(int nb, int ns, int tbits);
+int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n, uint32_t flags,
+                    const PlanConfig& pc, ompd_plan** out);
+int ompd_plan_retile(ompd_plan* p, const PlanConfig& pc);
+int ompd_plan_run_locked(ompd_plan* p, hipStream_t s);
+int ompd_plan_collect(ompd_plan* p, int32_t* per_cfg);
+int ompd_batch_locked(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n, uint32_t flags,
+                      hipStream_t s);
+void ompd_serving_shutdown(ompd_ctx* ctx);

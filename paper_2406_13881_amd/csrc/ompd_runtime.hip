@@ -1,0 +1,720 @@
+// Host runtime of libompd: contexts, resident plans (scratch arena, tiles,
+// captured HIP graph), the host-pointer batch path and the autotuner.
+// The serving loop lives in ompd_serving.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ompd.h"
+#include "ompd_device.h"
+#include "ompd_internal.h"
+
+namespace ompd {
+extern "C" __global__ void ompd_k_prep(const DevCfg*, int, int32_t*);
+extern "C" __global__ void ompd_k_solve(const DevCfg*, const Tile*, int, int32_t*);
+}  // namespace ompd
+
+using namespace ompd;
+
+static thread_local std::string g_err;
+
+int ompd_fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define CK(x)                                                                                   \
+    do {                                                                                        \
+        hipError_t e_ = (x);                                                                    \
+        if (e_ != hipSuccess)                                                                   \
+            return ompd_fail(OMPD_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+extern "C" int ompd_ctx_create(ompd_ctx** out, int device_ordinal, uint64_t budget)
+{
+    if (!out) return ompd_fail(OMPD_E_INVAL, "out is NULL");
+    int ndev = 0;
+    CK(hipGetDeviceCount(&ndev));
+    if (device_ordinal < 0 || device_ordinal >= ndev) return ompd_fail(OMPD_E_DEVICE, "no such device");
+    ompd_ctx* c = new ompd_ctx();
+    c->device = device_ordinal;
+    c->budget = budget ? budget : (64ull << 30);
+    hipError_t e = hipSetDevice(device_ordinal);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&c->prop, device_ordinal);
+    if (e != hipSuccess) {
+        delete c;
+        return ompd_fail(OMPD_E_DEVICE, hipGetErrorString(e));
+    }
+    c->n_cu = c->prop.multiProcessorCount;
+    size_t lds_max = c->prop.maxSharedMemoryPerMultiProcessor;
+    if (!lds_max) lds_max = c->prop.sharedMemPerBlock;
+    lds_max = std::min<size_t>(lds_max ? lds_max : 64 * 1024, 160 * 1024);
+    // dynamic LDS limit per kernel = device limit minus the kernel's static LDS
+    int dyn = (int)lds_max;
+    for (const void* k : {(const void*)ompd_k_solve, (const void*)ompd_k_prep}) {
+        hipFuncAttributes fa{};
+        int st = 0;
+        if (hipFuncGetAttributes(&fa, k) == hipSuccess) st = (int)fa.sharedSizeBytes;
+        int want = (int)lds_max - st;
+        if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, want) != hipSuccess) {
+            (void)hipGetLastError();
+            want = std::min(want, 64 * 1024 - st);
+        }
+        dyn = std::min(dyn, want);
+    }
+    (void)hipGetLastError();
+    c->lds_max = dyn;
+    *out = c;
+    return OMPD_OK;
+}
+
+extern "C" void ompd_ctx_destroy(ompd_ctx* c)
+{
+    if (!c) return;
+    ompd_serving_shutdown(c);
+    delete c;
+}
+
+extern "C" const char* ompd_last_error(const ompd_ctx*) { return g_err.c_str(); }
+
+extern "C" int ompd_device_info(ompd_ctx* c, int32_t* n_cu, int32_t* lds_bytes, int64_t* mem_bytes)
+{
+    if (!c) return ompd_fail(OMPD_E_INVAL, "ctx is NULL");
+    if (n_cu) *n_cu = c->n_cu;
+    if (lds_bytes) *lds_bytes = c->lds_max;
+    if (mem_bytes) *mem_bytes = (int64_t)c->prop.totalGlobalMem;
+    return OMPD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tile rules
+// ---------------------------------------------------------------------------
+// LDS bytes a tile of nb blocks and ns slices of tbits needs.
+size_t ompd_tile_lds(int nb, int ns, int tbits)
+{
+    size_t nsi = ns > 0 ? ns : 1;
+    size_t a16 = ~(size_t)15;
+    return ((2 * (size_t)nb * nsi * (tbits / 8) + 15) & a16) + (((size_t)nb + 15) & a16) + 12 * nsi;
+}
+
+static int floor_pow2(long x) { int p = 1; while ((long)p * 2 <= x) p *= 2; return p; }
+
+// Cut one CFG into tiles: the widest slice type that fits `lds` with one
+// slice, then as many slices per tile (a power of two, at most max_ns) as fit.
+static int make_tiles(int ci, int nb, int nv, size_t lds, int max_ns, int min_tbits, std::vector<Tile>& out)
+{
+    int wd = (nv + 63) / 64;
+    int tb = 0;
+    for (int t : {32, 16, 8}) {
+        if (t < min_tbits) continue;
+        if (ompd_tile_lds(nb, 1, t) <= lds) { tb = t; break; }
+    }
+    if (!tb) return -1;
+    if (wd == 0) {
+        out.push_back(Tile{ci, tb, 0, 0});
+        return 0;
+    }
+    int rw = wd * (64 / tb);
+    int ns = 1;
+    while (ns * 2 <= max_ns && ns * 2 <= rw && ompd_tile_lds(nb, ns * 2, tb) <= lds) ns *= 2;
+    int s = 0;
+    while (s < rw) {
+        int k = std::min(ns, floor_pow2(rw - s));
+        out.push_back(Tile{ci, tb, s, k});
+        s += k;
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+static int check_cfg_host(const ompd_cfg& g, int i)
+{
+    char buf[160];
+    auto bad = [&](const char* why) {
+        snprintf(buf, sizeof buf, "cfg %d: %s", i, why);
+        return ompd_fail(OMPD_E_INVAL, buf);
+    };
+    if (g.n_blocks < 2) return bad("n_blocks < 2");
+    if (g.n_edges < 0 || g.n_vars < 0) return bad("negative size");
+    if (g.entry < 0 || g.entry >= g.n_blocks || g.exit < 0 || g.exit >= g.n_blocks || g.entry == g.exit)
+        return bad("entry/exit out of range");
+    if (!g.succ_ptr || !g.space) return bad("succ_ptr/space missing");
+    if (g.n_edges > 0 && (!g.succ_idx || !g.edge_kind)) return bad("succ_idx/edge_kind missing");
+    if (g.n_vars > 0 && (!g.read_bits || !g.write_bits)) return bad("read/write bits missing");
+    if (g.call_summary && (g.n_summaries <= 0 || !g.summaries)) return bad("call summaries missing");
+    return OMPD_OK;
+}
+
+int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n, uint32_t flags,
+                    const PlanConfig& pc, ompd_plan** out)
+{
+    if (!ctx || !out || n < 0 || (n > 0 && !cfgs)) return ompd_fail(OMPD_E_INVAL, "bad arguments");
+    for (int i = 0; i < n; ++i) {
+        int rc = check_cfg_host(cfgs[i], i);
+        if (rc) return rc;
+    }
+    CK(hipSetDevice(ctx->device));
+    ompd_plan* p = new ompd_plan();
+    p->ctx = ctx;
+    p->n = n;
+    p->flags = flags;
+    p->cfg = pc;
+    p->res.assign(res, res + n);
+    p->h_cfgs.resize(n);
+
+    // scratch layout
+    struct Off { size_t aveout, mayp, nu, ave, ie, ig, avf, bnd, pp, pi, pe, lvp, lvb, tmp, info; };
+    std::vector<Off> off(n);
+    size_t total = 0;
+    auto take = [&](size_t bytes) { size_t o = total; total += align256(bytes); return o; };
+    int max_nb = 2;
+    for (int i = 0; i < n; ++i) {
+        const ompd_cfg& g = cfgs[i];
+        const ompd_result& r = res[i];
+        size_t wd = (size_t)(g.n_vars + 63) / 64;
+        size_t bv = (size_t)g.n_blocks * wd * 8, ev = (size_t)g.n_edges * wd * 8;
+        Off& o = off[i];
+        o.aveout = take(2 * bv);
+        o.mayp = take(2 * bv);
+        o.nu = (r.nu_host && r.nu_dev) ? 0 : take(2 * bv);
+        o.ave = (r.ave_host && r.ave_dev) ? 0 : take(2 * bv);
+        o.ie = (r.ins_entry_to_host && r.ins_entry_to_dev) ? 0 : take(2 * bv);
+        o.ig = (r.ins_edge_to_host && r.ins_edge_to_dev) ? 0 : take(2 * ev);
+        o.avf = (!r.avf_host == !r.avf_dev) ? 0 : take(2 * bv);
+        o.bnd = take(4 * wd * 8);
+        o.pp = take(4 * ((size_t)g.n_blocks + 1));
+        o.pi = take(4 * (size_t)std::max(g.n_edges, 1));
+        o.pe = take(4 * (size_t)std::max(g.n_edges, 1));
+        o.lvp = take(4 * ((size_t)g.n_blocks + 1));
+        o.lvb = take(4 * (size_t)g.n_blocks);
+        o.tmp = take(4 * ((size_t)g.n_blocks + 1));
+        o.info = take(4 * INFO_WORDS);
+        max_nb = std::max(max_nb, g.n_blocks);
+    }
+    size_t counter_off = take(256);
+    p->scratch_bytes = total;
+    hipError_t e = hipMalloc(&p->scratch, std::max<size_t>(total, 256));
+    if (e != hipSuccess) {
+        delete p;
+        return ompd_fail(OMPD_E_NOMEM, std::string("scratch allocation: ") + hipGetErrorString(e));
+    }
+    char* S = (char*)p->scratch;
+    p->d_counter = (int32_t*)(S + counter_off);
+
+    // default boundaries (host-built, one copy)
+    std::vector<uint64_t> bnd_host;
+    for (int i = 0; i < n; ++i) {
+        const ompd_cfg& g = cfgs[i];
+        const ompd_result& r = res[i];
+        int wd = (g.n_vars + 63) / 64;
+        DevCfg& d = p->h_cfgs[i];
+        memset(&d, 0, sizeof d);
+        d.nb = g.n_blocks; d.ne = g.n_edges; d.nv = g.n_vars; d.entry = g.entry; d.exit = g.exit; d.wd = wd;
+        d.n_sums = g.call_summary ? g.n_summaries : 0;
+        d.placement = (flags & OMPD_F_PLACEMENT_EAGER) ? 1 : 0;
+        d.sweep_cap = (int)((flags >> 16) & 0xFFFFu);
+        d.succ_ptr = g.succ_ptr; d.succ_idx = g.succ_idx; d.kind = g.edge_kind; d.space = g.space;
+        d.R = g.read_bits; d.W = g.write_bits;
+        uint64_t* bnd = (uint64_t*)(S + off[i].bnd);
+        d.ev_h = g.entry_valid_host ? g.entry_valid_host : bnd;
+        d.ev_d = g.entry_valid_dev ? g.entry_valid_dev : bnd + wd;
+        d.lx_h = g.exit_live_host ? g.exit_live_host : bnd + 2 * wd;
+        d.lx_d = g.exit_live_dev ? g.exit_live_dev : bnd + 3 * wd;
+        d.call = g.call_summary; d.sums = g.summaries;
+        size_t bvw = (size_t)g.n_blocks * wd, evw = (size_t)g.n_edges * wd;
+        uint64_t* nu = (uint64_t*)(S + off[i].nu);
+        uint64_t* ave = (uint64_t*)(S + off[i].ave);
+        uint64_t* ie = (uint64_t*)(S + off[i].ie);
+        uint64_t* ig = (uint64_t*)(S + off[i].ig);
+        uint64_t* avf = (uint64_t*)(S + off[i].avf);
+        // a requested half is written in place; a missing half goes to scratch
+        d.nu_h = r.nu_host ? r.nu_host : nu;               d.nu_d = r.nu_dev ? r.nu_dev : nu + bvw;
+        d.ave_h = r.ave_host ? r.ave_host : ave;           d.ave_d = r.ave_dev ? r.ave_dev : ave + bvw;
+        d.ie_h = r.ins_entry_to_host ? r.ins_entry_to_host : ie;
+        d.ie_d = r.ins_entry_to_dev ? r.ins_entry_to_dev : ie + bvw;
+        d.ig_h = r.ins_edge_to_host ? r.ins_edge_to_host : ig;
+        d.ig_d = r.ins_edge_to_dev ? r.ins_edge_to_dev : ig + evw;
+        if (r.avf_host || r.avf_dev) {
+            d.avf_h = r.avf_host ? r.avf_host : avf;
+            d.avf_d = r.avf_dev ? r.avf_dev : avf + bvw;
+        }
+        d.var_kind = r.var_kind; d.after_dev = r.after_dev; d.before_dev = r.before_dev;
+        uint64_t* ao = (uint64_t*)(S + off[i].aveout);
+        uint64_t* mp = (uint64_t*)(S + off[i].mayp);
+        d.aveout_h = ao; d.aveout_d = ao + bvw; d.mayp_h = mp; d.mayp_d = mp + bvw;
+        d.pred_ptr = (int32_t*)(S + off[i].pp); d.pred_idx = (int32_t*)(S + off[i].pi);
+        d.pred_eid = (int32_t*)(S + off[i].pe); d.level_ptr = (int32_t*)(S + off[i].lvp);
+        d.level_blk = (int32_t*)(S + off[i].lvb); d.tmp = (int32_t*)(S + off[i].tmp);
+        d.info = (int32_t*)(S + off[i].info);
+        // default boundary values
+        if (wd > 0) {
+            std::vector<uint64_t> b(4 * (size_t)wd, 0);
+            uint64_t last = (g.n_vars & 63) ? ((1ull << (g.n_vars & 63)) - 1) : ~0ull;
+            for (int w = 0; w < wd; ++w) {
+                uint64_t m = (w == wd - 1) ? last : ~0ull;
+                b[w] = m;            // entry valid on the host
+                b[2 * wd + w] = m;   // live on the host after exit
+            }
+            e = hipMemcpy(bnd, b.data(), b.size() * 8, hipMemcpyHostToDevice);
+            if (e != hipSuccess) { ompd_plan_destroy(p); return ompd_fail(OMPD_E_DEVICE, hipGetErrorString(e)); }
+        }
+    }
+    p->max_nb = max_nb;
+    e = hipMalloc(&p->d_cfgs, sizeof(DevCfg) * std::max(n, 1));
+    if (e == hipSuccess && n > 0)
+        e = hipMemcpy(p->d_cfgs, p->h_cfgs.data(), sizeof(DevCfg) * n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { ompd_plan_destroy(p); return ompd_fail(OMPD_E_DEVICE, hipGetErrorString(e)); }
+    p->h_info.assign((size_t)n * INFO_WORDS, 0);
+    int rc = ompd_plan_retile(p, pc);
+    if (rc) { ompd_plan_destroy(p); return rc; }
+    CK(hipEventCreate(&p->ev0));
+    CK(hipEventCreate(&p->ev1));
+    CK(hipEventCreate(&p->ev2));
+    *out = p;
+    return OMPD_OK;
+}
+
+// (Re)build tiles, launch shapes and the captured graph for a configuration.
+int ompd_plan_retile(ompd_plan* p, const PlanConfig& pc)
+{
+    ompd_ctx* ctx = p->ctx;
+    p->cfg = pc;
+    std::vector<Tile> tiles;
+    size_t lds = pc.lds_bytes;
+    if (lds == 0) {
+        // smallest budget that holds the largest CFG with one 16-bit slice, at least 32 KiB
+        lds = std::max<size_t>(32 * 1024, ompd_tile_lds(p->max_nb, 1, 16));
+        if (lds > (size_t)ctx->lds_max) lds = std::max<size_t>(32 * 1024, ompd_tile_lds(p->max_nb, 1, 8));
+    }
+    lds = std::min<size_t>(lds, ctx->lds_max);
+    for (int i = 0; i < p->n; ++i) {
+        const DevCfg& d = p->h_cfgs[i];
+        if (make_tiles(i, d.nb, d.nv, lds, pc.max_ns, pc.min_tbits, tiles) != 0) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "cfg %d: %d blocks exceed the on-chip budget of %zu bytes", i, d.nb, lds);
+            return ompd_fail(OMPD_E_NOMEM, buf);
+        }
+    }
+    // longest tiles first: work ~ blocks x slices of the widest type
+    std::stable_sort(tiles.begin(), tiles.end(), [&](const Tile& a, const Tile& b) {
+        double wa = (double)p->h_cfgs[a.cfg].nb * (1.0 + std::max(a.ns, 1) / 16.0);
+        double wb = (double)p->h_cfgs[b.cfg].nb * (1.0 + std::max(b.ns, 1) / 16.0);
+        return wa > wb;
+    });
+    size_t need = 16;
+    for (const Tile& t : tiles) need = std::max(need, ompd_tile_lds(p->h_cfgs[t.cfg].nb, t.ns, t.tbits));
+    p->lds_solve = (need + 255) & ~(size_t)255;
+    p->lds_prep = 4 * (size_t)p->max_nb + 64;
+    if (p->lds_prep > (size_t)ctx->lds_max)
+        return ompd_fail(OMPD_E_NOMEM, "CFG too large for the ingest kernel's on-chip level table");
+    p->h_tiles = tiles;
+    p->n_tiles = (int)tiles.size();
+    if (p->d_tiles) { (void)hipFree(p->d_tiles); p->d_tiles = nullptr; }
+    CK(hipMalloc(&p->d_tiles, sizeof(Tile) * std::max(p->n_tiles, 1)));
+    if (p->n_tiles)
+        CK(hipMemcpy(p->d_tiles, tiles.data(), sizeof(Tile) * p->n_tiles, hipMemcpyHostToDevice));
+    int per_cu = 0;
+    CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)ompd_k_solve, 64, p->lds_solve));
+    per_cu = std::max(1, per_cu);
+    if (pc.wg_per_cu > 0) per_cu = std::min(per_cu, pc.wg_per_cu);
+    p->grid_solve = std::max(1, std::min(p->n_tiles, per_cu * ctx->n_cu));
+    if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+    return OMPD_OK;
+}
+
+static int launch_all(ompd_plan* p, hipStream_t s, bool events)
+{
+    (void)hipGetLastError();
+    if (events) CK(hipEventRecord(p->ev0, s));
+    if (p->n > 0) {
+        hipLaunchKernelGGL(ompd_k_prep, dim3(p->n), dim3(256), p->lds_prep, s, (const DevCfg*)p->d_cfgs, p->n,
+                           p->d_counter);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return ompd_fail(OMPD_E_DEVICE, std::string("prep launch (lds ") + std::to_string(p->lds_prep) +
+                                                "): " + hipGetErrorString(e));
+    }
+    if (events) CK(hipEventRecord(p->ev1, s));
+    if (p->n_tiles > 0) {
+        hipLaunchKernelGGL(ompd_k_solve, dim3(p->grid_solve), dim3(64), p->lds_solve, s,
+                           (const DevCfg*)p->d_cfgs, (const Tile*)p->d_tiles, p->n_tiles, p->d_counter);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return ompd_fail(OMPD_E_DEVICE, std::string("solve launch (grid ") + std::to_string(p->grid_solve) +
+                                                ", lds " + std::to_string(p->lds_solve) + "): " + hipGetErrorString(e));
+    }
+    if (events) CK(hipEventRecord(p->ev2, s));
+    return OMPD_OK;
+}
+
+extern "C" int ompd_plan_create(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n, uint32_t flags,
+                                ompd_plan** out)
+{
+    if (!(flags & OMPD_F_DEVICE_PTRS)) return ompd_fail(OMPD_E_INVAL, "plans need OMPD_F_DEVICE_PTRS");
+    if (!ctx) return ompd_fail(OMPD_E_INVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    PlanConfig pc;
+    return ompd_plan_build(ctx, cfgs, res, n, flags, pc, out);
+}
+
+int ompd_plan_run_locked(ompd_plan* p, hipStream_t s)
+{
+    CK(hipSetDevice(p->ctx->device));
+    p->last_stream = s;
+    if (!p->cfg.use_graph) return launch_all(p, s, true);
+    if (!p->graph_exec) {
+        hipStream_t cs;
+        CK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        int rc = OMPD_OK;
+        if (e == hipSuccess) rc = launch_all(p, cs, true);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess || e2 != hipSuccess || rc != OMPD_OK || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            p->cfg.use_graph = false;     // capture unsupported here: launch directly
+            return launch_all(p, s, true);
+        }
+        e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            p->cfg.use_graph = false;
+            return launch_all(p, s, true);
+        }
+        p->graph = g;
+    }
+    CK(hipGraphLaunch(p->graph_exec, s));
+    return OMPD_OK;
+}
+
+extern "C" int ompd_plan_run(ompd_plan* p, void* stream)
+{
+    if (!p) return ompd_fail(OMPD_E_INVAL, "plan is NULL");
+    std::lock_guard<std::mutex> lk(p->ctx->mu);
+    return ompd_plan_run_locked(p, (hipStream_t)stream);
+}
+
+int ompd_plan_collect(ompd_plan* p, int32_t* per_cfg)
+{
+    CK(hipSetDevice(p->ctx->device));
+    CK(hipStreamSynchronize(p->last_stream));
+    if (p->n == 0) return OMPD_OK;
+    // info words live per CFG inside the scratch arena
+    for (int i = 0; i < p->n; ++i)
+        CK(hipMemcpyAsync(&p->h_info[(size_t)i * INFO_WORDS], p->h_cfgs[i].info, 4 * INFO_WORDS,
+                          hipMemcpyDeviceToHost, p->last_stream));
+    CK(hipStreamSynchronize(p->last_stream));
+    int first = OMPD_OK;
+    for (int i = 0; i < p->n; ++i) {
+        const int32_t* inf = &p->h_info[(size_t)i * INFO_WORDS];
+        int st = inf[INFO_STATUS];
+        if (per_cfg) per_cfg[i] = st;
+        for (int k = 0; k < 6; ++k) p->res[i].sweeps[k] = inf[INFO_SWEEPS + k];
+        if (st && first == OMPD_OK) {
+            first = st;
+            char buf[128];
+            snprintf(buf, sizeof buf, "cfg %d: %s", i,
+                     st == OMPD_E_INVAL ? "malformed CFG" : st == OMPD_E_NOCONVERGE ? "sweep cap reached" : "error");
+            g_err = buf;
+        }
+    }
+    return first;
+}
+
+extern "C" int ompd_plan_status(ompd_plan* p, int32_t* per_cfg)
+{
+    if (!p) return ompd_fail(OMPD_E_INVAL, "plan is NULL");
+    std::lock_guard<std::mutex> lk(p->ctx->mu);
+    return ompd_plan_collect(p, per_cfg);
+}
+
+extern "C" int ompd_plan_last_ms(ompd_plan* p, float* total_ms, float* solve_ms)
+{
+    if (!p) return ompd_fail(OMPD_E_INVAL, "plan is NULL");
+    CK(hipEventSynchronize(p->ev2));
+    float a = 0, b = 0;
+    CK(hipEventElapsedTime(&a, p->ev0, p->ev2));
+    CK(hipEventElapsedTime(&b, p->ev1, p->ev2));
+    if (total_ms) *total_ms = a;
+    if (solve_ms) *solve_ms = b;
+    return OMPD_OK;
+}
+
+extern "C" int ompd_plan_describe(ompd_plan* p, char* buf, int32_t len)
+{
+    if (!p || !buf || len <= 0) return ompd_fail(OMPD_E_INVAL, "bad arguments");
+    int n8 = 0, n16 = 0, n32 = 0;
+    for (const Tile& t : p->h_tiles) (t.tbits == 32 ? n32 : t.tbits == 16 ? n16 : n8)++;
+    snprintf(buf, len,
+             "{\"cfgs\": %d, \"tiles\": %d, \"tiles32\": %d, \"tiles16\": %d, \"tiles8\": %d, \"lds_solve\": %zu, "
+             "\"lds_prep\": %zu, \"grid_solve\": %d, \"max_ns\": %d, \"min_tbits\": %d, \"wg_per_cu\": %d, "
+             "\"graph\": %d, \"scratch_bytes\": %zu}",
+             p->n, p->n_tiles, n32, n16, n8, p->lds_solve, p->lds_prep, p->grid_solve, p->cfg.max_ns,
+             p->cfg.min_tbits, p->cfg.wg_per_cu, p->cfg.use_graph ? 1 : 0, p->scratch_bytes);
+    return OMPD_OK;
+}
+
+extern "C" void ompd_plan_destroy(ompd_plan* p)
+{
+    if (!p) return;
+    (void)hipSetDevice(p->ctx->device);
+    if (p->last_stream || p->graph_exec) (void)hipDeviceSynchronize();
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->d_tiles) (void)hipFree(p->d_tiles);
+    if (p->d_cfgs) (void)hipFree(p->d_cfgs);
+    if (p->scratch) (void)hipFree(p->scratch);
+    if (p->ev0) (void)hipEventDestroy(p->ev0);
+    if (p->ev1) (void)hipEventDestroy(p->ev1);
+    if (p->ev2) (void)hipEventDestroy(p->ev2);
+    delete p;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+extern "C" int ompd_plan_autotune(ompd_plan* p, void* stream, int32_t trials, float* best_ms)
+{
+    if (!p) return ompd_fail(OMPD_E_INVAL, "plan is NULL");
+    std::lock_guard<std::mutex> lk(p->ctx->mu);
+    hipStream_t s = (hipStream_t)stream;
+    trials = std::max(1, trials);
+    std::vector<PlanConfig> cands;
+    const size_t base = std::max<size_t>(16 * 1024, ompd_tile_lds(p->max_nb, 1, 8));
+    for (size_t lds : {(size_t)0, (size_t)24 * 1024, (size_t)32 * 1024, (size_t)40 * 1024, (size_t)54 * 1024,
+                       (size_t)80 * 1024, (size_t)160 * 1024}) {
+        if (lds && (lds < base || lds > (size_t)p->ctx->lds_max)) continue;
+        for (int max_ns : {4, 16, 64}) {
+            PlanConfig c = p->cfg;
+            c.lds_bytes = lds;
+            c.max_ns = max_ns;
+            c.wg_per_cu = 0;
+            cands.push_back(c);
+        }
+    }
+    PlanConfig best = p->cfg;
+    float best_t = 1e30f;
+    for (const PlanConfig& c : cands) {
+        int rc = ompd_plan_retile(p, c);
+        if (rc) continue;
+        float tot = 0;
+        bool ok = true;
+        for (int t = 0; t < trials + 1 && ok; ++t) {
+            if (ompd_plan_run_locked(p, s) != OMPD_OK) { ok = false; break; }
+            if (hipEventSynchronize(p->ev2) != hipSuccess) { ok = false; break; }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, p->ev0, p->ev2);
+            if (t > 0) tot += ms;   // first run warms the graph
+        }
+        if (!ok) continue;
+        float avg = tot / trials;
+        if (avg < best_t) { best_t = avg; best = c; }
+    }
+    int rc = ompd_plan_retile(p, best);
+    if (rc) return rc;
+    if (best_ms) *best_ms = best_t;
+    return OMPD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// host-pointer batch path (and the device-pointer one-shot path)
+// ---------------------------------------------------------------------------
+namespace {
+struct Staged {
+    std::vector<ompd_cfg> dcfg;
+    std::vector<ompd_result> dres;
+    void* dmem = nullptr;
+    size_t bytes = 0;
+    // output copies back: (device offset, host pointer, bytes)
+    struct Back { size_t off; void* host; size_t bytes; };
+    std::vector<Back> back;
+    ~Staged() { if (dmem) (void)hipFree(dmem); }
+};
+}  // namespace
+
+static int stage_inputs(const ompd_cfg* cfgs, ompd_result* res, int n, Staged& st, hipStream_t s)
+{
+    // layout: inputs then outputs, each 256-aligned
+    std::vector<uint8_t> host;
+    size_t total = 0;
+    auto reserve = [&](size_t bytes) { size_t o = total; total += align256(bytes); return o; };
+    struct In { size_t sp, si, kd, spc, R, W, evh, evd, lxh, lxd, call, sums; };
+    struct OutO { size_t nu_h, nu_d, ave_h, ave_d, avf_h, avf_d, ie_d, ie_h, ig_d, ig_h, vk, ad, bd; };
+    std::vector<In> in(n);
+    std::vector<OutO> oo(n);
+    for (int i = 0; i < n; ++i) {
+        const ompd_cfg& g = cfgs[i];
+        const ompd_result& r = res[i];
+        size_t wd = (size_t)(g.n_vars + 63) / 64;
+        size_t bv = (size_t)g.n_blocks * wd * 8, ev = (size_t)g.n_edges * wd * 8;
+        In& a = in[i];
+        a.sp = reserve(4 * ((size_t)g.n_blocks + 1));
+        a.si = reserve(4 * (size_t)g.n_edges);
+        a.kd = reserve((size_t)g.n_edges);
+        a.spc = reserve((size_t)g.n_blocks);
+        a.R = reserve(bv);
+        a.W = reserve(bv);
+        a.evh = g.entry_valid_host ? reserve(wd * 8) : SIZE_MAX;
+        a.evd = g.entry_valid_dev ? reserve(wd * 8) : SIZE_MAX;
+        a.lxh = g.exit_live_host ? reserve(wd * 8) : SIZE_MAX;
+        a.lxd = g.exit_live_dev ? reserve(wd * 8) : SIZE_MAX;
+        a.call = g.call_summary ? reserve(4 * (size_t)g.n_blocks) : SIZE_MAX;
+        a.sums = g.call_summary ? reserve((size_t)g.n_summaries * 16 * wd * 8) : SIZE_MAX;
+        (void)r;
+        (void)ev;
+    }
+    size_t in_bytes = total;
+    for (int i = 0; i < n; ++i) {
+        const ompd_cfg& g = cfgs[i];
+        const ompd_result& r = res[i];
+        size_t wd = (size_t)(g.n_vars + 63) / 64;
+        size_t bv = (size_t)g.n_blocks * wd * 8, ev = (size_t)g.n_edges * wd * 8;
+        OutO& o = oo[i];
+        auto opt = [&](const void* ptr, size_t bytes) { return ptr ? reserve(bytes) : SIZE_MAX; };
+        o.nu_h = opt(r.nu_host, bv); o.nu_d = opt(r.nu_dev, bv);
+        o.ave_h = opt(r.ave_host, bv); o.ave_d = opt(r.ave_dev, bv);
+        o.avf_h = (r.avf_host || r.avf_dev) ? reserve(bv) : SIZE_MAX;
+        o.avf_d = (r.avf_host || r.avf_dev) ? reserve(bv) : SIZE_MAX;
+        o.ie_d = opt(r.ins_entry_to_dev, bv); o.ie_h = opt(r.ins_entry_to_host, bv);
+        o.ig_d = opt(r.ins_edge_to_dev, ev); o.ig_h = opt(r.ins_edge_to_host, ev);
+        o.vk = opt(r.var_kind, (size_t)g.n_vars); o.ad = opt(r.after_dev, g.n_blocks); o.bd = opt(r.before_dev, g.n_blocks);
+    }
+    st.bytes = total;
+    hipError_t e = hipMalloc(&st.dmem, std::max<size_t>(total, 256));
+    if (e != hipSuccess) return ompd_fail(OMPD_E_NOMEM, std::string("device staging: ") + hipGetErrorString(e));
+    host.assign(in_bytes, 0);
+    char* D = (char*)st.dmem;
+    st.dcfg.resize(n);
+    st.dres.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const ompd_cfg& g = cfgs[i];
+        const ompd_result& r = res[i];
+        size_t wd = (size_t)(g.n_vars + 63) / 64;
+        size_t bv = (size_t)g.n_blocks * wd * 8, ev = (size_t)g.n_edges * wd * 8;
+        const In& a = in[i];
+        auto put = [&](size_t o, const void* src, size_t bytes) { if (bytes && src) memcpy(host.data() + o, src, bytes); };
+        put(a.sp, g.succ_ptr, 4 * ((size_t)g.n_blocks + 1));
+        put(a.si, g.succ_idx, 4 * (size_t)g.n_edges);
+        put(a.kd, g.edge_kind, (size_t)g.n_edges);
+        put(a.spc, g.space, (size_t)g.n_blocks);
+        put(a.R, g.read_bits, bv);
+        put(a.W, g.write_bits, bv);
+        if (a.evh != SIZE_MAX) put(a.evh, g.entry_valid_host, wd * 8);
+        if (a.evd != SIZE_MAX) put(a.evd, g.entry_valid_dev, wd * 8);
+        if (a.lxh != SIZE_MAX) put(a.lxh, g.exit_live_host, wd * 8);
+        if (a.lxd != SIZE_MAX) put(a.lxd, g.exit_live_dev, wd * 8);
+        if (a.call != SIZE_MAX) put(a.call, g.call_summary, 4 * (size_t)g.n_blocks);
+        if (a.sums != SIZE_MAX) put(a.sums, g.summaries, (size_t)g.n_summaries * 16 * wd * 8);
+        ompd_cfg d = g;
+        d.succ_ptr = (const int32_t*)(D + a.sp);
+        d.succ_idx = (const int32_t*)(D + a.si);
+        d.edge_kind = (const uint8_t*)(D + a.kd);
+        d.space = (const uint8_t*)(D + a.spc);
+        d.read_bits = (const uint64_t*)(D + a.R);
+        d.write_bits = (const uint64_t*)(D + a.W);
+        d.entry_valid_host = a.evh != SIZE_MAX ? (const uint64_t*)(D + a.evh) : nullptr;
+        d.entry_valid_dev = a.evd != SIZE_MAX ? (const uint64_t*)(D + a.evd) : nullptr;
+        d.exit_live_host = a.lxh != SIZE_MAX ? (const uint64_t*)(D + a.lxh) : nullptr;
+        d.exit_live_dev = a.lxd != SIZE_MAX ? (const uint64_t*)(D + a.lxd) : nullptr;
+        d.call_summary = a.call != SIZE_MAX ? (const int32_t*)(D + a.call) : nullptr;
+        d.summaries = a.sums != SIZE_MAX ? (const uint64_t*)(D + a.sums) : nullptr;
+        st.dcfg[i] = d;
+        const OutO& o = oo[i];
+        ompd_result dr;
+        memset(&dr, 0, sizeof dr);
+        auto outp = [&](size_t off, void* hp, size_t bytes) -> void* {
+            if (off == SIZE_MAX) return nullptr;
+            if (hp) st.back.push_back({off, hp, bytes});
+            return D + off;
+        };
+        dr.nu_host = (uint64_t*)outp(o.nu_h, r.nu_host, bv);
+        dr.nu_dev = (uint64_t*)outp(o.nu_d, r.nu_dev, bv);
+        dr.ave_host = (uint64_t*)outp(o.ave_h, r.ave_host, bv);
+        dr.ave_dev = (uint64_t*)outp(o.ave_d, r.ave_dev, bv);
+        dr.avf_host = (uint64_t*)outp(o.avf_h, r.avf_host, bv);
+        dr.avf_dev = (uint64_t*)outp(o.avf_d, r.avf_dev, bv);
+        dr.ins_entry_to_dev = (uint64_t*)outp(o.ie_d, r.ins_entry_to_dev, bv);
+        dr.ins_entry_to_host = (uint64_t*)outp(o.ie_h, r.ins_entry_to_host, bv);
+        dr.ins_edge_to_dev = (uint64_t*)outp(o.ig_d, r.ins_edge_to_dev, ev);
+        dr.ins_edge_to_host = (uint64_t*)outp(o.ig_h, r.ins_edge_to_host, ev);
+        dr.var_kind = (uint8_t*)outp(o.vk, r.var_kind, (size_t)g.n_vars);
+        dr.after_dev = (uint8_t*)outp(o.ad, r.after_dev, (size_t)g.n_blocks);
+        dr.before_dev = (uint8_t*)outp(o.bd, r.before_dev, (size_t)g.n_blocks);
+        st.dres[i] = dr;
+    }
+    if (in_bytes) CK(hipMemcpyAsync(st.dmem, host.data(), in_bytes, hipMemcpyHostToDevice, s));
+    CK(hipStreamSynchronize(s));
+    return OMPD_OK;
+}
+
+int ompd_batch_locked(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n, uint32_t flags,
+                      hipStream_t s)
+{
+    if (n < 0 || (n > 0 && (!cfgs || !res))) return ompd_fail(OMPD_E_INVAL, "bad arguments");
+    CK(hipSetDevice(ctx->device));
+    for (int i = 0; i < n; ++i) {
+        int rc = check_cfg_host(cfgs[i], i);
+        if (rc) return rc;
+    }
+    PlanConfig pc;
+    pc.use_graph = false;
+    if (flags & OMPD_F_DEVICE_PTRS) {
+        ompd_plan* p = nullptr;
+        int rc = ompd_plan_build(ctx, cfgs, res, n, flags, pc, &p);
+        if (rc) return rc;
+        rc = ompd_plan_run_locked(p, s);
+        if (rc == OMPD_OK) rc = ompd_plan_collect(p, nullptr);
+        ompd_plan_destroy(p);
+        return rc;
+    }
+    Staged st;
+    int rc = stage_inputs(cfgs, res, n, st, s);
+    if (rc) return rc;
+    ompd_plan* p = nullptr;
+    rc = ompd_plan_build(ctx, st.dcfg.data(), st.dres.data(), n, flags | OMPD_F_DEVICE_PTRS, pc, &p);
+    if (rc) return rc;
+    rc = ompd_plan_run_locked(p, s);
+    int rc2 = (rc == OMPD_OK) ? ompd_plan_collect(p, nullptr) : rc;
+    if (rc == OMPD_OK) {
+        for (int i = 0; i < n; ++i) memcpy(res[i].sweeps, p->res[i].sweeps, sizeof res[i].sweeps);
+        // copy outputs back (also for invalid CFGs: their buffers hold unspecified values)
+        std::vector<uint8_t> host(st.bytes);
+        hipError_t e = hipMemcpy(host.data(), st.dmem, st.bytes, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc2 = ompd_fail(OMPD_E_DEVICE, hipGetErrorString(e));
+        else
+            for (const auto& b : st.back) memcpy(b.host, host.data() + b.off, b.bytes);
+    }
+    ompd_plan_destroy(p);
+    return rc2;
+}
+
+extern "C" int ompd_analyze_batch(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n, uint32_t flags,
+                                  void* stream)
+{
+    if (!ctx) return ompd_fail(OMPD_E_INVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    return ompd_batch_locked(ctx, cfgs, res, n, flags, (hipStream_t)stream);
+}
+
+extern "C" int ompd_analyze_cfg(ompd_ctx* ctx, const ompd_cfg* cfg, ompd_result* res, uint32_t flags, void* stream)
+{
+    if (!ctx || !cfg || !res) return ompd_fail(OMPD_E_INVAL, "bad arguments");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    return ompd_batch_locked(ctx, cfg, res, 1, flags, (hipStream_t)stream);
+}

@@ -1,0 +1,164 @@
+"""GPU parity: every output of the HIP path equals the oracle's, bit for bit.
+
+The inputs are seeded synthetic CFGs (structured programs with loops,
+irreducible entries, device kernels; unstructured random DAGs with
+loop-entry marks; hand-built worked examples), at sizes that span many
+levels, several slices and a ragged last word.  All results are integers,
+so the tolerance is zero.
+"""
+import glob
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+KEYS = ("nu_h", "nu_d", "ave_h", "ave_d", "avf_h", "avf_d", "ins_entry_h", "ins_entry_d",
+        "ins_edge_h", "ins_edge_d", "var_kind", "after_dev", "before_dev")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2406_13881_amd as ompd
+    c = ompd.Context(0)
+    print("device:", c.device_info(), flush=True)
+    yield c
+    c.close()
+
+
+def assert_same(cfg, got, ref, tag=""):
+    for k in KEYS:
+        g = np.asarray(got[k])
+        r = np.asarray(ref[k]).reshape(g.shape)
+        if not np.array_equal(g, r):
+            bad = np.argwhere(g != r)
+            raise AssertionError("%s %s differs at %d places, first %s: got %s want %s" % (
+                tag, k, len(bad), bad[0].tolist(), g[tuple(bad[0])], r[tuple(bad[0])]))
+
+
+def _print(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_worked_examples(ctx):
+    SPACE = {"H": 0, "D": 1}
+    KIND = {"N": 0, "BACK": 1, "LE": 2}
+    cfgs = []
+    for path in sorted(glob.glob(os.path.join(GOLDEN, "P*.json"))):
+        g = json.load(open(path))
+        cfg, _ = synth.from_edges([(SPACE[s], r, w) for (s, r, w) in g["blocks"]],
+                                  [(s, d, KIND[k]) for (s, d, k) in g["edges"]], g["n_vars"])
+        cfgs.append(cfg)
+    _print("worked examples: %d CFGs" % len(cfgs))
+    got = ctx.analyze_batch(cfgs)
+    for i, cfg in enumerate(cfgs):
+        assert_same(cfg, got[i], oracle.solve(cfg), "example %d" % i)
+
+
+def test_config1_sweep(ctx):
+    """Config 1 shape: 300 seeded CFGs of 64 blocks x 32 variables in one batch."""
+    cfgs = [synth.c1(i) for i in range(300)]
+    _print("c1 sweep: %d CFGs" % len(cfgs))
+    got = ctx.analyze_batch(cfgs)
+    for i, cfg in enumerate(cfgs):
+        assert_same(cfg, got[i], oracle.solve(cfg), "c1 #%d" % i)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_dags_with_loop_entries(ctx, seed):
+    rng = np.random.Generator(np.random.PCG64(77 + seed))
+    cfgs = []
+    for j in range(40):
+        nb = int(rng.integers(2, 40)) if j else 2
+        nv = int(rng.choice([0, 1, 31, 32, 33, 63, 64, 65, 130, 300]))
+        if nb == 2:
+            cfgs.append(synth.from_edges([(0, [], []), (0, [], [])], [(0, 1, 0)], nv)[0])
+        else:
+            cfgs.append(synth.random_dag(1000 * seed + j, nb, nv, p_loop_entry=0.3))
+    _print("random dags seed %d" % seed)
+    got = ctx.analyze_batch(cfgs)
+    for i, cfg in enumerate(cfgs):
+        assert_same(cfg, got[i], oracle.solve(cfg), "dag %d/%d" % (seed, i))
+
+
+def test_structured_irreducible_multiword(ctx):
+    """Mid-size structured CFGs with irreducible loop entries, deep nesting
+    and 1..9 words of variables (ragged last word), several tiles each."""
+    cfgs = []
+    for j in range(24):
+        cfgs.append(synth.make_cfg(5_000 + j, n_user=50 + 37 * j, n_vars=17 + 23 * j, max_loop_depth=6,
+                                   device_frac=0.4, irr_loop_frac=0.2, p_read=0.15, p_write=0.08))
+    _print("structured irreducible: %d CFGs" % len(cfgs))
+    got = ctx.analyze_batch(cfgs)
+    for i, cfg in enumerate(cfgs):
+        assert_same(cfg, got[i], oracle.solve(cfg), "struct %d" % i)
+
+
+def test_boundaries(ctx):
+    """Non-default entry validity and exit liveness (callee-style contexts)."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    cfgs = []
+    for j in range(12):
+        cfg = synth.make_cfg(9_000 + j, n_user=80, n_vars=150, max_loop_depth=3, device_frac=0.3)
+        m = synth.var_mask(cfg.n_vars)
+        r = lambda: np.array([int(x) for x in rng.integers(0, 1 << 63, size=cfg.wd, dtype=np.uint64)], np.uint64) & m
+        evd = r()
+        cfg.entry_valid_d = evd
+        cfg.entry_valid_h = (~evd | r()) & m
+        cfg.exit_live_h = r()
+        cfg.exit_live_d = r()
+        cfgs.append(cfg)
+    got = ctx.analyze_batch(cfgs)
+    for i, cfg in enumerate(cfgs):
+        assert_same(cfg, got[i], oracle.solve(cfg), "boundary %d" % i)
+
+
+def test_eager_placement(ctx):
+    import paper_2406_13881_amd as ompd
+    cfgs = [synth.c1(i) for i in range(50)] + [synth.random_dag(40 + i, 20, 70, p_loop_entry=0.3) for i in range(20)]
+    got = ctx.analyze_batch(cfgs, flags=ompd.F_PLACEMENT_EAGER)
+    for i, cfg in enumerate(cfgs):
+        assert_same(cfg, got[i], oracle.solve(cfg, placement=1), "eager %d" % i)
+
+
+def test_config2_full(ctx):
+    """Config 2 at full size (16,384 blocks x 2,048 variables), every output."""
+    cfg = synth.c2(0)
+    _print("c2 full: %d blocks %d vars" % (cfg.n_blocks, cfg.n_vars))
+    got = ctx.analyze_cfg(cfg)
+    assert_same(cfg, got, oracle.solve(cfg), "c2")
+
+
+def test_malformed_is_rejected(ctx):
+    import paper_2406_13881_amd as ompd
+    good = synth.c1(0)
+    bad = synth.c1(1)
+    bad.succ_idx = bad.succ_idx.copy()
+    bad.succ_idx[0] = 0                       # an edge into ENTRY
+    with pytest.raises(ompd.OmpdError) as ei:
+        ctx.analyze_batch([good, bad])
+    assert ei.value.code == ompd.OMPD_E_INVAL
+    unreach = synth.from_edges([(0, [], []), (0, [], []), (0, [], []), (0, [], [])],
+                               [(0, 1, 0), (1, 3, 0), (2, 3, 0)], 5)[0]
+    with pytest.raises(ompd.OmpdError) as ei:
+        ctx.analyze_cfg(unreach)
+    assert ei.value.code == ompd.OMPD_E_INVAL
+
+
+def test_sweep_cap_reports_noconverge(ctx):
+    import paper_2406_13881_amd as ompd
+    cfg = synth.c1(3)
+    with pytest.raises(ompd.OmpdError) as ei:
+        ctx.analyze_cfg(cfg, flags=ompd.F_SWEEP_CAP(1))
+    assert ei.value.code == ompd.OMPD_E_NOCONVERGE
+    # and the default cap never triggers
+    got = ctx.analyze_cfg(cfg)
+    assert_same(cfg, got, oracle.solve(cfg), "after cap")

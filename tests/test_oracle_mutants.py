@@ -1,0 +1,109 @@
+"""Each plausible mistake planted in a copy of the oracle (a wrong meet, a
+dropped kill or gen term, a swapped space test, a lost loop-entry rule, ...)
+must be caught by at least one of the pins.  Runs on the CPU with gcc."""
+import glob
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import checkers
+import oracle
+import synth
+from test_oracle_pins import GOLDEN, load_golden, bits_of, VK
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+MUTANTS = {
+    "ave_meet_or": ("meet &= out[s][ix(g, g->pi[k], w)];", "meet |= out[s][ix(g, g->pi[k], w)];"),
+    "nu_no_kill": ("v = use_s(g, s, b, w) | (out & ~g->W[ix(g, b, w)]);", "v = use_s(g, s, b, w) | out;"),
+    "ave_no_nu_gen": ("vin = nu[s][ix(g, q, w)] | meet;", "vin = meet;"),
+    "transfer_space_swapped": ("uint64_t a1 = ((int)g->space[b] == s) ? (in_s | Wb) : (in_s & ~Wb);",
+                               "uint64_t a1 = ((int)g->space[b] != s) ? (in_s | Wb) : (in_s & ~Wb);"),
+    "transfer_no_stale": ("uint64_t a1 = ((int)g->space[b] == s) ? (in_s | Wb) : (in_s & ~Wb);",
+                          "uint64_t a1 = ((int)g->space[b] == s) ? (in_s | Wb) : in_s;"),
+    "later_no_neutral": ("all &= (lp | np);", "all &= lp;"),
+    "later_no_any": ("uint64_t vin = all & any & vmask(g, w);", "uint64_t vin = all & vmask(g, w);"),
+    "ins_edge_no_le": ("later_e & (le_mask(&g, e) | ~lin[s][ix(&g, q, w)]) & vmask(&g, w);",
+                       "later_e & (~lin[s][ix(&g, q, w)]) & vmask(&g, w);"),
+    "mayp_no_le": ("min |= (eag(g, nu[s], aveout[s], p, q, w) | mout[s][ix(g, p, w)]) & ~le_mask(g, e);",
+                   "min |= (eag(g, nu[s], aveout[s], p, q, w) | mout[s][ix(g, p, w)]);"),
+    "later_no_stop": ("uint64_t vout = vin & ~use_stop(g, s, q, w) & ~wr_s(g, s, q, w);",
+                      "uint64_t vout = vin & ~wr_s(g, s, q, w);"),
+    "avf_no_entry_gen": ("vin = ins_entry[s][ix(g, q, w)] | meet;", "vin = meet;"),
+    "fv_wrong_space": ("uint64_t np = (fv(g, s, nu, aveout, mout, p, q, e, w) & fv(g, o, nu, aveout, mout, p, q, e, w)) |",
+                       "uint64_t np = (fv(g, s, nu, aveout, mout, p, q, e, w) & fv(g, s, nu, aveout, mout, p, q, e, w)) |"),
+    "after_dev_from_host": ("for (int b = 0; b < nb; ++b) if (space[b] == 1) { after_dev[b] = 1; stk[top++] = b; }",
+                            "for (int b = 0; b < nb; ++b) if (space[b] == 0) { after_dev[b] = 1; stk[top++] = b; }"),
+    "map_from_wrong_end": ("if ((ins_edge_h[(size_t)e * g.wd + w] & bit) && !before_dev[t]) from = 1;",
+                           "if ((ins_edge_h[(size_t)e * g.wd + w] & bit) && !before_dev[q]) from = 1;"),
+    "alloc_always": ("((dev_access && !to && !from) ? 4 : 0)", "(dev_access ? 4 : 0)"),
+    "exit_not_live": ("if (b == g->exit) return g->lx[s][w];", "if (b == g->exit) return 0;"),
+}
+
+
+def run_pins():
+    """A compact version of the pin suite; returns True if every pin holds."""
+    try:
+        for path in sorted(glob.glob(os.path.join(GOLDEN, "P*.json"))):
+            g, cfg, pos = load_golden(path)
+            r = oracle.solve(cfg)
+            exp = g["expect"]
+            inv = {int(pos[i]): i for i in range(len(pos))}
+            for k in ("nu_h", "nu_d", "ave_h", "ave_d", "avf_h", "avf_d"):
+                if k in exp and bits_of(r[k]) != exp[k]:
+                    return False
+            for k in ("ins_edge_h", "ins_edge_d"):
+                if sorted(inv[e] for e in range(cfg.n_edges) if int(r[k][e, 0]) & 1) != sorted(exp[k]):
+                    return False
+            for k in ("ins_entry_h", "ins_entry_d"):
+                if [b for b in range(cfg.n_blocks) if int(r[k][b, 0]) & 1] != sorted(exp[k]):
+                    return False
+            if [int(x) for x in r["var_kind"]] != [VK[x] for x in exp["var_kind"]]:
+                return False
+        for seed in range(8):
+            cfg = synth.random_dag(seed, 9, 65, p_loop_entry=0.3 if seed % 2 else 0.0)
+            r = oracle.solve(cfg)
+            nu_h, nu_d = checkers.mop_nu(cfg)
+            if checkers.rows_int(r["nu_h"]) != nu_h or checkers.rows_int(r["nu_d"]) != nu_d:
+                return False
+            ave = checkers.mop_valid(cfg, [nu_h, nu_d], [{}, {}])
+            if (checkers.rows_int(r["ave_h"]), checkers.rows_int(r["ave_d"])) != ave:
+                return False
+            after, before = checkers.reach_labels(cfg)
+            if r["after_dev"].tolist() != after.tolist() or r["before_dev"].tolist() != before.tolist():
+                return False
+            if checkers.check_invariants(cfg, r):
+                return False
+        for seed in range(3):
+            cfg = synth.c1(seed)
+            r = oracle.solve(cfg)
+            if checkers.check_invariants(cfg, r):
+                return False
+            errs, _ = checkers.simulate_paths(cfg, r, walks=30, seed=seed)
+            if errs:
+                return False
+    except oracle.OracleError:
+        return False
+    return True
+
+
+def test_unmutated_passes():
+    assert run_pins()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert old in src, "mutation site not found: " + name
+    mut = tmp_path / ("oracle_%s.c" % name)
+    mut.write_text(src.replace(old, new, 1))
+    so = tmp_path / ("liboracle_%s.so" % name)
+    subprocess.check_call(["gcc", "-O1", "-fPIC", "-shared", "-o", str(so), str(mut)])
+    prev = oracle.use_library(str(so))
+    try:
+        assert not run_pins(), "the pins did not catch mutant " + name
+    finally:
+        oracle.restore_library(prev)
