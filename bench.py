@@ -55,6 +55,21 @@ def algorithmic_bytes(cfgs, want):
     return tot
 
 
+TUNED = os.path.join(ROOT, "paper_2406_13881_amd", "tuned.json")
+
+
+def load_tuned():
+    try:
+        return json.load(open(TUNED))
+    except (OSError, ValueError):
+        return {}
+
+
+def save_tuned(d):
+    with open(TUNED, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+
+
 def cpu_baseline(cfgs, seconds, threads):
     """The oracle as it stands, one CFG per thread, on the first CFGs of the
     batch until `seconds` of wall time have been used."""
@@ -88,7 +103,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=4096, help="CFGs in the batch")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="re-run the autotuner and store its choice in paper_2406_13881_amd/tuned.json")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-single", action="store_true")
@@ -115,10 +131,20 @@ def main():
     want = ompd.OUTPUTS
     rb = ResidentBatch(ctx, cfgs, want=want)
     stream = torch.cuda.current_stream().cuda_stream
-    if not args.no_autotune:
+    tuned = load_tuned()
+    key = "batch%d" % len(cfgs)
+    if args.autotune:
         t = time.perf_counter()
         best = rb.plan.autotune(stream, trials=2)
+        d = json.loads(rb.plan.describe())
+        tuned[key] = {k: d[k] for k in ("lds_bytes", "max_ns", "min_tbits", "wg_per_cu")}
+        tuned[key]["best_ms"] = best
+        save_tuned(tuned)
         log("autotune: best %.3f ms in %.1f s -> %s" % (best, time.perf_counter() - t, rb.plan.describe()))
+    elif key in tuned:
+        c = tuned[key]
+        rb.plan.configure(c["lds_bytes"], c["max_ns"], c["min_tbits"], c["wg_per_cu"])
+        log("using the stored autotuner choice %s" % c)
     plan_desc = json.loads(rb.plan.describe())
     for _ in range(args.warmup):
         rb.run(stream)
@@ -187,7 +213,14 @@ def main():
     if not args.no_single:
         c2 = synth.c2(0)
         sb = ResidentBatch(ctx, [c2], want=want)
-        sb.plan.autotune(stream, trials=1)
+        if "single" in tuned:
+            c = tuned["single"]
+            sb.plan.configure(c["lds_bytes"], c["max_ns"], c["min_tbits"], c["wg_per_cu"])
+        elif args.autotune:
+            sb.plan.autotune(stream, trials=1)
+            d = json.loads(sb.plan.describe())
+            tuned["single"] = {k: d[k] for k in ("lds_bytes", "max_ns", "min_tbits", "wg_per_cu")}
+            save_tuned(tuned)
         for _ in range(2):
             sb.run(stream)
         torch.cuda.synchronize()

@@ -177,6 +177,11 @@ int ompd_plan_status(ompd_plan* plan, int32_t* per_cfg);
  * workgroups per CU) `trials` times on `stream` and keeps the fastest.
  * Results are bit-identical for every candidate.  best_ms may be NULL. */
 int ompd_plan_autotune(ompd_plan* plan, void* stream, int32_t trials, float* best_ms);
+/* Set the launch configuration by hand (what the autotuner chooses among):
+ * LDS bytes per solve workgroup (0 = automatic), most bit-slices per tile,
+ * narrowest slice width (8, 16 or 32 bits), workgroups per CU (0 = as many
+ * as fit).  OMPD_E_NOMEM if a CFG does not fit the LDS budget. */
+int ompd_plan_configure(ompd_plan* plan, int64_t lds_bytes, int32_t max_ns, int32_t min_tbits, int32_t wg_per_cu);
 /* Describe the plan's current configuration as a NUL-terminated string. */
 int ompd_plan_describe(ompd_plan* plan, char* buf, int32_t len);
 /* Duration (ms) of the last ompd_plan_run measured with HIP events on its
@@ -195,6 +200,9 @@ void ompd_plan_destroy(ompd_plan* plan);
  * limit). */
 int ompd_submit(ompd_ctx* ctx, const ompd_cfg* cfg, ompd_result* res, uint32_t flags, ompd_ticket* out);
 int ompd_poll(ompd_ctx* ctx, ompd_ticket t, int* done);
+/* As ompd_poll; when done, *done_ns (may be NULL) is the completion time on
+ * the host's monotonic clock (CLOCK_MONOTONIC, nanoseconds). */
+int ompd_poll_ex(ompd_ctx* ctx, ompd_ticket t, int* done, int64_t* done_ns);
 int ompd_wait(ompd_ctx* ctx, ompd_ticket t, int64_t timeout_ns, int* done);
 /* Serving counters: admitted, completed, in flight, bytes in use. */
 int ompd_serving_stats(ompd_ctx* ctx, int64_t* admitted, int64_t* completed, int64_t* in_flight,

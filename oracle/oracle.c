@@ -71,6 +71,7 @@ typedef struct {
     const uint64_t* ev[2]; const uint64_t* lx[2];
     const int32_t* call; const uint64_t* sums;
     uint64_t lastmask;
+    int summary_mode;
     int32_t* rpo;  /* reverse post-order from ENTRY */
 } G;
 
@@ -164,7 +165,7 @@ static int validate_and_prepare(G* g)
             g->R[ix(g, g->exit, w)] | g->W[ix(g, g->exit, w)]) return OR_EINVAL;
         uint64_t pad = ~vmask(g, w);
         if ((g->ev[0][w] | g->ev[1][w] | g->lx[0][w] | g->lx[1][w]) & pad) return OR_EINVAL;
-        if (((g->ev[0][w] | g->ev[1][w]) & vmask(g, w)) != vmask(g, w)) return OR_EINVAL;
+        if (!g->summary_mode && ((g->ev[0][w] | g->ev[1][w]) & vmask(g, w)) != vmask(g, w)) return OR_EINVAL;
     }
     for (int b = 0; b < nb; ++b)
         for (int w = 0; w < g->wd; ++w)
@@ -481,7 +482,10 @@ static int64_t phase_avf(const G* g, const uint64_t* nu[2], uint64_t* const ins_
  *   lx_h/lx_d  : next use after EXIT (liveness after the region)        [wd]
  *   call       : [n_blocks] summary index for call blocks, -1 otherwise (NULL = no calls)
  *   sums       : [n_summaries][SUM_ROWS][wd]
- *   placement  : 0 = delayed placement (LATER), 1 = eager placement only
+ *   placement  : bit 0: 0 = delayed placement (LATER), 1 = eager placement only;
+ *                bit 8: evaluate a procedure summary — the boundary may leave a
+ *                variable valid in neither space (a summary's entry-validity
+ *                argument ranges over all of {0,1} per space)
  * Outputs (caller-owned; every pointer required):
  *   nu_*[nb*wd] NUin, ave_*[nb*wd] AVEin, avf_*[nb*wd] AVFin,
  *   ins_entry_*[nb*wd] copy into that space just before block b,
@@ -507,6 +511,8 @@ int oracle_solve(int32_t nb, int32_t ne, int32_t nv, int32_t entry, int32_t exit
     g.ev[0] = ev_h; g.ev[1] = ev_d; g.lx[0] = lx_h; g.lx[1] = lx_d;
     g.call = call; g.sums = sums;
     g.lastmask = (nv % 64) ? ((1ull << (nv % 64)) - 1ull) : ~0ull;
+    g.summary_mode = (placement >> 8) & 1;
+    placement &= 1;
     int rc = validate_and_prepare(&g);
     if (rc != OR_OK) { free(g.pp); free(g.pi); free(g.pe); free(g.rpo); return rc; }
 

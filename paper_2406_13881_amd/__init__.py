@@ -121,11 +121,13 @@ def lib():
             L.ompd_plan_status.argtypes = [_vp, _vp]
             L.ompd_plan_autotune.argtypes = [_vp, _vp, _i32, P(ctypes.c_float)]
             L.ompd_plan_describe.argtypes = [_vp, ctypes.c_char_p, _i32]
+            L.ompd_plan_configure.argtypes = [_vp, ctypes.c_int64, _i32, _i32, _i32]
             L.ompd_plan_last_ms.argtypes = [_vp, P(ctypes.c_float), P(ctypes.c_float)]
             L.ompd_plan_destroy.argtypes = [_vp]
             L.ompd_plan_destroy.restype = None
             L.ompd_submit.argtypes = [_vp, P(_Cfg), P(_Res), ctypes.c_uint32, P(ctypes.c_uint64)]
             L.ompd_poll.argtypes = [_vp, ctypes.c_uint64, P(ctypes.c_int)]
+            L.ompd_poll_ex.argtypes = [_vp, ctypes.c_uint64, P(ctypes.c_int), P(ctypes.c_int64)]
             L.ompd_wait.argtypes = [_vp, ctypes.c_uint64, ctypes.c_int64, P(ctypes.c_int)]
             L.ompd_serving_stats.argtypes = [_vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64),
                                              P(ctypes.c_int64)]
@@ -282,6 +284,72 @@ class Context:
         return outs
 
 
+class Request:
+    """A submitted analysis request (ompd_submit): the host buffers its
+    results land in stay referenced here until the request is collected."""
+
+    def __init__(self, ctx: "Context", cfg, flags: int = 0, want: Sequence[str] = OUTPUTS):
+        self.ctx = ctx
+        self._keep: list = []
+        self._C = _cfg_struct(cfg, self._keep)
+        self.out = _alloc_outputs(cfg, want)
+        self._R = _res_struct(self.out)
+        t = ctypes.c_uint64(0)
+        rc = lib().ompd_submit(ctx.h, ctypes.byref(self._C), ctypes.byref(self._R), int(flags), ctypes.byref(t))
+        self.rc = rc
+        self.ticket = t.value
+        self.done = False
+        self.done_ns = 0
+        self.status = 0
+
+    @property
+    def admitted(self) -> bool:
+        return self.rc == 0
+
+    def poll(self) -> bool:
+        """True once the request has completed (raises on its error)."""
+        if self.done:
+            return True
+        d = ctypes.c_int(0)
+        ns = ctypes.c_int64(0)
+        _check(lib().ompd_poll_ex(self.ctx.h, ctypes.c_uint64(self.ticket), ctypes.byref(d), ctypes.byref(ns)))
+        if d.value == 0:
+            return False
+        self.done = True
+        self.done_ns = ns.value
+        self.status = 0 if d.value == 1 else d.value
+        self.out["sweeps"] = np.array(list(self._R.sweeps), dtype=np.int32)
+        if self.status:
+            raise OmpdError(self.status, "request failed")
+        return True
+
+    def wait(self, timeout_s: float = -1.0) -> Dict[str, np.ndarray]:
+        if not self.done:
+            d = ctypes.c_int(0)
+            _check(lib().ompd_wait(self.ctx.h, ctypes.c_uint64(self.ticket),
+                                   int(timeout_s * 1e9) if timeout_s >= 0 else -1, ctypes.byref(d)))
+            self.done = True
+            self.status = 0 if d.value == 1 else d.value
+            self.out["sweeps"] = np.array(list(self._R.sweeps), dtype=np.int32)
+            if self.status:
+                raise OmpdError(self.status, "request failed")
+        return self.out
+
+
+def submit(ctx: "Context", cfg, flags: int = 0, want: Sequence[str] = OUTPUTS) -> Request:
+    """ompd_submit; check .admitted (False = OMPD_E_BUSY, retry later)."""
+    r = Request(ctx, cfg, flags, want)
+    if r.rc not in (0, OMPD_E_BUSY):
+        _check(r.rc)
+    return r
+
+
+def serving_stats(ctx: "Context") -> Dict[str, int]:
+    a, c, f, b = (ctypes.c_int64(0) for _ in range(4))
+    _check(lib().ompd_serving_stats(ctx.h, ctypes.byref(a), ctypes.byref(c), ctypes.byref(f), ctypes.byref(b)))
+    return {"admitted": a.value, "completed": c.value, "in_flight": f.value, "bytes_in_use": b.value}
+
+
 def ctx_create(device: int = 0, budget_bytes: int = 0) -> Context:
     return Context(device, budget_bytes)
 
@@ -347,6 +415,9 @@ class Plan:
         best = ctypes.c_float(0)
         _check(lib().ompd_plan_autotune(self.h, _vp(stream) if stream else None, int(trials), ctypes.byref(best)))
         return best.value
+
+    def configure(self, lds_bytes: int = 0, max_ns: int = 16, min_tbits: int = 8, wg_per_cu: int = 0):
+        _check(lib().ompd_plan_configure(self.h, int(lds_bytes), int(max_ns), int(min_tbits), int(wg_per_cu)))
 
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(1024)

@@ -51,8 +51,14 @@ struct DevCfg {
     uint64_t* mayp_h;   uint64_t* mayp_d;
     int32_t* pred_ptr;  int32_t* pred_idx; int32_t* pred_eid;
     int32_t* level_ptr; int32_t* level_blk; int32_t* tmp;
+    int32_t* rec_f;     // [2*nb] int4: level-ordered records with predecessors
+    int32_t* rec_b;     // [2*nb] int4: level-ordered records with successors
     int32_t* info;
 };
+
+// record meta word: neighbour count | flags
+constexpr uint32_t REC_COUNT = 0x00FFFFFFu;
+constexpr uint32_t REC_ENTRY = 1u << 24, REC_EXIT = 1u << 25, REC_DEV = 1u << 26, REC_CALL = 1u << 27;
 
 // A tile: one CFG, a range of bit-slices of width tbits (8, 16 or 32).
 struct Tile {

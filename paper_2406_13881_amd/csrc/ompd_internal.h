@@ -52,13 +52,26 @@ struct ompd_plan {
     int max_nb = 2;
     size_t lds_solve = 0, lds_prep = 0;
     int grid_solve = 1;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t g_prep = nullptr, g_solve = nullptr;
+    hipGraphExec_t gx_prep = nullptr, gx_solve = nullptr;
     hipStream_t last_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
 };
 
 int ompd_fail(int code, const std::string& msg);
+
+struct ScratchOff {
+    size_t aveout, mayp, nu, ave, ie, ig, avf, bnd, pp, pi, pe, lvp, lvb, tmp, recf, recb, info;
+};
+size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o);
+void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const ScratchOff& o, uint32_t flags,
+                      ompd::DevCfg& d, uint64_t* bnd_host);
+struct PlanConfig;
+int ompd_make_plan_tiles(ompd_ctx* ctx, const std::vector<ompd::DevCfg>& cfgs, const PlanConfig& pc,
+                         std::vector<ompd::Tile>& tiles, size_t& lds_solve, size_t& lds_prep, int& grid_solve);
+int ompd_launch_prep(const ompd::DevCfg* d_cfgs, int n, int32_t* d_counter, size_t lds, hipStream_t s);
+int ompd_launch_solve(const ompd::DevCfg* d_cfgs, const ompd::Tile* d_tiles, int n_tiles, int32_t* d_counter,
+                      int grid, size_t lds, hipStream_t s);
 size_t ompd_tile_lds(int nb, int ns, int tbits);
 int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n, uint32_t flags,
                     const PlanConfig& pc, ompd_plan** out);

@@ -33,6 +33,16 @@
 
 namespace ompd {
 
+// Views of generic pointers as global-memory pointers: loads and stores
+// through them compile to global_load/global_store, which only count
+// against vmcnt, so a wait for LDS does not also drain outstanding
+// global prefetches (flat accesses would count against both).
+#define GAS __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const GAS T* G(const T* p) { return (const GAS T*)p; }
+template <typename T>
+__device__ __forceinline__ GAS T* G(T* p) { return (GAS T*)p; }
+
 __device__ __forceinline__ void set_status(int32_t* info, int32_t code)
 {
     atomicCAS(&info[INFO_STATUS], 0, code);
@@ -108,6 +118,8 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
     }
     for (int e = c.succ_ptr[c.entry] + tid; e < c.succ_ptr[c.entry + 1]; e += nt)
         if (c.kind[e] == 1) err = 1;
+    for (int b = tid; b < nb; b += nt)
+        if (c.succ_ptr[b + 1] - c.succ_ptr[b] > (int)REC_COUNT) err = 1;
     if (wd > 0) {
         const uint64_t last = (c.nv & 63) ? ((1ull << (c.nv & 63)) - 1ull) : ~0ull;
         for (int w = tid; w < wd; w += nt) {
@@ -204,12 +216,54 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
         int pos = atomicAdd(&hist[lvl[b]], 1);
         c.level_blk[pos] = b;
     }
+    __syncthreads();
+    // level-ordered records: block, flags, first two predecessors / successors
+    // with their edge ids (LOOP_ENTRY in bit 31), and the CSR start of the rest
+    int4* RF = reinterpret_cast<int4*>(c.rec_f);
+    int4* RB = reinterpret_cast<int4*>(c.rec_b);
+    for (int pos = tid; pos < nb; pos += nt) {
+        const int b = c.level_blk[pos];
+        uint32_t fl = (b == c.entry ? REC_ENTRY : 0u) | (b == c.exit ? REC_EXIT : 0u) | (c.space[b] ? REC_DEV : 0u) |
+                      ((c.call && c.call[b] >= 0) ? REC_CALL : 0u);
+        int a = pp[b], cnt = pp[b + 1] - a;
+        int e0 = cnt > 0 ? c.pred_eid[a] : 0, e1 = cnt > 1 ? c.pred_eid[a + 1] : 0;
+        int4 r0, r1;
+        r0.x = b;
+        r0.y = (int)((uint32_t)cnt | fl);
+        r0.z = cnt > 0 ? c.pred_idx[a] : 0;
+        r0.w = cnt > 1 ? c.pred_idx[a + 1] : 0;
+        r1.x = (int)((uint32_t)e0 | ((cnt > 0 && c.kind[e0] == 2) ? 0x80000000u : 0u));
+        r1.y = (int)((uint32_t)e1 | ((cnt > 1 && c.kind[e1] == 2) ? 0x80000000u : 0u));
+        r1.z = a;
+        r1.w = lvl[b];
+        RF[2 * pos] = r0;
+        RF[2 * pos + 1] = r1;
+        a = c.succ_ptr[b];
+        cnt = c.succ_ptr[b + 1] - a;
+        r0.y = (int)((uint32_t)cnt | fl);
+        r0.z = cnt > 0 ? c.succ_idx[a] : 0;
+        r0.w = cnt > 1 ? c.succ_idx[a + 1] : 0;
+        r1.x = a;
+        r1.y = a + 1;
+        r1.z = a;
+        r1.w = lvl[b];
+        RB[2 * pos] = r0;
+        RB[2 * pos + 1] = r1;
+    }
     if (tid == 0) c.info[INFO_NLEVELS] = nL;
 }
 
 // --------------------------------------------------------------------------
 // solve
 // --------------------------------------------------------------------------
+// Level-ordered record of one block (32 bytes): its first two neighbours
+// (predecessors for forward phases, successors for the backward phase) with
+// their edge ids inline, so one load per item replaces the chain
+// level list -> CSR pointer -> CSR entry.
+//   meta = neighbour count (24 bits) | ENTRY<<24 | EXIT<<25 | DEVICE<<26 | CALL<<27
+//   e0/e1 = successor-CSR edge id | LOOP_ENTRY<<31
+//   ovf = start of the full neighbour list in the CSR (for neighbours 2..)
+//   lvl = the block's level
 template <typename T>
 struct Tv {
     const DevCfg& c;
@@ -217,27 +271,40 @@ struct Tv {
     __device__ __forceinline__ size_t row(int b, int k) const { return (size_t)b * RW + s0 + k; }
     __device__ __forceinline__ T ld(const uint64_t* p, int b, int k) const
     {
-        return reinterpret_cast<const T*>(p)[row(b, k)];
+        return G(reinterpret_cast<const T*>(p))[row(b, k)];
     }
     __device__ __forceinline__ void st(uint64_t* p, int b, int k, T v) const
     {
-        reinterpret_cast<T*>(p)[row(b, k)] = v;
+        G(reinterpret_cast<T*>(p))[row(b, k)] = v;
     }
     __device__ __forceinline__ T vec(const uint64_t* p, int k) const
     {
-        return reinterpret_cast<const T*>(p)[s0 + k];
+        return G(reinterpret_cast<const T*>(p))[s0 + k];
     }
     __device__ __forceinline__ T sum(int ci, int r, int k) const
     {
-        return reinterpret_cast<const T*>(c.sums)[((size_t)ci * SUM_ROWS + r) * RW + s0 + k];
+        return G(reinterpret_cast<const T*>(c.sums))[((size_t)ci * SUM_ROWS + r) * RW + s0 + k];
     }
 };
 
 template <typename T>
 __device__ __forceinline__ T ones() { return (T)~(T)0; }
 
+// Per-item data fetched one step ahead of its use (everything a sweep needs
+// that does not change while the phase iterates).
 template <typename T>
-__device__ bool solve_tile(const DevCfg& c, int s0, int ns, uint8_t* lds)
+struct Item {
+    int b, k, lvl;
+    uint32_t meta;
+    int n0, n1;
+    uint32_t e0, e1;
+    int ovf;
+    T vm;        // valid-variable mask of the item's slice
+    T x[12];
+};
+
+template <typename T>
+__device__ __forceinline__ bool solve_tile(const DevCfg& c, int s0, int ns, uint8_t* lds)
 {
     constexpr int BITS = 8 * (int)sizeof(T);
     const int lane = threadIdx.x;
@@ -250,18 +317,20 @@ __device__ bool solve_tile(const DevCfg& c, int s0, int ns, uint8_t* lds)
     T* SD = SH + (size_t)nb * nsi;
     uint8_t* FL = lds + ((2 * (size_t)nb * nsi * sizeof(T) + 15) & ~(size_t)15);
     uint32_t* ACC = reinterpret_cast<uint32_t*>(FL + ((nb + 15) & ~15));
-    const int nL = c.info[INFO_NLEVELS];
-    const int32_t* __restrict__ lp = c.level_ptr;
-    const int32_t* __restrict__ lb = c.level_blk;
-    const int32_t* __restrict__ sp = c.succ_ptr;
-    const int32_t* __restrict__ si = c.succ_idx;
-    const int32_t* __restrict__ pp = c.pred_ptr;
-    const int32_t* __restrict__ pi = c.pred_idx;
-    const int32_t* __restrict__ pe = c.pred_eid;
-    const uint8_t* __restrict__ kind = c.kind;
-    const uint8_t* __restrict__ space = c.space;
+    const int nL = G(c.info)[INFO_NLEVELS];
+    const GAS int32_t* __restrict__ lp = G(c.level_ptr);
+    const GAS int32_t* __restrict__ RF = G(c.rec_f);
+    const GAS int32_t* __restrict__ RB = G(c.rec_b);
+    const GAS int32_t* __restrict__ sp = G(c.succ_ptr);
+    const GAS int32_t* __restrict__ si = G(c.succ_idx);
+    const GAS int32_t* __restrict__ pi = G(c.pred_idx);
+    const GAS int32_t* __restrict__ pe = G(c.pred_eid);
+    const GAS uint8_t* __restrict__ kind = G(c.kind);
+    const GAS uint8_t* __restrict__ space = G(c.space);
+    const GAS int32_t* __restrict__ callv = G(c.call);
     const Tv<T> tv{c, s0, RW};
     const int cap = c.sweep_cap > 0 ? c.sweep_cap : 2 * nb + 2;
+    constexpr uint32_t M_ENTRY = REC_ENTRY, M_EXIT = REC_EXIT, M_DEV = REC_DEV, M_CALL = REC_CALL;
 
     auto vmask = [&](int k) -> T {
         long lo = (long)(s0 + k) * BITS;
@@ -269,31 +338,32 @@ __device__ bool solve_tile(const DevCfg& c, int s0, int ns, uint8_t* lds)
         if (lo >= c.nv) return (T)0;
         return (T)((1u << (unsigned)(c.nv - lo)) - 1u);
     };
-    auto is_call = [&](int b) -> int { return c.call ? c.call[b] : -1; };
+    auto sidx = [&](int b, int k) -> int { return (b << lg) + k; };
     // USE_s(b): a read in block b when b lies in space s; at EXIT the liveness after the region
     auto use = [&](int s, int b, int k) -> T {
         if (b == c.exit) return tv.vec(s ? c.lx_d : c.lx_h, k);
         T r = tv.ld(c.R, b, k);
         return ((int)space[b] == s) ? r : (T)0;
     };
-    // USE'_s(b): call blocks whose callee may touch the variable stop pending copies like a read
-    auto use_stop = [&](int s, int b, int k) -> T {
+    // USE'_s(b): a call whose callee may touch the variable stops pending copies like a read
+    auto use_stop = [&](int s, int b, int k, bool call) -> T {
         T u = use(s, b, k);
-        int ci = is_call(b);
-        if (ci >= 0)
+        if (call) {
+            int ci = callv[b];
             u |= tv.sum(ci, s ? SUM_MAYR_D : SUM_MAYR_H, k) | tv.sum(ci, SUM_MAYW_H, k) | tv.sum(ci, SUM_MAYW_D, k);
+        }
         return u;
     };
     auto wr = [&](int s, int b, int k) -> T {
         if (b == c.exit) return (T)0;
         return ((int)space[b] == s) ? tv.ld(c.W, b, k) : (T)0;
     };
-    // validity transfer of a block (write here: valid here; write in the other space: stale here)
-    auto valid_out = [&](int s, int b, int k, T in) -> T {
-        T w = (b == c.exit) ? (T)0 : tv.ld(c.W, b, k);
-        T a1 = ((int)space[b] == s) ? (T)(in | w) : (T)(in & ~w);
-        int ci = is_call(b);
-        if (ci >= 0) {
+    // validity transfer: write here -> valid here; write in the other space -> stale here;
+    // a call applies the callee's exit-validity table T_s[valid after own accesses][next use after the call]
+    auto valid_out = [&](int s, int b, int k, T in, T w, bool dev, bool call, T vm) -> T {
+        T a1 = (dev == (s == 1)) ? (T)(in | w) : (T)(in & ~w);
+        if (call) {
+            int ci = callv[b];
             const uint64_t* nus = s ? c.nu_d : c.nu_h;
             T l = 0;
             for (int e = sp[b]; e < sp[b + 1]; ++e) l |= tv.ld(nus, si[e], k);
@@ -302,24 +372,73 @@ __device__ bool solve_tile(const DevCfg& c, int s0, int ns, uint8_t* lds)
             T t10 = tv.sum(ci, base + 2, k), t11 = tv.sum(ci, base + 3, k);
             a1 = (T)((~a1 & ~l & t00) | (~a1 & l & t01) | (a1 & ~l & t10) | (a1 & l & t11));
         }
-        return (T)(a1 & vmask(k));
+        return (T)(a1 & vm);
+    };
+    // i-th neighbour (pred or succ) of an item beyond the two inline ones
+    auto nb_pred = [&](const Item<T>& it, int j, int& p, int& e) {
+        if (j == 0) { p = it.n0; e = (int)it.e0; return; }
+        if (j == 1) { p = it.n1; e = (int)it.e1; return; }
+        p = pi[it.ovf + j];
+        e = pe[it.ovf + j];
+        e |= (kind[e] == 2) ? (int)0x80000000 : 0;
+    };
+    auto nb_succ = [&](const Item<T>& it, int j) -> int {
+        if (j == 0) return it.n0;
+        if (j == 1) return it.n1;
+        return si[it.ovf + j];
     };
 
-    // sweep driver: forward (levels ascending) or backward (descending)
-    auto run_phase = [&](int phase, bool backward, auto&& item) -> bool {
+    // Pipelined sweep over the levels: the records and constants of the next
+    // step are loaded while the current step computes from LDS.
+    // The (position, slice) items of a sweep, in level order, are cut into
+    // chunks of 64 consecutive items; a chunk usually spans several narrow
+    // levels, which the wavefront evaluates one after another as masked
+    // passes.  Chunks are loaded two ahead of their use, so one global round
+    // trip serves several levels and overlaps with the work of two chunks.
+    const int n_items = nb << lg;
+    const int n_chunks = (n_items + 63) >> 6;
+    auto sweep = [&](bool backward, auto&& fetch, auto&& compute) -> bool {
+        const GAS int32_t* __restrict__ REC = backward ? RB : RF;
+        auto load = [&](int ch) -> Item<T> {
+            Item<T> it;
+            it.k = -1;
+            if (ch < 0 || ch >= n_chunks) return it;
+            int i = (ch << 6) + lane;
+            if (i < n_items) {
+                const GAS int32_t* r = REC + 8 * (size_t)(i >> lg);
+                it.b = r[0]; it.meta = (uint32_t)r[1]; it.n0 = r[2]; it.n1 = r[3];
+                it.e0 = (uint32_t)r[4]; it.e1 = (uint32_t)r[5]; it.ovf = r[6]; it.lvl = r[7];
+                it.k = i & (nsi - 1);
+                it.vm = vmask(it.k);
+                fetch(it);
+            }
+            return it;
+        };
+        const int step = backward ? -1 : 1;
+        int ch = backward ? n_chunks - 1 : 0;
+        bool changed = false;
+        Item<T> cur = load(ch), nx1 = load(ch + step);
+        for (int t = 0; t < n_chunks; ++t, ch += step) {
+            Item<T> nx2 = load(ch + 2 * step);
+            // levels present in this chunk (items are in level order)
+            const int last = min(63, n_items - 1 - (ch << 6));
+            const int lo = __shfl(cur.lvl, 0, 64), hi = __shfl(cur.lvl, last, 64);
+            if (!backward) {
+                for (int l = lo; l <= hi; ++l)
+                    if (cur.k >= 0 && cur.lvl == l) changed |= compute(cur);
+            } else {
+                for (int l = hi; l >= lo; --l)
+                    if (cur.k >= 0 && cur.lvl == l) changed |= compute(cur);
+            }
+            cur = nx1;
+            nx1 = nx2;
+        }
+        return changed;
+    };
+    auto run_phase = [&](int phase, bool backward, auto&& fetch, auto&& compute) -> bool {
         int sweeps = 0;
         for (;;) {
-            bool changed = false;
-            for (int li = 0; li < nL; ++li) {
-                const int l = backward ? (nL - 1 - li) : li;
-                const int a = lp[l];
-                const int n = (lp[l + 1] - a) << lg;
-                for (int i = lane; i < n; i += 64) {
-                    const int b = lb[a + (i >> lg)];
-                    const int k = i & (nsi - 1);
-                    changed |= item(b, k);
-                }
-            }
+            bool changed = sweep(backward, fetch, compute);
             ++sweeps;
             if (__ballot(changed) == 0ull) break;
             if (sweeps >= cap) {
@@ -327,14 +446,36 @@ __device__ bool solve_tile(const DevCfg& c, int s0, int ns, uint8_t* lds)
                 return false;
             }
         }
-        if (lane == 0) atomicMax(&c.info[INFO_SWEEPS + phase], sweeps);
+        if (lane == 0) atomicMax(&c.info[INFO_SWEEPS + phase], sweeps);   // flat atomic: once per phase
         return true;
     };
-    auto for_all_items = [&](auto&& f) {
+    // Streaming pass over all items in level order (outputs), also pipelined.
+    auto for_all = [&](auto&& fetch, auto&& f) {
         const int n = nb << lg;
-        for (int i = lane; i < n; i += 64) f(i >> lg, i & (nsi - 1));
+        auto load = [&](int c0) -> Item<T> {
+            Item<T> it;
+            int i = c0 + lane;
+            it.k = -1;
+            if (i < n) {
+                const GAS int32_t* r = RF + 8 * (size_t)(i >> lg);
+                it.b = r[0]; it.meta = (uint32_t)r[1]; it.n0 = r[2]; it.n1 = r[3];
+                it.e0 = (uint32_t)r[4]; it.e1 = (uint32_t)r[5]; it.ovf = r[6];
+                it.k = i & (nsi - 1);
+                it.vm = vmask(it.k);
+                fetch(it);
+            }
+            return it;
+        };
+        Item<T> cur = load(0);
+        for (int c0 = 0; c0 < n; c0 += 64) {
+            Item<T> nxt;
+            nxt.k = -1;
+            if (c0 + 64 < n) nxt = load(c0 + 64);
+            if (cur.k >= 0) f(cur);
+            cur = nxt;
+        }
     };
-    auto sidx = [&](int b, int k) -> size_t { return ((size_t)b << lg) + k; };
+    auto no_fetch = [](Item<T>&) {};
 
     // ---------------------------------------------------------------- init
     for (int i = lane; i < (nb << lg); i += 64) { SH[i] = 0; SD[i] = 0; }
@@ -346,112 +487,143 @@ __device__ bool solve_tile(const DevCfg& c, int s0, int ns, uint8_t* lds)
     __syncthreads();
 
     // ---------------------------------------------------------------- next use (backward, may)
-    // NUin_s(b) = USE_s(b) | (NUout_s(b) & ~W_b), NUout_s = OR over successors.
+    // NUin_s(b) = gen_s | (pass_s & OR over successors NUin_s(q)), with gen = USE_s and
+    // pass = ~W for a plain block, gen = USE_s | (~W & NU0_s), pass = ~W & NU1_s for a call,
+    // gen = the liveness after the region and pass = 0 at EXIT.
     // Flags bits 0/1: reaches EXIT / reaches a DEVICE block (before_dev).
-    if (!run_phase(PH_NU, true, [&](int b, int k) -> bool {
-            bool ch = false;
-            if (data) {
-                T oH = 0, oD = 0;
-                for (int e = sp[b]; e < sp[b + 1]; ++e) {
-                    int q = si[e];
-                    oH |= SH[sidx(q, k)];
-                    oD |= SD[sidx(q, k)];
+    if (!run_phase(PH_NU, true,
+            [&](Item<T>& it) {
+                if (!data) return;
+                const int b = it.b, k = it.k;
+                if (it.meta & M_EXIT) {
+                    it.x[0] = tv.vec(c.lx_h, k); it.x[1] = tv.vec(c.lx_d, k);
+                    it.x[2] = 0; it.x[3] = 0;
+                    return;
                 }
-                T vH, vD;
-                if (b == c.exit) {
-                    vH = tv.vec(c.lx_h, k);
-                    vD = tv.vec(c.lx_d, k);
+                T r = tv.ld(c.R, b, k), w = tv.ld(c.W, b, k);
+                T uH = (it.meta & M_DEV) ? (T)0 : r, uD = (it.meta & M_DEV) ? r : (T)0;
+                if (it.meta & M_CALL) {
+                    int ci = callv[b];
+                    it.x[0] = uH | (~w & tv.sum(ci, SUM_NU0_H, k));
+                    it.x[1] = uD | (~w & tv.sum(ci, SUM_NU0_D, k));
+                    it.x[2] = ~w & tv.sum(ci, SUM_NU1_H, k);
+                    it.x[3] = ~w & tv.sum(ci, SUM_NU1_D, k);
                 } else {
-                    T r = tv.ld(c.R, b, k), w = tv.ld(c.W, b, k);
-                    T uH = space[b] ? (T)0 : r, uD = space[b] ? r : (T)0;
-                    int ci = is_call(b);
-                    if (ci >= 0) {
-                        vH = uH | (~w & (tv.sum(ci, SUM_NU0_H, k) | (tv.sum(ci, SUM_NU1_H, k) & oH)));
-                        vD = uD | (~w & (tv.sum(ci, SUM_NU0_D, k) | (tv.sum(ci, SUM_NU1_D, k) & oD)));
-                    } else {
-                        vH = uH | (oH & ~w);
-                        vD = uD | (oD & ~w);
-                    }
+                    it.x[0] = uH; it.x[1] = uD; it.x[2] = ~w; it.x[3] = ~w;
                 }
-                T m = vmask(k);
-                vH &= m; vD &= m;
-                size_t li = sidx(b, k);
-                if (vH != SH[li]) { SH[li] = vH; ch = true; }
-                if (vD != SD[li]) { SD[li] = vD; ch = true; }
-            }
-            if (k == 0) {
-                uint8_t f = FL[b], g = 0;
-                for (int e = sp[b]; e < sp[b + 1]; ++e) g |= FL[si[e]];
-                uint8_t nf = (uint8_t)(f | (g & 3));
-                if (nf != f) { FL[b] = nf; ch = true; }
-            }
-            return ch;
-        }))
+            },
+            [&](Item<T>& it) -> bool {
+                const int b = it.b, k = it.k;
+                const int cnt = (int)(it.meta & REC_COUNT);
+                bool ch = false;
+                if (data) {
+                    T oH = 0, oD = 0;
+                    for (int j = 0; j < cnt; ++j) {
+                        int q = nb_succ(it, j);
+                        oH |= SH[sidx(q, k)];
+                        oD |= SD[sidx(q, k)];
+                    }
+                    T m = it.vm;
+                    T vH = (it.x[0] | (it.x[2] & oH)) & m;
+                    T vD = (it.x[1] | (it.x[3] & oD)) & m;
+                    int li = sidx(b, k);
+                    if (vH != SH[li]) { SH[li] = vH; ch = true; }
+                    if (vD != SD[li]) { SD[li] = vD; ch = true; }
+                }
+                if (k == 0) {
+                    uint8_t f = FL[b], g = 0;
+                    for (int j = 0; j < cnt; ++j) g |= FL[nb_succ(it, j)];
+                    uint8_t nf = (uint8_t)(f | (g & 3));
+                    if (nf != f) { FL[b] = nf; ch = true; }
+                }
+                return ch;
+            }))
         return false;
     if (data)
-        for_all_items([&](int b, int k) {
-            tv.st(c.nu_h, b, k, SH[sidx(b, k)]);
-            tv.st(c.nu_d, b, k, SD[sidx(b, k)]);
+        for_all(no_fetch, [&](const Item<T>& it) {
+            tv.st(c.nu_h, it.b, it.k, SH[sidx(it.b, it.k)]);
+            tv.st(c.nu_d, it.b, it.k, SD[sidx(it.b, it.k)]);
         });
     __syncthreads();
 
     // ---------------------------------------------------------------- validity with eager copies
     // AVEin_s(q) = NUin_s(q) | AND over preds AVEout_s(p); AVEin(ENTRY) = boundary.
     // Flags bits 2/3: reached from ENTRY / reached from a DEVICE block (after_dev).
-    auto ave_in = [&](int q, int k, T& iH, T& iD) {
-        if (q == c.entry) {
-            iH = tv.vec(c.ev_h, k);
-            iD = tv.vec(c.ev_d, k);
+    auto fetch_gen_w = [&](Item<T>& it, const uint64_t* gh, const uint64_t* gd) {
+        if (!data) return;
+        if (it.meta & M_ENTRY) {
+            it.x[0] = tv.vec(c.ev_h, it.k); it.x[1] = tv.vec(c.ev_d, it.k);
+        } else {
+            it.x[0] = tv.ld(gh, it.b, it.k); it.x[1] = tv.ld(gd, it.b, it.k);
+        }
+        it.x[2] = (it.meta & M_EXIT) ? (T)0 : tv.ld(c.W, it.b, it.k);
+    };
+    auto ave_in = [&](const Item<T>& it, T& iH, T& iD) {
+        const int k = it.k;
+        if (it.meta & M_ENTRY) {
+            iH = it.x[0]; iD = it.x[1];
         } else {
             T mH = ones<T>(), mD = ones<T>();
-            for (int j = pp[q]; j < pp[q + 1]; ++j) {
-                int p = pi[j];
+            const int cnt = (int)(it.meta & REC_COUNT);
+            for (int j = 0; j < cnt; ++j) {
+                int p, e;
+                nb_pred(it, j, p, e);
                 mH &= SH[sidx(p, k)];
                 mD &= SD[sidx(p, k)];
             }
-            iH = tv.ld(c.nu_h, q, k) | mH;
-            iD = tv.ld(c.nu_d, q, k) | mD;
+            iH = it.x[0] | mH;
+            iD = it.x[1] | mD;
         }
-        T m = vmask(k);
+        T m = it.vm;
         iH &= m; iD &= m;
     };
     for (int i = lane; i < (nb << lg); i += 64) { SH[i] = ones<T>(); SD[i] = ones<T>(); }
-    if (!run_phase(PH_AVE, false, [&](int q, int k) -> bool {
-            bool ch = false;
-            if (data) {
-                T iH, iD;
-                ave_in(q, k, iH, iD);
-                T oH = valid_out(0, q, k, iH), oD = valid_out(1, q, k, iD);
-                size_t li = sidx(q, k);
-                if (oH != SH[li]) { SH[li] = oH; ch = true; }
-                if (oD != SD[li]) { SD[li] = oD; ch = true; }
-            }
-            if (k == 0) {
-                uint8_t f = FL[q], g = 0;
-                for (int j = pp[q]; j < pp[q + 1]; ++j) g |= FL[pi[j]];
-                uint8_t nf = (uint8_t)(f | (g & 12));
-                if (nf != f) { FL[q] = nf; ch = true; }
-            }
-            return ch;
-        }))
+    if (!run_phase(PH_AVE, false,
+            [&](Item<T>& it) { fetch_gen_w(it, c.nu_h, c.nu_d); },
+            [&](Item<T>& it) -> bool {
+                const int q = it.b, k = it.k;
+                bool ch = false;
+                if (data) {
+                    T iH, iD;
+                    ave_in(it, iH, iD);
+                    const bool dev = it.meta & M_DEV, call = it.meta & M_CALL;
+                    T oH = valid_out(0, q, k, iH, it.x[2], dev, call, it.vm), oD = valid_out(1, q, k, iD, it.x[2], dev, call, it.vm);
+                    int li = sidx(q, k);
+                    if (oH != SH[li]) { SH[li] = oH; ch = true; }
+                    if (oD != SD[li]) { SD[li] = oD; ch = true; }
+                }
+                if (k == 0) {
+                    uint8_t f = FL[q], g = 0;
+                    const int cnt = (int)(it.meta & REC_COUNT);
+                    for (int j = 0; j < cnt; ++j) {
+                        int p, e;
+                        nb_pred(it, j, p, e);
+                        g |= FL[p];
+                    }
+                    uint8_t nf = (uint8_t)(f | (g & 12));
+                    if (nf != f) { FL[q] = nf; ch = true; }
+                }
+                return ch;
+            }))
         return false;
     if (data)
-        for_all_items([&](int q, int k) {
-            T iH, iD;
-            ave_in(q, k, iH, iD);
-            tv.st(c.ave_h, q, k, iH);
-            tv.st(c.ave_d, q, k, iD);
-            tv.st(c.aveout_h, q, k, SH[sidx(q, k)]);
-            tv.st(c.aveout_d, q, k, SD[sidx(q, k)]);
-        });
+        for_all([&](Item<T>& it) { fetch_gen_w(it, c.nu_h, c.nu_d); },
+                [&](const Item<T>& it) {
+                    T iH, iD;
+                    ave_in(it, iH, iD);
+                    tv.st(c.ave_h, it.b, it.k, iH);
+                    tv.st(c.ave_d, it.b, it.k, iD);
+                    tv.st(c.aveout_h, it.b, it.k, SH[sidx(it.b, it.k)]);
+                    tv.st(c.aveout_d, it.b, it.k, SD[sidx(it.b, it.k)]);
+                });
     {
         bool bad = false;
         for (int b = lane; b < nb; b += 64) {
             uint8_t f = FL[b];
             if ((f & 5) != 5) bad = true;
             if (s0 == 0) {
-                if (c.after_dev) c.after_dev[b] = (f >> 3) & 1;
-                if (c.before_dev) c.before_dev[b] = (f >> 1) & 1;
+                if (c.after_dev) G(c.after_dev)[b] = (f >> 3) & 1;
+                if (c.before_dev) G(c.before_dev)[b] = (f >> 1) & 1;
             }
         }
         if (__ballot(bad) != 0ull) {
@@ -461,36 +633,73 @@ __device__ bool solve_tile(const DevCfg& c, int s0, int ns, uint8_t* lds)
     }
     __syncthreads();
 
-    // EAG_s(e=p->q) = NUin_s(q) & ~AVEout_s(p)
+    // Constants of the two placement phases, per item: NU_s(q) in x0/x1, the stop
+    // masks USE'_s(q) | WR_s(q) in x2/x3, AVEout_s of the two inline predecessors in
+    // x4..x7 and (delay phase) their MAYPout_s in x8..x11.  EAG_s(e=p->q) = NU_s(q) & ~AVEout_s(p).
+    auto fetch_place = [&](Item<T>& it, bool with_mayp) {
+        const int b = it.b, k = it.k;
+        const bool call = it.meta & M_CALL;
+        it.x[0] = tv.ld(c.nu_h, b, k);
+        it.x[1] = tv.ld(c.nu_d, b, k);
+        it.x[2] = use_stop(0, b, k, call) | wr(0, b, k);
+        it.x[3] = use_stop(1, b, k, call) | wr(1, b, k);
+        const int cnt = (int)(it.meta & REC_COUNT);
+        if (cnt > 0) {
+            it.x[4] = tv.ld(c.aveout_h, it.n0, k); it.x[5] = tv.ld(c.aveout_d, it.n0, k);
+            if (with_mayp) { it.x[8] = tv.ld(c.mayp_h, it.n0, k); it.x[9] = tv.ld(c.mayp_d, it.n0, k); }
+        }
+        if (cnt > 1) {
+            it.x[6] = tv.ld(c.aveout_h, it.n1, k); it.x[7] = tv.ld(c.aveout_d, it.n1, k);
+            if (with_mayp) { it.x[10] = tv.ld(c.mayp_h, it.n1, k); it.x[11] = tv.ld(c.mayp_d, it.n1, k); }
+        }
+    };
+    // AVEout / MAYPout of predecessor j (inline for j < 2)
+    auto pred_vals = [&](const Item<T>& it, int j, int p, T& aH, T& aD, T& mH, T& mD, bool with_mayp) {
+        if (j == 0) {
+            aH = it.x[4]; aD = it.x[5];
+            if (with_mayp) { mH = it.x[8]; mD = it.x[9]; }
+        } else if (j == 1) {
+            aH = it.x[6]; aD = it.x[7];
+            if (with_mayp) { mH = it.x[10]; mD = it.x[11]; }
+        } else {
+            aH = tv.ld(c.aveout_h, p, it.k); aD = tv.ld(c.aveout_d, p, it.k);
+            if (with_mayp) { mH = tv.ld(c.mayp_h, p, it.k); mD = tv.ld(c.mayp_d, p, it.k); }
+        }
+    };
+
     if (c.placement == 0) {
         // ------------------------------------------------------------ pending copies (forward, may)
         // MAYP_s(e) = (EAG_s(e) | MAYPout_s(p)) & ~LE(e); MAYPout_s(q) = OR_e MAYP_s(e) & ~USE'_s(q) & ~WR_s(q)
         for (int i = lane; i < (nb << lg); i += 64) { SH[i] = 0; SD[i] = 0; }
         if (data) {
-            if (!run_phase(PH_MAYP, false, [&](int q, int k) -> bool {
-                    if (q == c.entry) return false;
-                    T nuH = tv.ld(c.nu_h, q, k), nuD = tv.ld(c.nu_d, q, k);
-                    T mH = 0, mD = 0;
-                    for (int j = pp[q]; j < pp[q + 1]; ++j) {
-                        int p = pi[j];
-                        T nle = (kind[pe[j]] == 2) ? (T)0 : ones<T>();
-                        T aH = tv.ld(c.aveout_h, p, k), aD = tv.ld(c.aveout_d, p, k);
-                        mH |= ((nuH & ~aH) | SH[sidx(p, k)]) & nle;
-                        mD |= ((nuD & ~aD) | SD[sidx(p, k)]) & nle;
-                    }
-                    T m = vmask(k);
-                    T vH = mH & ~use_stop(0, q, k) & ~wr(0, q, k) & m;
-                    T vD = mD & ~use_stop(1, q, k) & ~wr(1, q, k) & m;
-                    bool ch = false;
-                    size_t li = sidx(q, k);
-                    if (vH != SH[li]) { SH[li] = vH; ch = true; }
-                    if (vD != SD[li]) { SD[li] = vD; ch = true; }
-                    return ch;
-                }))
+            if (!run_phase(PH_MAYP, false,
+                    [&](Item<T>& it) { if (!(it.meta & M_ENTRY)) fetch_place(it, false); },
+                    [&](Item<T>& it) -> bool {
+                        if (it.meta & M_ENTRY) return false;
+                        const int q = it.b, k = it.k;
+                        T mH = 0, mD = 0;
+                        const int cnt = (int)(it.meta & REC_COUNT);
+                        for (int j = 0; j < cnt; ++j) {
+                            int p, e;
+                            nb_pred(it, j, p, e);
+                            T nle = (e < 0) ? (T)0 : ones<T>();
+                            T aH, aD, u0, u1;
+                            pred_vals(it, j, p, aH, aD, u0, u1, false);
+                            mH |= ((it.x[0] & ~aH) | SH[sidx(p, k)]) & nle;
+                            mD |= ((it.x[1] & ~aD) | SD[sidx(p, k)]) & nle;
+                        }
+                        T m = it.vm;
+                        T vH = mH & ~it.x[2] & m, vD = mD & ~it.x[3] & m;
+                        bool ch = false;
+                        int li = sidx(q, k);
+                        if (vH != SH[li]) { SH[li] = vH; ch = true; }
+                        if (vD != SD[li]) { SD[li] = vD; ch = true; }
+                        return ch;
+                    }))
                 return false;
-            for_all_items([&](int q, int k) {
-                tv.st(c.mayp_h, q, k, SH[sidx(q, k)]);
-                tv.st(c.mayp_d, q, k, SD[sidx(q, k)]);
+            for_all(no_fetch, [&](const Item<T>& it) {
+                tv.st(c.mayp_h, it.b, it.k, SH[sidx(it.b, it.k)]);
+                tv.st(c.mayp_d, it.b, it.k, SD[sidx(it.b, it.k)]);
             });
         }
         __syncthreads();
@@ -500,15 +709,17 @@ __device__ bool solve_tile(const DevCfg& c, int s0, int ns, uint8_t* lds)
         // FV_x(e) = (AVEout_x(p) | EAG_x(e)) & ~MAYP_x(e)
         // N'_s(e) = (FV_s(e) & FV_o(e)) | (LATER_s(e) & LE(e))
         // LATERin_s(q) = AND_e (L'_s | N'_s) & OR_e L'_s; LATERout_s(q) = LATERin_s(q) & ~USE'_s(q) & ~WR_s(q)
-        auto later_in = [&](int q, int k, T& lH, T& lD) {
-            T nuH = tv.ld(c.nu_h, q, k), nuD = tv.ld(c.nu_d, q, k);
+        auto later_in = [&](const Item<T>& it, T& lH, T& lD) {
+            const int k = it.k;
             T allH = ones<T>(), allD = ones<T>(), anyH = 0, anyD = 0;
-            for (int j = pp[q]; j < pp[q + 1]; ++j) {
-                int p = pi[j];
-                T le = (kind[pe[j]] == 2) ? ones<T>() : (T)0;
-                T aH = tv.ld(c.aveout_h, p, k), aD = tv.ld(c.aveout_d, p, k);
-                T mpH = tv.ld(c.mayp_h, p, k), mpD = tv.ld(c.mayp_d, p, k);
-                T eH = nuH & ~aH, eD = nuD & ~aD;
+            const int cnt = (int)(it.meta & REC_COUNT);
+            for (int j = 0; j < cnt; ++j) {
+                int p, e;
+                nb_pred(it, j, p, e);
+                T le = (e < 0) ? ones<T>() : (T)0;
+                T aH, aD, mpH, mpD;
+                pred_vals(it, j, p, aH, aD, mpH, mpD, true);
+                T eH = it.x[0] & ~aH, eD = it.x[1] & ~aD;
                 T fvH = (aH | eH) & ~((eH | mpH) & ~le);
                 T fvD = (aD | eD) & ~((eD | mpD) & ~le);
                 T latH = eH | SH[sidx(p, k)], latD = eD | SD[sidx(p, k)];
@@ -519,99 +730,142 @@ __device__ bool solve_tile(const DevCfg& c, int s0, int ns, uint8_t* lds)
                 anyH |= lpH;
                 anyD |= lpD;
             }
-            T m = vmask(k);
+            T m = it.vm;
             lH = allH & anyH & m;
             lD = allD & anyD & m;
         };
         for (int i = lane; i < (nb << lg); i += 64) { SH[i] = 0; SD[i] = 0; }
         if (data) {
-            if (!run_phase(PH_LATER, false, [&](int q, int k) -> bool {
-                    if (q == c.entry) return false;
-                    T lH, lD;
-                    later_in(q, k, lH, lD);
-                    T vH = lH & ~use_stop(0, q, k) & ~wr(0, q, k);
-                    T vD = lD & ~use_stop(1, q, k) & ~wr(1, q, k);
-                    bool ch = false;
-                    size_t li = sidx(q, k);
-                    if (vH != SH[li]) { SH[li] = vH; ch = true; }
-                    if (vD != SD[li]) { SD[li] = vD; ch = true; }
-                    return ch;
-                }))
+            if (!run_phase(PH_LATER, false,
+                    [&](Item<T>& it) { if (!(it.meta & M_ENTRY)) fetch_place(it, true); },
+                    [&](Item<T>& it) -> bool {
+                        if (it.meta & M_ENTRY) return false;
+                        T lH, lD;
+                        later_in(it, lH, lD);
+                        T vH = lH & ~it.x[2], vD = lD & ~it.x[3];
+                        bool ch = false;
+                        int li = sidx(it.b, it.k);
+                        if (vH != SH[li]) { SH[li] = vH; ch = true; }
+                        if (vD != SD[li]) { SD[li] = vD; ch = true; }
+                        return ch;
+                    }))
                 return false;
             // materialise: INS_ENTRY_s(q) = LATERin_s(q) & USE'_s(q);
             //              INS_EDGE_s(e=p->q) = LATER_s(e) & (LE(e) | ~LATERin_s(q))
-            for_all_items([&](int q, int k) {
-                T lH = 0, lD = 0;
-                if (q != c.entry) later_in(q, k, lH, lD);
-                tv.st(c.ie_h, q, k, lH & use_stop(0, q, k));
-                tv.st(c.ie_d, q, k, lD & use_stop(1, q, k));
-                T nuH = tv.ld(c.nu_h, q, k), nuD = tv.ld(c.nu_d, q, k);
-                T m = vmask(k);
-                for (int j = pp[q]; j < pp[q + 1]; ++j) {
-                    int p = pi[j], e = pe[j];
-                    T le = (kind[e] == 2) ? ones<T>() : (T)0;
-                    T latH = (nuH & ~tv.ld(c.aveout_h, p, k)) | SH[sidx(p, k)];
-                    T latD = (nuD & ~tv.ld(c.aveout_d, p, k)) | SD[sidx(p, k)];
-                    tv.st(c.ig_h, e, k, latH & (le | ~lH) & m);
-                    tv.st(c.ig_d, e, k, latD & (le | ~lD) & m);
-                }
-            });
+            for_all([&](Item<T>& it) { fetch_place(it, true); },
+                    [&](const Item<T>& it) {
+                        const int q = it.b, k = it.k;
+                        T lH = 0, lD = 0;
+                        if (!(it.meta & M_ENTRY)) later_in(it, lH, lD);
+                        const bool call = it.meta & M_CALL;
+                        tv.st(c.ie_h, q, k, lH & use_stop(0, q, k, call));
+                        tv.st(c.ie_d, q, k, lD & use_stop(1, q, k, call));
+                        T m = it.vm;
+                        const int cnt = (int)(it.meta & REC_COUNT);
+                        for (int j = 0; j < cnt; ++j) {
+                            int p, e;
+                            nb_pred(it, j, p, e);
+                            T le = (e < 0) ? ones<T>() : (T)0;
+                            T aH, aD, u0, u1;
+                            pred_vals(it, j, p, aH, aD, u0, u1, false);
+                            T latH = (it.x[0] & ~aH) | SH[sidx(p, k)];
+                            T latD = (it.x[1] & ~aD) | SD[sidx(p, k)];
+                            int eid = e & 0x7FFFFFFF;
+                            tv.st(c.ig_h, eid, k, latH & (le | ~lH) & m);
+                            tv.st(c.ig_d, eid, k, latD & (le | ~lD) & m);
+                        }
+                    });
         }
     } else if (data) {
         // eager placement only: every EAG is materialised on its edge
-        for_all_items([&](int q, int k) {
-            tv.st(c.ie_h, q, k, (T)0);
-            tv.st(c.ie_d, q, k, (T)0);
-            T nuH = tv.ld(c.nu_h, q, k), nuD = tv.ld(c.nu_d, q, k);
-            T m = vmask(k);
-            for (int j = pp[q]; j < pp[q + 1]; ++j) {
-                int p = pi[j], e = pe[j];
-                tv.st(c.ig_h, e, k, nuH & ~tv.ld(c.aveout_h, p, k) & m);
-                tv.st(c.ig_d, e, k, nuD & ~tv.ld(c.aveout_d, p, k) & m);
-            }
-        });
+        for_all([&](Item<T>& it) { fetch_place(it, false); },
+                [&](const Item<T>& it) {
+                    const int k = it.k;
+                    tv.st(c.ie_h, it.b, k, (T)0);
+                    tv.st(c.ie_d, it.b, k, (T)0);
+                    T m = it.vm;
+                    const int cnt = (int)(it.meta & REC_COUNT);
+                    for (int j = 0; j < cnt; ++j) {
+                        int p, e;
+                        nb_pred(it, j, p, e);
+                        T aH, aD, u0, u1;
+                        pred_vals(it, j, p, aH, aD, u0, u1, false);
+                        int eid = e & 0x7FFFFFFF;
+                        tv.st(c.ig_h, eid, k, it.x[0] & ~aH & m);
+                        tv.st(c.ig_d, eid, k, it.x[1] & ~aD & m);
+                    }
+                });
     }
     __syncthreads();
 
     // ---------------------------------------------------------------- validity after placement
     // AVFin_s(q) = INS_ENTRY_s(q) | AND_e (AVFout_s(p) | INS_EDGE_s(e))
-    auto avf_in = [&](int q, int k, T& iH, T& iD) {
-        if (q == c.entry) {
-            iH = tv.vec(c.ev_h, k);
-            iD = tv.vec(c.ev_d, k);
+    // x0/x1: INS_ENTRY (or the boundary at ENTRY), x2: W, x4..x7: INS_EDGE of the inline in-edges
+    auto fetch_avf = [&](Item<T>& it) {
+        fetch_gen_w(it, c.ie_h, c.ie_d);
+        const int cnt = (int)(it.meta & REC_COUNT);
+        if (cnt > 0) {
+            int e = (int)(it.e0 & 0x7FFFFFFFu);
+            it.x[4] = tv.ld(c.ig_h, e, it.k); it.x[5] = tv.ld(c.ig_d, e, it.k);
+        }
+        if (cnt > 1) {
+            int e = (int)(it.e1 & 0x7FFFFFFFu);
+            it.x[6] = tv.ld(c.ig_h, e, it.k); it.x[7] = tv.ld(c.ig_d, e, it.k);
+        }
+    };
+    auto edge_ins = [&](const Item<T>& it, int j, int e, T& gH, T& gD) {
+        if (j == 0) { gH = it.x[4]; gD = it.x[5]; }
+        else if (j == 1) { gH = it.x[6]; gD = it.x[7]; }
+        else {
+            int eid = e & 0x7FFFFFFF;
+            gH = tv.ld(c.ig_h, eid, it.k); gD = tv.ld(c.ig_d, eid, it.k);
+        }
+    };
+    auto avf_in = [&](const Item<T>& it, T& iH, T& iD) {
+        const int k = it.k;
+        if (it.meta & M_ENTRY) {
+            iH = it.x[0]; iD = it.x[1];
         } else {
             T mH = ones<T>(), mD = ones<T>();
-            for (int j = pp[q]; j < pp[q + 1]; ++j) {
-                int p = pi[j], e = pe[j];
-                mH &= SH[sidx(p, k)] | tv.ld(c.ig_h, e, k);
-                mD &= SD[sidx(p, k)] | tv.ld(c.ig_d, e, k);
+            const int cnt = (int)(it.meta & REC_COUNT);
+            for (int j = 0; j < cnt; ++j) {
+                int p, e;
+                nb_pred(it, j, p, e);
+                T gH, gD;
+                edge_ins(it, j, e, gH, gD);
+                mH &= SH[sidx(p, k)] | gH;
+                mD &= SD[sidx(p, k)] | gD;
             }
-            iH = tv.ld(c.ie_h, q, k) | mH;
-            iD = tv.ld(c.ie_d, q, k) | mD;
+            iH = it.x[0] | mH;
+            iD = it.x[1] | mD;
         }
-        T m = vmask(k);
+        T m = it.vm;
         iH &= m; iD &= m;
     };
     if (data) {
         for (int i = lane; i < (nb << lg); i += 64) { SH[i] = ones<T>(); SD[i] = ones<T>(); }
-        if (!run_phase(PH_AVF, false, [&](int q, int k) -> bool {
-                T iH, iD;
-                avf_in(q, k, iH, iD);
-                T oH = valid_out(0, q, k, iH), oD = valid_out(1, q, k, iD);
-                bool ch = false;
-                size_t li = sidx(q, k);
-                if (oH != SH[li]) { SH[li] = oH; ch = true; }
-                if (oD != SD[li]) { SD[li] = oD; ch = true; }
-                return ch;
-            }))
+        if (!run_phase(PH_AVF, false, fetch_avf,
+                [&](Item<T>& it) -> bool {
+                    T iH, iD;
+                    avf_in(it, iH, iD);
+                    const bool dev = it.meta & M_DEV, call = it.meta & M_CALL;
+                    T oH = valid_out(0, it.b, it.k, iH, it.x[2], dev, call, it.vm);
+                    T oD = valid_out(1, it.b, it.k, iD, it.x[2], dev, call, it.vm);
+                    bool ch = false;
+                    int li = sidx(it.b, it.k);
+                    if (oH != SH[li]) { SH[li] = oH; ch = true; }
+                    if (oD != SD[li]) { SD[li] = oD; ch = true; }
+                    return ch;
+                }))
             return false;
         // outputs, and the per-variable map kind (Table II):
         // map(to) copy into D: on p->q with !after_dev(p), before q with no after_dev predecessor;
         // map(from) copy into H: on p->q or before q with !before_dev(q).
-        for_all_items([&](int q, int k) {
+        for_all(fetch_avf, [&](const Item<T>& it) {
+            const int q = it.b, k = it.k;
             if (c.avf_h) {
                 T iH, iD;
-                avf_in(q, k, iH, iD);
+                avf_in(it, iH, iD);
                 tv.st(c.avf_h, q, k, iH);
                 tv.st(c.avf_d, q, k, iD);
             }
@@ -619,16 +873,22 @@ __device__ bool solve_tile(const DevCfg& c, int s0, int ns, uint8_t* lds)
                 T to = 0, from = 0, dev = 0;
                 const bool before_q = (FL[q] >> 1) & 1;
                 bool pred_after = false;
-                for (int j = pp[q]; j < pp[q + 1]; ++j) {
-                    int p = pi[j], e = pe[j];
+                const int cnt = (int)(it.meta & REC_COUNT);
+                for (int j = 0; j < cnt; ++j) {
+                    int p, e;
+                    nb_pred(it, j, p, e);
+                    T gH, gD;
+                    edge_ins(it, j, e, gH, gD);
                     bool after_p = (FL[p] >> 3) & 1;
                     pred_after |= after_p;
-                    if (!after_p) to |= tv.ld(c.ig_d, e, k);
-                    if (!before_q) from |= tv.ld(c.ig_h, e, k);
+                    if (!after_p) to |= gD;
+                    if (!before_q) from |= gH;
                 }
-                if (!pred_after) to |= tv.ld(c.ie_d, q, k);
-                if (!before_q) from |= tv.ld(c.ie_h, q, k);
-                if (space[q] && q != c.exit) dev = tv.ld(c.R, q, k) | tv.ld(c.W, q, k);
+                if (!(it.meta & M_ENTRY)) {
+                    if (!pred_after) to |= it.x[1];
+                    if (!before_q) from |= it.x[0];
+                }
+                if ((it.meta & M_DEV) && !(it.meta & M_EXIT)) dev = tv.ld(c.R, q, k) | it.x[2];
                 if (to) atomicOr(&ACC[k], (uint32_t)to);
                 if (from) atomicOr(&ACC[nsi + k], (uint32_t)from);
                 if (dev) atomicOr(&ACC[2 * nsi + k], (uint32_t)dev);
@@ -641,7 +901,7 @@ __device__ bool solve_tile(const DevCfg& c, int s0, int ns, uint8_t* lds)
                 if (gv >= c.nv) continue;
                 int k = v / BITS, bit = v % BITS;
                 uint32_t to = (ACC[k] >> bit) & 1u, from = (ACC[nsi + k] >> bit) & 1u, dv = (ACC[2 * nsi + k] >> bit) & 1u;
-                c.var_kind[gv] = (uint8_t)(to | (from << 1) | ((dv && !to && !from) ? 4u : 0u));
+                G(c.var_kind)[gv] = (uint8_t)(to | (from << 1) | ((dv && !to && !from) ? 4u : 0u));
             }
         }
     }
@@ -659,7 +919,7 @@ ompd_k_solve(const DevCfg* __restrict__ cfgs, const Tile* __restrict__ tiles, in
         if (t >= n_tiles) break;
         const Tile tl = tiles[t];
         const DevCfg c = cfgs[tl.cfg];
-        if (c.info[INFO_STATUS] != 0) continue;
+        if (G(c.info)[INFO_STATUS] != 0) continue;
         if (tl.tbits == 32) solve_tile<uint32_t>(c, tl.s0, tl.ns, slds);
         else if (tl.tbits == 16) solve_tile<uint16_t>(c, tl.s0, tl.ns, slds);
         else solve_tile<uint8_t>(c, tl.s0, tl.ns, slds);

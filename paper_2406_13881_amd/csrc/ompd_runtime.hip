@@ -38,6 +38,7 @@ int ompd_fail(int code, const std::string& msg)
     } while (0)
 
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static void drop_graphs(ompd_plan* p);
 
 // ---------------------------------------------------------------------------
 // context
@@ -159,6 +160,131 @@ static int check_cfg_host(const ompd_cfg& g, int i)
     return OMPD_OK;
 }
 
+// Scratch of one CFG, offsets relative to its base (each 256-aligned).
+size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o)
+{
+    size_t total = 0;
+    auto take = [&](size_t bytes) { size_t x = total; total += align256(bytes); return x; };
+    size_t wd = (size_t)(g.n_vars + 63) / 64;
+    size_t bv = (size_t)g.n_blocks * wd * 8, ev = (size_t)g.n_edges * wd * 8;
+    o.aveout = take(2 * bv);
+    o.mayp = take(2 * bv);
+    o.nu = (r.nu_host && r.nu_dev) ? SIZE_MAX : take(2 * bv);
+    o.ave = (r.ave_host && r.ave_dev) ? SIZE_MAX : take(2 * bv);
+    o.ie = (r.ins_entry_to_host && r.ins_entry_to_dev) ? SIZE_MAX : take(2 * bv);
+    o.ig = (r.ins_edge_to_host && r.ins_edge_to_dev) ? SIZE_MAX : take(2 * ev);
+    o.avf = (!r.avf_host == !r.avf_dev) ? SIZE_MAX : take(2 * bv);
+    o.bnd = take(4 * wd * 8);
+    o.pp = take(4 * ((size_t)g.n_blocks + 1));
+    o.pi = take(4 * (size_t)std::max(g.n_edges, 1));
+    o.pe = take(4 * (size_t)std::max(g.n_edges, 1));
+    o.lvp = take(4 * ((size_t)g.n_blocks + 1));
+    o.lvb = take(4 * (size_t)g.n_blocks);
+    o.tmp = take(4 * ((size_t)g.n_blocks + 1));
+    o.recf = take(32 * (size_t)g.n_blocks);
+    o.recb = take(32 * (size_t)g.n_blocks);
+    o.info = take(4 * INFO_WORDS);
+    return total;
+}
+
+// Fill the kernels' descriptor of one CFG whose scratch starts at `base`.
+// Default boundary values (for NULL boundaries) are written to bnd_host
+// ([4*wd] words: entry valid H, D, exit live H, D), to be copied to
+// base + o.bnd by the caller.
+void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const ScratchOff& o, uint32_t flags,
+                      DevCfg& d, uint64_t* bnd_host)
+{
+    int wd = (g.n_vars + 63) / 64;
+    memset(&d, 0, sizeof d);
+    d.nb = g.n_blocks; d.ne = g.n_edges; d.nv = g.n_vars; d.entry = g.entry; d.exit = g.exit; d.wd = wd;
+    d.n_sums = g.call_summary ? g.n_summaries : 0;
+    d.placement = (flags & OMPD_F_PLACEMENT_EAGER) ? 1 : 0;
+    d.sweep_cap = (int)((flags >> 16) & 0xFFFFu);
+    d.succ_ptr = g.succ_ptr; d.succ_idx = g.succ_idx; d.kind = g.edge_kind; d.space = g.space;
+    d.R = g.read_bits; d.W = g.write_bits;
+    uint64_t* bnd = (uint64_t*)(base + o.bnd);
+    d.ev_h = g.entry_valid_host ? g.entry_valid_host : bnd;
+    d.ev_d = g.entry_valid_dev ? g.entry_valid_dev : bnd + wd;
+    d.lx_h = g.exit_live_host ? g.exit_live_host : bnd + 2 * wd;
+    d.lx_d = g.exit_live_dev ? g.exit_live_dev : bnd + 3 * wd;
+    d.call = g.call_summary; d.sums = g.summaries;
+    size_t bvw = (size_t)g.n_blocks * wd, evw = (size_t)g.n_edges * wd;
+    auto at = [&](size_t off) { return off == SIZE_MAX ? (uint64_t*)nullptr : (uint64_t*)(base + off); };
+    uint64_t *nu = at(o.nu), *ave = at(o.ave), *ie = at(o.ie), *ig = at(o.ig), *avf = at(o.avf);
+    // a requested half is written in place; a missing half goes to scratch
+    d.nu_h = r.nu_host ? r.nu_host : nu;               d.nu_d = r.nu_dev ? r.nu_dev : nu + bvw;
+    d.ave_h = r.ave_host ? r.ave_host : ave;           d.ave_d = r.ave_dev ? r.ave_dev : ave + bvw;
+    d.ie_h = r.ins_entry_to_host ? r.ins_entry_to_host : ie;
+    d.ie_d = r.ins_entry_to_dev ? r.ins_entry_to_dev : ie + bvw;
+    d.ig_h = r.ins_edge_to_host ? r.ins_edge_to_host : ig;
+    d.ig_d = r.ins_edge_to_dev ? r.ins_edge_to_dev : ig + evw;
+    if (r.avf_host || r.avf_dev) {
+        d.avf_h = r.avf_host ? r.avf_host : avf;
+        d.avf_d = r.avf_dev ? r.avf_dev : avf + bvw;
+    }
+    d.var_kind = r.var_kind; d.after_dev = r.after_dev; d.before_dev = r.before_dev;
+    uint64_t* ao = at(o.aveout);
+    uint64_t* mp = at(o.mayp);
+    d.aveout_h = ao; d.aveout_d = ao + bvw; d.mayp_h = mp; d.mayp_d = mp + bvw;
+    d.pred_ptr = (int32_t*)(base + o.pp); d.pred_idx = (int32_t*)(base + o.pi);
+    d.pred_eid = (int32_t*)(base + o.pe); d.level_ptr = (int32_t*)(base + o.lvp);
+    d.level_blk = (int32_t*)(base + o.lvb); d.tmp = (int32_t*)(base + o.tmp);
+    d.rec_f = (int32_t*)(base + o.recf); d.rec_b = (int32_t*)(base + o.recb);
+    d.info = (int32_t*)(base + o.info);
+    if (bnd_host && wd > 0) {
+        uint64_t last = (g.n_vars & 63) ? ((1ull << (g.n_vars & 63)) - 1) : ~0ull;
+        for (int w = 0; w < 4 * wd; ++w) bnd_host[w] = 0;
+        for (int w = 0; w < wd; ++w) {
+            uint64_t m = (w == wd - 1) ? last : ~0ull;
+            bnd_host[w] = m;            // entry valid on the host
+            bnd_host[2 * wd + w] = m;   // live on the host after exit
+        }
+    }
+}
+
+// Tiles for a set of CFGs under a configuration, longest first, and the
+// launch sizes that go with them.
+int ompd_make_plan_tiles(ompd_ctx* ctx, const std::vector<DevCfg>& cfgs, const PlanConfig& pc,
+                         std::vector<Tile>& tiles, size_t& lds_solve, size_t& lds_prep, int& grid_solve)
+{
+    int max_nb = 2;
+    for (const DevCfg& d : cfgs) max_nb = std::max(max_nb, d.nb);
+    tiles.clear();
+    size_t lds = pc.lds_bytes;
+    if (lds == 0) {
+        // smallest budget that holds the largest CFG with one 16-bit slice, at least 32 KiB
+        lds = std::max<size_t>(32 * 1024, ompd_tile_lds(max_nb, 1, 16));
+        if (lds > (size_t)ctx->lds_max) lds = std::max<size_t>(32 * 1024, ompd_tile_lds(max_nb, 1, 8));
+    }
+    lds = std::min<size_t>(lds, ctx->lds_max);
+    for (int i = 0; i < (int)cfgs.size(); ++i) {
+        const DevCfg& d = cfgs[i];
+        if (make_tiles(i, d.nb, d.nv, lds, pc.max_ns, pc.min_tbits, tiles) != 0) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "cfg %d: %d blocks exceed the on-chip budget of %zu bytes", i, d.nb, lds);
+            return ompd_fail(OMPD_E_NOMEM, buf);
+        }
+    }
+    // longest tiles first: work ~ blocks x slices of the widest type
+    std::stable_sort(tiles.begin(), tiles.end(), [&](const Tile& a, const Tile& b) {
+        double wa = (double)cfgs[a.cfg].nb * (1.0 + std::max(a.ns, 1) / 16.0);
+        double wb = (double)cfgs[b.cfg].nb * (1.0 + std::max(b.ns, 1) / 16.0);
+        return wa > wb;
+    });
+    size_t need = 16;
+    for (const Tile& t : tiles) need = std::max(need, ompd_tile_lds(cfgs[t.cfg].nb, t.ns, t.tbits));
+    lds_solve = (need + 255) & ~(size_t)255;
+    lds_prep = 4 * (size_t)max_nb + 64;
+    if (lds_prep > (size_t)ctx->lds_max)
+        return ompd_fail(OMPD_E_NOMEM, "CFG too large for the ingest kernel's on-chip level table");
+    int per_cu = 0;
+    CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)ompd_k_solve, 64, lds_solve));
+    per_cu = std::max(1, per_cu);
+    if (pc.wg_per_cu > 0) per_cu = std::min(per_cu, pc.wg_per_cu);
+    grid_solve = std::max(1, std::min((int)tiles.size(), per_cu * ctx->n_cu));
+    return OMPD_OK;
+}
+
 int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n, uint32_t flags,
                     const PlanConfig& pc, ompd_plan** out)
 {
@@ -176,36 +302,17 @@ int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32
     p->res.assign(res, res + n);
     p->h_cfgs.resize(n);
 
-    // scratch layout
-    struct Off { size_t aveout, mayp, nu, ave, ie, ig, avf, bnd, pp, pi, pe, lvp, lvb, tmp, info; };
-    std::vector<Off> off(n);
+    std::vector<ScratchOff> off(n);
+    std::vector<size_t> base(n);
     size_t total = 0;
-    auto take = [&](size_t bytes) { size_t o = total; total += align256(bytes); return o; };
     int max_nb = 2;
     for (int i = 0; i < n; ++i) {
-        const ompd_cfg& g = cfgs[i];
-        const ompd_result& r = res[i];
-        size_t wd = (size_t)(g.n_vars + 63) / 64;
-        size_t bv = (size_t)g.n_blocks * wd * 8, ev = (size_t)g.n_edges * wd * 8;
-        Off& o = off[i];
-        o.aveout = take(2 * bv);
-        o.mayp = take(2 * bv);
-        o.nu = (r.nu_host && r.nu_dev) ? 0 : take(2 * bv);
-        o.ave = (r.ave_host && r.ave_dev) ? 0 : take(2 * bv);
-        o.ie = (r.ins_entry_to_host && r.ins_entry_to_dev) ? 0 : take(2 * bv);
-        o.ig = (r.ins_edge_to_host && r.ins_edge_to_dev) ? 0 : take(2 * ev);
-        o.avf = (!r.avf_host == !r.avf_dev) ? 0 : take(2 * bv);
-        o.bnd = take(4 * wd * 8);
-        o.pp = take(4 * ((size_t)g.n_blocks + 1));
-        o.pi = take(4 * (size_t)std::max(g.n_edges, 1));
-        o.pe = take(4 * (size_t)std::max(g.n_edges, 1));
-        o.lvp = take(4 * ((size_t)g.n_blocks + 1));
-        o.lvb = take(4 * (size_t)g.n_blocks);
-        o.tmp = take(4 * ((size_t)g.n_blocks + 1));
-        o.info = take(4 * INFO_WORDS);
-        max_nb = std::max(max_nb, g.n_blocks);
+        base[i] = total;
+        total += ompd_cfg_scratch(cfgs[i], res[i], off[i]);
+        max_nb = std::max(max_nb, cfgs[i].n_blocks);
     }
-    size_t counter_off = take(256);
+    size_t counter_off = total;
+    total += 256;
     p->scratch_bytes = total;
     hipError_t e = hipMalloc(&p->scratch, std::max<size_t>(total, 256));
     if (e != hipSuccess) {
@@ -214,62 +321,13 @@ int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32
     }
     char* S = (char*)p->scratch;
     p->d_counter = (int32_t*)(S + counter_off);
-
-    // default boundaries (host-built, one copy)
-    std::vector<uint64_t> bnd_host;
+    std::vector<uint64_t> bnd;
     for (int i = 0; i < n; ++i) {
-        const ompd_cfg& g = cfgs[i];
-        const ompd_result& r = res[i];
-        int wd = (g.n_vars + 63) / 64;
-        DevCfg& d = p->h_cfgs[i];
-        memset(&d, 0, sizeof d);
-        d.nb = g.n_blocks; d.ne = g.n_edges; d.nv = g.n_vars; d.entry = g.entry; d.exit = g.exit; d.wd = wd;
-        d.n_sums = g.call_summary ? g.n_summaries : 0;
-        d.placement = (flags & OMPD_F_PLACEMENT_EAGER) ? 1 : 0;
-        d.sweep_cap = (int)((flags >> 16) & 0xFFFFu);
-        d.succ_ptr = g.succ_ptr; d.succ_idx = g.succ_idx; d.kind = g.edge_kind; d.space = g.space;
-        d.R = g.read_bits; d.W = g.write_bits;
-        uint64_t* bnd = (uint64_t*)(S + off[i].bnd);
-        d.ev_h = g.entry_valid_host ? g.entry_valid_host : bnd;
-        d.ev_d = g.entry_valid_dev ? g.entry_valid_dev : bnd + wd;
-        d.lx_h = g.exit_live_host ? g.exit_live_host : bnd + 2 * wd;
-        d.lx_d = g.exit_live_dev ? g.exit_live_dev : bnd + 3 * wd;
-        d.call = g.call_summary; d.sums = g.summaries;
-        size_t bvw = (size_t)g.n_blocks * wd, evw = (size_t)g.n_edges * wd;
-        uint64_t* nu = (uint64_t*)(S + off[i].nu);
-        uint64_t* ave = (uint64_t*)(S + off[i].ave);
-        uint64_t* ie = (uint64_t*)(S + off[i].ie);
-        uint64_t* ig = (uint64_t*)(S + off[i].ig);
-        uint64_t* avf = (uint64_t*)(S + off[i].avf);
-        // a requested half is written in place; a missing half goes to scratch
-        d.nu_h = r.nu_host ? r.nu_host : nu;               d.nu_d = r.nu_dev ? r.nu_dev : nu + bvw;
-        d.ave_h = r.ave_host ? r.ave_host : ave;           d.ave_d = r.ave_dev ? r.ave_dev : ave + bvw;
-        d.ie_h = r.ins_entry_to_host ? r.ins_entry_to_host : ie;
-        d.ie_d = r.ins_entry_to_dev ? r.ins_entry_to_dev : ie + bvw;
-        d.ig_h = r.ins_edge_to_host ? r.ins_edge_to_host : ig;
-        d.ig_d = r.ins_edge_to_dev ? r.ins_edge_to_dev : ig + evw;
-        if (r.avf_host || r.avf_dev) {
-            d.avf_h = r.avf_host ? r.avf_host : avf;
-            d.avf_d = r.avf_dev ? r.avf_dev : avf + bvw;
-        }
-        d.var_kind = r.var_kind; d.after_dev = r.after_dev; d.before_dev = r.before_dev;
-        uint64_t* ao = (uint64_t*)(S + off[i].aveout);
-        uint64_t* mp = (uint64_t*)(S + off[i].mayp);
-        d.aveout_h = ao; d.aveout_d = ao + bvw; d.mayp_h = mp; d.mayp_d = mp + bvw;
-        d.pred_ptr = (int32_t*)(S + off[i].pp); d.pred_idx = (int32_t*)(S + off[i].pi);
-        d.pred_eid = (int32_t*)(S + off[i].pe); d.level_ptr = (int32_t*)(S + off[i].lvp);
-        d.level_blk = (int32_t*)(S + off[i].lvb); d.tmp = (int32_t*)(S + off[i].tmp);
-        d.info = (int32_t*)(S + off[i].info);
-        // default boundary values
-        if (wd > 0) {
-            std::vector<uint64_t> b(4 * (size_t)wd, 0);
-            uint64_t last = (g.n_vars & 63) ? ((1ull << (g.n_vars & 63)) - 1) : ~0ull;
-            for (int w = 0; w < wd; ++w) {
-                uint64_t m = (w == wd - 1) ? last : ~0ull;
-                b[w] = m;            // entry valid on the host
-                b[2 * wd + w] = m;   // live on the host after exit
-            }
-            e = hipMemcpy(bnd, b.data(), b.size() * 8, hipMemcpyHostToDevice);
+        size_t wd = (size_t)(cfgs[i].n_vars + 63) / 64;
+        bnd.assign(4 * wd, 0);
+        ompd_fill_devcfg(cfgs[i], res[i], S + base[i], off[i], flags, p->h_cfgs[i], bnd.data());
+        if (wd) {
+            e = hipMemcpy(S + base[i] + off[i].bnd, bnd.data(), 4 * wd * 8, hipMemcpyHostToDevice);
             if (e != hipSuccess) { ompd_plan_destroy(p); return ompd_fail(OMPD_E_DEVICE, hipGetErrorString(e)); }
         }
     }
@@ -288,77 +346,119 @@ int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32
     return OMPD_OK;
 }
 
-// (Re)build tiles, launch shapes and the captured graph for a configuration.
+// (Re)build tiles and launch shapes for a configuration (drops captured graphs).
 int ompd_plan_retile(ompd_plan* p, const PlanConfig& pc)
 {
     ompd_ctx* ctx = p->ctx;
-    p->cfg = pc;
     std::vector<Tile> tiles;
-    size_t lds = pc.lds_bytes;
-    if (lds == 0) {
-        // smallest budget that holds the largest CFG with one 16-bit slice, at least 32 KiB
-        lds = std::max<size_t>(32 * 1024, ompd_tile_lds(p->max_nb, 1, 16));
-        if (lds > (size_t)ctx->lds_max) lds = std::max<size_t>(32 * 1024, ompd_tile_lds(p->max_nb, 1, 8));
-    }
-    lds = std::min<size_t>(lds, ctx->lds_max);
-    for (int i = 0; i < p->n; ++i) {
-        const DevCfg& d = p->h_cfgs[i];
-        if (make_tiles(i, d.nb, d.nv, lds, pc.max_ns, pc.min_tbits, tiles) != 0) {
-            char buf[160];
-            snprintf(buf, sizeof buf, "cfg %d: %d blocks exceed the on-chip budget of %zu bytes", i, d.nb, lds);
-            return ompd_fail(OMPD_E_NOMEM, buf);
-        }
-    }
-    // longest tiles first: work ~ blocks x slices of the widest type
-    std::stable_sort(tiles.begin(), tiles.end(), [&](const Tile& a, const Tile& b) {
-        double wa = (double)p->h_cfgs[a.cfg].nb * (1.0 + std::max(a.ns, 1) / 16.0);
-        double wb = (double)p->h_cfgs[b.cfg].nb * (1.0 + std::max(b.ns, 1) / 16.0);
-        return wa > wb;
-    });
-    size_t need = 16;
-    for (const Tile& t : tiles) need = std::max(need, ompd_tile_lds(p->h_cfgs[t.cfg].nb, t.ns, t.tbits));
-    p->lds_solve = (need + 255) & ~(size_t)255;
-    p->lds_prep = 4 * (size_t)p->max_nb + 64;
-    if (p->lds_prep > (size_t)ctx->lds_max)
-        return ompd_fail(OMPD_E_NOMEM, "CFG too large for the ingest kernel's on-chip level table");
+    size_t lds_solve = 0, lds_prep = 0;
+    int grid = 1;
+    int rc = ompd_make_plan_tiles(ctx, p->h_cfgs, pc, tiles, lds_solve, lds_prep, grid);
+    if (rc) return rc;
+    p->cfg = pc;
+    p->lds_solve = lds_solve;
+    p->lds_prep = lds_prep;
+    p->grid_solve = grid;
     p->h_tiles = tiles;
     p->n_tiles = (int)tiles.size();
     if (p->d_tiles) { (void)hipFree(p->d_tiles); p->d_tiles = nullptr; }
     CK(hipMalloc(&p->d_tiles, sizeof(Tile) * std::max(p->n_tiles, 1)));
     if (p->n_tiles)
         CK(hipMemcpy(p->d_tiles, tiles.data(), sizeof(Tile) * p->n_tiles, hipMemcpyHostToDevice));
-    int per_cu = 0;
-    CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)ompd_k_solve, 64, p->lds_solve));
-    per_cu = std::max(1, per_cu);
-    if (pc.wg_per_cu > 0) per_cu = std::min(per_cu, pc.wg_per_cu);
-    p->grid_solve = std::max(1, std::min(p->n_tiles, per_cu * ctx->n_cu));
-    if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
-    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+    drop_graphs(p);
     return OMPD_OK;
 }
 
-static int launch_all(ompd_plan* p, hipStream_t s, bool events)
+int ompd_launch_prep(const DevCfg* d_cfgs, int n, int32_t* d_counter, size_t lds, hipStream_t s)
+{
+    if (n <= 0) return OMPD_OK;
+    hipLaunchKernelGGL(ompd_k_prep, dim3(n), dim3(256), lds, s, d_cfgs, n, d_counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return ompd_fail(OMPD_E_DEVICE, std::string("prep launch (lds ") + std::to_string(lds) + "): " +
+                                            hipGetErrorString(e));
+    return OMPD_OK;
+}
+
+int ompd_launch_solve(const DevCfg* d_cfgs, const Tile* d_tiles, int n_tiles, int32_t* d_counter, int grid,
+                      size_t lds, hipStream_t s)
+{
+    if (n_tiles <= 0) return OMPD_OK;
+    hipLaunchKernelGGL(ompd_k_solve, dim3(grid), dim3(64), lds, s, d_cfgs, d_tiles, n_tiles, d_counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return ompd_fail(OMPD_E_DEVICE, std::string("solve launch (grid ") + std::to_string(grid) + ", lds " +
+                                            std::to_string(lds) + "): " + hipGetErrorString(e));
+    return OMPD_OK;
+}
+
+static int launch_prep(ompd_plan* p, hipStream_t s)
+{
+    return ompd_launch_prep((const DevCfg*)p->d_cfgs, p->n, p->d_counter, p->lds_prep, s);
+}
+
+static int launch_solve(ompd_plan* p, hipStream_t s)
+{
+    return ompd_launch_solve((const DevCfg*)p->d_cfgs, (const Tile*)p->d_tiles, p->n_tiles, p->d_counter,
+                             p->grid_solve, p->lds_solve, s);
+}
+
+// Capture one launch function into an executable graph (nullptr if capture
+// is not available here).
+static hipGraphExec_t capture(ompd_plan* p, int (*fn)(ompd_plan*, hipStream_t), hipGraph_t* keep)
+{
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int rc = (e == hipSuccess) ? fn(p, cs) : OMPD_E_DEVICE;
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    (void)hipGetLastError();
+    if (e != hipSuccess || e2 != hipSuccess || rc != OMPD_OK || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return nullptr;
+    }
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphDestroy(g);
+        return nullptr;
+    }
+    *keep = g;
+    return x;
+}
+
+static void drop_graphs(ompd_plan* p)
+{
+    if (p->gx_prep) (void)hipGraphExecDestroy(p->gx_prep);
+    if (p->gx_solve) (void)hipGraphExecDestroy(p->gx_solve);
+    if (p->g_prep) (void)hipGraphDestroy(p->g_prep);
+    if (p->g_solve) (void)hipGraphDestroy(p->g_solve);
+    p->gx_prep = p->gx_solve = nullptr;
+    p->g_prep = p->g_solve = nullptr;
+}
+
+// Enqueue one solve: HIP events on the caller's stream around the ingest
+// kernel and around the persistent solve (events stay outside the graphs).
+static int launch_all(ompd_plan* p, hipStream_t s)
 {
     (void)hipGetLastError();
-    if (events) CK(hipEventRecord(p->ev0, s));
-    if (p->n > 0) {
-        hipLaunchKernelGGL(ompd_k_prep, dim3(p->n), dim3(256), p->lds_prep, s, (const DevCfg*)p->d_cfgs, p->n,
-                           p->d_counter);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess)
-            return ompd_fail(OMPD_E_DEVICE, std::string("prep launch (lds ") + std::to_string(p->lds_prep) +
-                                                "): " + hipGetErrorString(e));
+    if (p->cfg.use_graph && !p->gx_prep) {
+        p->gx_prep = capture(p, launch_prep, &p->g_prep);
+        p->gx_solve = capture(p, launch_solve, &p->g_solve);
+        if (!p->gx_prep || !p->gx_solve) {
+            drop_graphs(p);
+            p->cfg.use_graph = false;   // capture unavailable: launch directly
+        }
     }
-    if (events) CK(hipEventRecord(p->ev1, s));
-    if (p->n_tiles > 0) {
-        hipLaunchKernelGGL(ompd_k_solve, dim3(p->grid_solve), dim3(64), p->lds_solve, s,
-                           (const DevCfg*)p->d_cfgs, (const Tile*)p->d_tiles, p->n_tiles, p->d_counter);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess)
-            return ompd_fail(OMPD_E_DEVICE, std::string("solve launch (grid ") + std::to_string(p->grid_solve) +
-                                                ", lds " + std::to_string(p->lds_solve) + "): " + hipGetErrorString(e));
-    }
-    if (events) CK(hipEventRecord(p->ev2, s));
+    CK(hipEventRecord(p->ev0, s));
+    if (p->cfg.use_graph) CK(hipGraphLaunch(p->gx_prep, s));
+    else { int rc = launch_prep(p, s); if (rc) return rc; }
+    CK(hipEventRecord(p->ev1, s));
+    if (p->cfg.use_graph) CK(hipGraphLaunch(p->gx_solve, s));
+    else { int rc = launch_solve(p, s); if (rc) return rc; }
+    CK(hipEventRecord(p->ev2, s));
     return OMPD_OK;
 }
 
@@ -376,31 +476,7 @@ int ompd_plan_run_locked(ompd_plan* p, hipStream_t s)
 {
     CK(hipSetDevice(p->ctx->device));
     p->last_stream = s;
-    if (!p->cfg.use_graph) return launch_all(p, s, true);
-    if (!p->graph_exec) {
-        hipStream_t cs;
-        CK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        int rc = OMPD_OK;
-        if (e == hipSuccess) rc = launch_all(p, cs, true);
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(cs, &g);
-        (void)hipStreamDestroy(cs);
-        if (e != hipSuccess || e2 != hipSuccess || rc != OMPD_OK || !g) {
-            if (g) (void)hipGraphDestroy(g);
-            p->cfg.use_graph = false;     // capture unsupported here: launch directly
-            return launch_all(p, s, true);
-        }
-        e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            (void)hipGraphDestroy(g);
-            p->cfg.use_graph = false;
-            return launch_all(p, s, true);
-        }
-        p->graph = g;
-    }
-    CK(hipGraphLaunch(p->graph_exec, s));
-    return OMPD_OK;
+    return launch_all(p, s);
 }
 
 extern "C" int ompd_plan_run(ompd_plan* p, void* stream)
@@ -456,6 +532,21 @@ extern "C" int ompd_plan_last_ms(ompd_plan* p, float* total_ms, float* solve_ms)
     return OMPD_OK;
 }
 
+extern "C" int ompd_plan_configure(ompd_plan* p, int64_t lds_bytes, int32_t max_ns, int32_t min_tbits,
+                                   int32_t wg_per_cu)
+{
+    if (!p || lds_bytes < 0 || max_ns < 1 || (min_tbits != 8 && min_tbits != 16 && min_tbits != 32) || wg_per_cu < 0)
+        return ompd_fail(OMPD_E_INVAL, "bad plan configuration");
+    std::lock_guard<std::mutex> lk(p->ctx->mu);
+    PlanConfig c = p->cfg;
+    c.lds_bytes = (size_t)lds_bytes;
+    c.max_ns = max_ns;
+    c.min_tbits = min_tbits;
+    c.wg_per_cu = wg_per_cu;
+    c.use_graph = true;
+    return ompd_plan_retile(p, c);
+}
+
 extern "C" int ompd_plan_describe(ompd_plan* p, char* buf, int32_t len)
 {
     if (!p || !buf || len <= 0) return ompd_fail(OMPD_E_INVAL, "bad arguments");
@@ -463,9 +554,9 @@ extern "C" int ompd_plan_describe(ompd_plan* p, char* buf, int32_t len)
     for (const Tile& t : p->h_tiles) (t.tbits == 32 ? n32 : t.tbits == 16 ? n16 : n8)++;
     snprintf(buf, len,
              "{\"cfgs\": %d, \"tiles\": %d, \"tiles32\": %d, \"tiles16\": %d, \"tiles8\": %d, \"lds_solve\": %zu, "
-             "\"lds_prep\": %zu, \"grid_solve\": %d, \"max_ns\": %d, \"min_tbits\": %d, \"wg_per_cu\": %d, "
+             "\"lds_prep\": %zu, \"grid_solve\": %d, \"lds_bytes\": %zu, \"max_ns\": %d, \"min_tbits\": %d, \"wg_per_cu\": %d, "
              "\"graph\": %d, \"scratch_bytes\": %zu}",
-             p->n, p->n_tiles, n32, n16, n8, p->lds_solve, p->lds_prep, p->grid_solve, p->cfg.max_ns,
+             p->n, p->n_tiles, n32, n16, n8, p->lds_solve, p->lds_prep, p->grid_solve, p->cfg.lds_bytes, p->cfg.max_ns,
              p->cfg.min_tbits, p->cfg.wg_per_cu, p->cfg.use_graph ? 1 : 0, p->scratch_bytes);
     return OMPD_OK;
 }
@@ -474,9 +565,8 @@ extern "C" void ompd_plan_destroy(ompd_plan* p)
 {
     if (!p) return;
     (void)hipSetDevice(p->ctx->device);
-    if (p->last_stream || p->graph_exec) (void)hipDeviceSynchronize();
-    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->last_stream || p->gx_prep) (void)hipDeviceSynchronize();
+    drop_graphs(p);
     if (p->d_tiles) (void)hipFree(p->d_tiles);
     if (p->d_cfgs) (void)hipFree(p->d_cfgs);
     if (p->scratch) (void)hipFree(p->scratch);
@@ -497,9 +587,10 @@ extern "C" int ompd_plan_autotune(ompd_plan* p, void* stream, int32_t trials, fl
     trials = std::max(1, trials);
     std::vector<PlanConfig> cands;
     const size_t base = std::max<size_t>(16 * 1024, ompd_tile_lds(p->max_nb, 1, 8));
-    for (size_t lds : {(size_t)0, (size_t)24 * 1024, (size_t)32 * 1024, (size_t)40 * 1024, (size_t)54 * 1024,
-                       (size_t)80 * 1024, (size_t)160 * 1024}) {
-        if (lds && (lds < base || lds > (size_t)p->ctx->lds_max)) continue;
+    const size_t lds_cap = (size_t)p->ctx->lds_max;
+    for (size_t lds : {(size_t)0, base, (size_t)32 * 1024, (size_t)40 * 1024, (size_t)54 * 1024, (size_t)80 * 1024,
+                       lds_cap}) {
+        if (lds && (lds < base || lds > lds_cap)) continue;
         for (int max_ns : {4, 16, 64}) {
             PlanConfig c = p->cfg;
             c.lds_bytes = lds;
@@ -519,7 +610,9 @@ extern "C" int ompd_plan_autotune(ompd_plan* p, void* stream, int32_t trials, fl
             if (ompd_plan_run_locked(p, s) != OMPD_OK) { ok = false; break; }
             if (hipEventSynchronize(p->ev2) != hipSuccess) { ok = false; break; }
             float ms = 0;
-            (void)hipEventElapsedTime(&ms, p->ev0, p->ev2);
+            if (hipEventElapsedTime(&ms, p->ev0, p->ev2) != hipSuccess) {
+                return ompd_fail(OMPD_E_DEVICE, "autotune: event timing failed");
+            }
             if (t > 0) tot += ms;   // first run warms the graph
         }
         if (!ok) continue;

@@ -337,3 +337,84 @@ def random_dag(seed: int, n_blocks: int, n_vars: int, p_extra: float = 0.3, p_de
         blocks.append((sp, rd, wr))
     cfg, _ = from_edges(blocks, edges, n_vars)
     return cfg
+
+
+# --------------------------------------------------------------------------
+# programs (config 4)
+# --------------------------------------------------------------------------
+@dataclass
+class Program:
+    """Procedures sharing ``n_globals`` global variables (vars [0, n_globals)
+    of every procedure; the rest are locals).  Call site j is block
+    ``call_block[j]`` of procedure ``call_proc[j]``; ``callee[j]`` is the
+    called procedure or -1 for an external function."""
+    procs: List[CFG]
+    n_globals: int
+    call_proc: np.ndarray
+    call_block: np.ndarray
+    callee: np.ndarray
+    roots: List[int]
+
+
+C4 = dict(n_procs=2000, n_globals=256, n_locals=16, blocks=(32, 1024), mean_calls=3.0, max_calls=8,
+          scc_procs=100, scc_size=(2, 8), max_loop_depth=3, device_frac=0.30, p_read=0.2, p_write=0.1)
+
+
+def program(seed: int, n_procs: int = 2000, n_globals: int = 256, n_locals: int = 16,
+            blocks: Tuple[int, int] = (32, 1024), mean_calls: float = 3.0, max_calls: int = 8,
+            scc_procs: int = 100, scc_size: Tuple[int, int] = (2, 8), max_loop_depth: int = 3,
+            device_frac: float = 0.30, p_read: float = 0.2, p_write: float = 0.1,
+            external_frac: float = 0.0, threads: int = 0) -> Program:
+    """A random call graph: procedure i calls Poisson(mean_calls) (at most
+    max_calls) procedures of higher index; then scc_procs procedures are
+    grouped into cycles of U{scc_size} members (a call from each member to the
+    next), which makes recursive SCCs.  Procedure 0 and every procedure that
+    nobody calls are roots.  Each procedure is a structured CFG whose call
+    sites are distinct host statements."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    calls: List[List[int]] = [[] for _ in range(n_procs)]
+    for i in range(n_procs - 1):
+        k = min(int(rng.poisson(mean_calls)), max_calls)
+        if k:
+            calls[i].extend(int(x) for x in rng.integers(i + 1, n_procs, size=k))
+    members = rng.permutation(n_procs)[:scc_procs].tolist() if scc_procs else []
+    pos = 0
+    while pos < len(members):
+        sz = int(rng.integers(scc_size[0], scc_size[1] + 1))
+        grp = members[pos:pos + sz]
+        pos += sz
+        if len(grp) >= 2:
+            for a, b in zip(grp, grp[1:] + grp[:1]):
+                calls[a].append(int(b))
+    if external_frac > 0:
+        for i in range(n_procs):
+            if rng.random() < external_frac:
+                calls[i].append(-1)
+    lo, hi = blocks
+    sizes = [int(round(math.exp(math.log(lo) + rng.random() * (math.log(hi) - math.log(lo))))) for _ in range(n_procs)]
+    nv = n_globals + n_locals
+    seeds = [int(x) for x in rng.integers(0, 1 << 62, size=n_procs)]
+
+    def gen(i):
+        return make_cfg(seeds[i], n_user=sizes[i], n_vars=nv, max_loop_depth=max_loop_depth,
+                        device_frac=device_frac, p_read=p_read, p_write=p_write, n_call_sites=len(calls[i]))
+    threads = threads or min(16, os.cpu_count() or 4)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        procs = list(ex.map(gen, range(n_procs)))
+    cp, cb, ce = [], [], []
+    for i, c in enumerate(procs):
+        for j, blk in enumerate(c.call_blocks.tolist()):
+            cp.append(i)
+            cb.append(int(blk))
+            ce.append(calls[i][j])
+    called = set(x for x in ce if x >= 0)
+    roots = sorted(set([0]) | set(i for i in range(n_procs) if i not in called))
+    return Program(procs=procs, n_globals=n_globals, call_proc=np.array(cp, np.int32),
+                   call_block=np.array(cb, np.int32), callee=np.array(ce, np.int32), roots=roots)
+
+
+def c4(n_procs: int = 2000, **kw) -> Program:
+    prm = dict(C4)
+    prm.update(n_procs=n_procs)
+    prm.update(kw)
+    return program(item_seed(4, 0), **prm)
