@@ -26,6 +26,16 @@ problems of ``oracle.c``:
   make it valid on the host before the call (a host read at the call block);
   such demands feed back into the summaries, and the whole computation
   repeats until no demand changes.
+* The validity tables describe the callee under eager copies; a context's
+  final placement delays copies and can leave a copy stale at the callee's
+  exit where the eager one would be current.  So when a context is solved,
+  each of its calls is capped by the validity at EXIT, under the final
+  placement, of the callee context that the call leads to: the caller's
+  validity after the call is the table's value ANDed with that cap.  The
+  callee keeps valid at its exit whatever the caller reads next (its exit
+  liveness), so a cap never removes a needed copy.  Caps are taken afresh
+  from the latest context solutions, and the whole computation repeats
+  until neither the demands nor the caps change.
 
 External callees (index -1): may read and write every global on the host,
 need every global on the host on entry, leave the host copy valid and the
@@ -133,11 +143,12 @@ class ProgramOracle:
         for j in range(len(prog.call_proc)):
             self.sites[int(prog.call_proc[j])].append(j)
         self.demand: Dict[int, np.ndarray] = {}                          # call site -> host-read mask (caller words)
+        self.cap: Dict[tuple, Tuple[np.ndarray, np.ndarray]] = {}        # callee context -> (host, device) validity at EXIT
         self.sum_rows: Dict[int, np.ndarray] = {}
         self.visits = 0
 
     # -- call tables in a caller's variable layout ------------------------------------
-    def _caller_tables(self, P: int, summaries: Dict[int, np.ndarray]):
+    def _caller_tables(self, P: int, summaries: Dict[int, np.ndarray], sigma=None):
         cfg = self.p.procs[P]
         wd = cfg.wd
         gw = (self.G + 63) // 64
@@ -158,6 +169,12 @@ class ProgramOracle:
             for base in (SUM_TH_00, SUM_TD_00):
                 s[base + 2] |= lm
                 s[base + 3] |= lm
+            ckey = None if (sigma is None or q < 0) else (q, (tuple(sigma) + (j,))[-2:])
+            if ckey in self.cap:
+                ch, cd = self.cap[ckey]
+                for k4 in range(4):
+                    s[SUM_TH_00 + k4, :gw] &= ch | ~gm[:gw]
+                    s[SUM_TD_00 + k4, :gw] &= cd | ~gm[:gw]
             sums[k] = s
         return call, sums
 
@@ -171,9 +188,9 @@ class ProgramOracle:
                 R[blk] |= m
         return cfg, R
 
-    def _solve(self, P, summaries, boundary, summary_mode=False):
+    def _solve(self, P, summaries, boundary, summary_mode=False, sigma=None):
         cfg, R = self._cfg_with_demands(P)
-        call, sums = self._caller_tables(P, summaries)
+        call, sums = self._caller_tables(P, summaries, sigma)
         view = type(cfg)(n_blocks=cfg.n_blocks, n_vars=cfg.n_vars, succ_ptr=cfg.succ_ptr, succ_idx=cfg.succ_idx,
                          edge_kind=cfg.edge_kind, space=cfg.space, R=R, W=cfg.W, entry=cfg.entry, exit=cfg.exit)
         self.visits += 1
@@ -194,6 +211,12 @@ class ProgramOracle:
         comps = tarjan(n, succ)
         S: Dict[int, np.ndarray] = {}
         for comp in comps:
+            if len(comp) == 1 and comp[0] not in succ[comp[0]]:
+                # not recursive: every callee is final, one evaluation is exact
+                q = comp[0]
+                S[q] = self._evaluate(q, S)
+                S[q][:4] = self._may(q, S)
+                continue
             for q in comp:
                 r = np.zeros((SUM_ROWS, gw), np.uint64)
                 for k in range(4):
@@ -267,11 +290,14 @@ class ProgramOracle:
         return m & gm
 
     # -- top-down -------------------------------------------------------------------
-    def contexts(self, S) -> Tuple[Dict, Dict[int, np.ndarray]]:
-        """Context boundaries {(proc, sigma): (ev_h, ev_d, lx_h, lx_d)} and the
-        host-read demands they require."""
+    def contexts(self, S):
+        """Context boundaries {(proc, sigma): (ev_h, ev_d, lx_h, lx_d)}, the
+        host-read demands they require and, per call site, the validity at
+        EXIT (final placement) of the contexts it leads to."""
         G = self.G
+        gw = (G + 63) // 64
         ctx: Dict[Tuple[int, tuple], List[np.ndarray]] = {}
+        last: Dict[Tuple[int, tuple], dict] = {}
         feeders: Dict[Tuple[int, tuple], set] = defaultdict(set)
         work = deque()
         for r in self.p.roots:
@@ -282,7 +308,8 @@ class ProgramOracle:
         while work:
             key = work.popleft()
             P, sigma = key
-            cfg, call, sums, res = self._solve(P, S, ctx[key])
+            cfg, call, sums, res = self._solve(P, S, ctx[key], sigma=sigma)
+            last[key] = res
             wd = cfg.wd
             for j in self.sites[P]:
                 q = int(self.p.callee[j])
@@ -319,38 +346,40 @@ class ProgramOracle:
                 nkey = (q, (sigma + (j,))[-2:])
                 feeders[nkey].add(j)
                 if nkey not in ctx:
-                    ctx[nkey] = [ev_h, ev_d, lx_h, lx_d]
-                    work.append(nkey)
+                    m = [ev_h, ev_d, lx_h, lx_d]
                 else:
                     old = ctx[nkey]
                     m = [old[0] & ev_h, old[1] & ev_d, old[2] | lx_h, old[3] | lx_d]
-                    if any(not np.array_equal(a, b) for a, b in zip(old, m)):
-                        ctx[nkey] = m
-                        if nkey not in work:
-                            work.append(nkey)
-        # variables a merged context leaves valid nowhere: assume the host copy
-        # and make every feeding call site provide it
-        for key, b in ctx.items():
-            q = key[0]
-            qwd = self.p.procs[q].wd
-            gq = _gmask(G, qwd)
-            nowhere = gq & ~(b[0] | b[1])
-            if nowhere.any():
-                b[0] = b[0] | nowhere
-                for j in feeders[key]:
-                    P = int(self.p.call_proc[j])
-                    pwd = self.p.procs[P].wd
-                    d = new_demand.get(j, np.zeros(pwd, np.uint64))
-                    gw = min(pwd, qwd)
-                    d[:gw] |= nowhere[:gw]
-                    new_demand[j] = d
-        return ctx, new_demand
+                # variables valid in neither space (must-validity is empty after
+                # a join of host-fresh and device-fresh paths, or after a meet of
+                # callers): assume the host copy and make every call site that
+                # feeds this context provide it
+                nowhere = gq & ~(m[0] | m[1])
+                if nowhere.any():
+                    m[0] = m[0] | nowhere
+                    for jj in feeders[nkey]:
+                        P2 = int(self.p.call_proc[jj])
+                        pwd = self.p.procs[P2].wd
+                        d = new_demand.get(jj, np.zeros(pwd, np.uint64))
+                        d[:gw] |= nowhere[:gw]
+                        new_demand[jj] = d
+                if nkey not in ctx or any(not np.array_equal(a, b) for a, b in zip(ctx[nkey], m)):
+                    ctx[nkey] = m
+                    if nkey not in work:
+                        work.append(nkey)
+        caps: Dict[tuple, Tuple[np.ndarray, np.ndarray]] = {}
+        for key, res in last.items():
+            if key[1]:
+                qc = self.p.procs[key[0]]
+                caps[key] = (res["avf_h"][qc.exit][:gw].copy(), res["avf_d"][qc.exit][:gw].copy())
+        return ctx, new_demand, caps
 
-    def analyze(self, max_rounds: int = 20):
+    def analyze(self, max_rounds: int = 64):
         """Summaries, contexts and per-context results (with demands settled)."""
+        gm = _gmask(self.G, (self.G + 63) // 64)
         for _ in range(max_rounds):
             S = self.summarize()
-            ctx, nd = self.contexts(S)
+            ctx, nd, caps = self.contexts(S)
             grew = False
             for j, m in nd.items():
                 old = self.demand.get(j)
@@ -358,9 +387,15 @@ class ProgramOracle:
                 if old is None or not np.array_equal(old, cur):
                     self.demand[j] = cur
                     grew = True
+            caps = {k: (ch & gm, cd & gm) for k, (ch, cd) in caps.items()}
+            if caps.keys() != self.cap.keys() or any(
+                    not (np.array_equal(caps[k][0], self.cap[k][0]) and np.array_equal(caps[k][1], self.cap[k][1]))
+                    for k in caps):
+                self.cap = caps
+                grew = True
             if not grew:
                 results = {}
                 for key, b in ctx.items():
-                    results[key] = self._solve(key[0], S, b)[3]
+                    results[key] = self._solve(key[0], S, b, sigma=key[1])[3]
                 return S, ctx, results
-        raise RuntimeError("demands did not settle")
+        raise RuntimeError("demands and caps did not settle")

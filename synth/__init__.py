@@ -377,15 +377,25 @@ def program(seed: int, n_procs: int = 2000, n_globals: int = 256, n_locals: int 
         k = min(int(rng.poisson(mean_calls)), max_calls)
         if k:
             calls[i].extend(int(x) for x in rng.integers(i + 1, n_procs, size=k))
-    members = rng.permutation(n_procs)[:scc_procs].tolist() if scc_procs else []
-    pos = 0
-    while pos < len(members):
-        sz = int(rng.integers(scc_size[0], scc_size[1] + 1))
-        grp = members[pos:pos + sz]
-        pos += sz
-        if len(grp) >= 2:
-            for a, b in zip(grp, grp[1:] + grp[:1]):
-                calls[a].append(int(b))
+    # recursive groups are runs of consecutive procedures: calls of the random
+    # DAG only go to higher indices, so a cycle closed inside a run cannot pull
+    # procedures outside the run into its strongly connected component
+    placed = 0
+    taken = np.zeros(n_procs, bool)
+    attempts = 0
+    while placed < scc_procs and attempts < 100 * max(scc_procs, 1):
+        attempts += 1
+        sz = min(int(rng.integers(scc_size[0], scc_size[1] + 1)), scc_procs - placed)
+        if sz < 2:
+            break
+        start = int(rng.integers(0, n_procs - sz + 1))
+        if taken[start:start + sz].any():
+            continue
+        taken[start:start + sz] = True
+        grp = list(range(start, start + sz))
+        for a, b in zip(grp, grp[1:] + grp[:1]):
+            calls[a].append(int(b))
+        placed += sz
     if external_frac > 0:
         for i in range(n_procs):
             if rng.random() < external_frac:
@@ -396,8 +406,16 @@ def program(seed: int, n_procs: int = 2000, n_globals: int = 256, n_locals: int 
     seeds = [int(x) for x in rng.integers(0, 1 << 62, size=n_procs)]
 
     def gen(i):
-        return make_cfg(seeds[i], n_user=sizes[i], n_vars=nv, max_loop_depth=max_loop_depth,
-                        device_frac=device_frac, p_read=p_read, p_write=p_write, n_call_sites=len(calls[i]))
+        # a procedure too small to hold all its call statements is regrown
+        # (deterministically) until it does, so every call of the graph exists
+        n = sizes[i]
+        for attempt in range(64):
+            c = make_cfg(seeds[i] + attempt, n_user=n, n_vars=nv, max_loop_depth=max_loop_depth,
+                         device_frac=device_frac, p_read=p_read, p_write=p_write, n_call_sites=len(calls[i]))
+            if len(c.call_blocks) == len(calls[i]):
+                return c
+            n += max(2, n // 4)
+        raise RuntimeError("procedure %d cannot hold %d call sites" % (i, len(calls[i])))
     threads = threads or min(16, os.cpu_count() or 4)
     with ThreadPoolExecutor(max_workers=threads) as ex:
         procs = list(ex.map(gen, range(n_procs)))

@@ -287,3 +287,244 @@ def simulate_paths(cfg, res, walks: int, seed: int, cap_factor: int = 50) -> Tup
         if len(errs) > 20:
             break
     return errs, copies / max(walks, 1)
+
+
+# --------------------------------------------------------------------------
+# interprocedural checks
+# --------------------------------------------------------------------------
+def _bitset(v: int, n: int) -> np.ndarray:
+    return np.array([(v >> i) & 1 for i in range(n)], dtype=bool)
+
+
+def _vars_of(row: np.ndarray) -> List[int]:
+    v = row_int(row)
+    out = []
+    i = 0
+    while v:
+        if v & 1:
+            out.append(i)
+        v >>= 1
+        i += 1
+    return out
+
+
+def inline_program(prog, root: int, demands: Dict[int, np.ndarray], cap_depth: int = -1):
+    """Inline every call reached from ``root``.
+
+    Each call block keeps its own accesses (plus the host reads that
+    ``demands`` adds at that call site) and then branches into a fresh copy of
+    the callee, whose EXIT branches to the call block's successors.  Globals
+    (the first ``prog.n_globals`` variables) are shared; every inlined copy
+    gets fresh variables for the callee's locals, which are not live after
+    the program.  Returns (cfg, instances, pos) where instances lists
+    (procedure, call string, block offset, variable map) in creation order and
+    ``pos`` maps an instance block id to its id in the returned CFG.
+
+    With ``cap_depth >= 0`` a call made at that nesting depth is not expanded:
+    a host block that writes every global (and reads none) stands in for it,
+    so no next use crosses it.  Unrolling recursion this way gives the next
+    use of the paths with at most ``cap_depth`` nested calls, a lower bound
+    that grows to the exact solution."""
+    import synth
+    G = prog.n_globals
+    site_at: Dict[Tuple[int, int], int] = {}
+    for j in range(len(prog.call_proc)):
+        site_at[(int(prog.call_proc[j]), int(prog.call_block[j]))] = j
+    blocks: List[Tuple[int, List[int], List[int]]] = []
+    edges: List[Tuple[int, int, int]] = []
+    instances = []
+    nvars = [G]
+
+    def add(P: int, sigma: tuple) -> int:
+        cfg = prog.procs[P]
+        off = len(blocks)
+        vmap = list(range(G)) + list(range(nvars[0], nvars[0] + cfg.n_vars - G))
+        nvars[0] += cfg.n_vars - G
+        instances.append((P, sigma, off, vmap))
+        R = cfg.R.reshape(cfg.n_blocks, cfg.wd)
+        W = cfg.W.reshape(cfg.n_blocks, cfg.wd)
+        for b in range(cfg.n_blocks):
+            rd = set(_vars_of(R[b]))
+            j = site_at.get((P, b))
+            if j is not None and j in demands:
+                rd |= set(_vars_of(demands[j]))
+            blocks.append((int(cfg.space[b]), sorted(vmap[v] for v in rd), sorted(vmap[v] for v in _vars_of(W[b]))))
+        for b in range(cfg.n_blocks):
+            outs = [(int(cfg.succ_idx[e]) + off, int(cfg.edge_kind[e]))
+                    for e in range(int(cfg.succ_ptr[b]), int(cfg.succ_ptr[b + 1]))]
+            j = site_at.get((P, b))
+            if j is not None:
+                q = int(prog.callee[j])
+                assert q >= 0, "inlining needs every callee's body"
+                if len(sigma) == cap_depth:
+                    cap = len(blocks)
+                    blocks.append((0, [], list(range(G))))
+                    edges.append((b + off, cap, 0))
+                    for (t, k) in outs:
+                        edges.append((cap, t, k))
+                    continue
+                qoff = add(q, sigma + (j,))
+                qc = prog.procs[q]
+                edges.append((b + off, qc.entry + qoff, 0))
+                for (t, k) in outs:
+                    edges.append((qc.exit + qoff, t, k))
+            else:
+                for (t, k) in outs:
+                    edges.append((b + off, t, k))
+        return off
+
+    add(root, ())
+    rc = prog.procs[root]
+    nb = len(blocks)
+    order = [rc.entry] + [b for b in range(nb) if b not in (rc.entry, rc.exit)] + [rc.exit]
+    pos = {b: i for i, b in enumerate(order)}
+    cfg, _ = synth.from_edges([blocks[b] for b in order], [(pos[s], pos[d], k) for (s, d, k) in edges], nvars[0])
+    lx = synth.var_mask(nvars[0]).copy()
+    for (_, _, _, vmap) in instances[1:]:
+        for v in vmap[G:]:
+            lx[v >> 6] &= ~np.uint64(1 << (v & 63))
+    cfg.exit_live_h = lx
+    return cfg, instances, pos
+
+
+class _CtxBits:
+    """Per-context placement as boolean rows, built on first use."""
+
+    def __init__(self, cfg, res):
+        nv, wd = cfg.n_vars, cfg.wd
+        self.ie = [[_bitset(x, nv) for x in rows_int(res[k].reshape(-1, wd))] for k in ("ins_entry_h", "ins_entry_d")]
+        self.ig = [[_bitset(x, nv) for x in rows_int(res[k].reshape(-1, wd))] if cfg.n_edges else []
+                   for k in ("ins_edge_h", "ins_edge_d")]
+
+
+def simulate_program(prog, ctx, results, demands: Dict[int, np.ndarray], walks: int, seed: int,
+                     max_steps: int = 3000, max_depth: int = 30) -> Tuple[List[str], int]:
+    """Random walks over a whole program, checking the per-context placements.
+
+    A call block runs its own accesses (and the host reads that ``demands``
+    adds there), then the callee from ENTRY to EXIT in the context named by
+    the last two call sites, then the caller takes a successor.  Globals keep
+    one version state across frames; locals are per activation and start
+    valid on the host.  An external callee reads every global on the host and
+    writes every global there.  Copies placed in the running context fire as
+    walked; every read, and every copy's source, must hold the latest
+    version; at the program's exit the live copies must be current.  A walk
+    that exceeds ``max_steps`` or ``max_depth`` stops where it is (everything
+    it did so far was checked).  Returns (violations, walks cut short)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    G = prog.n_globals
+    site_at: Dict[Tuple[int, int], int] = {}
+    for j in range(len(prog.call_proc)):
+        site_at[(int(prog.call_proc[j]), int(prog.call_block[j]))] = j
+    views: Dict[int, View] = {}
+    rw: Dict[int, Tuple[list, list]] = {}
+    bits: Dict[tuple, _CtxBits] = {}
+    dem = {j: _bitset(row_int(m), prog.procs[int(prog.call_proc[j])].n_vars) for j, m in demands.items()}
+
+    def view(P):
+        if P not in views:
+            V = View(prog.procs[P])
+            views[P] = V
+            rw[P] = ([_bitset(x, V.cfg.n_vars) for x in V.R], [_bitset(x, V.cfg.n_vars) for x in V.W])
+        return views[P]
+
+    def cbits(key):
+        if key not in bits:
+            bits[key] = _CtxBits(prog.procs[key[0]], results[key])
+        return bits[key]
+
+    errs: List[str] = []
+    cut = 0
+    for wk in range(walks):
+        root = prog.roots[int(rng.integers(len(prog.roots)))]
+        rv = view(root)
+        nv0 = rv.cfg.n_vars
+        ev = [_bitset(rv.ev[0], nv0), _bitset(rv.ev[1], nv0)]
+        gver = np.zeros(G, np.int64)
+        gvs = [np.where(ev[s][:G], 0, -1).astype(np.int64) for s in (0, 1)]
+
+        def frame(P, key):
+            L = prog.procs[P].n_vars - G
+            fe = ev if P == root and key == (root, ()) else [np.ones(prog.procs[P].n_vars, bool),
+                                                            np.zeros(prog.procs[P].n_vars, bool)]
+            return dict(P=P, key=key, b=prog.procs[P].entry, after=False, lver=np.zeros(L, np.int64),
+                        lvs=[np.where(fe[s][G:], 0, -1).astype(np.int64) for s in (0, 1)])
+
+        stack = [frame(root, (root, ()))]
+        steps = 0
+        while stack and len(errs) <= 20:
+            fr = stack[-1]
+            P, key, b = fr["P"], fr["key"], fr["b"]
+            V = view(P)
+            Rb, Wb = rw[P]
+            cb = cbits(key)
+            ver = np.concatenate([gver, fr["lver"]])
+            vs = [np.concatenate([gvs[s], fr["lvs"][s]]) for s in (0, 1)]
+
+            def store():
+                gver[:] = ver[:G]
+                fr["lver"][:] = ver[G:]
+                for s in (0, 1):
+                    gvs[s][:] = vs[s][:G]
+                    fr["lvs"][s][:] = vs[s][G:]
+
+            def copy(mask, s, where):
+                if mask.any():
+                    bad = mask & (vs[1 - s] != ver)
+                    if bad.any():
+                        errs.append("walk %d %s: stale copy source into space %d at %s, vars %s"
+                                    % (wk, key, s, where, np.nonzero(bad)[0][:4].tolist()))
+                    vs[s] = np.where(mask, ver, vs[s])
+
+            if not fr["after"]:
+                for s in (0, 1):
+                    copy(cb.ie[s][b], s, "entry of %d" % b)
+                if b == V.exit:
+                    if len(stack) == 1:
+                        for s in (0, 1):
+                            bad = _bitset(V.lx[s], V.cfg.n_vars) & (vs[s] != ver)
+                            if bad.any():
+                                errs.append("walk %d: stale live-out in space %d, vars %s"
+                                            % (wk, s, np.nonzero(bad)[0][:4].tolist()))
+                    store()
+                    stack.pop()
+                    continue
+                x = V.space[b]
+                j = site_at.get((P, b))
+                rd = Rb[b] | dem[j] if j is not None and j in dem else Rb[b]
+                bad = rd & (vs[x] != ver)
+                if bad.any():
+                    errs.append("walk %d %s: stale read in block %d (space %d), vars %s"
+                                % (wk, key, b, x, np.nonzero(bad)[0][:4].tolist()))
+                if Wb[b].any():
+                    ver = ver + Wb[b].astype(np.int64)
+                    vs[x] = np.where(Wb[b], ver, vs[x])
+                fr["after"] = True
+                if j is not None:
+                    q = int(prog.callee[j])
+                    if q < 0:
+                        bad = vs[0][:G] != ver[:G]
+                        if bad.any():
+                            errs.append("walk %d %s: external call at %d reads stale host globals %s"
+                                        % (wk, key, b, np.nonzero(bad)[0][:4].tolist()))
+                        ver[:G] += 1
+                        vs[0][:G] = ver[:G]
+                    else:
+                        store()
+                        if len(stack) >= max_depth or steps >= max_steps:
+                            cut += 1
+                            break
+                        stack.append(frame(q, (q, (key[1] + (j,))[-2:])))
+                        continue
+            steps += 1
+            if steps >= max_steps:
+                cut += 1
+                break
+            succ = V.succ[b]
+            t, e = succ[int(rng.integers(len(succ)))]
+            for s in (0, 1):
+                copy(cb.ig[s][e], s, "edge %d" % e)
+            store()
+            fr["b"] = t
+            fr["after"] = False
+    return errs, cut
