@@ -137,13 +137,13 @@ def main():
         t = time.perf_counter()
         best = rb.plan.autotune(stream, trials=2)
         d = json.loads(rb.plan.describe())
-        tuned[key] = {k: d[k] for k in ("lds_bytes", "max_ns", "min_tbits", "wg_per_cu")}
+        tuned[key] = {k: d[k] for k in ("lds_bytes", "wg_per_cu")}
         tuned[key]["best_ms"] = best
         save_tuned(tuned)
         log("autotune: best %.3f ms in %.1f s -> %s" % (best, time.perf_counter() - t, rb.plan.describe()))
     elif key in tuned:
         c = tuned[key]
-        rb.plan.configure(c["lds_bytes"], c["max_ns"], c["min_tbits"], c["wg_per_cu"])
+        rb.plan.configure(c["lds_bytes"], c["wg_per_cu"])
         log("using the stored autotuner choice %s" % c)
     plan_desc = json.loads(rb.plan.describe())
     for _ in range(args.warmup):
@@ -215,11 +215,11 @@ def main():
         sb = ResidentBatch(ctx, [c2], want=want)
         if "single" in tuned:
             c = tuned["single"]
-            sb.plan.configure(c["lds_bytes"], c["max_ns"], c["min_tbits"], c["wg_per_cu"])
+            sb.plan.configure(c["lds_bytes"], c["wg_per_cu"])
         elif args.autotune:
             sb.plan.autotune(stream, trials=1)
             d = json.loads(sb.plan.describe())
-            tuned["single"] = {k: d[k] for k in ("lds_bytes", "max_ns", "min_tbits", "wg_per_cu")}
+            tuned["single"] = {k: d[k] for k in ("lds_bytes", "wg_per_cu")}
             save_tuned(tuned)
         for _ in range(2):
             sb.run(stream)

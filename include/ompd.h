@@ -173,15 +173,16 @@ int ompd_plan_create(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int3
                      ompd_plan** out);
 int ompd_plan_run(ompd_plan* plan, void* stream);
 int ompd_plan_status(ompd_plan* plan, int32_t* per_cfg);
-/* Autotuner: times each candidate (slice width rule, LDS per workgroup,
- * workgroups per CU) `trials` times on `stream` and keeps the fastest.
- * Results are bit-identical for every candidate.  best_ms may be NULL. */
+/* Autotuner: times each candidate launch configuration (LDS ring bytes per
+ * solve wavefront, wavefronts per CU) `trials` times on `stream` and keeps
+ * the fastest.  Results are bit-identical for every candidate.  best_ms may
+ * be NULL. */
 int ompd_plan_autotune(ompd_plan* plan, void* stream, int32_t trials, float* best_ms);
 /* Set the launch configuration by hand (what the autotuner chooses among):
- * LDS bytes per solve workgroup (0 = automatic), most bit-slices per tile,
- * narrowest slice width (8, 16 or 32 bits), workgroups per CU (0 = as many
- * as fit).  OMPD_E_NOMEM if a CFG does not fit the LDS budget. */
-int ompd_plan_configure(ompd_plan* plan, int64_t lds_bytes, int32_t max_ns, int32_t min_tbits, int32_t wg_per_cu);
+ * LDS bytes per solve wavefront for the ring of recently solved blocks
+ * (0 = default, 8 KiB; clamped to [1 KiB, the device limit]) and solve
+ * wavefronts per CU (0 = as many as fit). */
+int ompd_plan_configure(ompd_plan* plan, int64_t lds_bytes, int32_t wg_per_cu);
 /* Describe the plan's current configuration as a NUL-terminated string. */
 int ompd_plan_describe(ompd_plan* plan, char* buf, int32_t len);
 /* Duration (ms) of the last ompd_plan_run measured with HIP events on its

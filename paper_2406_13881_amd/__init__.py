@@ -121,7 +121,7 @@ def lib():
             L.ompd_plan_status.argtypes = [_vp, _vp]
             L.ompd_plan_autotune.argtypes = [_vp, _vp, _i32, P(ctypes.c_float)]
             L.ompd_plan_describe.argtypes = [_vp, ctypes.c_char_p, _i32]
-            L.ompd_plan_configure.argtypes = [_vp, ctypes.c_int64, _i32, _i32, _i32]
+            L.ompd_plan_configure.argtypes = [_vp, ctypes.c_int64, _i32]
             L.ompd_plan_last_ms.argtypes = [_vp, P(ctypes.c_float), P(ctypes.c_float)]
             L.ompd_plan_destroy.argtypes = [_vp]
             L.ompd_plan_destroy.restype = None
@@ -416,8 +416,9 @@ class Plan:
         _check(lib().ompd_plan_autotune(self.h, _vp(stream) if stream else None, int(trials), ctypes.byref(best)))
         return best.value
 
-    def configure(self, lds_bytes: int = 0, max_ns: int = 16, min_tbits: int = 8, wg_per_cu: int = 0):
-        _check(lib().ompd_plan_configure(self.h, int(lds_bytes), int(max_ns), int(min_tbits), int(wg_per_cu)))
+    def configure(self, lds_bytes: int = 0, wg_per_cu: int = 0):
+        """LDS ring bytes per solve wavefront (0 = default) and wavefronts per CU (0 = as many as fit)."""
+        _check(lib().ompd_plan_configure(self.h, int(lds_bytes), int(wg_per_cu)))
 
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(1024)

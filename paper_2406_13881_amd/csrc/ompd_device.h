@@ -7,7 +7,7 @@ namespace ompd {
 
 enum : int32_t {
     INFO_STATUS = 0,      // 0 ok, else an OMPD_E_* code
-    INFO_NLEVELS = 1,     // number of levels of the forward-edge DAG
+    INFO_RESERVED = 1,
     INFO_SWEEPS = 2,      // [2..7] max sweeps per phase over the CFG's tiles
     INFO_WORDS = 16
 };
@@ -47,12 +47,14 @@ struct DevCfg {
     uint8_t* var_kind;                     // may be NULL
     uint8_t* after_dev;                    // may be NULL
     uint8_t* before_dev;                   // may be NULL
-    uint64_t* aveout_h; uint64_t* aveout_d;
-    uint64_t* mayp_h;   uint64_t* mayp_d;
+    uint64_t* aveout_h; uint64_t* aveout_d;   // eager validity out; later validity after placement
+    uint64_t* mayp_h;   uint64_t* mayp_d;     // pending copies
+    uint64_t* later_h;  uint64_t* later_d;    // delayed copies
+    uint64_t* flg;      // per tile: [4][nb] words of the flag lane
     int32_t* pred_ptr;  int32_t* pred_idx; int32_t* pred_eid;
-    int32_t* level_ptr; int32_t* level_blk; int32_t* tmp;
-    int32_t* rec_f;     // [2*nb] int4: level-ordered records with predecessors
-    int32_t* rec_b;     // [2*nb] int4: level-ordered records with successors
+    int32_t* tmp;
+    int32_t* rec_f;     // [2*nb] int4: block records with predecessors, in block-id order
+    int32_t* rec_b;     // [2*nb] int4: block records with successors, in block-id order
     int32_t* info;
 };
 
@@ -60,12 +62,18 @@ struct DevCfg {
 constexpr uint32_t REC_COUNT = 0x00FFFFFFu;
 constexpr uint32_t REC_ENTRY = 1u << 24, REC_EXIT = 1u << 25, REC_DEV = 1u << 26, REC_CALL = 1u << 27;
 
-// A tile: one CFG, a range of bit-slices of width tbits (8, 16 or 32).
+// A tile: one CFG and a run of its 64-bit variable words, solved by one
+// wavefront (one lane per word plus the flag lane).
+constexpr int TILE_WORDS = 63;
 struct Tile {
     int32_t cfg;
-    int32_t tbits;
-    int32_t s0;   // first slice (in units of tbits)
-    int32_t ns;   // number of slices (0 only when the CFG has no variables)
+    int32_t s0;      // first word
+    int32_t nw;      // words (0 only when the CFG has no variables)
+    int32_t fslot;   // index of the tile within its CFG (flag-lane storage)
 };
+
+// Tiles of a CFG with wd words: ceil(wd / TILE_WORDS) (at least one), the
+// words split as evenly as possible.
+inline int tiles_of(int wd) { return wd <= 0 ? 1 : (wd + TILE_WORDS - 1) / TILE_WORDS; }
 
 }  // namespace ompd

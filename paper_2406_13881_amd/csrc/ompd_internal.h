@@ -27,10 +27,8 @@ struct ompd_ctx {
 
 // Tunable launch configuration of a plan; results never depend on it.
 struct PlanConfig {
-    size_t lds_bytes = 0;   // LDS per workgroup of the solve kernel (0 = automatic)
-    int max_ns = 16;        // most slices per tile
-    int min_tbits = 8;      // narrowest slice allowed
-    int wg_per_cu = 0;      // 0 = as many as fit
+    size_t lds_bytes = 0;   // LDS ring of recent blocks per solve wavefront (0 = default)
+    int wg_per_cu = 0;      // solve wavefronts per CU (0 = as many as fit)
     bool use_graph = true;  // replay a captured HIP graph
 };
 
@@ -61,7 +59,7 @@ struct ompd_plan {
 int ompd_fail(int code, const std::string& msg);
 
 struct ScratchOff {
-    size_t aveout, mayp, nu, ave, ie, ig, avf, bnd, pp, pi, pe, lvp, lvb, tmp, recf, recb, info;
+    size_t aveout, mayp, later, flg, nu, ave, ie, ig, avf, bnd, pp, pi, pe, tmp, recf, recb, info;
 };
 size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o);
 void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const ScratchOff& o, uint32_t flags,
@@ -72,7 +70,6 @@ int ompd_make_plan_tiles(ompd_ctx* ctx, const std::vector<ompd::DevCfg>& cfgs, c
 int ompd_launch_prep(const ompd::DevCfg* d_cfgs, int n, int32_t* d_counter, size_t lds, hipStream_t s);
 int ompd_launch_solve(const ompd::DevCfg* d_cfgs, const ompd::Tile* d_tiles, int n_tiles, int32_t* d_counter,
                       int grid, size_t lds, hipStream_t s);
-size_t ompd_tile_lds(int nb, int ns, int tbits);
 int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n, uint32_t flags,
                     const PlanConfig& pc, ompd_plan** out);
 int ompd_plan_retile(ompd_plan* p, const PlanConfig& pc);

@@ -17,7 +17,13 @@
 
 namespace ompd {
 extern "C" __global__ void ompd_k_prep(const DevCfg*, int, int32_t*);
-extern "C" __global__ void ompd_k_solve(const DevCfg*, const Tile*, int, int32_t*);
+extern "C" __global__ void ompd_k_nu(const DevCfg*, const Tile*, int, int32_t*, int);
+extern "C" __global__ void ompd_k_ave(const DevCfg*, const Tile*, int, int32_t*, int);
+extern "C" __global__ void ompd_k_mayp(const DevCfg*, const Tile*, int, int32_t*, int);
+extern "C" __global__ void ompd_k_later(const DevCfg*, const Tile*, int, int32_t*, int);
+extern "C" __global__ void ompd_k_avf(const DevCfg*, const Tile*, int, int32_t*, int);
+static const void* const k_phases[5] = {(const void*)ompd_k_nu, (const void*)ompd_k_ave, (const void*)ompd_k_mayp,
+                                        (const void*)ompd_k_later, (const void*)ompd_k_avf};
 }  // namespace ompd
 
 using namespace ompd;
@@ -64,7 +70,7 @@ extern "C" int ompd_ctx_create(ompd_ctx** out, int device_ordinal, uint64_t budg
     lds_max = std::min<size_t>(lds_max ? lds_max : 64 * 1024, 160 * 1024);
     // dynamic LDS limit per kernel = device limit minus the kernel's static LDS
     int dyn = (int)lds_max;
-    for (const void* k : {(const void*)ompd_k_solve, (const void*)ompd_k_prep}) {
+    for (const void* k : {k_phases[0], k_phases[1], k_phases[2], k_phases[3], k_phases[4], (const void*)ompd_k_prep}) {
         hipFuncAttributes fa{};
         int st = 0;
         if (hipFuncGetAttributes(&fa, k) == hipSuccess) st = (int)fa.sharedSizeBytes;
@@ -102,41 +108,21 @@ extern "C" int ompd_device_info(ompd_ctx* c, int32_t* n_cu, int32_t* lds_bytes, 
 // ---------------------------------------------------------------------------
 // tile rules
 // ---------------------------------------------------------------------------
-// LDS bytes a tile of nb blocks and ns slices of tbits needs.
-size_t ompd_tile_lds(int nb, int ns, int tbits)
-{
-    size_t nsi = ns > 0 ? ns : 1;
-    size_t a16 = ~(size_t)15;
-    return ((2 * (size_t)nb * nsi * (tbits / 8) + 15) & a16) + (((size_t)nb + 15) & a16) + 12 * nsi;
-}
-
-static int floor_pow2(long x) { int p = 1; while ((long)p * 2 <= x) p *= 2; return p; }
-
-// Cut one CFG into tiles: the widest slice type that fits `lds` with one
-// slice, then as many slices per tile (a power of two, at most max_ns) as fit.
-static int make_tiles(int ci, int nb, int nv, size_t lds, int max_ns, int min_tbits, std::vector<Tile>& out)
+// Cut one CFG into tiles: ceil(wd / TILE_WORDS) runs of words, split evenly.
+static void make_tiles(int ci, int nv, std::vector<Tile>& out)
 {
     int wd = (nv + 63) / 64;
-    int tb = 0;
-    for (int t : {32, 16, 8}) {
-        if (t < min_tbits) continue;
-        if (ompd_tile_lds(nb, 1, t) <= lds) { tb = t; break; }
-    }
-    if (!tb) return -1;
+    int t = tiles_of(wd);
     if (wd == 0) {
-        out.push_back(Tile{ci, tb, 0, 0});
-        return 0;
+        out.push_back(Tile{ci, 0, 0, 0});
+        return;
     }
-    int rw = wd * (64 / tb);
-    int ns = 1;
-    while (ns * 2 <= max_ns && ns * 2 <= rw && ompd_tile_lds(nb, ns * 2, tb) <= lds) ns *= 2;
-    int s = 0;
-    while (s < rw) {
-        int k = std::min(ns, floor_pow2(rw - s));
-        out.push_back(Tile{ci, tb, s, k});
-        s += k;
+    int s0 = 0;
+    for (int k = 0; k < t; ++k) {
+        int n = wd / t + (k < wd % t ? 1 : 0);
+        out.push_back(Tile{ci, s0, n, k});
+        s0 += n;
     }
-    return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -169,6 +155,8 @@ size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o)
     size_t bv = (size_t)g.n_blocks * wd * 8, ev = (size_t)g.n_edges * wd * 8;
     o.aveout = take(2 * bv);
     o.mayp = take(2 * bv);
+    o.later = take(2 * bv);
+    o.flg = take((size_t)tiles_of((int)wd) * 4 * (size_t)g.n_blocks * 8);
     o.nu = (r.nu_host && r.nu_dev) ? SIZE_MAX : take(2 * bv);
     o.ave = (r.ave_host && r.ave_dev) ? SIZE_MAX : take(2 * bv);
     o.ie = (r.ins_entry_to_host && r.ins_entry_to_dev) ? SIZE_MAX : take(2 * bv);
@@ -178,8 +166,6 @@ size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o)
     o.pp = take(4 * ((size_t)g.n_blocks + 1));
     o.pi = take(4 * (size_t)std::max(g.n_edges, 1));
     o.pe = take(4 * (size_t)std::max(g.n_edges, 1));
-    o.lvp = take(4 * ((size_t)g.n_blocks + 1));
-    o.lvb = take(4 * (size_t)g.n_blocks);
     o.tmp = take(4 * ((size_t)g.n_blocks + 1));
     o.recf = take(32 * (size_t)g.n_blocks);
     o.recb = take(32 * (size_t)g.n_blocks);
@@ -225,10 +211,12 @@ void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const
     d.var_kind = r.var_kind; d.after_dev = r.after_dev; d.before_dev = r.before_dev;
     uint64_t* ao = at(o.aveout);
     uint64_t* mp = at(o.mayp);
+    uint64_t* la = at(o.later);
     d.aveout_h = ao; d.aveout_d = ao + bvw; d.mayp_h = mp; d.mayp_d = mp + bvw;
+    d.later_h = la; d.later_d = la + bvw;
+    d.flg = at(o.flg);
     d.pred_ptr = (int32_t*)(base + o.pp); d.pred_idx = (int32_t*)(base + o.pi);
-    d.pred_eid = (int32_t*)(base + o.pe); d.level_ptr = (int32_t*)(base + o.lvp);
-    d.level_blk = (int32_t*)(base + o.lvb); d.tmp = (int32_t*)(base + o.tmp);
+    d.pred_eid = (int32_t*)(base + o.pe); d.tmp = (int32_t*)(base + o.tmp);
     d.rec_f = (int32_t*)(base + o.recf); d.rec_b = (int32_t*)(base + o.recb);
     d.info = (int32_t*)(base + o.info);
     if (bnd_host && wd > 0) {
@@ -242,44 +230,30 @@ void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const
     }
 }
 
-// Tiles for a set of CFGs under a configuration, longest first, and the
-// launch sizes that go with them.
+// Default LDS of one solve wavefront: the ring of recently computed blocks.
+constexpr size_t RING_BYTES_DEFAULT = 8 * 1024;
+
+// Tiles for a set of CFGs, longest first, and the launch sizes that go with
+// them under a configuration.
 int ompd_make_plan_tiles(ompd_ctx* ctx, const std::vector<DevCfg>& cfgs, const PlanConfig& pc,
                          std::vector<Tile>& tiles, size_t& lds_solve, size_t& lds_prep, int& grid_solve)
 {
-    int max_nb = 2;
-    for (const DevCfg& d : cfgs) max_nb = std::max(max_nb, d.nb);
     tiles.clear();
-    size_t lds = pc.lds_bytes;
-    if (lds == 0) {
-        // smallest budget that holds the largest CFG with one 16-bit slice, at least 32 KiB
-        lds = std::max<size_t>(32 * 1024, ompd_tile_lds(max_nb, 1, 16));
-        if (lds > (size_t)ctx->lds_max) lds = std::max<size_t>(32 * 1024, ompd_tile_lds(max_nb, 1, 8));
+    for (int i = 0; i < (int)cfgs.size(); ++i) make_tiles(i, cfgs[i].nv, tiles);
+    // a tile's work ~ its blocks times the sweeps, which grow with the CFG: longest first
+    std::stable_sort(tiles.begin(), tiles.end(),
+                     [&](const Tile& a, const Tile& b) { return cfgs[a.cfg].nb > cfgs[b.cfg].nb; });
+    size_t lds = pc.lds_bytes ? pc.lds_bytes : RING_BYTES_DEFAULT;
+    lds = std::min<size_t>(std::max<size_t>(lds, 1024), ctx->lds_max) & ~(size_t)255;
+    lds_solve = lds;
+    lds_prep = 0;
+    // one grid for every phase kernel: as many wavefronts as the tightest phase keeps resident
+    int per_cu = 1 << 20;
+    for (const void* k : k_phases) {
+        int n = 0;
+        CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64, lds_solve));
+        per_cu = std::min(per_cu, std::max(1, n));
     }
-    lds = std::min<size_t>(lds, ctx->lds_max);
-    for (int i = 0; i < (int)cfgs.size(); ++i) {
-        const DevCfg& d = cfgs[i];
-        if (make_tiles(i, d.nb, d.nv, lds, pc.max_ns, pc.min_tbits, tiles) != 0) {
-            char buf[160];
-            snprintf(buf, sizeof buf, "cfg %d: %d blocks exceed the on-chip budget of %zu bytes", i, d.nb, lds);
-            return ompd_fail(OMPD_E_NOMEM, buf);
-        }
-    }
-    // longest tiles first: work ~ blocks x slices of the widest type
-    std::stable_sort(tiles.begin(), tiles.end(), [&](const Tile& a, const Tile& b) {
-        double wa = (double)cfgs[a.cfg].nb * (1.0 + std::max(a.ns, 1) / 16.0);
-        double wb = (double)cfgs[b.cfg].nb * (1.0 + std::max(b.ns, 1) / 16.0);
-        return wa > wb;
-    });
-    size_t need = 16;
-    for (const Tile& t : tiles) need = std::max(need, ompd_tile_lds(cfgs[t.cfg].nb, t.ns, t.tbits));
-    lds_solve = (need + 255) & ~(size_t)255;
-    lds_prep = 4 * (size_t)max_nb + 64;
-    if (lds_prep > (size_t)ctx->lds_max)
-        return ompd_fail(OMPD_E_NOMEM, "CFG too large for the ingest kernel's on-chip level table");
-    int per_cu = 0;
-    CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)ompd_k_solve, 64, lds_solve));
-    per_cu = std::max(1, per_cu);
     if (pc.wg_per_cu > 0) per_cu = std::min(per_cu, pc.wg_per_cu);
     grid_solve = std::max(1, std::min((int)tiles.size(), per_cu * ctx->n_cu));
     return OMPD_OK;
@@ -384,7 +358,10 @@ int ompd_launch_solve(const DevCfg* d_cfgs, const Tile* d_tiles, int n_tiles, in
                       size_t lds, hipStream_t s)
 {
     if (n_tiles <= 0) return OMPD_OK;
-    hipLaunchKernelGGL(ompd_k_solve, dim3(grid), dim3(64), lds, s, d_cfgs, d_tiles, n_tiles, d_counter);
+    void (*ks[5])(const DevCfg*, const Tile*, int, int32_t*, int) = {ompd_k_nu, ompd_k_ave, ompd_k_mayp,
+                                                                      ompd_k_later, ompd_k_avf};
+    for (auto k : ks)
+        hipLaunchKernelGGL(k, dim3(grid), dim3(64), lds, s, d_cfgs, d_tiles, n_tiles, d_counter, (int)(lds / 8));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return ompd_fail(OMPD_E_DEVICE, std::string("solve launch (grid ") + std::to_string(grid) + ", lds " +
@@ -532,16 +509,12 @@ extern "C" int ompd_plan_last_ms(ompd_plan* p, float* total_ms, float* solve_ms)
     return OMPD_OK;
 }
 
-extern "C" int ompd_plan_configure(ompd_plan* p, int64_t lds_bytes, int32_t max_ns, int32_t min_tbits,
-                                   int32_t wg_per_cu)
+extern "C" int ompd_plan_configure(ompd_plan* p, int64_t lds_bytes, int32_t wg_per_cu)
 {
-    if (!p || lds_bytes < 0 || max_ns < 1 || (min_tbits != 8 && min_tbits != 16 && min_tbits != 32) || wg_per_cu < 0)
-        return ompd_fail(OMPD_E_INVAL, "bad plan configuration");
+    if (!p || lds_bytes < 0 || wg_per_cu < 0) return ompd_fail(OMPD_E_INVAL, "bad plan configuration");
     std::lock_guard<std::mutex> lk(p->ctx->mu);
     PlanConfig c = p->cfg;
     c.lds_bytes = (size_t)lds_bytes;
-    c.max_ns = max_ns;
-    c.min_tbits = min_tbits;
     c.wg_per_cu = wg_per_cu;
     c.use_graph = true;
     return ompd_plan_retile(p, c);
@@ -550,14 +523,13 @@ extern "C" int ompd_plan_configure(ompd_plan* p, int64_t lds_bytes, int32_t max_
 extern "C" int ompd_plan_describe(ompd_plan* p, char* buf, int32_t len)
 {
     if (!p || !buf || len <= 0) return ompd_fail(OMPD_E_INVAL, "bad arguments");
-    int n8 = 0, n16 = 0, n32 = 0;
-    for (const Tile& t : p->h_tiles) (t.tbits == 32 ? n32 : t.tbits == 16 ? n16 : n8)++;
+    long lanes = 0;
+    for (const Tile& t : p->h_tiles) lanes += t.nw;
     snprintf(buf, len,
-             "{\"cfgs\": %d, \"tiles\": %d, \"tiles32\": %d, \"tiles16\": %d, \"tiles8\": %d, \"lds_solve\": %zu, "
-             "\"lds_prep\": %zu, \"grid_solve\": %d, \"lds_bytes\": %zu, \"max_ns\": %d, \"min_tbits\": %d, \"wg_per_cu\": %d, "
-             "\"graph\": %d, \"scratch_bytes\": %zu}",
-             p->n, p->n_tiles, n32, n16, n8, p->lds_solve, p->lds_prep, p->grid_solve, p->cfg.lds_bytes, p->cfg.max_ns,
-             p->cfg.min_tbits, p->cfg.wg_per_cu, p->cfg.use_graph ? 1 : 0, p->scratch_bytes);
+             "{\"cfgs\": %d, \"tiles\": %d, \"words\": %ld, \"lds_solve\": %zu, \"grid_solve\": %d, "
+             "\"lds_bytes\": %zu, \"wg_per_cu\": %d, \"graph\": %d, \"scratch_bytes\": %zu}",
+             p->n, p->n_tiles, lanes, p->lds_solve, p->grid_solve, p->cfg.lds_bytes, p->cfg.wg_per_cu,
+             p->cfg.use_graph ? 1 : 0, p->scratch_bytes);
     return OMPD_OK;
 }
 
@@ -586,16 +558,13 @@ extern "C" int ompd_plan_autotune(ompd_plan* p, void* stream, int32_t trials, fl
     hipStream_t s = (hipStream_t)stream;
     trials = std::max(1, trials);
     std::vector<PlanConfig> cands;
-    const size_t base = std::max<size_t>(16 * 1024, ompd_tile_lds(p->max_nb, 1, 8));
     const size_t lds_cap = (size_t)p->ctx->lds_max;
-    for (size_t lds : {(size_t)0, base, (size_t)32 * 1024, (size_t)40 * 1024, (size_t)54 * 1024, (size_t)80 * 1024,
-                       lds_cap}) {
-        if (lds && (lds < base || lds > lds_cap)) continue;
-        for (int max_ns : {4, 16, 64}) {
+    for (size_t lds : {(size_t)2048, (size_t)4096, (size_t)8192, (size_t)16384, (size_t)32768}) {
+        if (lds > lds_cap) continue;
+        for (int wpc : {0, 8, 16}) {
             PlanConfig c = p->cfg;
             c.lds_bytes = lds;
-            c.max_ns = max_ns;
-            c.wg_per_cu = 0;
+            c.wg_per_cu = wpc;
             cands.push_back(c);
         }
     }
