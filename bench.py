@@ -13,7 +13,11 @@ Printed JSON line: the metric of the benchmark plus
   roofline      HBM roofline of the dominant kernel (the persistent solve),
   cpu_baseline  the CPU oracle timed on a bounded sample of the same batch,
   plain         the same CFGs as one plain per-CFG solve each, back to back,
-  single        the 16,384-block x 2,048-variable procedure on its own.
+  single        the 16,384-block x 2,048-variable procedure on its own,
+  serving       a stream of requests shaped like that procedure through the
+                serving loop (submit / poll): capacity in saturated mode,
+                then Poisson arrivals at 0.5, 0.8 and 1.0 x capacity with
+                p50 / p99 of completion minus arrival time.
 """
 import argparse
 import json
@@ -70,6 +74,87 @@ def save_tuned(d):
         json.dump(d, f, indent=1, sort_keys=True)
 
 
+# What a serving request asks for: the placement and its labels.
+SERVE_WANT = ("ins_entry_h", "ins_entry_d", "ins_edge_h", "ins_edge_d", "var_kind", "after_dev", "before_dev")
+
+
+def serving(ctx, n_pool, n_cap, n_warm, n_meas, loads):
+    """Capacity (requests/s with the queue kept full) and latency percentiles
+    under Poisson arrivals, on C2-shaped requests drawn from a pool of
+    distinct seeded CFGs."""
+    import numpy as np
+    import synth
+    import paper_2406_13881_amd as ompd
+    pool = [synth.c5_request(i) for i in range(n_pool)]
+
+    def drive(arrivals_s):
+        """Submit request k at arrivals_s[k] (None = as fast as admission allows);
+        returns per-request (arrival_ns, done_ns)."""
+        n = len(arrivals_s)
+        t0 = time.monotonic_ns()
+        arr_ns = [t0 + (0 if a is None else int(a * 1e9)) for a in arrivals_s]
+        live, out = [], [None] * n
+        i = 0
+        while i < n or live:
+            now = time.monotonic_ns()
+            while i < n and arr_ns[i] <= now:
+                r = ompd.submit(ctx, pool[i % n_pool], want=SERVE_WANT)
+                if not r.admitted:
+                    break                   # budget full: retry after completions (latency keeps counting)
+                live.append((i, r))
+                i += 1
+            still = []
+            for k, r in live:
+                if r.poll():
+                    out[k] = (arr_ns[k], r.done_ns)
+                else:
+                    still.append((k, r))
+            live = still
+            time.sleep(0.0002)
+        return out
+
+    burst = drive([None] * n_cap)
+    t_first = min(a for a, _ in burst)
+    cap = n_cap / ((max(d for _, d in burst) - t_first) * 1e-9)
+    res = {"workload": "requests shaped like the 16,384-block x 2,048-variable procedure (pool of %d seeded "
+                       "CFGs), placement and labels returned to host memory" % n_pool,
+           "capacity_rps": round(cap, 2), "capacity_requests": n_cap, "warmup": n_warm, "measured": n_meas,
+           "loads": []}
+    log("serving capacity: %.1f requests/s over %d requests" % (cap, n_cap))
+    for f in loads:
+        lam = f * cap
+        arrivals = list(synth.poisson_arrivals(lam, n_warm + n_meas, seed=int(1000 * f)))
+        got = drive(arrivals)[n_warm:]
+        lat = np.array([(d - a) * 1e-6 for a, d in got])
+        row = {"load": f, "offered_rps": round(lam, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3)}
+        res["loads"].append(row)
+        log("serving load %.1f: %s" % (f, row))
+    return res
+
+
+def kernel_bytes(cfgs):
+    """Algorithmic bytes of each kernel per launch over the batch: every array
+    the kernel must read or write, once (bv = a block vector, ev = an edge
+    vector, both in the stored 64-bit word layout).  Iteration traffic (state
+    rows revisited by later sweeps) is not algorithmic."""
+    out = dict.fromkeys(("ompd_k_prep", "ompd_k_nu", "ompd_k_ave", "ompd_k_edge0", "ompd_k_mayp",
+                         "ompd_k_edge1", "ompd_k_later", "ompd_k_avf"), 0)
+    for c in cfgs:
+        wd = (c.n_vars + 63) // 64
+        nb, ne = c.n_blocks, c.n_edges
+        bv, ev = nb * wd * 8, ne * wd * 8
+        out["ompd_k_prep"] += 4 * (nb + 1) + 5 * ne + nb + 4 * (nb + 1) + 8 * ne + 64 * nb
+        out["ompd_k_nu"] += 2 * bv + 2 * bv                    # R, W in; next use H/D out
+        out["ompd_k_ave"] += 3 * bv + 2 * bv + 2 * nb          # NU H/D, W in; validity H/D, labels out
+        out["ompd_k_edge0"] += 4 * bv + 4 * ev                 # NU, eager validity in; EAG, valid-after-edge out
+        out["ompd_k_mayp"] += 2 * bv + 2 * ev + 2 * bv         # R, W, EAG in; pending H/D out
+        out["ompd_k_edge1"] += 4 * ev + 2 * bv + ev            # EAG, valid-after-edge, pending in; both-valid out
+        out["ompd_k_later"] += 2 * bv + 3 * ev + 2 * bv + 2 * ev   # R, W, EAG, both in; copies (entry, edge) out
+        out["ompd_k_avf"] += 3 * bv + 2 * ev + 2 * bv + c.n_vars    # copies, W in; final validity, map kinds out
+    return out
+
+
 def cpu_baseline(cfgs, seconds, threads):
     """The oracle as it stands, one CFG per thread, on the first CFGs of the
     batch until `seconds` of wall time have been used."""
@@ -109,6 +194,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=300, help="measured requests per offered load")
+    ap.add_argument("--serve-warmup", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -152,14 +240,17 @@ def main():
         if (st != 0).any():
             raise SystemExit("solve reported errors for %d CFGs" % int((st != 0).sum()))
     torch.cuda.synchronize()
+    rb.plan.profile(True)              # HIP events after every kernel, on the launch stream
     solve_ms = []
     total_ms = []
+    per_kernel = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         rb.run(stream)
-        a, b = rb.plan.last_ms()       # HIP events on the launch stream (synchronises)
+        a, b = rb.plan.last_ms()       # synchronises on the last event
         total_ms.append(a)
         solve_ms.append(b)
+        per_kernel.append(rb.plan.kernel_ms())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = rb.plan.status()
@@ -168,12 +259,18 @@ def main():
     ms_step = 1e3 * dt / args.steps
     log("batched: %.3f ms/step (device %.3f ms, solve kernel %.3f ms), %.3e facts/s" % (
         ms_step, np.mean(total_ms), np.mean(solve_ms), value))
-    alg = algorithmic_bytes(cfgs, want)
-    achieved = alg / (np.mean(solve_ms) * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "algorithmic_bytes_per_launch": alg, "kernel": "ompd_k_solve",
-                "kernel_ms": round(float(np.mean(solve_ms)), 4)}
+    kms = {k: float(np.mean([d[k] for d in per_kernel])) for k in per_kernel[0]}
+    log("kernel ms: " + ", ".join("%s %.3f" % (k, v) for k, v in kms.items()))
+    dom = max(kms, key=kms.get)
+    kb = kernel_bytes(cfgs)
+    achieved = kb[dom] / (kms[dom] * 1e-3) / 1e9
+    path_bytes = algorithmic_bytes(cfgs, want)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+                "kernel": dom, "kernel_ms": round(kms[dom], 4), "algorithmic_bytes_per_launch": kb[dom],
+                "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
+                "path_algorithmic_bytes": path_bytes,
+                "path_frac": round(path_bytes / (np.mean(total_ms) * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)}
     out = {"metric": METRIC, "value": value, "unit": "facts/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u64", "data": "synthetic (seeded structured CFGs)",
@@ -236,6 +333,12 @@ def main():
                          "plan": json.loads(sb.plan.describe())}
         log("single c2: %.3f ms, %.3e facts/s" % (np.median(lat), out["single"]["value"]))
         sb.close()
+
+    if not args.no_serve:
+        sctx = ompd.Context(0, budget_bytes=64 << 30)
+        out["serving"] = serving(sctx, n_pool=32, n_cap=256, n_warm=args.serve_warmup, n_meas=args.serve_requests,
+                                 loads=(0.5, 0.8, 1.0))
+        sctx.close()
 
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)

@@ -65,6 +65,8 @@ enum { OMPD_MAP_TO = 1, OMPD_MAP_FROM = 2, OMPD_MAP_ALLOC = 4 };          /* var
 /* ---- flags ----------------------------------------------------------- */
 #define OMPD_F_DEVICE_PTRS (1u << 0)      /* all pointers are device pointers               */
 #define OMPD_F_PLACEMENT_EAGER (1u << 1)  /* materialise every eager copy (no delay)         */
+#define OMPD_F_SUMMARY (1u << 2)          /* procedure-summary evaluation: the entry boundary may
+                                             leave variables valid in neither space            */
 #define OMPD_F_SWEEP_CAP(n) ((((uint32_t)(n)) & 0xFFFFu) << 16) /* cap sweeps per phase */
 
 /* ---- one procedure ----------------------------------------------------
@@ -183,6 +185,15 @@ int ompd_plan_autotune(ompd_plan* plan, void* stream, int32_t trials, float* bes
  * (0 = default, 8 KiB; clamped to [1 KiB, the device limit]) and solve
  * wavefronts per CU (0 = as many as fit). */
 int ompd_plan_configure(ompd_plan* plan, int64_t lds_bytes, int32_t wg_per_cu);
+/* Profiling: with enable != 0, ompd_plan_run launches the kernels directly
+ * (no graph) and records a HIP event after each on the caller's stream;
+ * ompd_plan_kernel_ms then gives the duration (ms) of each kernel of the
+ * last run, in launch order: ingest, next use, validity, edge step 1,
+ * pending copies, edge step 2, delayed placement, final validity
+ * (*n_kernels = 8; at most `capacity` are written).  OMPD_E_INVAL if
+ * profiling is off. */
+int ompd_plan_profile(ompd_plan* plan, int32_t enable);
+int ompd_plan_kernel_ms(ompd_plan* plan, float* ms, int32_t capacity, int32_t* n_kernels);
 /* Describe the plan's current configuration as a NUL-terminated string. */
 int ompd_plan_describe(ompd_plan* plan, char* buf, int32_t len);
 /* Duration (ms) of the last ompd_plan_run measured with HIP events on its
@@ -208,6 +219,72 @@ int ompd_wait(ompd_ctx* ctx, ompd_ticket t, int64_t timeout_ns, int* done);
 /* Serving counters: admitted, completed, in flight, bytes in use. */
 int ompd_serving_stats(ompd_ctx* ctx, int64_t* admitted, int64_t* completed, int64_t* in_flight,
                        int64_t* bytes_in_use);
+
+/* ---- whole programs (section "Interprocedural Analysis") ---------------
+ * The side effects of a call on the globals are summarised per procedure
+ * and applied at its call sites, repeated over the call graph until nothing
+ * changes; external functions are treated pessimistically.
+ * procs[i] (host pointers) are the procedures; their call_summary,
+ * summaries and n_summaries fields must be NULL / 0 (the library fills
+ * them), and their boundary fields are used for roots only.  Variables
+ * [0, n_globals) are the globals of every procedure (n_vars >= n_globals;
+ * the rest are its locals).  Call site j is block call_block[j] of
+ * procedure call_proc[j] (a HOST block, at most one call per block) and
+ * calls procedure callee[j], or an external function if callee[j] = -1: it
+ * needs every global current on the host, may read and write every global
+ * there, and leaves the device copies stale.  A context is a procedure with
+ * the last two call sites of a call string that reaches it from a root;
+ * roots are contexts with an empty string.                                 */
+typedef struct {
+    int32_t n_procs, n_globals;
+    const ompd_cfg* procs;            /* [n_procs] */
+    int32_t n_calls;
+    const int32_t* call_proc;         /* [n_calls] */
+    const int32_t* call_block;        /* [n_calls] */
+    const int32_t* callee;            /* [n_calls] */
+    int32_t n_roots;
+    const int32_t* roots;             /* [n_roots] */
+} ompd_program;
+
+/* Enumerate the contexts (breadth first from the roots, call sites in
+ * order): ctx_proc[k], ctx_site0[k] = second-to-last call site (-1 if none),
+ * ctx_site1[k] = last call site (-1 for a root).  *n_contexts receives the
+ * count; the arrays (NULL allowed) receive at most `capacity` entries.
+ * OMPD_E_INVAL for a malformed program. */
+int ompd_program_contexts(ompd_ctx* ctx, const ompd_program* prog, int32_t* n_contexts, int32_t* ctx_proc,
+                          int32_t* ctx_site0, int32_t* ctx_site1, int32_t capacity);
+
+/* Outputs of ompd_analyze_program (host pointers, NULL = not requested):
+ *   per_context [n_contexts] results of each context's solve, in the order
+ *               of ompd_program_contexts, each sized by its procedure
+ *   boundaries  per context, in that order, 4*wd words of its procedure:
+ *               entry valid host, entry valid device, exit live host, exit
+ *               live device (the meet over the contexts' callers)
+ *   summaries   [n_procs*16*gw] (gw = ceil(n_globals/64)) summary rows of
+ *               each procedure over the globals (row order as above)
+ *   demands     [n_calls*gw] globals each call site must make current on
+ *               the host (read at the call block) so that the callee's
+ *               context has every global valid somewhere
+ *   rounds      outer rounds until demands and exit-validity caps settled
+ *   solves      CFG solves run on the device                              */
+typedef struct {
+    ompd_result* per_context;
+    uint64_t* boundaries;
+    uint64_t* summaries;
+    uint64_t* demands;
+    int32_t rounds;
+    int32_t reserved;
+    int64_t solves;
+} ompd_program_result;
+
+/* Interprocedural solve on the device: summaries bottom-up over the
+ * strongly connected components of the call graph (recursion iterates
+ * within a component), then contexts top-down in rounds, then host-read
+ * demands and exit-validity caps fed back until they settle.  Every CFG
+ * solve is a batched device solve of the procedures concerned.  flags:
+ * OMPD_F_SWEEP_CAP only.  OMPD_E_NOCONVERGE if the outer rounds do not
+ * settle within 64. */
+int ompd_analyze_program(ompd_ctx* ctx, const ompd_program* prog, ompd_program_result* out, uint32_t flags);
 
 #ifdef __cplusplus
 }

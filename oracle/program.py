@@ -20,12 +20,14 @@ problems of ``oracle.c``:
   context gives, at each call site, the validity after the caller's own
   accesses in the final placement (entry validity of the callee) and the
   caller's next use after the call (exit liveness of the callee).  Several
-  callers that reach one context meet: validity by AND, liveness by OR.  A
-  variable that the meet leaves valid in neither space is assumed valid on
-  the host in that context, and every call site feeding the context must then
-  make it valid on the host before the call (a host read at the call block);
-  such demands feed back into the summaries, and the whole computation
-  repeats until no demand changes.
+  callers that reach one context meet: validity by AND, liveness by OR,
+  over everything contributed so far, in rounds that re-solve every context
+  whose boundary changed.  A variable that the meet leaves valid in neither
+  space is assumed valid on the host in that context, and the call site that
+  leads to the context (the last of its call string) must then make it valid
+  on the host before the call (a host read at the call block); such demands
+  feed back into the summaries, and the whole computation repeats until no
+  demand changes.
 * The validity tables describe the callee under eager copies; a context's
   final placement delays copies and can leave a copy stale at the callee's
   exit where the eager one would be current.  So when a context is solved,
@@ -43,7 +45,6 @@ device copy stale.
 """
 from __future__ import annotations
 
-from collections import defaultdict, deque
 from typing import Dict, List, Tuple
 
 import numpy as np
@@ -292,81 +293,89 @@ class ProgramOracle:
     # -- top-down -------------------------------------------------------------------
     def contexts(self, S):
         """Context boundaries {(proc, sigma): (ev_h, ev_d, lx_h, lx_d)}, the
-        host-read demands they require and, per call site, the validity at
-        EXIT (final placement) of the contexts it leads to."""
+        host-read demands they require and, per context, its validity at EXIT
+        under the final placement (the caps of the next round).
+
+        Rounds: every context whose boundary is new or changed is solved;
+        each of its calls contributes the validity after the call block's own
+        accesses and the next use after the call to the callee context (the
+        last two call sites); a context's boundary is the meet of everything
+        contributed to it so far (validity AND, liveness OR), so boundaries
+        only move one way and the rounds end.  Bits left valid in neither
+        space are then assumed valid on the host and demanded, as a host read,
+        at the call site that leads to the context (the last site of its call
+        string)."""
         G = self.G
         gw = (G + 63) // 64
         ctx: Dict[Tuple[int, tuple], List[np.ndarray]] = {}
         last: Dict[Tuple[int, tuple], dict] = {}
-        feeders: Dict[Tuple[int, tuple], set] = defaultdict(set)
-        work = deque()
         for r in self.p.roots:
-            b = list(self.p.procs[r].boundary())
-            ctx[(r, ())] = b
-            work.append((r, ()))
+            ctx[(r, ())] = list(self.p.procs[r].boundary())
+        dirty = sorted(ctx)
         new_demand: Dict[int, np.ndarray] = {}
-        while work:
-            key = work.popleft()
-            P, sigma = key
-            cfg, call, sums, res = self._solve(P, S, ctx[key], sigma=sigma)
-            last[key] = res
-            wd = cfg.wd
-            for j in self.sites[P]:
-                q = int(self.p.callee[j])
-                if q < 0:
-                    continue
-                c = int(self.p.call_block[j])
-                # validity after the call block's own accesses (final placement)
-                w = cfg.W[c]
-                a1_h = res["avf_h"][c] | w
-                a1_d = res["avf_d"][c] & ~w
-                l_h = np.zeros(wd, np.uint64)
-                l_d = np.zeros(wd, np.uint64)
-                for e in range(int(cfg.succ_ptr[c]), int(cfg.succ_ptr[c + 1])):
-                    t = int(cfg.succ_idx[e])
-                    l_h |= res["nu_h"][t]
-                    l_d |= res["nu_d"][t]
-                qc = self.p.procs[q]
-                qwd = qc.wd
-                gw = (G + 63) // 64
-                gq = _gmask(G, qwd)
-                lq = _vmask(qc.n_vars, qwd) & ~gq
-                ev_h = np.zeros(qwd, np.uint64)
-                ev_d = np.zeros(qwd, np.uint64)
-                lx_h = np.zeros(qwd, np.uint64)
-                lx_d = np.zeros(qwd, np.uint64)
-                ev_h[:gw] = a1_h[:gw]
-                ev_d[:gw] = a1_d[:gw]
-                lx_h[:gw] = l_h[:gw]
-                lx_d[:gw] = l_d[:gw]
-                ev_h = (ev_h & gq) | lq
-                ev_d &= gq
-                lx_h &= gq
-                lx_d &= gq
-                nkey = (q, (sigma + (j,))[-2:])
-                feeders[nkey].add(j)
-                if nkey not in ctx:
-                    m = [ev_h, ev_d, lx_h, lx_d]
-                else:
+        while dirty:
+            acc: Dict[Tuple[int, tuple], List[np.ndarray]] = {}
+            for key in dirty:
+                P, sigma = key
+                cfg, call, sums, res = self._solve(P, S, ctx[key], sigma=sigma)
+                last[key] = res
+                wd = cfg.wd
+                for j in self.sites[P]:
+                    q = int(self.p.callee[j])
+                    if q < 0:
+                        continue
+                    c = int(self.p.call_block[j])
+                    # validity after the call block's own accesses (final placement)
+                    w = cfg.W[c]
+                    a1_h = res["avf_h"][c] | w
+                    a1_d = res["avf_d"][c] & ~w
+                    l_h = np.zeros(wd, np.uint64)
+                    l_d = np.zeros(wd, np.uint64)
+                    for e in range(int(cfg.succ_ptr[c]), int(cfg.succ_ptr[c + 1])):
+                        t = int(cfg.succ_idx[e])
+                        l_h |= res["nu_h"][t]
+                        l_d |= res["nu_d"][t]
+                    qc = self.p.procs[q]
+                    qwd = qc.wd
+                    gq = _gmask(G, qwd)
+                    lq = _vmask(qc.n_vars, qwd) & ~gq
+                    m = [np.zeros(qwd, np.uint64) for _ in range(4)]
+                    m[0][:gw] = a1_h[:gw]
+                    m[1][:gw] = a1_d[:gw]
+                    m[2][:gw] = l_h[:gw]
+                    m[3][:gw] = l_d[:gw]
+                    m = [(m[0] & gq) | lq, m[1] & gq, m[2] & gq, m[3] & gq]
+                    nkey = (q, (sigma + (j,))[-2:])
+                    if nkey in acc:
+                        a = acc[nkey]
+                        acc[nkey] = [a[0] & m[0], a[1] & m[1], a[2] | m[2], a[3] | m[3]]
+                    else:
+                        acc[nkey] = m
+            dirty = []
+            for nkey in sorted(acc):
+                a = acc[nkey]
+                if nkey in ctx:
                     old = ctx[nkey]
-                    m = [old[0] & ev_h, old[1] & ev_d, old[2] | lx_h, old[3] | lx_d]
-                # variables valid in neither space (must-validity is empty after
-                # a join of host-fresh and device-fresh paths, or after a meet of
-                # callers): assume the host copy and make every call site that
-                # feeds this context provide it
+                    m = [old[0] & a[0], old[1] & a[1], old[2] | a[2], old[3] | a[3]]
+                else:
+                    m = a
+                q = nkey[0]
+                gq = _gmask(G, self.p.procs[q].wd)
+                # variables valid in neither space (must-validity is empty after a
+                # join of host-fresh and device-fresh paths, or after a meet of
+                # callers): assume the host copy and make the call site that leads
+                # here provide it
                 nowhere = gq & ~(m[0] | m[1])
                 if nowhere.any():
                     m[0] = m[0] | nowhere
-                    for jj in feeders[nkey]:
-                        P2 = int(self.p.call_proc[jj])
-                        pwd = self.p.procs[P2].wd
-                        d = new_demand.get(jj, np.zeros(pwd, np.uint64))
-                        d[:gw] |= nowhere[:gw]
-                        new_demand[jj] = d
-                if nkey not in ctx or any(not np.array_equal(a, b) for a, b in zip(ctx[nkey], m)):
+                    jj = nkey[1][-1]
+                    P2 = int(self.p.call_proc[jj])
+                    d = new_demand.get(jj, np.zeros(self.p.procs[P2].wd, np.uint64))
+                    d[:gw] |= nowhere[:gw]
+                    new_demand[jj] = d
+                if nkey not in ctx or any(not np.array_equal(x, y) for x, y in zip(ctx[nkey], m)):
                     ctx[nkey] = m
-                    if nkey not in work:
-                        work.append(nkey)
+                    dirty.append(nkey)
         caps: Dict[tuple, Tuple[np.ndarray, np.ndarray]] = {}
         for key, res in last.items():
             if key[1]:

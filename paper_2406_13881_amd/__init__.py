@@ -25,7 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libompd.so")
-_SOURCES = ["csrc/ompd_kernels.hip", "csrc/ompd_runtime.hip", "csrc/ompd_serving.hip"]
+_SOURCES = ["csrc/ompd_kernels.hip", "csrc/ompd_runtime.hip", "csrc/ompd_serving.hip", "csrc/ompd_program.hip"]
 
 OMPD_OK = 0
 OMPD_E_INVAL = -1
@@ -89,6 +89,16 @@ class _Res(ctypes.Structure):
                 ("after_dev", _vp), ("before_dev", _vp), ("sweeps", _i32 * 6)]
 
 
+class _Prog(ctypes.Structure):
+    _fields_ = [("n_procs", _i32), ("n_globals", _i32), ("procs", _vp), ("n_calls", _i32),
+                ("call_proc", _vp), ("call_block", _vp), ("callee", _vp), ("n_roots", _i32), ("roots", _vp)]
+
+
+class _ProgRes(ctypes.Structure):
+    _fields_ = [("per_context", _vp), ("boundaries", _vp), ("summaries", _vp), ("demands", _vp),
+                ("rounds", _i32), ("reserved", _i32), ("solves", ctypes.c_int64)]
+
+
 _RES_FIELD = {"nu_h": "nu_host", "nu_d": "nu_dev", "ave_h": "ave_host", "ave_d": "ave_dev",
               "avf_h": "avf_host", "avf_d": "avf_dev", "ins_entry_h": "ins_entry_to_host",
               "ins_entry_d": "ins_entry_to_dev", "ins_edge_h": "ins_edge_to_host",
@@ -122,6 +132,8 @@ def lib():
             L.ompd_plan_autotune.argtypes = [_vp, _vp, _i32, P(ctypes.c_float)]
             L.ompd_plan_describe.argtypes = [_vp, ctypes.c_char_p, _i32]
             L.ompd_plan_configure.argtypes = [_vp, ctypes.c_int64, _i32]
+            L.ompd_plan_profile.argtypes = [_vp, _i32]
+            L.ompd_plan_kernel_ms.argtypes = [_vp, P(ctypes.c_float), _i32, P(_i32)]
             L.ompd_plan_last_ms.argtypes = [_vp, P(ctypes.c_float), P(ctypes.c_float)]
             L.ompd_plan_destroy.argtypes = [_vp]
             L.ompd_plan_destroy.restype = None
@@ -131,6 +143,8 @@ def lib():
             L.ompd_wait.argtypes = [_vp, ctypes.c_uint64, ctypes.c_int64, P(ctypes.c_int)]
             L.ompd_serving_stats.argtypes = [_vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64),
                                              P(ctypes.c_int64)]
+            L.ompd_program_contexts.argtypes = [_vp, P(_Prog), P(_i32), _vp, _vp, _vp, _i32]
+            L.ompd_analyze_program.argtypes = [_vp, P(_Prog), P(_ProgRes), ctypes.c_uint32]
             _handle = L
         return _handle
 
@@ -284,6 +298,78 @@ class Context:
         return outs
 
 
+def _prog_struct(prog, keep: list) -> _Prog:
+    """Marshal a program (procs, n_globals, call_proc, call_block, callee, roots)."""
+    n = len(prog.procs)
+    C = (_Cfg * n)()
+    for i, c in enumerate(prog.procs):
+        C[i] = _cfg_struct(c, keep)
+    keep.append(C)
+    arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.int32)) for a in (prog.call_proc, prog.call_block,
+                                                                         prog.callee, prog.roots)]
+    keep.extend(arrs)
+    P = _Prog()
+    P.n_procs, P.n_globals = n, int(prog.n_globals)
+    P.procs = _vp(ctypes.addressof(C))
+    P.n_calls = int(arrs[0].size)
+    P.call_proc, P.call_block, P.callee = (_np_ptr(a) if a.size else None for a in arrs[:3])
+    P.n_roots, P.roots = int(arrs[3].size), _np_ptr(arrs[3])
+    return P
+
+
+def _sigma(s0: int, s1: int) -> tuple:
+    return () if s1 < 0 else ((s1,) if s0 < 0 else (s0, s1))
+
+
+def _program_contexts(self, prog) -> List[tuple]:
+    """Contexts of a program as (procedure, call string of at most two sites), in library order."""
+    keep: list = []
+    P = _prog_struct(prog, keep)
+    n = _i32(0)
+    _check(lib().ompd_program_contexts(self.h, ctypes.byref(P), ctypes.byref(n), None, None, None, 0))
+    cp = np.zeros(max(n.value, 1), np.int32)
+    c0 = np.zeros_like(cp)
+    c1 = np.zeros_like(cp)
+    _check(lib().ompd_program_contexts(self.h, ctypes.byref(P), ctypes.byref(n), _np_ptr(cp), _np_ptr(c0),
+                                       _np_ptr(c1), n.value))
+    return [(int(cp[k]), _sigma(int(c0[k]), int(c1[k]))) for k in range(n.value)]
+
+
+def _analyze_program(self, prog, flags: int = 0, want: Sequence[str] = OUTPUTS) -> Dict:
+    """ompd_analyze_program: per-context results, boundaries, summaries and demands."""
+    keys = self.program_contexts(prog)
+    keep: list = []
+    P = _prog_struct(prog, keep)
+    outs = [_alloc_outputs(prog.procs[p], want) for (p, _) in keys]
+    R = (_Res * max(len(keys), 1))()
+    for k, o in enumerate(outs):
+        R[k] = _res_struct(o)
+    wds = [(prog.procs[p].n_vars + 63) // 64 for (p, _) in keys]
+    bnd = np.zeros(max(4 * sum(wds), 1), np.uint64)
+    gw = (int(prog.n_globals) + 63) // 64
+    summ = np.zeros((len(prog.procs), 16, gw), np.uint64)
+    nc = int(np.asarray(prog.call_proc).size)
+    dem = np.zeros((nc, gw), np.uint64)
+    out = _ProgRes()
+    out.per_context = _vp(ctypes.addressof(R))
+    out.boundaries = _np_ptr(bnd)
+    out.summaries = _np_ptr(summ) if summ.size else None
+    out.demands = _np_ptr(dem) if dem.size else None
+    _check(lib().ompd_analyze_program(self.h, ctypes.byref(P), ctypes.byref(out), int(flags)))
+    bounds, off = [], 0
+    for wdk in wds:
+        bounds.append([bnd[off + i * wdk: off + (i + 1) * wdk] for i in range(4)])
+        off += 4 * wdk
+    for k in range(len(keys)):
+        outs[k]["sweeps"] = np.array(list(R[k].sweeps), dtype=np.int32)
+    return {"contexts": keys, "results": outs, "boundaries": bounds, "summaries": summ, "demands": dem,
+            "rounds": out.rounds, "solves": out.solves}
+
+
+Context.program_contexts = _program_contexts
+Context.analyze_program = _analyze_program
+
+
 class Request:
     """A submitted analysis request (ompd_submit): the host buffers its
     results land in stay referenced here until the request is collected."""
@@ -419,6 +505,20 @@ class Plan:
     def configure(self, lds_bytes: int = 0, wg_per_cu: int = 0):
         """LDS ring bytes per solve wavefront (0 = default) and wavefronts per CU (0 = as many as fit)."""
         _check(lib().ompd_plan_configure(self.h, int(lds_bytes), int(wg_per_cu)))
+
+    KERNELS = ("ompd_k_prep", "ompd_k_nu", "ompd_k_ave", "ompd_k_edge0", "ompd_k_mayp", "ompd_k_edge1",
+               "ompd_k_later", "ompd_k_avf")
+
+    def profile(self, enable: bool = True):
+        """Time every kernel of the following runs with HIP events on their stream."""
+        _check(lib().ompd_plan_profile(self.h, 1 if enable else 0))
+
+    def kernel_ms(self) -> Dict[str, float]:
+        """Per-kernel durations (ms) of the last profiled run."""
+        buf = (ctypes.c_float * 8)()
+        n = _i32(0)
+        _check(lib().ompd_plan_kernel_ms(self.h, buf, 8, ctypes.byref(n)))
+        return {k: float(buf[i]) for i, k in enumerate(self.KERNELS[:n.value])}
 
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(1024)

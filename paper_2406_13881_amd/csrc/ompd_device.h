@@ -26,7 +26,7 @@ enum : int32_t {
 // scratch owned by the plan.
 struct DevCfg {
     int32_t nb, ne, nv, entry, exit, wd;   // wd = 64-bit words per row
-    int32_t n_sums, placement, sweep_cap, pad;
+    int32_t n_sums, placement, sweep_cap, pad;   // placement: bit 0 eager, bit 1 summary evaluation
     const int32_t* succ_ptr;
     const int32_t* succ_idx;
     const uint8_t* kind;
@@ -50,6 +50,8 @@ struct DevCfg {
     uint64_t* aveout_h; uint64_t* aveout_d;   // eager validity out; later validity after placement
     uint64_t* mayp_h;   uint64_t* mayp_d;     // pending copies
     uint64_t* later_h;  uint64_t* later_d;    // delayed copies
+    uint64_t* eag_h;    uint64_t* eag_d;      // per edge: eager copies
+    uint64_t* both;     // per edge: valid in both spaces under the final placement
     uint64_t* flg;      // per tile: [4][nb] words of the flag lane
     int32_t* pred_ptr;  int32_t* pred_idx; int32_t* pred_eid;
     int32_t* tmp;
@@ -70,6 +72,13 @@ struct Tile {
     int32_t s0;      // first word
     int32_t nw;      // words (0 only when the CFG has no variables)
     int32_t fslot;   // index of the tile within its CFG (flag-lane storage)
+};
+
+// Work item of the edge-parallel steps: a tile and the first block of a
+// 64-block chunk of it.
+struct EdgeItem {
+    int32_t tile;
+    int32_t b0;
 };
 
 // Tiles of a CFG with wd words: ceil(wd / TILE_WORDS) (at least one), the

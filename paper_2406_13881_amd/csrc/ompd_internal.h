@@ -44,6 +44,9 @@ struct ompd_plan {
     std::vector<ompd::Tile> h_tiles;
     ompd::Tile* d_tiles = nullptr;
     int n_tiles = 0;
+    ompd::EdgeItem* d_items = nullptr;
+    int n_items = 0;
+    int grid_edge = 1;
     int32_t* d_counter = nullptr;
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
@@ -54,22 +57,30 @@ struct ompd_plan {
     hipGraphExec_t gx_prep = nullptr, gx_solve = nullptr;
     hipStream_t last_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+    bool profile = false;          // launch directly and time every kernel
+    hipEvent_t evk[7] = {};        // after each solve kernel (profile runs)
 };
 
 int ompd_fail(int code, const std::string& msg);
 
 struct ScratchOff {
-    size_t aveout, mayp, later, flg, nu, ave, ie, ig, avf, bnd, pp, pi, pe, tmp, recf, recb, info;
+    size_t aveout, mayp, later, flg, eag, both, nu, ave, ie, ig, avf, bnd, pp, pi, pe, tmp, recf, recb, info;
 };
 size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o);
 void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const ScratchOff& o, uint32_t flags,
                       ompd::DevCfg& d, uint64_t* bnd_host);
-struct PlanConfig;
-int ompd_make_plan_tiles(ompd_ctx* ctx, const std::vector<ompd::DevCfg>& cfgs, const PlanConfig& pc,
-                         std::vector<ompd::Tile>& tiles, size_t& lds_solve, size_t& lds_prep, int& grid_solve);
+// Launch shape of a set of CFGs: tiles (longest first), edge-step items and grids.
+struct Shape {
+    std::vector<ompd::Tile> tiles;
+    std::vector<ompd::EdgeItem> items;
+    size_t lds_solve = 0, lds_prep = 0;
+    int grid_solve = 1, grid_edge = 1;
+};
+int ompd_make_shape(ompd_ctx* ctx, const std::vector<ompd::DevCfg>& cfgs, const PlanConfig& pc, Shape& sh);
 int ompd_launch_prep(const ompd::DevCfg* d_cfgs, int n, int32_t* d_counter, size_t lds, hipStream_t s);
-int ompd_launch_solve(const ompd::DevCfg* d_cfgs, const ompd::Tile* d_tiles, int n_tiles, int32_t* d_counter,
-                      int grid, size_t lds, hipStream_t s);
+int ompd_launch_solve(const ompd::DevCfg* d_cfgs, const ompd::Tile* d_tiles, int n_tiles, const ompd::EdgeItem* d_items,
+                      int n_items, int32_t* d_counter, int grid, int grid_edge, size_t lds, hipStream_t s,
+                      hipEvent_t* after = nullptr);
 int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n, uint32_t flags,
                     const PlanConfig& pc, ompd_plan** out);
 int ompd_plan_retile(ompd_plan* p, const PlanConfig& pc);

@@ -1,0 +1,1047 @@
+// Whole-program (interprocedural) solve of libompd: per-procedure summaries
+// bottom-up over the call graph's strongly connected components, call-string
+// contexts top-down, and the host-read demands and exit-validity caps that
+// feed back until they settle.  Every CFG solve is a batched device solve
+// (ompd_plan_*); the small kernels below build the call tables, gather the
+// summary rows, form the may-sets, and meet the callers' contributions into
+// the callee contexts.  The host only orders the work (components, levels,
+// rounds) and tests for convergence.
+//
+// Summaries (per procedure P, over the globals; section "Interprocedural
+// Analysis": the side effects of a call on global variables, per space):
+//   NU0_s, NU1_s : next use in s at P's entry when the globals are dead /
+//                  live in s after P returns,
+//   T_s[e][l]    : validity in s at P's exit (eager copies) when the globals
+//                  are valid in both / neither space at entry (e) and live /
+//                  dead after the return (l),
+//   MAYR_s, MAYW_s: may be read / written in s by P or anything it calls.
+// Each problem is gen/kill per bit, so the four boundary evaluations define
+// the transfer exactly.  Inside a recursive component the next-use rows
+// iterate from 0, then the validity tables from all ones, then the may-sets
+// from 0.  External callees need every global on the host, may read and
+// write all of them there and leave the device copies stale.
+//
+// Contexts (procedure, last two call sites) are solved in rounds: every
+// context whose boundary changed is solved; each call contributes, to the
+// callee context it leads to, the validity after the call block's own
+// accesses under the final placement and the next use after the call; a
+// context's boundary is the meet of everything contributed in the outer
+// round so far (validity AND, liveness OR).  Globals then valid in neither
+// space are assumed valid on the host, and the call site leading to the
+// context must make them so (a host read at the call block).  Each call is
+// capped by the validity at EXIT, under the final placement, of the callee
+// context it leads to (from the previous outer round).  Outer rounds repeat
+// until the demands and caps no longer change.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ompd.h"
+#include "ompd_device.h"
+#include "ompd_internal.h"
+
+using namespace ompd;
+
+#define GAS __attribute__((address_space(1)))
+
+namespace {
+
+__device__ __forceinline__ uint64_t word_mask(int nbits, int w)
+{
+    const int lo = 64 * w;
+    if (nbits >= lo + 64) return ~0ull;
+    if (nbits <= lo) return 0ull;
+    return (1ull << (nbits - lo)) - 1ull;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+// Call table of one call site in the caller's variable layout: the callee's
+// summary rows on the globals (an external callee's fixed rows), the cap of
+// the callee context on the validity tables, identity for the caller's
+// locals (NU1 = 1, T[e][l] = e).
+struct CallTabItem {
+    uint64_t* dst;        // [16][wd]
+    const uint64_t* src;  // [16][gw] callee rows, or NULL for an external callee
+    const uint64_t* cap;  // [2][gw] host / device caps, or NULL
+    int32_t wd, gw, G, nv;
+};
+
+__global__ void __launch_bounds__(256) k_calltab(const CallTabItem* __restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const CallTabItem I = items[it];
+        for (int x = threadIdx.x; x < SUM_ROWS * I.wd; x += blockDim.x) {
+            const int r = x / I.wd, w = x % I.wd;
+            const uint64_t gm = word_mask(I.G, w), lm = word_mask(I.nv, w) & ~gm;
+            uint64_t v = 0;
+            if (w < I.gw) {
+                if (I.src) v = I.src[r * I.gw + w];
+                else {
+                    const bool one = r == SUM_MAYR_H || r == SUM_MAYW_H || r == SUM_NU0_H || r == SUM_NU1_H ||
+                                     r == SUM_NU1_D || (r >= SUM_TH && r < SUM_TH + 4);
+                    v = one ? ~0ull : 0ull;
+                }
+                v &= gm;
+                if (I.cap) {
+                    if (r >= SUM_TH && r < SUM_TH + 4) v &= I.cap[w];
+                    if (r >= SUM_TD && r < SUM_TD + 4) v &= I.cap[I.gw + w];
+                }
+            }
+            if (r == SUM_NU1_H || r == SUM_NU1_D || r == SUM_TH + 2 || r == SUM_TH + 3 || r == SUM_TD + 2 ||
+                r == SUM_TD + 3)
+                v |= lm;
+            I.dst[r * I.wd + w] = v;
+        }
+    }
+}
+
+// Summary rows of a procedure from one boundary evaluation (e, l): the next
+// use at its entry (e = 0 only) and the validity at its exit.
+struct SumItem {
+    uint64_t* S;          // [16][gw] rows of the procedure
+    const uint64_t *nu_h, *nu_d, *ave_h, *ave_d;
+    int32_t entry, exit, wd, gw, G, eps, ell, rows;   // rows: bit 0 next use, bit 1 validity tables
+    int32_t* changed;
+};
+
+__global__ void __launch_bounds__(64) k_sumgather(const SumItem* __restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const SumItem I = items[it];
+        for (int w = threadIdx.x; w < I.gw; w += blockDim.x) {
+            const uint64_t gm = word_mask(I.G, w);
+            bool ch = false;
+            auto put = [&](int r, uint64_t v) {
+                v &= gm;
+                if (I.S[r * I.gw + w] != v) { I.S[r * I.gw + w] = v; ch = true; }
+            };
+            if ((I.rows & 1) && I.eps == 0) {
+                const int base = I.ell ? SUM_NU1_H : SUM_NU0_H;
+                put(base, I.nu_h[(size_t)I.entry * I.wd + w]);
+                put(base + 1, I.nu_d[(size_t)I.entry * I.wd + w]);
+            }
+            if (I.rows & 2) {
+                put(SUM_TH + 2 * I.eps + I.ell, I.ave_h[(size_t)I.exit * I.wd + w]);
+                put(SUM_TD + 2 * I.eps + I.ell, I.ave_d[(size_t)I.exit * I.wd + w]);
+            }
+            if (ch) atomicOr(I.changed, 1);
+        }
+    }
+}
+
+// May-read / may-write rows of a procedure: its own host / device blocks
+// (reads including the demanded ones) and every callee.
+struct MayItem {
+    uint64_t* S;
+    const uint64_t *R, *W;
+    const uint8_t* space;
+    const int32_t* callees;   // [n_sites], -1 = external
+    const uint64_t* Sall;     // rows of every procedure
+    int32_t nb, wd, gw, G, n_sites;
+    int32_t* changed;
+};
+
+__global__ void __launch_bounds__(64) k_may(const MayItem* __restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const MayItem I = items[it];
+        for (int w = threadIdx.x; w < I.gw; w += blockDim.x) {
+            const uint64_t gm = word_mask(I.G, w);
+            uint64_t m[4] = {0, 0, 0, 0};
+            for (int b = 0; b < I.nb; ++b) {
+                const int d = I.space[b] ? 1 : 0;
+                m[d] |= I.R[(size_t)b * I.wd + w];
+                m[2 + d] |= I.W[(size_t)b * I.wd + w];
+            }
+            for (int k = 0; k < I.n_sites; ++k) {
+                const int q = I.callees[k];
+                if (q < 0) { m[SUM_MAYR_H] |= ~0ull; m[SUM_MAYW_H] |= ~0ull; }
+                else
+                    for (int r = 0; r < 4; ++r) m[r] |= I.Sall[((size_t)q * SUM_ROWS + r) * I.gw + w];
+            }
+            bool ch = false;
+            for (int r = 0; r < 4; ++r) {
+                const uint64_t v = m[r] & gm;
+                if (I.S[r * I.gw + w] != v) { I.S[r * I.gw + w] = v; ch = true; }
+            }
+            if (ch) atomicOr(I.changed, 1);
+        }
+    }
+}
+
+// Host reads demanded at call blocks: Rd = R with the demand rows ORed in.
+struct DemandItem {
+    uint64_t* Rd;
+    const uint64_t* R;
+    const uint64_t* demand;   // [gw]
+    int32_t block, wd, gw;
+};
+
+__global__ void __launch_bounds__(64) k_demand(const DemandItem* __restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const DemandItem I = items[it];
+        for (int w = threadIdx.x; w < I.wd; w += blockDim.x) {
+            uint64_t v = I.R[(size_t)I.block * I.wd + w];
+            if (w < I.gw) v |= I.demand[w];
+            I.Rd[(size_t)I.block * I.wd + w] = v;
+        }
+    }
+}
+
+// Contribution of one solved call to the callee context it leads to:
+// validity after the call block's own accesses (final placement) and next
+// use after the call, on the globals; the callee's locals are valid on the
+// host at its entry and dead at its exit.
+struct ContribItem {
+    const uint64_t *avf_h, *avf_d, *nu_h, *nu_d, *W;
+    const int32_t *succ_ptr, *succ_idx;
+    uint64_t* acc;            // [4][gw] of the callee context
+    int32_t c, wd, gw, G, cnv;
+};
+
+__global__ void __launch_bounds__(64) k_contrib(const ContribItem* __restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const ContribItem I = items[it];
+        for (int w = threadIdx.x; w < I.gw; w += blockDim.x) {
+            const uint64_t gm = word_mask(I.G, w), lq = word_mask(I.cnv, w) & ~gm;
+            const size_t cw = (size_t)I.c * I.wd + w;
+            const uint64_t wr = I.W[cw];
+            const uint64_t a1h = I.avf_h[cw] | wr, a1d = I.avf_d[cw] & ~wr;
+            uint64_t lh = 0, ld = 0;
+            for (int e = I.succ_ptr[I.c]; e < I.succ_ptr[I.c + 1]; ++e) {
+                const int t = I.succ_idx[e];
+                lh |= I.nu_h[(size_t)t * I.wd + w];
+                ld |= I.nu_d[(size_t)t * I.wd + w];
+            }
+            atomicAnd((unsigned long long*)&I.acc[w], (unsigned long long)((a1h & gm) | lq));
+            atomicAnd((unsigned long long*)&I.acc[I.gw + w], (unsigned long long)(a1d & gm));
+            atomicOr((unsigned long long*)&I.acc[2 * I.gw + w], (unsigned long long)(lh & gm));
+            atomicOr((unsigned long long*)&I.acc[3 * I.gw + w], (unsigned long long)(ld & gm));
+        }
+    }
+}
+
+// Meet of a context's round contributions into its boundary; globals valid
+// in neither space are taken as valid on the host and demanded at the call
+// site leading to the context.
+struct UpdItem {
+    uint64_t* bnd;            // [4][wd] of the context
+    const uint64_t* acc;      // [4][gw]
+    uint64_t* demand;         // [gw] of the site leading here
+    int32_t* changed;         // per context
+    int32_t wd, gw, G, nv, present;
+};
+
+__global__ void __launch_bounds__(64) k_update(const UpdItem* __restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const UpdItem I = items[it];
+        bool ch = false;
+        for (int w = threadIdx.x; w < I.wd; w += blockDim.x) {
+            const uint64_t gm = word_mask(I.G, w), lm = word_mask(I.nv, w) & ~gm;
+            uint64_t a[4];
+            if (w < I.gw) for (int k = 0; k < 4; ++k) a[k] = I.acc[k * I.gw + w];
+            else { a[0] = lm; a[1] = 0; a[2] = 0; a[3] = 0; }
+            uint64_t m[4];
+            if (I.present) {
+                m[0] = I.bnd[w] & a[0];
+                m[1] = I.bnd[I.wd + w] & a[1];
+                m[2] = I.bnd[2 * I.wd + w] | a[2];
+                m[3] = I.bnd[3 * I.wd + w] | a[3];
+            } else
+                for (int k = 0; k < 4; ++k) m[k] = a[k];
+            const uint64_t nowhere = gm & ~(m[0] | m[1]);
+            if (nowhere) {
+                m[0] |= nowhere;
+                atomicOr((unsigned long long*)&I.demand[w], (unsigned long long)nowhere);
+            }
+            for (int k = 0; k < 4; ++k) {
+                if (!I.present || I.bnd[k * I.wd + w] != m[k]) ch = true;
+                I.bnd[k * I.wd + w] = m[k];
+            }
+        }
+        if (ch) atomicOr(I.changed, 1);
+    }
+}
+
+// Validity at EXIT under the final placement of a context (its callers' cap).
+struct CapItem {
+    uint64_t* cap;            // [2][gw]
+    const uint64_t *avf_h, *avf_d;
+    int32_t exit, wd, gw, G;
+};
+
+__global__ void __launch_bounds__(64) k_cap(const CapItem* __restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const CapItem I = items[it];
+        for (int w = threadIdx.x; w < I.gw; w += blockDim.x) {
+            const uint64_t gm = word_mask(I.G, w);
+            I.cap[w] = I.avf_h[(size_t)I.exit * I.wd + w] & gm;
+            I.cap[I.gw + w] = I.avf_d[(size_t)I.exit * I.wd + w] & gm;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+#define CK(x)                                                                                   \
+    do {                                                                                        \
+        hipError_t e_ = (x);                                                                    \
+        if (e_ != hipSuccess)                                                                   \
+            return ompd_fail(OMPD_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+static inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Structure {
+    int n = 0, G = 0, gw = 0, nc = 0;
+    std::vector<int> wd, nb, ne;
+    std::vector<std::vector<int>> sites;   // per procedure: its call sites in order
+    std::vector<int> site_k;               // call site -> index among its caller's sites
+    // contexts
+    std::vector<int> cproc, cs0, cs1;
+    std::vector<std::vector<int>> child;   // per context: per site k, the callee context or -1
+    std::vector<std::vector<int>> comps;   // strongly connected components, callees first
+    std::vector<int> comp_level;           // per component
+};
+
+int check_program(const ompd_program* P, Structure& st)
+{
+    char buf[200];
+    auto bad = [&](const char* why, int i) {
+        snprintf(buf, sizeof buf, "program: %s (%d)", why, i);
+        return ompd_fail(OMPD_E_INVAL, buf);
+    };
+    if (!P || P->n_procs <= 0 || !P->procs || P->n_globals < 0 || P->n_calls < 0 || P->n_roots <= 0 || !P->roots)
+        return bad("bad sizes or missing arrays", 0);
+    if (P->n_calls > 0 && (!P->call_proc || !P->call_block || !P->callee)) return bad("call arrays missing", 0);
+    st.n = P->n_procs;
+    st.G = P->n_globals;
+    st.gw = (st.G + 63) / 64;
+    st.nc = P->n_calls;
+    st.wd.resize(st.n);
+    st.nb.resize(st.n);
+    st.ne.resize(st.n);
+    st.sites.assign(st.n, {});
+    for (int i = 0; i < st.n; ++i) {
+        const ompd_cfg& g = P->procs[i];
+        if (g.n_vars < st.G) return bad("procedure has fewer variables than globals", i);
+        if (g.call_summary || g.summaries || g.n_summaries) return bad("procedure carries call summaries", i);
+        if (g.n_blocks < 2 || g.entry < 0 || g.exit < 0 || g.entry >= g.n_blocks || g.exit >= g.n_blocks)
+            return bad("bad procedure shape", i);
+        st.wd[i] = (g.n_vars + 63) / 64;
+        st.nb[i] = g.n_blocks;
+        st.ne[i] = g.n_edges;
+    }
+    st.site_k.assign(st.nc, -1);
+    std::map<std::pair<int, int>, int> seen;
+    for (int j = 0; j < st.nc; ++j) {
+        const int p = P->call_proc[j], b = P->call_block[j], q = P->callee[j];
+        if (p < 0 || p >= st.n || q < -1 || q >= st.n) return bad("call site out of range", j);
+        const ompd_cfg& g = P->procs[p];
+        if (b < 0 || b >= g.n_blocks || b == g.entry || b == g.exit || g.space[b] != 0)
+            return bad("call block is not a host block of its procedure", j);
+        if (seen.count({p, b})) return bad("two calls in one block", j);
+        seen[{p, b}] = j;
+        st.site_k[j] = (int)st.sites[p].size();
+        st.sites[p].push_back(j);
+    }
+    for (int k = 0; k < P->n_roots; ++k)
+        if (P->roots[k] < 0 || P->roots[k] >= st.n) return bad("root out of range", k);
+    // contexts, breadth first from the roots
+    std::map<std::tuple<int, int, int>, int> idx;
+    std::deque<int> work;
+    auto add = [&](int q, int s0, int s1) -> int {
+        auto key = std::make_tuple(q, s0, s1);
+        auto itr = idx.find(key);
+        if (itr != idx.end()) return itr->second;
+        const int id = (int)st.cproc.size();
+        idx[key] = id;
+        st.cproc.push_back(q);
+        st.cs0.push_back(s0);
+        st.cs1.push_back(s1);
+        st.child.emplace_back();
+        work.push_back(id);
+        return id;
+    };
+    for (int k = 0; k < P->n_roots; ++k) add(P->roots[k], -1, -1);
+    while (!work.empty()) {
+        const int x = work.front();
+        work.pop_front();
+        const int p = st.cproc[x];
+        std::vector<int> ch(st.sites[p].size(), -1);
+        for (size_t k = 0; k < st.sites[p].size(); ++k) {
+            const int j = st.sites[p][k], q = P->callee[j];
+            if (q >= 0) ch[k] = add(q, st.cs1[x], j);
+        }
+        st.child[x] = ch;
+    }
+    // strongly connected components (iterative Tarjan), callees first
+    std::vector<std::vector<int>> succ(st.n);
+    for (int j = 0; j < st.nc; ++j)
+        if (P->callee[j] >= 0) succ[P->call_proc[j]].push_back(P->callee[j]);
+    std::vector<int> index(st.n, -1), low(st.n, 0), comp_of(st.n, -1);
+    std::vector<char> on(st.n, 0);
+    std::vector<int> stk;
+    int counter = 0;
+    for (int root = 0; root < st.n; ++root) {
+        if (index[root] >= 0) continue;
+        std::vector<std::pair<int, size_t>> call{{root, 0}};
+        while (!call.empty()) {
+            auto& fr = call.back();
+            const int v = fr.first;
+            if (fr.second == 0 && index[v] < 0) {
+                index[v] = low[v] = counter++;
+                stk.push_back(v);
+                on[v] = 1;
+            }
+            bool pushed = false;
+            while (fr.second < succ[v].size()) {
+                const int u = succ[v][fr.second++];
+                if (index[u] < 0) { call.push_back({u, 0}); pushed = true; break; }
+                if (on[u]) low[v] = std::min(low[v], index[u]);
+            }
+            if (pushed) continue;
+            if (low[v] == index[v]) {
+                std::vector<int> comp;
+                for (;;) {
+                    const int u = stk.back();
+                    stk.pop_back();
+                    on[u] = 0;
+                    comp_of[u] = (int)st.comps.size();
+                    comp.push_back(u);
+                    if (u == v) break;
+                }
+                st.comps.push_back(comp);
+            }
+            call.pop_back();
+            if (!call.empty()) low[call.back().first] = std::min(low[call.back().first], low[v]);
+        }
+    }
+    st.comp_level.assign(st.comps.size(), 0);
+    for (size_t ci = 0; ci < st.comps.size(); ++ci)   // callees' components come first
+        for (int v : st.comps[ci])
+            for (int u : succ[v])
+                if (comp_of[u] != (int)ci) st.comp_level[ci] = std::max(st.comp_level[ci], st.comp_level[comp_of[u]] + 1);
+    return OMPD_OK;
+}
+
+// Device copy of the program and the state of the solve.
+struct Prog {
+    ompd_ctx* ctx = nullptr;
+    const ompd_program* P = nullptr;
+    Structure st;
+    hipStream_t s = nullptr;
+    uint32_t flags = 0;
+    int64_t solves = 0;
+    char* arena = nullptr;
+    // per procedure (device pointers into the arena)
+    std::vector<int32_t*> sp, si, call;
+    std::vector<uint8_t*> kind, space;
+    std::vector<uint64_t*> R, Rd, W, sbnd;   // sbnd: [4 evaluations][4][wd] summary boundaries
+    std::vector<int32_t*> callees;           // [n_sites]
+    std::vector<uint64_t*> ptab;             // [n_sites][16][wd] call tables of the summary evaluations
+    uint64_t* S = nullptr;                   // [n][16][gw]
+    uint64_t* demand = nullptr;              // [nc][gw]   (accumulated)
+    uint64_t* demand_new = nullptr;          // [nc][gw]   (this outer round)
+    uint64_t* caps = nullptr;                // [nctx][2][gw]
+    int32_t* flag = nullptr;                 // scratch flags
+    // per context
+    std::vector<uint64_t*> bnd, ctab, acc;
+    std::vector<uint64_t*> o_nu_h, o_nu_d, o_ave_h, o_ave_d, o_avf_h, o_avf_d, o_ie_h, o_ie_d, o_ig_h, o_ig_d;
+    std::vector<uint8_t*> o_vk, o_ad, o_bd;
+    std::vector<int32_t> sweeps;             // [nctx][6]
+    // summary evaluation outputs (per procedure, 4 evaluations, nu/ave H/D)
+    std::vector<uint64_t*> e_out;            // [4][4][nb][wd]
+    char* arena_items = nullptr;             // staging of kernel work items
+    std::vector<char> cap_valid;             // per context: a cap from the previous outer round exists
+    ~Prog() { if (arena) (void)hipFree(arena); }
+};
+
+template <typename T>
+int upload_items(const std::vector<T>& v, void (*k)(const T*, int), int threads, hipStream_t s, char* scratch)
+{
+    if (v.empty()) return OMPD_OK;
+    CK(hipMemcpyAsync(scratch, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+    const int grid = (int)std::min<size_t>(v.size(), 4096);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(threads), 0, s, (const T*)scratch, (int)v.size());
+    CK(hipGetLastError());
+    CK(hipStreamSynchronize(s));
+    return OMPD_OK;
+}
+
+// Solve a batch of CFGs given by device-pointer descriptors.
+int run_batch(Prog& G, std::vector<ompd_cfg>& cfgs, std::vector<ompd_result>& res, uint32_t flags)
+{
+    if (cfgs.empty()) return OMPD_OK;
+    PlanConfig pc;
+    pc.use_graph = false;   // one-shot plans: capturing a graph would not be replayed
+    ompd_plan* plan = nullptr;
+    int rc = ompd_plan_build(G.ctx, cfgs.data(), res.data(), (int32_t)cfgs.size(),
+                             flags | OMPD_F_DEVICE_PTRS | (G.flags & 0xFFFF0000u), pc, &plan);
+    if (rc) return rc;
+    rc = ompd_plan_run_locked(plan, G.s);
+    if (rc == OMPD_OK) rc = ompd_plan_collect(plan, nullptr);
+    for (size_t i = 0; i < cfgs.size(); ++i) memcpy(res[i].sweeps, plan->res[i].sweeps, sizeof res[i].sweeps);
+    ompd_plan_destroy(plan);
+    G.solves += (int64_t)cfgs.size();
+    return rc;
+}
+
+int read_flag(Prog& G, int32_t* dflag, int& out)
+{
+    CK(hipMemcpyAsync(&out, dflag, 4, hipMemcpyDeviceToHost, G.s));
+    CK(hipStreamSynchronize(G.s));
+    return OMPD_OK;
+}
+
+int zero_flag(Prog& G, int32_t* dflag)
+{
+    CK(hipMemsetAsync(dflag, 0, 4, G.s));
+    return OMPD_OK;
+}
+
+int setup(Prog& G)
+{
+    const Structure& st = G.st;
+    const ompd_program* P = G.P;
+    const int n = st.n, gw = st.gw, nctx = (int)st.cproc.size();
+    // arena layout
+    size_t total = 0;
+    auto take = [&](size_t bytes) { size_t x = total; total += a256(std::max<size_t>(bytes, 8)); return x; };
+    struct PO { size_t sp, si, kind, space, R, Rd, W, call, sbnd, callees, ptab, eout; };
+    std::vector<PO> po(n);
+    for (int i = 0; i < n; ++i) {
+        const size_t nb = st.nb[i], ne = st.ne[i], wd = st.wd[i], ns = st.sites[i].size();
+        po[i].sp = take(4 * (nb + 1));
+        po[i].si = take(4 * ne);
+        po[i].kind = take(ne);
+        po[i].space = take(nb);
+        po[i].R = take(8 * nb * wd);
+        po[i].Rd = take(8 * nb * wd);
+        po[i].W = take(8 * nb * wd);
+        po[i].call = take(4 * nb);
+        po[i].sbnd = take(8 * 16 * wd);
+        po[i].callees = take(4 * ns);
+        po[i].ptab = take(8 * ns * SUM_ROWS * wd);
+        po[i].eout = take(8 * 16 * nb * wd);
+    }
+    const size_t oS = take(8 * (size_t)n * SUM_ROWS * gw);
+    const size_t oD = take(8 * (size_t)std::max(st.nc, 1) * gw);
+    const size_t oDn = take(8 * (size_t)std::max(st.nc, 1) * gw);
+    const size_t oC = take(8 * (size_t)nctx * 2 * gw);
+    const size_t oF = take(4 * (size_t)(nctx + 16));
+    struct CO { size_t bnd, ctab, acc, out; };
+    std::vector<CO> co(nctx);
+    for (int x = 0; x < nctx; ++x) {
+        const int p = st.cproc[x];
+        const size_t nb = st.nb[p], ne = st.ne[p], wd = st.wd[p], ns = st.sites[p].size();
+        co[x].bnd = take(8 * 4 * wd);
+        co[x].ctab = take(8 * ns * SUM_ROWS * wd);
+        co[x].acc = take(8 * 4 * gw);
+        co[x].out = take(8 * (8 * nb * wd + 2 * ne * wd) + (size_t)P->procs[p].n_vars + 2 * nb + 64);
+    }
+    const size_t oItems = take(64ull << 20);   // staging of kernel work items
+    hipError_t e = hipMalloc(&G.arena, total);
+    if (e != hipSuccess) return ompd_fail(OMPD_E_NOMEM, std::string("program arena: ") + hipGetErrorString(e));
+    char* A = G.arena;
+    G.sp.resize(n); G.si.resize(n); G.kind.resize(n); G.space.resize(n); G.R.resize(n); G.Rd.resize(n);
+    G.W.resize(n); G.call.resize(n); G.sbnd.resize(n); G.callees.resize(n); G.ptab.resize(n); G.e_out.resize(n);
+    std::vector<uint64_t> hb;
+    for (int i = 0; i < n; ++i) {
+        const ompd_cfg& g = P->procs[i];
+        const size_t nb = st.nb[i], ne = st.ne[i], wd = st.wd[i], ns = st.sites[i].size();
+        G.sp[i] = (int32_t*)(A + po[i].sp); G.si[i] = (int32_t*)(A + po[i].si);
+        G.kind[i] = (uint8_t*)(A + po[i].kind); G.space[i] = (uint8_t*)(A + po[i].space);
+        G.R[i] = (uint64_t*)(A + po[i].R); G.Rd[i] = (uint64_t*)(A + po[i].Rd); G.W[i] = (uint64_t*)(A + po[i].W);
+        G.call[i] = (int32_t*)(A + po[i].call); G.sbnd[i] = (uint64_t*)(A + po[i].sbnd);
+        G.callees[i] = (int32_t*)(A + po[i].callees); G.ptab[i] = (uint64_t*)(A + po[i].ptab);
+        G.e_out[i] = (uint64_t*)(A + po[i].eout);
+        CK(hipMemcpyAsync(G.sp[i], g.succ_ptr, 4 * (nb + 1), hipMemcpyHostToDevice, G.s));
+        if (ne) {
+            CK(hipMemcpyAsync(G.si[i], g.succ_idx, 4 * ne, hipMemcpyHostToDevice, G.s));
+            CK(hipMemcpyAsync(G.kind[i], g.edge_kind, ne, hipMemcpyHostToDevice, G.s));
+        }
+        CK(hipMemcpyAsync(G.space[i], g.space, nb, hipMemcpyHostToDevice, G.s));
+        if (wd) {
+            CK(hipMemcpyAsync(G.R[i], g.read_bits, 8 * nb * wd, hipMemcpyHostToDevice, G.s));
+            CK(hipMemcpyAsync(G.Rd[i], g.read_bits, 8 * nb * wd, hipMemcpyHostToDevice, G.s));
+            CK(hipMemcpyAsync(G.W[i], g.write_bits, 8 * nb * wd, hipMemcpyHostToDevice, G.s));
+        }
+        std::vector<int32_t> call(nb, -1), cal(std::max<size_t>(ns, 1), -1);
+        for (size_t k = 0; k < ns; ++k) {
+            call[P->call_block[st.sites[i][k]]] = (int32_t)k;
+            cal[k] = P->callee[st.sites[i][k]];
+        }
+        CK(hipMemcpyAsync(G.call[i], call.data(), 4 * nb, hipMemcpyHostToDevice, G.s));
+        CK(hipMemcpyAsync(G.callees[i], cal.data(), 4 * cal.size(), hipMemcpyHostToDevice, G.s));
+        // summary boundaries, evaluation 2e+l: entry valid (e ? globals : none) on both spaces
+        // plus the locals on the host; globals live after exit in both spaces iff l
+        hb.assign(16 * wd, 0);
+        for (int ev = 0; ev < 4; ++ev) {
+            const int eps = ev >> 1, ell = ev & 1;
+            for (size_t w = 0; w < wd; ++w) {
+                const int lo = 64 * (int)w;
+                auto mask = [&](int bits) -> uint64_t {
+                    if (bits >= lo + 64) return ~0ull;
+                    if (bits <= lo) return 0ull;
+                    return (1ull << (bits - lo)) - 1ull;
+                };
+                const uint64_t gm = mask(st.G), lm = mask(g.n_vars) & ~gm;
+                hb[(ev * 4 + 0) * wd + w] = (eps ? gm : 0) | lm;
+                hb[(ev * 4 + 1) * wd + w] = eps ? gm : 0;
+                hb[(ev * 4 + 2) * wd + w] = ell ? gm : 0;
+                hb[(ev * 4 + 3) * wd + w] = ell ? gm : 0;
+            }
+        }
+        if (wd) CK(hipMemcpyAsync(G.sbnd[i], hb.data(), 8 * 16 * wd, hipMemcpyHostToDevice, G.s));
+        CK(hipStreamSynchronize(G.s));   // host vectors are reused
+    }
+    G.S = (uint64_t*)(A + oS);
+    G.demand = (uint64_t*)(A + oD);
+    G.demand_new = (uint64_t*)(A + oDn);
+    G.caps = (uint64_t*)(A + oC);
+    G.flag = (int32_t*)(A + oF);
+    CK(hipMemsetAsync(G.demand, 0, 8 * (size_t)std::max(st.nc, 1) * gw, G.s));
+    G.bnd.resize(nctx); G.ctab.resize(nctx); G.acc.resize(nctx);
+    for (auto* v : {&G.o_nu_h, &G.o_nu_d, &G.o_ave_h, &G.o_ave_d, &G.o_avf_h, &G.o_avf_d, &G.o_ie_h, &G.o_ie_d,
+                    &G.o_ig_h, &G.o_ig_d})
+        v->resize(nctx);
+    G.o_vk.resize(nctx); G.o_ad.resize(nctx); G.o_bd.resize(nctx);
+    G.sweeps.assign((size_t)nctx * 6, 0);
+    for (int x = 0; x < nctx; ++x) {
+        const int p = st.cproc[x];
+        const size_t nb = st.nb[p], ne = st.ne[p], wd = st.wd[p];
+        G.bnd[x] = (uint64_t*)(A + co[x].bnd);
+        G.ctab[x] = (uint64_t*)(A + co[x].ctab);
+        G.acc[x] = (uint64_t*)(A + co[x].acc);
+        uint64_t* o = (uint64_t*)(A + co[x].out);
+        const size_t bv = nb * wd, evv = ne * wd;
+        G.o_nu_h[x] = o; G.o_nu_d[x] = o + bv; G.o_ave_h[x] = o + 2 * bv; G.o_ave_d[x] = o + 3 * bv;
+        G.o_avf_h[x] = o + 4 * bv; G.o_avf_d[x] = o + 5 * bv; G.o_ie_h[x] = o + 6 * bv; G.o_ie_d[x] = o + 7 * bv;
+        G.o_ig_h[x] = o + 8 * bv; G.o_ig_d[x] = o + 8 * bv + evv;
+        uint8_t* b8 = (uint8_t*)(o + 8 * bv + 2 * evv);
+        G.o_vk[x] = b8; G.o_ad[x] = b8 + P->procs[p].n_vars; G.o_bd[x] = b8 + P->procs[p].n_vars + nb;
+    }
+    G.arena_items = A + oItems;
+    return OMPD_OK;
+}
+
+// Call tables of procedure p for the summary evaluations (no caps) or of
+// context x (caps of the callee contexts when they exist).
+void calltab_items(Prog& G, int p, int x, std::vector<CallTabItem>& out)
+{
+    const Structure& st = G.st;
+    const size_t wd = st.wd[p];
+    for (size_t k = 0; k < st.sites[p].size(); ++k) {
+        const int j = st.sites[p][k], q = G.P->callee[j];
+        CallTabItem I;
+        I.dst = (x < 0 ? G.ptab[p] : G.ctab[x]) + k * SUM_ROWS * wd;
+        I.src = q < 0 ? nullptr : G.S + (size_t)q * SUM_ROWS * st.gw;
+        I.cap = nullptr;
+        if (x >= 0 && q >= 0) {
+            const int cx = st.child[x][k];
+            if (cx >= 0 && G.cap_valid[cx]) I.cap = G.caps + (size_t)cx * 2 * st.gw;
+        }
+        I.wd = (int32_t)wd; I.gw = st.gw; I.G = st.G; I.nv = G.P->procs[p].n_vars;
+        out.push_back(I);
+    }
+}
+
+ompd_cfg dev_cfg(Prog& G, int p)
+{
+    const ompd_cfg& g = G.P->procs[p];
+    ompd_cfg d;
+    memset(&d, 0, sizeof d);
+    d.n_blocks = g.n_blocks; d.n_edges = g.n_edges; d.n_vars = g.n_vars; d.entry = g.entry; d.exit = g.exit;
+    d.succ_ptr = G.sp[p]; d.succ_idx = G.si[p]; d.edge_kind = G.kind[p]; d.space = G.space[p];
+    d.read_bits = G.Rd[p]; d.write_bits = G.W[p];
+    if (!G.st.sites[p].empty()) {
+        d.call_summary = G.call[p];
+        d.n_summaries = (int32_t)G.st.sites[p].size();
+    }
+    return d;
+}
+
+// Evaluate the summaries of a set of procedures (4 boundary solves each) and
+// gather the rows selected by `rows` (bit 0 next use, bit 1 validity tables).
+int evaluate(Prog& G, const std::vector<int>& procs, int rows, int& changed)
+{
+    const Structure& st = G.st;
+    changed = 0;
+    if (procs.empty()) return OMPD_OK;
+    std::vector<CallTabItem> ct;
+    for (int p : procs) calltab_items(G, p, -1, ct);
+    int rc = upload_items(ct, k_calltab, 256, G.s, G.arena_items);
+    if (rc) return rc;
+    std::vector<ompd_cfg> cfgs;
+    std::vector<ompd_result> res;
+    for (int p : procs) {
+        const size_t wd = st.wd[p], bv = (size_t)st.nb[p] * wd;
+        for (int ev = 0; ev < 4; ++ev) {
+            ompd_cfg d = dev_cfg(G, p);
+            if (d.call_summary) d.summaries = G.ptab[p];
+            d.entry_valid_host = G.sbnd[p] + (ev * 4 + 0) * wd;
+            d.entry_valid_dev = G.sbnd[p] + (ev * 4 + 1) * wd;
+            d.exit_live_host = G.sbnd[p] + (ev * 4 + 2) * wd;
+            d.exit_live_dev = G.sbnd[p] + (ev * 4 + 3) * wd;
+            ompd_result r;
+            memset(&r, 0, sizeof r);
+            uint64_t* o = G.e_out[p] + (size_t)ev * 4 * bv;
+            r.nu_host = o; r.nu_dev = o + bv; r.ave_host = o + 2 * bv; r.ave_dev = o + 3 * bv;
+            cfgs.push_back(d);
+            res.push_back(r);
+        }
+    }
+    rc = run_batch(G, cfgs, res, OMPD_F_SUMMARY);
+    if (rc) return rc;
+    std::vector<SumItem> si;
+    for (int p : procs) {
+        const size_t wd = st.wd[p], bv = (size_t)st.nb[p] * wd;
+        for (int ev = 0; ev < 4; ++ev) {
+            SumItem I;
+            const uint64_t* o = G.e_out[p] + (size_t)ev * 4 * bv;
+            I.S = G.S + (size_t)p * SUM_ROWS * st.gw;
+            I.nu_h = o; I.nu_d = o + bv; I.ave_h = o + 2 * bv; I.ave_d = o + 3 * bv;
+            I.entry = G.P->procs[p].entry; I.exit = G.P->procs[p].exit;
+            I.wd = (int32_t)wd; I.gw = st.gw; I.G = st.G; I.eps = ev >> 1; I.ell = ev & 1; I.rows = rows;
+            I.changed = G.flag;
+            si.push_back(I);
+        }
+    }
+    rc = zero_flag(G, G.flag);
+    if (rc) return rc;
+    rc = upload_items(si, k_sumgather, 64, G.s, G.arena_items);
+    if (rc) return rc;
+    return read_flag(G, G.flag, changed);
+}
+
+int may_rows(Prog& G, const std::vector<int>& procs, int& changed)
+{
+    const Structure& st = G.st;
+    std::vector<MayItem> mi;
+    for (int p : procs) {
+        MayItem I;
+        I.S = G.S + (size_t)p * SUM_ROWS * st.gw;
+        I.R = G.Rd[p]; I.W = G.W[p]; I.space = G.space[p];
+        I.callees = G.callees[p]; I.Sall = G.S;
+        I.nb = st.nb[p]; I.wd = st.wd[p]; I.gw = st.gw; I.G = st.G; I.n_sites = (int32_t)st.sites[p].size();
+        I.changed = G.flag;
+        mi.push_back(I);
+    }
+    int rc = zero_flag(G, G.flag);
+    if (rc) return rc;
+    rc = upload_items(mi, k_may, 64, G.s, G.arena_items);
+    if (rc) return rc;
+    return read_flag(G, G.flag, changed);
+}
+
+// Bottom-up: components by level; a non-recursive procedure is evaluated
+// once, a recursive component iterates its next-use rows from 0, then its
+// validity tables from all ones, then its may-sets from 0.
+int summarize(Prog& G)
+{
+    const Structure& st = G.st;
+    CK(hipMemsetAsync(G.S, 0, 8 * (size_t)st.n * SUM_ROWS * st.gw, G.s));
+    int max_level = 0;
+    for (int l : st.comp_level) max_level = std::max(max_level, l);
+    std::vector<uint64_t> ones(4 * (size_t)st.gw * 2, 0);
+    for (int level = 0; level <= max_level; ++level) {
+        std::vector<int> single, recur_procs;
+        std::vector<const std::vector<int>*> recur;
+        for (size_t ci = 0; ci < st.comps.size(); ++ci) {
+            if (st.comp_level[ci] != level) continue;
+            const std::vector<int>& comp = st.comps[ci];
+            bool self = false;
+            if (comp.size() == 1)
+                for (int j : st.sites[comp[0]]) self |= G.P->callee[j] == comp[0];
+            if (comp.size() == 1 && !self) single.push_back(comp[0]);
+            else {
+                recur.push_back(&comp);
+                recur_procs.insert(recur_procs.end(), comp.begin(), comp.end());
+            }
+        }
+        int ch = 0;
+        int rc = evaluate(G, single, 3, ch);
+        if (rc) return rc;
+        rc = may_rows(G, single, ch);
+        if (rc) return rc;
+        if (recur_procs.empty()) continue;
+        // recursive components: validity tables start at all ones over the globals
+        std::vector<uint64_t> row(8 * (size_t)st.gw);
+        for (int w = 0; w < st.gw; ++w) {
+            const int lo = 64 * w;
+            const uint64_t gm = st.G >= lo + 64 ? ~0ull : (st.G <= lo ? 0ull : (1ull << (st.G - lo)) - 1ull);
+            for (int k = 0; k < 8; ++k) row[(size_t)k * st.gw + w] = gm;
+        }
+        for (int p : recur_procs)
+            CK(hipMemcpyAsync(G.S + ((size_t)p * SUM_ROWS + SUM_TH) * st.gw, row.data(), 8 * row.size(),
+                              hipMemcpyHostToDevice, G.s));
+        CK(hipStreamSynchronize(G.s));
+        for (int rows : {1, 2}) {
+            do {
+                rc = evaluate(G, recur_procs, rows, ch);
+                if (rc) return rc;
+            } while (ch);
+        }
+        do {
+            rc = may_rows(G, recur_procs, ch);
+            if (rc) return rc;
+        } while (ch);
+    }
+    return OMPD_OK;
+}
+
+// Top-down rounds over the contexts of one outer round.
+int contexts(Prog& G)
+{
+    const Structure& st = G.st;
+    const ompd_program* P = G.P;
+    const int nctx = (int)st.cproc.size(), gw = st.gw;
+    std::vector<char> present(nctx, 0);
+    CK(hipMemsetAsync(G.demand_new, 0, 8 * (size_t)std::max(st.nc, 1) * gw, G.s));
+    // root contexts: their own boundaries
+    std::vector<int> dirty;
+    for (int x = 0; x < nctx; ++x) {
+        if (st.cs1[x] >= 0) continue;
+        const int p = st.cproc[x];
+        const ompd_cfg& g = P->procs[p];
+        const size_t wd = st.wd[p];
+        std::vector<uint64_t> b(4 * wd, 0);
+        for (size_t w = 0; w < wd; ++w) {
+            const int lo = 64 * (int)w;
+            const uint64_t m = g.n_vars >= lo + 64 ? ~0ull : (g.n_vars <= lo ? 0ull : (1ull << (g.n_vars - lo)) - 1ull);
+            b[w] = g.entry_valid_host ? g.entry_valid_host[w] : m;
+            b[wd + w] = g.entry_valid_dev ? g.entry_valid_dev[w] : 0;
+            b[2 * wd + w] = g.exit_live_host ? g.exit_live_host[w] : m;
+            b[3 * wd + w] = g.exit_live_dev ? g.exit_live_dev[w] : 0;
+        }
+        if (wd) CK(hipMemcpyAsync(G.bnd[x], b.data(), 8 * 4 * wd, hipMemcpyHostToDevice, G.s));
+        CK(hipStreamSynchronize(G.s));
+        present[x] = 1;
+        dirty.push_back(x);
+    }
+    std::vector<uint64_t> acc_init;
+    while (!dirty.empty()) {
+        // solve every dirty context
+        std::vector<CallTabItem> ct;
+        for (int x : dirty) calltab_items(G, st.cproc[x], x, ct);
+        int rc = upload_items(ct, k_calltab, 256, G.s, G.arena_items);
+        if (rc) return rc;
+        std::vector<ompd_cfg> cfgs;
+        std::vector<ompd_result> res;
+        for (int x : dirty) {
+            const int p = st.cproc[x];
+            const size_t wd = st.wd[p];
+            ompd_cfg d = dev_cfg(G, p);
+            if (d.call_summary) d.summaries = G.ctab[x];
+            d.entry_valid_host = G.bnd[x]; d.entry_valid_dev = G.bnd[x] + wd;
+            d.exit_live_host = G.bnd[x] + 2 * wd; d.exit_live_dev = G.bnd[x] + 3 * wd;
+            ompd_result r;
+            memset(&r, 0, sizeof r);
+            r.nu_host = G.o_nu_h[x]; r.nu_dev = G.o_nu_d[x]; r.ave_host = G.o_ave_h[x]; r.ave_dev = G.o_ave_d[x];
+            r.avf_host = G.o_avf_h[x]; r.avf_dev = G.o_avf_d[x];
+            r.ins_entry_to_host = G.o_ie_h[x]; r.ins_entry_to_dev = G.o_ie_d[x];
+            r.ins_edge_to_host = G.o_ig_h[x]; r.ins_edge_to_dev = G.o_ig_d[x];
+            r.var_kind = G.o_vk[x]; r.after_dev = G.o_ad[x]; r.before_dev = G.o_bd[x];
+            cfgs.push_back(d);
+            res.push_back(r);
+        }
+        rc = run_batch(G, cfgs, res, 0);
+        if (rc) return rc;
+        for (size_t i = 0; i < dirty.size(); ++i)
+            memcpy(&G.sweeps[(size_t)dirty[i] * 6], res[i].sweeps, sizeof res[i].sweeps);
+        // contributions of every solved call to its callee context
+        std::vector<int> touched;
+        std::vector<char> is_t(nctx, 0);
+        std::vector<ContribItem> cb;
+        for (int x : dirty) {
+            const int p = st.cproc[x];
+            for (size_t k = 0; k < st.sites[p].size(); ++k) {
+                const int cx = st.child[x][k];
+                if (cx < 0) continue;
+                if (!is_t[cx]) { is_t[cx] = 1; touched.push_back(cx); }
+                ContribItem I;
+                I.avf_h = G.o_avf_h[x]; I.avf_d = G.o_avf_d[x]; I.nu_h = G.o_nu_h[x]; I.nu_d = G.o_nu_d[x];
+                I.W = G.W[p]; I.succ_ptr = G.sp[p]; I.succ_idx = G.si[p];
+                I.acc = G.acc[cx];
+                I.c = P->call_block[st.sites[p][k]]; I.wd = st.wd[p]; I.gw = gw; I.G = st.G;
+                I.cnv = P->procs[st.cproc[cx]].n_vars;
+                cb.push_back(I);
+            }
+        }
+        // accumulators start at the meet's identity: validity all ones, liveness none
+        acc_init.assign(4 * (size_t)gw, 0);
+        for (int w = 0; w < 2 * gw; ++w) acc_init[w] = ~0ull;
+        for (int cx : touched)
+            CK(hipMemcpyAsync(G.acc[cx], acc_init.data(), 8 * 4 * gw, hipMemcpyHostToDevice, G.s));
+        rc = upload_items(cb, k_contrib, 64, G.s, G.arena_items);
+        if (rc) return rc;
+        // meet into the boundaries
+        int32_t* chg = G.flag + 16;
+        CK(hipMemsetAsync(chg, 0, 4 * (size_t)nctx, G.s));
+        std::vector<UpdItem> up;
+        for (int cx : touched) {
+            const int q = st.cproc[cx];
+            UpdItem I;
+            I.bnd = G.bnd[cx]; I.acc = G.acc[cx];
+            I.demand = G.demand_new + (size_t)st.cs1[cx] * gw;
+            I.changed = chg + cx;
+            I.wd = st.wd[q]; I.gw = gw; I.G = st.G; I.nv = P->procs[q].n_vars; I.present = present[cx];
+            up.push_back(I);
+        }
+        rc = upload_items(up, k_update, 64, G.s, G.arena_items);
+        if (rc) return rc;
+        std::vector<int32_t> hc(nctx);
+        CK(hipMemcpyAsync(hc.data(), chg, 4 * (size_t)nctx, hipMemcpyDeviceToHost, G.s));
+        CK(hipStreamSynchronize(G.s));
+        dirty.clear();
+        for (int cx : touched) {
+            present[cx] = 1;
+            if (hc[cx]) dirty.push_back(cx);
+        }
+        std::sort(dirty.begin(), dirty.end());
+    }
+    return OMPD_OK;
+}
+
+}  // namespace
+
+extern "C" int ompd_program_contexts(ompd_ctx* ctx, const ompd_program* prog, int32_t* n_contexts, int32_t* ctx_proc,
+                                     int32_t* ctx_site0, int32_t* ctx_site1, int32_t capacity)
+{
+    if (!ctx || !n_contexts) return ompd_fail(OMPD_E_INVAL, "ctx / n_contexts is NULL");
+    Structure st;
+    int rc = check_program(prog, st);
+    if (rc) return rc;
+    const int n = (int)st.cproc.size();
+    *n_contexts = n;
+    for (int x = 0; x < n && x < capacity; ++x) {
+        if (ctx_proc) ctx_proc[x] = st.cproc[x];
+        if (ctx_site0) ctx_site0[x] = st.cs0[x];
+        if (ctx_site1) ctx_site1[x] = st.cs1[x];
+    }
+    return OMPD_OK;
+}
+
+extern "C" int ompd_analyze_program(ompd_ctx* ctx, const ompd_program* prog, ompd_program_result* out, uint32_t flags)
+{
+    if (!ctx || !out) return ompd_fail(OMPD_E_INVAL, "ctx / out is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Prog G;
+    G.ctx = ctx;
+    G.P = prog;
+    G.flags = flags & 0xFFFF0000u;
+    int rc = check_program(prog, G.st);
+    if (rc) return rc;
+    CK(hipSetDevice(ctx->device));
+    CK(hipStreamCreateWithFlags(&G.s, hipStreamNonBlocking));
+    struct StreamGuard { hipStream_t s; ~StreamGuard() { (void)hipStreamDestroy(s); } } sg{G.s};
+    rc = setup(G);
+    if (rc) return rc;
+    const Structure& st = G.st;
+    const int nctx = (int)st.cproc.size(), gw = st.gw;
+    G.cap_valid.assign(nctx, 0);
+    std::vector<uint64_t> dem((size_t)std::max(st.nc, 1) * gw, 0), dnew(dem.size()), capv((size_t)nctx * 2 * gw),
+        capn(capv.size());
+    int rounds = 0;
+    bool settled = false;
+    while (rounds < 64) {
+        ++rounds;
+        rc = summarize(G);
+        if (rc) return rc;
+        rc = contexts(G);
+        if (rc) return rc;
+        // new caps: validity at EXIT of every non-root context
+        std::vector<CapItem> ci;
+        for (int x = 0; x < nctx; ++x) {
+            if (st.cs1[x] < 0) continue;
+            const int p = st.cproc[x];
+            CapItem I;
+            I.cap = G.caps + (size_t)x * 2 * gw;
+            I.avf_h = G.o_avf_h[x]; I.avf_d = G.o_avf_d[x];
+            I.exit = prog->procs[p].exit; I.wd = st.wd[p]; I.gw = gw; I.G = st.G;
+            ci.push_back(I);
+        }
+        // previous caps, for the comparison
+        if (gw) CK(hipMemcpyAsync(capv.data(), G.caps, 8 * capv.size(), hipMemcpyDeviceToHost, G.s));
+        CK(hipStreamSynchronize(G.s));
+        rc = upload_items(ci, k_cap, 64, G.s, G.arena_items);
+        if (rc) return rc;
+        if (gw) CK(hipMemcpyAsync(capn.data(), G.caps, 8 * capn.size(), hipMemcpyDeviceToHost, G.s));
+        if (st.nc && gw) CK(hipMemcpyAsync(dnew.data(), G.demand_new, 8 * (size_t)st.nc * gw, hipMemcpyDeviceToHost, G.s));
+        CK(hipStreamSynchronize(G.s));
+        bool grew = false;
+        for (int x = 0; x < nctx; ++x) {
+            if (st.cs1[x] < 0) continue;
+            bool same = G.cap_valid[x];
+            for (int w = 0; w < 2 * gw && same; ++w) same = capv[(size_t)x * 2 * gw + w] == capn[(size_t)x * 2 * gw + w];
+            if (!same) grew = true;
+            G.cap_valid[x] = 1;
+        }
+        for (size_t k = 0; k < (size_t)st.nc * gw; ++k) {
+            const uint64_t v = dem[k] | dnew[k];
+            if (v != dem[k]) { dem[k] = v; grew = true; }
+        }
+        if (!grew) { settled = true; break; }
+        // apply the demands: reads at the call blocks
+        if (st.nc && gw) CK(hipMemcpyAsync(G.demand, dem.data(), 8 * (size_t)st.nc * gw, hipMemcpyHostToDevice, G.s));
+        std::vector<DemandItem> di;
+        for (int j = 0; j < st.nc; ++j) {
+            const int p = prog->call_proc[j];
+            DemandItem I;
+            I.Rd = G.Rd[p]; I.R = G.R[p]; I.demand = G.demand + (size_t)j * gw;
+            I.block = prog->call_block[j]; I.wd = st.wd[p]; I.gw = gw;
+            di.push_back(I);
+        }
+        rc = upload_items(di, k_demand, 64, G.s, G.arena_items);
+        if (rc) return rc;
+    }
+    out->rounds = rounds;
+    out->solves = G.solves;
+    if (!settled) return ompd_fail(OMPD_E_NOCONVERGE, "program: demands and caps did not settle in 64 rounds");
+    // results to the host
+    if (out->summaries && gw)
+        CK(hipMemcpyAsync(out->summaries, G.S, 8 * (size_t)st.n * SUM_ROWS * gw, hipMemcpyDeviceToHost, G.s));
+    if (out->demands && st.nc && gw)
+        memcpy(out->demands, dem.data(), 8 * (size_t)st.nc * gw);
+    size_t boff = 0;
+    for (int x = 0; x < nctx; ++x) {
+        const int p = st.cproc[x];
+        const size_t nb = st.nb[p], ne = st.ne[p], wd = st.wd[p], bv = nb * wd, ev = ne * wd;
+        if (out->boundaries && wd)
+            CK(hipMemcpyAsync(out->boundaries + boff, G.bnd[x], 8 * 4 * wd, hipMemcpyDeviceToHost, G.s));
+        boff += 4 * wd;
+        if (!out->per_context) continue;
+        ompd_result& r = out->per_context[x];
+        auto cp = [&](void* dst, const void* src, size_t bytes) -> int {
+            if (dst && bytes) CK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, G.s));
+            return OMPD_OK;
+        };
+        int e = 0;
+        e |= cp(r.nu_host, G.o_nu_h[x], 8 * bv); e |= cp(r.nu_dev, G.o_nu_d[x], 8 * bv);
+        e |= cp(r.ave_host, G.o_ave_h[x], 8 * bv); e |= cp(r.ave_dev, G.o_ave_d[x], 8 * bv);
+        e |= cp(r.avf_host, G.o_avf_h[x], 8 * bv); e |= cp(r.avf_dev, G.o_avf_d[x], 8 * bv);
+        e |= cp(r.ins_entry_to_host, G.o_ie_h[x], 8 * bv); e |= cp(r.ins_entry_to_dev, G.o_ie_d[x], 8 * bv);
+        e |= cp(r.ins_edge_to_host, G.o_ig_h[x], 8 * ev); e |= cp(r.ins_edge_to_dev, G.o_ig_d[x], 8 * ev);
+        e |= cp(r.var_kind, G.o_vk[x], (size_t)prog->procs[p].n_vars);
+        e |= cp(r.after_dev, G.o_ad[x], nb); e |= cp(r.before_dev, G.o_bd[x], nb);
+        if (e) return OMPD_E_DEVICE;
+        memcpy(r.sweeps, &G.sweeps[(size_t)x * 6], sizeof r.sweeps);
+    }
+    CK(hipStreamSynchronize(G.s));
+    return OMPD_OK;
+}

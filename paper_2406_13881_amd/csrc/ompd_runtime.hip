@@ -22,6 +22,8 @@ extern "C" __global__ void ompd_k_ave(const DevCfg*, const Tile*, int, int32_t*,
 extern "C" __global__ void ompd_k_mayp(const DevCfg*, const Tile*, int, int32_t*, int);
 extern "C" __global__ void ompd_k_later(const DevCfg*, const Tile*, int, int32_t*, int);
 extern "C" __global__ void ompd_k_avf(const DevCfg*, const Tile*, int, int32_t*, int);
+extern "C" __global__ void ompd_k_edge0(const DevCfg*, const Tile*, const EdgeItem*, int, int32_t*);
+extern "C" __global__ void ompd_k_edge1(const DevCfg*, const Tile*, const EdgeItem*, int, int32_t*);
 static const void* const k_phases[5] = {(const void*)ompd_k_nu, (const void*)ompd_k_ave, (const void*)ompd_k_mayp,
                                         (const void*)ompd_k_later, (const void*)ompd_k_avf};
 }  // namespace ompd
@@ -156,6 +158,8 @@ size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o)
     o.aveout = take(2 * bv);
     o.mayp = take(2 * bv);
     o.later = take(2 * bv);
+    o.eag = take(2 * ev);
+    o.both = take(ev);
     o.flg = take((size_t)tiles_of((int)wd) * 4 * (size_t)g.n_blocks * 8);
     o.nu = (r.nu_host && r.nu_dev) ? SIZE_MAX : take(2 * bv);
     o.ave = (r.ave_host && r.ave_dev) ? SIZE_MAX : take(2 * bv);
@@ -184,7 +188,7 @@ void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const
     memset(&d, 0, sizeof d);
     d.nb = g.n_blocks; d.ne = g.n_edges; d.nv = g.n_vars; d.entry = g.entry; d.exit = g.exit; d.wd = wd;
     d.n_sums = g.call_summary ? g.n_summaries : 0;
-    d.placement = (flags & OMPD_F_PLACEMENT_EAGER) ? 1 : 0;
+    d.placement = ((flags & OMPD_F_PLACEMENT_EAGER) ? 1 : 0) | ((flags & OMPD_F_SUMMARY) ? 2 : 0);
     d.sweep_cap = (int)((flags >> 16) & 0xFFFFu);
     d.succ_ptr = g.succ_ptr; d.succ_idx = g.succ_idx; d.kind = g.edge_kind; d.space = g.space;
     d.R = g.read_bits; d.W = g.write_bits;
@@ -214,6 +218,8 @@ void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const
     uint64_t* la = at(o.later);
     d.aveout_h = ao; d.aveout_d = ao + bvw; d.mayp_h = mp; d.mayp_d = mp + bvw;
     d.later_h = la; d.later_d = la + bvw;
+    uint64_t* ea = at(o.eag);
+    d.eag_h = ea; d.eag_d = ea + evw; d.both = at(o.both);
     d.flg = at(o.flg);
     d.pred_ptr = (int32_t*)(base + o.pp); d.pred_idx = (int32_t*)(base + o.pi);
     d.pred_eid = (int32_t*)(base + o.pe); d.tmp = (int32_t*)(base + o.tmp);
@@ -233,29 +239,36 @@ void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const
 // Default LDS of one solve wavefront: the ring of recently computed blocks.
 constexpr size_t RING_BYTES_DEFAULT = 8 * 1024;
 
-// Tiles for a set of CFGs, longest first, and the launch sizes that go with
-// them under a configuration.
-int ompd_make_plan_tiles(ompd_ctx* ctx, const std::vector<DevCfg>& cfgs, const PlanConfig& pc,
-                         std::vector<Tile>& tiles, size_t& lds_solve, size_t& lds_prep, int& grid_solve)
+// Tiles for a set of CFGs, longest first, the edge-step items and the launch
+// sizes that go with them under a configuration.
+int ompd_make_shape(ompd_ctx* ctx, const std::vector<DevCfg>& cfgs, const PlanConfig& pc, Shape& sh)
 {
+    std::vector<Tile>& tiles = sh.tiles;
     tiles.clear();
+    sh.items.clear();
     for (int i = 0; i < (int)cfgs.size(); ++i) make_tiles(i, cfgs[i].nv, tiles);
     // a tile's work ~ its blocks times the sweeps, which grow with the CFG: longest first
     std::stable_sort(tiles.begin(), tiles.end(),
                      [&](const Tile& a, const Tile& b) { return cfgs[a.cfg].nb > cfgs[b.cfg].nb; });
+    for (int t = 0; t < (int)tiles.size(); ++t)
+        if (tiles[t].nw > 0)
+            for (int b0 = 0; b0 < cfgs[tiles[t].cfg].nb; b0 += 64) sh.items.push_back(EdgeItem{t, b0});
     size_t lds = pc.lds_bytes ? pc.lds_bytes : RING_BYTES_DEFAULT;
     lds = std::min<size_t>(std::max<size_t>(lds, 1024), ctx->lds_max) & ~(size_t)255;
-    lds_solve = lds;
-    lds_prep = 0;
+    sh.lds_solve = lds;
+    sh.lds_prep = 0;
     // one grid for every phase kernel: as many wavefronts as the tightest phase keeps resident
     int per_cu = 1 << 20;
     for (const void* k : k_phases) {
         int n = 0;
-        CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64, lds_solve));
+        CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64, lds));
         per_cu = std::min(per_cu, std::max(1, n));
     }
     if (pc.wg_per_cu > 0) per_cu = std::min(per_cu, pc.wg_per_cu);
-    grid_solve = std::max(1, std::min((int)tiles.size(), per_cu * ctx->n_cu));
+    sh.grid_solve = std::max(1, std::min((int)tiles.size(), per_cu * ctx->n_cu));
+    int pe = 1;
+    CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pe, (const void*)ompd_k_edge0, 64, 0));
+    sh.grid_edge = std::max(1, std::min((int)sh.items.size(), std::max(1, pe) * ctx->n_cu));
     return OMPD_OK;
 }
 
@@ -324,21 +337,25 @@ int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32
 int ompd_plan_retile(ompd_plan* p, const PlanConfig& pc)
 {
     ompd_ctx* ctx = p->ctx;
-    std::vector<Tile> tiles;
-    size_t lds_solve = 0, lds_prep = 0;
-    int grid = 1;
-    int rc = ompd_make_plan_tiles(ctx, p->h_cfgs, pc, tiles, lds_solve, lds_prep, grid);
+    Shape sh;
+    int rc = ompd_make_shape(ctx, p->h_cfgs, pc, sh);
     if (rc) return rc;
     p->cfg = pc;
-    p->lds_solve = lds_solve;
-    p->lds_prep = lds_prep;
-    p->grid_solve = grid;
-    p->h_tiles = tiles;
-    p->n_tiles = (int)tiles.size();
+    p->lds_solve = sh.lds_solve;
+    p->lds_prep = sh.lds_prep;
+    p->grid_solve = sh.grid_solve;
+    p->grid_edge = sh.grid_edge;
+    p->h_tiles = sh.tiles;
+    p->n_tiles = (int)sh.tiles.size();
+    p->n_items = (int)sh.items.size();
     if (p->d_tiles) { (void)hipFree(p->d_tiles); p->d_tiles = nullptr; }
+    if (p->d_items) { (void)hipFree(p->d_items); p->d_items = nullptr; }
     CK(hipMalloc(&p->d_tiles, sizeof(Tile) * std::max(p->n_tiles, 1)));
+    CK(hipMalloc(&p->d_items, sizeof(EdgeItem) * std::max(p->n_items, 1)));
     if (p->n_tiles)
-        CK(hipMemcpy(p->d_tiles, tiles.data(), sizeof(Tile) * p->n_tiles, hipMemcpyHostToDevice));
+        CK(hipMemcpy(p->d_tiles, sh.tiles.data(), sizeof(Tile) * p->n_tiles, hipMemcpyHostToDevice));
+    if (p->n_items)
+        CK(hipMemcpy(p->d_items, sh.items.data(), sizeof(EdgeItem) * p->n_items, hipMemcpyHostToDevice));
     drop_graphs(p);
     return OMPD_OK;
 }
@@ -354,14 +371,28 @@ int ompd_launch_prep(const DevCfg* d_cfgs, int n, int32_t* d_counter, size_t lds
     return OMPD_OK;
 }
 
-int ompd_launch_solve(const DevCfg* d_cfgs, const Tile* d_tiles, int n_tiles, int32_t* d_counter, int grid,
-                      size_t lds, hipStream_t s)
+int ompd_launch_solve(const DevCfg* d_cfgs, const Tile* d_tiles, int n_tiles, const EdgeItem* d_items, int n_items,
+                      int32_t* d_counter, int grid, int grid_edge, size_t lds, hipStream_t s, hipEvent_t* after)
 {
     if (n_tiles <= 0) return OMPD_OK;
-    void (*ks[5])(const DevCfg*, const Tile*, int, int32_t*, int) = {ompd_k_nu, ompd_k_ave, ompd_k_mayp,
-                                                                      ompd_k_later, ompd_k_avf};
-    for (auto k : ks)
-        hipLaunchKernelGGL(k, dim3(grid), dim3(64), lds, s, d_cfgs, d_tiles, n_tiles, d_counter, (int)(lds / 8));
+    const int rw = (int)(lds / 8);
+    auto mark = [&](int k) { if (after) (void)hipEventRecord(after[k], s); };
+    hipLaunchKernelGGL(ompd_k_nu, dim3(grid), dim3(64), lds, s, d_cfgs, d_tiles, n_tiles, d_counter, rw);
+    mark(0);
+    hipLaunchKernelGGL(ompd_k_ave, dim3(grid), dim3(64), lds, s, d_cfgs, d_tiles, n_tiles, d_counter, rw);
+    mark(1);
+    if (n_items > 0)
+        hipLaunchKernelGGL(ompd_k_edge0, dim3(grid_edge), dim3(64), 0, s, d_cfgs, d_tiles, d_items, n_items, d_counter);
+    mark(2);
+    hipLaunchKernelGGL(ompd_k_mayp, dim3(grid), dim3(64), lds, s, d_cfgs, d_tiles, n_tiles, d_counter, rw);
+    mark(3);
+    if (n_items > 0)
+        hipLaunchKernelGGL(ompd_k_edge1, dim3(grid_edge), dim3(64), 0, s, d_cfgs, d_tiles, d_items, n_items, d_counter);
+    mark(4);
+    hipLaunchKernelGGL(ompd_k_later, dim3(grid), dim3(64), lds, s, d_cfgs, d_tiles, n_tiles, d_counter, rw);
+    mark(5);
+    hipLaunchKernelGGL(ompd_k_avf, dim3(grid), dim3(64), lds, s, d_cfgs, d_tiles, n_tiles, d_counter, rw);
+    mark(6);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return ompd_fail(OMPD_E_DEVICE, std::string("solve launch (grid ") + std::to_string(grid) + ", lds " +
@@ -376,8 +407,9 @@ static int launch_prep(ompd_plan* p, hipStream_t s)
 
 static int launch_solve(ompd_plan* p, hipStream_t s)
 {
-    return ompd_launch_solve((const DevCfg*)p->d_cfgs, (const Tile*)p->d_tiles, p->n_tiles, p->d_counter,
-                             p->grid_solve, p->lds_solve, s);
+    return ompd_launch_solve((const DevCfg*)p->d_cfgs, (const Tile*)p->d_tiles, p->n_tiles,
+                             (const EdgeItem*)p->d_items, p->n_items, p->d_counter, p->grid_solve, p->grid_edge,
+                             p->lds_solve, s);
 }
 
 // Capture one launch function into an executable graph (nullptr if capture
@@ -430,6 +462,18 @@ static int launch_all(ompd_plan* p, hipStream_t s)
         }
     }
     CK(hipEventRecord(p->ev0, s));
+    if (p->profile) {
+        // direct launches with an event after every kernel, all on the caller's stream
+        int rc = launch_prep(p, s);
+        if (rc) return rc;
+        CK(hipEventRecord(p->ev1, s));
+        rc = ompd_launch_solve((const DevCfg*)p->d_cfgs, (const Tile*)p->d_tiles, p->n_tiles,
+                               (const EdgeItem*)p->d_items, p->n_items, p->d_counter, p->grid_solve, p->grid_edge,
+                               p->lds_solve, s, p->evk);
+        if (rc) return rc;
+        CK(hipEventRecord(p->ev2, s));
+        return OMPD_OK;
+    }
     if (p->cfg.use_graph) CK(hipGraphLaunch(p->gx_prep, s));
     else { int rc = launch_prep(p, s); if (rc) return rc; }
     CK(hipEventRecord(p->ev1, s));
@@ -509,6 +553,32 @@ extern "C" int ompd_plan_last_ms(ompd_plan* p, float* total_ms, float* solve_ms)
     return OMPD_OK;
 }
 
+extern "C" int ompd_plan_profile(ompd_plan* p, int32_t enable)
+{
+    if (!p) return ompd_fail(OMPD_E_INVAL, "plan is NULL");
+    std::lock_guard<std::mutex> lk(p->ctx->mu);
+    if (enable && !p->evk[0])
+        for (hipEvent_t& e : p->evk) CK(hipEventCreate(&e));
+    p->profile = enable != 0;
+    return OMPD_OK;
+}
+
+extern "C" int ompd_plan_kernel_ms(ompd_plan* p, float* ms, int32_t capacity, int32_t* n_kernels)
+{
+    if (!p || !ms) return ompd_fail(OMPD_E_INVAL, "bad arguments");
+    if (!p->profile) return ompd_fail(OMPD_E_INVAL, "profiling is off for this plan");
+    CK(hipEventSynchronize(p->ev2));
+    const int n = 8;
+    if (n_kernels) *n_kernels = n;
+    hipEvent_t marks[9] = {p->ev0, p->ev1, p->evk[0], p->evk[1], p->evk[2], p->evk[3], p->evk[4], p->evk[5], p->evk[6]};
+    for (int k = 0; k < n && k < capacity; ++k) {
+        float x = 0;
+        CK(hipEventElapsedTime(&x, marks[k], marks[k + 1]));
+        ms[k] = x;
+    }
+    return OMPD_OK;
+}
+
 extern "C" int ompd_plan_configure(ompd_plan* p, int64_t lds_bytes, int32_t wg_per_cu)
 {
     if (!p || lds_bytes < 0 || wg_per_cu < 0) return ompd_fail(OMPD_E_INVAL, "bad plan configuration");
@@ -540,11 +610,14 @@ extern "C" void ompd_plan_destroy(ompd_plan* p)
     if (p->last_stream || p->gx_prep) (void)hipDeviceSynchronize();
     drop_graphs(p);
     if (p->d_tiles) (void)hipFree(p->d_tiles);
+    if (p->d_items) (void)hipFree(p->d_items);
     if (p->d_cfgs) (void)hipFree(p->d_cfgs);
     if (p->scratch) (void)hipFree(p->scratch);
     if (p->ev0) (void)hipEventDestroy(p->ev0);
     if (p->ev1) (void)hipEventDestroy(p->ev1);
     if (p->ev2) (void)hipEventDestroy(p->ev2);
+    for (hipEvent_t e : p->evk)
+        if (e) (void)hipEventDestroy(e);
     delete p;
 }
 

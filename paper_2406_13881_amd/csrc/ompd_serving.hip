@@ -170,12 +170,13 @@ static void launcher_main(ServingState* S)
                              nullptr);
         }
         PlanConfig pc;
-        std::vector<Tile> tiles;
-        size_t lds_solve = 0, lds_prep = 0;
-        int grid = 1;
-        int rc = ompd_make_plan_tiles(S->ctx, h, pc, tiles, lds_solve, lds_prep, grid);
+        Shape sh;
+        int rc = ompd_make_shape(S->ctx, h, pc, sh);
+        const std::vector<Tile>& tiles = sh.tiles;
         size_t cfg_bytes = a256(sizeof(DevCfg) * k), tile_bytes = a256(sizeof(Tile) * std::max<size_t>(tiles.size(), 1));
+        size_t item_bytes = a256(sizeof(EdgeItem) * std::max<size_t>(sh.items.size(), 1));
         size_t info_bytes = a256(4 * INFO_WORDS * (size_t)k);
+        tile_bytes += item_bytes;   // tiles, then the edge-step items
         st->tab_bytes = cfg_bytes + tile_bytes + 256;
         st->pin_bytes = cfg_bytes + tile_bytes + info_bytes;
         bool ok_mem = (rc == OMPD_OK) && S->dev.alloc(st->tab_bytes, st->tab_off);
@@ -200,6 +201,8 @@ static void launcher_main(ServingState* S)
             char* pin = S->pin_base + st->pin_off;
             memcpy(pin, h.data(), sizeof(DevCfg) * k);
             if (!tiles.empty()) memcpy(pin + cfg_bytes, tiles.data(), sizeof(Tile) * tiles.size());
+            if (!sh.items.empty())
+                memcpy(pin + cfg_bytes + (tile_bytes - item_bytes), sh.items.data(), sizeof(EdgeItem) * sh.items.size());
             char* dtab = S->dev_base + st->tab_off;
             hipStream_t s = st->stream;
             hipError_t e = hipSuccess;
@@ -211,10 +214,11 @@ static void launcher_main(ServingState* S)
                 e = hipMemcpyAsync(dtab, pin, cfg_bytes + tile_bytes, hipMemcpyHostToDevice, s);
             int32_t* counter = (int32_t*)(dtab + cfg_bytes + tile_bytes);
             if (e != hipSuccess) rc = OMPD_E_DEVICE;
-            if (rc == OMPD_OK) rc = ompd_launch_prep((const DevCfg*)dtab, k, counter, lds_prep, s);
+            if (rc == OMPD_OK) rc = ompd_launch_prep((const DevCfg*)dtab, k, counter, sh.lds_prep, s);
             if (rc == OMPD_OK)
                 rc = ompd_launch_solve((const DevCfg*)dtab, (const Tile*)(dtab + cfg_bytes), (int)tiles.size(),
-                                       counter, grid, lds_solve, s);
+                                       (const EdgeItem*)(dtab + cfg_bytes + (tile_bytes - item_bytes)),
+                                       (int)sh.items.size(), counter, sh.grid_solve, sh.grid_edge, sh.lds_solve, s);
             // per-request status words back to pinned memory
             st->info_pin_off = st->pin_off + cfg_bytes + tile_bytes;
             for (int i = 0; i < k && rc == OMPD_OK; ++i)

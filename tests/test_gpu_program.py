@@ -1,0 +1,103 @@
+"""GPU parity of the interprocedural solve (ompd_analyze_program): every
+context's outputs, every context boundary, every procedure summary and every
+call site's host-read demand equal the oracle driver's, bit for bit, on
+non-recursive, recursive and external-call programs and on a C4-shaped
+program of 300 procedures.  At the full C4 size (2,000 procedures) the
+oracle would take minutes, so the device result is checked with
+whole-program random walks (no stale read or copy source), which hold for
+any size."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from checkers import simulate_program
+from oracle.program import ProgramOracle
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("nu_h", "nu_d", "ave_h", "ave_d", "avf_h", "avf_d", "ins_entry_h", "ins_entry_d",
+        "ins_edge_h", "ins_edge_d", "var_kind", "after_dev", "before_dev")
+
+
+def _print(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2406_13881_amd as ompd
+    c = ompd.Context(0)
+    yield c
+    c.close()
+
+
+def compare(prog, got, tag):
+    po = ProgramOracle(prog)
+    S, ctxb, results = po.analyze()
+    gw = (prog.n_globals + 63) // 64
+    keys = got["contexts"]
+    assert sorted(keys) == sorted(results.keys()), "%s: context sets differ" % tag
+    for k, key in enumerate(keys):
+        ref, mine = results[key], got["results"][k]
+        for name in KEYS:
+            a = np.asarray(mine[name])
+            b = np.asarray(ref[name]).reshape(a.shape)
+            assert np.array_equal(a, b), "%s: context %s output %s differs" % (tag, key, name)
+        for i in range(4):
+            assert np.array_equal(got["boundaries"][k][i], np.asarray(ctxb[key][i])), \
+                "%s: context %s boundary %d differs" % (tag, key, i)
+    for p in range(len(prog.procs)):
+        assert np.array_equal(got["summaries"][p], S[p]), "%s: summary of procedure %d differs" % (tag, p)
+    for j in range(len(prog.call_proc)):
+        want = po.demand[j][:gw] if j in po.demand else np.zeros(gw, np.uint64)
+        assert np.array_equal(got["demands"][j], want), "%s: demand of call site %d differs" % (tag, j)
+    return po
+
+
+SMALL = dict(n_procs=6, n_globals=12, n_locals=5, blocks=(4, 14), mean_calls=2.0, max_calls=3, scc_procs=0,
+             max_loop_depth=2, device_frac=0.4, p_read=0.25, p_write=0.15, threads=1)
+
+
+@pytest.mark.parametrize("kind", ["plain", "recursive", "external"])
+def test_program_small(ctx, kind):
+    extra = {"plain": {}, "recursive": dict(scc_procs=4, scc_size=(2, 3), mean_calls=1.0),
+             "external": dict(n_procs=8, scc_procs=5, scc_size=(2, 3), external_frac=0.3)}[kind]
+    for seed in range(6):
+        prm = dict(SMALL)
+        prm.update(extra)
+        prog = synth.program(31_000 + 100 * len(kind) + seed, **prm)
+        _print("program %s seed %d: %d procs %d calls" % (kind, seed, len(prog.procs), len(prog.call_proc)))
+        got = ctx.analyze_program(prog)
+        compare(prog, got, "%s/%d" % (kind, seed))
+
+
+def test_program_multiword_globals(ctx):
+    # globals spanning words, locals sharing the last global word
+    prog = synth.program(4_711, n_procs=10, n_globals=100, n_locals=40, blocks=(6, 30), mean_calls=1.5,
+                         max_calls=3, scc_procs=4, scc_size=(2, 2), external_frac=0.2, threads=1)
+    got = ctx.analyze_program(prog)
+    compare(prog, got, "multiword")
+
+
+def test_program_c4_shape(ctx):
+    prog = synth.c4(n_procs=300)
+    _print("c4-shaped: %d procs %d calls %d blocks" % (len(prog.procs), len(prog.call_proc),
+                                                        sum(c.n_blocks for c in prog.procs)))
+    got = ctx.analyze_program(prog)
+    _print("device: %d contexts, %d rounds, %d solves" % (len(got["contexts"]), got["rounds"], got["solves"]))
+    compare(prog, got, "c4-300")
+
+
+def test_program_c4_full_walks(ctx):
+    prog = synth.c4()
+    _print("c4: %d procs %d calls" % (len(prog.procs), len(prog.call_proc)))
+    got = ctx.analyze_program(prog)
+    _print("device: %d contexts, %d rounds, %d solves" % (len(got["contexts"]), got["rounds"], got["solves"]))
+    results = {key: got["results"][k] for k, key in enumerate(got["contexts"])}
+    demands = {j: got["demands"][j] for j in range(len(prog.call_proc)) if got["demands"][j].any()}
+    errs, cut = simulate_program(prog, None, results, demands, walks=200, seed=7, max_steps=6000)
+    assert not errs, errs[:5]
+    assert cut < 200
