@@ -133,6 +133,25 @@ def serving(ctx, n_pool, n_cap, n_warm, n_meas, loads):
     return res
 
 
+TRAFFIC = os.path.join(ROOT, "profiles", "hbm_traffic_c3_batch4096.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2406_13881_amd", "csrc", "ompd_kernels.hip")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    record (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC))
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != sha or kernel not in rec.get("per_launch", {}):
+        return None
+    return rec["per_launch"][kernel]["total_bytes"]
+
+
 def kernel_bytes(cfgs):
     """Algorithmic bytes of each kernel per launch over the batch: every array
     the kernel must read or write, once (bv = a block vector, ev = an edge
@@ -195,6 +214,9 @@ def main():
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES of device memory (a device-to-device copy of known size, "
+                         "to calibrate the HBM byte counters of a profiler) and exit")
     ap.add_argument("--serve-requests", type=int, default=300, help="measured requests per offered load")
     ap.add_argument("--serve-warmup", type=int, default=50)
     args = ap.parse_args()
@@ -205,6 +227,15 @@ def main():
 
     import numpy as np
     import torch
+    if args.copy_calibration:
+        n = args.copy_calibration // 8
+        x = torch.ones(n, dtype=torch.int64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("copied %d bytes" % (8 * n))
+        return
     import synth
     import paper_2406_13881_amd as ompd
     from paper_2406_13881_amd.resident import ResidentBatch
@@ -266,7 +297,7 @@ def main():
     achieved = kb[dom] / (kms[dom] * 1e-3) / 1e9
     path_bytes = algorithmic_bytes(cfgs, want)
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": measured_traffic(dom),
                 "kernel": dom, "kernel_ms": round(kms[dom], 4), "algorithmic_bytes_per_launch": kb[dom],
                 "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
                 "path_algorithmic_bytes": path_bytes,
