@@ -157,20 +157,24 @@ def kernel_bytes(cfgs):
     the kernel must read or write, once (bv = a block vector, ev = an edge
     vector, both in the stored 64-bit word layout).  Iteration traffic (state
     rows revisited by later sweeps) is not algorithmic."""
-    out = dict.fromkeys(("ompd_k_prep", "ompd_k_nu", "ompd_k_ave", "ompd_k_edge0", "ompd_k_mayp",
-                         "ompd_k_edge1", "ompd_k_later", "ompd_k_avf"), 0)
+    out = dict.fromkeys(("ompd_k_prep", "ompd_k_nu", "ompd_k_ave", "ompd_k_post_ave", "ompd_k_mayp",
+                         "ompd_k_post_mayp", "ompd_k_later", "ompd_k_post_later", "ompd_k_avf",
+                         "ompd_k_post_avf", "ompd_k_varkind"), 0)
     for c in cfgs:
         wd = (c.n_vars + 63) // 64
         nb, ne = c.n_blocks, c.n_edges
         bv, ev = nb * wd * 8, ne * wd * 8
         out["ompd_k_prep"] += 4 * (nb + 1) + 5 * ne + nb + 4 * (nb + 1) + 8 * ne + 64 * nb
         out["ompd_k_nu"] += 2 * bv + 2 * bv                    # R, W in; next use H/D out
-        out["ompd_k_ave"] += 3 * bv + 2 * bv + 2 * nb          # NU H/D, W in; validity H/D, labels out
-        out["ompd_k_edge0"] += 4 * bv + 4 * ev                 # NU, eager validity in; EAG, valid-after-edge out
+        out["ompd_k_ave"] += 3 * bv + 2 * bv + 2 * nb          # NU H/D, W in; validity after each block H/D, labels out
+        out["ompd_k_post_ave"] += 4 * bv + 2 * bv + 4 * ev     # NU, validity after in; validity before, EAG, valid-after-edge out
         out["ompd_k_mayp"] += 2 * bv + 2 * ev + 2 * bv         # R, W, EAG in; pending H/D out
-        out["ompd_k_edge1"] += 4 * ev + 2 * bv + ev            # EAG, valid-after-edge, pending in; both-valid out
-        out["ompd_k_later"] += 2 * bv + 3 * ev + 2 * bv + 2 * ev   # R, W, EAG, both in; copies (entry, edge) out
-        out["ompd_k_avf"] += 3 * bv + 2 * ev + 2 * bv + c.n_vars    # copies, W in; final validity, map kinds out
+        out["ompd_k_post_mayp"] += 4 * ev + 2 * bv + ev        # EAG, valid-after-edge, pending in; both-valid out
+        out["ompd_k_later"] += 2 * bv + 3 * ev + 2 * bv        # R, W, EAG, both in; delayed H/D out
+        out["ompd_k_post_later"] += 3 * ev + 3 * bv + 2 * bv + 2 * ev   # EAG, both, delayed, R in; copies out
+        out["ompd_k_avf"] += 3 * bv + 2 * ev + 2 * bv          # copies before blocks, W, copies on edges in; validity after out
+        out["ompd_k_post_avf"] += 2 * bv + 2 * ev + 4 * bv + 2 * bv + 3 * wd * 8   # copies, validity after, R, W in; validity before, map masks out
+        out["ompd_k_varkind"] += 3 * wd * 8 + c.n_vars         # map masks in; map kinds out
     return out
 
 

@@ -181,16 +181,19 @@ int ompd_plan_status(ompd_plan* plan, int32_t* per_cfg);
  * be NULL. */
 int ompd_plan_autotune(ompd_plan* plan, void* stream, int32_t trials, float* best_ms);
 /* Set the launch configuration by hand (what the autotuner chooses among):
- * LDS bytes per solve wavefront for the ring of recently solved blocks
- * (0 = default, 8 KiB; clamped to [1 KiB, the device limit]) and solve
- * wavefronts per CU (0 = as many as fit). */
+ * LDS bytes per solve workgroup for the ring of recently solved blocks
+ * (1 KiB per block; 0 = default, 16 KiB; rounded down to a power of two
+ * of KiB within [8 KiB, 64 KiB] and to what the device's LDS holds) and
+ * solve workgroups per CU (0 = as many as fit). */
 int ompd_plan_configure(ompd_plan* plan, int64_t lds_bytes, int32_t wg_per_cu);
 /* Profiling: with enable != 0, ompd_plan_run launches the kernels directly
  * (no graph) and records a HIP event after each on the caller's stream;
  * ompd_plan_kernel_ms then gives the duration (ms) of each kernel of the
- * last run, in launch order: ingest, next use, validity, edge step 1,
- * pending copies, edge step 2, delayed placement, final validity
- * (*n_kernels = 8; at most `capacity` are written).  OMPD_E_INVAL if
+ * last run, in launch order: ingest, next use, validity, validity pass
+ * (AVEin, eager copies), pending copies, pending pass (valid in both
+ * spaces), delayed placement, placement pass (the copies), final
+ * validity, final pass (AVFin, map-kind masks), map kinds
+ * (*n_kernels = 11; at most `capacity` are written).  OMPD_E_INVAL if
  * profiling is off. */
 int ompd_plan_profile(ompd_plan* plan, int32_t enable);
 int ompd_plan_kernel_ms(ompd_plan* plan, float* ms, int32_t capacity, int32_t* n_kernels);

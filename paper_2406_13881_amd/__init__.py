@@ -506,8 +506,8 @@ class Plan:
         """LDS ring bytes per solve wavefront (0 = default) and wavefronts per CU (0 = as many as fit)."""
         _check(lib().ompd_plan_configure(self.h, int(lds_bytes), int(wg_per_cu)))
 
-    KERNELS = ("ompd_k_prep", "ompd_k_nu", "ompd_k_ave", "ompd_k_edge0", "ompd_k_mayp", "ompd_k_edge1",
-               "ompd_k_later", "ompd_k_avf")
+    KERNELS = ("ompd_k_prep", "ompd_k_nu", "ompd_k_ave", "ompd_k_post_ave", "ompd_k_mayp", "ompd_k_post_mayp",
+               "ompd_k_later", "ompd_k_post_later", "ompd_k_avf", "ompd_k_post_avf", "ompd_k_varkind")
 
     def profile(self, enable: bool = True):
         """Time every kernel of the following runs with HIP events on their stream."""
@@ -515,9 +515,9 @@ class Plan:
 
     def kernel_ms(self) -> Dict[str, float]:
         """Per-kernel durations (ms) of the last profiled run."""
-        buf = (ctypes.c_float * 8)()
+        buf = (ctypes.c_float * 16)()
         n = _i32(0)
-        _check(lib().ompd_plan_kernel_ms(self.h, buf, 8, ctypes.byref(n)))
+        _check(lib().ompd_plan_kernel_ms(self.h, buf, 16, ctypes.byref(n)))
         return {k: float(buf[i]) for i, k in enumerate(self.KERNELS[:n.value])}
 
     def describe(self) -> str:

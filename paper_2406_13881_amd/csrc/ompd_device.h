@@ -1,6 +1,7 @@
 // Device-side descriptors shared by the HIP kernels and the host runtime of
 // libompd (internal; the public interface is include/ompd.h).
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 namespace ompd {
@@ -53,6 +54,7 @@ struct DevCfg {
     uint64_t* eag_h;    uint64_t* eag_d;      // per edge: eager copies
     uint64_t* both;     // per edge: valid in both spaces under the final placement
     uint64_t* flg;      // per tile: [4][nb] words of the flag lane
+    uint64_t* vk_acc;   // [3][wd] map-kind masks (to, from, used on the device); NULL = no map kinds
     int32_t* pred_ptr;  int32_t* pred_idx; int32_t* pred_eid;
     int32_t* tmp;
     int32_t* rec_f;     // [2*nb] int4: block records with predecessors, in block-id order
@@ -65,7 +67,8 @@ constexpr uint32_t REC_COUNT = 0x00FFFFFFu;
 constexpr uint32_t REC_ENTRY = 1u << 24, REC_EXIT = 1u << 25, REC_DEV = 1u << 26, REC_CALL = 1u << 27;
 
 // A tile: one CFG and a run of its 64-bit variable words, solved by one
-// wavefront (one lane per word plus the flag lane).
+// workgroup (a compute wavefront with one lane per word plus the flag
+// lane, and a helper wavefront that stores its results).
 constexpr int TILE_WORDS = 63;
 struct Tile {
     int32_t cfg;
@@ -74,8 +77,8 @@ struct Tile {
     int32_t fslot;   // index of the tile within its CFG (flag-lane storage)
 };
 
-// Work item of the edge-parallel steps: a tile and the first block of a
-// 64-block chunk of it.
+// Work item of the pass kernels: a tile and the first block of a 64-block
+// chunk of it.
 struct EdgeItem {
     int32_t tile;
     int32_t b0;
@@ -84,5 +87,20 @@ struct EdgeItem {
 // Tiles of a CFG with wd words: ceil(wd / TILE_WORDS) (at least one), the
 // words split as evenly as possible.
 inline int tiles_of(int wd) { return wd <= 0 ? 1 : (wd + TILE_WORDS - 1) / TILE_WORDS; }
+
+// LDS of a phase workgroup: CTL_BYTES of coordination words, the ring of the
+// next REC_RING block records (32 bytes each), the ring of the last RS
+// results (1 KiB each), then the inputs of the next IN_RING steps
+// (phase_inputs(ph) words of 512 bytes each).
+constexpr int CTL_BYTES = 256;
+constexpr int REC_RING = 128;
+constexpr int IN_RING = 8;
+constexpr int LDS_FIXED = CTL_BYTES + 32 * REC_RING;
+inline int phase_inputs(int ph) { return 2 + (ph == PH_NU ? 2 : ph == PH_AVE ? 3 : ph == PH_MAYP ? 6 : ph == PH_LATER ? 8 : 7); }
+inline size_t phase_lds(int ph, int ring_slots) { return LDS_FIXED + (size_t)ring_slots * 1024 + (size_t)IN_RING * phase_inputs(ph) * 512; }
+// Work counters (int32) of one solve launch: phases 0..4, passes 8..11, map kinds 12.
+constexpr int N_COUNTERS = 16;
+// Kernels of one solve launch, in launch order (prep excluded).
+constexpr int N_SOLVE_KERNELS = 10;
 
 }  // namespace ompd

@@ -25,10 +25,19 @@ struct ompd_ctx {
     std::mutex srv_mu;
 };
 
+// Launch sizes of one solve: slots of the result ring, each phase kernel's
+// LDS bytes and grid, and the grid of the pass kernels.
+struct LaunchDims {
+    int ring_slots = 16;
+    size_t lds[5] = {0, 0, 0, 0, 0};
+    int grid[5] = {1, 1, 1, 1, 1};
+    int grid_edge = 1;
+};
+
 // Tunable launch configuration of a plan; results never depend on it.
 struct PlanConfig {
-    size_t lds_bytes = 0;   // LDS ring of recent blocks per solve wavefront (0 = default)
-    int wg_per_cu = 0;      // solve wavefronts per CU (0 = as many as fit)
+    size_t lds_bytes = 0;   // bytes of the result ring per phase workgroup (0 = default)
+    int wg_per_cu = 0;      // phase workgroups per CU (0 = as many as fit)
     bool use_graph = true;  // replay a captured HIP graph
 };
 
@@ -46,25 +55,24 @@ struct ompd_plan {
     int n_tiles = 0;
     ompd::EdgeItem* d_items = nullptr;
     int n_items = 0;
-    int grid_edge = 1;
     int32_t* d_counter = nullptr;
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
     int max_nb = 2;
-    size_t lds_solve = 0, lds_prep = 0;
-    int grid_solve = 1;
+    LaunchDims dims;
+    size_t lds_prep = 0;
     hipGraph_t g_prep = nullptr, g_solve = nullptr;
     hipGraphExec_t gx_prep = nullptr, gx_solve = nullptr;
     hipStream_t last_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
     bool profile = false;          // launch directly and time every kernel
-    hipEvent_t evk[7] = {};        // after each solve kernel (profile runs)
+    hipEvent_t evk[ompd::N_SOLVE_KERNELS] = {};   // after each solve kernel (profile runs)
 };
 
 int ompd_fail(int code, const std::string& msg);
 
 struct ScratchOff {
-    size_t aveout, mayp, later, flg, eag, both, nu, ave, ie, ig, avf, bnd, pp, pi, pe, tmp, recf, recb, info;
+    size_t aveout, mayp, later, flg, eag, both, nu, ave, ie, ig, avf, vk, bnd, pp, pi, pe, tmp, recf, recb, info;
 };
 size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o);
 void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const ScratchOff& o, uint32_t flags,
@@ -73,13 +81,13 @@ void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const
 struct Shape {
     std::vector<ompd::Tile> tiles;
     std::vector<ompd::EdgeItem> items;
-    size_t lds_solve = 0, lds_prep = 0;
-    int grid_solve = 1, grid_edge = 1;
+    LaunchDims dims;
+    size_t lds_prep = 0;
 };
 int ompd_make_shape(ompd_ctx* ctx, const std::vector<ompd::DevCfg>& cfgs, const PlanConfig& pc, Shape& sh);
 int ompd_launch_prep(const ompd::DevCfg* d_cfgs, int n, int32_t* d_counter, size_t lds, hipStream_t s);
 int ompd_launch_solve(const ompd::DevCfg* d_cfgs, const ompd::Tile* d_tiles, int n_tiles, const ompd::EdgeItem* d_items,
-                      int n_items, int32_t* d_counter, int grid, int grid_edge, size_t lds, hipStream_t s,
+                      int n_items, int32_t* d_counter, const LaunchDims& dims, hipStream_t s,
                       hipEvent_t* after = nullptr);
 int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n, uint32_t flags,
                     const PlanConfig& pc, ompd_plan** out);

@@ -1,19 +1,26 @@
 // HIP kernels (gfx950) for the OMPDart data-flow solve.
 //
-// ompd_k_prep  (one 256-thread workgroup per CFG): ingest and normalise --
+// ompd_k_prep (one 256-thread workgroup per CFG): ingest and normalise --
 //   validates the CSR and the boundary rules, builds the predecessor CSR
 //   (with the successor-edge id of every predecessor link) and writes one
 //   32-byte record per block for each direction (flags, first two
 //   neighbours with their edge ids, CSR start of the rest, call index).
 //
-// ompd_k_solve (persistent, one wavefront per tile): a tile is one CFG and a
-//   run of up to 63 64-bit words of its variables.  The tile runs every
-//   phase of the method on its variables:
-//     next use (backward may), validity with eager copies (forward must),
-//     pending copies (forward may), delayed placement (forward AND/OR) and
-//     its materialisation, validity after placement (forward must), the
-//     reachability facts behind the map/update labels, and the per-variable
-//     map kind (Table II).
+// Phase kernels (persistent, two wavefronts per tile): a tile is one CFG
+//   and a run of up to 63 64-bit words of its variables.  One kernel per
+//   iterated problem of the method, in this order:
+//     ompd_k_nu     next use (backward may)
+//     ompd_k_ave    validity with eager copies (forward must) and the
+//                   reachability facts behind the map/update labels
+//     ompd_k_mayp   pending copies (forward may)
+//     ompd_k_later  delayed placement (forward AND/OR)
+//     ompd_k_avf    validity after placement (forward must)
+// Pass kernels (one wavefront per 64-block chunk of a tile, no iteration)
+//   write what follows from a fixed point: ompd_k_post_ave (AVEin, eager
+//   copies per edge), ompd_k_post_mayp (valid in both spaces per edge),
+//   ompd_k_post_later (the copies themselves), ompd_k_post_avf (AVFin and
+//   the map-kind masks); ompd_k_varkind turns the masks into the
+//   per-variable map kind (Table II).
 //
 // All arithmetic is integer AND / OR / ANDN; variables never interact, so
 // any split of the variable axis is exact.
@@ -22,6 +29,7 @@
 #include "ompd_device.h"
 
 #define OMPD_E_INVAL_ (-1)
+#define OMPD_E_DEVICE_ (-3)
 #define OMPD_E_NOCONVERGE_ (-4)
 
 namespace ompd {
@@ -76,13 +84,15 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
     __shared__ int s_err;
     __shared__ int32_t s_scan[16];
     const int ci = blockIdx.x;
-    if (ci == 0 && threadIdx.x < 8) solve_counter[threadIdx.x] = 0;   // one tile counter per phase
+    if (ci == 0 && threadIdx.x < 16) solve_counter[threadIdx.x] = 0;   // work counters of the solve kernels
     if (ci >= n_cfgs) return;
     const DevCfg c = cfgs[ci];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int nb = c.nb, ne = c.ne, wd = c.wd;
     if (tid == 0) s_err = 0;
     for (int i = tid; i < INFO_WORDS; i += nt) c.info[i] = 0;
+    if (c.var_kind)
+        for (int i = tid; i < 3 * wd; i += nt) c.vk_acc[i] = 0;
     __syncthreads();
 
     // validation, stage 1: pointers, kinds, spaces
@@ -192,31 +202,31 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
 // --------------------------------------------------------------------------
 // solve
 // --------------------------------------------------------------------------
-// One wavefront solves one tile: a CFG and a run of up to 63 consecutive
-// 64-bit words of its variable axis.  Lane l owns word s0 + l of every row;
-// in the two phases that compute the CFG's reachability facts, lane nw (the
-// flag lane) carries them as a pseudo-variable word whose inputs are
-// synthesised so that the same equations compute them:
+// One workgroup of two wavefronts solves one tile: a CFG and a run of up to
+// 63 consecutive 64-bit words of its variable axis.  Lane l owns word s0 + l
+// of every row; in the two phases that compute the CFG's reachability facts,
+// lane nw (the flag lane) carries them as a pseudo-variable word whose inputs
+// are synthesised so that the same equations compute them:
 //   next use, host channel, bit 0 : the block reaches EXIT
 //   next use, device channel, bit 1: a DEVICE block is reachable from here
 //   eager validity, host channel, bit 0: the block is NOT reached from ENTRY
 //   eager validity, host channel, bit 1: no DEVICE block reaches the block
-// The CFG structure is the same for every lane, so the walk over blocks is
-// scalar control flow (records and neighbour lists come through the scalar
-// cache) and the lanes only do the bit arithmetic.
+// Lanes past the tile shadow word s0 (same inputs, same results), so the walk
+// has no lane divergence and its block records stay scalar loads.
 //
 // A phase is a sequence of Gauss-Seidel sweeps in block-id order (reverse
-// order for the backward phase).  The value of the block just computed stays
-// in registers, the last RS blocks sit in an LDS ring (read one step ahead),
-// and every other neighbour value comes from the phase's state rows in
-// global memory, which also hold the previous sweep's values of blocks not
-// yet visited.  The global inputs of block b+D are loaded right after block
-// b is computed (D slots of registers), so a step does not wait for memory.
+// order for the backward phase).  The compute wavefront walks the blocks and
+// touches global memory only on rare paths: the value of the block just
+// computed stays in registers, the last RS steps sit in an LDS ring, and the
+// helper wavefront keeps the block records and, IR steps ahead, each step's
+// inputs (including the state of its first other neighbour) ready in LDS;
+// the helper also copies the compute wavefront's results to the state rows.
+// The two meet through counters in LDS.
 // Every phase is monotone on a finite lattice, so any visiting order reaches
 // the same fixed point, and each block's value only moves one way between
-// sweeps: a sweep changed nothing exactly when the popcount of the state
-// is unchanged.  Outputs derived from a phase's state are written on every
-// sweep; the last sweep writes the fixed point.
+// sweeps: a sweep changed nothing exactly when the popcount of the state is
+// unchanged.  Outputs derived from the state are written by edge-parallel
+// passes after the phase (no iteration).
 typedef uint64_t u64;
 #define CAS __attribute__((address_space(4)))
 
@@ -249,14 +259,81 @@ __device__ __forceinline__ u64 tsel(u64 a1, u64 l, u64 t00, u64 t01, u64 t10, u6
 
 __device__ __forceinline__ uint32_t popc2(u64 a, u64 b) { return (uint32_t)(__popcll(a) + __popcll(b)); }
 
+// A state row written by the other wavefront of the workgroup in this kernel:
+// read past the (non-coherent) first-level cache.
+__device__ __forceinline__ u64 ld_fresh(const GAS u64* p)
+{
+    return __hip_atomic_load(const_cast<GAS u64*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A value loaded on a rarely taken path, made ready before the paths join: the
+// compiler then waits for the load on that path only, instead of at the join,
+// where the wait would also drain the loads issued ahead on the common path.
+__device__ __forceinline__ u64 settle(u64 x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// Copy of one 64-bit word per lane from global memory into LDS without
+// registers: lane l's word lands at dst[l] (low half) and dst[64 + l] (high
+// half); dst is wave-uniform.  Completion is counted by vmcnt.
+constexpr unsigned CPOL_SC1 = 16;   // read past the first-level cache
+template <unsigned CPOL>
+__device__ __forceinline__ void dma64(const GAS u64* src, uint32_t* dst)
+{
+    const GAS uint32_t* s32 = reinterpret_cast<const GAS uint32_t*>(src);
+    __builtin_amdgcn_global_load_lds(s32, (__attribute__((address_space(3))) void*)dst, 4, 0, CPOL);
+    __builtin_amdgcn_global_load_lds(s32 + 1, (__attribute__((address_space(3))) void*)(dst + 64), 4, 0, CPOL);
+}
+
+// Coordination of the two wavefronts of a tile (LDS).
+struct Ctl {
+    int tile;        // the tile of this round
+    int skip;        // its CFG already failed
+    int produced;    // steps whose state is in the ring (compute wavefront)
+    int consumed;    // steps the helper has read from the ring
+    int flushed;     // steps whose state-row stores have completed
+    int done;        // the compute wavefront has finished the phase
+    int abort;       // a wait ran out: both wavefronts stop
+    int rec_filled;  // steps whose block record is in the record ring (helper)
+    int in_ready;    // steps whose inputs are in the input ring (helper)
+};
+constexpr int CTL_WORDS = CTL_BYTES / 8;   // u64 words reserved for Ctl at the start of the LDS
+static_assert(sizeof(Ctl) <= CTL_BYTES, "coordination words");
+constexpr int SPIN_MAX = 1 << 23;   // bound of every wait (far above any legitimate one)
+
+__device__ __forceinline__ int lds_get(int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ __forceinline__ void lds_put(int* p, int v)
+{
+    if ((threadIdx.x & 63) == 0) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// LDS accesses before this point complete before LDS writes after it (LDS only: pending
+// global loads are not waited for)
+__device__ __forceinline__ void lds_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local"); }
+// LDS reads after this point are not moved before the counter read that precedes it
+__device__ __forceinline__ void lds_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local"); }
+
+// Wait (bounded) until *p >= target; false if the wait ran out or the other side gave up.
+__device__ __forceinline__ bool wait_for(int* p, int target, int* abort)
+{
+    for (int k = 0; k < SPIN_MAX; ++k) {
+        if (__builtin_amdgcn_readfirstlane(lds_get(p)) >= target) { lds_acquire(); return true; }
+        if (__builtin_amdgcn_readfirstlane(lds_get(abort))) return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    lds_put(abort, 1);
+    return false;
+}
+
 // State rows of the iterated vector of one phase, per lane: data lanes
 // address [nb][wd] rows at their word, the flag lane its own [nb] column.
 struct Rows {
     GAS u64* h;
     GAS u64* d;
     int str;
-    __device__ __forceinline__ u64 ldh(int b) const { return h[(size_t)b * str]; }
-    __device__ __forceinline__ u64 ldd(int b) const { return d[(size_t)b * str]; }
+    __device__ __forceinline__ u64 ldh(int b) const { return ld_fresh(h + (size_t)b * str); }
+    __device__ __forceinline__ u64 ldd(int b) const { return ld_fresh(d + (size_t)b * str); }
     __device__ __forceinline__ void st(int b, u64 x, u64 y) const
     {
         h[(size_t)b * str] = x;
@@ -264,30 +341,24 @@ struct Rows {
     }
 };
 
-// Per-block inputs loaded D steps ahead: phase inputs and the state of at
-// most one far neighbour (more than RS blocks back, or not yet visited).
-template <int NX>
-struct Slot {
-    u64 x[NX];
-    u64 fh, fd;
-};
-
 template <int PH>
-__device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int fslot, u64* ring, int ring_words)
+__device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int fslot, u64* lds, int RS)
 {
     constexpr bool with_flags = PH == PH_NU || PH == PH_AVE;   // phases with the flag lane
     constexpr bool BWD = PH == PH_NU;
-    constexpr int D = (PH == PH_NU || PH == PH_AVE) ? 8 : (PH == PH_MAYP ? 6 : 5);   // load-ahead depth
     constexpr int NX = PH == PH_NU ? 2 : PH == PH_AVE ? 3 : PH == PH_MAYP ? 6 : PH == PH_LATER ? 8 : 7;
-    const int lane = threadIdx.x;
+    constexpr int NI = NX + 2;        // inputs of a step: the phase's own and the first far neighbour (h, d)
+    constexpr int IR = IN_RING;       // steps whose inputs the helper keeps ready
+    const int lane = threadIdx.x & 63;
+    const bool helper = threadIdx.x >= 64;
     const int nb = c.nb, wd = c.wd;
     // a tile without variables (nw = 0) has only flag lanes (they compute the same facts)
     const bool dat = lane < nw, flg = with_flags && (lane == nw || nw == 0), act = dat || flg;
     const int w = s0 + (dat ? lane : 0);
-    // Every lane runs every step (no divergence around the walk, so records stay scalar loads
-    // and waits stay precise): lanes past the tile shadow word s0 and store the same values.
-    int RS = 1;
-    while (RS < 64 && (size_t)4 * RS * 64 <= (size_t)ring_words) RS *= 2;   // slots of 2*64 words
+    Ctl* ctl = reinterpret_cast<Ctl*>(lds);
+    int4* rring = reinterpret_cast<int4*>(lds + CTL_WORDS);   // REC_RING records of 2 int4
+    u64* ring = lds + CTL_WORDS + REC_RING * 4;               // RS steps of results (h, d)
+    u64* iring = ring + (size_t)RS * 128;                     // IR steps of inputs (NI words)
     // valid-variable mask of the lane's word (shadow lanes share word s0's; the flag lane uses bits 0-1)
     const u64 vm = flg ? 3ull : ((w == wd - 1 && (c.nv & 63)) ? ((1ull << (c.nv & 63)) - 1ull) : ~0ull);
     const int cap = c.sweep_cap > 0 ? c.sweep_cap : 2 * nb + 2;
@@ -301,8 +372,10 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // data arrays of a CFG without variables may be empty: loads then read a flag word instead
     auto arr = [&](const u64* a) -> const GAS u64* { return wd ? G(a) : (const GAS u64*)FLG; };
     auto row = [&](const u64* a, int b) -> u64 { return arr(a)[(size_t)b * wd + wo]; };
-    auto vec = [&](const u64* a) -> u64 { return arr(a)[wo]; };
-    auto sum = [&](int ci, int r) -> u64 { return arr(c.sums)[((size_t)ci * SUM_ROWS + r) * wd + wo]; };
+    auto rowp = [&](const u64* a, int b) -> const GAS u64* { return arr(a) + (size_t)b * wd + wo; };
+    // (both only at compute time, on rare paths: ENTRY, EXIT, call blocks)
+    auto vec = [&](const u64* a) -> u64 { return settle(arr(a)[wo]); };
+    auto sum = [&](int ci, int r) -> u64 { return settle(arr(c.sums)[((size_t)ci * SUM_ROWS + r) * wd + wo]); };
     auto rows_of = [&](u64* h, u64* d, int fl) -> Rows {
         Rows r;
         if (flg) { r.h = FLG + (size_t)fl * nb; r.d = FLG + (size_t)(fl + 1) * nb; r.str = 1; }
@@ -310,8 +383,15 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         return r;
     };
     u64* rg = ring + lane;
-    auto ring_h = [&](int b) -> u64& { return rg[(size_t)(b & (RS - 1)) * 128]; };
-    auto ring_d = [&](int b) -> u64& { return rg[(size_t)(b & (RS - 1)) * 128 + 64]; };
+    auto slot_h = [&](int g) -> u64& { return rg[(size_t)(g & (RS - 1)) * 128]; };
+    auto slot_d = [&](int g) -> u64& { return rg[(size_t)(g & (RS - 1)) * 128 + 64]; };
+    // input k of step g: 64 low halves, then 64 high halves
+    uint32_t* iring32 = reinterpret_cast<uint32_t*>(iring);
+    auto in32 = [&](int g, int k) -> uint32_t* { return iring32 + ((size_t)(g & (IR - 1)) * NI + k) * 128; };
+    auto in_get = [&](int g, int k) -> u64 {
+        const uint32_t* q = in32(g, k) + lane;
+        return (u64)q[0] | ((u64)q[64] << 32);
+    };
 
     // neighbour j of a record (j >= 2 from the CSR); edge id with LOOP_ENTRY in bit 31
     auto nbr_f = [&](const Rec& r, int j, int& p, uint32_t& e) {
@@ -326,112 +406,280 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         if (j == 1) return r.n1;
         return SI[r.ovf + j];
     };
-    auto nbr = [&](const Rec& r, int j) -> int {
-        if constexpr (BWD) return nbr_b(r, j);
-        else { int p; uint32_t e; nbr_f(r, j, p, e); return p; }
-    };
     // distance of neighbour p from block b in walk order (1 = the block just before)
     auto dist = [&](int b, int p) -> int { return BWD ? (p - b) : (b - p); };
-    // loaded with the slot (D steps ahead): not yet visited, or visited before both the ring
-    // and the slot window; at compute time 1 = registers, 2..RS = ring (read a step ahead),
-    // RS+1..D = read then
-    const int FARD = RS > D ? RS : D;
-    auto is_far = [&](int d) -> bool { return d <= 0 || d > FARD; };
-    // neighbour state from memory: the previous sweep's row (or the initial value in sweep 0)
-    // for a block not yet visited, this sweep's row for one visited more than RS steps ago
-    auto far_val = [&](const Rows& S, int p, int d, int sweep, u64 init, u64& h, u64& dd) {
-        if (d <= 0 && sweep == 0) { h = init; dd = init; }
-        else { h = S.ldh(p); dd = S.ldd(p); }
+    auto blk = [&](int i) -> int { return BWD ? nb - 1 - i : i; };
+    // At compute time a neighbour at distance 1 is in registers and one at 2..RS in the ring;
+    // the first other one ("far": not yet visited in this sweep, or more than RS steps back)
+    // comes with the step's inputs.
+    auto is_far = [&](int d) -> bool { return d <= 0 || d > RS; };
+    auto first_far = [&](const Rec& r, int b, int& p, int& d) -> bool {
+        const int cnt = (int)(r.meta & REC_COUNT);
+        if (cnt > 0) { const int dd = dist(b, r.n0); if (is_far(dd)) { p = r.n0; d = dd; return true; } }
+        if (cnt > 1) { const int dd = dist(b, r.n1); if (is_far(dd)) { p = r.n1; d = dd; return true; } }
+        return false;
+    };
+    // record of step g from the record ring
+    auto rec_at = [&](int g) -> Rec {
+        const int4* q = rring + 2 * (g & (REC_RING - 1));
+        const int4 a = q[0], z = q[1];
+        Rec r;
+        r.meta = (uint32_t)__builtin_amdgcn_readfirstlane(a.x);
+        r.n0 = __builtin_amdgcn_readfirstlane(a.y);
+        r.n1 = __builtin_amdgcn_readfirstlane(a.z);
+        r.e0 = (uint32_t)__builtin_amdgcn_readfirstlane(a.w);
+        r.e1 = (uint32_t)__builtin_amdgcn_readfirstlane(z.x);
+        r.ovf = __builtin_amdgcn_readfirstlane(z.y);
+        r.ci = __builtin_amdgcn_readfirstlane(z.z);
+        r.pad = 0;
+        return r;
     };
 
-    // One sweep.  pre(b, r, x) loads the block's own inputs into x;
-    // comp(b, r, x, nh, nd, ph, pd, sweep, vh, vd) computes the new state and writes outputs.
-    auto walk = [&](const Rows& S, u64 init, int sweep, uint32_t& pc, auto&& pre, auto&& comp) {
-        constexpr int dir = BWD ? -1 : 1;
-        auto blk = [&](int i) -> int { return BWD ? nb - 1 - i : i; };
-        Slot<NX> sl[D];
-        auto load = [&](int b, Slot<NX>& s) {
-            const Rec r = ldrec(REC, b);
-            const int cnt = (int)(r.meta & REC_COUNT);
-            // the first far neighbour (a fixed number of loads per slot: the block's own row otherwise)
-            const int d0 = cnt > 0 ? dist(b, r.n0) : 1, d1 = cnt > 1 ? dist(b, r.n1) : 1;
-            const bool f0 = cnt > 0 && is_far(d0), f1 = !f0 && cnt > 1 && is_far(d1);
-            const int fp = f0 ? r.n0 : f1 ? r.n1 : b, fd = f0 ? d0 : f1 ? d1 : 1;
-            const u64 lh = S.ldh(fp), ld = S.ldd(fp);
-            const bool use_init = (f0 || f1) && fd <= 0 && sweep == 0;
-            s.fh = use_init ? init : lh;
-            s.fd = use_init ? init : ld;
-            pre(b, r, s.x);
-        };
-        for (int k = 0; k < D && k < nb; ++k) load(blk(k), sl[k]);
-        u64 ph = init, pd = init;                   // state of the block computed last
-        u64 ch_[2] = {init, init}, cd_[2] = {init, init};   // ring values of the current block's neighbours
-        for (int i0 = 0; i0 < nb; i0 += D) {
+    // ---------------------------------------------------------------- helper wavefront
+    // Each round: keeps the record ring filled (32 records at a time, lane l loads half
+    // l & 1 of the record of step rf + l / 2); loads the inputs of up to IR steps ahead of the
+    // compute wavefront; stores the results the compute wavefront has put in the ring since
+    // the last round; waits for all of it; then publishes the inputs and how far the ring may
+    // be reused and the rows read.
+    // The far neighbour of step s was last computed at step u (this sweep, or the previous one
+    // when it is not yet visited): from the rows when u was stored in an earlier round, from the
+    // ring when it is computed but not stored yet (its slot is not released before this round
+    // ends), the initial value in the first sweep.  Steps whose u is not computed yet wait.
+    auto helper_loop = [&](const Rows& S, u64 init, auto&& pre) {
+        int gf = 0, fi = 0;   // next step to store and its index within the sweep
+        int rf = 0, ri = 0;   // next step whose record is loaded and its index within the sweep
+        int pf = 0, pi = 0;   // next step whose inputs are loaded and its index within the sweep
+        int spins = 0;
+        for (;;) {
+            const int prod = __builtin_amdgcn_readfirstlane(lds_get(&ctl->produced));
+            lds_acquire();
+            const int low = prod < pf ? prod : pf;
+            if (rf < pf + IR + 1 && rf + 32 <= low + REC_RING) {
+                int li = ri + (lane >> 1);
+                while (li >= nb) li -= nb;
+                const int b = blk(li);
+                const GAS int32_t* q = G(REC) + 8 * (size_t)b + 4 * (lane & 1);
+                int4 v;
+                v.x = q[0]; v.y = q[1]; v.z = q[2]; v.w = q[3];
+                rring[2 * ((rf + (lane >> 1)) & (REC_RING - 1)) + (lane & 1)] = v;
+                rf += 32;
+                ri += 32;
+                while (ri >= nb) ri -= nb;
+                lds_release();
+                lds_put(&ctl->rec_filled, rf);
+                spins = 0;
+                continue;
+            }
+            const int fend = prod < gf + 32 ? prod : gf + 32;
+            int pend = prod + IR < rf ? prod + IR : rf;
+            if (pend > pf + IR) pend = pf + IR;
+            // plan steps pf .. pf + n - 1 (records and far-neighbour sources; LDS reads only)
+            int src[IR], at[IR], fp_[IR], bl[IR];   // far: 0 initial value, 1 rows of block fp_, 2 ring slot at
+            uint32_t rm[IR], re0[IR], re1[IR];       // what the input addresses need of the records
+            int n = 0;
+            bool stop = false;
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const int i = i0 + k;
-                if (i < nb) {
-                    const int b = blk(i);
-                    const Rec r = ldrec(REC, b);
-                    const int cnt = (int)(r.meta & REC_COUNT);
-                    // ring values of the next block's neighbours, read while this block computes
-                    u64 nh_[2] = {0, 0}, nd_[2] = {0, 0};
-                    if (i + 1 < nb) {
-                        const Rec rn = ldrec(REC, b + dir);
-                        const int cn = (int)(rn.meta & REC_COUNT);
-                        for (int j = 0; j < 2 && j < cn; ++j) {
-                            const int p = j == 0 ? rn.n0 : rn.n1, d = dist(b + dir, p);
-                            if (d >= 2 && d <= RS) { nh_[j] = ring_h(p); nd_[j] = ring_d(p); }
-                        }
+            for (int t = 0; t < IR; ++t) {
+                const int st = pf + t;
+                src[t] = 0; at[t] = 0; fp_[t] = 0; bl[t] = 0; rm[t] = 0; re0[t] = 0; re1[t] = 0;
+                if (!stop && st < pend) {
+                    int li = pi + t;
+                    while (li >= nb) li -= nb;
+                    const int b = blk(li);
+                    const Rec r = rec_at(st);
+                    int p = b, d = 0, u = -1;
+                    if (first_far(r, b, p, d)) u = d > 0 ? st - d : (st >= nb ? st - d - nb : -1);
+                    if (u >= prod) stop = true;   // not computed yet
+                    else {
+                        src[t] = u < 0 ? 0 : u < gf ? 1 : 2;
+                        at[t] = u;
+                        fp_[t] = p;
+                        bl[t] = b;
+                        rm[t] = r.meta; re0[t] = r.e0; re1[t] = r.e1;
+                        ++n;
                     }
-                    u64 vh_[2], vd_[2];
-                    bool far_used = false;
-                    for (int j = 0; j < 2; ++j) {
-                        vh_[j] = 0; vd_[j] = 0;
-                        if (j >= cnt) continue;
-                        const int p = j == 0 ? r.n0 : r.n1, d = dist(b, p);
-                        if (d == 1) { vh_[j] = ph; vd_[j] = pd; }
-                        else if (d >= 2 && d <= RS) { vh_[j] = ch_[j]; vd_[j] = cd_[j]; }
-                        else if (is_far(d) && !far_used) { vh_[j] = sl[k].fh; vd_[j] = sl[k].fd; far_used = true; }
-                        else far_val(S, p, d, sweep, init, vh_[j], vd_[j]);
-                    }
-                    u64 vh, vd;
-                    comp(b, r, sl[k].x, vh_, vd_, ph, pd, sweep, vh, vd);
-                    pc += popc2(vh, vd);
-                    S.st(b, vh, vd);
-                    if (RS >= 2) { ring_h(b) = vh; ring_d(b) = vd; }
-                    ph = vh; pd = vd;
-                    ch_[0] = nh_[0]; ch_[1] = nh_[1]; cd_[0] = nd_[0]; cd_[1] = nd_[1];
-                    if (i + D < nb) load(blk(i + D), sl[k]);
                 }
             }
+            // nothing to store and nothing that can be loaded yet (the prefetch may also be waiting
+            // for a step the compute wavefront will never reach, after its last sweep)
+            if (fend == gf && n == 0) {
+                if (__builtin_amdgcn_readfirstlane(lds_get(&ctl->done)) &&
+                    __builtin_amdgcn_readfirstlane(lds_get(&ctl->produced)) == gf)
+                    return;
+                if (__builtin_amdgcn_readfirstlane(lds_get(&ctl->abort))) return;
+                // the compute wavefront always ends with `done` or `abort`; this bound only keeps the kernel finite
+                if (++spins > 4 * SPIN_MAX) { lds_put(&ctl->abort, 1); return; }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            spins = 0;
+            // far values from the ring (not stored yet; their slots stay until this round ends) or
+            // the initial value, straight into the input slots
+            for (int t = 0; t < n; ++t) {
+                if (src[t] != 1) {
+                    const u64 h = src[t] == 2 ? slot_h(at[t]) : init, d = src[t] == 2 ? slot_d(at[t]) : init;
+                    uint32_t* q = in32(pf + t, NX) + lane;
+                    q[0] = (uint32_t)h; q[64] = (uint32_t)(h >> 32);
+                    q[128] = (uint32_t)d; q[192] = (uint32_t)(d >> 32);
+                }
+            }
+            // results of steps gf .. fend - 1 to the rows
+            for (; gf < fend; ++gf) {
+                const int b = blk(fi);
+                const u64 h = slot_h(gf), d = slot_d(gf);
+                if (act) S.st(b, h, d);
+                fi = fi + 1 == nb ? 0 : fi + 1;
+            }
+            // the other inputs: copies from global memory straight into the input slots (no LDS read
+            // follows them before the wait); far rows past the first-level cache (the helper stored them)
+            for (int t = 0; t < n; ++t) {
+                const int st = pf + t;
+                Rec r;
+                r.meta = rm[t]; r.e0 = re0[t]; r.e1 = re1[t]; r.n0 = 0; r.n1 = 0; r.ovf = 0; r.ci = -1; r.pad = 0;
+                const GAS u64* a[NX];
+                pre(bl[t], r, a);
+#pragma unroll
+                for (int k = 0; k < NX; ++k) dma64<0>(a[k], in32(st, k));
+                if (src[t] == 1) {
+                    dma64<CPOL_SC1>(S.h + (size_t)fp_[t] * S.str, in32(st, NX));
+                    dma64<CPOL_SC1>(S.d + (size_t)fp_[t] * S.str, in32(st, NX + 1));
+                }
+            }
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            lds_release();
+            lds_put(&ctl->consumed, gf);
+            lds_put(&ctl->flushed, gf);
+            pf += n;
+            pi += n;
+            while (pi >= nb) pi -= nb;
+            lds_put(&ctl->in_ready, pf);
         }
     };
-    // a neighbour beyond the first two, at compute time
-    auto extra = [&](const Rows& S, int b, int p, int sweep, u64 init, u64 ph, u64 pd, u64& h, u64& d) {
+
+    // ---------------------------------------------------------------- compute wavefront
+    int gbase = 0;          // global step index of the current sweep's first step
+    int cons = 0, flsh = 0, rcf = 0, inr = 0;   // last seen helper progress
+    bool ok = true;
+    // wait (bounded) until the helper's counter *p exceeds g; `seen` caches its last value
+    auto need = [&](int* p, int& seen, int g) {
+        if (seen > g) return;
+        seen = __builtin_amdgcn_readfirstlane(lds_get(p));
+        if (seen > g) { lds_acquire(); return; }
+        if (!wait_for(p, g + 1, &ctl->abort)) ok = false;
+        seen = g + 1;
+    };
+    // record of the block of step g (a record without neighbours once the helper has stopped:
+    // every access stays in bounds)
+    auto recl = [&](int g) -> Rec {
+        need(&ctl->rec_filled, rcf, g);
+        if (!ok) {
+            Rec r;
+            r.meta = 0; r.n0 = 0; r.n1 = 0; r.e0 = 0; r.e1 = 0; r.ovf = 0; r.ci = -1; r.pad = 0;
+            return r;
+        }
+        return rec_at(g);
+    };
+    // neighbour p at distance d of the block of step g, from the rows: the previous sweep's (or
+    // the initial value in sweep 0) for a block not yet visited, this sweep's for one visited
+    // more than RS steps ago
+    auto far_val = [&](const Rows& S, int p, int d, int g, int sweep, u64 init, u64& h, u64& dd) {
+        if (d <= 0 && sweep == 0) { h = init; dd = init; return; }
+        if (d > 0) need(&ctl->flushed, flsh, g - d);
+        h = settle(S.ldh(p));
+        dd = settle(S.ldd(p));
+    };
+
+    // One sweep: comp(b, r, x, nh, nd, ph, pd, sweep, g, vh, vd) computes the new state of the
+    // block of step g from its inputs x and its first two neighbours' states nh, nd.
+    auto walk = [&](const Rows& S, u64 init, int sweep, uint32_t& pc, auto&& comp) {
+        constexpr int dir = BWD ? -1 : 1;
+        u64 ph = init, pd = init;                           // state of the block computed last
+        u64 ch_[2] = {init, init}, cd_[2] = {init, init};   // ring values of the current block's neighbours
+        Rec rc = recl(gbase);                               // record of the current block
+        for (int i = 0; i < nb; ++i) {
+            const int b = blk(i), g = gbase + i;
+            const Rec r = rc;
+            const int cnt = (int)(r.meta & REC_COUNT);
+            need(&ctl->in_ready, inr, g);
+            u64 x[NX];
+#pragma unroll
+            for (int k = 0; k < NX; ++k) x[k] = in_get(g, k);
+            const u64 fh = in_get(g, NX), fdv = in_get(g, NX + 1);
+            // ring values of the next block's neighbours, read while this block computes
+            u64 nh_[2] = {0, 0}, nd_[2] = {0, 0};
+            if (i + 1 < nb) {
+                const Rec rn = recl(g + 1);
+                rc = rn;
+                const int cn = (int)(rn.meta & REC_COUNT);
+                for (int j = 0; j < 2 && j < cn; ++j) {
+                    const int p = j == 0 ? rn.n0 : rn.n1, d = dist(b + dir, p);
+                    if (d >= 2 && d <= RS) { nh_[j] = slot_h(g + 1 - d); nd_[j] = slot_d(g + 1 - d); }
+                }
+            }
+            u64 vh_[2], vd_[2];
+            bool far_used = false;
+            for (int j = 0; j < 2; ++j) {
+                vh_[j] = 0; vd_[j] = 0;
+                if (j >= cnt) continue;
+                const int p = j == 0 ? r.n0 : r.n1, d = dist(b, p);
+                if (d == 1) { vh_[j] = ph; vd_[j] = pd; }
+                else if (d >= 2 && d <= RS) { vh_[j] = ch_[j]; vd_[j] = cd_[j]; }
+                else if (!far_used) { vh_[j] = fh; vd_[j] = fdv; far_used = true; }
+                else far_val(S, p, d, g, sweep, init, vh_[j], vd_[j]);
+            }
+            u64 vh, vd;
+            comp(b, r, x, vh_, vd_, ph, pd, sweep, g, vh, vd);
+            pc += popc2(vh, vd);
+            // the ring slot of step g was last used by step g - RS: the helper must have read it
+            need(&ctl->consumed, cons, g - RS);
+            slot_h(g) = vh;
+            slot_d(g) = vd;
+            lds_release();
+            lds_put(&ctl->produced, g + 1);
+            ph = vh; pd = vd;
+            ch_[0] = nh_[0]; ch_[1] = nh_[1]; cd_[0] = nd_[0]; cd_[1] = nd_[1];
+        }
+    };
+    // a neighbour beyond the first two, at compute time (g = the current step)
+    auto extra = [&](const Rows& S, int b, int p, int sweep, int g, u64 init, u64 ph, u64 pd, u64& h, u64& d) {
         const int dd = dist(b, p);
         if (dd == 1) { h = ph; d = pd; }
-        else if (dd >= 2 && dd <= RS) { h = ring_h(p); d = ring_d(p); }
-        else far_val(S, p, dd, sweep, init, h, d);
+        else if (dd >= 2 && dd <= RS) { h = slot_h(g - dd); d = slot_d(g - dd); }
+        else far_val(S, p, dd, g, sweep, init, h, d);
     };
+    // Run a phase: the compute wavefront sweeps, the helper feeds and stores; false on an error.
     auto run_phase = [&](const Rows& S, u64 init, auto&& pre, auto&& comp) -> bool {
+        if (helper) {
+            helper_loop(S, init, pre);
+            return true;
+        }
         int sweeps = 0;
         uint32_t last = (uint32_t)nb * 2u * (uint32_t)__popcll(init);
+        bool good = true;
         for (;;) {
             uint32_t pc = 0;
-            walk(S, init, sweeps, pc, pre, comp);
+            walk(S, init, sweeps, pc, comp);
+            gbase += nb;
             ++sweeps;
+            // the next sweep reads this sweep's rows for blocks it has not visited yet
+            need(&ctl->flushed, flsh, gbase - 1);
+            if (!ok) break;
             const bool ch = act && pc != last;
             last = pc;
             if (__ballot(ch) == 0ull) break;
             if (sweeps >= cap) {
                 if (lane == 0) set_status(c.info, OMPD_E_NOCONVERGE_);
-                return false;
+                good = false;
+                break;
             }
         }
+        lds_put(&ctl->done, 1);
+        if (!ok) {
+            if (lane == 0) set_status(c.info, OMPD_E_DEVICE_);
+            return false;
+        }
         if (lane == 0) atomicMax(&c.info[INFO_SWEEPS + PH], sweeps);
-        __threadfence_block();
-        return true;
+        return good;
     };
     // NUout of a call block: OR over its successors' next use (final)
     auto nu_after = [&](int b, u64& lh, u64& ld) {
@@ -440,8 +688,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         lh = 0; ld = 0;
         for (int j = 0; j < cnt; ++j) {
             int q = nbr_b(rb, j);
-            lh |= row(c.nu_h, q);
-            ld |= row(c.nu_d, q);
+            lh |= settle(row(c.nu_h, q));
+            ld |= settle(row(c.nu_d, q));
         }
     };
     // validity transfer of block b (a call applies the callee's exit-validity
@@ -468,14 +716,13 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // replaces the pass term by ~W & (NU0_s | (NU1_s & OR ...)); NUin(EXIT) = live after.
     if constexpr (PH == PH_NU) {
         const Rows S = rows_of(c.nu_h, c.nu_d, 0);
-        // x0 = R, x1 = W (flag lane: R = 2, W = 2 at DEVICE blocks)
-        auto pre = [&](int b, const Rec& r, u64* x) {
-            const u64 rr = row(c.R, b), ww = row(c.W, b);
-            x[0] = flg ? 2ull : rr;
-            x[1] = flg ? ((r.meta & REC_DEV) ? 2ull : 0ull) : ww;
+        // x0 = R, x1 = W (flag lane: R = 2, W = 2 at DEVICE blocks, substituted when computed)
+        auto pre = [&](int b, const Rec& r, const GAS u64** x) {
+            x[0] = rowp(c.R, b);
+            x[1] = rowp(c.W, b);
         };
         auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd, int sweep,
-                        u64& vh, u64& vd) {
+                        int g, u64& vh, u64& vd) {
             if (r.meta & REC_EXIT) {
                 const u64 lh = vec(c.lx_h), ld = vec(c.lx_d);
                 vh = flg ? 1ull : lh;
@@ -486,11 +733,11 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             u64 oh = nh[0] | nh[1], od = nd[0] | nd[1];
             for (int j = 2; j < cnt; ++j) {
                 u64 h, d;
-                extra(S, b, nbr_b(r, j), sweep, 0ull, ph, pd, h, d);
+                extra(S, b, nbr_b(r, j), sweep, g, 0ull, ph, pd, h, d);
                 oh |= h; od |= d;
             }
             const bool dev = r.meta & REC_DEV;
-            const u64 rr = x[0], ww = x[1];
+            const u64 rr = flg ? 2ull : x[0], ww = flg ? (dev ? 2ull : 0ull) : x[1];
             if (r.meta & REC_CALL) {
                 const int ci = r.ci;   // the flag lane passes through (NU0 = 0, NU1 = all ones)
                 const u64 ch = sum(ci, SUM_NU0_H) | (sum(ci, SUM_NU1_H) & oh);
@@ -506,19 +753,18 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     }
 
     // ------------------------------------------------------------ validity with eager copies (forward, must)
-    // AVEin_s(q) = NUin_s(q) | AND over preds AVEout_s(p); AVEin(ENTRY) = boundary.
+    // AVEout_s(q) = transfer of AVEin_s(q) = NUin_s(q) | AND over preds AVEout_s(p); AVEin(ENTRY) = boundary.
     if constexpr (PH == PH_AVE) {
         const Rows S = rows_of(c.aveout_h, c.aveout_d, 2);
         const u64 init = ~0ull & vm;
-        // x0/x1 = NU (flag lane: 0), x2 = W (flag lane: 2 at DEVICE blocks)
-        auto pre = [&](int b, const Rec& r, u64* x) {
-            const u64 nh = row(c.nu_h, b), nd = row(c.nu_d, b), ww = row(c.W, b);
-            x[0] = flg ? 0ull : nh;
-            x[1] = flg ? 0ull : nd;
-            x[2] = flg ? ((r.meta & REC_DEV) ? 2ull : 0ull) : ww;
+        // x0/x1 = NU (flag lane: 0), x2 = W (flag lane: 2 at DEVICE blocks), substituted when computed
+        auto pre = [&](int b, const Rec& r, const GAS u64** x) {
+            x[0] = rowp(c.nu_h, b);
+            x[1] = rowp(c.nu_d, b);
+            x[2] = rowp(c.W, b);
         };
         auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd, int sweep,
-                        u64& vh, u64& vd) {
+                        int g, u64& vh, u64& vd) {
             u64 ih, id;
             if (r.meta & REC_ENTRY) {
                 const u64 eh = vec(c.ev_h), ed = vec(c.ev_d);
@@ -533,21 +779,21 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                     int p; uint32_t e;
                     nbr_f(r, j, p, e);
                     u64 h, d;
-                    extra(S, b, p, sweep, init, ph, pd, h, d);
+                    extra(S, b, p, sweep, g, init, ph, pd, h, d);
                     mh &= h; md &= d;
                 }
-                ih = x[0] | mh;
-                id = x[1] | md;
+                ih = (flg ? 0ull : x[0]) | mh;
+                id = (flg ? 0ull : x[1]) | md;
             }
-            ih &= vm; id &= vm;
-            if (dat) { G(c.ave_h)[(size_t)b * wd + wo] = ih; G(c.ave_d)[(size_t)b * wd + wo] = id; }
-            valid_out(b, r, ih, id, x[2], vh, vd);
+            valid_out(b, r, ih & vm, id & vm, flg ? ((r.meta & REC_DEV) ? 2ull : 0ull) : x[2], vh, vd);
         };
         if (!run_phase(S, init, pre, comp)) return;
+        if (helper) return;
         // reachability: every block reached from ENTRY and reaching EXIT
         bool bad = false;
         for (int b = lane; b < nb; b += 64) {
-            u64 fnu = FLG[b], fave = FLG[(size_t)2 * nb + b], fnud = FLG[(size_t)nb + b];
+            const u64 fnu = ld_fresh(FLG + b), fave = ld_fresh(FLG + (size_t)2 * nb + b);
+            const u64 fnud = ld_fresh(FLG + (size_t)nb + b);
             if (!(fnu & 1) || (fave & 1)) bad = true;
             if (s0 == 0) {
                 if (c.after_dev) G(c.after_dev)[b] = (uint8_t)(((fave >> 1) & 1) ^ 1);
@@ -576,6 +822,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         sd = ud | (dev ? ww : 0ull);
     };
     auto erow = [&](const u64* a, uint32_t e) -> u64 { return G(a)[(size_t)(e & 0x7FFFFFFFu) * wd + wo]; };
+    auto erowp = [&](const u64* a, uint32_t e) -> const GAS u64* { return G(a) + (size_t)(e & 0x7FFFFFFFu) * wd + wo; };
 
     // -------------------------------------------------------- pending copies (forward, may)
     // MAYP_s(e) = (EAG_s(e) | MAYPout_s(p)) & ~LE(e), EAG_s(e=p->q) = NU_s(q) & ~AVEout_s(p);
@@ -584,15 +831,15 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         if (c.placement & 1) return;
         const Rows S = rows_of(c.mayp_h, c.mayp_d, 0);
         // x0 = R, x1 = W, x2..x5 = EAG_H/D of the two inline in-edges
-        auto pre = [&](int b, const Rec& r, u64* x) {
-            x[0] = row(c.R, b); x[1] = row(c.W, b);
+        auto pre = [&](int b, const Rec& r, const GAS u64** x) {
+            x[0] = rowp(c.R, b); x[1] = rowp(c.W, b);
             const int cnt = (int)(r.meta & REC_COUNT);
             const uint32_t e0 = cnt > 0 ? r.e0 : 0u, e1 = cnt > 1 ? r.e1 : 0u;   // edge 0 stands in for a missing one
-            x[2] = erow(c.eag_h, e0); x[3] = erow(c.eag_d, e0);
-            x[4] = erow(c.eag_h, e1); x[5] = erow(c.eag_d, e1);
+            x[2] = erowp(c.eag_h, e0); x[3] = erowp(c.eag_d, e0);
+            x[4] = erowp(c.eag_h, e1); x[5] = erowp(c.eag_d, e1);
         };
         auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd, int sweep,
-                        u64& vh, u64& vd) {
+                        int g, u64& vh, u64& vd) {
             if (r.meta & REC_ENTRY) { vh = 0; vd = 0; return; }
             const int cnt = (int)(r.meta & REC_COUNT);
             u64 mh = 0, md = 0;
@@ -603,8 +850,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 u64 gh, gd, sh, sd;
                 if (j < 2) { gh = x[2 + 2 * j]; gd = x[3 + 2 * j]; sh = nh[j]; sd = nd[j]; }
                 else {
-                    gh = erow(c.eag_h, e); gd = erow(c.eag_d, e);
-                    extra(S, b, p, sweep, 0ull, ph, pd, sh, sd);
+                    gh = settle(erow(c.eag_h, e)); gd = settle(erow(c.eag_d, e));
+                    extra(S, b, p, sweep, g, 0ull, ph, pd, sh, sd);
                 }
                 mh |= gh | sh;
                 md |= gd | sd;
@@ -622,105 +869,65 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // LATER_s(e) = EAG_s(e) | LATERout_s(p); L'_s(e) = LATER_s(e) & ~LE(e)
     // N'_s(e) = BOTH(e) | (LATER_s(e) & LE(e)), BOTH(e) = FV_H(e) & FV_D(e)
     // LATERin_s(q) = AND_e (L'_s | N'_s) & OR_e L'_s; LATERout_s(q) = LATERin_s(q) & ~USE'_s(q) & ~WR_s(q)
-    // materialised on every sweep: INS_ENTRY_s(q) = LATERin_s(q) & USE'_s(q),
-    //   INS_EDGE_s(e=p->q) = LATER_s(e) & (LE(e) | ~LATERin_s(q))
+    // (the copies themselves are materialised after the phase)
     if constexpr (PH == PH_LATER) {
-        if (!(c.placement & 1)) {
-            const Rows S = rows_of(c.later_h, c.later_d, 0);
-            // x0 = R, x1 = W, x2..x4 / x5..x7 = EAG_H, EAG_D, BOTH of the two inline in-edges
-            auto pre = [&](int b, const Rec& r, u64* x) {
-                x[0] = row(c.R, b); x[1] = row(c.W, b);
-                const int cnt = (int)(r.meta & REC_COUNT);
-                const uint32_t e0 = cnt > 0 ? r.e0 : 0u, e1 = cnt > 1 ? r.e1 : 0u;
-                x[2] = erow(c.eag_h, e0); x[3] = erow(c.eag_d, e0); x[4] = erow(c.both, e0);
-                x[5] = erow(c.eag_h, e1); x[6] = erow(c.eag_d, e1); x[7] = erow(c.both, e1);
-            };
-            auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd,
-                            int sweep, u64& vh, u64& vd) {
-                u64 uh, ud, sth, std_;
-                use_wr(b, r, x[0], x[1], uh, ud, sth, std_);
-                if (r.meta & REC_ENTRY) {
-                    vh = 0; vd = 0;
-                    G(c.ie_h)[(size_t)b * wd + wo] = 0;
-                    G(c.ie_d)[(size_t)b * wd + wo] = 0;
-                    return;
+        if (c.placement & 1) return;
+        const Rows S = rows_of(c.later_h, c.later_d, 0);
+        // x0 = R, x1 = W, x2..x4 / x5..x7 = EAG_H, EAG_D, BOTH of the two inline in-edges
+        auto pre = [&](int b, const Rec& r, const GAS u64** x) {
+            x[0] = rowp(c.R, b); x[1] = rowp(c.W, b);
+            const int cnt = (int)(r.meta & REC_COUNT);
+            const uint32_t e0 = cnt > 0 ? r.e0 : 0u, e1 = cnt > 1 ? r.e1 : 0u;
+            x[2] = erowp(c.eag_h, e0); x[3] = erowp(c.eag_d, e0); x[4] = erowp(c.both, e0);
+            x[5] = erowp(c.eag_h, e1); x[6] = erowp(c.eag_d, e1); x[7] = erowp(c.both, e1);
+        };
+        auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd, int sweep,
+                        int g, u64& vh, u64& vd) {
+            if (r.meta & REC_ENTRY) { vh = 0; vd = 0; return; }
+            u64 uh, ud, sth, std_;
+            use_wr(b, r, x[0], x[1], uh, ud, sth, std_);
+            const int cnt = (int)(r.meta & REC_COUNT);
+            u64 allh = ~0ull, alld = ~0ull, anyh = 0, anyd = 0;
+            for (int j = 0; j < cnt; ++j) {
+                int p; uint32_t e;
+                nbr_f(r, j, p, e);
+                u64 gh, gd, bo, sh, sd;
+                if (j < 2) { gh = x[2 + 3 * j]; gd = x[3 + 3 * j]; bo = x[4 + 3 * j]; sh = nh[j]; sd = nd[j]; }
+                else {
+                    gh = settle(erow(c.eag_h, e)); gd = settle(erow(c.eag_d, e)); bo = settle(erow(c.both, e));
+                    extra(S, b, p, sweep, g, 0ull, ph, pd, sh, sd);
                 }
-                const int cnt = (int)(r.meta & REC_COUNT);
-                u64 allh = ~0ull, alld = ~0ull, anyh = 0, anyd = 0;
-                u64 lat_h[2] = {0, 0}, lat_d[2] = {0, 0};
-                auto edge = [&](int j, int p, uint32_t e, u64& gh, u64& gd, u64& bo, u64& sh, u64& sd) {
-                    if (j < 2) { gh = x[2 + 3 * j]; gd = x[3 + 3 * j]; bo = x[4 + 3 * j]; sh = nh[j]; sd = nd[j]; }
-                    else {
-                        gh = erow(c.eag_h, e); gd = erow(c.eag_d, e); bo = erow(c.both, e);
-                        extra(S, b, p, sweep, 0ull, ph, pd, sh, sd);
-                    }
-                };
-                for (int j = 0; j < cnt; ++j) {
-                    int p; uint32_t e;
-                    nbr_f(r, j, p, e);
-                    u64 gh, gd, bo, sh, sd;
-                    edge(j, p, e, gh, gd, bo, sh, sd);
-                    const u64 le = (e & 0x80000000u) ? ~0ull : 0ull;
-                    const u64 lh = gh | sh, ld = gd | sd;
-                    const u64 lph = lh & ~le, lpd = ld & ~le;
-                    allh &= lph | bo | (lh & le);
-                    alld &= lpd | bo | (ld & le);
-                    anyh |= lph;
-                    anyd |= lpd;
-                    if (j < 2) { lat_h[j] = lh; lat_d[j] = ld; }
-                }
-                const u64 inh = allh & anyh & vm, ind = alld & anyd & vm;
-                vh = inh & ~sth;
-                vd = ind & ~std_;
-                G(c.ie_h)[(size_t)b * wd + wo] = inh & uh;
-                G(c.ie_d)[(size_t)b * wd + wo] = ind & ud;
-                for (int j = 0; j < cnt; ++j) {
-                    int p; uint32_t e;
-                    nbr_f(r, j, p, e);
-                    u64 lh, ld;
-                    if (j < 2) { lh = lat_h[j]; ld = lat_d[j]; }
-                    else {
-                        u64 gh, gd, bo, sh, sd;
-                        edge(j, p, e, gh, gd, bo, sh, sd);
-                        lh = gh | sh; ld = gd | sd;
-                    }
-                    const u64 le = (e & 0x80000000u) ? ~0ull : 0ull;
-                    const size_t eid = e & 0x7FFFFFFFu;
-                    G(c.ig_h)[eid * wd + wo] = lh & (le | ~inh) & vm;
-                    G(c.ig_d)[eid * wd + wo] = ld & (le | ~ind) & vm;
-                }
-            };
-            run_phase(S, 0ull, pre, comp);
-        } else if (dat) {
-            // eager placement only: every EAG is materialised on its edge
-            for (int b = 0; b < nb; ++b) {
-                G(c.ie_h)[(size_t)b * wd + wo] = 0;
-                G(c.ie_d)[(size_t)b * wd + wo] = 0;
+                const u64 le = (e & 0x80000000u) ? ~0ull : 0ull;
+                const u64 lh = gh | sh, ld = gd | sd;
+                const u64 lph = lh & ~le, lpd = ld & ~le;
+                allh &= lph | bo | (lh & le);
+                alld &= lpd | bo | (ld & le);
+                anyh |= lph;
+                anyd |= lpd;
             }
-            for (int e = 0; e < c.ne; ++e) {
-                G(c.ig_h)[(size_t)e * wd + wo] = G(c.eag_h)[(size_t)e * wd + wo];
-                G(c.ig_d)[(size_t)e * wd + wo] = G(c.eag_d)[(size_t)e * wd + wo];
-            }
-        }
+            vh = allh & anyh & vm & ~sth;
+            vd = alld & anyd & vm & ~std_;
+        };
+        run_phase(S, 0ull, pre, comp);
         return;
     }
 
     // ------------------------------------------------------------ validity after placement (forward, must)
-    // AVFin_s(q) = INS_ENTRY_s(q) | AND_e (AVFout_s(p) | INS_EDGE_s(e)); the state reuses the
-    // eager-validity rows.
+    // AVFout_s(q) = transfer of AVFin_s(q) = INS_ENTRY_s(q) | AND_e (AVFout_s(p) | INS_EDGE_s(e));
+    // the state reuses the eager-validity rows.
     if constexpr (PH == PH_AVF) {
         const Rows S = rows_of(c.aveout_h, c.aveout_d, 2);
         const u64 init = ~0ull & vm;
         // x0/x1 = INS_ENTRY, x2 = W, x3..x6 = INS_EDGE_H/D of the two inline in-edges
-        auto pre = [&](int b, const Rec& r, u64* x) {
-            x[0] = row(c.ie_h, b); x[1] = row(c.ie_d, b); x[2] = row(c.W, b);
+        auto pre = [&](int b, const Rec& r, const GAS u64** x) {
+            x[0] = rowp(c.ie_h, b); x[1] = rowp(c.ie_d, b); x[2] = rowp(c.W, b);
             const int cnt = (int)(r.meta & REC_COUNT);
             const uint32_t e0 = cnt > 0 ? r.e0 : 0u, e1 = cnt > 1 ? r.e1 : 0u;
-            x[3] = erow(c.ig_h, e0); x[4] = erow(c.ig_d, e0);
-            x[5] = erow(c.ig_h, e1); x[6] = erow(c.ig_d, e1);
+            x[3] = erowp(c.ig_h, e0); x[4] = erowp(c.ig_d, e0);
+            x[5] = erowp(c.ig_h, e1); x[6] = erowp(c.ig_d, e1);
         };
         auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd, int sweep,
-                        u64& vh, u64& vd) {
+                        int g, u64& vh, u64& vd) {
             u64 ih, id;
             if (r.meta & REC_ENTRY) { ih = vec(c.ev_h); id = vec(c.ev_d); }
             else {
@@ -732,8 +939,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                     u64 gh, gd, sh, sd;
                     if (j < 2) { gh = x[3 + 2 * j]; gd = x[4 + 2 * j]; sh = nh[j]; sd = nd[j]; }
                     else {
-                        gh = erow(c.ig_h, e); gd = erow(c.ig_d, e);
-                        extra(S, b, p, sweep, init, ph, pd, sh, sd);
+                        gh = settle(erow(c.ig_h, e)); gd = settle(erow(c.ig_d, e));
+                        extra(S, b, p, sweep, g, init, ph, pd, sh, sd);
                     }
                     mh &= sh | gh;
                     md &= sd | gd;
@@ -741,133 +948,209 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 ih = x[0] | mh;
                 id = x[1] | md;
             }
-            ih &= vm; id &= vm;
-            if (c.avf_h) { G(c.avf_h)[(size_t)b * wd + wo] = ih; G(c.avf_d)[(size_t)b * wd + wo] = id; }
-            valid_out(b, r, ih, id, x[2], vh, vd);
+            valid_out(b, r, ih & vm, id & vm, x[2], vh, vd);
         };
-        if (!run_phase(S, init, pre, comp)) return;
-
-        // Per-variable map kind (Table II), from the final placement in one pass:
-        // map(to) = a copy into the device on p->q with no DEVICE block before p, or before q
-        // when no predecessor has one; map(from) = a copy into the host on p->q or before q
-        // when no DEVICE block follows q; alloc = used only on the device.
-        if (c.var_kind && dat) {
-            u64 to = 0, fr = 0, dv = 0;
-            for (int b = 0; b < nb; ++b) {
-                const Rec r = ldrec(c.rec_f, b);
-                const int cnt = (int)(r.meta & REC_COUNT);
-                const u64 not_before = ((FLG[(size_t)nb + b] >> 1) & 1) - 1;   // all ones: no DEVICE block follows b
-                if (!(r.meta & REC_ENTRY)) {
-                    u64 none_after = ~0ull;                                        // no predecessor after a DEVICE block
-                    for (int j = 0; j < cnt; ++j) {
-                        int p; uint32_t e;
-                        nbr_f(r, j, p, e);
-                        const u64 p_clear = 0ull - ((FLG[(size_t)2 * nb + p] >> 1) & 1);   // all ones: p not after DEVICE
-                        to |= erow(c.ig_d, e) & p_clear;
-                        fr |= erow(c.ig_h, e) & not_before;
-                        none_after &= p_clear;
-                    }
-                    to |= row(c.ie_d, b) & none_after;
-                    fr |= row(c.ie_h, b) & not_before;
-                }
-                if ((r.meta & REC_DEV) && !(r.meta & REC_EXIT)) dv |= row(c.R, b) | row(c.W, b);
-            }
-            const int base = w * 64;
-            for (int i = 0; i < 64 && base + i < c.nv; ++i) {
-                const uint32_t t1 = (uint32_t)((to >> i) & 1), f1 = (uint32_t)((fr >> i) & 1);
-                const uint32_t d1 = (uint32_t)((dv >> i) & 1);
-                G(c.var_kind)[base + i] = (uint8_t)(t1 | (f1 << 1) | ((d1 && !t1 && !f1) ? 4u : 0u));
-            }
-        }
+        run_phase(S, init, pre, comp);
     }
 }
 
-// Edge-parallel steps between the walks (no iteration): lanes over words,
-// one wavefront per (tile, block) chunk of 64 source blocks.
-//   after AVE : EAG_s(e=p->q) = NU_s(q) & ~AVEout_s(p);  VE_s(e) = AVEout_s(p) | NU_s(q)
-//               (VE is kept in the INS_EDGE rows until the delayed placement overwrites them)
-//   after MAYP: BOTH(e) = FV_H(e) & FV_D(e), FV_x(e) = VE_x(e) & ~((EAG_x(e) | MAYPout_x(p)) & ~LE(e))
-template <int STEP>
-__device__ __forceinline__ void edge_step(const DevCfg& c, int s0, int nw, int b0)
+// ---------------------------------------------------------------------------
+// Edge-parallel passes (no iteration): lanes over words, one wavefront per
+// (tile, 64-block chunk) item.
+//   PASS_AVE  : AVEin_s(b) (output); per out-edge e = b->q:
+//               EAG_s(e) = NU_s(q) & ~AVEout_s(b), VE_s(e) = AVEout_s(b) | NU_s(q)
+//               (VE is kept in the INS_EDGE rows until the placement overwrites them)
+//   PASS_MAYP : per out-edge: BOTH(e) = FV_H(e) & FV_D(e),
+//               FV_x(e) = VE_x(e) & ~((EAG_x(e) | MAYPout_x(b)) & ~LE(e))
+//   PASS_LATER: LATERin_s(q) and the copies INS_ENTRY_s(q) = LATERin_s(q) & USE'_s(q),
+//               INS_EDGE_s(e = p->q) = LATER_s(e) & (LE(e) | ~LATERin_s(q)); eager placement:
+//               INS_ENTRY = 0, INS_EDGE = EAG
+//   PASS_AVF  : AVFin_s(q) (output) and the per-variable map kind accumulators (Table II):
+//               map(to) = a copy into the device on p->q with no DEVICE block before p, or
+//               before q when no predecessor has one; map(from) = a copy into the host on
+//               p->q or before q when no DEVICE block follows q; alloc = used only on the device
+enum { PASS_AVE = 0, PASS_MAYP = 1, PASS_LATER = 2, PASS_AVF = 3 };
+
+template <int PASS>
+__device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int fslot, int b0)
 {
     const int lane = threadIdx.x;
     if (lane >= nw) return;
-    const int wd = c.wd;
+    const int nb = c.nb, wd = c.wd;
     const size_t wo = (size_t)(s0 + lane);
+    const int w = s0 + lane;
+    const u64 vm = (w == wd - 1 && (c.nv & 63)) ? ((1ull << (c.nv & 63)) - 1ull) : ~0ull;
     const CAS int32_t* SP = K(c.succ_ptr);
     const CAS int32_t* SI = K(c.succ_idx);
+    const CAS int32_t* PP = K(c.pred_ptr);
+    const CAS int32_t* PI = K(c.pred_idx);
+    const CAS int32_t* PE = K(c.pred_eid);
     const CAS uint8_t* KD = K(c.kind);
-    const int b1 = min(b0 + 64, c.nb);
-#pragma unroll 4
-    for (int p = b0; p < b1; ++p) {
-        const int a = SP[p], z = SP[p + 1];
-        if (a == z) continue;
-        const u64 aoh = G(c.aveout_h)[(size_t)p * wd + wo], aod = G(c.aveout_d)[(size_t)p * wd + wo];
-        u64 mph = 0, mpd = 0;
-        if constexpr (STEP == 1) { mph = G(c.mayp_h)[(size_t)p * wd + wo]; mpd = G(c.mayp_d)[(size_t)p * wd + wo]; }
-        for (int e = a; e < z; ++e) {
-            const size_t ei = (size_t)e * wd + wo;
-            if constexpr (STEP == 0) {
-                const int q = SI[e];
-                const u64 nuh = G(c.nu_h)[(size_t)q * wd + wo], nud = G(c.nu_d)[(size_t)q * wd + wo];
-                G(c.eag_h)[ei] = nuh & ~aoh;
-                G(c.eag_d)[ei] = nud & ~aod;
-                G(c.ig_h)[ei] = aoh | nuh;
-                G(c.ig_d)[ei] = aod | nud;
+    const GAS u64* FLG = G(c.flg) + (size_t)fslot * 4 * nb;
+    auto row = [&](const u64* a, int b) -> u64 { return G(a)[(size_t)b * wd + wo]; };
+    auto erow = [&](const u64* a, int e) -> u64 { return G(a)[(size_t)e * wd + wo]; };
+    auto put = [&](u64* a, size_t r, u64 v) { G(a)[r * wd + wo] = v; };
+    const int b1 = min(b0 + 64, nb);
+    if constexpr (PASS == PASS_AVE || PASS == PASS_MAYP) {
+        for (int b = b0; b < b1; ++b) {
+            const u64 aoh = row(c.aveout_h, b), aod = row(c.aveout_d, b);
+            if constexpr (PASS == PASS_AVE) {
+                u64 ih, id;
+                if (b == c.entry) { ih = G(c.ev_h)[wo]; id = G(c.ev_d)[wo]; }
+                else {
+                    u64 mh = ~0ull, md = ~0ull;
+                    for (int k = PP[b]; k < PP[b + 1]; ++k) {
+                        const int p = PI[k];
+                        mh &= row(c.aveout_h, p);
+                        md &= row(c.aveout_d, p);
+                    }
+                    ih = row(c.nu_h, b) | mh;
+                    id = row(c.nu_d, b) | md;
+                }
+                put(c.ave_h, b, ih & vm);
+                put(c.ave_d, b, id & vm);
+                for (int e = SP[b]; e < SP[b + 1]; ++e) {
+                    const int q = SI[e];
+                    const u64 nuh = row(c.nu_h, q), nud = row(c.nu_d, q);
+                    put(c.eag_h, e, nuh & ~aoh);
+                    put(c.eag_d, e, nud & ~aod);
+                    put(c.ig_h, e, aoh | nuh);
+                    put(c.ig_d, e, aod | nud);
+                }
             } else {
-                const u64 nle = KD[e] == 2 ? 0ull : ~0ull;
-                const u64 fvh = G(c.ig_h)[ei] & ~((G(c.eag_h)[ei] | mph) & nle);
-                const u64 fvd = G(c.ig_d)[ei] & ~((G(c.eag_d)[ei] | mpd) & nle);
-                G(c.both)[ei] = fvh & fvd;
+                const u64 mph = row(c.mayp_h, b), mpd = row(c.mayp_d, b);
+                for (int e = SP[b]; e < SP[b + 1]; ++e) {
+                    const u64 nle = KD[e] == 2 ? 0ull : ~0ull;
+                    const u64 fvh = erow(c.ig_h, e) & ~((erow(c.eag_h, e) | mph) & nle);
+                    const u64 fvd = erow(c.ig_d, e) & ~((erow(c.eag_d, e) | mpd) & nle);
+                    put(c.both, e, fvh & fvd);
+                }
             }
+        }
+    }
+    if constexpr (PASS == PASS_LATER) {
+        const bool eager = c.placement & 1;
+        for (int q = b0; q < b1; ++q) {
+            const int a = PP[q], z = PP[q + 1];
+            if (eager || q == c.entry) {
+                put(c.ie_h, q, 0);
+                put(c.ie_d, q, 0);
+                for (int k = a; k < z; ++k) {
+                    const int e = PE[k];
+                    put(c.ig_h, e, eager ? erow(c.eag_h, e) : 0ull);
+                    put(c.ig_d, e, eager ? erow(c.eag_d, e) : 0ull);
+                }
+                continue;
+            }
+            u64 allh = ~0ull, alld = ~0ull, anyh = 0, anyd = 0;
+            for (int k = a; k < z; ++k) {
+                const int p = PI[k], e = PE[k];
+                const u64 le = KD[e] == 2 ? ~0ull : 0ull;
+                const u64 lh = erow(c.eag_h, e) | row(c.later_h, p), ld = erow(c.eag_d, e) | row(c.later_d, p);
+                const u64 bo = erow(c.both, e);
+                const u64 lph = lh & ~le, lpd = ld & ~le;
+                allh &= lph | bo | (lh & le);
+                alld &= lpd | bo | (ld & le);
+                anyh |= lph;
+                anyd |= lpd;
+            }
+            const u64 inh = allh & anyh & vm, ind = alld & anyd & vm;
+            // USE'_s(q)
+            const bool dev = c.space[q] != 0;
+            u64 uh, ud;
+            if (q == c.exit) { uh = G(c.lx_h)[wo]; ud = G(c.lx_d)[wo]; }
+            else {
+                const u64 rr = row(c.R, q);
+                uh = dev ? 0ull : rr;
+                ud = dev ? rr : 0ull;
+                const int ci = c.call ? c.call[q] : -1;
+                if (ci >= 0) {
+                    const GAS u64* sm = G(c.sums) + (size_t)ci * SUM_ROWS * wd + wo;
+                    const u64 mw = sm[SUM_MAYW_H * wd] | sm[SUM_MAYW_D * wd];
+                    uh |= sm[SUM_MAYR_H * wd] | mw;
+                    ud |= sm[SUM_MAYR_D * wd] | mw;
+                }
+            }
+            put(c.ie_h, q, inh & uh);
+            put(c.ie_d, q, ind & ud);
+            for (int k = a; k < z; ++k) {
+                const int p = PI[k], e = PE[k];
+                const u64 le = KD[e] == 2 ? ~0ull : 0ull;
+                const u64 lh = erow(c.eag_h, e) | row(c.later_h, p), ld = erow(c.eag_d, e) | row(c.later_d, p);
+                put(c.ig_h, e, lh & (le | ~inh) & vm);
+                put(c.ig_d, e, ld & (le | ~ind) & vm);
+            }
+        }
+    }
+    if constexpr (PASS == PASS_AVF) {
+        u64 to = 0, fr = 0, dv = 0;
+        for (int q = b0; q < b1; ++q) {
+            const int a = PP[q], z = PP[q + 1];
+            const u64 ieh = row(c.ie_h, q), ied = row(c.ie_d, q);
+            const u64 not_before = ((FLG[(size_t)nb + q] >> 1) & 1) - 1;   // all ones: no DEVICE block follows q
+            u64 ih, id;
+            if (q == c.entry) { ih = G(c.ev_h)[wo]; id = G(c.ev_d)[wo]; }
+            else {
+                u64 mh = ~0ull, md = ~0ull, none_after = ~0ull;
+                for (int k = a; k < z; ++k) {
+                    const int p = PI[k], e = PE[k];
+                    const u64 gh = erow(c.ig_h, e), gd = erow(c.ig_d, e);
+                    mh &= row(c.aveout_h, p) | gh;
+                    md &= row(c.aveout_d, p) | gd;
+                    const u64 p_clear = 0ull - ((FLG[(size_t)2 * nb + p] >> 1) & 1);   // all ones: p not after DEVICE
+                    to |= gd & p_clear;
+                    fr |= gh & not_before;
+                    none_after &= p_clear;
+                }
+                ih = ieh | mh;
+                id = ied | md;
+                to |= ied & none_after;
+                fr |= ieh & not_before;
+            }
+            if (c.space[q] && q != c.exit) dv |= row(c.R, q) | row(c.W, q);
+            if (c.avf_h) { put(c.avf_h, q, ih & vm); put(c.avf_d, q, id & vm); }
+        }
+        if (c.var_kind) {
+            GAS u64* acc = G(c.vk_acc);
+            if (to) atomicOr((unsigned long long*)&acc[wo], (unsigned long long)to);
+            if (fr) atomicOr((unsigned long long*)&acc[wd + wo], (unsigned long long)fr);
+            if (dv) atomicOr((unsigned long long*)&acc[2 * wd + wo], (unsigned long long)dv);
         }
     }
 }
 
 template <int PH>
 __device__ __forceinline__ void phase_kernel(const DevCfg* __restrict__ cfgs, const Tile* __restrict__ tiles, int n_tiles,
-                                             int32_t* __restrict__ counter, int ring_words)
+                                             int32_t* __restrict__ counter, int ring_slots)
 {
-    extern __shared__ __align__(16) u64 ring[];
+    extern __shared__ __align__(16) u64 lds[];
+    Ctl* ctl = reinterpret_cast<Ctl*>(lds);
     for (;;) {
-        int t = 0;
-        if (threadIdx.x == 0) t = atomicAdd(&counter[PH], 1);
-        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0, 64));
+        if (threadIdx.x == 0) {
+            const int t = atomicAdd(&counter[PH], 1);
+            ctl->tile = t;
+            // one read of the CFG's status for both wavefronts (another tile may fail meanwhile)
+            ctl->skip = t < n_tiles ? G(cfgs[tiles[t].cfg].info)[INFO_STATUS] != 0 : 1;
+            ctl->produced = 0; ctl->consumed = 0; ctl->flushed = 0; ctl->done = 0; ctl->abort = 0;
+            ctl->rec_filled = 0; ctl->in_ready = 0;
+        }
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(ctl->tile);
         if (t >= n_tiles) break;
         const Tile tl = tiles[t];
         const DevCfg c = cfgs[tl.cfg];
-        if (G(c.info)[INFO_STATUS] != 0) continue;
-        solve_phase<PH>(c, tl.s0, tl.nw, tl.fslot, ring, ring_words);
+        if (!__builtin_amdgcn_readfirstlane(ctl->skip)) solve_phase<PH>(c, tl.s0, tl.nw, tl.fslot, lds, ring_slots);
+        __syncthreads();
     }
 }
 
-// Work items of the edge steps: (tile, first block of a 64-block chunk),
-// claimed through counter slots 5 and 6.
-template <int STEP>
-__device__ __forceinline__ void edge_kernel(const DevCfg* __restrict__ cfgs, const Tile* __restrict__ tiles,
-                                            const EdgeItem* __restrict__ items, int n_items, int32_t* __restrict__ counter)
-{
-    for (;;) {
-        int it = 0;
-        if (threadIdx.x == 0) it = atomicAdd(&counter[5 + STEP], 1);
-        it = __builtin_amdgcn_readfirstlane(__shfl(it, 0, 64));
-        if (it >= n_items) break;
-        const EdgeItem item = items[it];
-        const Tile tl = tiles[item.tile];
-        const DevCfg c = cfgs[tl.cfg];
-        if (G(c.info)[INFO_STATUS] != 0 || tl.nw == 0) continue;
-        if (STEP == 1 && (c.placement & 1)) continue;   // the eager placement needs no pending-copy facts
-        edge_step<STEP>(c, tl.s0, tl.nw, item.b0);
-    }
-}
-
-// One persistent kernel per phase; the phases of all tiles run in this order.
+// One persistent kernel per phase (two wavefronts per tile); the phases of all tiles run in this order.
 #define OMPD_PHASE_KERNEL(name, ph)                                                                          \
-    extern "C" __global__ void __launch_bounds__(64) name(const DevCfg* __restrict__ cfgs,                  \
-                                                           const Tile* __restrict__ tiles, int n_tiles,     \
-                                                           int32_t* __restrict__ counter, int ring_words)   \
+    extern "C" __global__ void __launch_bounds__(128) name(const DevCfg* __restrict__ cfgs,                 \
+                                                            const Tile* __restrict__ tiles, int n_tiles,    \
+                                                            int32_t* __restrict__ counter, int ring_slots)  \
     {                                                                                                        \
-        phase_kernel<ph>(cfgs, tiles, n_tiles, counter, ring_words);                                         \
+        phase_kernel<ph>(cfgs, tiles, n_tiles, counter, ring_slots);                                         \
     }
 OMPD_PHASE_KERNEL(ompd_k_nu, PH_NU)
 OMPD_PHASE_KERNEL(ompd_k_ave, PH_AVE)
@@ -875,17 +1158,61 @@ OMPD_PHASE_KERNEL(ompd_k_mayp, PH_MAYP)
 OMPD_PHASE_KERNEL(ompd_k_later, PH_LATER)
 OMPD_PHASE_KERNEL(ompd_k_avf, PH_AVF)
 
-extern "C" __global__ void __launch_bounds__(64)
-ompd_k_edge0(const DevCfg* __restrict__ cfgs, const Tile* __restrict__ tiles, const EdgeItem* __restrict__ items,
-             int n_items, int32_t* __restrict__ counter)
+// Edge-parallel passes over (tile, chunk) items, claimed through counter slots 8..11.
+template <int PASS>
+__device__ __forceinline__ void pass_kernel(const DevCfg* __restrict__ cfgs, const Tile* __restrict__ tiles,
+                                            const EdgeItem* __restrict__ items, int n_items, int32_t* __restrict__ counter)
 {
-    edge_kernel<0>(cfgs, tiles, items, n_items, counter);
+    for (;;) {
+        int it = 0;
+        if (threadIdx.x == 0) it = atomicAdd(&counter[8 + PASS], 1);
+        it = __builtin_amdgcn_readfirstlane(__shfl(it, 0, 64));
+        if (it >= n_items) break;
+        const EdgeItem item = items[it];
+        const Tile tl = tiles[item.tile];
+        const DevCfg c = cfgs[tl.cfg];
+        if (G(c.info)[INFO_STATUS] != 0 || tl.nw == 0) continue;
+        if ((PASS == PASS_MAYP) && (c.placement & 1)) continue;   // the eager placement needs no pending copies
+        edge_pass<PASS>(c, tl.s0, tl.nw, tl.fslot, item.b0);
+    }
 }
-extern "C" __global__ void __launch_bounds__(64)
-ompd_k_edge1(const DevCfg* __restrict__ cfgs, const Tile* __restrict__ tiles, const EdgeItem* __restrict__ items,
-             int n_items, int32_t* __restrict__ counter)
+#define OMPD_PASS_KERNEL(name, pass)                                                                         \
+    extern "C" __global__ void __launch_bounds__(64) name(const DevCfg* __restrict__ cfgs,                  \
+                                                           const Tile* __restrict__ tiles,                  \
+                                                           const EdgeItem* __restrict__ items, int n_items, \
+                                                           int32_t* __restrict__ counter)                   \
+    {                                                                                                        \
+        pass_kernel<pass>(cfgs, tiles, items, n_items, counter);                                             \
+    }
+OMPD_PASS_KERNEL(ompd_k_post_ave, PASS_AVE)
+OMPD_PASS_KERNEL(ompd_k_post_mayp, PASS_MAYP)
+OMPD_PASS_KERNEL(ompd_k_post_later, PASS_LATER)
+OMPD_PASS_KERNEL(ompd_k_post_avf, PASS_AVF)
+
+// Map kinds from the masks: one wavefront per tile (claimed through counter
+// slot 12), one lane per variable of each of the tile's words.
+extern "C" __global__ void __launch_bounds__(64) ompd_k_varkind(const DevCfg* __restrict__ cfgs,
+                                                                 const Tile* __restrict__ tiles, int n_tiles,
+                                                                 int32_t* __restrict__ counter)
 {
-    edge_kernel<1>(cfgs, tiles, items, n_items, counter);
+    for (;;) {
+        int t = 0;
+        if (threadIdx.x == 0) t = atomicAdd(&counter[12], 1);
+        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0, 64));
+        if (t >= n_tiles) break;
+        const Tile tl = tiles[t];
+        const DevCfg c = cfgs[tl.cfg];
+        if (!c.var_kind || tl.nw == 0 || G(c.info)[INFO_STATUS] != 0) continue;
+        const GAS u64* acc = G(c.vk_acc);
+        for (int w = tl.s0; w < tl.s0 + tl.nw; ++w) {
+            const int v = w * 64 + (int)threadIdx.x;
+            if (v >= c.nv) break;
+            const int i = threadIdx.x;
+            const uint32_t t1 = (uint32_t)((acc[w] >> i) & 1), f1 = (uint32_t)((acc[c.wd + w] >> i) & 1);
+            const uint32_t d1 = (uint32_t)((acc[2 * c.wd + w] >> i) & 1);
+            G(c.var_kind)[v] = (uint8_t)(t1 | (f1 << 1) | ((d1 && !t1 && !f1) ? 4u : 0u));
+        }
+    }
 }
 
 }  // namespace ompd

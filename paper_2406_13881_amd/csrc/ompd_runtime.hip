@@ -22,10 +22,15 @@ extern "C" __global__ void ompd_k_ave(const DevCfg*, const Tile*, int, int32_t*,
 extern "C" __global__ void ompd_k_mayp(const DevCfg*, const Tile*, int, int32_t*, int);
 extern "C" __global__ void ompd_k_later(const DevCfg*, const Tile*, int, int32_t*, int);
 extern "C" __global__ void ompd_k_avf(const DevCfg*, const Tile*, int, int32_t*, int);
-extern "C" __global__ void ompd_k_edge0(const DevCfg*, const Tile*, const EdgeItem*, int, int32_t*);
-extern "C" __global__ void ompd_k_edge1(const DevCfg*, const Tile*, const EdgeItem*, int, int32_t*);
+extern "C" __global__ void ompd_k_post_ave(const DevCfg*, const Tile*, const EdgeItem*, int, int32_t*);
+extern "C" __global__ void ompd_k_post_mayp(const DevCfg*, const Tile*, const EdgeItem*, int, int32_t*);
+extern "C" __global__ void ompd_k_post_later(const DevCfg*, const Tile*, const EdgeItem*, int, int32_t*);
+extern "C" __global__ void ompd_k_post_avf(const DevCfg*, const Tile*, const EdgeItem*, int, int32_t*);
+extern "C" __global__ void ompd_k_varkind(const DevCfg*, const Tile*, int, int32_t*);
 static const void* const k_phases[5] = {(const void*)ompd_k_nu, (const void*)ompd_k_ave, (const void*)ompd_k_mayp,
                                         (const void*)ompd_k_later, (const void*)ompd_k_avf};
+// threads of a phase workgroup: the compute and the helper wavefront
+constexpr int PHASE_THREADS = 128;
 }  // namespace ompd
 
 using namespace ompd;
@@ -166,6 +171,7 @@ size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o)
     o.ie = (r.ins_entry_to_host && r.ins_entry_to_dev) ? SIZE_MAX : take(2 * bv);
     o.ig = (r.ins_edge_to_host && r.ins_edge_to_dev) ? SIZE_MAX : take(2 * ev);
     o.avf = (!r.avf_host == !r.avf_dev) ? SIZE_MAX : take(2 * bv);
+    o.vk = r.var_kind ? take(3 * wd * 8) : SIZE_MAX;
     o.bnd = take(4 * wd * 8);
     o.pp = take(4 * ((size_t)g.n_blocks + 1));
     o.pi = take(4 * (size_t)std::max(g.n_edges, 1));
@@ -221,6 +227,7 @@ void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const
     uint64_t* ea = at(o.eag);
     d.eag_h = ea; d.eag_d = ea + evw; d.both = at(o.both);
     d.flg = at(o.flg);
+    d.vk_acc = at(o.vk);
     d.pred_ptr = (int32_t*)(base + o.pp); d.pred_idx = (int32_t*)(base + o.pi);
     d.pred_eid = (int32_t*)(base + o.pe); d.tmp = (int32_t*)(base + o.tmp);
     d.rec_f = (int32_t*)(base + o.recf); d.rec_b = (int32_t*)(base + o.recb);
@@ -236,8 +243,8 @@ void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const
     }
 }
 
-// Default LDS of one solve wavefront: the ring of recently computed blocks.
-constexpr size_t RING_BYTES_DEFAULT = 8 * 1024;
+// Default result ring of one phase workgroup (recently computed blocks, 1 KiB each).
+constexpr size_t RING_BYTES_DEFAULT = 16 * 1024;
 
 // Tiles for a set of CFGs, longest first, the edge-step items and the launch
 // sizes that go with them under a configuration.
@@ -253,22 +260,26 @@ int ompd_make_shape(ompd_ctx* ctx, const std::vector<DevCfg>& cfgs, const PlanCo
     for (int t = 0; t < (int)tiles.size(); ++t)
         if (tiles[t].nw > 0)
             for (int b0 = 0; b0 < cfgs[tiles[t].cfg].nb; b0 += 64) sh.items.push_back(EdgeItem{t, b0});
-    size_t lds = pc.lds_bytes ? pc.lds_bytes : RING_BYTES_DEFAULT;
-    lds = std::min<size_t>(std::max<size_t>(lds, 1024), ctx->lds_max) & ~(size_t)255;
-    sh.lds_solve = lds;
+    // result ring: a power of two of 1 KiB slots in [8, 64], as large as every phase's LDS allows
+    const size_t want = pc.lds_bytes ? pc.lds_bytes : RING_BYTES_DEFAULT;
+    int rs = 8;
+    while (rs < 64 && (size_t)(2 * rs) * 1024 <= want) rs *= 2;
+    while (rs > 1 && phase_lds(PH_LATER, rs) > (size_t)ctx->lds_max) rs /= 2;
+    LaunchDims& dm = sh.dims;
+    dm.ring_slots = rs;
     sh.lds_prep = 0;
-    // one grid for every phase kernel: as many wavefronts as the tightest phase keeps resident
-    int per_cu = 1 << 20;
-    for (const void* k : k_phases) {
+    // each phase kernel: as many workgroups as it keeps resident
+    for (int ph = 0; ph < 5; ++ph) {
+        dm.lds[ph] = phase_lds(ph, rs);
         int n = 0;
-        CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64, lds));
-        per_cu = std::min(per_cu, std::max(1, n));
+        CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_phases[ph], PHASE_THREADS, dm.lds[ph]));
+        n = std::max(1, n);
+        if (pc.wg_per_cu > 0) n = std::min(n, pc.wg_per_cu);
+        dm.grid[ph] = std::max(1, std::min((int)tiles.size(), n * ctx->n_cu));
     }
-    if (pc.wg_per_cu > 0) per_cu = std::min(per_cu, pc.wg_per_cu);
-    sh.grid_solve = std::max(1, std::min((int)tiles.size(), per_cu * ctx->n_cu));
     int pe = 1;
-    CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pe, (const void*)ompd_k_edge0, 64, 0));
-    sh.grid_edge = std::max(1, std::min((int)sh.items.size(), std::max(1, pe) * ctx->n_cu));
+    CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pe, (const void*)ompd_k_post_ave, 64, 0));
+    dm.grid_edge = std::max(1, std::min((int)std::max<size_t>(sh.items.size(), tiles.size()), std::max(1, pe) * ctx->n_cu));
     return OMPD_OK;
 }
 
@@ -341,10 +352,8 @@ int ompd_plan_retile(ompd_plan* p, const PlanConfig& pc)
     int rc = ompd_make_shape(ctx, p->h_cfgs, pc, sh);
     if (rc) return rc;
     p->cfg = pc;
-    p->lds_solve = sh.lds_solve;
+    p->dims = sh.dims;
     p->lds_prep = sh.lds_prep;
-    p->grid_solve = sh.grid_solve;
-    p->grid_edge = sh.grid_edge;
     p->h_tiles = sh.tiles;
     p->n_tiles = (int)sh.tiles.size();
     p->n_items = (int)sh.items.size();
@@ -372,31 +381,41 @@ int ompd_launch_prep(const DevCfg* d_cfgs, int n, int32_t* d_counter, size_t lds
 }
 
 int ompd_launch_solve(const DevCfg* d_cfgs, const Tile* d_tiles, int n_tiles, const EdgeItem* d_items, int n_items,
-                      int32_t* d_counter, int grid, int grid_edge, size_t lds, hipStream_t s, hipEvent_t* after)
+                      int32_t* d_counter, const LaunchDims& dm, hipStream_t s, hipEvent_t* after)
 {
     if (n_tiles <= 0) return OMPD_OK;
-    const int rw = (int)(lds / 8);
-    auto mark = [&](int k) { if (after) (void)hipEventRecord(after[k], s); };
-    hipLaunchKernelGGL(ompd_k_nu, dim3(grid), dim3(64), lds, s, d_cfgs, d_tiles, n_tiles, d_counter, rw);
-    mark(0);
-    hipLaunchKernelGGL(ompd_k_ave, dim3(grid), dim3(64), lds, s, d_cfgs, d_tiles, n_tiles, d_counter, rw);
-    mark(1);
-    if (n_items > 0)
-        hipLaunchKernelGGL(ompd_k_edge0, dim3(grid_edge), dim3(64), 0, s, d_cfgs, d_tiles, d_items, n_items, d_counter);
-    mark(2);
-    hipLaunchKernelGGL(ompd_k_mayp, dim3(grid), dim3(64), lds, s, d_cfgs, d_tiles, n_tiles, d_counter, rw);
-    mark(3);
-    if (n_items > 0)
-        hipLaunchKernelGGL(ompd_k_edge1, dim3(grid_edge), dim3(64), 0, s, d_cfgs, d_tiles, d_items, n_items, d_counter);
-    mark(4);
-    hipLaunchKernelGGL(ompd_k_later, dim3(grid), dim3(64), lds, s, d_cfgs, d_tiles, n_tiles, d_counter, rw);
-    mark(5);
-    hipLaunchKernelGGL(ompd_k_avf, dim3(grid), dim3(64), lds, s, d_cfgs, d_tiles, n_tiles, d_counter, rw);
-    mark(6);
+    const int rs = dm.ring_slots, grid_edge = dm.grid_edge;
+    int k = 0;
+    auto mark = [&]() { if (after) (void)hipEventRecord(after[k], s); ++k; };
+    int ph = 0;
+    auto phase = [&](const void* fn) {
+        void* args[] = {(void*)&d_cfgs, (void*)&d_tiles, (void*)&n_tiles, (void*)&d_counter, (void*)&rs};
+        (void)hipLaunchKernel(fn, dim3(dm.grid[ph]), dim3(PHASE_THREADS), args, dm.lds[ph], s);
+        ++ph;
+        mark();
+    };
+    auto pass = [&](const void* fn) {
+        if (n_items > 0) {
+            void* args[] = {(void*)&d_cfgs, (void*)&d_tiles, (void*)&d_items, (void*)&n_items, (void*)&d_counter};
+            (void)hipLaunchKernel(fn, dim3(grid_edge), dim3(64), args, 0, s);
+        }
+        mark();
+    };
+    phase((const void*)ompd_k_nu);
+    phase((const void*)ompd_k_ave);
+    pass((const void*)ompd_k_post_ave);
+    phase((const void*)ompd_k_mayp);
+    pass((const void*)ompd_k_post_mayp);
+    phase((const void*)ompd_k_later);
+    pass((const void*)ompd_k_post_later);
+    phase((const void*)ompd_k_avf);
+    pass((const void*)ompd_k_post_avf);
+    hipLaunchKernelGGL(ompd_k_varkind, dim3(grid_edge), dim3(64), 0, s, d_cfgs, d_tiles, n_tiles, d_counter);
+    mark();
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
-        return ompd_fail(OMPD_E_DEVICE, std::string("solve launch (grid ") + std::to_string(grid) + ", lds " +
-                                            std::to_string(lds) + "): " + hipGetErrorString(e));
+        return ompd_fail(OMPD_E_DEVICE, std::string("solve launch (ring slots ") + std::to_string(rs) + "): " +
+                                            hipGetErrorString(e));
     return OMPD_OK;
 }
 
@@ -408,8 +427,7 @@ static int launch_prep(ompd_plan* p, hipStream_t s)
 static int launch_solve(ompd_plan* p, hipStream_t s)
 {
     return ompd_launch_solve((const DevCfg*)p->d_cfgs, (const Tile*)p->d_tiles, p->n_tiles,
-                             (const EdgeItem*)p->d_items, p->n_items, p->d_counter, p->grid_solve, p->grid_edge,
-                             p->lds_solve, s);
+                             (const EdgeItem*)p->d_items, p->n_items, p->d_counter, p->dims, s);
 }
 
 // Capture one launch function into an executable graph (nullptr if capture
@@ -468,8 +486,7 @@ static int launch_all(ompd_plan* p, hipStream_t s)
         if (rc) return rc;
         CK(hipEventRecord(p->ev1, s));
         rc = ompd_launch_solve((const DevCfg*)p->d_cfgs, (const Tile*)p->d_tiles, p->n_tiles,
-                               (const EdgeItem*)p->d_items, p->n_items, p->d_counter, p->grid_solve, p->grid_edge,
-                               p->lds_solve, s, p->evk);
+                               (const EdgeItem*)p->d_items, p->n_items, p->d_counter, p->dims, s, p->evk);
         if (rc) return rc;
         CK(hipEventRecord(p->ev2, s));
         return OMPD_OK;
@@ -568,9 +585,10 @@ extern "C" int ompd_plan_kernel_ms(ompd_plan* p, float* ms, int32_t capacity, in
     if (!p || !ms) return ompd_fail(OMPD_E_INVAL, "bad arguments");
     if (!p->profile) return ompd_fail(OMPD_E_INVAL, "profiling is off for this plan");
     CK(hipEventSynchronize(p->ev2));
-    const int n = 8;
+    const int n = 1 + N_SOLVE_KERNELS;
     if (n_kernels) *n_kernels = n;
-    hipEvent_t marks[9] = {p->ev0, p->ev1, p->evk[0], p->evk[1], p->evk[2], p->evk[3], p->evk[4], p->evk[5], p->evk[6]};
+    hipEvent_t marks[2 + N_SOLVE_KERNELS] = {p->ev0, p->ev1};
+    for (int k = 0; k < N_SOLVE_KERNELS; ++k) marks[2 + k] = p->evk[k];
     for (int k = 0; k < n && k < capacity; ++k) {
         float x = 0;
         CK(hipEventElapsedTime(&x, marks[k], marks[k + 1]));
@@ -596,9 +614,10 @@ extern "C" int ompd_plan_describe(ompd_plan* p, char* buf, int32_t len)
     long lanes = 0;
     for (const Tile& t : p->h_tiles) lanes += t.nw;
     snprintf(buf, len,
-             "{\"cfgs\": %d, \"tiles\": %d, \"words\": %ld, \"lds_solve\": %zu, \"grid_solve\": %d, "
+             "{\"cfgs\": %d, \"tiles\": %d, \"words\": %ld, \"ring_slots\": %d, \"grid_phases\": [%d, %d, %d, %d, %d], "
              "\"lds_bytes\": %zu, \"wg_per_cu\": %d, \"graph\": %d, \"scratch_bytes\": %zu}",
-             p->n, p->n_tiles, lanes, p->lds_solve, p->grid_solve, p->cfg.lds_bytes, p->cfg.wg_per_cu,
+             p->n, p->n_tiles, lanes, p->dims.ring_slots, p->dims.grid[0], p->dims.grid[1], p->dims.grid[2],
+             p->dims.grid[3], p->dims.grid[4], p->cfg.lds_bytes, p->cfg.wg_per_cu,
              p->cfg.use_graph ? 1 : 0, p->scratch_bytes);
     return OMPD_OK;
 }
@@ -631,10 +650,8 @@ extern "C" int ompd_plan_autotune(ompd_plan* p, void* stream, int32_t trials, fl
     hipStream_t s = (hipStream_t)stream;
     trials = std::max(1, trials);
     std::vector<PlanConfig> cands;
-    const size_t lds_cap = (size_t)p->ctx->lds_max;
-    for (size_t lds : {(size_t)2048, (size_t)4096, (size_t)8192, (size_t)16384, (size_t)32768}) {
-        if (lds > lds_cap) continue;
-        for (int wpc : {0, 8, 16}) {
+    for (size_t lds : {(size_t)8192, (size_t)16384, (size_t)32768}) {
+        for (int wpc : {0, 2, 4}) {
             PlanConfig c = p->cfg;
             c.lds_bytes = lds;
             c.wg_per_cu = wpc;

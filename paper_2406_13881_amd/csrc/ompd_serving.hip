@@ -218,7 +218,7 @@ static void launcher_main(ServingState* S)
             if (rc == OMPD_OK)
                 rc = ompd_launch_solve((const DevCfg*)dtab, (const Tile*)(dtab + cfg_bytes), (int)tiles.size(),
                                        (const EdgeItem*)(dtab + cfg_bytes + (tile_bytes - item_bytes)),
-                                       (int)sh.items.size(), counter, sh.grid_solve, sh.grid_edge, sh.lds_solve, s);
+                                       (int)sh.items.size(), counter, sh.dims, s);
             // per-request status words back to pinned memory
             st->info_pin_off = st->pin_off + cfg_bytes + tile_bytes;
             for (int i = 0; i < k && rc == OMPD_OK; ++i)
