@@ -175,6 +175,8 @@ def kernel_bytes(cfgs):
         out["ompd_k_avf"] += 3 * bv + 2 * ev + 2 * bv          # copies before blocks, W, copies on edges in; validity after out
         out["ompd_k_post_avf"] += 2 * bv + 2 * ev + 4 * bv + 2 * bv + 3 * wd * 8   # copies, validity after, R, W in; validity before, map masks out
         out["ompd_k_varkind"] += 3 * wd * 8 + c.n_vars         # map masks in; map kinds out
+    # the per-tile kernel runs every phase and pass
+    out["ompd_k_solve"] = sum(v for k, v in out.items() if k != "ompd_k_prep")
     return out
 
 

@@ -67,6 +67,8 @@ enum { OMPD_MAP_TO = 1, OMPD_MAP_FROM = 2, OMPD_MAP_ALLOC = 4 };          /* var
 #define OMPD_F_PLACEMENT_EAGER (1u << 1)  /* materialise every eager copy (no delay)         */
 #define OMPD_F_SUMMARY (1u << 2)          /* procedure-summary evaluation: the entry boundary may
                                              leave variables valid in neither space            */
+#define OMPD_F_TILE_KERNEL (1u << 3)      /* one persistent kernel runs every phase of a tile
+                                             (same results) instead of one kernel per phase */
 #define OMPD_F_SWEEP_CAP(n) ((((uint32_t)(n)) & 0xFFFFu) << 16) /* cap sweeps per phase */
 
 /* ---- one procedure ----------------------------------------------------
@@ -192,10 +194,16 @@ int ompd_plan_configure(ompd_plan* plan, int64_t lds_bytes, int32_t wg_per_cu);
  * last run, in launch order: ingest, next use, validity, validity pass
  * (AVEin, eager copies), pending copies, pending pass (valid in both
  * spaces), delayed placement, placement pass (the copies), final
- * validity, final pass (AVFin, map-kind masks), map kinds
- * (*n_kernels = 11; at most `capacity` are written).  OMPD_E_INVAL if
- * profiling is off. */
+ * validity, final pass (AVFin, map-kind masks), map kinds (*n_kernels =
+ * 11), or ingest and the per-tile kernel (*n_kernels = 2) after
+ * ompd_plan_split_kernels(plan, 0).  At most `capacity` are written.
+ * OMPD_E_INVAL if profiling is off. */
 int ompd_plan_profile(ompd_plan* plan, int32_t enable);
+/* Launch layout; results are identical either way.  By default (split !=
+ * 0) one kernel per phase and per pass runs over all tiles; with split ==
+ * 0 one persistent kernel runs every phase and pass of a tile, tile after
+ * tile.  OMPD_E_INVAL for a NULL plan. */
+int ompd_plan_split_kernels(ompd_plan* plan, int32_t split);
 int ompd_plan_kernel_ms(ompd_plan* plan, float* ms, int32_t capacity, int32_t* n_kernels);
 /* Describe the plan's current configuration as a NUL-terminated string. */
 int ompd_plan_describe(ompd_plan* plan, char* buf, int32_t len);

@@ -38,6 +38,7 @@ OMPD_E_TIMEOUT = -7
 
 F_DEVICE_PTRS = 1 << 0
 F_PLACEMENT_EAGER = 1 << 1
+F_TILE_KERNEL = 1 << 3
 
 
 def F_SWEEP_CAP(n: int) -> int:
@@ -133,6 +134,7 @@ def lib():
             L.ompd_plan_describe.argtypes = [_vp, ctypes.c_char_p, _i32]
             L.ompd_plan_configure.argtypes = [_vp, ctypes.c_int64, _i32]
             L.ompd_plan_profile.argtypes = [_vp, _i32]
+            L.ompd_plan_split_kernels.argtypes = [_vp, _i32]
             L.ompd_plan_kernel_ms.argtypes = [_vp, P(ctypes.c_float), _i32, P(_i32)]
             L.ompd_plan_last_ms.argtypes = [_vp, P(ctypes.c_float), P(ctypes.c_float)]
             L.ompd_plan_destroy.argtypes = [_vp]
@@ -508,6 +510,11 @@ class Plan:
 
     KERNELS = ("ompd_k_prep", "ompd_k_nu", "ompd_k_ave", "ompd_k_post_ave", "ompd_k_mayp", "ompd_k_post_mayp",
                "ompd_k_later", "ompd_k_post_later", "ompd_k_avf", "ompd_k_post_avf", "ompd_k_varkind")
+    KERNELS_TILE = ("ompd_k_prep", "ompd_k_solve")
+
+    def split_kernels(self, split: bool = True):
+        """One kernel per phase and pass (the default), or one per-tile kernel for every phase."""
+        _check(lib().ompd_plan_split_kernels(self.h, 1 if split else 0))
 
     def profile(self, enable: bool = True):
         """Time every kernel of the following runs with HIP events on their stream."""
@@ -518,7 +525,8 @@ class Plan:
         buf = (ctypes.c_float * 16)()
         n = _i32(0)
         _check(lib().ompd_plan_kernel_ms(self.h, buf, 16, ctypes.byref(n)))
-        return {k: float(buf[i]) for i, k in enumerate(self.KERNELS[:n.value])}
+        names = self.KERNELS if n.value == len(self.KERNELS) else self.KERNELS_TILE
+        return {k: float(buf[i]) for i, k in enumerate(names[:n.value])}
 
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(1024)

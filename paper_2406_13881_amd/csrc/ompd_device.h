@@ -88,16 +88,19 @@ struct EdgeItem {
 // words split as evenly as possible.
 inline int tiles_of(int wd) { return wd <= 0 ? 1 : (wd + TILE_WORDS - 1) / TILE_WORDS; }
 
-// LDS of a phase workgroup: CTL_BYTES of coordination words, the ring of the
-// next REC_RING block records (32 bytes each), the ring of the last RS
-// results (1 KiB each), then the inputs of the next IN_RING steps
-// (phase_inputs(ph) words of 512 bytes each).
+// LDS of a phase workgroup: CTL_BYTES of coordination words, the ring of
+// the last RS results (1 KiB each), the inputs of the next in_ring(ph)
+// steps (phase_inputs(ph) words of 512 bytes each), their 16-byte
+// descriptors, then one state of identity words (1 KiB).
 constexpr int CTL_BYTES = 256;
-constexpr int REC_RING = 128;
-constexpr int IN_RING = 8;
-constexpr int LDS_FIXED = CTL_BYTES + 32 * REC_RING;
+constexpr int LDS_FIXED = CTL_BYTES;
+// steps of inputs kept ready per phase (a power of two; more for the phases with fewer inputs)
+constexpr int in_ring(int ph) { return ph == PH_NU || ph == PH_AVE ? 16 : 8; }
 inline int phase_inputs(int ph) { return 2 + (ph == PH_NU ? 2 : ph == PH_AVE ? 3 : ph == PH_MAYP ? 6 : ph == PH_LATER ? 8 : 7); }
-inline size_t phase_lds(int ph, int ring_slots) { return LDS_FIXED + (size_t)ring_slots * 1024 + (size_t)IN_RING * phase_inputs(ph) * 512; }
+inline size_t phase_lds(int ph, int ring_slots)
+{
+    return LDS_FIXED + (size_t)ring_slots * 1024 + (size_t)in_ring(ph) * (phase_inputs(ph) * 512 + 16) + 1024;
+}
 // Work counters (int32) of one solve launch: phases 0..4, passes 8..11, map kinds 12.
 constexpr int N_COUNTERS = 16;
 // Kernels of one solve launch, in launch order (prep excluded).

@@ -29,15 +29,19 @@ struct ompd_ctx {
 // LDS bytes and grid, and the grid of the pass kernels.
 struct LaunchDims {
     int ring_slots = 16;
+    bool split = true;           // one kernel per phase and pass (else the per-tile kernel)
     size_t lds[5] = {0, 0, 0, 0, 0};
     int grid[5] = {1, 1, 1, 1, 1};
     int grid_edge = 1;
+    size_t lds_tile = 0;         // the per-tile kernel: LDS of its largest phase
+    int grid_tile = 1;
 };
 
 // Tunable launch configuration of a plan; results never depend on it.
 struct PlanConfig {
     size_t lds_bytes = 0;   // bytes of the result ring per phase workgroup (0 = default)
     int wg_per_cu = 0;      // phase workgroups per CU (0 = as many as fit)
+    bool split = true;      // one kernel per phase and pass (else one per-tile kernel)
     bool use_graph = true;  // replay a captured HIP graph
 };
 

@@ -239,6 +239,15 @@ struct Rec {
     int32_t pad;
 };
 
+// Step descriptor: x flags, y and z the LDS byte offsets of the states of neighbours 0 and 1
+// (a ring slot, the step's far input, or the identity state), w the block.  Flag bits 0-1 / 2-3:
+// where neighbour 0 / 1 is found: 0 nowhere (missing), 1 the block computed last, 2 the ring,
+// 3 the far input.
+constexpr uint32_t DF_SLOW = 1u << 4;   // ENTRY, EXIT, a call, no or more than two neighbours, two far ones
+constexpr uint32_t DF_DEV = 1u << 5;    // a DEVICE block
+constexpr uint32_t DF_LE0 = 1u << 6;    // edge of neighbour 0 is a loop entry (forward phases)
+constexpr uint32_t DF_LE1 = 1u << 7;    // edge of neighbour 1 is a loop entry
+
 template <typename T>
 __device__ __forceinline__ const CAS T* K(const T* p) { return (const CAS T*)p; }
 
@@ -296,8 +305,7 @@ struct Ctl {
     int flushed;     // steps whose state-row stores have completed
     int done;        // the compute wavefront has finished the phase
     int abort;       // a wait ran out: both wavefronts stop
-    int rec_filled;  // steps whose block record is in the record ring (helper)
-    int in_ready;    // steps whose inputs are in the input ring (helper)
+    int in_ready;    // steps whose inputs and descriptors are in LDS (helper)
 };
 constexpr int CTL_WORDS = CTL_BYTES / 8;   // u64 words reserved for Ctl at the start of the LDS
 static_assert(sizeof(Ctl) <= CTL_BYTES, "coordination words");
@@ -348,7 +356,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     constexpr bool BWD = PH == PH_NU;
     constexpr int NX = PH == PH_NU ? 2 : PH == PH_AVE ? 3 : PH == PH_MAYP ? 6 : PH == PH_LATER ? 8 : 7;
     constexpr int NI = NX + 2;        // inputs of a step: the phase's own and the first far neighbour (h, d)
-    constexpr int IR = IN_RING;       // steps whose inputs the helper keeps ready
+    constexpr int IR = in_ring(PH);   // steps whose inputs the helper keeps ready
     const int lane = threadIdx.x & 63;
     const bool helper = threadIdx.x >= 64;
     const int nb = c.nb, wd = c.wd;
@@ -356,9 +364,15 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     const bool dat = lane < nw, flg = with_flags && (lane == nw || nw == 0), act = dat || flg;
     const int w = s0 + (dat ? lane : 0);
     Ctl* ctl = reinterpret_cast<Ctl*>(lds);
-    int4* rring = reinterpret_cast<int4*>(lds + CTL_WORDS);   // REC_RING records of 2 int4
-    u64* ring = lds + CTL_WORDS + REC_RING * 4;               // RS steps of results (h, d)
-    u64* iring = ring + (size_t)RS * 128;                     // IR steps of inputs (NI words)
+    // Every 64-bit per-lane word in LDS is stored split: 64 low halves, then 64 high halves
+    // (512 bytes); a state (h, d) is two such words (1 KiB).
+    char* lds8 = reinterpret_cast<char*>(lds);
+    constexpr int RING_OFF = CTL_BYTES;                                   // RS states: the last results
+    const int IN_OFF = RING_OFF + RS * 1024;                              // IR steps of NI input words
+    const int DESC_OFF = IN_OFF + IR * NI * 512;                          // IR step descriptors
+    const int IDENT_OFF = DESC_OFF + IR * 16;                             // one state of identity words
+    u64* iring = reinterpret_cast<u64*>(lds8 + IN_OFF);
+    int4* dring = reinterpret_cast<int4*>(lds8 + DESC_OFF);
     // valid-variable mask of the lane's word (shadow lanes share word s0's; the flag lane uses bits 0-1)
     const u64 vm = flg ? 3ull : ((w == wd - 1 && (c.nv & 63)) ? ((1ull << (c.nv & 63)) - 1ull) : ~0ull);
     const int cap = c.sweep_cap > 0 ? c.sweep_cap : 2 * nb + 2;
@@ -382,9 +396,19 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         else { r.h = G(h) + wo; r.d = G(d) + wo; r.str = wd; }
         return r;
     };
-    u64* rg = ring + lane;
-    auto slot_h = [&](int g) -> u64& { return rg[(size_t)(g & (RS - 1)) * 128]; };
-    auto slot_d = [&](int g) -> u64& { return rg[(size_t)(g & (RS - 1)) * 128 + 64]; };
+    // the word at LDS byte offset `at` (split layout), this lane's
+    auto w_get = [&](int at) -> u64 {
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(lds8 + at) + lane;
+        return (u64)q[0] | ((u64)q[64] << 32);
+    };
+    auto w_put = [&](int at, u64 v) {
+        uint32_t* q = reinterpret_cast<uint32_t*>(lds8 + at) + lane;
+        q[0] = (uint32_t)v;
+        q[64] = (uint32_t)(v >> 32);
+    };
+    auto ring_at = [&](int g) -> int { return RING_OFF + (g & (RS - 1)) * 1024; };   // state of step g
+    auto slot_h = [&](int g) -> u64 { return w_get(ring_at(g)); };
+    auto slot_d = [&](int g) -> u64 { return w_get(ring_at(g) + 512); };
     // input k of step g: 64 low halves, then 64 high halves
     uint32_t* iring32 = reinterpret_cast<uint32_t*>(iring);
     auto in32 = [&](int g, int k) -> uint32_t* { return iring32 + ((size_t)(g & (IR - 1)) * NI + k) * 128; };
@@ -419,85 +443,85 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         if (cnt > 1) { const int dd = dist(b, r.n1); if (is_far(dd)) { p = r.n1; d = dd; return true; } }
         return false;
     };
-    // record of step g from the record ring
-    auto rec_at = [&](int g) -> Rec {
-        const int4* q = rring + 2 * (g & (REC_RING - 1));
-        const int4 a = q[0], z = q[1];
-        Rec r;
-        r.meta = (uint32_t)__builtin_amdgcn_readfirstlane(a.x);
-        r.n0 = __builtin_amdgcn_readfirstlane(a.y);
-        r.n1 = __builtin_amdgcn_readfirstlane(a.z);
-        r.e0 = (uint32_t)__builtin_amdgcn_readfirstlane(a.w);
-        r.e1 = (uint32_t)__builtin_amdgcn_readfirstlane(z.x);
-        r.ovf = __builtin_amdgcn_readfirstlane(z.y);
-        r.ci = __builtin_amdgcn_readfirstlane(z.z);
-        r.pad = 0;
-        return r;
-    };
-
     // ---------------------------------------------------------------- helper wavefront
-    // Each round: keeps the record ring filled (32 records at a time, lane l loads half
-    // l & 1 of the record of step rf + l / 2); loads the inputs of up to IR steps ahead of the
-    // compute wavefront; stores the results the compute wavefront has put in the ring since
-    // the last round; waits for all of it; then publishes the inputs and how far the ring may
-    // be reused and the rows read.
+    // Each round: plans the steps up to IR ahead of the compute wavefront (block records through
+    // the scalar cache; each step's descriptor and, when it is not in the rows, its far
+    // neighbour's state go to LDS); stores the results the compute wavefront has put in the ring
+    // since the last round; copies the other inputs from global memory straight into LDS; waits
+    // for all of it; then publishes the inputs and how far the ring may be reused and the rows
+    // read.
     // The far neighbour of step s was last computed at step u (this sweep, or the previous one
     // when it is not yet visited): from the rows when u was stored in an earlier round, from the
     // ring when it is computed but not stored yet (its slot is not released before this round
     // ends), the initial value in the first sweep.  Steps whose u is not computed yet wait.
+    // far neighbour of the block b of step st: p, and the step u of its state (-1: the initial value)
+    auto far_of = [&](const Rec& r, int b, int st, int& p) -> int {
+        int d = 0;
+        p = b;
+        if (!first_far(r, b, p, d)) return -1;
+        return d > 0 ? st - d : (st >= nb ? st - d - nb : -1);
+    };
     auto helper_loop = [&](const Rows& S, u64 init, auto&& pre) {
         int gf = 0, fi = 0;   // next step to store and its index within the sweep
-        int rf = 0, ri = 0;   // next step whose record is loaded and its index within the sweep
         int pf = 0, pi = 0;   // next step whose inputs are loaded and its index within the sweep
         int spins = 0;
         for (;;) {
             const int prod = __builtin_amdgcn_readfirstlane(lds_get(&ctl->produced));
             lds_acquire();
-            const int low = prod < pf ? prod : pf;
-            if (rf < pf + IR + 1 && rf + 32 <= low + REC_RING) {
-                int li = ri + (lane >> 1);
-                while (li >= nb) li -= nb;
-                const int b = blk(li);
-                const GAS int32_t* q = G(REC) + 8 * (size_t)b + 4 * (lane & 1);
-                int4 v;
-                v.x = q[0]; v.y = q[1]; v.z = q[2]; v.w = q[3];
-                rring[2 * ((rf + (lane >> 1)) & (REC_RING - 1)) + (lane & 1)] = v;
-                rf += 32;
-                ri += 32;
-                while (ri >= nb) ri -= nb;
-                lds_release();
-                lds_put(&ctl->rec_filled, rf);
-                spins = 0;
-                continue;
-            }
             const int fend = prod < gf + 32 ? prod : gf + 32;
-            int pend = prod + IR < rf ? prod + IR : rf;
-            if (pend > pf + IR) pend = pf + IR;
-            // plan steps pf .. pf + n - 1 (records and far-neighbour sources; LDS reads only)
-            int src[IR], at[IR], fp_[IR], bl[IR];   // far: 0 initial value, 1 rows of block fp_, 2 ring slot at
-            uint32_t rm[IR], re0[IR], re1[IR];       // what the input addresses need of the records
+            const int pend = prod < pf ? prod + IR : pf + IR;   // input slots free
+            const int gf0 = gf;
+            // plan: descriptors, and far values that do not come from the rows (LDS writes only)
             int n = 0;
             bool stop = false;
+            for (int s4 = pf, l4 = pi; s4 < pend && !stop; s4 += 4) {
+                Rec r4[4];
+                int b4[4];
 #pragma unroll
-            for (int t = 0; t < IR; ++t) {
-                const int st = pf + t;
-                src[t] = 0; at[t] = 0; fp_[t] = 0; bl[t] = 0; rm[t] = 0; re0[t] = 0; re1[t] = 0;
-                if (!stop && st < pend) {
-                    int li = pi + t;
-                    while (li >= nb) li -= nb;
-                    const int b = blk(li);
-                    const Rec r = rec_at(st);
-                    int p = b, d = 0, u = -1;
-                    if (first_far(r, b, p, d)) u = d > 0 ? st - d : (st >= nb ? st - d - nb : -1);
-                    if (u >= prod) stop = true;   // not computed yet
-                    else {
-                        src[t] = u < 0 ? 0 : u < gf ? 1 : 2;
-                        at[t] = u;
-                        fp_[t] = p;
-                        bl[t] = b;
-                        rm[t] = r.meta; re0[t] = r.e0; re1[t] = r.e1;
-                        ++n;
+                for (int q = 0; q < 4; ++q) {   // four records in flight
+                    int lq = l4 + q;
+                    while (lq >= nb) lq -= nb;
+                    b4[q] = blk(lq);
+                    if (s4 + q < pend) r4[q] = ldrec(REC, b4[q]);
+                }
+                l4 += 4;
+                while (l4 >= nb) l4 -= nb;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int st = s4 + q;
+                    if (stop || st >= pend) break;
+                    const int b = b4[q];
+                    const Rec& r = r4[q];
+                    int p;
+                    const int u = far_of(r, b, st, p);
+                    if (u >= prod) { stop = true; break; }   // not computed yet
+                    const int cnt = (int)(r.meta & REC_COUNT);
+                    uint32_t fl = (cnt > 2 || cnt == 0 || (r.meta & (REC_ENTRY | REC_EXIT | REC_CALL))) ? DF_SLOW : 0u;
+                    fl |= (r.meta & REC_DEV) ? DF_DEV : 0u;
+                    fl |= (r.e0 & 0x80000000u) ? DF_LE0 : 0u;
+                    fl |= ((r.e1 & 0x80000000u) && cnt > 1) ? DF_LE1 : 0u;
+                    int loc[2] = {IDENT_OFF, IDENT_OFF};   // where the state of each neighbour is found
+                    bool far = false;
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        if (j < cnt) {
+                            const int dj = dist(b, j == 0 ? r.n0 : r.n1);
+                            uint32_t k;
+                            if (dj == 1) k = 1;
+                            else if (dj >= 2 && dj <= RS) { k = 2; loc[j] = ring_at(st - dj); }
+                            else if (!far) { k = 3; far = true; loc[j] = IN_OFF + ((st & (IR - 1)) * NI + NX) * 512; }
+                            else { k = 0; fl |= DF_SLOW; }
+                            fl |= k << (2 * j);
+                        }
                     }
+                    if (u < 0 || u >= gf0) {
+                        const u64 h = u < 0 ? init : slot_h(u), d = u < 0 ? init : slot_d(u);
+                        uint32_t* qq = in32(st, NX) + lane;
+                        qq[0] = (uint32_t)h; qq[64] = (uint32_t)(h >> 32);
+                        qq[128] = (uint32_t)d; qq[192] = (uint32_t)(d >> 32);
+                    }
+                    if (lane == 0) dring[st & (IR - 1)] = make_int4((int)fl, loc[0], loc[1], b);
+                    ++n;
                 }
             }
             // nothing to store and nothing that can be loaded yet (the prefetch may also be waiting
@@ -513,36 +537,49 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 continue;
             }
             spins = 0;
-            // far values from the ring (not stored yet; their slots stay until this round ends) or
-            // the initial value, straight into the input slots
-            for (int t = 0; t < n; ++t) {
-                if (src[t] != 1) {
-                    const u64 h = src[t] == 2 ? slot_h(at[t]) : init, d = src[t] == 2 ? slot_d(at[t]) : init;
-                    uint32_t* q = in32(pf + t, NX) + lane;
-                    q[0] = (uint32_t)h; q[64] = (uint32_t)(h >> 32);
-                    q[128] = (uint32_t)d; q[192] = (uint32_t)(d >> 32);
+            // results of steps gf .. fend - 1 to the rows, eight ring reads in flight at a time
+            while (gf < fend) {
+                u64 h[8], d[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) { h[t] = slot_h(gf + t); d[t] = slot_d(gf + t); }
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    if (gf < fend) {
+                        if (act) S.st(blk(fi), h[t], d[t]);
+                        fi = fi + 1 == nb ? 0 : fi + 1;
+                        ++gf;
+                    }
                 }
-            }
-            // results of steps gf .. fend - 1 to the rows
-            for (; gf < fend; ++gf) {
-                const int b = blk(fi);
-                const u64 h = slot_h(gf), d = slot_d(gf);
-                if (act) S.st(b, h, d);
-                fi = fi + 1 == nb ? 0 : fi + 1;
             }
             // the other inputs: copies from global memory straight into the input slots (no LDS read
             // follows them before the wait); far rows past the first-level cache (the helper stored them)
-            for (int t = 0; t < n; ++t) {
-                const int st = pf + t;
-                Rec r;
-                r.meta = rm[t]; r.e0 = re0[t]; r.e1 = re1[t]; r.n0 = 0; r.n1 = 0; r.ovf = 0; r.ci = -1; r.pad = 0;
-                const GAS u64* a[NX];
-                pre(bl[t], r, a);
+            for (int t4 = 0, l4 = pi; t4 < n; t4 += 4) {
+                Rec r4[4];
+                int b4[4];
 #pragma unroll
-                for (int k = 0; k < NX; ++k) dma64<0>(a[k], in32(st, k));
-                if (src[t] == 1) {
-                    dma64<CPOL_SC1>(S.h + (size_t)fp_[t] * S.str, in32(st, NX));
-                    dma64<CPOL_SC1>(S.d + (size_t)fp_[t] * S.str, in32(st, NX + 1));
+                for (int q = 0; q < 4; ++q) {   // four records in flight
+                    int lq = l4 + q;
+                    while (lq >= nb) lq -= nb;
+                    b4[q] = blk(lq);
+                    if (t4 + q < n) r4[q] = ldrec(REC, b4[q]);
+                }
+                l4 += 4;
+                while (l4 >= nb) l4 -= nb;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (t4 + q < n) {
+                        const int st = pf + t4 + q, b = b4[q];
+                        const GAS u64* a[NX];
+                        pre(b, r4[q], a);
+#pragma unroll
+                        for (int k = 0; k < NX; ++k) dma64<0>(a[k], in32(st, k));
+                        int p;
+                        const int u = far_of(r4[q], b, st, p);
+                        if (u >= 0 && u < gf0) {
+                            dma64<CPOL_SC1>(S.h + (size_t)p * S.str, in32(st, NX));
+                            dma64<CPOL_SC1>(S.d + (size_t)p * S.str, in32(st, NX + 1));
+                        }
+                    }
                 }
             }
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -558,7 +595,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
 
     // ---------------------------------------------------------------- compute wavefront
     int gbase = 0;          // global step index of the current sweep's first step
-    int cons = 0, flsh = 0, rcf = 0, inr = 0;   // last seen helper progress
+    int cons = 0, flsh = 0, inr = 0;   // last seen helper progress
     bool ok = true;
     // wait (bounded) until the helper's counter *p exceeds g; `seen` caches its last value
     auto need = [&](int* p, int& seen, int g) {
@@ -567,17 +604,6 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         if (seen > g) { lds_acquire(); return; }
         if (!wait_for(p, g + 1, &ctl->abort)) ok = false;
         seen = g + 1;
-    };
-    // record of the block of step g (a record without neighbours once the helper has stopped:
-    // every access stays in bounds)
-    auto recl = [&](int g) -> Rec {
-        need(&ctl->rec_filled, rcf, g);
-        if (!ok) {
-            Rec r;
-            r.meta = 0; r.n0 = 0; r.n1 = 0; r.e0 = 0; r.e1 = 0; r.ovf = 0; r.ci = -1; r.pad = 0;
-            return r;
-        }
-        return rec_at(g);
     };
     // neighbour p at distance d of the block of step g, from the rows: the previous sweep's (or
     // the initial value in sweep 0) for a block not yet visited, this sweep's for one visited
@@ -589,55 +615,91 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         dd = settle(S.ldd(p));
     };
 
-    // One sweep: comp(b, r, x, nh, nd, ph, pd, sweep, g, vh, vd) computes the new state of the
-    // block of step g from its inputs x and its first two neighbours' states nh, nd.
-    auto walk = [&](const Rows& S, u64 init, int sweep, uint32_t& pc, auto&& comp) {
-        constexpr int dir = BWD ? -1 : 1;
-        u64 ph = init, pd = init;                           // state of the block computed last
-        u64 ch_[2] = {init, init}, cd_[2] = {init, init};   // ring values of the current block's neighbours
-        Rec rc = recl(gbase);                               // record of the current block
-        for (int i = 0; i < nb; ++i) {
-            const int b = blk(i), g = gbase + i;
-            const Rec r = rc;
-            const int cnt = (int)(r.meta & REC_COUNT);
-            need(&ctl->in_ready, inr, g);
-            u64 x[NX];
+    // One sweep.  fast(x, nh, nd, fl, vh, vd) computes the new state of an ordinary block (not
+    // ENTRY, EXIT or a call, at most two neighbours, at most one of them far) from its inputs x,
+    // its step flags and its first two neighbours' states (`ident` for a missing one);
+    // comp(b, r, x, nh, nd, ph, pd, sweep, g, vh, vd) computes any block.
+    // The walk is pipelined by a step: while step g computes, step g + 1's inputs and the states
+    // of its neighbours other than the block computed last (a ring slot or the far input) are
+    // being read, and so is the descriptor of step g + 2.
+    auto desc = [&](int g, uint32_t& fl, int& l0, int& l1) {
+        const int4 dn = dring[g & (IR - 1)];
+        fl = (uint32_t)__builtin_amdgcn_readfirstlane(dn.x);
+        l0 = __builtin_amdgcn_readfirstlane(dn.y);
+        l1 = __builtin_amdgcn_readfirstlane(dn.z);
+    };
+    // inputs of step g and the states at its neighbours' locations (no branch: a missing
+    // neighbour and the block computed last point at the identity state)
+    auto fetch = [&](int g, int l0, int l1, u64* x, u64* nh, u64* nd) {
 #pragma unroll
-            for (int k = 0; k < NX; ++k) x[k] = in_get(g, k);
-            const u64 fh = in_get(g, NX), fdv = in_get(g, NX + 1);
-            // ring values of the next block's neighbours, read while this block computes
-            u64 nh_[2] = {0, 0}, nd_[2] = {0, 0};
+        for (int k = 0; k < NX; ++k) x[k] = in_get(g, k);
+        nh[0] = w_get(l0); nd[0] = w_get(l0 + 512);
+        nh[1] = w_get(l1); nd[1] = w_get(l1 + 512);
+    };
+    auto walk = [&](const Rows& S, u64 init, int sweep, uint32_t& pc, auto&& fast, auto&& comp) {
+        u64 ph = init, pd = init;   // state of the block computed last
+        uint32_t fl0, fl1 = 0;
+        int a0, b0, a1 = IDENT_OFF, b1 = IDENT_OFF;
+        need(&ctl->in_ready, inr, gbase);
+        desc(gbase, fl0, a0, b0);
+        u64 x[NX], nh[2], nd[2];
+        fetch(gbase, a0, b0, x, nh, nd);
+        if (nb > 1) {
+            need(&ctl->in_ready, inr, gbase + 1);
+            desc(gbase + 1, fl1, a1, b1);
+        }
+        for (int i = 0; i < nb; ++i) {
+            const int g = gbase + i;
+            const uint32_t fl = fl0;
+            // the next step's reads
+            u64 x1[NX], nh1[2], nd1[2];
+            uint32_t fl2 = 0;
+            int a2 = IDENT_OFF, b2 = IDENT_OFF;
             if (i + 1 < nb) {
-                const Rec rn = recl(g + 1);
-                rc = rn;
-                const int cn = (int)(rn.meta & REC_COUNT);
-                for (int j = 0; j < 2 && j < cn; ++j) {
-                    const int p = j == 0 ? rn.n0 : rn.n1, d = dist(b + dir, p);
-                    if (d >= 2 && d <= RS) { nh_[j] = slot_h(g + 1 - d); nd_[j] = slot_d(g + 1 - d); }
+                fetch(g + 1, a1, b1, x1, nh1, nd1);
+                if (i + 2 < nb) {
+                    need(&ctl->in_ready, inr, g + 2);
+                    desc(g + 2, fl2, a2, b2);
                 }
             }
             u64 vh_[2], vd_[2];
-            bool far_used = false;
+#pragma unroll
             for (int j = 0; j < 2; ++j) {
-                vh_[j] = 0; vd_[j] = 0;
-                if (j >= cnt) continue;
-                const int p = j == 0 ? r.n0 : r.n1, d = dist(b, p);
-                if (d == 1) { vh_[j] = ph; vd_[j] = pd; }
-                else if (d >= 2 && d <= RS) { vh_[j] = ch_[j]; vd_[j] = cd_[j]; }
-                else if (!far_used) { vh_[j] = fh; vd_[j] = fdv; far_used = true; }
-                else far_val(S, p, d, g, sweep, init, vh_[j], vd_[j]);
+                const bool last = ((fl >> (2 * j)) & 3u) == 1u;
+                vh_[j] = last ? ph : nh[j];
+                vd_[j] = last ? pd : nd[j];
             }
             u64 vh, vd;
-            comp(b, r, x, vh_, vd_, ph, pd, sweep, g, vh, vd);
+            if (!(fl & DF_SLOW)) fast(x, vh_, vd_, fl, vh, vd);
+            else {
+                // any block: neighbour values by the general rule, then the full transfer
+                const int b = blk(i);
+                const Rec r = ldrec(REC, b);
+                const int cnt = (int)(r.meta & REC_COUNT);
+                bool far_used = false;
+                for (int j = 0; j < 2; ++j) {
+                    vh_[j] = 0; vd_[j] = 0;
+                    if (j >= cnt) continue;
+                    const int p = j == 0 ? r.n0 : r.n1, d = dist(b, p);
+                    if (d == 1) { vh_[j] = ph; vd_[j] = pd; }
+                    else if (d >= 2 && d <= RS) { vh_[j] = slot_h(g - d); vd_[j] = slot_d(g - d); }
+                    else if (!far_used) { vh_[j] = in_get(g, NX); vd_[j] = in_get(g, NX + 1); far_used = true; }
+                    else far_val(S, p, d, g, sweep, init, vh_[j], vd_[j]);
+                }
+                comp(b, r, x, vh_, vd_, ph, pd, sweep, g, vh, vd);
+            }
             pc += popc2(vh, vd);
             // the ring slot of step g was last used by step g - RS: the helper must have read it
             need(&ctl->consumed, cons, g - RS);
-            slot_h(g) = vh;
-            slot_d(g) = vd;
+            w_put(ring_at(g), vh);
+            w_put(ring_at(g) + 512, vd);
             lds_release();
             lds_put(&ctl->produced, g + 1);
             ph = vh; pd = vd;
-            ch_[0] = nh_[0]; ch_[1] = nh_[1]; cd_[0] = nd_[0]; cd_[1] = nd_[1];
+            fl0 = fl1; fl1 = fl2; a1 = a2; b1 = b2;
+#pragma unroll
+            for (int k = 0; k < NX; ++k) x[k] = x1[k];
+            nh[0] = nh1[0]; nh[1] = nh1[1]; nd[0] = nd1[0]; nd[1] = nd1[1];
         }
     };
     // a neighbour beyond the first two, at compute time (g = the current step)
@@ -648,17 +710,19 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         else far_val(S, p, dd, g, sweep, init, h, d);
     };
     // Run a phase: the compute wavefront sweeps, the helper feeds and stores; false on an error.
-    auto run_phase = [&](const Rows& S, u64 init, auto&& pre, auto&& comp) -> bool {
+    auto run_phase = [&](const Rows& S, u64 init, u64 ident, auto&& pre, auto&& fast, auto&& comp) -> bool {
         if (helper) {
             helper_loop(S, init, pre);
             return true;
         }
+        w_put(IDENT_OFF, ident);   // the state of a missing neighbour
+        w_put(IDENT_OFF + 512, ident);
         int sweeps = 0;
         uint32_t last = (uint32_t)nb * 2u * (uint32_t)__popcll(init);
         bool good = true;
         for (;;) {
             uint32_t pc = 0;
-            walk(S, init, sweeps, pc, comp);
+            walk(S, init, sweeps, pc, fast, comp);
             gbase += nb;
             ++sweeps;
             // the next sweep reads this sweep's rows for blocks it has not visited yet
@@ -748,7 +812,14 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             vh = (dev ? 0ull : rr) | (~ww & oh);
             vd = (dev ? rr : 0ull) | (~ww & od);
         };
-        run_phase(S, 0ull, pre, comp);
+        auto fast = [&](const u64* x, const u64* nh, const u64* nd, uint32_t fl, u64& vh, u64& vd) {
+            const bool dev = fl & DF_DEV;
+            const u64 rr = flg ? 2ull : x[0], ww = flg ? (dev ? 2ull : 0ull) : x[1];
+            const u64 oh = nh[0] | nh[1], od = nd[0] | nd[1];
+            vh = (dev ? 0ull : rr) | (~ww & oh);
+            vd = (dev ? rr : 0ull) | (~ww & od);
+        };
+        run_phase(S, 0ull, 0ull, pre, fast, comp);
         return;
     }
 
@@ -787,7 +858,14 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             }
             valid_out(b, r, ih & vm, id & vm, flg ? ((r.meta & REC_DEV) ? 2ull : 0ull) : x[2], vh, vd);
         };
-        if (!run_phase(S, init, pre, comp)) return;
+        auto fast = [&](const u64* x, const u64* nh, const u64* nd, uint32_t fl, u64& vh, u64& vd) {
+            const bool dev = fl & DF_DEV;
+            const u64 ih = ((flg ? 0ull : x[0]) | (nh[0] & nh[1])) & vm, id = ((flg ? 0ull : x[1]) | (nd[0] & nd[1])) & vm;
+            const u64 wr = flg ? (dev ? 2ull : 0ull) : x[2];
+            vh = (dev ? (ih & ~wr) : (ih | wr)) & vm;
+            vd = (dev ? (id | wr) : (id & ~wr)) & vm;
+        };
+        if (!run_phase(S, init, ~0ull, pre, fast, comp)) return;
         if (helper) return;
         // reachability: every block reached from ENTRY and reaching EXIT
         bool bad = false;
@@ -848,7 +926,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 nbr_f(r, j, p, e);
                 if (e & 0x80000000u) continue;   // loop entry: nothing stays pending
                 u64 gh, gd, sh, sd;
-                if (j < 2) { gh = x[2 + 2 * j]; gd = x[3 + 2 * j]; sh = nh[j]; sd = nd[j]; }
+                if (j < 2) {   // (selects, not indexing: the arrays stay in registers)
+                    gh = j ? x[4] : x[2]; gd = j ? x[5] : x[3]; sh = j ? nh[1] : nh[0]; sd = j ? nd[1] : nd[0];
+                }
                 else {
                     gh = settle(erow(c.eag_h, e)); gd = settle(erow(c.eag_d, e));
                     extra(S, b, p, sweep, g, 0ull, ph, pd, sh, sd);
@@ -861,7 +941,17 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             vh = mh & ~sth & vm;
             vd = md & ~std_ & vm;
         };
-        run_phase(S, 0ull, pre, comp);
+        // (the stop masks of an ordinary block: its own accesses)
+        auto fast = [&](const u64* x, const u64* nh, const u64* nd, uint32_t fl, u64& vh, u64& vd) {
+            const bool dev = fl & DF_DEV;
+            const bool t0 = (fl & 3u) && !(fl & DF_LE0), t1 = ((fl >> 2) & 3u) && !(fl & DF_LE1);
+            const u64 mh = (t0 ? (x[2] | nh[0]) : 0ull) | (t1 ? (x[4] | nh[1]) : 0ull);
+            const u64 md = (t0 ? (x[3] | nd[0]) : 0ull) | (t1 ? (x[5] | nd[1]) : 0ull);
+            const u64 sth = dev ? 0ull : (x[0] | x[1]), std_ = dev ? (x[0] | x[1]) : 0ull;
+            vh = mh & ~sth & vm;
+            vd = md & ~std_ & vm;
+        };
+        run_phase(S, 0ull, 0ull, pre, fast, comp);
         return;
     }
 
@@ -892,7 +982,10 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 int p; uint32_t e;
                 nbr_f(r, j, p, e);
                 u64 gh, gd, bo, sh, sd;
-                if (j < 2) { gh = x[2 + 3 * j]; gd = x[3 + 3 * j]; bo = x[4 + 3 * j]; sh = nh[j]; sd = nd[j]; }
+                if (j < 2) {
+                    gh = j ? x[5] : x[2]; gd = j ? x[6] : x[3]; bo = j ? x[7] : x[4];
+                    sh = j ? nh[1] : nh[0]; sd = j ? nd[1] : nd[0];
+                }
                 else {
                     gh = settle(erow(c.eag_h, e)); gd = settle(erow(c.eag_d, e)); bo = settle(erow(c.both, e));
                     extra(S, b, p, sweep, g, 0ull, ph, pd, sh, sd);
@@ -908,7 +1001,20 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             vh = allh & anyh & vm & ~sth;
             vd = alld & anyd & vm & ~std_;
         };
-        run_phase(S, 0ull, pre, comp);
+        // (per edge, (L & ~LE) | N' = L | BOTH whatever LE is; only the OR term skips loop entries)
+        auto fast = [&](const u64* x, const u64* nh, const u64* nd, uint32_t fl, u64& vh, u64& vd) {
+            const bool dev = fl & DF_DEV;
+            const bool p0 = fl & 3u, p1 = (fl >> 2) & 3u;
+            const u64 l0h = x[2] | nh[0], l0d = x[3] | nd[0], l1h = x[5] | nh[1], l1d = x[6] | nd[1];
+            const u64 allh = (p0 ? (l0h | x[4]) : ~0ull) & (p1 ? (l1h | x[7]) : ~0ull);
+            const u64 alld = (p0 ? (l0d | x[4]) : ~0ull) & (p1 ? (l1d | x[7]) : ~0ull);
+            const bool a0 = p0 && !(fl & DF_LE0), a1 = p1 && !(fl & DF_LE1);
+            const u64 anyh = (a0 ? l0h : 0ull) | (a1 ? l1h : 0ull), anyd = (a0 ? l0d : 0ull) | (a1 ? l1d : 0ull);
+            const u64 sth = dev ? 0ull : (x[0] | x[1]), std_ = dev ? (x[0] | x[1]) : 0ull;
+            vh = allh & anyh & vm & ~sth;
+            vd = alld & anyd & vm & ~std_;
+        };
+        run_phase(S, 0ull, 0ull, pre, fast, comp);
         return;
     }
 
@@ -937,7 +1043,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                     int p; uint32_t e;
                     nbr_f(r, j, p, e);
                     u64 gh, gd, sh, sd;
-                    if (j < 2) { gh = x[3 + 2 * j]; gd = x[4 + 2 * j]; sh = nh[j]; sd = nd[j]; }
+                    if (j < 2) {
+                        gh = j ? x[5] : x[3]; gd = j ? x[6] : x[4]; sh = j ? nh[1] : nh[0]; sd = j ? nd[1] : nd[0];
+                    }
                     else {
                         gh = settle(erow(c.ig_h, e)); gd = settle(erow(c.ig_d, e));
                         extra(S, b, p, sweep, g, init, ph, pd, sh, sd);
@@ -950,7 +1058,16 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             }
             valid_out(b, r, ih & vm, id & vm, x[2], vh, vd);
         };
-        run_phase(S, init, pre, comp);
+        auto fast = [&](const u64* x, const u64* nh, const u64* nd, uint32_t fl, u64& vh, u64& vd) {
+            const bool dev = fl & DF_DEV;
+            const bool p0 = fl & 3u, p1 = (fl >> 2) & 3u;
+            const u64 mh = (p0 ? (nh[0] | x[3]) : ~0ull) & (p1 ? (nh[1] | x[5]) : ~0ull);
+            const u64 md = (p0 ? (nd[0] | x[4]) : ~0ull) & (p1 ? (nd[1] | x[6]) : ~0ull);
+            const u64 ih = (x[0] | mh) & vm, id = (x[1] | md) & vm, wr = x[2];
+            vh = (dev ? (ih & ~wr) : (ih | wr)) & vm;
+            vd = (dev ? (id | wr) : (id & ~wr)) & vm;
+        };
+        run_phase(S, init, ~0ull, pre, fast, comp);
     }
 }
 
@@ -974,7 +1091,7 @@ enum { PASS_AVE = 0, PASS_MAYP = 1, PASS_LATER = 2, PASS_AVF = 3 };
 template <int PASS>
 __device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int fslot, int b0)
 {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     if (lane >= nw) return;
     const int nb = c.nb, wd = c.wd;
     const size_t wo = (size_t)(s0 + lane);
@@ -1119,6 +1236,22 @@ __device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int f
     }
 }
 
+// One phase of one tile by the whole workgroup (both wavefronts); a CFG that already failed is skipped.
+template <int PH>
+__device__ __forceinline__ void tile_phase(const DevCfg& c, const Tile& tl, u64* lds, int ring_slots)
+{
+    Ctl* ctl = reinterpret_cast<Ctl*>(lds);
+    if (threadIdx.x == 0) {
+        // one read of the CFG's status for both wavefronts (another tile may fail meanwhile)
+        ctl->skip = G(c.info)[INFO_STATUS] != 0;
+        ctl->produced = 0; ctl->consumed = 0; ctl->flushed = 0; ctl->done = 0; ctl->abort = 0;
+        ctl->in_ready = 0;
+    }
+    __syncthreads();
+    if (!__builtin_amdgcn_readfirstlane(ctl->skip)) solve_phase<PH>(c, tl.s0, tl.nw, tl.fslot, lds, ring_slots);
+    __syncthreads();
+}
+
 template <int PH>
 __device__ __forceinline__ void phase_kernel(const DevCfg* __restrict__ cfgs, const Tile* __restrict__ tiles, int n_tiles,
                                              int32_t* __restrict__ counter, int ring_slots)
@@ -1126,21 +1259,14 @@ __device__ __forceinline__ void phase_kernel(const DevCfg* __restrict__ cfgs, co
     extern __shared__ __align__(16) u64 lds[];
     Ctl* ctl = reinterpret_cast<Ctl*>(lds);
     for (;;) {
-        if (threadIdx.x == 0) {
-            const int t = atomicAdd(&counter[PH], 1);
-            ctl->tile = t;
-            // one read of the CFG's status for both wavefronts (another tile may fail meanwhile)
-            ctl->skip = t < n_tiles ? G(cfgs[tiles[t].cfg].info)[INFO_STATUS] != 0 : 1;
-            ctl->produced = 0; ctl->consumed = 0; ctl->flushed = 0; ctl->done = 0; ctl->abort = 0;
-            ctl->rec_filled = 0; ctl->in_ready = 0;
-        }
+        if (threadIdx.x == 0) ctl->tile = atomicAdd(&counter[PH], 1);
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(ctl->tile);
+        __syncthreads();
         if (t >= n_tiles) break;
         const Tile tl = tiles[t];
         const DevCfg c = cfgs[tl.cfg];
-        if (!__builtin_amdgcn_readfirstlane(ctl->skip)) solve_phase<PH>(c, tl.s0, tl.nw, tl.fslot, lds, ring_slots);
-        __syncthreads();
+        tile_phase<PH>(c, tl, lds, ring_slots);
     }
 }
 
@@ -1189,6 +1315,20 @@ OMPD_PASS_KERNEL(ompd_k_post_mayp, PASS_MAYP)
 OMPD_PASS_KERNEL(ompd_k_post_later, PASS_LATER)
 OMPD_PASS_KERNEL(ompd_k_post_avf, PASS_AVF)
 
+// The map kinds of one tile's variables from its masks; wavefront k takes words s0 + k, s0 + k + waves, ...
+__device__ __forceinline__ void tile_varkind(const DevCfg& c, const Tile& tl, int first, int step)
+{
+    const GAS u64* acc = G(c.vk_acc);
+    const int i = threadIdx.x & 63;
+    for (int w = tl.s0 + first; w < tl.s0 + tl.nw; w += step) {
+        const int v = w * 64 + i;
+        if (v >= c.nv) break;
+        const u64 t = ld_fresh(acc + w), f = ld_fresh(acc + c.wd + w), d = ld_fresh(acc + 2 * c.wd + w);
+        const uint32_t t1 = (uint32_t)((t >> i) & 1), f1 = (uint32_t)((f >> i) & 1), d1 = (uint32_t)((d >> i) & 1);
+        G(c.var_kind)[v] = (uint8_t)(t1 | (f1 << 1) | ((d1 && !t1 && !f1) ? 4u : 0u));
+    }
+}
+
 // Map kinds from the masks: one wavefront per tile (claimed through counter
 // slot 12), one lane per variable of each of the tile's words.
 extern "C" __global__ void __launch_bounds__(64) ompd_k_varkind(const DevCfg* __restrict__ cfgs,
@@ -1203,15 +1343,51 @@ extern "C" __global__ void __launch_bounds__(64) ompd_k_varkind(const DevCfg* __
         const Tile tl = tiles[t];
         const DevCfg c = cfgs[tl.cfg];
         if (!c.var_kind || tl.nw == 0 || G(c.info)[INFO_STATUS] != 0) continue;
-        const GAS u64* acc = G(c.vk_acc);
-        for (int w = tl.s0; w < tl.s0 + tl.nw; ++w) {
-            const int v = w * 64 + (int)threadIdx.x;
-            if (v >= c.nv) break;
-            const int i = threadIdx.x;
-            const uint32_t t1 = (uint32_t)((acc[w] >> i) & 1), f1 = (uint32_t)((acc[c.wd + w] >> i) & 1);
-            const uint32_t d1 = (uint32_t)((acc[2 * c.wd + w] >> i) & 1);
-            G(c.var_kind)[v] = (uint8_t)(t1 | (f1 << 1) | ((d1 && !t1 && !f1) ? 4u : 0u));
-        }
+        tile_varkind(c, tl, 0, 1);
+    }
+}
+
+// A pass over one tile by the whole workgroup: wavefront k takes the 64-block chunks k, k + 2, ...
+// (after an acquire, so that the state rows the helper wavefront stored are read fresh).
+template <int PASS>
+__device__ __forceinline__ void tile_pass(const DevCfg& c, const Tile& tl)
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const bool skip = G(c.info)[INFO_STATUS] != 0 || tl.nw == 0 || (PASS == PASS_MAYP && (c.placement & 1));
+    if (!skip)
+        for (int b0 = 64 * (int)(threadIdx.x >> 6); b0 < c.nb; b0 += 128) edge_pass<PASS>(c, tl.s0, tl.nw, tl.fslot, b0);
+    __syncthreads();
+}
+
+// The whole solve of each tile in one persistent kernel: a workgroup takes a tile (longest first,
+// claimed through counter slot 13) and runs every phase and pass on it, so tiles never wait for
+// each other between phases.
+extern "C" __global__ void __launch_bounds__(128) ompd_k_solve(const DevCfg* __restrict__ cfgs,
+                                                                const Tile* __restrict__ tiles, int n_tiles,
+                                                                int32_t* __restrict__ counter, int ring_slots)
+{
+    extern __shared__ __align__(16) u64 lds[];
+    Ctl* ctl = reinterpret_cast<Ctl*>(lds);
+    for (;;) {
+        if (threadIdx.x == 0) ctl->tile = atomicAdd(&counter[13], 1);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(ctl->tile);
+        __syncthreads();
+        if (t >= n_tiles) break;
+        const Tile tl = tiles[t];
+        const DevCfg c = cfgs[tl.cfg];
+        tile_phase<PH_NU>(c, tl, lds, ring_slots);
+        tile_phase<PH_AVE>(c, tl, lds, ring_slots);
+        tile_pass<PASS_AVE>(c, tl);
+        tile_phase<PH_MAYP>(c, tl, lds, ring_slots);
+        tile_pass<PASS_MAYP>(c, tl);
+        tile_phase<PH_LATER>(c, tl, lds, ring_slots);
+        tile_pass<PASS_LATER>(c, tl);
+        tile_phase<PH_AVF>(c, tl, lds, ring_slots);
+        tile_pass<PASS_AVF>(c, tl);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (c.var_kind && tl.nw > 0 && G(c.info)[INFO_STATUS] == 0) tile_varkind(c, tl, (int)(threadIdx.x >> 6), 2);
+        __syncthreads();
     }
 }
 

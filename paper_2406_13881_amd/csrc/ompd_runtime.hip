@@ -27,6 +27,7 @@ extern "C" __global__ void ompd_k_post_mayp(const DevCfg*, const Tile*, const Ed
 extern "C" __global__ void ompd_k_post_later(const DevCfg*, const Tile*, const EdgeItem*, int, int32_t*);
 extern "C" __global__ void ompd_k_post_avf(const DevCfg*, const Tile*, const EdgeItem*, int, int32_t*);
 extern "C" __global__ void ompd_k_varkind(const DevCfg*, const Tile*, int, int32_t*);
+extern "C" __global__ void ompd_k_solve(const DevCfg*, const Tile*, int, int32_t*, int);
 static const void* const k_phases[5] = {(const void*)ompd_k_nu, (const void*)ompd_k_ave, (const void*)ompd_k_mayp,
                                         (const void*)ompd_k_later, (const void*)ompd_k_avf};
 // threads of a phase workgroup: the compute and the helper wavefront
@@ -77,7 +78,8 @@ extern "C" int ompd_ctx_create(ompd_ctx** out, int device_ordinal, uint64_t budg
     lds_max = std::min<size_t>(lds_max ? lds_max : 64 * 1024, 160 * 1024);
     // dynamic LDS limit per kernel = device limit minus the kernel's static LDS
     int dyn = (int)lds_max;
-    for (const void* k : {k_phases[0], k_phases[1], k_phases[2], k_phases[3], k_phases[4], (const void*)ompd_k_prep}) {
+    for (const void* k : {k_phases[0], k_phases[1], k_phases[2], k_phases[3], k_phases[4], (const void*)ompd_k_prep,
+                          (const void*)ompd_k_solve}) {
         hipFuncAttributes fa{};
         int st = 0;
         if (hipFuncGetAttributes(&fa, k) == hipSuccess) st = (int)fa.sharedSizeBytes;
@@ -277,6 +279,16 @@ int ompd_make_shape(ompd_ctx* ctx, const std::vector<DevCfg>& cfgs, const PlanCo
         if (pc.wg_per_cu > 0) n = std::min(n, pc.wg_per_cu);
         dm.grid[ph] = std::max(1, std::min((int)tiles.size(), n * ctx->n_cu));
     }
+    dm.split = pc.split;
+    dm.lds_tile = 0;
+    for (int ph = 0; ph < 5; ++ph) dm.lds_tile = std::max(dm.lds_tile, dm.lds[ph]);
+    {
+        int n = 0;
+        CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)ompd_k_solve, PHASE_THREADS, dm.lds_tile));
+        n = std::max(1, n);
+        if (pc.wg_per_cu > 0) n = std::min(n, pc.wg_per_cu);
+        dm.grid_tile = std::max(1, std::min((int)tiles.size(), n * ctx->n_cu));
+    }
     int pe = 1;
     CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pe, (const void*)ompd_k_post_ave, 64, 0));
     dm.grid_edge = std::max(1, std::min((int)std::max<size_t>(sh.items.size(), tiles.size()), std::max(1, pe) * ctx->n_cu));
@@ -297,6 +309,7 @@ int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32
     p->n = n;
     p->flags = flags;
     p->cfg = pc;
+    if (flags & OMPD_F_TILE_KERNEL) p->cfg.split = false;
     p->res.assign(res, res + n);
     p->h_cfgs.resize(n);
 
@@ -335,7 +348,7 @@ int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32
         e = hipMemcpy(p->d_cfgs, p->h_cfgs.data(), sizeof(DevCfg) * n, hipMemcpyHostToDevice);
     if (e != hipSuccess) { ompd_plan_destroy(p); return ompd_fail(OMPD_E_DEVICE, hipGetErrorString(e)); }
     p->h_info.assign((size_t)n * INFO_WORDS, 0);
-    int rc = ompd_plan_retile(p, pc);
+    int rc = ompd_plan_retile(p, p->cfg);
     if (rc) { ompd_plan_destroy(p); return rc; }
     CK(hipEventCreate(&p->ev0));
     CK(hipEventCreate(&p->ev1));
@@ -387,6 +400,17 @@ int ompd_launch_solve(const DevCfg* d_cfgs, const Tile* d_tiles, int n_tiles, co
     const int rs = dm.ring_slots, grid_edge = dm.grid_edge;
     int k = 0;
     auto mark = [&]() { if (after) (void)hipEventRecord(after[k], s); ++k; };
+    if (!dm.split) {
+        // every phase and pass of a tile in one persistent kernel
+        hipLaunchKernelGGL(ompd_k_solve, dim3(dm.grid_tile), dim3(PHASE_THREADS), dm.lds_tile, s, d_cfgs, d_tiles,
+                           n_tiles, d_counter, rs);
+        mark();
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return ompd_fail(OMPD_E_DEVICE, std::string("solve launch (ring slots ") + std::to_string(rs) + "): " +
+                                                hipGetErrorString(e));
+        return OMPD_OK;
+    }
     int ph = 0;
     auto phase = [&](const void* fn) {
         void* args[] = {(void*)&d_cfgs, (void*)&d_tiles, (void*)&n_tiles, (void*)&d_counter, (void*)&rs};
@@ -585,7 +609,7 @@ extern "C" int ompd_plan_kernel_ms(ompd_plan* p, float* ms, int32_t capacity, in
     if (!p || !ms) return ompd_fail(OMPD_E_INVAL, "bad arguments");
     if (!p->profile) return ompd_fail(OMPD_E_INVAL, "profiling is off for this plan");
     CK(hipEventSynchronize(p->ev2));
-    const int n = 1 + N_SOLVE_KERNELS;
+    const int n = 1 + (p->dims.split ? N_SOLVE_KERNELS : 1);
     if (n_kernels) *n_kernels = n;
     hipEvent_t marks[2 + N_SOLVE_KERNELS] = {p->ev0, p->ev1};
     for (int k = 0; k < N_SOLVE_KERNELS; ++k) marks[2 + k] = p->evk[k];
@@ -608,15 +632,27 @@ extern "C" int ompd_plan_configure(ompd_plan* p, int64_t lds_bytes, int32_t wg_p
     return ompd_plan_retile(p, c);
 }
 
+extern "C" int ompd_plan_split_kernels(ompd_plan* p, int32_t split)
+{
+    if (!p) return ompd_fail(OMPD_E_INVAL, "plan is NULL");
+    std::lock_guard<std::mutex> lk(p->ctx->mu);
+    PlanConfig c = p->cfg;
+    c.split = split != 0;
+    c.use_graph = true;
+    return ompd_plan_retile(p, c);
+}
+
 extern "C" int ompd_plan_describe(ompd_plan* p, char* buf, int32_t len)
 {
     if (!p || !buf || len <= 0) return ompd_fail(OMPD_E_INVAL, "bad arguments");
     long lanes = 0;
     for (const Tile& t : p->h_tiles) lanes += t.nw;
     snprintf(buf, len,
-             "{\"cfgs\": %d, \"tiles\": %d, \"words\": %ld, \"ring_slots\": %d, \"grid_phases\": [%d, %d, %d, %d, %d], "
+             "{\"cfgs\": %d, \"tiles\": %d, \"words\": %ld, \"ring_slots\": %d, \"split\": %d, \"grid_tile\": %d, "
+             "\"grid_phases\": [%d, %d, %d, %d, %d], "
              "\"lds_bytes\": %zu, \"wg_per_cu\": %d, \"graph\": %d, \"scratch_bytes\": %zu}",
-             p->n, p->n_tiles, lanes, p->dims.ring_slots, p->dims.grid[0], p->dims.grid[1], p->dims.grid[2],
+             p->n, p->n_tiles, lanes, p->dims.ring_slots, (int)p->dims.split, p->dims.grid_tile, p->dims.grid[0],
+             p->dims.grid[1], p->dims.grid[2],
              p->dims.grid[3], p->dims.grid[4], p->cfg.lds_bytes, p->cfg.wg_per_cu,
              p->cfg.use_graph ? 1 : 0, p->scratch_bytes);
     return OMPD_OK;

@@ -162,3 +162,20 @@ def test_sweep_cap_reports_noconverge(ctx):
     # and the default cap never triggers
     got = ctx.analyze_cfg(cfg)
     assert_same(cfg, got, oracle.solve(cfg), "after cap")
+
+
+def test_tile_kernel_matches_oracle(ctx):
+    """The per-tile launch layout (one persistent kernel runs every phase
+    and pass of a tile) gives the same results as the default one kernel
+    per phase: both equal the oracle on a mixed batch with multi-tile
+    CFGs."""
+    import paper_2406_13881_amd as ompd
+    cfgs = [synth.c1(i) for i in range(20)]
+    cfgs += [synth.make_cfg(6_100 + j, n_user=60 + 50 * j, n_vars=40 + 1300 * j, max_loop_depth=4,
+                            device_frac=0.4, irr_loop_frac=0.1) for j in range(4)]
+    cfgs += [synth.random_dag(77 + j, 30, 90, p_loop_entry=0.3) for j in range(6)]
+    refs = [oracle.solve(c) for c in cfgs]
+    for flags in (0, ompd.F_TILE_KERNEL):
+        got = ctx.analyze_batch(cfgs, flags=flags)
+        for i, cfg in enumerate(cfgs):
+            assert_same(cfg, got[i], refs[i], "flags=%d #%d" % (flags, i))
