@@ -178,14 +178,14 @@ int ompd_plan_create(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int3
 int ompd_plan_run(ompd_plan* plan, void* stream);
 int ompd_plan_status(ompd_plan* plan, int32_t* per_cfg);
 /* Autotuner: times each candidate launch configuration (LDS ring bytes per
- * solve wavefront, wavefronts per CU) `trials` times on `stream` and keeps
+ * solve workgroup, workgroups per CU) `trials` times on `stream` and keeps
  * the fastest.  Results are bit-identical for every candidate.  best_ms may
  * be NULL. */
 int ompd_plan_autotune(ompd_plan* plan, void* stream, int32_t trials, float* best_ms);
 /* Set the launch configuration by hand (what the autotuner chooses among):
  * LDS bytes per solve workgroup for the ring of recently solved blocks
- * (1 KiB per block; 0 = default, 16 KiB; rounded down to a power of two
- * of KiB within [8 KiB, 64 KiB] and to what the device's LDS holds) and
+ * (256 bytes per block; 0 = default, 16 KiB; rounded down to a power of
+ * two of blocks within [8, 64] and to what the device's LDS holds) and
  * solve workgroups per CU (0 = as many as fit). */
 int ompd_plan_configure(ompd_plan* plan, int64_t lds_bytes, int32_t wg_per_cu);
 /* Profiling: with enable != 0, ompd_plan_run launches the kernels directly

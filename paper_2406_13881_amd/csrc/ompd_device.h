@@ -59,6 +59,8 @@ struct DevCfg {
     int32_t* tmp;
     int32_t* rec_f;     // [2*nb] int4: block records with predecessors, in block-id order
     int32_t* rec_b;     // [2*nb] int4: block records with successors, in block-id order
+    int32_t* step_f;    // [2*nb] int4: step entries of the forward walk, in walk order
+    int32_t* step_b;    // [2*nb] int4: step entries of the backward walk, in walk order
     int32_t* info;
 };
 
@@ -69,7 +71,12 @@ constexpr uint32_t REC_ENTRY = 1u << 24, REC_EXIT = 1u << 25, REC_DEV = 1u << 26
 // A tile: one CFG and a run of its 64-bit variable words, solved by one
 // workgroup (a compute wavefront with one lane per word plus the flag
 // lane, and a helper wavefront that stores its results).
-constexpr int TILE_WORDS = 63;
+// Lanes of the compute wavefront that hold words (the rest idle); LDS
+// holds LANES lanes of every word.
+constexpr int LANES = 16;
+constexpr int TILE_WORDS = LANES - 1;
+constexpr int WORD_BYTES = 8 * LANES;        // one word of every lane in LDS
+constexpr int STATE_BYTES = 2 * WORD_BYTES;  // a state (h, d)
 struct Tile {
     int32_t cfg;
     int32_t s0;      // first word
@@ -99,7 +106,8 @@ constexpr int in_ring(int ph) { return ph == PH_NU || ph == PH_AVE ? 16 : 8; }
 inline int phase_inputs(int ph) { return 2 + (ph == PH_NU ? 2 : ph == PH_AVE ? 3 : ph == PH_MAYP ? 6 : ph == PH_LATER ? 8 : 7); }
 inline size_t phase_lds(int ph, int ring_slots)
 {
-    return LDS_FIXED + (size_t)ring_slots * 1024 + (size_t)in_ring(ph) * (phase_inputs(ph) * 512 + 16) + 1024;
+    return LDS_FIXED + (size_t)ring_slots * STATE_BYTES + (size_t)in_ring(ph) * (phase_inputs(ph) * WORD_BYTES + 16) +
+           STATE_BYTES;
 }
 // Work counters (int32) of one solve launch: phases 0..4, passes 8..11, map kinds 12.
 constexpr int N_COUNTERS = 16;

@@ -76,7 +76,7 @@ struct ompd_plan {
 int ompd_fail(int code, const std::string& msg);
 
 struct ScratchOff {
-    size_t aveout, mayp, later, flg, eag, both, nu, ave, ie, ig, avf, vk, bnd, pp, pi, pe, tmp, recf, recb, info;
+    size_t aveout, mayp, later, flg, eag, both, nu, ave, ie, ig, avf, vk, bnd, pp, pi, pe, tmp, recf, recb, stf, stb, info;
 };
 size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o);
 void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const ScratchOff& o, uint32_t flags,
@@ -89,7 +89,7 @@ struct Shape {
     size_t lds_prep = 0;
 };
 int ompd_make_shape(ompd_ctx* ctx, const std::vector<ompd::DevCfg>& cfgs, const PlanConfig& pc, Shape& sh);
-int ompd_launch_prep(const ompd::DevCfg* d_cfgs, int n, int32_t* d_counter, size_t lds, hipStream_t s);
+int ompd_launch_prep(const ompd::DevCfg* d_cfgs, int n, int32_t* d_counter, size_t lds, int ring_slots, hipStream_t s);
 int ompd_launch_solve(const ompd::DevCfg* d_cfgs, const ompd::Tile* d_tiles, int n_tiles, const ompd::EdgeItem* d_items,
                       int n_items, int32_t* d_counter, const LaunchDims& dims, hipStream_t s,
                       hipEvent_t* after = nullptr);

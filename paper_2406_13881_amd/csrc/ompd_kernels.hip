@@ -4,10 +4,14 @@
 //   validates the CSR and the boundary rules, builds the predecessor CSR
 //   (with the successor-edge id of every predecessor link) and writes one
 //   32-byte record per block for each direction (flags, first two
-//   neighbours with their edge ids, CSR start of the rest, call index).
+//   neighbours with their edge ids, CSR start of the rest, call index),
+//   and for each direction a 32-byte step entry per position of the walk
+//   (where the states of the first two neighbours are found for the
+//   launch's ring size, the far neighbour and how many steps back its state
+//   was computed, the block and its first two edge ids).
 //
 // Phase kernels (persistent, two wavefronts per tile): a tile is one CFG
-//   and a run of up to 63 64-bit words of its variables.  One kernel per
+//   and a run of up to 15 64-bit words of its variables.  One kernel per
 //   iterated problem of the method, in this order:
 //     ompd_k_nu     next use (backward may)
 //     ompd_k_ave    validity with eager copies (forward must) and the
@@ -49,6 +53,52 @@ __device__ __forceinline__ void set_status(int32_t* info, int32_t code)
     atomicCAS(&info[INFO_STATUS], 0, code);
 }
 
+// Step flags (the x word of a step entry and of a step descriptor).  Bits 0-1 / 2-3: where the
+// state of neighbour 0 / 1 is found: 0 nowhere (missing), 1 the block computed last, 2 the ring,
+// 3 the far input.
+constexpr uint32_t DF_SLOW = 1u << 4;   // ENTRY, EXIT, a call, no or more than two neighbours, two far ones
+constexpr uint32_t DF_DEV = 1u << 5;    // a DEVICE block
+constexpr uint32_t DF_LE0 = 1u << 6;    // edge of neighbour 0 is a loop entry (forward phases)
+constexpr uint32_t DF_LE1 = 1u << 7;    // edge of neighbour 1 is a loop entry
+constexpr uint32_t SF_FAR = 1u << 8;    // one of the first two neighbours is far (step entries only)
+constexpr uint32_t SF_BACK = 1u << 9;   // ... and not visited yet in the sweep
+constexpr uint32_t DF_MASK = 0xFFu;     // the bits a step descriptor carries
+// A step entry (two int4, one per walk position): x flags; y the ring distances of neighbours
+// 0 and 1 (bits 0-7, 8-15; flag code 2 only); z the far neighbour; w how many steps before the
+// current one its state was computed (this sweep's or, when SF_BACK, the previous sweep's); then
+// the block, the edge ids of neighbours 0 and 1 (0 when missing) and an unused word.
+// The step entry of the block b at walk position i, from its record r0 / r1 (ring of rs slots).
+__device__ __forceinline__ void make_step(const int4& r0, const int4& r1, int b, bool bwd, int nb, int rs,
+                                          int4& t0, int4& t1)
+{
+    const uint32_t meta = (uint32_t)r0.x, e0 = (uint32_t)r0.w, e1 = (uint32_t)r1.x;
+    const int cnt = (int)(meta & REC_COUNT);
+    uint32_t fl = (cnt > 2 || cnt == 0 || (meta & (REC_ENTRY | REC_EXIT | REC_CALL))) ? DF_SLOW : 0u;
+    fl |= (meta & REC_DEV) ? DF_DEV : 0u;
+    fl |= (e0 & 0x80000000u) ? DF_LE0 : 0u;
+    fl |= ((e1 & 0x80000000u) && cnt > 1) ? DF_LE1 : 0u;
+    int dd = 0, fp = 0, fo = 0;
+    bool far = false;
+    for (int j = 0; j < 2 && j < cnt; ++j) {
+        const int p = j == 0 ? r0.y : r0.z;
+        const int d = bwd ? p - b : b - p;   // 1: the block just before in the walk
+        uint32_t k;
+        if (d == 1) k = 1;
+        else if (d >= 2 && d <= rs) { k = 2; dd |= d << (8 * j); }
+        else if (!far) {
+            k = 3;
+            far = true;
+            fp = p;
+            fo = d > 0 ? d : d + nb;
+            fl |= SF_FAR | (d > 0 ? 0u : SF_BACK);
+        }
+        else { k = 0; fl |= DF_SLOW; }
+        fl |= k << (2 * j);
+    }
+    t0 = make_int4((int)fl, dd, fp, fo);
+    t1 = make_int4(b, cnt > 0 ? (int)(e0 & 0x7FFFFFFFu) : 0, cnt > 1 ? (int)(e1 & 0x7FFFFFFFu) : 0, 0);
+}
+
 // Inclusive prefix sum of a[0..n) in global memory by one workgroup.
 __device__ void block_scan_inclusive(int32_t* a, int n, int32_t* sh)
 {
@@ -79,7 +129,7 @@ __device__ void block_scan_inclusive(int32_t* a, int n, int32_t* sh)
 // ingest / normalise
 // --------------------------------------------------------------------------
 extern "C" __global__ void __launch_bounds__(256)
-ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ solve_counter)
+ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ solve_counter, int ring_slots)
 {
     __shared__ int s_err;
     __shared__ int32_t s_scan[16];
@@ -197,13 +247,28 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
         RB[2 * b] = r0;
         RB[2 * b + 1] = r1;
     }
+    __syncthreads();
+    // step entries in walk order: position i is block i forward, block nb - 1 - i backward
+    int4* SF = reinterpret_cast<int4*>(c.step_f);
+    int4* SB = reinterpret_cast<int4*>(c.step_b);
+    for (int i = tid; i < nb; i += nt) {
+        int4 t0, t1;
+        make_step(RF[2 * i], RF[2 * i + 1], i, false, nb, ring_slots, t0, t1);
+        SF[2 * i] = t0;
+        SF[2 * i + 1] = t1;
+        const int b = nb - 1 - i;
+        make_step(RB[2 * b], RB[2 * b + 1], b, true, nb, ring_slots, t0, t1);
+        SB[2 * i] = t0;
+        SB[2 * i + 1] = t1;
+    }
 }
 
 // --------------------------------------------------------------------------
 // solve
 // --------------------------------------------------------------------------
 // One workgroup of two wavefronts solves one tile: a CFG and a run of up to
-// 63 consecutive 64-bit words of its variable axis.  Lane l owns word s0 + l
+// TILE_WORDS (15) consecutive 64-bit words of its variable axis; lanes 0 to
+// LANES - 1 (16) of each wavefront take part.  Lane l owns word s0 + l
 // of every row; in the two phases that compute the CFG's reachability facts,
 // lane nw (the flag lane) carries them as a pseudo-variable word whose inputs
 // are synthesised so that the same equations compute them:
@@ -211,8 +276,11 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
 //   next use, device channel, bit 1: a DEVICE block is reachable from here
 //   eager validity, host channel, bit 0: the block is NOT reached from ENTRY
 //   eager validity, host channel, bit 1: no DEVICE block reaches the block
-// Lanes past the tile shadow word s0 (same inputs, same results), so the walk
-// has no lane divergence and its block records stay scalar loads.
+// Lanes past the tile (below LANES) shadow word s0 (same inputs, same
+// results), so the walk has no lane divergence and its block records stay
+// scalar loads.  Narrow tiles keep the LDS of a workgroup small (about 20 KiB),
+// so that many tiles are resident per CU: most CFGs have few words, and a
+// step costs the same instructions whatever the tile's width.
 //
 // A phase is a sequence of Gauss-Seidel sweeps in block-id order (reverse
 // order for the backward phase).  The compute wavefront walks the blocks and
@@ -239,14 +307,6 @@ struct Rec {
     int32_t pad;
 };
 
-// Step descriptor: x flags, y and z the LDS byte offsets of the states of neighbours 0 and 1
-// (a ring slot, the step's far input, or the identity state), w the block.  Flag bits 0-1 / 2-3:
-// where neighbour 0 / 1 is found: 0 nowhere (missing), 1 the block computed last, 2 the ring,
-// 3 the far input.
-constexpr uint32_t DF_SLOW = 1u << 4;   // ENTRY, EXIT, a call, no or more than two neighbours, two far ones
-constexpr uint32_t DF_DEV = 1u << 5;    // a DEVICE block
-constexpr uint32_t DF_LE0 = 1u << 6;    // edge of neighbour 0 is a loop entry (forward phases)
-constexpr uint32_t DF_LE1 = 1u << 7;    // edge of neighbour 1 is a loop entry
 
 template <typename T>
 __device__ __forceinline__ const CAS T* K(const T* p) { return (const CAS T*)p; }
@@ -285,7 +345,7 @@ __device__ __forceinline__ u64 settle(u64 x)
 }
 
 // Copy of one 64-bit word per lane from global memory into LDS without
-// registers: lane l's word lands at dst[l] (low half) and dst[64 + l] (high
+// registers: lane l's word lands at dst[l] (low half) and dst[LANES + l] (high
 // half); dst is wave-uniform.  Completion is counted by vmcnt.
 constexpr unsigned CPOL_SC1 = 16;   // read past the first-level cache
 template <unsigned CPOL>
@@ -293,7 +353,7 @@ __device__ __forceinline__ void dma64(const GAS u64* src, uint32_t* dst)
 {
     const GAS uint32_t* s32 = reinterpret_cast<const GAS uint32_t*>(src);
     __builtin_amdgcn_global_load_lds(s32, (__attribute__((address_space(3))) void*)dst, 4, 0, CPOL);
-    __builtin_amdgcn_global_load_lds(s32 + 1, (__attribute__((address_space(3))) void*)(dst + 64), 4, 0, CPOL);
+    __builtin_amdgcn_global_load_lds(s32 + 1, (__attribute__((address_space(3))) void*)(dst + LANES), 4, 0, CPOL);
 }
 
 // Coordination of the two wavefronts of a tile (LDS).
@@ -364,12 +424,12 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     const bool dat = lane < nw, flg = with_flags && (lane == nw || nw == 0), act = dat || flg;
     const int w = s0 + (dat ? lane : 0);
     Ctl* ctl = reinterpret_cast<Ctl*>(lds);
-    // Every 64-bit per-lane word in LDS is stored split: 64 low halves, then 64 high halves
-    // (512 bytes); a state (h, d) is two such words (1 KiB).
+    // Every 64-bit per-lane word in LDS is stored split: LANES low halves, then LANES high
+    // halves (WORD_BYTES); a state (h, d) is two such words (STATE_BYTES).
     char* lds8 = reinterpret_cast<char*>(lds);
     constexpr int RING_OFF = CTL_BYTES;                                   // RS states: the last results
-    const int IN_OFF = RING_OFF + RS * 1024;                              // IR steps of NI input words
-    const int DESC_OFF = IN_OFF + IR * NI * 512;                          // IR step descriptors
+    const int IN_OFF = RING_OFF + RS * STATE_BYTES;                       // IR steps of NI input words
+    const int DESC_OFF = IN_OFF + IR * NI * WORD_BYTES;                   // IR step descriptors
     const int IDENT_OFF = DESC_OFF + IR * 16;                             // one state of identity words
     u64* iring = reinterpret_cast<u64*>(lds8 + IN_OFF);
     int4* dring = reinterpret_cast<int4*>(lds8 + DESC_OFF);
@@ -399,22 +459,22 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // the word at LDS byte offset `at` (split layout), this lane's
     auto w_get = [&](int at) -> u64 {
         const uint32_t* q = reinterpret_cast<const uint32_t*>(lds8 + at) + lane;
-        return (u64)q[0] | ((u64)q[64] << 32);
+        return (u64)q[0] | ((u64)q[LANES] << 32);
     };
     auto w_put = [&](int at, u64 v) {
         uint32_t* q = reinterpret_cast<uint32_t*>(lds8 + at) + lane;
         q[0] = (uint32_t)v;
-        q[64] = (uint32_t)(v >> 32);
+        q[LANES] = (uint32_t)(v >> 32);
     };
-    auto ring_at = [&](int g) -> int { return RING_OFF + (g & (RS - 1)) * 1024; };   // state of step g
+    auto ring_at = [&](int g) -> int { return RING_OFF + (g & (RS - 1)) * STATE_BYTES; };   // state of step g
     auto slot_h = [&](int g) -> u64 { return w_get(ring_at(g)); };
-    auto slot_d = [&](int g) -> u64 { return w_get(ring_at(g) + 512); };
-    // input k of step g: 64 low halves, then 64 high halves
+    auto slot_d = [&](int g) -> u64 { return w_get(ring_at(g) + WORD_BYTES); };
+    // input k of step g: LANES low halves, then LANES high halves
     uint32_t* iring32 = reinterpret_cast<uint32_t*>(iring);
-    auto in32 = [&](int g, int k) -> uint32_t* { return iring32 + ((size_t)(g & (IR - 1)) * NI + k) * 128; };
+    auto in32 = [&](int g, int k) -> uint32_t* { return iring32 + ((size_t)(g & (IR - 1)) * NI + k) * (2 * LANES); };
     auto in_get = [&](int g, int k) -> u64 {
         const uint32_t* q = in32(g, k) + lane;
-        return (u64)q[0] | ((u64)q[64] << 32);
+        return (u64)q[0] | ((u64)q[LANES] << 32);
     };
 
     // neighbour j of a record (j >= 2 from the CSR); edge id with LOOP_ENTRY in bit 31
@@ -436,15 +496,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // At compute time a neighbour at distance 1 is in registers and one at 2..RS in the ring;
     // the first other one ("far": not yet visited in this sweep, or more than RS steps back)
     // comes with the step's inputs.
-    auto is_far = [&](int d) -> bool { return d <= 0 || d > RS; };
-    auto first_far = [&](const Rec& r, int b, int& p, int& d) -> bool {
-        const int cnt = (int)(r.meta & REC_COUNT);
-        if (cnt > 0) { const int dd = dist(b, r.n0); if (is_far(dd)) { p = r.n0; d = dd; return true; } }
-        if (cnt > 1) { const int dd = dist(b, r.n1); if (is_far(dd)) { p = r.n1; d = dd; return true; } }
-        return false;
-    };
     // ---------------------------------------------------------------- helper wavefront
-    // Each round: plans the steps up to IR ahead of the compute wavefront (block records through
+    // Each round: plans the steps up to IR ahead of the compute wavefront (step entries through
     // the scalar cache; each step's descriptor and, when it is not in the rows, its far
     // neighbour's state go to LDS); stores the results the compute wavefront has put in the ring
     // since the last round; copies the other inputs from global memory straight into LDS; waits
@@ -454,12 +507,19 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // when it is not yet visited): from the rows when u was stored in an earlier round, from the
     // ring when it is computed but not stored yet (its slot is not released before this round
     // ends), the initial value in the first sweep.  Steps whose u is not computed yet wait.
-    // far neighbour of the block b of step st: p, and the step u of its state (-1: the initial value)
-    auto far_of = [&](const Rec& r, int b, int st, int& p) -> int {
-        int d = 0;
-        p = b;
-        if (!first_far(r, b, p, d)) return -1;
-        return d > 0 ? st - d : (st >= nb ? st - d - nb : -1);
+    const CAS int32_t* STEP = K(BWD ? c.step_b : c.step_f);
+    // words 0-3 / 4-7 of the step entry at walk position i (scalar loads)
+    auto step_lo = [&](int i) -> int4 {
+        const CAS int32_t* q = STEP + 8 * (size_t)i;
+        return make_int4(q[0], q[1], q[2], q[3]);
+    };
+    auto step_hi = [&](int i) -> int4 {
+        const CAS int32_t* q = STEP + 8 * (size_t)i + 4;
+        return make_int4(q[0], q[1], q[2], q[3]);
+    };
+    // step u of the far neighbour's state for step st with entry word x / w (-1: the initial value)
+    auto far_step = [&](uint32_t x, int w, int st) -> int {
+        return ((x & SF_BACK) && st < nb) ? -1 : st - w;
     };
     auto helper_loop = [&](const Rows& S, u64 init, auto&& pre) {
         int gf = 0, fi = 0;   // next step to store and its index within the sweep
@@ -475,14 +535,12 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             int n = 0;
             bool stop = false;
             for (int s4 = pf, l4 = pi; s4 < pend && !stop; s4 += 4) {
-                Rec r4[4];
-                int b4[4];
+                int4 t4[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {   // four records in flight
+                for (int q = 0; q < 4; ++q) {   // four entries in flight
                     int lq = l4 + q;
                     while (lq >= nb) lq -= nb;
-                    b4[q] = blk(lq);
-                    if (s4 + q < pend) r4[q] = ldrec(REC, b4[q]);
+                    if (s4 + q < pend) t4[q] = step_lo(lq);
                 }
                 l4 += 4;
                 while (l4 >= nb) l4 -= nb;
@@ -490,37 +548,20 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 for (int q = 0; q < 4; ++q) {
                     const int st = s4 + q;
                     if (stop || st >= pend) break;
-                    const int b = b4[q];
-                    const Rec& r = r4[q];
-                    int p;
-                    const int u = far_of(r, b, st, p);
-                    if (u >= prod) { stop = true; break; }   // not computed yet
-                    const int cnt = (int)(r.meta & REC_COUNT);
-                    uint32_t fl = (cnt > 2 || cnt == 0 || (r.meta & (REC_ENTRY | REC_EXIT | REC_CALL))) ? DF_SLOW : 0u;
-                    fl |= (r.meta & REC_DEV) ? DF_DEV : 0u;
-                    fl |= (r.e0 & 0x80000000u) ? DF_LE0 : 0u;
-                    fl |= ((r.e1 & 0x80000000u) && cnt > 1) ? DF_LE1 : 0u;
-                    int loc[2] = {IDENT_OFF, IDENT_OFF};   // where the state of each neighbour is found
-                    bool far = false;
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        if (j < cnt) {
-                            const int dj = dist(b, j == 0 ? r.n0 : r.n1);
-                            uint32_t k;
-                            if (dj == 1) k = 1;
-                            else if (dj >= 2 && dj <= RS) { k = 2; loc[j] = ring_at(st - dj); }
-                            else if (!far) { k = 3; far = true; loc[j] = IN_OFF + ((st & (IR - 1)) * NI + NX) * 512; }
-                            else { k = 0; fl |= DF_SLOW; }
-                            fl |= k << (2 * j);
-                        }
-                    }
-                    if (u < 0 || u >= gf0) {
+                    const uint32_t fl = (uint32_t)t4[q].x;
+                    const int u = far_step(fl, t4[q].w, st);
+                    if ((fl & SF_FAR) && u >= prod) { stop = true; break; }   // not computed yet
+                    const int far_at = IN_OFF + ((st & (IR - 1)) * NI + NX) * WORD_BYTES;
+                    const uint32_t k0 = fl & 3u, k1 = (fl >> 2) & 3u;
+                    const int loc0 = k0 == 2 ? ring_at(st - (t4[q].y & 0xFF)) : k0 == 3 ? far_at : IDENT_OFF;
+                    const int loc1 = k1 == 2 ? ring_at(st - ((t4[q].y >> 8) & 0xFF)) : k1 == 3 ? far_at : IDENT_OFF;
+                    if ((fl & SF_FAR) && (u < 0 || u >= gf0)) {
                         const u64 h = u < 0 ? init : slot_h(u), d = u < 0 ? init : slot_d(u);
                         uint32_t* qq = in32(st, NX) + lane;
-                        qq[0] = (uint32_t)h; qq[64] = (uint32_t)(h >> 32);
-                        qq[128] = (uint32_t)d; qq[192] = (uint32_t)(d >> 32);
+                        qq[0] = (uint32_t)h; qq[LANES] = (uint32_t)(h >> 32);
+                        qq[2 * LANES] = (uint32_t)d; qq[3 * LANES] = (uint32_t)(d >> 32);
                     }
-                    if (lane == 0) dring[st & (IR - 1)] = make_int4((int)fl, loc[0], loc[1], b);
+                    if (lane == 0) dring[st & (IR - 1)] = make_int4((int)(fl & DF_MASK), loc0, loc1, 0);
                     ++n;
                 }
             }
@@ -554,28 +595,27 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             // the other inputs: copies from global memory straight into the input slots (no LDS read
             // follows them before the wait); far rows past the first-level cache (the helper stored them)
             for (int t4 = 0, l4 = pi; t4 < n; t4 += 4) {
-                Rec r4[4];
-                int b4[4];
+                int4 s4[4], e4[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {   // four records in flight
+                for (int q = 0; q < 4; ++q) {   // four entries in flight
                     int lq = l4 + q;
                     while (lq >= nb) lq -= nb;
-                    b4[q] = blk(lq);
-                    if (t4 + q < n) r4[q] = ldrec(REC, b4[q]);
+                    if (t4 + q < n) { s4[q] = step_lo(lq); e4[q] = step_hi(lq); }
                 }
                 l4 += 4;
                 while (l4 >= nb) l4 -= nb;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     if (t4 + q < n) {
-                        const int st = pf + t4 + q, b = b4[q];
+                        const int st = pf + t4 + q;
                         const GAS u64* a[NX];
-                        pre(b, r4[q], a);
+                        pre(e4[q].x, (uint32_t)e4[q].y, (uint32_t)e4[q].z, a);
 #pragma unroll
                         for (int k = 0; k < NX; ++k) dma64<0>(a[k], in32(st, k));
-                        int p;
-                        const int u = far_of(r4[q], b, st, p);
-                        if (u >= 0 && u < gf0) {
+                        const uint32_t fl = (uint32_t)s4[q].x;
+                        const int u = far_step(fl, s4[q].w, st);
+                        if ((fl & SF_FAR) && u >= 0 && u < gf0) {
+                            const int p = s4[q].z;
                             dma64<CPOL_SC1>(S.h + (size_t)p * S.str, in32(st, NX));
                             dma64<CPOL_SC1>(S.d + (size_t)p * S.str, in32(st, NX + 1));
                         }
@@ -633,8 +673,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     auto fetch = [&](int g, int l0, int l1, u64* x, u64* nh, u64* nd) {
 #pragma unroll
         for (int k = 0; k < NX; ++k) x[k] = in_get(g, k);
-        nh[0] = w_get(l0); nd[0] = w_get(l0 + 512);
-        nh[1] = w_get(l1); nd[1] = w_get(l1 + 512);
+        nh[0] = w_get(l0); nd[0] = w_get(l0 + WORD_BYTES);
+        nh[1] = w_get(l1); nd[1] = w_get(l1 + WORD_BYTES);
     };
     auto walk = [&](const Rows& S, u64 init, int sweep, uint32_t& pc, auto&& fast, auto&& comp) {
         u64 ph = init, pd = init;   // state of the block computed last
@@ -692,7 +732,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             // the ring slot of step g was last used by step g - RS: the helper must have read it
             need(&ctl->consumed, cons, g - RS);
             w_put(ring_at(g), vh);
-            w_put(ring_at(g) + 512, vd);
+            w_put(ring_at(g) + WORD_BYTES, vd);
             lds_release();
             lds_put(&ctl->produced, g + 1);
             ph = vh; pd = vd;
@@ -716,7 +756,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             return true;
         }
         w_put(IDENT_OFF, ident);   // the state of a missing neighbour
-        w_put(IDENT_OFF + 512, ident);
+        w_put(IDENT_OFF + WORD_BYTES, ident);
         int sweeps = 0;
         uint32_t last = (uint32_t)nb * 2u * (uint32_t)__popcll(init);
         bool good = true;
@@ -781,7 +821,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     if constexpr (PH == PH_NU) {
         const Rows S = rows_of(c.nu_h, c.nu_d, 0);
         // x0 = R, x1 = W (flag lane: R = 2, W = 2 at DEVICE blocks, substituted when computed)
-        auto pre = [&](int b, const Rec& r, const GAS u64** x) {
+        auto pre = [&](int b, uint32_t, uint32_t, const GAS u64** x) {
             x[0] = rowp(c.R, b);
             x[1] = rowp(c.W, b);
         };
@@ -829,7 +869,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         const Rows S = rows_of(c.aveout_h, c.aveout_d, 2);
         const u64 init = ~0ull & vm;
         // x0/x1 = NU (flag lane: 0), x2 = W (flag lane: 2 at DEVICE blocks), substituted when computed
-        auto pre = [&](int b, const Rec& r, const GAS u64** x) {
+        auto pre = [&](int b, uint32_t, uint32_t, const GAS u64** x) {
             x[0] = rowp(c.nu_h, b);
             x[1] = rowp(c.nu_d, b);
             x[2] = rowp(c.W, b);
@@ -869,7 +909,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         if (helper) return;
         // reachability: every block reached from ENTRY and reaching EXIT
         bool bad = false;
-        for (int b = lane; b < nb; b += 64) {
+        for (int b = lane; b < nb; b += LANES) {
             const u64 fnu = ld_fresh(FLG + b), fave = ld_fresh(FLG + (size_t)2 * nb + b);
             const u64 fnud = ld_fresh(FLG + (size_t)nb + b);
             if (!(fnu & 1) || (fave & 1)) bad = true;
@@ -909,10 +949,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         if (c.placement & 1) return;
         const Rows S = rows_of(c.mayp_h, c.mayp_d, 0);
         // x0 = R, x1 = W, x2..x5 = EAG_H/D of the two inline in-edges
-        auto pre = [&](int b, const Rec& r, const GAS u64** x) {
+        // (edge 0 stands in for a missing neighbour's edge)
+        auto pre = [&](int b, uint32_t e0, uint32_t e1, const GAS u64** x) {
             x[0] = rowp(c.R, b); x[1] = rowp(c.W, b);
-            const int cnt = (int)(r.meta & REC_COUNT);
-            const uint32_t e0 = cnt > 0 ? r.e0 : 0u, e1 = cnt > 1 ? r.e1 : 0u;   // edge 0 stands in for a missing one
             x[2] = erowp(c.eag_h, e0); x[3] = erowp(c.eag_d, e0);
             x[4] = erowp(c.eag_h, e1); x[5] = erowp(c.eag_d, e1);
         };
@@ -964,10 +1003,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         if (c.placement & 1) return;
         const Rows S = rows_of(c.later_h, c.later_d, 0);
         // x0 = R, x1 = W, x2..x4 / x5..x7 = EAG_H, EAG_D, BOTH of the two inline in-edges
-        auto pre = [&](int b, const Rec& r, const GAS u64** x) {
+        auto pre = [&](int b, uint32_t e0, uint32_t e1, const GAS u64** x) {
             x[0] = rowp(c.R, b); x[1] = rowp(c.W, b);
-            const int cnt = (int)(r.meta & REC_COUNT);
-            const uint32_t e0 = cnt > 0 ? r.e0 : 0u, e1 = cnt > 1 ? r.e1 : 0u;
             x[2] = erowp(c.eag_h, e0); x[3] = erowp(c.eag_d, e0); x[4] = erowp(c.both, e0);
             x[5] = erowp(c.eag_h, e1); x[6] = erowp(c.eag_d, e1); x[7] = erowp(c.both, e1);
         };
@@ -1025,10 +1062,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         const Rows S = rows_of(c.aveout_h, c.aveout_d, 2);
         const u64 init = ~0ull & vm;
         // x0/x1 = INS_ENTRY, x2 = W, x3..x6 = INS_EDGE_H/D of the two inline in-edges
-        auto pre = [&](int b, const Rec& r, const GAS u64** x) {
+        auto pre = [&](int b, uint32_t e0, uint32_t e1, const GAS u64** x) {
             x[0] = rowp(c.ie_h, b); x[1] = rowp(c.ie_d, b); x[2] = rowp(c.W, b);
-            const int cnt = (int)(r.meta & REC_COUNT);
-            const uint32_t e0 = cnt > 0 ? r.e0 : 0u, e1 = cnt > 1 ? r.e1 : 0u;
             x[3] = erowp(c.ig_h, e0); x[4] = erowp(c.ig_d, e0);
             x[5] = erowp(c.ig_h, e1); x[6] = erowp(c.ig_d, e1);
         };
@@ -1248,7 +1283,9 @@ __device__ __forceinline__ void tile_phase(const DevCfg& c, const Tile& tl, u64*
         ctl->in_ready = 0;
     }
     __syncthreads();
-    if (!__builtin_amdgcn_readfirstlane(ctl->skip)) solve_phase<PH>(c, tl.s0, tl.nw, tl.fslot, lds, ring_slots);
+    // lanes past LANES hold no word and stay out
+    if (!__builtin_amdgcn_readfirstlane(ctl->skip) && (threadIdx.x & 63) < LANES)
+        solve_phase<PH>(c, tl.s0, tl.nw, tl.fslot, lds, ring_slots);
     __syncthreads();
 }
 

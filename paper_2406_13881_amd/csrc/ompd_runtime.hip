@@ -16,7 +16,7 @@
 #include "ompd_internal.h"
 
 namespace ompd {
-extern "C" __global__ void ompd_k_prep(const DevCfg*, int, int32_t*);
+extern "C" __global__ void ompd_k_prep(const DevCfg*, int, int32_t*, int);
 extern "C" __global__ void ompd_k_nu(const DevCfg*, const Tile*, int, int32_t*, int);
 extern "C" __global__ void ompd_k_ave(const DevCfg*, const Tile*, int, int32_t*, int);
 extern "C" __global__ void ompd_k_mayp(const DevCfg*, const Tile*, int, int32_t*, int);
@@ -181,6 +181,8 @@ size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o)
     o.tmp = take(4 * ((size_t)g.n_blocks + 1));
     o.recf = take(32 * (size_t)g.n_blocks);
     o.recb = take(32 * (size_t)g.n_blocks);
+    o.stf = take(32 * (size_t)g.n_blocks);
+    o.stb = take(32 * (size_t)g.n_blocks);
     o.info = take(4 * INFO_WORDS);
     return total;
 }
@@ -233,6 +235,7 @@ void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const
     d.pred_ptr = (int32_t*)(base + o.pp); d.pred_idx = (int32_t*)(base + o.pi);
     d.pred_eid = (int32_t*)(base + o.pe); d.tmp = (int32_t*)(base + o.tmp);
     d.rec_f = (int32_t*)(base + o.recf); d.rec_b = (int32_t*)(base + o.recb);
+    d.step_f = (int32_t*)(base + o.stf); d.step_b = (int32_t*)(base + o.stb);
     d.info = (int32_t*)(base + o.info);
     if (bnd_host && wd > 0) {
         uint64_t last = (g.n_vars & 63) ? ((1ull << (g.n_vars & 63)) - 1) : ~0ull;
@@ -245,8 +248,8 @@ void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const
     }
 }
 
-// Default result ring of one phase workgroup (recently computed blocks, 1 KiB each).
-constexpr size_t RING_BYTES_DEFAULT = 16 * 1024;
+// Default result ring of one phase workgroup (recently computed blocks, STATE_BYTES each).
+constexpr size_t RING_BYTES_DEFAULT = 64 * STATE_BYTES;
 
 // Tiles for a set of CFGs, longest first, the edge-step items and the launch
 // sizes that go with them under a configuration.
@@ -262,10 +265,10 @@ int ompd_make_shape(ompd_ctx* ctx, const std::vector<DevCfg>& cfgs, const PlanCo
     for (int t = 0; t < (int)tiles.size(); ++t)
         if (tiles[t].nw > 0)
             for (int b0 = 0; b0 < cfgs[tiles[t].cfg].nb; b0 += 64) sh.items.push_back(EdgeItem{t, b0});
-    // result ring: a power of two of 1 KiB slots in [8, 64], as large as every phase's LDS allows
+    // result ring: a power of two of STATE_BYTES slots in [8, 64], as large as every phase's LDS allows
     const size_t want = pc.lds_bytes ? pc.lds_bytes : RING_BYTES_DEFAULT;
     int rs = 8;
-    while (rs < 64 && (size_t)(2 * rs) * 1024 <= want) rs *= 2;
+    while (rs < 64 && (size_t)(2 * rs) * STATE_BYTES <= want) rs *= 2;
     while (rs > 1 && phase_lds(PH_LATER, rs) > (size_t)ctx->lds_max) rs /= 2;
     LaunchDims& dm = sh.dims;
     dm.ring_slots = rs;
@@ -382,10 +385,10 @@ int ompd_plan_retile(ompd_plan* p, const PlanConfig& pc)
     return OMPD_OK;
 }
 
-int ompd_launch_prep(const DevCfg* d_cfgs, int n, int32_t* d_counter, size_t lds, hipStream_t s)
+int ompd_launch_prep(const DevCfg* d_cfgs, int n, int32_t* d_counter, size_t lds, int ring_slots, hipStream_t s)
 {
     if (n <= 0) return OMPD_OK;
-    hipLaunchKernelGGL(ompd_k_prep, dim3(n), dim3(256), lds, s, d_cfgs, n, d_counter);
+    hipLaunchKernelGGL(ompd_k_prep, dim3(n), dim3(256), lds, s, d_cfgs, n, d_counter, ring_slots);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return ompd_fail(OMPD_E_DEVICE, std::string("prep launch (lds ") + std::to_string(lds) + "): " +
@@ -445,7 +448,7 @@ int ompd_launch_solve(const DevCfg* d_cfgs, const Tile* d_tiles, int n_tiles, co
 
 static int launch_prep(ompd_plan* p, hipStream_t s)
 {
-    return ompd_launch_prep((const DevCfg*)p->d_cfgs, p->n, p->d_counter, p->lds_prep, s);
+    return ompd_launch_prep((const DevCfg*)p->d_cfgs, p->n, p->d_counter, p->lds_prep, p->dims.ring_slots, s);
 }
 
 static int launch_solve(ompd_plan* p, hipStream_t s)
@@ -686,8 +689,8 @@ extern "C" int ompd_plan_autotune(ompd_plan* p, void* stream, int32_t trials, fl
     hipStream_t s = (hipStream_t)stream;
     trials = std::max(1, trials);
     std::vector<PlanConfig> cands;
-    for (size_t lds : {(size_t)8192, (size_t)16384, (size_t)32768}) {
-        for (int wpc : {0, 2, 4}) {
+    for (size_t lds : {(size_t)16 * STATE_BYTES, (size_t)32 * STATE_BYTES, (size_t)64 * STATE_BYTES}) {
+        for (int wpc : {0, 4}) {
             PlanConfig c = p->cfg;
             c.lds_bytes = lds;
             c.wg_per_cu = wpc;

@@ -214,7 +214,7 @@ static void launcher_main(ServingState* S)
                 e = hipMemcpyAsync(dtab, pin, cfg_bytes + tile_bytes, hipMemcpyHostToDevice, s);
             int32_t* counter = (int32_t*)(dtab + cfg_bytes + tile_bytes);
             if (e != hipSuccess) rc = OMPD_E_DEVICE;
-            if (rc == OMPD_OK) rc = ompd_launch_prep((const DevCfg*)dtab, k, counter, sh.lds_prep, s);
+            if (rc == OMPD_OK) rc = ompd_launch_prep((const DevCfg*)dtab, k, counter, sh.lds_prep, sh.dims.ring_slots, s);
             if (rc == OMPD_OK)
                 rc = ompd_launch_solve((const DevCfg*)dtab, (const Tile*)(dtab + cfg_bytes), (int)tiles.size(),
                                        (const EdgeItem*)(dtab + cfg_bytes + (tile_bytes - item_bytes)),
