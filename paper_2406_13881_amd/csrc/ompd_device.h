@@ -101,8 +101,10 @@ inline int tiles_of(int wd) { return wd <= 0 ? 1 : (wd + TILE_WORDS - 1) / TILE_
 // descriptors, then one state of identity words (1 KiB).
 constexpr int CTL_BYTES = 256;
 constexpr int LDS_FIXED = CTL_BYTES;
-// steps of inputs kept ready per phase (a power of two; more for the phases with fewer inputs)
-constexpr int in_ring(int ph) { return ph == PH_NU || ph == PH_AVE ? 16 : 8; }
+// steps of inputs kept ready per phase (a power of two; more for the phases with fewer inputs).
+// The helper wavefront refills them in rounds whose fixed cost is spread over the steps it
+// finds free, so a deeper ring means fewer, longer rounds.
+constexpr int in_ring(int ph) { return ph == PH_NU || ph == PH_AVE ? 32 : 16; }
 inline int phase_inputs(int ph) { return 2 + (ph == PH_NU ? 2 : ph == PH_AVE ? 3 : ph == PH_MAYP ? 6 : ph == PH_LATER ? 8 : 7); }
 inline size_t phase_lds(int ph, int ring_slots)
 {

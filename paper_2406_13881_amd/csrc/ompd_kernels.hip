@@ -344,16 +344,16 @@ __device__ __forceinline__ u64 settle(u64 x)
     return x;
 }
 
-// Copy of one 64-bit word per lane from global memory into LDS without
-// registers: lane l's word lands at dst[l] (low half) and dst[LANES + l] (high
-// half); dst is wave-uniform.  Completion is counted by vmcnt.
+// Copy of one 64-bit word per owning lane from global memory into LDS without
+// registers, by 2 LANES lanes: lane l < LANES copies the low half of its word
+// `src` to dst[l], lane LANES + l (hi, the same src) the high half to
+// dst[LANES + l]; dst is wave-uniform.  Completion is counted by vmcnt.
 constexpr unsigned CPOL_SC1 = 16;   // read past the first-level cache
 template <unsigned CPOL>
-__device__ __forceinline__ void dma64(const GAS u64* src, uint32_t* dst)
+__device__ __forceinline__ void dma_word(const GAS u64* src, bool hi, uint32_t* dst)
 {
-    const GAS uint32_t* s32 = reinterpret_cast<const GAS uint32_t*>(src);
+    const GAS uint32_t* s32 = reinterpret_cast<const GAS uint32_t*>(src) + (hi ? 1 : 0);
     __builtin_amdgcn_global_load_lds(s32, (__attribute__((address_space(3))) void*)dst, 4, 0, CPOL);
-    __builtin_amdgcn_global_load_lds(s32 + 1, (__attribute__((address_space(3))) void*)(dst + LANES), 4, 0, CPOL);
 }
 
 // Coordination of the two wavefronts of a tile (LDS).
@@ -417,12 +417,17 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     constexpr int NX = PH == PH_NU ? 2 : PH == PH_AVE ? 3 : PH == PH_MAYP ? 6 : PH == PH_LATER ? 8 : 7;
     constexpr int NI = NX + 2;        // inputs of a step: the phase's own and the first far neighbour (h, d)
     constexpr int IR = in_ring(PH);   // steps whose inputs the helper keeps ready
+    // Lanes 0 .. LANES - 1 of both wavefronts own the tile's words; lanes LANES .. 2 LANES - 1 of
+    // the helper mirror them (same word, same rows) only to copy the high halves of input words
+    // (`hi`): every other per-lane LDS write and global store is made by the low lanes.
     const int lane = threadIdx.x & 63;
+    const int ln = lane & (LANES - 1);
+    const bool hi = lane >= LANES;
     const bool helper = threadIdx.x >= 64;
     const int nb = c.nb, wd = c.wd;
     // a tile without variables (nw = 0) has only flag lanes (they compute the same facts)
-    const bool dat = lane < nw, flg = with_flags && (lane == nw || nw == 0), act = dat || flg;
-    const int w = s0 + (dat ? lane : 0);
+    const bool dat = ln < nw, flg = with_flags && (ln == nw || nw == 0), act = dat || flg;
+    const int w = s0 + (dat ? ln : 0);
     Ctl* ctl = reinterpret_cast<Ctl*>(lds);
     // Every 64-bit per-lane word in LDS is stored split: LANES low halves, then LANES high
     // halves (WORD_BYTES); a state (h, d) is two such words (STATE_BYTES).
@@ -458,11 +463,11 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     };
     // the word at LDS byte offset `at` (split layout), this lane's
     auto w_get = [&](int at) -> u64 {
-        const uint32_t* q = reinterpret_cast<const uint32_t*>(lds8 + at) + lane;
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(lds8 + at) + ln;
         return (u64)q[0] | ((u64)q[LANES] << 32);
     };
-    auto w_put = [&](int at, u64 v) {
-        uint32_t* q = reinterpret_cast<uint32_t*>(lds8 + at) + lane;
+    auto w_put = [&](int at, u64 v) {   // (low lanes)
+        uint32_t* q = reinterpret_cast<uint32_t*>(lds8 + at) + ln;
         q[0] = (uint32_t)v;
         q[LANES] = (uint32_t)(v >> 32);
     };
@@ -473,7 +478,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     uint32_t* iring32 = reinterpret_cast<uint32_t*>(iring);
     auto in32 = [&](int g, int k) -> uint32_t* { return iring32 + ((size_t)(g & (IR - 1)) * NI + k) * (2 * LANES); };
     auto in_get = [&](int g, int k) -> u64 {
-        const uint32_t* q = in32(g, k) + lane;
+        const uint32_t* q = in32(g, k) + ln;
         return (u64)q[0] | ((u64)q[LANES] << 32);
     };
 
@@ -555,9 +560,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                     const uint32_t k0 = fl & 3u, k1 = (fl >> 2) & 3u;
                     const int loc0 = k0 == 2 ? ring_at(st - (t4[q].y & 0xFF)) : k0 == 3 ? far_at : IDENT_OFF;
                     const int loc1 = k1 == 2 ? ring_at(st - ((t4[q].y >> 8) & 0xFF)) : k1 == 3 ? far_at : IDENT_OFF;
-                    if ((fl & SF_FAR) && (u < 0 || u >= gf0)) {
+                    if ((fl & SF_FAR) && (u < 0 || u >= gf0) && !hi) {
                         const u64 h = u < 0 ? init : slot_h(u), d = u < 0 ? init : slot_d(u);
-                        uint32_t* qq = in32(st, NX) + lane;
+                        uint32_t* qq = in32(st, NX) + ln;
                         qq[0] = (uint32_t)h; qq[LANES] = (uint32_t)(h >> 32);
                         qq[2 * LANES] = (uint32_t)d; qq[3 * LANES] = (uint32_t)(d >> 32);
                     }
@@ -574,7 +579,10 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 if (__builtin_amdgcn_readfirstlane(lds_get(&ctl->abort))) return;
                 // the compute wavefront always ends with `done` or `abort`; this bound only keeps the kernel finite
                 if (++spins > 4 * SPIN_MAX) { lds_put(&ctl->abort, 1); return; }
-                __builtin_amdgcn_s_sleep(1);
+                // a compute step takes thousands of cycles: poll less once idle, leaving the
+                // issue slots to the other wavefronts of the SIMD
+                if (spins > 1) __builtin_amdgcn_s_sleep(8);
+                else __builtin_amdgcn_s_sleep(1);
                 continue;
             }
             spins = 0;
@@ -586,7 +594,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
                     if (gf < fend) {
-                        if (act) S.st(blk(fi), h[t], d[t]);
+                        if (act && !hi) S.st(blk(fi), h[t], d[t]);
                         fi = fi + 1 == nb ? 0 : fi + 1;
                         ++gf;
                     }
@@ -611,13 +619,13 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                         const GAS u64* a[NX];
                         pre(e4[q].x, (uint32_t)e4[q].y, (uint32_t)e4[q].z, a);
 #pragma unroll
-                        for (int k = 0; k < NX; ++k) dma64<0>(a[k], in32(st, k));
+                        for (int k = 0; k < NX; ++k) dma_word<0>(a[k], hi, in32(st, k));
                         const uint32_t fl = (uint32_t)s4[q].x;
                         const int u = far_step(fl, s4[q].w, st);
                         if ((fl & SF_FAR) && u >= 0 && u < gf0) {
                             const int p = s4[q].z;
-                            dma64<CPOL_SC1>(S.h + (size_t)p * S.str, in32(st, NX));
-                            dma64<CPOL_SC1>(S.d + (size_t)p * S.str, in32(st, NX + 1));
+                            dma_word<CPOL_SC1>(S.h + (size_t)p * S.str, hi, in32(st, NX));
+                            dma_word<CPOL_SC1>(S.d + (size_t)p * S.str, hi, in32(st, NX + 1));
                         }
                     }
                 }
@@ -659,9 +667,13 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // ENTRY, EXIT or a call, at most two neighbours, at most one of them far) from its inputs x,
     // its step flags and its first two neighbours' states (`ident` for a missing one);
     // comp(b, r, x, nh, nd, ph, pd, sweep, g, vh, vd) computes any block.
-    // The walk is pipelined by a step: while step g computes, step g + 1's inputs and the states
-    // of its neighbours other than the block computed last (a ring slot or the far input) are
-    // being read, and so is the descriptor of step g + 2.
+    // The walk is pipelined: while step g computes, the reads of step g + 1's inputs and of the
+    // states of its neighbours other than the block computed last (a ring slot or the far
+    // input) are in flight, and so is the read of step g + 3's descriptor; step g + 2's
+    // descriptor, read during step g - 1, is decoded after step g.  LDS completes a wavefront's
+    // accesses in order, so waiting for older reads leaves the newer ones in flight; the
+    // counters are read before the next step's reads are issued, since a wait for a counter
+    // also waits for every LDS access before it.
     auto desc = [&](int g, uint32_t& fl, int& l0, int& l1) {
         const int4 dn = dring[g & (IR - 1)];
         fl = (uint32_t)__builtin_amdgcn_readfirstlane(dn.x);
@@ -678,30 +690,34 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     };
     auto walk = [&](const Rows& S, u64 init, int sweep, uint32_t& pc, auto&& fast, auto&& comp) {
         u64 ph = init, pd = init;   // state of the block computed last
-        uint32_t fl0, fl1 = 0;
+        uint32_t fl0, fl1 = 0;      // flags of steps g and g + 1
         int a0, b0, a1 = IDENT_OFF, b1 = IDENT_OFF;
+        int4 dq2 = make_int4(0, IDENT_OFF, IDENT_OFF, 0);   // descriptor of step g + 2, not decoded
+        // two sets of step inputs, used in turn (the loop below runs two steps per round)
+        u64 xa[NX], nha[2], nda[2], xb[NX], nhb[2], ndb[2];
         need(&ctl->in_ready, inr, gbase);
         desc(gbase, fl0, a0, b0);
-        u64 x[NX], nh[2], nd[2];
-        fetch(gbase, a0, b0, x, nh, nd);
+        fetch(gbase, a0, b0, xa, nha, nda);
         if (nb > 1) {
             need(&ctl->in_ready, inr, gbase + 1);
             desc(gbase + 1, fl1, a1, b1);
         }
-        for (int i = 0; i < nb; ++i) {
+        if (nb > 2) {
+            need(&ctl->in_ready, inr, gbase + 2);
+            dq2 = dring[(gbase + 2) & (IR - 1)];
+        }
+        // step gbase + i with its inputs in (x, nh, nd); the next step's go to (y, ny, nz)
+        auto step = [&](int i, const u64* x, const u64* nh, const u64* nd, u64* y, u64* ny, u64* nz) {
             const int g = gbase + i;
             const uint32_t fl = fl0;
-            // the next step's reads
-            u64 x1[NX], nh1[2], nd1[2];
-            uint32_t fl2 = 0;
-            int a2 = IDENT_OFF, b2 = IDENT_OFF;
-            if (i + 1 < nb) {
-                fetch(g + 1, a1, b1, x1, nh1, nd1);
-                if (i + 2 < nb) {
-                    need(&ctl->in_ready, inr, g + 2);
-                    desc(g + 2, fl2, a2, b2);
-                }
+            // the ring slot of step g was last used by step g - RS: the helper must have read it
+            need(&ctl->consumed, cons, g - RS);
+            int4 dq3 = make_int4(0, IDENT_OFF, IDENT_OFF, 0);
+            if (i + 3 < nb) {
+                need(&ctl->in_ready, inr, g + 3);
+                dq3 = dring[(g + 3) & (IR - 1)];
             }
+            if (i + 1 < nb) fetch(g + 1, a1, b1, y, ny, nz);
             u64 vh_[2], vd_[2];
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
@@ -729,17 +745,22 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 comp(b, r, x, vh_, vd_, ph, pd, sweep, g, vh, vd);
             }
             pc += popc2(vh, vd);
-            // the ring slot of step g was last used by step g - RS: the helper must have read it
-            need(&ctl->consumed, cons, g - RS);
             w_put(ring_at(g), vh);
             w_put(ring_at(g) + WORD_BYTES, vd);
-            lds_release();
+            // the state goes before the counter (program order; LDS keeps it)
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
             lds_put(&ctl->produced, g + 1);
             ph = vh; pd = vd;
-            fl0 = fl1; fl1 = fl2; a1 = a2; b1 = b2;
-#pragma unroll
-            for (int k = 0; k < NX; ++k) x[k] = x1[k];
-            nh[0] = nh1[0]; nh[1] = nh1[1]; nd[0] = nd1[0]; nd[1] = nd1[1];
+            fl0 = fl1;
+            fl1 = (uint32_t)__builtin_amdgcn_readfirstlane(dq2.x);
+            a1 = __builtin_amdgcn_readfirstlane(dq2.y);
+            b1 = __builtin_amdgcn_readfirstlane(dq2.z);
+            dq2 = dq3;
+        };
+        for (int i = 0; i < nb; i += 2) {
+            step(i, xa, nha, nda, xb, nhb, ndb);
+            if (i + 1 >= nb) break;
+            step(i + 1, xb, nhb, ndb, xa, nha, nda);
         }
     };
     // a neighbour beyond the first two, at compute time (g = the current step)
@@ -1283,8 +1304,8 @@ __device__ __forceinline__ void tile_phase(const DevCfg& c, const Tile& tl, u64*
         ctl->in_ready = 0;
     }
     __syncthreads();
-    // lanes past LANES hold no word and stay out
-    if (!__builtin_amdgcn_readfirstlane(ctl->skip) && (threadIdx.x & 63) < LANES)
+    // lanes past LANES hold no word and stay out (the helper's next LANES copy high halves)
+    if (!__builtin_amdgcn_readfirstlane(ctl->skip) && (threadIdx.x & 63) < (threadIdx.x >= 64 ? 2 * LANES : LANES))
         solve_phase<PH>(c, tl.s0, tl.nw, tl.fslot, lds, ring_slots);
     __syncthreads();
 }
@@ -1295,6 +1316,9 @@ __device__ __forceinline__ void phase_kernel(const DevCfg* __restrict__ cfgs, co
 {
     extern __shared__ __align__(16) u64 lds[];
     Ctl* ctl = reinterpret_cast<Ctl*>(lds);
+    // tiles come longest first; those of the longest CFGs bound the launch, so their wavefronts
+    // take the SIMD's issue slots first
+    const int nb_max = n_tiles > 0 ? cfgs[tiles[0].cfg].nb : 0;
     for (;;) {
         if (threadIdx.x == 0) ctl->tile = atomicAdd(&counter[PH], 1);
         __syncthreads();
@@ -1303,6 +1327,8 @@ __device__ __forceinline__ void phase_kernel(const DevCfg* __restrict__ cfgs, co
         if (t >= n_tiles) break;
         const Tile tl = tiles[t];
         const DevCfg c = cfgs[tl.cfg];
+        if (2 * c.nb >= nb_max) __builtin_amdgcn_s_setprio(3);
+        else __builtin_amdgcn_s_setprio(0);
         tile_phase<PH>(c, tl, lds, ring_slots);
     }
 }
