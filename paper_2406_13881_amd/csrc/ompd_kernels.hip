@@ -502,8 +502,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // the first other one ("far": not yet visited in this sweep, or more than RS steps back)
     // comes with the step's inputs.
     // ---------------------------------------------------------------- helper wavefront
-    // Each round: plans the steps up to IR ahead of the compute wavefront (step entries through
-    // the scalar cache; each step's descriptor and, when it is not in the rows, its far
+    // Each round: plans the steps up to IR ahead of the compute wavefront (one step per lane;
+    // each step's descriptor and, when it is not in the rows, its far
     // neighbour's state go to LDS); stores the results the compute wavefront has put in the ring
     // since the last round; copies the other inputs from global memory straight into LDS; waits
     // for all of it; then publishes the inputs and how far the ring may be reused and the rows
@@ -512,16 +512,6 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // when it is not yet visited): from the rows when u was stored in an earlier round, from the
     // ring when it is computed but not stored yet (its slot is not released before this round
     // ends), the initial value in the first sweep.  Steps whose u is not computed yet wait.
-    const CAS int32_t* STEP = K(BWD ? c.step_b : c.step_f);
-    // words 0-3 / 4-7 of the step entry at walk position i (scalar loads)
-    auto step_lo = [&](int i) -> int4 {
-        const CAS int32_t* q = STEP + 8 * (size_t)i;
-        return make_int4(q[0], q[1], q[2], q[3]);
-    };
-    auto step_hi = [&](int i) -> int4 {
-        const CAS int32_t* q = STEP + 8 * (size_t)i + 4;
-        return make_int4(q[0], q[1], q[2], q[3]);
-    };
     // step u of the far neighbour's state for step st with entry word x / w (-1: the initial value)
     auto far_step = [&](uint32_t x, int w, int st) -> int {
         return ((x & SF_BACK) && st < nb) ? -1 : st - w;
@@ -530,44 +520,48 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         int gf = 0, fi = 0;   // next step to store and its index within the sweep
         int pf = 0, pi = 0;   // next step whose inputs are loaded and its index within the sweep
         int spins = 0;
+        // Lane j plans step pf + j (walk position pi + j): its step entry is loaded by the lane
+        // after the previous round, so that the load is in flight while the helper waits.
+        typedef int v4i __attribute__((ext_vector_type(4)));
+        const GAS v4i* STV = reinterpret_cast<const GAS v4i*>(G(BWD ? c.step_b : c.step_f));
+        v4i ev, xv;   // words 0-3 and 4-7 of the lane's entry
+        auto load_entries = [&]() {
+            int l = pi + lane;
+            while (l >= nb) l -= nb;
+            ev = STV[2 * l];
+            xv = STV[2 * l + 1];
+        };
+        load_entries();
         for (;;) {
             const int prod = __builtin_amdgcn_readfirstlane(lds_get(&ctl->produced));
             lds_acquire();
             const int fend = prod < gf + 32 ? prod : gf + 32;
             const int pend = prod < pf ? prod + IR : pf + IR;   // input slots free
             const int gf0 = gf;
-            // plan: descriptors, and far values that do not come from the rows (LDS writes only)
-            int n = 0;
-            bool stop = false;
-            for (int s4 = pf, l4 = pi; s4 < pend && !stop; s4 += 4) {
-                int4 t4[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {   // four entries in flight
-                    int lq = l4 + q;
-                    while (lq >= nb) lq -= nb;
-                    if (s4 + q < pend) t4[q] = step_lo(lq);
-                }
-                l4 += 4;
-                while (l4 >= nb) l4 -= nb;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int st = s4 + q;
-                    if (stop || st >= pend) break;
-                    const uint32_t fl = (uint32_t)t4[q].x;
-                    const int u = far_step(fl, t4[q].w, st);
-                    if ((fl & SF_FAR) && u >= prod) { stop = true; break; }   // not computed yet
-                    const int far_at = IN_OFF + ((st & (IR - 1)) * NI + NX) * WORD_BYTES;
-                    const uint32_t k0 = fl & 3u, k1 = (fl >> 2) & 3u;
-                    const int loc0 = k0 == 2 ? ring_at(st - (t4[q].y & 0xFF)) : k0 == 3 ? far_at : IDENT_OFF;
-                    const int loc1 = k1 == 2 ? ring_at(st - ((t4[q].y >> 8) & 0xFF)) : k1 == 3 ? far_at : IDENT_OFF;
-                    if ((fl & SF_FAR) && (u < 0 || u >= gf0) && !hi) {
-                        const u64 h = u < 0 ? init : slot_h(u), d = u < 0 ? init : slot_d(u);
-                        uint32_t* qq = in32(st, NX) + ln;
-                        qq[0] = (uint32_t)h; qq[LANES] = (uint32_t)(h >> 32);
-                        qq[2 * LANES] = (uint32_t)d; qq[3 * LANES] = (uint32_t)(d >> 32);
-                    }
-                    if (lane == 0) dring[st & (IR - 1)] = make_int4((int)(fl & DF_MASK), loc0, loc1, 0);
-                    ++n;
+            // plan, one step per lane: descriptors, and far values that do not come from the rows
+            // (LDS writes only); steps stop at the first one whose far state is not computed yet
+            const int st = pf + lane;
+            const uint32_t fl = (uint32_t)ev.x;
+            const int u = far_step(fl, ev.w, st);
+            const bool cand = st < pend;
+            const u64 stopm = __ballot(cand && (fl & SF_FAR) && u >= prod);
+            const int n = stopm ? (int)__builtin_ctzll(stopm) : pend - pf;
+            if (lane < n) {
+                const int far_at = IN_OFF + ((st & (IR - 1)) * NI + NX) * WORD_BYTES;
+                const uint32_t k0 = fl & 3u, k1 = (fl >> 2) & 3u;
+                const int loc0 = k0 == 2 ? ring_at(st - (ev.y & 0xFF)) : k0 == 3 ? far_at : IDENT_OFF;
+                const int loc1 = k1 == 2 ? ring_at(st - ((ev.y >> 8) & 0xFF)) : k1 == 3 ? far_at : IDENT_OFF;
+                dring[st & (IR - 1)] = make_int4((int)(fl & DF_MASK), loc0, loc1, 0);
+            }
+            // far states from the ring (computed, not stored yet) or the initial value
+            for (u64 cm = __ballot(lane < n && (fl & SF_FAR) && (u < 0 || u >= gf0)); cm; cm &= cm - 1) {
+                const int j = (int)__builtin_ctzll(cm);
+                const int uj = __builtin_amdgcn_readlane(u, j);
+                if (!hi) {
+                    const u64 h = uj < 0 ? init : slot_h(uj), d = uj < 0 ? init : slot_d(uj);
+                    uint32_t* qq = in32(pf + j, NX) + ln;
+                    qq[0] = (uint32_t)h; qq[LANES] = (uint32_t)(h >> 32);
+                    qq[2 * LANES] = (uint32_t)d; qq[3 * LANES] = (uint32_t)(d >> 32);
                 }
             }
             // nothing to store and nothing that can be loaded yet (the prefetch may also be waiting
@@ -602,32 +596,19 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             }
             // the other inputs: copies from global memory straight into the input slots (no LDS read
             // follows them before the wait); far rows past the first-level cache (the helper stored them)
-            for (int t4 = 0, l4 = pi; t4 < n; t4 += 4) {
-                int4 s4[4], e4[4];
+            for (int j = 0; j < n; ++j) {
+                const int sj = pf + j;
+                const GAS u64* a[NX];
+                pre(__builtin_amdgcn_readlane(xv.x, j), (uint32_t)__builtin_amdgcn_readlane(xv.y, j),
+                    (uint32_t)__builtin_amdgcn_readlane(xv.z, j), a);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {   // four entries in flight
-                    int lq = l4 + q;
-                    while (lq >= nb) lq -= nb;
-                    if (t4 + q < n) { s4[q] = step_lo(lq); e4[q] = step_hi(lq); }
-                }
-                l4 += 4;
-                while (l4 >= nb) l4 -= nb;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (t4 + q < n) {
-                        const int st = pf + t4 + q;
-                        const GAS u64* a[NX];
-                        pre(e4[q].x, (uint32_t)e4[q].y, (uint32_t)e4[q].z, a);
-#pragma unroll
-                        for (int k = 0; k < NX; ++k) dma_word<0>(a[k], hi, in32(st, k));
-                        const uint32_t fl = (uint32_t)s4[q].x;
-                        const int u = far_step(fl, s4[q].w, st);
-                        if ((fl & SF_FAR) && u >= 0 && u < gf0) {
-                            const int p = s4[q].z;
-                            dma_word<CPOL_SC1>(S.h + (size_t)p * S.str, hi, in32(st, NX));
-                            dma_word<CPOL_SC1>(S.d + (size_t)p * S.str, hi, in32(st, NX + 1));
-                        }
-                    }
+                for (int k = 0; k < NX; ++k) dma_word<0>(a[k], hi, in32(sj, k));
+                const uint32_t flj = (uint32_t)__builtin_amdgcn_readlane((int)fl, j);
+                const int uj = __builtin_amdgcn_readlane(u, j);
+                if ((flj & SF_FAR) && uj >= 0 && uj < gf0) {
+                    const int p = __builtin_amdgcn_readlane(ev.z, j);
+                    dma_word<CPOL_SC1>(S.h + (size_t)p * S.str, hi, in32(sj, NX));
+                    dma_word<CPOL_SC1>(S.d + (size_t)p * S.str, hi, in32(sj, NX + 1));
                 }
             }
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -638,6 +619,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             pi += n;
             while (pi >= nb) pi -= nb;
             lds_put(&ctl->in_ready, pf);
+            if (n) load_entries();
         }
     };
 
