@@ -164,7 +164,7 @@ def kernel_bytes(cfgs):
         wd = (c.n_vars + 63) // 64
         nb, ne = c.n_blocks, c.n_edges
         bv, ev = nb * wd * 8, ne * wd * 8
-        out["ompd_k_prep"] += 4 * (nb + 1) + 5 * ne + nb + 4 * (nb + 1) + 8 * ne + 64 * nb
+        out["ompd_k_prep"] += 4 * (nb + 1) + 5 * ne + nb + 4 * (nb + 1) + 8 * ne + 128 * nb   # + records, step entries
         out["ompd_k_nu"] += 2 * bv + 2 * bv                    # R, W in; next use H/D out
         out["ompd_k_ave"] += 3 * bv + 2 * bv + 2 * nb          # NU H/D, W in; validity after each block H/D, labels out
         out["ompd_k_post_ave"] += 4 * bv + 2 * bv + 4 * ev     # NU, validity after in; validity before, EAG, valid-after-edge out
