@@ -70,6 +70,11 @@ enum { OMPD_MAP_TO = 1, OMPD_MAP_FROM = 2, OMPD_MAP_ALLOC = 4 };          /* var
 #define OMPD_F_TILE_KERNEL (1u << 3)      /* one persistent kernel runs every phase of a tile
                                              (same results) instead of one kernel per phase */
 #define OMPD_F_SWEEP_CAP(n) ((((uint32_t)(n)) & 0xFFFFu) << 16) /* cap sweeps per phase */
+/* Ring of recently solved blocks per solve workgroup, for the one-shot entry
+ * points (what ompd_plan_configure sets for a plan): n = 8, 16, 32 or 64
+ * blocks (other values round down to one of these; 0 = default, 64).  Results
+ * do not depend on it. */
+#define OMPD_F_RING_SLOTS(n) ((uint32_t)((n) >= 64 ? 4 : (n) >= 32 ? 3 : (n) >= 16 ? 2 : (n) >= 8 ? 1 : 0) << 8)
 
 /* ---- one procedure ----------------------------------------------------
  * A CFG of basic blocks (the CFG half of the paper's AST-CFG, Figure 2).

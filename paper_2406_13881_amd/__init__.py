@@ -41,6 +41,12 @@ F_PLACEMENT_EAGER = 1 << 1
 F_TILE_KERNEL = 1 << 3
 
 
+def F_RING_SLOTS(n: int) -> int:
+    """Ring of recently solved blocks per solve workgroup (8, 16, 32 or 64;
+    0 = default) for the one-shot entry points."""
+    return (4 if n >= 64 else 3 if n >= 32 else 2 if n >= 16 else 1 if n >= 8 else 0) << 8
+
+
 def F_SWEEP_CAP(n: int) -> int:
     return (int(n) & 0xFFFF) << 16
 

@@ -355,6 +355,14 @@ __device__ __forceinline__ void dma_word(const GAS u64* src, bool hi, uint32_t* 
     const GAS uint32_t* s32 = reinterpret_cast<const GAS uint32_t*>(src) + (hi ? 1 : 0);
     __builtin_amdgcn_global_load_lds(s32, (__attribute__((address_space(3))) void*)dst, 4, 0, CPOL);
 }
+// The same from a row whose start `row` is wave-uniform, the lane's half at byte `off` of it
+// (scalar base plus a 32-bit lane offset: no per-lane address arithmetic).
+template <unsigned CPOL>
+__device__ __forceinline__ void dma_row(const GAS u64* row, uint32_t off, uint32_t* dst)
+{
+    const GAS uint32_t* s32 = reinterpret_cast<const GAS uint32_t*>(reinterpret_cast<const GAS char*>(row) + off);
+    __builtin_amdgcn_global_load_lds(s32, (__attribute__((address_space(3))) void*)dst, 4, 0, CPOL);
+}
 
 // Coordination of the two wavefronts of a tile (LDS).
 struct Ctl {
@@ -451,7 +459,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // data arrays of a CFG without variables may be empty: loads then read a flag word instead
     auto arr = [&](const u64* a) -> const GAS u64* { return wd ? G(a) : (const GAS u64*)FLG; };
     auto row = [&](const u64* a, int b) -> u64 { return arr(a)[(size_t)b * wd + wo]; };
-    auto rowp = [&](const u64* a, int b) -> const GAS u64* { return arr(a) + (size_t)b * wd + wo; };
+    // start of row b (wave-uniform) and the byte of the lane's half-word within a row
+    auto rowu = [&](const u64* a, int b) -> const GAS u64* { return arr(a) + (size_t)b * wd; };
+    const uint32_t hoff = (uint32_t)wo * 8u + (hi ? 4u : 0u);
     // (both only at compute time, on rare paths: ENTRY, EXIT, call blocks)
     auto vec = [&](const u64* a) -> u64 { return settle(arr(a)[wo]); };
     auto sum = [&](int ci, int r) -> u64 { return settle(arr(c.sums)[((size_t)ci * SUM_ROWS + r) * wd + wo]); };
@@ -602,7 +612,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 pre(__builtin_amdgcn_readlane(xv.x, j), (uint32_t)__builtin_amdgcn_readlane(xv.y, j),
                     (uint32_t)__builtin_amdgcn_readlane(xv.z, j), a);
 #pragma unroll
-                for (int k = 0; k < NX; ++k) dma_word<0>(a[k], hi, in32(sj, k));
+                for (int k = 0; k < NX; ++k) dma_row<0>(a[k], hoff, in32(sj, k));
                 const uint32_t flj = (uint32_t)__builtin_amdgcn_readlane((int)fl, j);
                 const int uj = __builtin_amdgcn_readlane(u, j);
                 if ((flj & SF_FAR) && uj >= 0 && uj < gf0) {
@@ -825,8 +835,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         const Rows S = rows_of(c.nu_h, c.nu_d, 0);
         // x0 = R, x1 = W (flag lane: R = 2, W = 2 at DEVICE blocks, substituted when computed)
         auto pre = [&](int b, uint32_t, uint32_t, const GAS u64** x) {
-            x[0] = rowp(c.R, b);
-            x[1] = rowp(c.W, b);
+            x[0] = rowu(c.R, b);
+            x[1] = rowu(c.W, b);
         };
         auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd, int sweep,
                         int g, u64& vh, u64& vd) {
@@ -873,9 +883,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         const u64 init = ~0ull & vm;
         // x0/x1 = NU (flag lane: 0), x2 = W (flag lane: 2 at DEVICE blocks), substituted when computed
         auto pre = [&](int b, uint32_t, uint32_t, const GAS u64** x) {
-            x[0] = rowp(c.nu_h, b);
-            x[1] = rowp(c.nu_d, b);
-            x[2] = rowp(c.W, b);
+            x[0] = rowu(c.nu_h, b);
+            x[1] = rowu(c.nu_d, b);
+            x[2] = rowu(c.W, b);
         };
         auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd, int sweep,
                         int g, u64& vh, u64& vd) {
@@ -943,7 +953,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         sd = ud | (dev ? ww : 0ull);
     };
     auto erow = [&](const u64* a, uint32_t e) -> u64 { return G(a)[(size_t)(e & 0x7FFFFFFFu) * wd + wo]; };
-    auto erowp = [&](const u64* a, uint32_t e) -> const GAS u64* { return G(a) + (size_t)(e & 0x7FFFFFFFu) * wd + wo; };
+    auto erowu = [&](const u64* a, uint32_t e) -> const GAS u64* { return G(a) + (size_t)(e & 0x7FFFFFFFu) * wd; };
 
     // -------------------------------------------------------- pending copies (forward, may)
     // MAYP_s(e) = (EAG_s(e) | MAYPout_s(p)) & ~LE(e), EAG_s(e=p->q) = NU_s(q) & ~AVEout_s(p);
@@ -954,9 +964,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         // x0 = R, x1 = W, x2..x5 = EAG_H/D of the two inline in-edges
         // (edge 0 stands in for a missing neighbour's edge)
         auto pre = [&](int b, uint32_t e0, uint32_t e1, const GAS u64** x) {
-            x[0] = rowp(c.R, b); x[1] = rowp(c.W, b);
-            x[2] = erowp(c.eag_h, e0); x[3] = erowp(c.eag_d, e0);
-            x[4] = erowp(c.eag_h, e1); x[5] = erowp(c.eag_d, e1);
+            x[0] = rowu(c.R, b); x[1] = rowu(c.W, b);
+            x[2] = erowu(c.eag_h, e0); x[3] = erowu(c.eag_d, e0);
+            x[4] = erowu(c.eag_h, e1); x[5] = erowu(c.eag_d, e1);
         };
         auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd, int sweep,
                         int g, u64& vh, u64& vd) {
@@ -1007,9 +1017,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         const Rows S = rows_of(c.later_h, c.later_d, 0);
         // x0 = R, x1 = W, x2..x4 / x5..x7 = EAG_H, EAG_D, BOTH of the two inline in-edges
         auto pre = [&](int b, uint32_t e0, uint32_t e1, const GAS u64** x) {
-            x[0] = rowp(c.R, b); x[1] = rowp(c.W, b);
-            x[2] = erowp(c.eag_h, e0); x[3] = erowp(c.eag_d, e0); x[4] = erowp(c.both, e0);
-            x[5] = erowp(c.eag_h, e1); x[6] = erowp(c.eag_d, e1); x[7] = erowp(c.both, e1);
+            x[0] = rowu(c.R, b); x[1] = rowu(c.W, b);
+            x[2] = erowu(c.eag_h, e0); x[3] = erowu(c.eag_d, e0); x[4] = erowu(c.both, e0);
+            x[5] = erowu(c.eag_h, e1); x[6] = erowu(c.eag_d, e1); x[7] = erowu(c.both, e1);
         };
         auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd, int sweep,
                         int g, u64& vh, u64& vd) {
@@ -1066,9 +1076,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         const u64 init = ~0ull & vm;
         // x0/x1 = INS_ENTRY, x2 = W, x3..x6 = INS_EDGE_H/D of the two inline in-edges
         auto pre = [&](int b, uint32_t e0, uint32_t e1, const GAS u64** x) {
-            x[0] = rowp(c.ie_h, b); x[1] = rowp(c.ie_d, b); x[2] = rowp(c.W, b);
-            x[3] = erowp(c.ig_h, e0); x[4] = erowp(c.ig_d, e0);
-            x[5] = erowp(c.ig_h, e1); x[6] = erowp(c.ig_d, e1);
+            x[0] = rowu(c.ie_h, b); x[1] = rowu(c.ie_d, b); x[2] = rowu(c.W, b);
+            x[3] = erowu(c.ig_h, e0); x[4] = erowu(c.ig_d, e0);
+            x[5] = erowu(c.ig_h, e1); x[6] = erowu(c.ig_d, e1);
         };
         auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd, int sweep,
                         int g, u64& vh, u64& vd) {

@@ -313,6 +313,7 @@ int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32
     p->flags = flags;
     p->cfg = pc;
     if (flags & OMPD_F_TILE_KERNEL) p->cfg.split = false;
+    if (const uint32_t r = (flags >> 8) & 7u) p->cfg.lds_bytes = (size_t)(4u << r) * STATE_BYTES;   // 8 .. 64 slots
     p->res.assign(res, res + n);
     p->h_cfgs.resize(n);
 

@@ -179,3 +179,26 @@ def test_tile_kernel_matches_oracle(ctx):
         got = ctx.analyze_batch(cfgs, flags=flags)
         for i, cfg in enumerate(cfgs):
             assert_same(cfg, got[i], refs[i], "flags=%d #%d" % (flags, i))
+
+
+def test_ring_sizes_match_oracle(ctx):
+    """Results do not depend on the ring of recently solved blocks: with 8 to
+    64 ring slots (so that neighbours 9 to 64 steps back move between the
+    ring and the far input, and the input lookahead exceeds the ring) every
+    output equals the oracle, tiny CFGs (two and four blocks, a self-loop)
+    included."""
+    import paper_2406_13881_amd as ompd
+    cfgs = [synth.c1(i) for i in range(10)]
+    cfgs += [synth.make_cfg(6_300 + j, n_user=150 + 120 * j, n_vars=20 + 700 * j, max_loop_depth=4,
+                            device_frac=0.4, irr_loop_frac=0.1) for j in range(4)]
+    cfgs += [synth.random_dag(91 + j, 40, 120, p_loop_entry=0.3) for j in range(4)]
+    tiny, _ = synth.from_edges([(0, [], []), (0, [], [])], [(0, 1, 0)], 3)
+    loop, _ = synth.from_edges([(0, [], []), (1, [0, 65], [0]), (0, [0, 1], [65]), (0, [], [])],
+                               [(0, 1, 2), (1, 1, 1), (1, 2, 0), (2, 3, 0)], 70)
+    cfgs += [tiny, loop]
+    refs = [oracle.solve(c) for c in cfgs]
+    for rs in (8, 16, 32, 64):
+        _print("ring slots %d: %d CFGs" % (rs, len(cfgs)))
+        got = ctx.analyze_batch(cfgs, flags=ompd.F_RING_SLOTS(rs))
+        for i, cfg in enumerate(cfgs):
+            assert_same(cfg, got[i], refs[i], "ring %d #%d" % (rs, i))
