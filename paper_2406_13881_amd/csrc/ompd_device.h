@@ -84,10 +84,14 @@ struct Tile {
     int32_t fslot;   // index of the tile within its CFG (flag-lane storage)
 };
 
-// Work item of the pass kernels: a tile and the first block of a 64-block
-// chunk of it.
+// Work item of the pass kernels: a CFG, a run of up to PASS_WORDS of its
+// words (one per lane of a wavefront, independent of the solve tiles) and the
+// first block of a 64-block chunk.
+constexpr int PASS_WORDS = 64;
 struct EdgeItem {
-    int32_t tile;
+    int32_t cfg;
+    int32_t s0;
+    int32_t nw;
     int32_t b0;
 };
 

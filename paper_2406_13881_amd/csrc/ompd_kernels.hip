@@ -1350,11 +1350,11 @@ __device__ __forceinline__ void pass_kernel(const DevCfg* __restrict__ cfgs, con
         it = __builtin_amdgcn_readfirstlane(__shfl(it, 0, 64));
         if (it >= n_items) break;
         const EdgeItem item = items[it];
-        const Tile tl = tiles[item.tile];
-        const DevCfg c = cfgs[tl.cfg];
-        if (G(c.info)[INFO_STATUS] != 0 || tl.nw == 0) continue;
+        const DevCfg c = cfgs[item.cfg];
+        if (G(c.info)[INFO_STATUS] != 0 || item.nw == 0) continue;
         if ((PASS == PASS_MAYP) && (c.placement & 1)) continue;   // the eager placement needs no pending copies
-        edge_pass<PASS>(c, tl.s0, tl.nw, tl.fslot, item.b0);
+        // every solve tile's flag lane computes the same reachability facts: tile 0's columns
+        edge_pass<PASS>(c, item.s0, item.nw, 0, item.b0);
     }
 }
 #define OMPD_PASS_KERNEL(name, pass)                                                                         \

@@ -262,9 +262,22 @@ int ompd_make_shape(ompd_ctx* ctx, const std::vector<DevCfg>& cfgs, const PlanCo
     // a tile's work ~ its blocks times the sweeps, which grow with the CFG: longest first
     std::stable_sort(tiles.begin(), tiles.end(),
                      [&](const Tile& a, const Tile& b) { return cfgs[a.cfg].nb > cfgs[b.cfg].nb; });
-    for (int t = 0; t < (int)tiles.size(); ++t)
-        if (tiles[t].nw > 0)
-            for (int b0 = 0; b0 < cfgs[tiles[t].cfg].nb; b0 += 64) sh.items.push_back(EdgeItem{t, b0});
+    // pass items: runs of up to PASS_WORDS words (the passes need no LDS, so a full wavefront of
+    // words each), 64-block chunks, longest CFGs first
+    {
+        std::vector<int> order(cfgs.size());
+        for (int i = 0; i < (int)order.size(); ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cfgs[a].nb > cfgs[b].nb; });
+        for (int i : order) {
+            const int wd = cfgs[i].wd;
+            if (wd <= 0) continue;
+            const int runs = (wd + PASS_WORDS - 1) / PASS_WORDS;
+            for (int r = 0; r < runs; ++r) {
+                const int s0 = (int)((int64_t)wd * r / runs), s1 = (int)((int64_t)wd * (r + 1) / runs);
+                for (int b0 = 0; b0 < cfgs[i].nb; b0 += 64) sh.items.push_back(EdgeItem{i, s0, s1 - s0, b0});
+            }
+        }
+    }
     // result ring: a power of two of STATE_BYTES slots in [8, 64], as large as every phase's LDS allows
     const size_t want = pc.lds_bytes ? pc.lds_bytes : RING_BYTES_DEFAULT;
     int rs = 8;
