@@ -100,9 +100,9 @@ struct EdgeItem {
 inline int tiles_of(int wd) { return wd <= 0 ? 1 : (wd + TILE_WORDS - 1) / TILE_WORDS; }
 
 // LDS of a phase workgroup: CTL_BYTES of coordination words, the ring of
-// the last RS results (1 KiB each), the inputs of the next in_ring(ph)
-// steps (phase_inputs(ph) words of 512 bytes each), their 16-byte
-// descriptors, then one state of identity words (1 KiB).
+// the last RS results (STATE_BYTES each), the inputs of the next in_ring(ph)
+// steps (phase_inputs(ph) words of WORD_BYTES each), their 16-byte
+// descriptors, then one state of identity words (STATE_BYTES).
 constexpr int CTL_BYTES = 256;
 constexpr int LDS_FIXED = CTL_BYTES;
 // steps of inputs kept ready per phase (a power of two; more for the phases with fewer inputs).
