@@ -220,6 +220,7 @@ def main():
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-program", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory (a device-to-device copy of known size, "
                          "to calibrate the HBM byte counters of a profiler) and exit")
@@ -374,6 +375,28 @@ def main():
                          "plan": json.loads(sb.plan.describe())}
         log("single c2: %.3f ms, %.3e facts/s" % (np.median(lat), out["single"]["value"]))
         sb.close()
+
+    if not args.no_program:
+        # whole-program analysis: summaries bottom-up, then every (procedure, call string <= 2)
+        # context solved; synchronous, host arrays in and out, so the time includes the copies
+        prog = synth.c4()
+        t0 = time.perf_counter()
+        got = ctx.analyze_program(prog)
+        first = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        got = ctx.analyze_program(prog)
+        dt = time.perf_counter() - t0
+        pf = sum(prog.procs[p].n_blocks * prog.procs[p].n_vars for (p, _) in got["contexts"])
+        out["program"] = {"workload": "%d procedures (%d-%d blocks, %d globals + %d locals), %d call sites, "
+                                      "contexts = call strings of length <= 2" % (
+                                          len(prog.procs), synth.C4["blocks"][0], synth.C4["blocks"][1],
+                                          prog.n_globals, synth.C4["n_locals"], len(prog.call_proc)),
+                          "ms": 1e3 * dt, "first_ms": 1e3 * first, "contexts": len(got["contexts"]),
+                          "solves": int(got["solves"]), "rounds": int(got["rounds"]), "facts": int(pf),
+                          "value": pf / dt, "unit": "facts/s (host arrays in and out)"}
+        log("program c4: %.1f ms (first %.1f ms), %d contexts, %d solves, %d rounds, %.3e facts/s" % (
+            1e3 * dt, 1e3 * first, len(got["contexts"]), got["solves"], got["rounds"], pf / dt))
+        del got
 
     if not args.no_serve:
         sctx = ompd.Context(0, budget_bytes=64 << 30)
