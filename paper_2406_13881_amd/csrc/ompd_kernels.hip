@@ -356,12 +356,14 @@ __device__ __forceinline__ void dma_word(const GAS u64* src, bool hi, uint32_t* 
     __builtin_amdgcn_global_load_lds(s32, (__attribute__((address_space(3))) void*)dst, 4, 0, CPOL);
 }
 // The same from a row whose start `row` is wave-uniform, the lane's half at byte `off` of it
-// (scalar base plus a 32-bit lane offset: no per-lane address arithmetic).
+// (scalar base plus a 32-bit lane offset: no per-lane address arithmetic), to the LDS address
+// `dst` (wave-uniform, kept in scalar registers).
+#define LDS3 __attribute__((address_space(3)))
 template <unsigned CPOL>
-__device__ __forceinline__ void dma_row(const GAS u64* row, uint32_t off, uint32_t* dst)
+__device__ __forceinline__ void dma_row(const GAS u64* row, uint32_t off, LDS3 char* dst)
 {
     const GAS uint32_t* s32 = reinterpret_cast<const GAS uint32_t*>(reinterpret_cast<const GAS char*>(row) + off);
-    __builtin_amdgcn_global_load_lds(s32, (__attribute__((address_space(3))) void*)dst, 4, 0, CPOL);
+    __builtin_amdgcn_global_load_lds(s32, (LDS3 void*)dst, 4, 0, CPOL);
 }
 
 // Coordination of the two wavefronts of a tile (LDS).
@@ -440,6 +442,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // Every 64-bit per-lane word in LDS is stored split: LANES low halves, then LANES high
     // halves (WORD_BYTES); a state (h, d) is two such words (STATE_BYTES).
     char* lds8 = reinterpret_cast<char*>(lds);
+    // the same as a wave-uniform 32-bit LDS address (scalar registers)
+    const uint32_t lds3 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(size_t)(LDS3 char*)lds8);
     constexpr int RING_OFF = CTL_BYTES;                                   // RS states: the last results
     const int IN_OFF = RING_OFF + RS * STATE_BYTES;                       // IR steps of NI input words
     const int DESC_OFF = IN_OFF + IR * NI * WORD_BYTES;                   // IR step descriptors
@@ -611,8 +615,10 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 const GAS u64* a[NX];
                 pre(__builtin_amdgcn_readlane(xv.x, j), (uint32_t)__builtin_amdgcn_readlane(xv.y, j),
                     (uint32_t)__builtin_amdgcn_readlane(xv.z, j), a);
+                const uint32_t slot = (uint32_t)__builtin_amdgcn_readfirstlane(
+                    (int)(lds3 + IN_OFF + (uint32_t)((sj & (IR - 1)) * NI) * WORD_BYTES));
 #pragma unroll
-                for (int k = 0; k < NX; ++k) dma_row<0>(a[k], hoff, in32(sj, k));
+                for (int k = 0; k < NX; ++k) dma_row<0>(a[k], hoff, (LDS3 char*)(size_t)(slot + k * WORD_BYTES));
                 const uint32_t flj = (uint32_t)__builtin_amdgcn_readlane((int)fl, j);
                 const int uj = __builtin_amdgcn_readlane(u, j);
                 if ((flj & SF_FAR) && uj >= 0 && uj < gf0) {
