@@ -277,18 +277,20 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
 //   eager validity, host channel, bit 0: the block is NOT reached from ENTRY
 //   eager validity, host channel, bit 1: no DEVICE block reaches the block
 // Lanes past the tile (below LANES) shadow word s0 (same inputs, same
-// results), so the walk has no lane divergence and its block records stay
-// scalar loads.  Narrow tiles keep the LDS of a workgroup small (about 20 KiB),
-// so that many tiles are resident per CU: most CFGs have few words, and a
-// step costs the same instructions whatever the tile's width.
+// results), so the walk has no lane divergence and everything about a step
+// except its data is wave-uniform.  Narrow tiles keep the LDS of a workgroup
+// small (25-40 KiB with the default ring), so that several tiles are resident
+// per CU: most CFGs have few words, and a step costs the same instructions
+// whatever the tile's width.
 //
 // A phase is a sequence of Gauss-Seidel sweeps in block-id order (reverse
 // order for the backward phase).  The compute wavefront walks the blocks and
 // touches global memory only on rare paths: the value of the block just
 // computed stays in registers, the last RS steps sit in an LDS ring, and the
-// helper wavefront keeps the block records and, IR steps ahead, each step's
-// inputs (including the state of its first other neighbour) ready in LDS;
-// the helper also copies the compute wavefront's results to the state rows.
+// helper wavefront keeps, up to IR steps ahead, each step's descriptor and
+// inputs (including the state of its first other neighbour) ready in LDS,
+// planned from the step entries the ingest kernel wrote; the helper also
+// copies the compute wavefront's results to the state rows.
 // The two meet through counters in LDS.
 // Every phase is monotone on a finite lattice, so any visiting order reaches
 // the same fixed point, and each block's value only moves one way between
