@@ -463,6 +463,7 @@ struct Prog {
     std::vector<uint64_t*> bnd, ctab, acc;
     std::vector<uint64_t*> o_nu_h, o_nu_d, o_ave_h, o_ave_d, o_avf_h, o_avf_d, o_ie_h, o_ie_d, o_ig_h, o_ig_d;
     std::vector<uint8_t*> o_vk, o_ad, o_bd;
+    std::vector<char*> ctx_end;              // end of each context's arena region (bnd .. outputs)
     std::vector<int32_t> sweeps;             // [nctx][6]
     // summary evaluation outputs (per procedure, 4 evaluations, nu/ave H/D)
     std::vector<uint64_t*> e_out;            // [4][4][nb][wd]
@@ -620,7 +621,7 @@ int setup(Prog& G)
     for (auto* v : {&G.o_nu_h, &G.o_nu_d, &G.o_ave_h, &G.o_ave_d, &G.o_avf_h, &G.o_avf_d, &G.o_ie_h, &G.o_ie_d,
                     &G.o_ig_h, &G.o_ig_d})
         v->resize(nctx);
-    G.o_vk.resize(nctx); G.o_ad.resize(nctx); G.o_bd.resize(nctx);
+    G.o_vk.resize(nctx); G.o_ad.resize(nctx); G.o_bd.resize(nctx); G.ctx_end.resize(nctx);
     G.sweeps.assign((size_t)nctx * 6, 0);
     for (int x = 0; x < nctx; ++x) {
         const int p = st.cproc[x];
@@ -635,6 +636,7 @@ int setup(Prog& G)
         G.o_ig_h[x] = o + 8 * bv; G.o_ig_d[x] = o + 8 * bv + evv;
         uint8_t* b8 = (uint8_t*)(o + 8 * bv + 2 * evv);
         G.o_vk[x] = b8; G.o_ad[x] = b8 + P->procs[p].n_vars; G.o_bd[x] = b8 + P->procs[p].n_vars + nb;
+        G.ctx_end[x] = (char*)(b8 + P->procs[p].n_vars + 2 * nb);
     }
     G.arena_items = A + oItems;
     return OMPD_OK;
@@ -1018,29 +1020,55 @@ extern "C" int ompd_analyze_program(ompd_ctx* ctx, const ompd_program* prog, omp
         CK(hipMemcpyAsync(out->summaries, G.S, 8 * (size_t)st.n * SUM_ROWS * gw, hipMemcpyDeviceToHost, G.s));
     if (out->demands && st.nc && gw)
         memcpy(out->demands, dem.data(), 8 * (size_t)st.nc * gw);
-    size_t boff = 0;
-    for (int x = 0; x < nctx; ++x) {
+    // Per-context results: each context's region of the arena (boundaries, tables, outputs) is
+    // contiguous and the regions follow each other, so runs of contexts go to a pinned staging
+    // buffer in one copy and are scattered to the caller's arrays on the host (thousands of
+    // small copies to pageable memory would cost more than the solve).
+    std::vector<size_t> boffs(nctx);
+    {
+        size_t boff = 0;
+        for (int x = 0; x < nctx; ++x) { boffs[x] = boff; boff += 4 * (size_t)st.wd[st.cproc[x]]; }
+    }
+    auto scatter = [&](int x, const char* base, const char* src) {
+        // base: device address that src (a host copy of the same bytes) stands for
         const int p = st.cproc[x];
         const size_t nb = st.nb[p], ne = st.ne[p], wd = st.wd[p], bv = nb * wd, ev = ne * wd;
-        if (out->boundaries && wd)
-            CK(hipMemcpyAsync(out->boundaries + boff, G.bnd[x], 8 * 4 * wd, hipMemcpyDeviceToHost, G.s));
-        boff += 4 * wd;
-        if (!out->per_context) continue;
+        auto at = [&](const void* dev) { return src + ((const char*)dev - base); };
+        if (out->boundaries && wd) memcpy(out->boundaries + boffs[x], at(G.bnd[x]), 8 * 4 * wd);
+        if (!out->per_context) return;
         ompd_result& r = out->per_context[x];
-        auto cp = [&](void* dst, const void* src, size_t bytes) -> int {
-            if (dst && bytes) CK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, G.s));
-            return OMPD_OK;
-        };
-        int e = 0;
-        e |= cp(r.nu_host, G.o_nu_h[x], 8 * bv); e |= cp(r.nu_dev, G.o_nu_d[x], 8 * bv);
-        e |= cp(r.ave_host, G.o_ave_h[x], 8 * bv); e |= cp(r.ave_dev, G.o_ave_d[x], 8 * bv);
-        e |= cp(r.avf_host, G.o_avf_h[x], 8 * bv); e |= cp(r.avf_dev, G.o_avf_d[x], 8 * bv);
-        e |= cp(r.ins_entry_to_host, G.o_ie_h[x], 8 * bv); e |= cp(r.ins_entry_to_dev, G.o_ie_d[x], 8 * bv);
-        e |= cp(r.ins_edge_to_host, G.o_ig_h[x], 8 * ev); e |= cp(r.ins_edge_to_dev, G.o_ig_d[x], 8 * ev);
-        e |= cp(r.var_kind, G.o_vk[x], (size_t)prog->procs[p].n_vars);
-        e |= cp(r.after_dev, G.o_ad[x], nb); e |= cp(r.before_dev, G.o_bd[x], nb);
-        if (e) return OMPD_E_DEVICE;
+        auto cp = [&](void* dst, const void* dev, size_t bytes) { if (dst && bytes) memcpy(dst, at(dev), bytes); };
+        cp(r.nu_host, G.o_nu_h[x], 8 * bv); cp(r.nu_dev, G.o_nu_d[x], 8 * bv);
+        cp(r.ave_host, G.o_ave_h[x], 8 * bv); cp(r.ave_dev, G.o_ave_d[x], 8 * bv);
+        cp(r.avf_host, G.o_avf_h[x], 8 * bv); cp(r.avf_dev, G.o_avf_d[x], 8 * bv);
+        cp(r.ins_entry_to_host, G.o_ie_h[x], 8 * bv); cp(r.ins_entry_to_dev, G.o_ie_d[x], 8 * bv);
+        cp(r.ins_edge_to_host, G.o_ig_h[x], 8 * ev); cp(r.ins_edge_to_dev, G.o_ig_d[x], 8 * ev);
+        cp(r.var_kind, G.o_vk[x], (size_t)prog->procs[p].n_vars);
+        cp(r.after_dev, G.o_ad[x], nb); cp(r.before_dev, G.o_bd[x], nb);
         memcpy(r.sweeps, &G.sweeps[(size_t)x * 6], sizeof r.sweeps);
+    };
+    const size_t STAGE = (size_t)64 << 20;
+    char* stage = nullptr;
+    if (hipHostMalloc((void**)&stage, STAGE, hipHostMallocDefault) != hipSuccess)
+        return ompd_fail(OMPD_E_NOMEM, "program: pinned staging buffer");
+    struct StageGuard { char* p; ~StageGuard() { (void)hipHostFree(p); } } stg{stage};
+    CK(hipStreamSynchronize(G.s));
+    std::vector<char> big;   // a context larger than the staging buffer (not in the shapes this targets)
+    for (int x = 0; x < nctx;) {
+        const char* base = (const char*)G.bnd[x];
+        int y = x;
+        while (y < nctx && (size_t)(G.ctx_end[y] - base) <= STAGE) ++y;
+        if (y == x) {
+            big.resize((size_t)(G.ctx_end[x] - base));
+            CK(hipMemcpy(big.data(), base, big.size(), hipMemcpyDeviceToHost));
+            scatter(x, base, big.data());
+            ++x;
+            continue;
+        }
+        CK(hipMemcpyAsync(stage, base, (size_t)(G.ctx_end[y - 1] - base), hipMemcpyDeviceToHost, G.s));
+        CK(hipStreamSynchronize(G.s));
+        for (int c = x; c < y; ++c) scatter(c, base, stage);
+        x = y;
     }
     CK(hipStreamSynchronize(G.s));
     return OMPD_OK;
