@@ -80,7 +80,7 @@ struct ScratchOff {
 };
 size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o);
 void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const ScratchOff& o, uint32_t flags,
-                      ompd::DevCfg& d, uint64_t* bnd_host);
+                      ompd::DevCfg& d, uint64_t* bnd_host, uint64_t* bnd_dev = nullptr);
 // Launch shape of a set of CFGs: tiles (longest first), edge-step items and grids.
 struct Shape {
     std::vector<ompd::Tile> tiles;

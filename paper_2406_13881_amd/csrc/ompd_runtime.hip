@@ -189,10 +189,10 @@ size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o)
 
 // Fill the kernels' descriptor of one CFG whose scratch starts at `base`.
 // Default boundary values (for NULL boundaries) are written to bnd_host
-// ([4*wd] words: entry valid H, D, exit live H, D), to be copied to
-// base + o.bnd by the caller.
+// ([4*wd] words: entry valid H, D, exit live H, D), to be copied by the
+// caller to bnd_dev (default: base + o.bnd), where the descriptor points.
 void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const ScratchOff& o, uint32_t flags,
-                      DevCfg& d, uint64_t* bnd_host)
+                      DevCfg& d, uint64_t* bnd_host, uint64_t* bnd_dev)
 {
     int wd = (g.n_vars + 63) / 64;
     memset(&d, 0, sizeof d);
@@ -202,7 +202,7 @@ void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const
     d.sweep_cap = (int)((flags >> 16) & 0xFFFFu);
     d.succ_ptr = g.succ_ptr; d.succ_idx = g.succ_idx; d.kind = g.edge_kind; d.space = g.space;
     d.R = g.read_bits; d.W = g.write_bits;
-    uint64_t* bnd = (uint64_t*)(base + o.bnd);
+    uint64_t* bnd = bnd_dev ? bnd_dev : (uint64_t*)(base + o.bnd);
     d.ev_h = g.entry_valid_host ? g.entry_valid_host : bnd;
     d.ev_d = g.entry_valid_dev ? g.entry_valid_dev : bnd + wd;
     d.lx_h = g.exit_live_host ? g.exit_live_host : bnd + 2 * wd;
@@ -341,6 +341,15 @@ int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32
     }
     size_t counter_off = total;
     total += 256;
+    // default boundaries of every CFG, side by side (one upload)
+    std::vector<size_t> boff(n);
+    size_t bnd_words = 0;
+    for (int i = 0; i < n; ++i) {
+        boff[i] = bnd_words;
+        bnd_words += 4 * (size_t)((cfgs[i].n_vars + 63) / 64);
+    }
+    const size_t bnd_off = total;
+    total += (8 * bnd_words + 255) & ~(size_t)255;
     p->scratch_bytes = total;
     hipError_t e = hipMalloc(&p->scratch, std::max<size_t>(total, 256));
     if (e != hipSuccess) {
@@ -349,15 +358,14 @@ int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32
     }
     char* S = (char*)p->scratch;
     p->d_counter = (int32_t*)(S + counter_off);
-    std::vector<uint64_t> bnd;
-    for (int i = 0; i < n; ++i) {
-        size_t wd = (size_t)(cfgs[i].n_vars + 63) / 64;
-        bnd.assign(4 * wd, 0);
-        ompd_fill_devcfg(cfgs[i], res[i], S + base[i], off[i], flags, p->h_cfgs[i], bnd.data());
-        if (wd) {
-            e = hipMemcpy(S + base[i] + off[i].bnd, bnd.data(), 4 * wd * 8, hipMemcpyHostToDevice);
-            if (e != hipSuccess) { ompd_plan_destroy(p); return ompd_fail(OMPD_E_DEVICE, hipGetErrorString(e)); }
-        }
+    std::vector<uint64_t> bnd(std::max<size_t>(bnd_words, 1), 0);
+    uint64_t* bnd_dev = (uint64_t*)(S + bnd_off);
+    for (int i = 0; i < n; ++i)
+        ompd_fill_devcfg(cfgs[i], res[i], S + base[i], off[i], flags, p->h_cfgs[i], bnd.data() + boff[i],
+                         bnd_dev + boff[i]);
+    if (bnd_words) {
+        e = hipMemcpy(bnd_dev, bnd.data(), 8 * bnd_words, hipMemcpyHostToDevice);
+        if (e != hipSuccess) { ompd_plan_destroy(p); return ompd_fail(OMPD_E_DEVICE, hipGetErrorString(e)); }
     }
     p->max_nb = max_nb;
     e = hipMalloc(&p->d_cfgs, sizeof(DevCfg) * std::max(n, 1));
