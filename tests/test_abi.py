@@ -37,3 +37,19 @@ def test_no_silent_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(ompd, "_handle", None)
     with pytest.raises(ompd.OmpdNotBuilt):
         ompd.lib()
+
+
+def test_ring_slots_flag_matches_header(tmp_path):
+    """The binding's F_RING_SLOTS encodes ring sizes exactly as the header's
+    OMPD_F_RING_SLOTS macro (compiled with the host C compiler)."""
+    import subprocess
+    ns = [0, 1, 7, 8, 9, 15, 16, 31, 32, 63, 64, 65, 1000]
+    src = tmp_path / "rs.c"
+    src.write_text('#include <stdio.h>\n#include "ompd.h"\nint main(void) {\n' +
+                   "".join('printf("%%u\\n", (unsigned)OMPD_F_RING_SLOTS(%d));\n' % n for n in ns) +
+                   "return 0;\n}\n")
+    exe = tmp_path / "rs"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got == [ompd.F_RING_SLOTS(n) for n in ns]
+    assert [ompd.F_RING_SLOTS(n) >> 8 for n in (8, 16, 32, 64)] == [1, 2, 3, 4]
