@@ -1063,6 +1063,14 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         auto fast = [&](const u64* x, const u64* nh, const u64* nd, uint32_t fl, u64& vh, u64& vd) {
             const bool dev = fl & DF_DEV;
             const bool p0 = fl & 3u, p1 = (fl >> 2) & 3u;
+            if (p0 && !p1) {
+                // one predecessor: its term is both the AND and (unless the edge enters a loop) the OR
+                const u64 l0h = x[2] | nh[0], l0d = x[3] | nd[0], st = x[0] | x[1];
+                const u64 keep = (fl & DF_LE0) ? 0ull : vm;
+                vh = l0h & keep & (dev ? ~0ull : ~st);
+                vd = l0d & keep & (dev ? ~st : ~0ull);
+                return;
+            }
             const u64 l0h = x[2] | nh[0], l0d = x[3] | nd[0], l1h = x[5] | nh[1], l1d = x[6] | nd[1];
             const u64 allh = (p0 ? (l0h | x[4]) : ~0ull) & (p1 ? (l1h | x[7]) : ~0ull);
             const u64 alld = (p0 ? (l0d | x[4]) : ~0ull) & (p1 ? (l1d | x[7]) : ~0ull);
