@@ -62,6 +62,7 @@ constexpr uint32_t DF_LE0 = 1u << 6;    // edge of neighbour 0 is a loop entry (
 constexpr uint32_t DF_LE1 = 1u << 7;    // edge of neighbour 1 is a loop entry
 constexpr uint32_t SF_FAR = 1u << 8;    // one of the first two neighbours is far (step entries only)
 constexpr uint32_t SF_BACK = 1u << 9;   // ... and not visited yet in the sweep
+constexpr uint32_t SF_ONE = 1u << 10;   // at most one neighbour: no rows of a second edge are read
 constexpr uint32_t DF_MASK = 0xFFu;     // the bits a step descriptor carries
 // A step entry (two int4, one per walk position): x flags; y the ring distances of neighbours
 // 0 and 1 (bits 0-7, 8-15; flag code 2 only); z the far neighbour; w how many steps before the
@@ -77,6 +78,7 @@ __device__ __forceinline__ void make_step(const int4& r0, const int4& r1, int b,
     fl |= (meta & REC_DEV) ? DF_DEV : 0u;
     fl |= (e0 & 0x80000000u) ? DF_LE0 : 0u;
     fl |= ((e1 & 0x80000000u) && cnt > 1) ? DF_LE1 : 0u;
+    fl |= cnt <= 1 ? SF_ONE : 0u;
     int dd = 0, fp = 0, fo = 0;
     bool far = false;
     for (int j = 0; j < 2 && j < cnt; ++j) {
@@ -427,6 +429,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     constexpr bool with_flags = PH == PH_NU || PH == PH_AVE;   // phases with the flag lane
     constexpr bool BWD = PH == PH_NU;
     constexpr int NX = PH == PH_NU ? 2 : PH == PH_AVE ? 3 : PH == PH_MAYP ? 6 : PH == PH_LATER ? 8 : 7;
+    // the first input that is a row of the second edge (NX: the phase reads no edge rows)
+    constexpr int NX1 = PH == PH_MAYP ? 4 : PH == PH_LATER ? 5 : PH == PH_AVF ? 5 : NX;
     constexpr int NI = NX + 2;        // inputs of a step: the phase's own and the first far neighbour (h, d)
     constexpr int IR = in_ring(PH);   // steps whose inputs the helper keeps ready
     // Lanes 0 .. LANES - 1 of both wavefronts own the tile's words; lanes LANES .. 2 LANES - 1 of
@@ -619,9 +623,12 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                     (uint32_t)__builtin_amdgcn_readlane(xv.z, j), a);
                 const uint32_t slot = (uint32_t)__builtin_amdgcn_readfirstlane(
                     (int)(lds3 + IN_OFF + (uint32_t)((sj & (IR - 1)) * NI) * WORD_BYTES));
-#pragma unroll
-                for (int k = 0; k < NX; ++k) dma_row<0>(a[k], hoff, (LDS3 char*)(size_t)(slot + k * WORD_BYTES));
                 const uint32_t flj = (uint32_t)__builtin_amdgcn_readlane((int)fl, j);
+                // (a block with one neighbour never reads the second edge's slots)
+                const int nx = (flj & SF_ONE) ? NX1 : NX;
+#pragma unroll
+                for (int k = 0; k < NX; ++k)
+                    if (k < nx) dma_row<0>(a[k], hoff, (LDS3 char*)(size_t)(slot + k * WORD_BYTES));
                 const int uj = __builtin_amdgcn_readlane(u, j);
                 if ((flj & SF_FAR) && uj >= 0 && uj < gf0) {
                     const int p = __builtin_amdgcn_readlane(ev.z, j);
@@ -970,7 +977,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         if (c.placement & 1) return;
         const Rows S = rows_of(c.mayp_h, c.mayp_d, 0);
         // x0 = R, x1 = W, x2..x5 = EAG_H/D of the two inline in-edges
-        // (edge 0 stands in for a missing neighbour's edge)
+        // (the second edge's rows are not loaded for a block with one neighbour)
         auto pre = [&](int b, uint32_t e0, uint32_t e1, const GAS u64** x) {
             x[0] = rowu(c.R, b); x[1] = rowu(c.W, b);
             x[2] = erowu(c.eag_h, e0); x[3] = erowu(c.eag_d, e0);
