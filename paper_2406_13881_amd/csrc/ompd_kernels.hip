@@ -325,12 +325,12 @@ __device__ __forceinline__ Rec ldrec(const int32_t* base, int b)
     return r;
 }
 
-__device__ __forceinline__ u64 tsel(u64 a1, u64 l, u64 t00, u64 t01, u64 t10, u64 t11)
+template <class T>
+__device__ __forceinline__ T tsel(T a1, T l, T t00, T t01, T t10, T t11)
 {
     return (~a1 & ~l & t00) | (~a1 & l & t01) | (a1 & ~l & t10) | (a1 & l & t11);
 }
 
-__device__ __forceinline__ uint32_t popc2(u64 a, u64 b) { return (uint32_t)(__popcll(a) + __popcll(b)); }
 
 // A state row written by the other wavefront of the workgroup in this kernel:
 // read past the (non-coherent) first-level cache.
@@ -339,10 +339,17 @@ __device__ __forceinline__ u64 ld_fresh(const GAS u64* p)
     return __hip_atomic_load(const_cast<GAS u64*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ uint32_t ld_half(const GAS u64* p, bool hi)
+{
+    return __hip_atomic_load(const_cast<GAS uint32_t*>(reinterpret_cast<const GAS uint32_t*>(p)) + (hi ? 1 : 0),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // A value loaded on a rarely taken path, made ready before the paths join: the
 // compiler then waits for the load on that path only, instead of at the join,
 // where the wait would also drain the loads issued ahead on the common path.
-__device__ __forceinline__ u64 settle(u64 x)
+template <class T>
+__device__ __forceinline__ T settle(T x)
 {
     asm volatile("" : "+v"(x));
     return x;
@@ -416,6 +423,9 @@ struct Rows {
     int str;
     __device__ __forceinline__ u64 ldh(int b) const { return ld_fresh(h + (size_t)b * str); }
     __device__ __forceinline__ u64 ldd(int b) const { return ld_fresh(d + (size_t)b * str); }
+    // the low (hi = false) or high half of the word
+    __device__ __forceinline__ uint32_t ldh32(int b, bool hi) const { return ld_half(h + (size_t)b * str, hi); }
+    __device__ __forceinline__ uint32_t ldd32(int b, bool hi) const { return ld_half(d + (size_t)b * str, hi); }
     __device__ __forceinline__ void st(int b, u64 x, u64 y) const
     {
         h[(size_t)b * str] = x;
@@ -433,12 +443,19 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     constexpr int NX1 = PH == PH_MAYP ? 4 : PH == PH_LATER ? 5 : PH == PH_AVF ? 5 : NX;
     constexpr int NI = NX + 2;        // inputs of a step: the phase's own and the first far neighbour (h, d)
     constexpr int IR = in_ring(PH);   // steps whose inputs the helper keeps ready
-    // Lanes 0 .. LANES - 1 of both wavefronts own the tile's words; lanes LANES .. 2 LANES - 1 of
-    // the helper mirror them (same word, same rows) only to copy the high halves of input words
-    // (`hi`): every other per-lane LDS write and global store is made by the low lanes.
+    // Lanes 0 .. LANES - 1 of both wavefronts own the tile's words, lanes LANES .. 2 LANES - 1
+    // (`hi`) the same words again.  The compute wavefront works on half-words: lane ln holds the
+    // low 32 bits of word s0 + ln, lane ln + LANES the high 32 bits, so that a bitwise operation
+    // is one instruction and reading a word from LDS one 32-lane access.  In the helper the high
+    // lanes only copy the high halves of input words; its other per-lane LDS writes and its
+    // global stores are made by the low lanes, a 64-bit word each.
     const int lane = threadIdx.x & 63;
     const int ln = lane & (LANES - 1);
     const bool hi = lane >= LANES;
+    const int l32 = lane & (2 * LANES - 1);   // the lane's half-word in the split LDS layout
+    typedef uint32_t hw;                      // a half-word (compute wavefront)
+    // a constant of the flag lane (bits 0-1: the low half)
+    auto lo = [&](uint32_t v) -> hw { return hi ? 0u : v; };
     const bool helper = threadIdx.x >= 64;
     const int nb = c.nb, wd = c.wd;
     // a tile without variables (nw = 0) has only flag lanes (they compute the same facts)
@@ -457,7 +474,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     u64* iring = reinterpret_cast<u64*>(lds8 + IN_OFF);
     int4* dring = reinterpret_cast<int4*>(lds8 + DESC_OFF);
     // valid-variable mask of the lane's word (shadow lanes share word s0's; the flag lane uses bits 0-1)
-    const u64 vm = flg ? 3ull : ((w == wd - 1 && (c.nv & 63)) ? ((1ull << (c.nv & 63)) - 1ull) : ~0ull);
+    const u64 vm64 = flg ? 3ull : ((w == wd - 1 && (c.nv & 63)) ? ((1ull << (c.nv & 63)) - 1ull) : ~0ull);
+    const hw vm = (hw)(hi ? vm64 >> 32 : vm64);   // its half
     const int cap = c.sweep_cap > 0 ? c.sweep_cap : 2 * nb + 2;
     const int32_t* REC = BWD ? c.rec_b : c.rec_f;
     const CAS int32_t* PI = K(c.pred_idx);
@@ -468,20 +486,22 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     const size_t wo = (size_t)w;
     // data arrays of a CFG without variables may be empty: loads then read a flag word instead
     auto arr = [&](const u64* a) -> const GAS u64* { return wd ? G(a) : (const GAS u64*)FLG; };
-    auto row = [&](const u64* a, int b) -> u64 { return arr(a)[(size_t)b * wd + wo]; };
+    // the lane's half of a word (compute wavefront)
+    auto half = [&](const GAS u64* p) -> hw { return reinterpret_cast<const GAS uint32_t*>(p)[hi ? 1 : 0]; };
+    auto row = [&](const u64* a, int b) -> hw { return half(arr(a) + (size_t)b * wd + wo); };
     // start of row b (wave-uniform) and the byte of the lane's half-word within a row
     auto rowu = [&](const u64* a, int b) -> const GAS u64* { return arr(a) + (size_t)b * wd; };
     const uint32_t hoff = (uint32_t)wo * 8u + (hi ? 4u : 0u);
     // (both only at compute time, on rare paths: ENTRY, EXIT, call blocks)
-    auto vec = [&](const u64* a) -> u64 { return settle(arr(a)[wo]); };
-    auto sum = [&](int ci, int r) -> u64 { return settle(arr(c.sums)[((size_t)ci * SUM_ROWS + r) * wd + wo]); };
+    auto vec = [&](const u64* a) -> hw { return settle(half(arr(a) + wo)); };
+    auto sum = [&](int ci, int r) -> hw { return settle(half(arr(c.sums) + ((size_t)ci * SUM_ROWS + r) * wd + wo)); };
     auto rows_of = [&](u64* h, u64* d, int fl) -> Rows {
         Rows r;
         if (flg) { r.h = FLG + (size_t)fl * nb; r.d = FLG + (size_t)(fl + 1) * nb; r.str = 1; }
         else { r.h = G(h) + wo; r.d = G(d) + wo; r.str = wd; }
         return r;
     };
-    // the word at LDS byte offset `at` (split layout), this lane's
+    // the word at LDS byte offset `at` (split layout), this lane's (helper)
     auto w_get = [&](int at) -> u64 {
         const uint32_t* q = reinterpret_cast<const uint32_t*>(lds8 + at) + ln;
         return (u64)q[0] | ((u64)q[LANES] << 32);
@@ -497,10 +517,12 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // input k of step g: LANES low halves, then LANES high halves
     uint32_t* iring32 = reinterpret_cast<uint32_t*>(iring);
     auto in32 = [&](int g, int k) -> uint32_t* { return iring32 + ((size_t)(g & (IR - 1)) * NI + k) * (2 * LANES); };
-    auto in_get = [&](int g, int k) -> u64 {
-        const uint32_t* q = in32(g, k) + ln;
-        return (u64)q[0] | ((u64)q[LANES] << 32);
-    };
+    // the same as half-words (compute wavefront)
+    auto c_get = [&](int at) -> hw { return reinterpret_cast<const uint32_t*>(lds8 + at)[l32]; };
+    auto c_put = [&](int at, hw v) { reinterpret_cast<uint32_t*>(lds8 + at)[l32] = v; };
+    auto cslot_h = [&](int g) -> hw { return c_get(ring_at(g)); };
+    auto cslot_d = [&](int g) -> hw { return c_get(ring_at(g) + WORD_BYTES); };
+    auto cin = [&](int g, int k) -> hw { return in32(g, k)[l32]; };
 
     // neighbour j of a record (j >= 2 from the CSR); edge id with LOOP_ENTRY in bit 31
     auto nbr_f = [&](const Rec& r, int j, int& p, uint32_t& e) {
@@ -663,11 +685,11 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // neighbour p at distance d of the block of step g, from the rows: the previous sweep's (or
     // the initial value in sweep 0) for a block not yet visited, this sweep's for one visited
     // more than RS steps ago
-    auto far_val = [&](const Rows& S, int p, int d, int g, int sweep, u64 init, u64& h, u64& dd) {
+    auto far_val = [&](const Rows& S, int p, int d, int g, int sweep, hw init, hw& h, hw& dd) {
         if (d <= 0 && sweep == 0) { h = init; dd = init; return; }
         if (d > 0) need(&ctl->flushed, flsh, g - d);
-        h = settle(S.ldh(p));
-        dd = settle(S.ldd(p));
+        h = settle(S.ldh32(p, hi));
+        dd = settle(S.ldd32(p, hi));
     };
 
     // One sweep.  fast(x, nh, nd, fl, vh, vd) computes the new state of an ordinary block (not
@@ -689,19 +711,19 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     };
     // inputs of step g and the states at its neighbours' locations (no branch: a missing
     // neighbour and the block computed last point at the identity state)
-    auto fetch = [&](int g, int l0, int l1, u64* x, u64* nh, u64* nd) {
+    auto fetch = [&](int g, int l0, int l1, hw* x, hw* nh, hw* nd) {
 #pragma unroll
-        for (int k = 0; k < NX; ++k) x[k] = in_get(g, k);
-        nh[0] = w_get(l0); nd[0] = w_get(l0 + WORD_BYTES);
-        nh[1] = w_get(l1); nd[1] = w_get(l1 + WORD_BYTES);
+        for (int k = 0; k < NX; ++k) x[k] = cin(g, k);
+        nh[0] = c_get(l0); nd[0] = c_get(l0 + WORD_BYTES);
+        nh[1] = c_get(l1); nd[1] = c_get(l1 + WORD_BYTES);
     };
-    auto walk = [&](const Rows& S, u64 init, int sweep, uint32_t& pc, auto&& fast, auto&& comp) {
-        u64 ph = init, pd = init;   // state of the block computed last
+    auto walk = [&](const Rows& S, hw init, int sweep, uint32_t& pc, auto&& fast, auto&& comp) {
+        hw ph = init, pd = init;   // state of the block computed last
         uint32_t fl0, fl1 = 0;      // flags of steps g and g + 1
         int a0, b0, a1 = IDENT_OFF, b1 = IDENT_OFF;
         int4 dq2 = make_int4(0, IDENT_OFF, IDENT_OFF, 0);   // descriptor of step g + 2, not decoded
         // two sets of step inputs, used in turn (the loop below runs two steps per round)
-        u64 xa[NX], nha[2], nda[2], xb[NX], nhb[2], ndb[2];
+        hw xa[NX], nha[2], nda[2], xb[NX], nhb[2], ndb[2];
         need(&ctl->in_ready, inr, gbase);
         desc(gbase, fl0, a0, b0);
         fetch(gbase, a0, b0, xa, nha, nda);
@@ -714,7 +736,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             dq2 = dring[(gbase + 2) & (IR - 1)];
         }
         // step gbase + i with its inputs in (x, nh, nd); the next step's go to (y, ny, nz)
-        auto step = [&](int i, const u64* x, const u64* nh, const u64* nd, u64* y, u64* ny, u64* nz) {
+        auto step = [&](int i, const hw* x, const hw* nh, const hw* nd, hw* y, hw* ny, hw* nz) {
             const int g = gbase + i;
             const uint32_t fl = fl0;
             // the ring slot of step g was last used by step g - RS: the helper must have read it
@@ -725,14 +747,14 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 dq3 = dring[(g + 3) & (IR - 1)];
             }
             if (i + 1 < nb) fetch(g + 1, a1, b1, y, ny, nz);
-            u64 vh_[2], vd_[2];
+            hw vh_[2], vd_[2];
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const bool last = ((fl >> (2 * j)) & 3u) == 1u;
                 vh_[j] = last ? ph : nh[j];
                 vd_[j] = last ? pd : nd[j];
             }
-            u64 vh, vd;
+            hw vh, vd;
             if (!(fl & DF_SLOW)) fast(x, vh_, vd_, fl, vh, vd);
             else {
                 // any block: neighbour values by the general rule, then the full transfer
@@ -745,15 +767,15 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                     if (j >= cnt) continue;
                     const int p = j == 0 ? r.n0 : r.n1, d = dist(b, p);
                     if (d == 1) { vh_[j] = ph; vd_[j] = pd; }
-                    else if (d >= 2 && d <= RS) { vh_[j] = slot_h(g - d); vd_[j] = slot_d(g - d); }
-                    else if (!far_used) { vh_[j] = in_get(g, NX); vd_[j] = in_get(g, NX + 1); far_used = true; }
+                    else if (d >= 2 && d <= RS) { vh_[j] = cslot_h(g - d); vd_[j] = cslot_d(g - d); }
+                    else if (!far_used) { vh_[j] = cin(g, NX); vd_[j] = cin(g, NX + 1); far_used = true; }
                     else far_val(S, p, d, g, sweep, init, vh_[j], vd_[j]);
                 }
                 comp(b, r, x, vh_, vd_, ph, pd, sweep, g, vh, vd);
             }
-            pc += popc2(vh, vd);
-            w_put(ring_at(g), vh);
-            w_put(ring_at(g) + WORD_BYTES, vd);
+            pc += (uint32_t)(__popc(vh) + __popc(vd));
+            c_put(ring_at(g), vh);
+            c_put(ring_at(g) + WORD_BYTES, vd);
             // the state goes before the counter (program order; LDS keeps it)
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
             lds_put(&ctl->produced, g + 1);
@@ -771,22 +793,24 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         }
     };
     // a neighbour beyond the first two, at compute time (g = the current step)
-    auto extra = [&](const Rows& S, int b, int p, int sweep, int g, u64 init, u64 ph, u64 pd, u64& h, u64& d) {
+    auto extra = [&](const Rows& S, int b, int p, int sweep, int g, hw init, hw ph, hw pd, hw& h, hw& d) {
         const int dd = dist(b, p);
         if (dd == 1) { h = ph; d = pd; }
-        else if (dd >= 2 && dd <= RS) { h = slot_h(g - dd); d = slot_d(g - dd); }
+        else if (dd >= 2 && dd <= RS) { h = cslot_h(g - dd); d = cslot_d(g - dd); }
         else far_val(S, p, dd, g, sweep, init, h, d);
     };
     // Run a phase: the compute wavefront sweeps, the helper feeds and stores; false on an error.
-    auto run_phase = [&](const Rows& S, u64 init, u64 ident, auto&& pre, auto&& fast, auto&& comp) -> bool {
+    // (init64: the initial state of the lane's word; ident64: the state of a missing neighbour)
+    auto run_phase = [&](const Rows& S, u64 init64, u64 ident64, auto&& pre, auto&& fast, auto&& comp) -> bool {
         if (helper) {
-            helper_loop(S, init, pre);
+            helper_loop(S, init64, pre);
             return true;
         }
-        w_put(IDENT_OFF, ident);   // the state of a missing neighbour
-        w_put(IDENT_OFF + WORD_BYTES, ident);
+        const hw init = (hw)(hi ? init64 >> 32 : init64), ident = (hw)ident64;
+        c_put(IDENT_OFF, ident);
+        c_put(IDENT_OFF + WORD_BYTES, ident);
         int sweeps = 0;
-        uint32_t last = (uint32_t)nb * 2u * (uint32_t)__popcll(init);
+        uint32_t last = (uint32_t)nb * 2u * (uint32_t)__popc(init);
         bool good = true;
         for (;;) {
             uint32_t pc = 0;
@@ -814,7 +838,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         return good;
     };
     // NUout of a call block: OR over its successors' next use (final)
-    auto nu_after = [&](int b, u64& lh, u64& ld) {
+    auto nu_after = [&](int b, hw& lh, hw& ld) {
         const Rec rb = ldrec(c.rec_b, b);
         const int cnt = (int)(rb.meta & REC_COUNT);
         lh = 0; ld = 0;
@@ -826,16 +850,16 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     };
     // validity transfer of block b (a call applies the callee's exit-validity
     // tables to the validity after the block's own accesses and the next use after the call)
-    auto valid_out = [&](int b, const Rec& r, u64 ih, u64 id, u64 wr, u64& oh, u64& od) {
+    auto valid_out = [&](int b, const Rec& r, hw ih, hw id, hw wr, hw& oh, hw& od) {
         const bool dev = r.meta & REC_DEV;
-        u64 ah = dev ? (ih & ~wr) : (ih | wr);
-        u64 ad = dev ? (id | wr) : (id & ~wr);
+        hw ah = dev ? (ih & ~wr) : (ih | wr);
+        hw ad = dev ? (id | wr) : (id & ~wr);
         if (r.meta & REC_CALL) {
-            u64 lh, ld;
+            hw lh, ld;
             nu_after(b, lh, ld);
             const int ci = r.ci;   // the flag lane passes through (identity tables)
-            const u64 th = tsel(ah, lh, sum(ci, SUM_TH + 0), sum(ci, SUM_TH + 1), sum(ci, SUM_TH + 2), sum(ci, SUM_TH + 3));
-            const u64 td = tsel(ad, ld, sum(ci, SUM_TD + 0), sum(ci, SUM_TD + 1), sum(ci, SUM_TD + 2), sum(ci, SUM_TD + 3));
+            const hw th = tsel(ah, lh, sum(ci, SUM_TH + 0), sum(ci, SUM_TH + 1), sum(ci, SUM_TH + 2), sum(ci, SUM_TH + 3));
+            const hw td = tsel(ad, ld, sum(ci, SUM_TD + 0), sum(ci, SUM_TD + 1), sum(ci, SUM_TD + 2), sum(ci, SUM_TD + 3));
             ah = flg ? ah : th;
             ad = flg ? ad : td;
         }
@@ -853,39 +877,39 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             x[0] = rowu(c.R, b);
             x[1] = rowu(c.W, b);
         };
-        auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd, int sweep,
-                        int g, u64& vh, u64& vd) {
+        auto comp = [&](int b, const Rec& r, const hw* x, const hw* nh, const hw* nd, hw ph, hw pd, int sweep,
+                        int g, hw& vh, hw& vd) {
             if (r.meta & REC_EXIT) {
-                const u64 lh = vec(c.lx_h), ld = vec(c.lx_d);
-                vh = flg ? 1ull : lh;
-                vd = flg ? 0ull : ld;
+                const hw lh = vec(c.lx_h), ld = vec(c.lx_d);
+                vh = flg ? lo(1) : lh;
+                vd = flg ? 0u : ld;
                 return;
             }
             const int cnt = (int)(r.meta & REC_COUNT);
-            u64 oh = nh[0] | nh[1], od = nd[0] | nd[1];
+            hw oh = nh[0] | nh[1], od = nd[0] | nd[1];
             for (int j = 2; j < cnt; ++j) {
-                u64 h, d;
-                extra(S, b, nbr_b(r, j), sweep, g, 0ull, ph, pd, h, d);
+                hw h, d;
+                extra(S, b, nbr_b(r, j), sweep, g, 0u, ph, pd, h, d);
                 oh |= h; od |= d;
             }
             const bool dev = r.meta & REC_DEV;
-            const u64 rr = flg ? 2ull : x[0], ww = flg ? (dev ? 2ull : 0ull) : x[1];
+            const hw rr = flg ? lo(2) : x[0], ww = flg ? (dev ? lo(2) : 0u) : x[1];
             if (r.meta & REC_CALL) {
                 const int ci = r.ci;   // the flag lane passes through (NU0 = 0, NU1 = all ones)
-                const u64 ch = sum(ci, SUM_NU0_H) | (sum(ci, SUM_NU1_H) & oh);
-                const u64 cd = sum(ci, SUM_NU0_D) | (sum(ci, SUM_NU1_D) & od);
+                const hw ch = sum(ci, SUM_NU0_H) | (sum(ci, SUM_NU1_H) & oh);
+                const hw cd = sum(ci, SUM_NU0_D) | (sum(ci, SUM_NU1_D) & od);
                 oh = flg ? oh : ch;
                 od = flg ? od : cd;
             }
-            vh = (dev ? 0ull : rr) | (~ww & oh);
-            vd = (dev ? rr : 0ull) | (~ww & od);
+            vh = (dev ? 0u : rr) | (~ww & oh);
+            vd = (dev ? rr : 0u) | (~ww & od);
         };
-        auto fast = [&](const u64* x, const u64* nh, const u64* nd, uint32_t fl, u64& vh, u64& vd) {
+        auto fast = [&](const hw* x, const hw* nh, const hw* nd, uint32_t fl, hw& vh, hw& vd) {
             const bool dev = fl & DF_DEV;
-            const u64 rr = flg ? 2ull : x[0], ww = flg ? (dev ? 2ull : 0ull) : x[1];
-            const u64 oh = nh[0] | nh[1], od = nd[0] | nd[1];
-            vh = (dev ? 0ull : rr) | (~ww & oh);
-            vd = (dev ? rr : 0ull) | (~ww & od);
+            const hw rr = flg ? lo(2) : x[0], ww = flg ? (dev ? lo(2) : 0u) : x[1];
+            const hw oh = nh[0] | nh[1], od = nd[0] | nd[1];
+            vh = (dev ? 0u : rr) | (~ww & oh);
+            vd = (dev ? rr : 0u) | (~ww & od);
         };
         run_phase(S, 0ull, 0ull, pre, fast, comp);
         return;
@@ -895,49 +919,49 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // AVEout_s(q) = transfer of AVEin_s(q) = NUin_s(q) | AND over preds AVEout_s(p); AVEin(ENTRY) = boundary.
     if constexpr (PH == PH_AVE) {
         const Rows S = rows_of(c.aveout_h, c.aveout_d, 2);
-        const u64 init = ~0ull & vm;
+        const hw init = vm;
         // x0/x1 = NU (flag lane: 0), x2 = W (flag lane: 2 at DEVICE blocks), substituted when computed
         auto pre = [&](int b, uint32_t, uint32_t, const GAS u64** x) {
             x[0] = rowu(c.nu_h, b);
             x[1] = rowu(c.nu_d, b);
             x[2] = rowu(c.W, b);
         };
-        auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd, int sweep,
-                        int g, u64& vh, u64& vd) {
-            u64 ih, id;
+        auto comp = [&](int b, const Rec& r, const hw* x, const hw* nh, const hw* nd, hw ph, hw pd, int sweep,
+                        int g, hw& vh, hw& vd) {
+            hw ih, id;
             if (r.meta & REC_ENTRY) {
-                const u64 eh = vec(c.ev_h), ed = vec(c.ev_d);
-                ih = flg ? 2ull : eh;
-                id = flg ? 0ull : ed;
+                const hw eh = vec(c.ev_h), ed = vec(c.ev_d);
+                ih = flg ? lo(2) : eh;
+                id = flg ? 0u : ed;
             } else {
                 const int cnt = (int)(r.meta & REC_COUNT);
                 // meet over the predecessors (all ones over none: a block no edge enters)
-                u64 mh = cnt == 0 ? ~0ull : cnt > 1 ? (nh[0] & nh[1]) : nh[0];
-                u64 md = cnt == 0 ? ~0ull : cnt > 1 ? (nd[0] & nd[1]) : nd[0];
+                hw mh = cnt == 0 ? ~0u : cnt > 1 ? (nh[0] & nh[1]) : nh[0];
+                hw md = cnt == 0 ? ~0u : cnt > 1 ? (nd[0] & nd[1]) : nd[0];
                 for (int j = 2; j < cnt; ++j) {
                     int p; uint32_t e;
                     nbr_f(r, j, p, e);
-                    u64 h, d;
+                    hw h, d;
                     extra(S, b, p, sweep, g, init, ph, pd, h, d);
                     mh &= h; md &= d;
                 }
-                ih = (flg ? 0ull : x[0]) | mh;
-                id = (flg ? 0ull : x[1]) | md;
+                ih = (flg ? 0u : x[0]) | mh;
+                id = (flg ? 0u : x[1]) | md;
             }
-            valid_out(b, r, ih & vm, id & vm, flg ? ((r.meta & REC_DEV) ? 2ull : 0ull) : x[2], vh, vd);
+            valid_out(b, r, ih & vm, id & vm, flg ? ((r.meta & REC_DEV) ? lo(2) : 0u) : x[2], vh, vd);
         };
-        auto fast = [&](const u64* x, const u64* nh, const u64* nd, uint32_t fl, u64& vh, u64& vd) {
+        auto fast = [&](const hw* x, const hw* nh, const hw* nd, uint32_t fl, hw& vh, hw& vd) {
             const bool dev = fl & DF_DEV;
-            const u64 ih = ((flg ? 0ull : x[0]) | (nh[0] & nh[1])) & vm, id = ((flg ? 0ull : x[1]) | (nd[0] & nd[1])) & vm;
-            const u64 wr = flg ? (dev ? 2ull : 0ull) : x[2];
+            const hw ih = ((flg ? 0u : x[0]) | (nh[0] & nh[1])) & vm, id = ((flg ? 0u : x[1]) | (nd[0] & nd[1])) & vm;
+            const hw wr = flg ? (dev ? lo(2) : 0u) : x[2];
             vh = (dev ? (ih & ~wr) : (ih | wr)) & vm;
             vd = (dev ? (id | wr) : (id & ~wr)) & vm;
         };
-        if (!run_phase(S, init, ~0ull, pre, fast, comp)) return;
+        if (!run_phase(S, vm64, ~0ull, pre, fast, comp)) return;
         if (helper) return;
         // reachability: every block reached from ENTRY and reaching EXIT
         bool bad = false;
-        for (int b = lane; b < nb; b += LANES) {
+        for (int b = l32; b < nb; b += 2 * LANES) {
             const u64 fnu = ld_fresh(FLG + b), fave = ld_fresh(FLG + (size_t)2 * nb + b);
             const u64 fnud = ld_fresh(FLG + (size_t)nb + b);
             if (!(fnu & 1) || (fave & 1)) bad = true;
@@ -953,21 +977,21 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
 
     // USE'_s(b) (a call whose callee may touch the variable stops pending copies like a read)
     // and the stop masks USE'_s | WR_s of a block, from R, W (and the live-after vectors at EXIT)
-    auto use_wr = [&](int b, const Rec& r, u64 rr, u64 ww, u64& uh, u64& ud, u64& sh, u64& sd) {
+    auto use_wr = [&](int b, const Rec& r, hw rr, hw ww, hw& uh, hw& ud, hw& sh, hw& sd) {
         const bool dev = r.meta & REC_DEV;
         if (r.meta & REC_EXIT) { uh = vec(c.lx_h); ud = vec(c.lx_d); sh = uh; sd = ud; return; }
-        uh = dev ? 0ull : rr;
-        ud = dev ? rr : 0ull;
+        uh = dev ? 0u : rr;
+        ud = dev ? rr : 0u;
         if (r.meta & REC_CALL) {
             const int ci = r.ci;
-            u64 mw = sum(ci, SUM_MAYW_H) | sum(ci, SUM_MAYW_D);
+            hw mw = sum(ci, SUM_MAYW_H) | sum(ci, SUM_MAYW_D);
             uh |= sum(ci, SUM_MAYR_H) | mw;
             ud |= sum(ci, SUM_MAYR_D) | mw;
         }
-        sh = uh | (dev ? 0ull : ww);
-        sd = ud | (dev ? ww : 0ull);
+        sh = uh | (dev ? 0u : ww);
+        sd = ud | (dev ? ww : 0u);
     };
-    auto erow = [&](const u64* a, uint32_t e) -> u64 { return G(a)[(size_t)(e & 0x7FFFFFFFu) * wd + wo]; };
+    auto erow = [&](const u64* a, uint32_t e) -> hw { return half(G(a) + (size_t)(e & 0x7FFFFFFFu) * wd + wo); };
     auto erowu = [&](const u64* a, uint32_t e) -> const GAS u64* { return G(a) + (size_t)(e & 0x7FFFFFFFu) * wd; };
 
     // -------------------------------------------------------- pending copies (forward, may)
@@ -983,38 +1007,38 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             x[2] = erowu(c.eag_h, e0); x[3] = erowu(c.eag_d, e0);
             x[4] = erowu(c.eag_h, e1); x[5] = erowu(c.eag_d, e1);
         };
-        auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd, int sweep,
-                        int g, u64& vh, u64& vd) {
+        auto comp = [&](int b, const Rec& r, const hw* x, const hw* nh, const hw* nd, hw ph, hw pd, int sweep,
+                        int g, hw& vh, hw& vd) {
             if (r.meta & REC_ENTRY) { vh = 0; vd = 0; return; }
             const int cnt = (int)(r.meta & REC_COUNT);
-            u64 mh = 0, md = 0;
+            hw mh = 0, md = 0;
             for (int j = 0; j < cnt; ++j) {
                 int p; uint32_t e;
                 nbr_f(r, j, p, e);
                 if (e & 0x80000000u) continue;   // loop entry: nothing stays pending
-                u64 gh, gd, sh, sd;
+                hw gh, gd, sh, sd;
                 if (j < 2) {   // (selects, not indexing: the arrays stay in registers)
                     gh = j ? x[4] : x[2]; gd = j ? x[5] : x[3]; sh = j ? nh[1] : nh[0]; sd = j ? nd[1] : nd[0];
                 }
                 else {
                     gh = settle(erow(c.eag_h, e)); gd = settle(erow(c.eag_d, e));
-                    extra(S, b, p, sweep, g, 0ull, ph, pd, sh, sd);
+                    extra(S, b, p, sweep, g, 0u, ph, pd, sh, sd);
                 }
                 mh |= gh | sh;
                 md |= gd | sd;
             }
-            u64 uh, ud, sth, std_;
+            hw uh, ud, sth, std_;
             use_wr(b, r, x[0], x[1], uh, ud, sth, std_);
             vh = mh & ~sth & vm;
             vd = md & ~std_ & vm;
         };
         // (the stop masks of an ordinary block: its own accesses)
-        auto fast = [&](const u64* x, const u64* nh, const u64* nd, uint32_t fl, u64& vh, u64& vd) {
+        auto fast = [&](const hw* x, const hw* nh, const hw* nd, uint32_t fl, hw& vh, hw& vd) {
             const bool dev = fl & DF_DEV;
             const bool t0 = (fl & 3u) && !(fl & DF_LE0), t1 = ((fl >> 2) & 3u) && !(fl & DF_LE1);
-            const u64 mh = (t0 ? (x[2] | nh[0]) : 0ull) | (t1 ? (x[4] | nh[1]) : 0ull);
-            const u64 md = (t0 ? (x[3] | nd[0]) : 0ull) | (t1 ? (x[5] | nd[1]) : 0ull);
-            const u64 sth = dev ? 0ull : (x[0] | x[1]), std_ = dev ? (x[0] | x[1]) : 0ull;
+            const hw mh = (t0 ? (x[2] | nh[0]) : 0u) | (t1 ? (x[4] | nh[1]) : 0u);
+            const hw md = (t0 ? (x[3] | nd[0]) : 0u) | (t1 ? (x[5] | nd[1]) : 0u);
+            const hw sth = dev ? 0u : (x[0] | x[1]), std_ = dev ? (x[0] | x[1]) : 0u;
             vh = mh & ~sth & vm;
             vd = md & ~std_ & vm;
         };
@@ -1036,28 +1060,28 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             x[2] = erowu(c.eag_h, e0); x[3] = erowu(c.eag_d, e0); x[4] = erowu(c.both, e0);
             x[5] = erowu(c.eag_h, e1); x[6] = erowu(c.eag_d, e1); x[7] = erowu(c.both, e1);
         };
-        auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd, int sweep,
-                        int g, u64& vh, u64& vd) {
+        auto comp = [&](int b, const Rec& r, const hw* x, const hw* nh, const hw* nd, hw ph, hw pd, int sweep,
+                        int g, hw& vh, hw& vd) {
             if (r.meta & REC_ENTRY) { vh = 0; vd = 0; return; }
-            u64 uh, ud, sth, std_;
+            hw uh, ud, sth, std_;
             use_wr(b, r, x[0], x[1], uh, ud, sth, std_);
             const int cnt = (int)(r.meta & REC_COUNT);
-            u64 allh = ~0ull, alld = ~0ull, anyh = 0, anyd = 0;
+            hw allh = ~0u, alld = ~0u, anyh = 0, anyd = 0;
             for (int j = 0; j < cnt; ++j) {
                 int p; uint32_t e;
                 nbr_f(r, j, p, e);
-                u64 gh, gd, bo, sh, sd;
+                hw gh, gd, bo, sh, sd;
                 if (j < 2) {
                     gh = j ? x[5] : x[2]; gd = j ? x[6] : x[3]; bo = j ? x[7] : x[4];
                     sh = j ? nh[1] : nh[0]; sd = j ? nd[1] : nd[0];
                 }
                 else {
                     gh = settle(erow(c.eag_h, e)); gd = settle(erow(c.eag_d, e)); bo = settle(erow(c.both, e));
-                    extra(S, b, p, sweep, g, 0ull, ph, pd, sh, sd);
+                    extra(S, b, p, sweep, g, 0u, ph, pd, sh, sd);
                 }
-                const u64 le = (e & 0x80000000u) ? ~0ull : 0ull;
-                const u64 lh = gh | sh, ld = gd | sd;
-                const u64 lph = lh & ~le, lpd = ld & ~le;
+                const hw le = (e & 0x80000000u) ? ~0u : 0u;
+                const hw lh = gh | sh, ld = gd | sd;
+                const hw lph = lh & ~le, lpd = ld & ~le;
                 allh &= lph | bo | (lh & le);
                 alld &= lpd | bo | (ld & le);
                 anyh |= lph;
@@ -1067,23 +1091,23 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             vd = alld & anyd & vm & ~std_;
         };
         // (per edge, (L & ~LE) | N' = L | BOTH whatever LE is; only the OR term skips loop entries)
-        auto fast = [&](const u64* x, const u64* nh, const u64* nd, uint32_t fl, u64& vh, u64& vd) {
+        auto fast = [&](const hw* x, const hw* nh, const hw* nd, uint32_t fl, hw& vh, hw& vd) {
             const bool dev = fl & DF_DEV;
             const bool p0 = fl & 3u, p1 = (fl >> 2) & 3u;
             if (p0 && !p1) {
                 // one predecessor: its term is both the AND and (unless the edge enters a loop) the OR
-                const u64 l0h = x[2] | nh[0], l0d = x[3] | nd[0], st = x[0] | x[1];
-                const u64 keep = (fl & DF_LE0) ? 0ull : vm;
-                vh = l0h & keep & (dev ? ~0ull : ~st);
-                vd = l0d & keep & (dev ? ~st : ~0ull);
+                const hw l0h = x[2] | nh[0], l0d = x[3] | nd[0], st = x[0] | x[1];
+                const hw keep = (fl & DF_LE0) ? 0u : vm;
+                vh = l0h & keep & (dev ? ~0u : ~st);
+                vd = l0d & keep & (dev ? ~st : ~0u);
                 return;
             }
-            const u64 l0h = x[2] | nh[0], l0d = x[3] | nd[0], l1h = x[5] | nh[1], l1d = x[6] | nd[1];
-            const u64 allh = (p0 ? (l0h | x[4]) : ~0ull) & (p1 ? (l1h | x[7]) : ~0ull);
-            const u64 alld = (p0 ? (l0d | x[4]) : ~0ull) & (p1 ? (l1d | x[7]) : ~0ull);
+            const hw l0h = x[2] | nh[0], l0d = x[3] | nd[0], l1h = x[5] | nh[1], l1d = x[6] | nd[1];
+            const hw allh = (p0 ? (l0h | x[4]) : ~0u) & (p1 ? (l1h | x[7]) : ~0u);
+            const hw alld = (p0 ? (l0d | x[4]) : ~0u) & (p1 ? (l1d | x[7]) : ~0u);
             const bool a0 = p0 && !(fl & DF_LE0), a1 = p1 && !(fl & DF_LE1);
-            const u64 anyh = (a0 ? l0h : 0ull) | (a1 ? l1h : 0ull), anyd = (a0 ? l0d : 0ull) | (a1 ? l1d : 0ull);
-            const u64 sth = dev ? 0ull : (x[0] | x[1]), std_ = dev ? (x[0] | x[1]) : 0ull;
+            const hw anyh = (a0 ? l0h : 0u) | (a1 ? l1h : 0u), anyd = (a0 ? l0d : 0u) | (a1 ? l1d : 0u);
+            const hw sth = dev ? 0u : (x[0] | x[1]), std_ = dev ? (x[0] | x[1]) : 0u;
             vh = allh & anyh & vm & ~sth;
             vd = alld & anyd & vm & ~std_;
         };
@@ -1096,24 +1120,24 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // the state reuses the eager-validity rows.
     if constexpr (PH == PH_AVF) {
         const Rows S = rows_of(c.aveout_h, c.aveout_d, 2);
-        const u64 init = ~0ull & vm;
+        const hw init = vm;
         // x0/x1 = INS_ENTRY, x2 = W, x3..x6 = INS_EDGE_H/D of the two inline in-edges
         auto pre = [&](int b, uint32_t e0, uint32_t e1, const GAS u64** x) {
             x[0] = rowu(c.ie_h, b); x[1] = rowu(c.ie_d, b); x[2] = rowu(c.W, b);
             x[3] = erowu(c.ig_h, e0); x[4] = erowu(c.ig_d, e0);
             x[5] = erowu(c.ig_h, e1); x[6] = erowu(c.ig_d, e1);
         };
-        auto comp = [&](int b, const Rec& r, const u64* x, const u64* nh, const u64* nd, u64 ph, u64 pd, int sweep,
-                        int g, u64& vh, u64& vd) {
-            u64 ih, id;
+        auto comp = [&](int b, const Rec& r, const hw* x, const hw* nh, const hw* nd, hw ph, hw pd, int sweep,
+                        int g, hw& vh, hw& vd) {
+            hw ih, id;
             if (r.meta & REC_ENTRY) { ih = vec(c.ev_h); id = vec(c.ev_d); }
             else {
                 const int cnt = (int)(r.meta & REC_COUNT);
-                u64 mh = ~0ull, md = ~0ull;
+                hw mh = ~0u, md = ~0u;
                 for (int j = 0; j < cnt; ++j) {
                     int p; uint32_t e;
                     nbr_f(r, j, p, e);
-                    u64 gh, gd, sh, sd;
+                    hw gh, gd, sh, sd;
                     if (j < 2) {
                         gh = j ? x[5] : x[3]; gd = j ? x[6] : x[4]; sh = j ? nh[1] : nh[0]; sd = j ? nd[1] : nd[0];
                     }
@@ -1129,16 +1153,16 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             }
             valid_out(b, r, ih & vm, id & vm, x[2], vh, vd);
         };
-        auto fast = [&](const u64* x, const u64* nh, const u64* nd, uint32_t fl, u64& vh, u64& vd) {
+        auto fast = [&](const hw* x, const hw* nh, const hw* nd, uint32_t fl, hw& vh, hw& vd) {
             const bool dev = fl & DF_DEV;
             const bool p0 = fl & 3u, p1 = (fl >> 2) & 3u;
-            const u64 mh = (p0 ? (nh[0] | x[3]) : ~0ull) & (p1 ? (nh[1] | x[5]) : ~0ull);
-            const u64 md = (p0 ? (nd[0] | x[4]) : ~0ull) & (p1 ? (nd[1] | x[6]) : ~0ull);
-            const u64 ih = (x[0] | mh) & vm, id = (x[1] | md) & vm, wr = x[2];
+            const hw mh = (p0 ? (nh[0] | x[3]) : ~0u) & (p1 ? (nh[1] | x[5]) : ~0u);
+            const hw md = (p0 ? (nd[0] | x[4]) : ~0u) & (p1 ? (nd[1] | x[6]) : ~0u);
+            const hw ih = (x[0] | mh) & vm, id = (x[1] | md) & vm, wr = x[2];
             vh = (dev ? (ih & ~wr) : (ih | wr)) & vm;
             vd = (dev ? (id | wr) : (id & ~wr)) & vm;
         };
-        run_phase(S, init, ~0ull, pre, fast, comp);
+        run_phase(S, vm64, ~0ull, pre, fast, comp);
     }
 }
 
@@ -1319,8 +1343,8 @@ __device__ __forceinline__ void tile_phase(const DevCfg& c, const Tile& tl, u64*
         ctl->in_ready = 0;
     }
     __syncthreads();
-    // lanes past LANES hold no word and stay out (the helper's next LANES copy high halves)
-    if (!__builtin_amdgcn_readfirstlane(ctl->skip) && (threadIdx.x & 63) < (threadIdx.x >= 64 ? 2 * LANES : LANES))
+    // lanes past 2 LANES hold no word and stay out
+    if (!__builtin_amdgcn_readfirstlane(ctl->skip) && (threadIdx.x & 63) < 2 * LANES)
         solve_phase<PH>(c, tl.s0, tl.nw, tl.fslot, lds, ring_slots);
     __syncthreads();
 }
