@@ -270,15 +270,16 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
 // --------------------------------------------------------------------------
 // One workgroup of two wavefronts solves one tile: a CFG and a run of up to
 // TILE_WORDS (15) consecutive 64-bit words of its variable axis; lanes 0 to
-// LANES - 1 (16) of each wavefront take part.  Lane l owns word s0 + l
-// of every row; in the two phases that compute the CFG's reachability facts,
+// 2 LANES - 1 (32) of each wavefront take part.  Lanes l and l + LANES own the
+// low and high halves of word s0 + l of every row; in the two phases that
+// compute the CFG's reachability facts,
 // lane nw (the flag lane) carries them as a pseudo-variable word whose inputs
 // are synthesised so that the same equations compute them:
 //   next use, host channel, bit 0 : the block reaches EXIT
 //   next use, device channel, bit 1: a DEVICE block is reachable from here
 //   eager validity, host channel, bit 0: the block is NOT reached from ENTRY
 //   eager validity, host channel, bit 1: no DEVICE block reaches the block
-// Lanes past the tile (below LANES) shadow word s0 (same inputs, same
+// Lanes past the tile (below LANES, and their high partners) shadow word s0 (same inputs, same
 // results), so the walk has no lane divergence and everything about a step
 // except its data is wave-uniform.  Narrow tiles keep the LDS of a workgroup
 // small (25-40 KiB with the default ring), so that several tiles are resident
@@ -421,15 +422,14 @@ struct Rows {
     GAS u64* h;
     GAS u64* d;
     int str;
-    __device__ __forceinline__ u64 ldh(int b) const { return ld_fresh(h + (size_t)b * str); }
-    __device__ __forceinline__ u64 ldd(int b) const { return ld_fresh(d + (size_t)b * str); }
     // the low (hi = false) or high half of the word
     __device__ __forceinline__ uint32_t ldh32(int b, bool hi) const { return ld_half(h + (size_t)b * str, hi); }
     __device__ __forceinline__ uint32_t ldd32(int b, bool hi) const { return ld_half(d + (size_t)b * str, hi); }
-    __device__ __forceinline__ void st(int b, u64 x, u64 y) const
+    // store the low (hi = false) or high halves of the words
+    __device__ __forceinline__ void st32(int b, bool hi, uint32_t x, uint32_t y) const
     {
-        h[(size_t)b * str] = x;
-        d[(size_t)b * str] = y;
+        reinterpret_cast<GAS uint32_t*>(h + (size_t)b * str)[hi ? 1 : 0] = x;
+        reinterpret_cast<GAS uint32_t*>(d + (size_t)b * str)[hi ? 1 : 0] = y;
     }
 };
 
@@ -444,16 +444,14 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     constexpr int NI = NX + 2;        // inputs of a step: the phase's own and the first far neighbour (h, d)
     constexpr int IR = in_ring(PH);   // steps whose inputs the helper keeps ready
     // Lanes 0 .. LANES - 1 of both wavefronts own the tile's words, lanes LANES .. 2 LANES - 1
-    // (`hi`) the same words again.  The compute wavefront works on half-words: lane ln holds the
-    // low 32 bits of word s0 + ln, lane ln + LANES the high 32 bits, so that a bitwise operation
-    // is one instruction and reading a word from LDS one 32-lane access.  In the helper the high
-    // lanes only copy the high halves of input words; its other per-lane LDS writes and its
-    // global stores are made by the low lanes, a 64-bit word each.
+    // (`hi`) the same words again: both wavefronts work on half-words, lane ln holding the low
+    // 32 bits of word s0 + ln and lane ln + LANES the high 32 bits, so that a bitwise operation
+    // is one instruction and a word's LDS access, copy or store one 32-lane access.
     const int lane = threadIdx.x & 63;
     const int ln = lane & (LANES - 1);
     const bool hi = lane >= LANES;
     const int l32 = lane & (2 * LANES - 1);   // the lane's half-word in the split LDS layout
-    typedef uint32_t hw;                      // a half-word (compute wavefront)
+    typedef uint32_t hw;                      // a half-word
     // a constant of the flag lane (bits 0-1: the low half)
     auto lo = [&](uint32_t v) -> hw { return hi ? 0u : v; };
     const bool helper = threadIdx.x >= 64;
@@ -471,7 +469,6 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     const int IN_OFF = RING_OFF + RS * STATE_BYTES;                       // IR steps of NI input words
     const int DESC_OFF = IN_OFF + IR * NI * WORD_BYTES;                   // IR step descriptors
     const int IDENT_OFF = DESC_OFF + IR * 16;                             // one state of identity words
-    u64* iring = reinterpret_cast<u64*>(lds8 + IN_OFF);
     int4* dring = reinterpret_cast<int4*>(lds8 + DESC_OFF);
     // valid-variable mask of the lane's word (shadow lanes share word s0's; the flag lane uses bits 0-1)
     const u64 vm64 = flg ? 3ull : ((w == wd - 1 && (c.nv & 63)) ? ((1ull << (c.nv & 63)) - 1ull) : ~0ull);
@@ -486,7 +483,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     const size_t wo = (size_t)w;
     // data arrays of a CFG without variables may be empty: loads then read a flag word instead
     auto arr = [&](const u64* a) -> const GAS u64* { return wd ? G(a) : (const GAS u64*)FLG; };
-    // the lane's half of a word (compute wavefront)
+    // the lane's half of a word
     auto half = [&](const GAS u64* p) -> hw { return reinterpret_cast<const GAS uint32_t*>(p)[hi ? 1 : 0]; };
     auto row = [&](const u64* a, int b) -> hw { return half(arr(a) + (size_t)b * wd + wo); };
     // start of row b (wave-uniform) and the byte of the lane's half-word within a row
@@ -501,27 +498,15 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         else { r.h = G(h) + wo; r.d = G(d) + wo; r.str = wd; }
         return r;
     };
-    // the word at LDS byte offset `at` (split layout), this lane's (helper)
-    auto w_get = [&](int at) -> u64 {
-        const uint32_t* q = reinterpret_cast<const uint32_t*>(lds8 + at) + ln;
-        return (u64)q[0] | ((u64)q[LANES] << 32);
-    };
-    auto w_put = [&](int at, u64 v) {   // (low lanes)
-        uint32_t* q = reinterpret_cast<uint32_t*>(lds8 + at) + ln;
-        q[0] = (uint32_t)v;
-        q[LANES] = (uint32_t)(v >> 32);
-    };
-    auto ring_at = [&](int g) -> int { return RING_OFF + (g & (RS - 1)) * STATE_BYTES; };   // state of step g
-    auto slot_h = [&](int g) -> u64 { return w_get(ring_at(g)); };
-    auto slot_d = [&](int g) -> u64 { return w_get(ring_at(g) + WORD_BYTES); };
-    // input k of step g: LANES low halves, then LANES high halves
-    uint32_t* iring32 = reinterpret_cast<uint32_t*>(iring);
-    auto in32 = [&](int g, int k) -> uint32_t* { return iring32 + ((size_t)(g & (IR - 1)) * NI + k) * (2 * LANES); };
-    // the same as half-words (compute wavefront)
+    // the lane's half of the word at LDS byte offset `at` (split layout)
     auto c_get = [&](int at) -> hw { return reinterpret_cast<const uint32_t*>(lds8 + at)[l32]; };
     auto c_put = [&](int at, hw v) { reinterpret_cast<uint32_t*>(lds8 + at)[l32] = v; };
+    auto ring_at = [&](int g) -> int { return RING_OFF + (g & (RS - 1)) * STATE_BYTES; };   // state of step g
     auto cslot_h = [&](int g) -> hw { return c_get(ring_at(g)); };
     auto cslot_d = [&](int g) -> hw { return c_get(ring_at(g) + WORD_BYTES); };
+    // input k of step g: LANES low halves, then LANES high halves
+    uint32_t* iring32 = reinterpret_cast<uint32_t*>(lds8 + IN_OFF);
+    auto in32 = [&](int g, int k) -> uint32_t* { return iring32 + ((size_t)(g & (IR - 1)) * NI + k) * (2 * LANES); };
     auto cin = [&](int g, int k) -> hw { return in32(g, k)[l32]; };
 
     // neighbour j of a record (j >= 2 from the CSR); edge id with LOOP_ENTRY in bit 31
@@ -558,7 +543,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     auto far_step = [&](uint32_t x, int w, int st) -> int {
         return ((x & SF_BACK) && st < nb) ? -1 : st - w;
     };
-    auto helper_loop = [&](const Rows& S, u64 init, auto&& pre) {
+    auto helper_loop = [&](const Rows& S, u64 init64, auto&& pre) {
+        const hw init = (hw)(hi ? init64 >> 32 : init64);
         int gf = 0, fi = 0;   // next step to store and its index within the sweep
         int pf = 0, pi = 0;   // next step whose inputs are loaded and its index within the sweep
         int spins = 0;
@@ -599,12 +585,10 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             for (u64 cm = __ballot(lane < n && (fl & SF_FAR) && (u < 0 || u >= gf0)); cm; cm &= cm - 1) {
                 const int j = (int)__builtin_ctzll(cm);
                 const int uj = __builtin_amdgcn_readlane(u, j);
-                if (!hi) {
-                    const u64 h = uj < 0 ? init : slot_h(uj), d = uj < 0 ? init : slot_d(uj);
-                    uint32_t* qq = in32(pf + j, NX) + ln;
-                    qq[0] = (uint32_t)h; qq[LANES] = (uint32_t)(h >> 32);
-                    qq[2 * LANES] = (uint32_t)d; qq[3 * LANES] = (uint32_t)(d >> 32);
-                }
+                const hw h = uj < 0 ? init : cslot_h(uj), d = uj < 0 ? init : cslot_d(uj);
+                uint32_t* qq = in32(pf + j, NX) + l32;
+                qq[0] = h;
+                qq[2 * LANES] = d;
             }
             // nothing to store and nothing that can be loaded yet (the prefetch may also be waiting
             // for a step the compute wavefront will never reach, after its last sweep)
@@ -624,13 +608,13 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             spins = 0;
             // results of steps gf .. fend - 1 to the rows, eight ring reads in flight at a time
             while (gf < fend) {
-                u64 h[8], d[8];
+                hw h[8], d[8];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) { h[t] = slot_h(gf + t); d[t] = slot_d(gf + t); }
+                for (int t = 0; t < 8; ++t) { h[t] = cslot_h(gf + t); d[t] = cslot_d(gf + t); }
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
                     if (gf < fend) {
-                        if (act && !hi) S.st(blk(fi), h[t], d[t]);
+                        if (act) S.st32(blk(fi), hi, h[t], d[t]);
                         fi = fi + 1 == nb ? 0 : fi + 1;
                         ++gf;
                     }
