@@ -123,6 +123,14 @@ def lib():
         if _handle is None:
             if not os.path.exists(_SO):
                 raise OmpdNotBuilt("libompd.so is not built (run __graft_entry__.build())")
+            # torch ships its own HIP runtime under the same library name: it has to be loaded
+            # before libompd, which then binds to it.  In the other order the process holds the
+            # system runtime first and torch, when it is used later (device buffers, streams),
+            # finds no GPU.
+            try:
+                import torch  # noqa: F401
+            except ImportError:
+                pass
             L = ctypes.CDLL(_SO)
             P = ctypes.POINTER
             L.ompd_ctx_create.argtypes = [P(_vp), ctypes.c_int, ctypes.c_uint64]
