@@ -202,3 +202,32 @@ def test_ring_sizes_match_oracle(ctx):
         got = ctx.analyze_batch(cfgs, flags=ompd.F_RING_SLOTS(rs))
         for i, cfg in enumerate(cfgs):
             assert_same(cfg, got[i], refs[i], "ring %d #%d" % (rs, i))
+
+
+def test_config3_batch_resident_sampled(ctx):
+    """Config 3 at full size in the launch configuration the benchmark times:
+    the 4,096-CFG batch resident in device memory under one plan, run twice
+    (the second run overwrites the first run's outputs).  Every CFG reports
+    success, and every output of a sample of CFGs (the most blocks, the
+    fewest, the most variables, the fewest, the most block words, and seeded
+    random picks) equals the oracle's."""
+    import torch
+    from paper_2406_13881_amd.resident import ResidentBatch
+    cfgs = synth.c3(4096, threads=8)
+    nb = np.array([c.n_blocks for c in cfgs])
+    nv = np.array([c.n_vars for c in cfgs])
+    picks = {int(nb.argmax()), int(nb.argmin()), int(nv.argmax()), int(nv.argmin()),
+             int((nb * ((nv + 63) // 64)).argmax())}
+    picks |= set(int(i) for i in np.random.default_rng(2406).choice(len(cfgs), 8, replace=False))
+    _print("c3 batch: %d CFGs, %d blocks, checking %s" % (len(cfgs), int(nb.sum()), sorted(picks)))
+    rb = ResidentBatch(ctx, cfgs)
+    try:
+        stream = torch.cuda.current_stream().cuda_stream
+        rb.run(stream)
+        rb.run(stream)
+        torch.cuda.synchronize()
+        assert (rb.plan.status() == 0).all()
+        for i in sorted(picks):
+            assert_same(cfgs[i], rb.fetch(i), oracle.solve(cfgs[i]), "c3 #%d" % i)
+    finally:
+        rb.close()
