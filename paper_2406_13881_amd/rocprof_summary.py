@@ -2,6 +2,7 @@
 and HBM traffic from the FETCH_SIZE / WRITE_SIZE counters).
 
     python -m paper_2406_13881_amd.rocprof_summary trace DB
+    python -m paper_2406_13881_amd.rocprof_summary counters DB [DB ...]
     python -m paper_2406_13881_amd.rocprof_summary traffic --fetch DB --write DB \\
         --cal-fetch DB --cal-write DB --cal-bytes N --json OUT.json --workload TEXT
 
@@ -45,6 +46,19 @@ def counter_per_dispatch(db_path, counter):
     return {k: (len(d), sum(d.values()) / len(d)) for k, d in agg.items()}
 
 
+def counters(db_paths, prefix="ompd_k_"):
+    """{kernel: {counter: average per dispatch}} over every counter of the given runs."""
+    out = collections.defaultdict(dict)
+    for path in db_paths:
+        db = sqlite3.connect(path)
+        names = [r[0] for r in db.execute("select distinct counter_name from counters_collection")]
+        for c in names:
+            for k, (_n, avg) in counter_per_dispatch(path, c).items():
+                if k.startswith(prefix):
+                    out[k.split("(")[0]][c] = avg
+    return dict(out)
+
+
 def traffic(fetch_db, write_db, cal_fetch_db, cal_write_db, cal_bytes, prefix="ompd_k_"):
     fetch = counter_per_dispatch(fetch_db, "FETCH_SIZE")
     write = counter_per_dispatch(write_db, "WRITE_SIZE")
@@ -69,6 +83,8 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("trace")
     t.add_argument("db")
+    c = sub.add_parser("counters")
+    c.add_argument("dbs", nargs="+")
     f = sub.add_parser("traffic")
     for a in ("--fetch", "--write", "--cal-fetch", "--cal-write", "--json", "--workload"):
         f.add_argument(a, required=True)
@@ -79,6 +95,14 @@ def main(argv=None):
         print("|---|---|---|")
         for k, (n, avg) in sorted(kernel_durations(args.db).items(), key=lambda kv: -kv[1][1]):
             print("| %s | %d | %.3f |" % (k[:60], n, avg / 1e3))
+        return 0
+    if args.cmd == "counters":
+        per = counters(args.dbs)
+        cols = sorted({n for v in per.values() for n in v})
+        print("| kernel | " + " | ".join(cols) + " |")
+        print("|---|" + "---|" * len(cols))
+        for k in sorted(per):
+            print("| %s | " % k + " | ".join("%.4g" % per[k].get(n, float("nan")) for n in cols) + " |")
         return 0
     rec = traffic(args.fetch, args.write, args.cal_fetch, args.cal_write, args.cal_bytes)
     rec = dict({"workload": args.workload,
