@@ -133,6 +133,11 @@ struct ServingState {
     int64_t admitted = 0, completed = 0;
     int max_steps = 4;
     int max_step_reqs = 256;
+    // While another step runs, a new one waits until min_step_reqs requests are pending or the
+    // oldest has waited max_wait_ns: fewer, larger steps keep the few hardware queues busy with
+    // many tiles each instead of a request or two.
+    int min_step_reqs = 32;
+    int64_t max_wait_ns = 20 * 1000 * 1000;
     size_t max_reqs = 4096;
 };
 
@@ -143,13 +148,16 @@ static void launcher_main(ServingState* S)
     (void)hipSetDevice(S->ctx->device);
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
-        S->cv_launch.wait(lk, [&] {
+        auto ready = [&] {
             if (S->stop) return true;
             if (S->pending.empty()) return false;
-            for (int b : S->stream_busy)
-                if (!b) return true;
-            return false;
-        });
+            int n_free = 0, n_busy = 0;
+            for (int b : S->stream_busy) ++(b ? n_busy : n_free);
+            if (n_free == 0) return false;
+            if (n_busy == 0 || (int)S->pending.size() >= S->min_step_reqs) return true;
+            return now_ns() - S->pending.front()->t_submit >= S->max_wait_ns;
+        };
+        while (!ready()) S->cv_launch.wait_for(lk, std::chrono::milliseconds(1));
         if (S->stop && S->pending.empty()) break;
         if (S->stop) break;
         int si = -1;
