@@ -69,10 +69,11 @@ constexpr uint32_t REC_COUNT = 0x00FFFFFFu;
 constexpr uint32_t REC_ENTRY = 1u << 24, REC_EXIT = 1u << 25, REC_DEV = 1u << 26, REC_CALL = 1u << 27;
 
 // A tile: one CFG and a run of its 64-bit variable words, solved by one
-// workgroup (a compute wavefront with one lane per word plus the flag
-// lane, and a helper wavefront that stores its results).
-// Lanes of the compute wavefront that hold words (the rest idle); LDS
-// holds LANES lanes of every word.
+// workgroup (a compute wavefront with two lanes per word, its low and high
+// halves, plus the flag lane's two, and a helper wavefront that feeds it and
+// stores its results).
+// Words per tile slot (LANES, one of them for the flag lane); lane l and
+// l + LANES hold the halves of word l, and LDS holds LANES words of every row.
 constexpr int LANES = 16;
 constexpr int TILE_WORDS = LANES - 1;
 constexpr int WORD_BYTES = 8 * LANES;        // one word of every lane in LDS

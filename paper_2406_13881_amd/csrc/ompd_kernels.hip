@@ -460,8 +460,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     const bool dat = ln < nw, flg = with_flags && (ln == nw || nw == 0), act = dat || flg;
     const int w = s0 + (dat ? ln : 0);
     Ctl* ctl = reinterpret_cast<Ctl*>(lds);
-    // Every 64-bit per-lane word in LDS is stored split: LANES low halves, then LANES high
-    // halves (WORD_BYTES); a state (h, d) is two such words (STATE_BYTES).
+    // Every row's LANES words in LDS are stored split: LANES low halves, then LANES high
+    // halves (WORD_BYTES), which is lane l32's half-word at index l32; a state (h, d) is two
+    // such rows (STATE_BYTES).
     char* lds8 = reinterpret_cast<char*>(lds);
     // the same as a wave-uniform 32-bit LDS address (scalar registers)
     const uint32_t lds3 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(size_t)(LDS3 char*)lds8);
