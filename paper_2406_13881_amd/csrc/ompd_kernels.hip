@@ -63,7 +63,16 @@ constexpr uint32_t DF_LE1 = 1u << 7;    // edge of neighbour 1 is a loop entry
 constexpr uint32_t SF_FAR = 1u << 8;    // one of the first two neighbours is far (step entries only)
 constexpr uint32_t SF_BACK = 1u << 9;   // ... and not visited yet in the sweep
 constexpr uint32_t SF_ONE = 1u << 10;   // at most one neighbour: no rows of a second edge are read
-constexpr uint32_t DF_MASK = 0xFFu;     // the bits a step descriptor carries
+constexpr uint32_t DF_MASK = 0xFFu;     // the bits a step descriptor carries from the step entry
+// bits the helper adds to a step descriptor, so that the transfer functions select with masks
+// (one scalar bit-field extract each) instead of compares
+constexpr int DD_LAST0 = 8, DD_LAST1 = 9;   // neighbour j is the block computed last (registers)
+constexpr int DD_P0 = 10, DD_P1 = 11;       // neighbour j exists
+constexpr int DD_A0 = 12, DD_A1 = 13;       // ... and its edge does not enter a loop
+constexpr int DD_DEV = 5;                   // the bit of DF_DEV
+static_assert(DF_DEV == 1u << DD_DEV && DF_MASK < 1u << DD_LAST0, "descriptor bits");
+// all ones if bit `bit` of the wave-uniform word fl is set, else zero
+__device__ __forceinline__ uint32_t fmask(uint32_t fl, int bit) { return (uint32_t)((int32_t)(fl << (31 - bit)) >> 31); }
 // A step entry (two int4, one per walk position): x flags; y the ring distances of neighbours
 // 0 and 1 (bits 0-7, 8-15; flag code 2 only); z the far neighbour; w how many steps before the
 // current one its state was computed (this sweep's or, when SF_BACK, the previous sweep's); then
@@ -580,7 +589,11 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 const uint32_t k0 = fl & 3u, k1 = (fl >> 2) & 3u;
                 const int loc0 = k0 == 2 ? ring_at(st - (ev.y & 0xFF)) : k0 == 3 ? far_at : IDENT_OFF;
                 const int loc1 = k1 == 2 ? ring_at(st - ((ev.y >> 8) & 0xFF)) : k1 == 3 ? far_at : IDENT_OFF;
-                dring[st & (IR - 1)] = make_int4((int)(fl & DF_MASK), loc0, loc1, 0);
+                uint32_t dd = fl & DF_MASK;
+                dd |= (k0 == 1 ? 1u << DD_LAST0 : 0u) | (k1 == 1 ? 1u << DD_LAST1 : 0u);
+                dd |= (k0 ? 1u << DD_P0 : 0u) | (k1 ? 1u << DD_P1 : 0u);
+                dd |= (k0 && !(fl & DF_LE0) ? 1u << DD_A0 : 0u) | (k1 && !(fl & DF_LE1) ? 1u << DD_A1 : 0u);
+                dring[st & (IR - 1)] = make_int4((int)dd, loc0, loc1, 0);
             }
             // far states from the ring (computed, not stored yet) or the initial value
             for (u64 cm = __ballot(lane < n && (fl & SF_FAR) && (u < 0 || u >= gf0)); cm; cm &= cm - 1) {
@@ -735,9 +748,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             hw vh_[2], vd_[2];
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                const bool last = ((fl >> (2 * j)) & 3u) == 1u;
-                vh_[j] = last ? ph : nh[j];
-                vd_[j] = last ? pd : nd[j];
+                const hw last = fmask(fl, DD_LAST0 + j);
+                vh_[j] = (ph & last) | (nh[j] & ~last);
+                vd_[j] = (pd & last) | (nd[j] & ~last);
             }
             hw vh, vd;
             if (!(fl & DF_SLOW)) fast(x, vh_, vd_, fl, vh, vd);
@@ -890,11 +903,11 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             vd = (dev ? rr : 0u) | (~ww & od);
         };
         auto fast = [&](const hw* x, const hw* nh, const hw* nd, uint32_t fl, hw& vh, hw& vd) {
-            const bool dev = fl & DF_DEV;
-            const hw rr = flg ? lo(2) : x[0], ww = flg ? (dev ? lo(2) : 0u) : x[1];
+            const hw dev = fmask(fl, DD_DEV);
+            const hw rr = flg ? lo(2) : x[0], ww = flg ? (lo(2) & dev) : x[1];
             const hw oh = nh[0] | nh[1], od = nd[0] | nd[1];
-            vh = (dev ? 0u : rr) | (~ww & oh);
-            vd = (dev ? rr : 0u) | (~ww & od);
+            vh = (rr & ~dev) | (~ww & oh);
+            vd = (rr & dev) | (~ww & od);
         };
         run_phase(S, 0ull, 0ull, pre, fast, comp);
         return;
@@ -936,11 +949,11 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             valid_out(b, r, ih & vm, id & vm, flg ? ((r.meta & REC_DEV) ? lo(2) : 0u) : x[2], vh, vd);
         };
         auto fast = [&](const hw* x, const hw* nh, const hw* nd, uint32_t fl, hw& vh, hw& vd) {
-            const bool dev = fl & DF_DEV;
+            const hw dev = fmask(fl, DD_DEV);
             const hw ih = ((flg ? 0u : x[0]) | (nh[0] & nh[1])) & vm, id = ((flg ? 0u : x[1]) | (nd[0] & nd[1])) & vm;
-            const hw wr = flg ? (dev ? lo(2) : 0u) : x[2];
-            vh = (dev ? (ih & ~wr) : (ih | wr)) & vm;
-            vd = (dev ? (id | wr) : (id & ~wr)) & vm;
+            const hw wr = flg ? (lo(2) & dev) : x[2];
+            vh = ((ih & ~wr & dev) | ((ih | wr) & ~dev)) & vm;
+            vd = (((id | wr) & dev) | (id & ~wr & ~dev)) & vm;
         };
         if (!run_phase(S, vm64, ~0ull, pre, fast, comp)) return;
         if (helper) return;
@@ -1019,13 +1032,12 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         };
         // (the stop masks of an ordinary block: its own accesses)
         auto fast = [&](const hw* x, const hw* nh, const hw* nd, uint32_t fl, hw& vh, hw& vd) {
-            const bool dev = fl & DF_DEV;
-            const bool t0 = (fl & 3u) && !(fl & DF_LE0), t1 = ((fl >> 2) & 3u) && !(fl & DF_LE1);
-            const hw mh = (t0 ? (x[2] | nh[0]) : 0u) | (t1 ? (x[4] | nh[1]) : 0u);
-            const hw md = (t0 ? (x[3] | nd[0]) : 0u) | (t1 ? (x[5] | nd[1]) : 0u);
-            const hw sth = dev ? 0u : (x[0] | x[1]), std_ = dev ? (x[0] | x[1]) : 0u;
-            vh = mh & ~sth & vm;
-            vd = md & ~std_ & vm;
+            const hw dev = fmask(fl, DD_DEV), t0 = fmask(fl, DD_A0), t1 = fmask(fl, DD_A1);
+            const hw mh = ((x[2] | nh[0]) & t0) | ((x[4] | nh[1]) & t1);
+            const hw md = ((x[3] | nd[0]) & t0) | ((x[5] | nd[1]) & t1);
+            const hw st = x[0] | x[1];
+            vh = mh & ~(st & ~dev) & vm;
+            vd = md & ~(st & dev) & vm;
         };
         run_phase(S, 0ull, 0ull, pre, fast, comp);
         return;
@@ -1077,24 +1089,21 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         };
         // (per edge, (L & ~LE) | N' = L | BOTH whatever LE is; only the OR term skips loop entries)
         auto fast = [&](const hw* x, const hw* nh, const hw* nd, uint32_t fl, hw& vh, hw& vd) {
-            const bool dev = fl & DF_DEV;
-            const bool p0 = fl & 3u, p1 = (fl >> 2) & 3u;
-            if (p0 && !p1) {
+            const hw dev = fmask(fl, DD_DEV), a0 = fmask(fl, DD_A0), st = x[0] | x[1];
+            const hw l0h = x[2] | nh[0], l0d = x[3] | nd[0];
+            if ((fl & (3u << DD_P0)) == (1u << DD_P0)) {
                 // one predecessor: its term is both the AND and (unless the edge enters a loop) the OR
-                const hw l0h = x[2] | nh[0], l0d = x[3] | nd[0], st = x[0] | x[1];
-                const hw keep = (fl & DF_LE0) ? 0u : vm;
-                vh = l0h & keep & (dev ? ~0u : ~st);
-                vd = l0d & keep & (dev ? ~st : ~0u);
+                vh = l0h & a0 & vm & ~(st & ~dev);
+                vd = l0d & a0 & vm & ~(st & dev);
                 return;
             }
-            const hw l0h = x[2] | nh[0], l0d = x[3] | nd[0], l1h = x[5] | nh[1], l1d = x[6] | nd[1];
-            const hw allh = (p0 ? (l0h | x[4]) : ~0u) & (p1 ? (l1h | x[7]) : ~0u);
-            const hw alld = (p0 ? (l0d | x[4]) : ~0u) & (p1 ? (l1d | x[7]) : ~0u);
-            const bool a0 = p0 && !(fl & DF_LE0), a1 = p1 && !(fl & DF_LE1);
-            const hw anyh = (a0 ? l0h : 0u) | (a1 ? l1h : 0u), anyd = (a0 ? l0d : 0u) | (a1 ? l1d : 0u);
-            const hw sth = dev ? 0u : (x[0] | x[1]), std_ = dev ? (x[0] | x[1]) : 0u;
-            vh = allh & anyh & vm & ~sth;
-            vd = alld & anyd & vm & ~std_;
+            const hw p0 = fmask(fl, DD_P0), p1 = fmask(fl, DD_P1), a1 = fmask(fl, DD_A1);
+            const hw l1h = x[5] | nh[1], l1d = x[6] | nd[1];
+            const hw allh = (l0h | x[4] | ~p0) & (l1h | x[7] | ~p1);
+            const hw alld = (l0d | x[4] | ~p0) & (l1d | x[7] | ~p1);
+            const hw anyh = (l0h & a0) | (l1h & a1), anyd = (l0d & a0) | (l1d & a1);
+            vh = allh & anyh & vm & ~(st & ~dev);
+            vd = alld & anyd & vm & ~(st & dev);
         };
         run_phase(S, 0ull, 0ull, pre, fast, comp);
         return;
@@ -1139,13 +1148,12 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             valid_out(b, r, ih & vm, id & vm, x[2], vh, vd);
         };
         auto fast = [&](const hw* x, const hw* nh, const hw* nd, uint32_t fl, hw& vh, hw& vd) {
-            const bool dev = fl & DF_DEV;
-            const bool p0 = fl & 3u, p1 = (fl >> 2) & 3u;
-            const hw mh = (p0 ? (nh[0] | x[3]) : ~0u) & (p1 ? (nh[1] | x[5]) : ~0u);
-            const hw md = (p0 ? (nd[0] | x[4]) : ~0u) & (p1 ? (nd[1] | x[6]) : ~0u);
+            const hw dev = fmask(fl, DD_DEV), p0 = fmask(fl, DD_P0), p1 = fmask(fl, DD_P1);
+            const hw mh = (nh[0] | x[3] | ~p0) & (nh[1] | x[5] | ~p1);
+            const hw md = (nd[0] | x[4] | ~p0) & (nd[1] | x[6] | ~p1);
             const hw ih = (x[0] | mh) & vm, id = (x[1] | md) & vm, wr = x[2];
-            vh = (dev ? (ih & ~wr) : (ih | wr)) & vm;
-            vd = (dev ? (id | wr) : (id & ~wr)) & vm;
+            vh = ((ih & ~wr & dev) | ((ih | wr) & ~dev)) & vm;
+            vd = (((id | wr) & dev) | (id & ~wr & ~dev)) & vm;
         };
         run_phase(S, vm64, ~0ull, pre, fast, comp);
     }
