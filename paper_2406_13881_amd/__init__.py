@@ -262,6 +262,43 @@ def _alloc_outputs(cfg, want: Sequence[str]) -> Dict[str, np.ndarray]:
     return out
 
 
+_RES_INDEX = {k: [f[0] for f in _Res._fields_].index(v) for k, v in _RES_FIELD.items()}
+
+
+def _alloc_outputs_many(cfgs: Sequence, want: Sequence[str], R) -> List[Dict[str, np.ndarray]]:
+    """Output arrays of many CFGs (as _alloc_outputs), one zeroed buffer per output with each
+    CFG's arrays as views into it; writes their addresses into the result structs R."""
+    n = len(cfgs)
+    nb = np.array([int(c.n_blocks) for c in cfgs], np.int64)
+    nv = np.array([int(c.n_vars) for c in cfgs], np.int64)
+    ne = np.array([int(np.asarray(c.succ_idx).shape[0]) for c in cfgs], np.int64)
+    wd = (nv + 63) // 64
+    words = np.frombuffer(R, dtype=np.uint64).reshape(len(R), ctypes.sizeof(_Res) // 8)
+    outs: List[Dict[str, np.ndarray]] = [dict() for _ in range(n)]
+    for k in want:
+        if k.startswith("ins_edge") or k not in ("var_kind", "after_dev", "before_dev"):
+            rows, dt = (ne if k.startswith("ins_edge") else nb), np.uint64
+            size = rows * wd
+        else:
+            rows, dt = (nv if k == "var_kind" else nb), np.uint8
+            size = rows
+        off = np.zeros(n + 1, np.int64)
+        np.cumsum(size, out=off[1:])
+        buf = np.zeros(max(int(off[-1]), 1), dt)
+        words[:n, _RES_INDEX[k]] = np.uint64(buf.ctypes.data) + (off[:n] * buf.itemsize).astype(np.uint64)
+        for i in range(n):
+            a = buf[off[i]:off[i + 1]]
+            outs[i][k] = a.reshape(int(rows[i]), int(wd[i])) if dt is np.uint64 else a
+    return outs
+
+
+def _sweeps_of(R, n: int) -> np.ndarray:
+    """[n, 6] int32 copy of the sweeps fields of the first n result structs."""
+    ints = np.frombuffer(R, dtype=np.int32).reshape(len(R), ctypes.sizeof(_Res) // 4)
+    at = _Res.sweeps.offset // 4
+    return ints[:n, at:at + 6].copy()
+
+
 def _res_struct(out: Dict[str, np.ndarray]) -> _Res:
     r = _Res()
     for k, a in out.items():
@@ -302,15 +339,13 @@ class Context:
         n = len(cfgs)
         C = (_Cfg * max(n, 1))()
         R = (_Res * max(n, 1))()
-        outs = []
         for i, g in enumerate(cfgs):
             C[i] = _cfg_struct(g, keep)
-            o = _alloc_outputs(g, want)
-            outs.append(o)
-            R[i] = _res_struct(o)
+        outs = _alloc_outputs_many(cfgs, want, R)
         _check(lib().ompd_analyze_batch(self.h, C, R, n, int(flags), None))
+        sweeps = _sweeps_of(R, n)
         for i in range(n):
-            outs[i]["sweeps"] = np.array(list(R[i].sweeps), dtype=np.int32)
+            outs[i]["sweeps"] = sweeps[i]
         return outs
 
 
@@ -356,10 +391,8 @@ def _analyze_program(self, prog, flags: int = 0, want: Sequence[str] = OUTPUTS) 
     keys = self.program_contexts(prog)
     keep: list = []
     P = _prog_struct(prog, keep)
-    outs = [_alloc_outputs(prog.procs[p], want) for (p, _) in keys]
     R = (_Res * max(len(keys), 1))()
-    for k, o in enumerate(outs):
-        R[k] = _res_struct(o)
+    outs = _alloc_outputs_many([prog.procs[p] for (p, _) in keys], want, R)
     wds = [(prog.procs[p].n_vars + 63) // 64 for (p, _) in keys]
     bnd = np.zeros(max(4 * sum(wds), 1), np.uint64)
     gw = (int(prog.n_globals) + 63) // 64
@@ -376,8 +409,9 @@ def _analyze_program(self, prog, flags: int = 0, want: Sequence[str] = OUTPUTS) 
     for wdk in wds:
         bounds.append([bnd[off + i * wdk: off + (i + 1) * wdk] for i in range(4)])
         off += 4 * wdk
+    sweeps = _sweeps_of(R, len(keys))
     for k in range(len(keys)):
-        outs[k]["sweeps"] = np.array(list(R[k].sweeps), dtype=np.int32)
+        outs[k]["sweeps"] = sweeps[k]
     return {"contexts": keys, "results": outs, "boundaries": bounds, "summaries": summ, "demands": dem,
             "rounds": out.rounds, "solves": out.solves}
 

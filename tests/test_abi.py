@@ -53,3 +53,26 @@ def test_ring_slots_flag_matches_header(tmp_path):
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     assert got == [ompd.F_RING_SLOTS(n) for n in ns]
     assert [ompd.F_RING_SLOTS(n) >> 8 for n in (8, 16, 32, 64)] == [1, 2, 3, 4]
+
+
+def test_bulk_output_views_match_per_cfg_outputs():
+    """The binding's one-buffer-per-output allocation gives every CFG the same zeroed,
+    contiguous arrays as allocating them one by one, at the addresses written into the
+    result structs, without overlaps."""
+    import synth
+    cfgs = [synth.c1(i) for i in range(4)] + [synth.random_dag(5, 20, 70, p_loop_entry=0.3)]
+    cfgs.append(synth.from_edges([(0, [], []), (0, [], [])], [(0, 1, 0)], 0)[0])   # no variables
+    R = (ompd._Res * len(cfgs))()
+    outs = ompd._alloc_outputs_many(cfgs, ompd.OUTPUTS, R)
+    spans = []
+    for i, c in enumerate(cfgs):
+        ref = ompd._alloc_outputs(c, ompd.OUTPUTS)
+        for k in ompd.OUTPUTS:
+            a = outs[i][k]
+            assert a.shape == ref[k].shape and a.dtype == ref[k].dtype
+            assert a.flags["C_CONTIGUOUS"] and not a.any()
+            if a.nbytes:   # (an empty array's address is never written through)
+                assert getattr(R[i], ompd._RES_FIELD[k]) == a.ctypes.data
+                spans.append((a.ctypes.data, a.ctypes.data + a.nbytes))
+    spans.sort()
+    assert all(e <= s for (_, e), (s, _) in zip(spans, spans[1:]))
