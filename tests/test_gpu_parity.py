@@ -231,3 +231,19 @@ def test_config3_batch_resident_sampled(ctx):
             assert_same(cfgs[i], rb.fetch(i), oracle.solve(cfgs[i]), "c3 #%d" % i)
     finally:
         rb.close()
+
+
+def test_word_counts_at_tile_boundaries(ctx):
+    """Variable counts on both sides of the word and tile boundaries (a tile holds up to 15
+    64-bit words): 63, 64 and 65 variables; 959, 960 and 961 (15 words, full or with one more
+    word, which makes two tiles); 1,024; 1,919 to 1,921 (30 words and 31).  Every output of
+    every CFG equals the oracle's, in one batch and each alone."""
+    cfgs = [synth.make_cfg(7_100 + k, n_user=70 + 9 * k, n_vars=nv, max_loop_depth=3, device_frac=0.35,
+                           irr_loop_frac=0.1)
+            for k, nv in enumerate((63, 64, 65, 959, 960, 961, 1024, 1919, 1920, 1921))]
+    refs = [oracle.solve(c) for c in cfgs]
+    got = ctx.analyze_batch(cfgs)
+    for i, cfg in enumerate(cfgs):
+        assert_same(cfg, got[i], refs[i], "batch nv=%d" % cfg.n_vars)
+    for cfg, ref in zip(cfgs, refs):
+        assert_same(cfg, ctx.analyze_cfg(cfg), ref, "alone nv=%d" % cfg.n_vars)
