@@ -247,3 +247,13 @@ def test_word_counts_at_tile_boundaries(ctx):
         assert_same(cfg, got[i], refs[i], "batch nv=%d" % cfg.n_vars)
     for cfg, ref in zip(cfgs, refs):
         assert_same(cfg, ctx.analyze_cfg(cfg), ref, "alone nv=%d" % cfg.n_vars)
+
+
+def test_large_cfg_past_16_bit_block_ids(ctx):
+    """One CFG of 131,074 blocks (block and edge ids past 16 bits, far neighbours up to the
+    whole walk away) and 130 variables (three words, the last ragged): every output equals
+    the oracle's."""
+    cfg = synth.make_cfg(7_200, n_user=131_072, n_vars=130, max_loop_depth=6, device_frac=0.4,
+                         irr_loop_frac=0.01)
+    _print("large: %d blocks %d edges %d vars" % (cfg.n_blocks, len(cfg.succ_idx), cfg.n_vars))
+    assert_same(cfg, ctx.analyze_cfg(cfg), oracle.solve(cfg), "large")
