@@ -257,3 +257,27 @@ def test_large_cfg_past_16_bit_block_ids(ctx):
                          irr_loop_frac=0.01)
     _print("large: %d blocks %d edges %d vars" % (cfg.n_blocks, len(cfg.succ_idx), cfg.n_vars))
     assert_same(cfg, ctx.analyze_cfg(cfg), oracle.solve(cfg), "large")
+
+
+def test_wide_fan_in_and_fan_out(ctx):
+    """A loop whose header branches to 300 cases that all join again (300 successors of one
+    block, 300 predecessors of another: neighbours past the first two, in the ring and far
+    beyond it), with random accesses on host and device blocks: every output equals the
+    oracle's, for several ring sizes."""
+    import paper_2406_13881_amd as ompd
+    rng = np.random.default_rng(2406)
+    k, nv = 300, 100
+    blocks = [(0, [], [])]                                   # ENTRY
+    for _ in range(k + 2):                                   # header, cases, join
+        rd = sorted(set(rng.integers(0, nv, 6).tolist()))
+        wr = sorted(set(rng.integers(0, nv, 3).tolist()))
+        blocks.append((int(rng.random() < 0.4), rd, wr))
+    blocks.append((0, [], []))                               # EXIT
+    hdr, join, ex = 1, k + 2, k + 3
+    edges = [(0, hdr, 2)] + [(hdr, 2 + c, 0) for c in range(k)] + [(2 + c, join, 0) for c in range(k)]
+    edges += [(join, hdr, 1), (join, ex, 0)]
+    cfg, _ = synth.from_edges(blocks, edges, nv)
+    ref = oracle.solve(cfg)
+    for rs in (8, 64):
+        got = ctx.analyze_batch([cfg], flags=ompd.F_RING_SLOTS(rs))[0]
+        assert_same(cfg, got, ref, "fan ring %d" % rs)
