@@ -636,21 +636,24 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             }
             // the other inputs: copies from global memory straight into the input slots (no LDS read
             // follows them before the wait); far rows past the first-level cache (the helper stored them)
+            // per step, worked out by its plan lane: the LDS address of its input slots, whether a
+            // block with one neighbour skips the second edge's rows, whether the far state comes
+            // from the rows
+            const uint32_t slotv = lds3 + IN_OFF + (uint32_t)((st & (IR - 1)) * NI) * WORD_BYTES;
+            const u64 onem = __ballot(fl & SF_ONE);
+            const u64 rowm = __ballot((fl & SF_FAR) && u >= 0 && u < gf0);
             for (int j = 0; j < n; ++j) {
                 const int sj = pf + j;
                 const GAS u64* a[NX];
                 pre(__builtin_amdgcn_readlane(xv.x, j), (uint32_t)__builtin_amdgcn_readlane(xv.y, j),
                     (uint32_t)__builtin_amdgcn_readlane(xv.z, j), a);
-                const uint32_t slot = (uint32_t)__builtin_amdgcn_readfirstlane(
-                    (int)(lds3 + IN_OFF + (uint32_t)((sj & (IR - 1)) * NI) * WORD_BYTES));
-                const uint32_t flj = (uint32_t)__builtin_amdgcn_readlane((int)fl, j);
+                const uint32_t slot = (uint32_t)__builtin_amdgcn_readlane((int)slotv, j);
                 // (a block with one neighbour never reads the second edge's slots)
-                const int nx = (flj & SF_ONE) ? NX1 : NX;
+                const int nx = ((onem >> j) & 1) ? NX1 : NX;
 #pragma unroll
                 for (int k = 0; k < NX; ++k)
                     if (k < nx) dma_row<0>(a[k], hoff, (LDS3 char*)(size_t)(slot + k * WORD_BYTES));
-                const int uj = __builtin_amdgcn_readlane(u, j);
-                if ((flj & SF_FAR) && uj >= 0 && uj < gf0) {
+                if ((rowm >> j) & 1) {
                     const int p = __builtin_amdgcn_readlane(ev.z, j);
                     dma_word<CPOL_SC1>(S.h + (size_t)p * S.str, hi, in32(sj, NX));
                     dma_word<CPOL_SC1>(S.d + (size_t)p * S.str, hi, in32(sj, NX + 1));
