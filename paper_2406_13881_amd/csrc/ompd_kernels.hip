@@ -496,8 +496,11 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // the lane's half of a word
     auto half = [&](const GAS u64* p) -> hw { return reinterpret_cast<const GAS uint32_t*>(p)[hi ? 1 : 0]; };
     auto row = [&](const u64* a, int b) -> hw { return half(arr(a) + (size_t)b * wd + wo); };
-    // start of row b (wave-uniform) and the byte of the lane's half-word within a row
-    auto rowu = [&](const u64* a, int b) -> const GAS u64* { return arr(a) + (size_t)b * wd; };
+    // start of the row at byte offset ob (wave-uniform) and the byte of the lane's half-word
+    // within a row
+    auto rowu = [&](const u64* a, u64 ob) -> const GAS u64* {
+        return reinterpret_cast<const GAS u64*>(reinterpret_cast<const GAS char*>(arr(a)) + ob);
+    };
     const uint32_t hoff = (uint32_t)wo * 8u + (hi ? 4u : 0u);
     // (both only at compute time, on rare paths: ENTRY, EXIT, call blocks)
     auto vec = [&](const u64* a) -> hw { return settle(half(arr(a) + wo)); };
@@ -642,11 +645,17 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             const uint32_t slotv = lds3 + IN_OFF + (uint32_t)((st & (IR - 1)) * NI) * WORD_BYTES;
             const u64 onem = __ballot(fl & SF_ONE);
             const u64 rowm = __ballot((fl & SF_FAR) && u >= 0 && u < gf0);
+            // and the byte offsets of its block's row and of its first two edges' rows
+            const u64 rowb = (u64)wd * 8u;
+            const u64 obv = (uint32_t)xv.x * rowb, oe0v = (uint32_t)xv.y * rowb, oe1v = (uint32_t)xv.z * rowb;
+            auto at = [&](u64 v, int j) -> u64 {
+                return (u64)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, j) |
+                       ((u64)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), j) << 32);
+            };
             for (int j = 0; j < n; ++j) {
                 const int sj = pf + j;
                 const GAS u64* a[NX];
-                pre(__builtin_amdgcn_readlane(xv.x, j), (uint32_t)__builtin_amdgcn_readlane(xv.y, j),
-                    (uint32_t)__builtin_amdgcn_readlane(xv.z, j), a);
+                pre(at(obv, j), at(oe0v, j), at(oe1v, j), a);
                 const uint32_t slot = (uint32_t)__builtin_amdgcn_readlane((int)slotv, j);
                 // (a block with one neighbour never reads the second edge's slots)
                 const int nx = ((onem >> j) & 1) ? NX1 : NX;
@@ -874,9 +883,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     if constexpr (PH == PH_NU) {
         const Rows S = rows_of(c.nu_h, c.nu_d, 0);
         // x0 = R, x1 = W (flag lane: R = 2, W = 2 at DEVICE blocks, substituted when computed)
-        auto pre = [&](int b, uint32_t, uint32_t, const GAS u64** x) {
-            x[0] = rowu(c.R, b);
-            x[1] = rowu(c.W, b);
+        auto pre = [&](u64 ob, u64, u64, const GAS u64** x) {
+            x[0] = rowu(c.R, ob);
+            x[1] = rowu(c.W, ob);
         };
         auto comp = [&](int b, const Rec& r, const hw* x, const hw* nh, const hw* nd, hw ph, hw pd, int sweep,
                         int g, hw& vh, hw& vd) {
@@ -922,10 +931,10 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         const Rows S = rows_of(c.aveout_h, c.aveout_d, 2);
         const hw init = vm;
         // x0/x1 = NU (flag lane: 0), x2 = W (flag lane: 2 at DEVICE blocks), substituted when computed
-        auto pre = [&](int b, uint32_t, uint32_t, const GAS u64** x) {
-            x[0] = rowu(c.nu_h, b);
-            x[1] = rowu(c.nu_d, b);
-            x[2] = rowu(c.W, b);
+        auto pre = [&](u64 ob, u64, u64, const GAS u64** x) {
+            x[0] = rowu(c.nu_h, ob);
+            x[1] = rowu(c.nu_d, ob);
+            x[2] = rowu(c.W, ob);
         };
         auto comp = [&](int b, const Rec& r, const hw* x, const hw* nh, const hw* nd, hw ph, hw pd, int sweep,
                         int g, hw& vh, hw& vd) {
@@ -993,7 +1002,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         sd = ud | (dev ? ww : 0u);
     };
     auto erow = [&](const u64* a, uint32_t e) -> hw { return half(G(a) + (size_t)(e & 0x7FFFFFFFu) * wd + wo); };
-    auto erowu = [&](const u64* a, uint32_t e) -> const GAS u64* { return G(a) + (size_t)(e & 0x7FFFFFFFu) * wd; };
+    auto erowu = [&](const u64* a, u64 oe) -> const GAS u64* {
+        return reinterpret_cast<const GAS u64*>(reinterpret_cast<const GAS char*>(G(a)) + oe);
+    };
 
     // -------------------------------------------------------- pending copies (forward, may)
     // MAYP_s(e) = (EAG_s(e) | MAYPout_s(p)) & ~LE(e), EAG_s(e=p->q) = NU_s(q) & ~AVEout_s(p);
@@ -1003,10 +1014,10 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         const Rows S = rows_of(c.mayp_h, c.mayp_d, 0);
         // x0 = R, x1 = W, x2..x5 = EAG_H/D of the two inline in-edges
         // (the second edge's rows are not loaded for a block with one neighbour)
-        auto pre = [&](int b, uint32_t e0, uint32_t e1, const GAS u64** x) {
-            x[0] = rowu(c.R, b); x[1] = rowu(c.W, b);
-            x[2] = erowu(c.eag_h, e0); x[3] = erowu(c.eag_d, e0);
-            x[4] = erowu(c.eag_h, e1); x[5] = erowu(c.eag_d, e1);
+        auto pre = [&](u64 ob, u64 oe0, u64 oe1, const GAS u64** x) {
+            x[0] = rowu(c.R, ob); x[1] = rowu(c.W, ob);
+            x[2] = erowu(c.eag_h, oe0); x[3] = erowu(c.eag_d, oe0);
+            x[4] = erowu(c.eag_h, oe1); x[5] = erowu(c.eag_d, oe1);
         };
         auto comp = [&](int b, const Rec& r, const hw* x, const hw* nh, const hw* nd, hw ph, hw pd, int sweep,
                         int g, hw& vh, hw& vd) {
@@ -1055,10 +1066,10 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         if (c.placement & 1) return;
         const Rows S = rows_of(c.later_h, c.later_d, 0);
         // x0 = R, x1 = W, x2..x4 / x5..x7 = EAG_H, EAG_D, BOTH of the two inline in-edges
-        auto pre = [&](int b, uint32_t e0, uint32_t e1, const GAS u64** x) {
-            x[0] = rowu(c.R, b); x[1] = rowu(c.W, b);
-            x[2] = erowu(c.eag_h, e0); x[3] = erowu(c.eag_d, e0); x[4] = erowu(c.both, e0);
-            x[5] = erowu(c.eag_h, e1); x[6] = erowu(c.eag_d, e1); x[7] = erowu(c.both, e1);
+        auto pre = [&](u64 ob, u64 oe0, u64 oe1, const GAS u64** x) {
+            x[0] = rowu(c.R, ob); x[1] = rowu(c.W, ob);
+            x[2] = erowu(c.eag_h, oe0); x[3] = erowu(c.eag_d, oe0); x[4] = erowu(c.both, oe0);
+            x[5] = erowu(c.eag_h, oe1); x[6] = erowu(c.eag_d, oe1); x[7] = erowu(c.both, oe1);
         };
         auto comp = [&](int b, const Rec& r, const hw* x, const hw* nh, const hw* nd, hw ph, hw pd, int sweep,
                         int g, hw& vh, hw& vd) {
@@ -1119,10 +1130,10 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         const Rows S = rows_of(c.aveout_h, c.aveout_d, 2);
         const hw init = vm;
         // x0/x1 = INS_ENTRY, x2 = W, x3..x6 = INS_EDGE_H/D of the two inline in-edges
-        auto pre = [&](int b, uint32_t e0, uint32_t e1, const GAS u64** x) {
-            x[0] = rowu(c.ie_h, b); x[1] = rowu(c.ie_d, b); x[2] = rowu(c.W, b);
-            x[3] = erowu(c.ig_h, e0); x[4] = erowu(c.ig_d, e0);
-            x[5] = erowu(c.ig_h, e1); x[6] = erowu(c.ig_d, e1);
+        auto pre = [&](u64 ob, u64 oe0, u64 oe1, const GAS u64** x) {
+            x[0] = rowu(c.ie_h, ob); x[1] = rowu(c.ie_d, ob); x[2] = rowu(c.W, ob);
+            x[3] = erowu(c.ig_h, oe0); x[4] = erowu(c.ig_d, oe0);
+            x[5] = erowu(c.ig_h, oe1); x[6] = erowu(c.ig_d, oe1);
         };
         auto comp = [&](int b, const Rec& r, const hw* x, const hw* nh, const hw* nd, hw ph, hw pd, int sweep,
                         int g, hw& vh, hw& vd) {
