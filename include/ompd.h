@@ -221,7 +221,9 @@ void ompd_plan_destroy(ompd_plan* plan);
  * if it fits the context's device-memory budget and a slot is free
  * (otherwise OMPD_E_BUSY: poll/wait on earlier tickets and retry), and
  * returns at once; a background thread groups admitted requests into steps
- * that run concurrently on several streams.  `res` (host pointers) must
+ * that run concurrently on several streams (while one runs, the next waits
+ * for 32 pending requests or 20 ms, whichever comes first, so that steps are
+ * large).  `res` (host pointers) must
  * stay valid until poll reports done.  poll: *done = 0 pending, 1 done,
  * negative = that request's error code; a done ticket is released by the
  * poll that reports it.  wait blocks until done or timeout_ns (< 0 = no
