@@ -17,17 +17,20 @@ problems of ``oracle.c``:
   changes.  Each problem is gen/kill per bit, so two (resp. four) boundary
   evaluations define the function exactly.
 * Top-down, contexts are (procedure, last two call sites).  Solving a
-  context gives, at each call site, the validity after the caller's own
-  accesses in the final placement (entry validity of the callee) and the
-  caller's next use after the call (exit liveness of the callee).  Several
-  callers that reach one context meet: validity by AND, liveness by OR,
-  over everything contributed so far, in rounds that re-solve every context
-  whose boundary changed.  A variable that the meet leaves valid in neither
-  space is assumed valid on the host in that context, and the call site that
-  leads to the context (the last of its call string) must then make it valid
-  on the host before the call (a host read at the call block); such demands
-  feed back into the summaries, and the whole computation repeats until no
-  demand changes.
+  context gives, at each call site, the caller's next use after the call
+  (exit liveness of the callee) and the validity after the call block's own
+  accesses under eager copies (entry validity of the callee).  Several calls
+  that reach one context meet: liveness by OR, validity by AND.  Next use
+  grows with exit liveness and eager validity shrinks with entry validity,
+  so the exit liveness of every context is one least fixed point and, given
+  it, the entry validity one greatest fixed point: any order of the context
+  solves reaches them.  A global that the AND leaves valid in neither space
+  (host-fresh and device-fresh callers meeting) and that the context reads
+  before writing it is demanded as a host read at the call site that leads
+  to the context (the last of its call string), unless a calling context
+  lacks that global at its own entry (its demand comes first); a global the
+  context never reads may stay valid nowhere.  Demands feed back into the
+  summaries, and the whole computation repeats until no demand changes.
 * The validity tables describe the callee under eager copies; a context's
   final placement delays copies and can leave a copy stale at the callee's
   exit where the eager one would be current.  So when a context is solved,
@@ -136,8 +139,11 @@ def external_summary(gm: np.ndarray) -> np.ndarray:
 
 
 class ProgramOracle:
-    def __init__(self, prog):
+    def __init__(self, prog, placement: int = 0):
+        """``placement``: 0 delayed copies (the method), 1 eager copies only
+        (every solve of the driver materialises each eager copy)."""
         self.p = prog
+        self.placement = placement
         self.n = len(prog.procs)
         self.G = prog.n_globals
         self.sites: List[List[int]] = [[] for _ in range(self.n)]      # call-site ids per caller
@@ -146,6 +152,7 @@ class ProgramOracle:
         self.demand: Dict[int, np.ndarray] = {}                          # call site -> host-read mask (caller words)
         self.cap: Dict[tuple, Tuple[np.ndarray, np.ndarray]] = {}        # callee context -> (host, device) validity at EXIT
         self.sum_rows: Dict[int, np.ndarray] = {}
+        self.nowhere: Dict[tuple, np.ndarray] = {}                       # last contexts(): globals valid nowhere
         self.visits = 0
 
     # -- call tables in a caller's variable layout ------------------------------------
@@ -195,7 +202,7 @@ class ProgramOracle:
         view = type(cfg)(n_blocks=cfg.n_blocks, n_vars=cfg.n_vars, succ_ptr=cfg.succ_ptr, succ_idx=cfg.succ_idx,
                          edge_kind=cfg.edge_kind, space=cfg.space, R=R, W=cfg.W, entry=cfg.entry, exit=cfg.exit)
         self.visits += 1
-        res = solve(view, placement=SUMMARY_MODE if summary_mode else 0,
+        res = solve(view, placement=(SUMMARY_MODE if summary_mode else 0) | self.placement,
                     call=call if self.sites[P] else None, sums=sums if self.sites[P] else None,
                     boundary=boundary)
         return view, call, sums, res
@@ -291,104 +298,250 @@ class ProgramOracle:
         return m & gm
 
     # -- top-down -------------------------------------------------------------------
-    def contexts(self, S):
-        """Context boundaries {(proc, sigma): (ev_h, ev_d, lx_h, lx_d)}, the
-        host-read demands they require and, per context, its validity at EXIT
-        under the final placement (the caps of the next round).
+    def context_graph(self):
+        """Contexts reachable from the roots and the call edges between them:
+        {key: [(site, callee key), ...]} with key = (procedure, last <= 2 sites)."""
+        out: Dict[Tuple[int, tuple], List[Tuple[int, Tuple[int, tuple]]]] = {}
+        todo = [(r, ()) for r in self.p.roots]
+        while todo:
+            key = todo.pop()
+            if key in out:
+                continue
+            P, sigma = key
+            edges = []
+            for j in self.sites[P]:
+                q = int(self.p.callee[j])
+                if q >= 0:
+                    nk = (q, (sigma + (j,))[-2:])
+                    edges.append((j, nk))
+                    todo.append(nk)
+            out[key] = edges
+        return out
 
-        Rounds: every context whose boundary is new or changed is solved;
-        each of its calls contributes the validity after the call block's own
-        accesses and the next use after the call to the callee context (the
-        last two call sites); a context's boundary is the meet of everything
-        contributed to it so far (validity AND, liveness OR), so boundaries
-        only move one way and the rounds end.  Bits left valid in neither
-        space are then assumed valid on the host and demanded, as a host read,
-        at the call site that leads to the context (the last site of its call
-        string)."""
+    def _call_values(self, P, cfg, res, j):
+        """What call site j of a solved context of P gives its callee: the
+        validity after the call block's own accesses under eager copies, and
+        the next use after the call (successor entries), over the globals."""
+        c = int(self.p.call_block[j])
+        w = cfg.W[c]
+        a1_h = res["ave_h"][c] | w
+        a1_d = res["ave_d"][c] & ~w
+        l_h = np.zeros(cfg.wd, np.uint64)
+        l_d = np.zeros(cfg.wd, np.uint64)
+        for e in range(int(cfg.succ_ptr[c]), int(cfg.succ_ptr[c + 1])):
+            t = int(cfg.succ_idx[e])
+            l_h |= res["nu_h"][t]
+            l_d |= res["nu_d"][t]
+        return a1_h, a1_d, l_h, l_d
+
+    def _iterate(self, graph, keys, value, contrib, meet, identity, schedule):
+        """Chaotic iteration of one monotone boundary system over the context
+        graph: the value of a non-root context is the meet, over its incoming
+        call edges, of the latest contribution of each (identity while the
+        caller is unsolved); roots keep theirs.  ``contrib(key, bnd)`` solves a
+        context and returns {(site, callee key): contribution}.  Every schedule
+        reaches the same fixed point because the contributions move one way."""
+        into: Dict[Tuple[int, tuple], List[Tuple[Tuple[int, tuple], int]]] = {k: [] for k in keys}
+        for k in keys:
+            for (j, nk) in graph[k]:
+                into[nk].append((k, j))
+        latest: Dict[Tuple[Tuple[int, tuple], int], np.ndarray] = {}
+
+        def recompute(nk):
+            v = identity(nk)
+            for (k, j) in into[nk]:
+                if (k, j) in latest:
+                    v = meet(v, latest[(k, j)])
+            return v
+
+        order = sorted(keys)
+        if schedule == "rounds":
+            dirty = order
+            while dirty:
+                touched = set()
+                for k in dirty:
+                    for (j, nk), v in contrib(k, value[k]).items():
+                        latest[(k, j)] = v
+                        touched.add(nk)
+                dirty = []
+                for nk in sorted(touched):
+                    if nk[1] == () and nk[0] in self.roots_set:
+                        continue
+                    v = recompute(nk)
+                    if any(not np.array_equal(a, b) for a, b in zip(v, value[nk])):
+                        value[nk] = v
+                        dirty.append(nk)
+        elif schedule in ("fifo", "lifo"):
+            queue = list(order) if schedule == "fifo" else list(reversed(order))
+            queued = set(queue)
+            while queue:
+                k = queue.pop(0) if schedule == "fifo" else queue.pop()
+                queued.discard(k)
+                for (j, nk), v in contrib(k, value[k]).items():
+                    latest[(k, j)] = v
+                    if nk[1] == () and nk[0] in self.roots_set:
+                        continue
+                    w = recompute(nk)
+                    if any(not np.array_equal(a, b) for a, b in zip(w, value[nk])):
+                        value[nk] = w
+                        if nk not in queued:
+                            queued.add(nk)
+                            queue.append(nk)
+        else:
+            raise ValueError(schedule)
+        return value
+
+    def contexts(self, S, schedule: str = "rounds"):
+        """Context boundaries {(proc, sigma): (ev_h, ev_d, lx_h, lx_d)}, the
+        host-read demands they require, per context its validity at EXIT under
+        the final placement (the caps of the next outer round), and the
+        contexts' final solutions.
+
+        Two monotone systems over the context graph, solved one after the
+        other (each has one fixed point, whatever the order of the solves):
+        * exit liveness, least fixed point: a context's host / device exit
+          liveness is the OR, over the calls that lead to it, of the caller's
+          next use after the call; next use only grows with exit liveness;
+        * entry validity, greatest fixed point given that liveness: the AND,
+          over the calls, of the caller's eager validity after the call
+          block's own accesses; eager validity only shrinks with entry
+          validity.
+        A global that the AND leaves valid in neither space and that the
+        context reads before writing it needs its host copy made current by
+        the callers: it is demanded, as a host read, at the call site that
+        leads to the context (the last site of its call string), unless a
+        caller context is itself missing that global at entry (the caller's
+        own demand comes first); if every remaining gap is of that kind (a
+        cycle of recursive contexts), all of them are demanded.  A global the
+        context never reads may stay valid nowhere (its solve allows it)."""
         G = self.G
         gw = (G + 63) // 64
-        ctx: Dict[Tuple[int, tuple], List[np.ndarray]] = {}
-        last: Dict[Tuple[int, tuple], dict] = {}
-        for r in self.p.roots:
-            ctx[(r, ())] = list(self.p.procs[r].boundary())
-        dirty = sorted(ctx)
-        new_demand: Dict[int, np.ndarray] = {}
-        while dirty:
-            acc: Dict[Tuple[int, tuple], List[np.ndarray]] = {}
-            for key in dirty:
-                P, sigma = key
-                cfg, call, sums, res = self._solve(P, S, ctx[key], sigma=sigma)
-                last[key] = res
-                wd = cfg.wd
-                for j in self.sites[P]:
-                    q = int(self.p.callee[j])
-                    if q < 0:
-                        continue
-                    c = int(self.p.call_block[j])
-                    # validity after the call block's own accesses (final placement)
-                    w = cfg.W[c]
-                    a1_h = res["avf_h"][c] | w
-                    a1_d = res["avf_d"][c] & ~w
-                    l_h = np.zeros(wd, np.uint64)
-                    l_d = np.zeros(wd, np.uint64)
-                    for e in range(int(cfg.succ_ptr[c]), int(cfg.succ_ptr[c + 1])):
-                        t = int(cfg.succ_idx[e])
-                        l_h |= res["nu_h"][t]
-                        l_d |= res["nu_d"][t]
-                    qc = self.p.procs[q]
-                    qwd = qc.wd
-                    gq = _gmask(G, qwd)
-                    lq = _vmask(qc.n_vars, qwd) & ~gq
-                    m = [np.zeros(qwd, np.uint64) for _ in range(4)]
-                    m[0][:gw] = a1_h[:gw]
-                    m[1][:gw] = a1_d[:gw]
-                    m[2][:gw] = l_h[:gw]
-                    m[3][:gw] = l_d[:gw]
-                    m = [(m[0] & gq) | lq, m[1] & gq, m[2] & gq, m[3] & gq]
-                    nkey = (q, (sigma + (j,))[-2:])
-                    if nkey in acc:
-                        a = acc[nkey]
-                        acc[nkey] = [a[0] & m[0], a[1] & m[1], a[2] | m[2], a[3] | m[3]]
-                    else:
-                        acc[nkey] = m
-            dirty = []
-            for nkey in sorted(acc):
-                a = acc[nkey]
-                if nkey in ctx:
-                    old = ctx[nkey]
-                    m = [old[0] & a[0], old[1] & a[1], old[2] | a[2], old[3] | a[3]]
-                else:
-                    m = a
-                q = nkey[0]
-                gq = _gmask(G, self.p.procs[q].wd)
-                # variables valid in neither space (must-validity is empty after a
-                # join of host-fresh and device-fresh paths, or after a meet of
-                # callers): assume the host copy and make the call site that leads
-                # here provide it
-                nowhere = gq & ~(m[0] | m[1])
-                if nowhere.any():
-                    m[0] = m[0] | nowhere
-                    jj = nkey[1][-1]
-                    P2 = int(self.p.call_proc[jj])
-                    d = new_demand.get(jj, np.zeros(self.p.procs[P2].wd, np.uint64))
-                    d[:gw] |= nowhere[:gw]
-                    new_demand[jj] = d
-                if nkey not in ctx or any(not np.array_equal(x, y) for x, y in zip(ctx[nkey], m)):
-                    ctx[nkey] = m
-                    dirty.append(nkey)
-        caps: Dict[tuple, Tuple[np.ndarray, np.ndarray]] = {}
-        for key, res in last.items():
-            if key[1]:
-                qc = self.p.procs[key[0]]
-                caps[key] = (res["avf_h"][qc.exit][:gw].copy(), res["avf_d"][qc.exit][:gw].copy())
-        return ctx, new_demand, caps
+        graph = self.context_graph()
+        keys = sorted(graph)
+        self.roots_set = set(self.p.roots)
+        is_root = {k: (k[1] == () and k[0] in self.roots_set) for k in keys}
 
-    def analyze(self, max_rounds: int = 64):
-        """Summaries, contexts and per-context results (with demands settled)."""
+        def masks(q):
+            qc = self.p.procs[q]
+            gq = _gmask(G, qc.wd)
+            return gq, _vmask(qc.n_vars, qc.wd) & ~gq
+
+        def to_callee(x, nk):
+            qc = self.p.procs[nk[0]]
+            m = np.zeros(qc.wd, np.uint64)
+            m[:gw] = x[:gw]
+            return m & _gmask(G, qc.wd)
+
+        bnd: Dict[Tuple[int, tuple], List[np.ndarray]] = {}
+        for k in keys:
+            if is_root[k]:
+                bnd[k] = [np.asarray(x, np.uint64).copy() for x in self.p.procs[k[0]].boundary()]
+            else:
+                gq, lq = masks(k[0])
+                wd = self.p.procs[k[0]].wd
+                bnd[k] = [gq | lq, gq.copy(), np.zeros(wd, np.uint64), np.zeros(wd, np.uint64)]
+
+        # exit liveness (least fixed point); entry validity does not enter next use
+        live = {k: (bnd[k][2], bnd[k][3]) for k in keys}
+
+        def contrib_live(k, lv):
+            P, sigma = k
+            b = bnd[k]
+            cfg, _, _, res = self._solve(P, S, (b[0], b[1], lv[0], lv[1]), summary_mode=True, sigma=sigma)
+            out = {}
+            for (j, nk) in graph[k]:
+                _, _, l_h, l_d = self._call_values(P, cfg, res, j)
+                out[(j, nk)] = (to_callee(l_h, nk), to_callee(l_d, nk))
+            return out
+
+        live = self._iterate(graph, keys, live, contrib_live, lambda a, b: (a[0] | b[0], a[1] | b[1]),
+                             lambda nk: (np.zeros(self.p.procs[nk[0]].wd, np.uint64),
+                                         np.zeros(self.p.procs[nk[0]].wd, np.uint64)), schedule)
+        for k in keys:
+            bnd[k][2], bnd[k][3] = live[k]
+
+        # entry validity (greatest fixed point) with that liveness
+        valid = {k: (bnd[k][0], bnd[k][1]) for k in keys}
+
+        def top(nk):
+            gq, lq = masks(nk[0])
+            return (gq | lq, gq.copy())
+
+        def contrib_valid(k, ev):
+            P, sigma = k
+            b = bnd[k]
+            cfg, _, _, res = self._solve(P, S, (ev[0], ev[1], b[2], b[3]), summary_mode=True, sigma=sigma)
+            out = {}
+            for (j, nk) in graph[k]:
+                a1_h, a1_d, _, _ = self._call_values(P, cfg, res, j)
+                gq, lq = masks(nk[0])
+                out[(j, nk)] = (to_callee(a1_h, nk) | lq, to_callee(a1_d, nk))
+            return out
+
+        valid = self._iterate(graph, keys, valid, contrib_valid, lambda a, b: (a[0] & b[0], a[1] & b[1]), top,
+                              schedule)
+        for k in keys:
+            bnd[k][0], bnd[k][1] = valid[k]
+
+        # final solves (a non-root context may leave globals valid nowhere), and the caps they give
+        results = {}
+        caps: Dict[tuple, Tuple[np.ndarray, np.ndarray]] = {}
+        for k in keys:
+            res = self._solve(k[0], S, tuple(bnd[k]), summary_mode=not is_root[k], sigma=k[1])[3]
+            results[k] = res
+            if k[1]:
+                qc = self.p.procs[k[0]]
+                caps[k] = (res["avf_h"][qc.exit][:gw].copy(), res["avf_d"][qc.exit][:gw].copy())
+
+        # globals valid nowhere that the context reads before writing them (next
+        # use at its ENTRY, which does not depend on entry validity): host-read
+        # demands at the leading call site; a gap the context never reads stays
+        gaps = {}
+        for k in keys:
+            if not is_root[k]:
+                qc = self.p.procs[k[0]]
+                gq, _ = masks(k[0])
+                need = results[k]["nu_h"][qc.entry] | results[k]["nu_d"][qc.entry]
+                nw = gq & ~(bnd[k][0] | bnd[k][1]) & need
+                if nw.any():
+                    gaps[k] = nw
+        callers: Dict[Tuple[int, tuple], List[Tuple[int, tuple]]] = {k: [] for k in keys}
+        for k in keys:
+            for (j, nk) in graph[k]:
+                callers[nk].append(k)
+        new_demand: Dict[int, np.ndarray] = {}
+
+        def demand(k, bits):
+            jj = k[1][-1]
+            P2 = int(self.p.call_proc[jj])
+            d = new_demand.get(jj, np.zeros(self.p.procs[P2].wd, np.uint64))
+            d[:gw] |= bits[:gw]
+            new_demand[jj] = d
+
+        for k, nw in gaps.items():
+            inherited = np.zeros(gw, np.uint64)
+            for x in callers[k]:
+                if x in gaps:
+                    inherited |= gaps[x][:gw]
+            own = nw.copy()
+            own[:gw] &= ~inherited
+            if own.any():
+                demand(k, own)
+        if gaps and not new_demand:
+            for k, nw in gaps.items():
+                demand(k, nw)
+        self.nowhere = {k: nw.copy() for k, nw in gaps.items()}
+        return bnd, new_demand, caps, results
+
+    def analyze(self, max_rounds: int = 64, schedule: str = "rounds"):
+        """Summaries, context boundaries and per-context results, after the
+        outer rounds (summaries, then contexts) have settled the demands and
+        the caps.  ``schedule`` orders the context solves inside a round
+        ("rounds", "fifo" or "lifo"); the result does not depend on it."""
         gm = _gmask(self.G, (self.G + 63) // 64)
         for _ in range(max_rounds):
             S = self.summarize()
-            ctx, nd, caps = self.contexts(S)
+            ctx, nd, caps, results = self.contexts(S, schedule)
             grew = False
             for j, m in nd.items():
                 old = self.demand.get(j)
@@ -403,8 +556,5 @@ class ProgramOracle:
                 self.cap = caps
                 grew = True
             if not grew:
-                results = {}
-                for key, b in ctx.items():
-                    results[key] = self._solve(key[0], S, b, sigma=key[1])[3]
                 return S, ctx, results
         raise RuntimeError("demands and caps did not settle")

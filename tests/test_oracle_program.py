@@ -11,7 +11,14 @@ share no code with it:
 * unrolling: on recursive programs, the root's next use is the limit of the
   inlined program unrolled to growing call depth;
 * simulation: random walks through calls, recursion and external callees
-  never read or copy a stale version.
+  never read or copy a stale version;
+* schedule independence: Jacobi rounds, FIFO and LIFO worklists over the
+  context solves give the same boundaries, demands and placements;
+* eager copies: with every eager copy materialised, the validity of every
+  block of every context equals that of its inlined copy (both directions)
+  when no two call strings meet;
+* necessity of demands: dropping any demanded global reopens the gap it
+  closes (valid nowhere, yet read) in a context of that call site.
 """
 import numpy as np
 import pytest
@@ -157,3 +164,150 @@ def test_summaries_of_c4_shape():
     comps = tarjan(len(prog.procs), succ)
     assert max(len(c) for c in comps) <= 8
     assert sum(1 for c in comps if len(c) > 1) >= 3
+
+
+# ---------------------------------------------------------------------------
+# The context boundaries are fixed points, not artefacts of a schedule
+# ---------------------------------------------------------------------------
+def _outputs(po, S, ctx, results):
+    out = {"S": {p: S[p].tobytes() for p in S}, "demand": {j: po.demand[j].tobytes() for j in po.demand}}
+    for key in ctx:
+        out[("bnd",) + key] = tuple(np.asarray(x).tobytes() for x in ctx[key])
+        out[("res",) + key] = tuple(np.asarray(results[key][k]).tobytes() for k in sorted(results[key])
+                                    if k != "visits")
+    return out
+
+
+SCHEDULE_CASES = [("plain", {}), ("recursive", dict(scc_procs=4, scc_size=(2, 3), mean_calls=1.0)),
+                  ("external", dict(n_procs=8, scc_procs=5, scc_size=(2, 3), external_frac=0.3)),
+                  ("deep", dict(n_procs=9, mean_calls=2.5, max_calls=4))]
+
+
+@pytest.mark.parametrize("kind,extra", SCHEDULE_CASES, ids=[c[0] for c in SCHEDULE_CASES])
+def test_context_solution_does_not_depend_on_the_schedule(kind, extra):
+    # Jacobi rounds, a FIFO worklist and a LIFO worklist over the context
+    # solves give the same boundaries, demands, summaries and placements
+    for seed in range(5):
+        prog = small_program(11_000 + 97 * len(kind) + seed, **extra)
+        ref = None
+        for schedule in ("rounds", "fifo", "lifo"):
+            po = ProgramOracle(prog)
+            S, ctx, results = po.analyze(schedule=schedule)
+            got = _outputs(po, S, ctx, results)
+            if ref is None:
+                ref = got
+            else:
+                assert got == ref, "%s seed %d: schedule %s changes the result" % (kind, seed, schedule)
+
+
+def _shallow(prog):
+    # non-recursive, no external callee, and every call string at most two
+    # calls deep: no two call strings meet in one context
+    if (prog.callee < 0).any():
+        return False
+    _, inst, _ = inline_program(prog, 0, {})
+    return len(prog.roots) == 1 and max(len(sg) for (_, sg, _, _) in inst) <= 2
+
+
+def test_eager_validity_equals_the_inlined_program():
+    # With eager copies everywhere the final validity is the eager one, so no
+    # cap can bind; without merged call strings no demand arises; then the
+    # validity of every block of every context equals that of its inlined
+    # copy, in both directions (the one-sided pin above only bounds it).
+    found = deep = 0
+    for seed in range(200):
+        prog = small_program(13_000 + seed, n_procs=3, mean_calls=2.0, max_calls=3)
+        if not _shallow(prog):
+            continue
+        po = ProgramOracle(prog, placement=1)
+        _, ctx, results = po.analyze()
+        assert not po.demand, "seed %d: a shallow program needs no demand" % seed
+        big, instances, pos = inline_program(prog, 0, {})
+        ref = oracle.solve(big, placement=1)
+        G = prog.n_globals
+        for (P, sigma, off, vmap) in instances:
+            cfg = prog.procs[P]
+            mask = (1 << (cfg.n_vars if not sigma else G)) - 1
+            r = results[(P, sigma)]
+            for b in range(cfg.n_blocks):
+                # a callee's ENTRY holds its boundary: the inlined program copies
+                # on the call edge into it, the context on ENTRY's out-edges, so
+                # validity agrees from the first block on
+                names = ("nu_h", "nu_d") if (sigma and b == cfg.entry) else \
+                    ("ave_h", "ave_d", "avf_h", "avf_d", "nu_h", "nu_d")
+                for k in names:
+                    assert masked(r[k][b], mask) == masked(ref[k][pos[off + b]], mask), \
+                        "seed %d: %s of %s block %d differs from the inlined program" % (seed, k, (P, sigma), b)
+        found += 1
+        deep += sum(1 for (_, sg, _, _) in instances if len(sg) == 2)
+        if found >= 16:
+            break
+    assert found >= 16 and deep >= 20
+
+
+def merge_program(seed, n_globals=10):
+    """Root calls A at two sites, A calls B, B calls C: the call strings
+    (site 0, A->B, B->C) and (site 1, A->B, B->C) meet in C's context.
+    Every other block is a random host or device statement over the globals,
+    so the two paths into C often leave a global fresh in different spaces."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def stmt(p=0.3):
+        dev = int(rng.random() < 0.5)
+        rd = [v for v in range(n_globals) if rng.random() < p]
+        wr = [v for v in range(n_globals) if rng.random() < p]
+        return (dev, rd, wr)
+
+    def chain(body):
+        blocks = [(0, [], [])] + body + [(0, [], [])]
+        edges = [(i, i + 1, 0) for i in range(len(blocks) - 1)]
+        return synth.from_edges(blocks, edges, n_globals)[0]
+
+    host_call = (0, [], [])
+    root = chain([stmt(), host_call, stmt(), stmt(), host_call, stmt()])      # calls at blocks 2 and 5
+    # nothing is live after the program, so the liveness after the two calls
+    # depends on what the root reads next, and may differ
+    root.exit_live_h = np.zeros(root.wd, np.uint64)
+    # the callees touch few globals, so many pass through all three of them
+    a = chain([stmt(0.1), host_call, stmt(0.1)])                               # call at block 2
+    b = chain([host_call, stmt(0.1)])                                          # call at block 1
+    c = chain([stmt(0.1), stmt(0.1)])
+    return synth.Program(procs=[root, a, b, c], n_globals=n_globals,
+                         call_proc=np.array([0, 0, 1, 2], np.int32), call_block=np.array([2, 5, 2, 1], np.int32),
+                         callee=np.array([1, 1, 2, 3], np.int32), roots=[0])
+
+
+def test_every_demand_is_needed():
+    # Dropping any demanded global of any call site and solving the contexts
+    # again leaves that global valid in neither space, and read, in a context
+    # the site leads to: the demand is exactly what closes that gap.
+    checked = programs = 0
+    for seed in range(200):
+        prog = merge_program(19_000 + seed)
+        po = ProgramOracle(prog)
+        po.analyze()
+        if not po.demand:
+            continue
+        programs += 1
+        gw = (prog.n_globals + 63) // 64
+        for j, m in sorted(po.demand.items()):
+            for v in range(64 * gw):
+                if not (int(m[v >> 6]) >> (v & 63)) & 1:
+                    continue
+                po2 = ProgramOracle(prog)
+                po2.demand = {jj: mm.copy() for jj, mm in po.demand.items()}
+                po2.cap = dict(po.cap)
+                po2.demand[j][v >> 6] &= ~np.uint64(1 << (v & 63))
+                S2 = po2.summarize()
+                po2.contexts(S2)
+                gaps = [k for k, nw in po2.nowhere.items()
+                        if k[1] and k[1][-1] == j and (int(nw[v >> 6]) >> (v & 63)) & 1]
+                assert gaps, "seed %d: demand of global %d at site %d is not needed" % (seed, v, j)
+                checked += 1
+        # and the demands make the program safe
+        _, ctx, results = po.analyze()
+        errs, _ = simulate_program(prog, ctx, results, po.demand, walks=20, seed=seed)
+        assert not errs, errs[:5]
+        if checked >= 40:
+            break
+    assert programs >= 10 and checked >= 15
