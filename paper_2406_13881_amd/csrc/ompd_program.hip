@@ -21,17 +21,20 @@
 // from 0.  External callees need every global on the host, may read and
 // write all of them there and leave the device copies stale.
 //
-// Contexts (procedure, last two call sites) are solved in rounds: every
-// context whose boundary changed is solved; each call contributes, to the
-// callee context it leads to, the validity after the call block's own
-// accesses under the final placement and the next use after the call; a
-// context's boundary is the meet of everything contributed in the outer
-// round so far (validity AND, liveness OR).  Globals then valid in neither
-// space are assumed valid on the host, and the call site leading to the
-// context must make them so (a host read at the call block).  Each call is
-// capped by the validity at EXIT, under the final placement, of the callee
-// context it leads to (from the previous outer round).  Outer rounds repeat
-// until the demands and caps no longer change.
+// Contexts (procedure, last two call sites): each call gives the callee
+// context it leads to the caller's next use after the call (exit liveness)
+// and the validity after the call block's own accesses under eager copies
+// (entry validity).  Liveness meets by OR and only grows with liveness;
+// eager validity meets by AND and only shrinks with validity; so the exit
+// liveness of all contexts is one least fixed point and, given it, the entry
+// validity one greatest fixed point, each solved here in rounds of batched
+// context solves.  A global then valid in neither space that the context
+// reads before writing it is demanded as a host read at the call site
+// leading to the context (a host read at the call block), unless a calling
+// context lacks it too.  Each call is capped by the validity at EXIT, under
+// the final placement, of the callee context it leads to (from the previous
+// outer round).  Outer rounds repeat until the demands and caps no longer
+// change.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -198,15 +201,17 @@ __global__ void __launch_bounds__(64) k_demand(const DemandItem* __restrict__ it
     }
 }
 
-// Contribution of one solved call to the callee context it leads to:
-// validity after the call block's own accesses (final placement) and next
-// use after the call, on the globals; the callee's locals are valid on the
-// host at its entry and dead at its exit.
+// Contribution of one solved call to the callee context it leads to, on the
+// globals: in the liveness system the caller's next use after the call (the
+// OR of next use over the call block's successors), in the validity system
+// the validity after the call block's own accesses under eager copies.  One
+// slot per call edge of the context graph keeps the latest contribution.
 struct ContribItem {
-    const uint64_t *avf_h, *avf_d, *nu_h, *nu_d, *W;
+    const uint64_t *a_h, *a_d;   // liveness: next use (H, D); validity: eager validity (H, D)
+    const uint64_t* W;
     const int32_t *succ_ptr, *succ_idx;
-    uint64_t* acc;            // [4][gw] of the callee context
-    int32_t c, wd, gw, G, cnv;
+    uint64_t* out;               // [2][gw] slot of the call edge
+    int32_t c, wd, gw, G, live;
 };
 
 __global__ void __launch_bounds__(64) k_contrib(const ContribItem* __restrict__ items, int n)
@@ -214,64 +219,127 @@ __global__ void __launch_bounds__(64) k_contrib(const ContribItem* __restrict__ 
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const ContribItem I = items[it];
         for (int w = threadIdx.x; w < I.gw; w += blockDim.x) {
-            const uint64_t gm = word_mask(I.G, w), lq = word_mask(I.cnv, w) & ~gm;
-            const size_t cw = (size_t)I.c * I.wd + w;
-            const uint64_t wr = I.W[cw];
-            const uint64_t a1h = I.avf_h[cw] | wr, a1d = I.avf_d[cw] & ~wr;
-            uint64_t lh = 0, ld = 0;
-            for (int e = I.succ_ptr[I.c]; e < I.succ_ptr[I.c + 1]; ++e) {
-                const int t = I.succ_idx[e];
-                lh |= I.nu_h[(size_t)t * I.wd + w];
-                ld |= I.nu_d[(size_t)t * I.wd + w];
+            const uint64_t gm = word_mask(I.G, w);
+            uint64_t h = 0, d = 0;
+            if (I.live) {
+                for (int e = I.succ_ptr[I.c]; e < I.succ_ptr[I.c + 1]; ++e) {
+                    const size_t t = (size_t)I.succ_idx[e] * I.wd + w;
+                    h |= I.a_h[t];
+                    d |= I.a_d[t];
+                }
+            } else {
+                const size_t cw = (size_t)I.c * I.wd + w;
+                const uint64_t wr = I.W[cw];
+                h = I.a_h[cw] | wr;
+                d = I.a_d[cw] & ~wr;
             }
-            atomicAnd((unsigned long long*)&I.acc[w], (unsigned long long)((a1h & gm) | lq));
-            atomicAnd((unsigned long long*)&I.acc[I.gw + w], (unsigned long long)(a1d & gm));
-            atomicOr((unsigned long long*)&I.acc[2 * I.gw + w], (unsigned long long)(lh & gm));
-            atomicOr((unsigned long long*)&I.acc[3 * I.gw + w], (unsigned long long)(ld & gm));
+            I.out[w] = h & gm;
+            I.out[I.gw + w] = d & gm;
         }
     }
 }
 
-// Meet of a context's round contributions into its boundary; globals valid
-// in neither space are taken as valid on the host and demanded at the call
-// site leading to the context.
-struct UpdItem {
-    uint64_t* bnd;            // [4][wd] of the context
-    const uint64_t* acc;      // [4][gw]
-    uint64_t* demand;         // [gw] of the site leading here
-    int32_t* changed;         // per context
-    int32_t wd, gw, G, nv, present;
+// Meet of the latest contributions of every call edge into a context:
+// liveness by OR (exit liveness; the callee's locals are dead after it),
+// validity by AND (entry validity; the callee's locals are valid on the host
+// at its entry).  The boundary is rewritten, and the context marked, when
+// the meet differs from it.
+struct MeetItem {
+    uint64_t* bnd;               // [4][wd] of the context
+    const uint64_t* contrib;     // [n_call_edges][2][gw]
+    const int32_t* in_edges;     // call edges into the context
+    int32_t* changed;
+    int32_t n_in, wd, gw, G, nv, live;
 };
 
-__global__ void __launch_bounds__(64) k_update(const UpdItem* __restrict__ items, int n)
+__global__ void __launch_bounds__(64) k_meet(const MeetItem* __restrict__ items, int n)
 {
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
-        const UpdItem I = items[it];
+        const MeetItem I = items[it];
         bool ch = false;
         for (int w = threadIdx.x; w < I.wd; w += blockDim.x) {
             const uint64_t gm = word_mask(I.G, w), lm = word_mask(I.nv, w) & ~gm;
-            uint64_t a[4];
-            if (w < I.gw) for (int k = 0; k < 4; ++k) a[k] = I.acc[k * I.gw + w];
-            else { a[0] = lm; a[1] = 0; a[2] = 0; a[3] = 0; }
-            uint64_t m[4];
-            if (I.present) {
-                m[0] = I.bnd[w] & a[0];
-                m[1] = I.bnd[I.wd + w] & a[1];
-                m[2] = I.bnd[2 * I.wd + w] | a[2];
-                m[3] = I.bnd[3 * I.wd + w] | a[3];
-            } else
-                for (int k = 0; k < 4; ++k) m[k] = a[k];
-            const uint64_t nowhere = gm & ~(m[0] | m[1]);
-            if (nowhere) {
-                m[0] |= nowhere;
-                atomicOr((unsigned long long*)&I.demand[w], (unsigned long long)nowhere);
+            uint64_t h = I.live ? 0ull : ~0ull, d = h;
+            if (w < I.gw) {
+                for (int k = 0; k < I.n_in; ++k) {
+                    const uint64_t* c = I.contrib + (size_t)I.in_edges[k] * 2 * I.gw;
+                    if (I.live) { h |= c[w]; d |= c[I.gw + w]; }
+                    else { h &= c[w]; d &= c[I.gw + w]; }
+                }
             }
-            for (int k = 0; k < 4; ++k) {
-                if (!I.present || I.bnd[k * I.wd + w] != m[k]) ch = true;
-                I.bnd[k * I.wd + w] = m[k];
-            }
+            const int base = I.live ? 2 : 0;
+            if (I.live) { h &= gm; d &= gm; }
+            else { h = (h & gm) | lm; d &= gm; }
+            uint64_t* bh = I.bnd + (size_t)base * I.wd + w;
+            uint64_t* bd = I.bnd + (size_t)(base + 1) * I.wd + w;
+            if (*bh != h || *bd != d) { *bh = h; *bd = d; ch = true; }
         }
         if (ch) atomicOr(I.changed, 1);
+    }
+}
+
+// Globals a context leaves valid in neither space at its entry and reads
+// there before writing them (next use at ENTRY, either space).
+struct GapItem {
+    uint64_t* gap;               // [gw] of the context
+    const uint64_t *bnd, *nu_h, *nu_d;
+    int32_t* any;
+    int32_t entry, wd, gw, G;
+};
+
+__global__ void __launch_bounds__(64) k_gap(const GapItem* __restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const GapItem I = items[it];
+        for (int w = threadIdx.x; w < I.gw; w += blockDim.x) {
+            const size_t ew = (size_t)I.entry * I.wd + w;
+            const uint64_t need = I.nu_h[ew] | I.nu_d[ew];
+            const uint64_t v = word_mask(I.G, w) & ~(I.bnd[w] | I.bnd[I.wd + w]) & need;
+            I.gap[w] = v;
+            if (v) atomicOr(I.any, 1);
+        }
+    }
+}
+
+// Host-read demand at the call site leading to a context: its gaps that no
+// calling context lacks at its own entry (or every gap, when `all`).
+struct OwnItem {
+    const uint64_t* gaps;        // [n_contexts][gw]
+    const int32_t* callers;      // calling context of each call edge into this one
+    uint64_t* demand;            // [gw] of the leading call site
+    int32_t* any;
+    int32_t x, n_callers, gw, all;
+};
+
+__global__ void __launch_bounds__(64) k_own(const OwnItem* __restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const OwnItem I = items[it];
+        for (int w = threadIdx.x; w < I.gw; w += blockDim.x) {
+            uint64_t inherited = 0;
+            if (!I.all)
+                for (int k = 0; k < I.n_callers; ++k) inherited |= I.gaps[(size_t)I.callers[k] * I.gw + w];
+            const uint64_t own = I.gaps[(size_t)I.x * I.gw + w] & ~inherited;
+            if (own) {
+                atomicOr((unsigned long long*)&I.demand[w], (unsigned long long)own);
+                atomicOr(I.any, 1);
+            }
+        }
+    }
+}
+
+// Plain word copy (initial context boundaries).
+struct CopyItem {
+    uint64_t* dst;
+    const uint64_t* src;
+    int32_t n;
+};
+
+__global__ void __launch_bounds__(64) k_copy(const CopyItem* __restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const CopyItem I = items[it];
+        for (int w = threadIdx.x; w < I.n; w += blockDim.x) I.dst[w] = I.src[w];
     }
 }
 
@@ -460,7 +528,17 @@ struct Prog {
     uint64_t* caps = nullptr;                // [nctx][2][gw]
     int32_t* flag = nullptr;                 // scratch flags
     // per context
-    std::vector<uint64_t*> bnd, ctab, acc;
+    std::vector<uint64_t*> bnd, ctab;
+    // context graph: call edges (caller context, site), numbered caller by caller
+    int n_edges = 0;
+    std::vector<std::vector<int>> eid;       // per context: per site k, its call edge or -1
+    std::vector<int> in_ptr;                 // [nctx+1] into in_edges / callers
+    int32_t* in_edges = nullptr;             // call edges into each context
+    int32_t* callers = nullptr;              // the calling context of each of those edges
+    uint64_t* contrib = nullptr;             // [n_edges][2][gw] latest contribution per edge
+    uint64_t* gaps = nullptr;                // [nctx][gw]
+    uint64_t* bnd0 = nullptr;                // initial boundaries, contexts back to back
+    std::vector<size_t> bnd0_off;
     std::vector<uint64_t*> o_nu_h, o_nu_d, o_ave_h, o_ave_d, o_avf_h, o_avf_d, o_ie_h, o_ie_d, o_ig_h, o_ig_d;
     std::vector<uint8_t*> o_vk, o_ad, o_bd;
     std::vector<char*> ctx_end;              // end of each context's arena region (bnd .. outputs)
@@ -545,14 +623,42 @@ int setup(Prog& G)
     const size_t oDn = take(8 * (size_t)std::max(st.nc, 1) * gw);
     const size_t oC = take(8 * (size_t)nctx * 2 * gw);
     const size_t oF = take(4 * (size_t)(nctx + 16));
-    struct CO { size_t bnd, ctab, acc, out; };
+    // call edges of the context graph and, per context, the edges into it
+    G.eid.assign(nctx, {});
+    G.n_edges = 0;
+    std::vector<int> indeg(nctx + 1, 0);
+    for (int x = 0; x < nctx; ++x) {
+        G.eid[x].assign(st.child[x].size(), -1);
+        for (size_t k = 0; k < st.child[x].size(); ++k)
+            if (st.child[x][k] >= 0) { G.eid[x][k] = G.n_edges++; ++indeg[st.child[x][k]]; }
+    }
+    G.in_ptr.assign(nctx + 1, 0);
+    for (int x = 0; x < nctx; ++x) G.in_ptr[x + 1] = G.in_ptr[x] + indeg[x];
+    std::vector<int32_t> h_in(std::max(G.n_edges, 1)), h_callers(std::max(G.n_edges, 1));
+    {
+        std::vector<int> fill(G.in_ptr.begin(), G.in_ptr.end() - 1);
+        for (int x = 0; x < nctx; ++x)
+            for (size_t k = 0; k < st.child[x].size(); ++k) {
+                const int cx = st.child[x][k];
+                if (cx < 0) continue;
+                h_in[fill[cx]] = G.eid[x][k];
+                h_callers[fill[cx]++] = x;
+            }
+    }
+    const size_t oCb = take(8 * (size_t)std::max(G.n_edges, 1) * 2 * gw);
+    const size_t oIn = take(4 * h_in.size());
+    const size_t oCl = take(4 * h_callers.size());
+    const size_t oGap = take(8 * (size_t)nctx * gw);
+    G.bnd0_off.assign(nctx + 1, 0);
+    for (int x = 0; x < nctx; ++x) G.bnd0_off[x + 1] = G.bnd0_off[x] + 4 * (size_t)st.wd[st.cproc[x]];
+    const size_t oB0 = take(8 * G.bnd0_off[nctx]);
+    struct CO { size_t bnd, ctab, out; };
     std::vector<CO> co(nctx);
     for (int x = 0; x < nctx; ++x) {
         const int p = st.cproc[x];
         const size_t nb = st.nb[p], ne = st.ne[p], wd = st.wd[p], ns = st.sites[p].size();
         co[x].bnd = take(8 * 4 * wd);
         co[x].ctab = take(8 * ns * SUM_ROWS * wd);
-        co[x].acc = take(8 * 4 * gw);
         co[x].out = take(8 * (8 * nb * wd + 2 * ne * wd) + (size_t)P->procs[p].n_vars + 2 * nb + 64);
     }
     const size_t oItems = take(64ull << 20);   // staging of kernel work items
@@ -617,7 +723,46 @@ int setup(Prog& G)
     G.caps = (uint64_t*)(A + oC);
     G.flag = (int32_t*)(A + oF);
     CK(hipMemsetAsync(G.demand, 0, 8 * (size_t)std::max(st.nc, 1) * gw, G.s));
-    G.bnd.resize(nctx); G.ctab.resize(nctx); G.acc.resize(nctx);
+    G.contrib = (uint64_t*)(A + oCb);
+    G.in_edges = (int32_t*)(A + oIn);
+    G.callers = (int32_t*)(A + oCl);
+    G.gaps = (uint64_t*)(A + oGap);
+    G.bnd0 = (uint64_t*)(A + oB0);
+    CK(hipMemcpyAsync(G.in_edges, h_in.data(), 4 * h_in.size(), hipMemcpyHostToDevice, G.s));
+    CK(hipMemcpyAsync(G.callers, h_callers.data(), 4 * h_callers.size(), hipMemcpyHostToDevice, G.s));
+    // initial boundaries: a root context its procedure's own (defaults: valid and live on the
+    // host only); any other context valid everywhere on the globals (the top of the validity
+    // meet), its locals valid on the host, nothing live after its exit
+    {
+        std::vector<uint64_t> b0(std::max<size_t>(G.bnd0_off[nctx], 1), 0);
+        for (int x = 0; x < nctx; ++x) {
+            const int p = st.cproc[x];
+            const ompd_cfg& g = P->procs[p];
+            const size_t wd = st.wd[p];
+            uint64_t* b = b0.data() + G.bnd0_off[x];
+            for (size_t w = 0; w < wd; ++w) {
+                const int lo = 64 * (int)w;
+                auto mask = [&](int bits) -> uint64_t {
+                    if (bits >= lo + 64) return ~0ull;
+                    if (bits <= lo) return 0ull;
+                    return (1ull << (bits - lo)) - 1ull;
+                };
+                const uint64_t vm = mask(g.n_vars), gm = mask(st.G);
+                if (st.cs1[x] < 0) {
+                    b[w] = g.entry_valid_host ? g.entry_valid_host[w] : vm;
+                    b[wd + w] = g.entry_valid_dev ? g.entry_valid_dev[w] : 0;
+                    b[2 * wd + w] = g.exit_live_host ? g.exit_live_host[w] : vm;
+                    b[3 * wd + w] = g.exit_live_dev ? g.exit_live_dev[w] : 0;
+                } else {
+                    b[w] = vm;
+                    b[wd + w] = gm;
+                }
+            }
+        }
+        CK(hipMemcpyAsync(G.bnd0, b0.data(), 8 * b0.size(), hipMemcpyHostToDevice, G.s));
+        CK(hipStreamSynchronize(G.s));
+    }
+    G.bnd.resize(nctx); G.ctab.resize(nctx);
     for (auto* v : {&G.o_nu_h, &G.o_nu_d, &G.o_ave_h, &G.o_ave_d, &G.o_avf_h, &G.o_avf_d, &G.o_ie_h, &G.o_ie_d,
                     &G.o_ig_h, &G.o_ig_d})
         v->resize(nctx);
@@ -628,7 +773,6 @@ int setup(Prog& G)
         const size_t nb = st.nb[p], ne = st.ne[p], wd = st.wd[p];
         G.bnd[x] = (uint64_t*)(A + co[x].bnd);
         G.ctab[x] = (uint64_t*)(A + co[x].ctab);
-        G.acc[x] = (uint64_t*)(A + co[x].acc);
         uint64_t* o = (uint64_t*)(A + co[x].out);
         const size_t bv = nb * wd, evv = ne * wd;
         G.o_nu_h[x] = o; G.o_nu_d[x] = o + bv; G.o_ave_h[x] = o + 2 * bv; G.o_ave_d[x] = o + 3 * bv;
@@ -807,68 +951,61 @@ int summarize(Prog& G)
     return OMPD_OK;
 }
 
-// Top-down rounds over the contexts of one outer round.
-int contexts(Prog& G)
+// Solve a set of contexts with their current boundaries and call tables
+// (summary mode: a non-root context may leave a global valid nowhere).
+int solve_contexts(Prog& G, const std::vector<int>& xs)
+{
+    const Structure& st = G.st;
+    std::vector<CallTabItem> ct;
+    for (int x : xs) calltab_items(G, st.cproc[x], x, ct);
+    int rc = upload_items(ct, k_calltab, 256, G.s, G.arena_items);
+    if (rc) return rc;
+    std::vector<ompd_cfg> cfgs;
+    std::vector<ompd_result> res;
+    for (int x : xs) {
+        const int p = st.cproc[x];
+        const size_t wd = st.wd[p];
+        ompd_cfg d = dev_cfg(G, p);
+        if (d.call_summary) d.summaries = G.ctab[x];
+        d.entry_valid_host = G.bnd[x]; d.entry_valid_dev = G.bnd[x] + wd;
+        d.exit_live_host = G.bnd[x] + 2 * wd; d.exit_live_dev = G.bnd[x] + 3 * wd;
+        ompd_result r;
+        memset(&r, 0, sizeof r);
+        r.nu_host = G.o_nu_h[x]; r.nu_dev = G.o_nu_d[x]; r.ave_host = G.o_ave_h[x]; r.ave_dev = G.o_ave_d[x];
+        r.avf_host = G.o_avf_h[x]; r.avf_dev = G.o_avf_d[x];
+        r.ins_entry_to_host = G.o_ie_h[x]; r.ins_entry_to_dev = G.o_ie_d[x];
+        r.ins_edge_to_host = G.o_ig_h[x]; r.ins_edge_to_dev = G.o_ig_d[x];
+        r.var_kind = G.o_vk[x]; r.after_dev = G.o_ad[x]; r.before_dev = G.o_bd[x];
+        cfgs.push_back(d);
+        res.push_back(r);
+    }
+    rc = run_batch(G, cfgs, res, OMPD_F_SUMMARY);
+    if (rc) return rc;
+    for (size_t i = 0; i < xs.size(); ++i) memcpy(&G.sweeps[(size_t)xs[i] * 6], res[i].sweeps, sizeof res[i].sweeps);
+    return OMPD_OK;
+}
+
+// One monotone boundary system over the context graph, solved by rounds:
+// every context whose boundary changed is solved, each of its calls writes
+// its contribution to its edge slot, and every context reached recomputes the
+// meet over all edges into it.  live = 1: exit liveness (least fixed point,
+// contributions only grow); live = 0: entry validity (greatest fixed point,
+// contributions only shrink).  Each system has one fixed point, so the order
+// of the solves does not matter.  Every context is solved in the first round,
+// so every edge slot holds a contribution before any meet reads it.
+int boundary_system(Prog& G, int live)
 {
     const Structure& st = G.st;
     const ompd_program* P = G.P;
     const int nctx = (int)st.cproc.size(), gw = st.gw;
-    std::vector<char> present(nctx, 0);
-    CK(hipMemsetAsync(G.demand_new, 0, 8 * (size_t)std::max(st.nc, 1) * gw, G.s));
-    // root contexts: their own boundaries
-    std::vector<int> dirty;
-    for (int x = 0; x < nctx; ++x) {
-        if (st.cs1[x] >= 0) continue;
-        const int p = st.cproc[x];
-        const ompd_cfg& g = P->procs[p];
-        const size_t wd = st.wd[p];
-        std::vector<uint64_t> b(4 * wd, 0);
-        for (size_t w = 0; w < wd; ++w) {
-            const int lo = 64 * (int)w;
-            const uint64_t m = g.n_vars >= lo + 64 ? ~0ull : (g.n_vars <= lo ? 0ull : (1ull << (g.n_vars - lo)) - 1ull);
-            b[w] = g.entry_valid_host ? g.entry_valid_host[w] : m;
-            b[wd + w] = g.entry_valid_dev ? g.entry_valid_dev[w] : 0;
-            b[2 * wd + w] = g.exit_live_host ? g.exit_live_host[w] : m;
-            b[3 * wd + w] = g.exit_live_dev ? g.exit_live_dev[w] : 0;
-        }
-        if (wd) CK(hipMemcpyAsync(G.bnd[x], b.data(), 8 * 4 * wd, hipMemcpyHostToDevice, G.s));
-        CK(hipStreamSynchronize(G.s));
-        present[x] = 1;
-        dirty.push_back(x);
-    }
-    std::vector<uint64_t> acc_init;
+    std::vector<int> dirty(nctx);
+    for (int x = 0; x < nctx; ++x) dirty[x] = x;
+    std::vector<char> is_t(nctx, 0);
+    std::vector<int32_t> hc(nctx);
     while (!dirty.empty()) {
-        // solve every dirty context
-        std::vector<CallTabItem> ct;
-        for (int x : dirty) calltab_items(G, st.cproc[x], x, ct);
-        int rc = upload_items(ct, k_calltab, 256, G.s, G.arena_items);
+        int rc = solve_contexts(G, dirty);
         if (rc) return rc;
-        std::vector<ompd_cfg> cfgs;
-        std::vector<ompd_result> res;
-        for (int x : dirty) {
-            const int p = st.cproc[x];
-            const size_t wd = st.wd[p];
-            ompd_cfg d = dev_cfg(G, p);
-            if (d.call_summary) d.summaries = G.ctab[x];
-            d.entry_valid_host = G.bnd[x]; d.entry_valid_dev = G.bnd[x] + wd;
-            d.exit_live_host = G.bnd[x] + 2 * wd; d.exit_live_dev = G.bnd[x] + 3 * wd;
-            ompd_result r;
-            memset(&r, 0, sizeof r);
-            r.nu_host = G.o_nu_h[x]; r.nu_dev = G.o_nu_d[x]; r.ave_host = G.o_ave_h[x]; r.ave_dev = G.o_ave_d[x];
-            r.avf_host = G.o_avf_h[x]; r.avf_dev = G.o_avf_d[x];
-            r.ins_entry_to_host = G.o_ie_h[x]; r.ins_entry_to_dev = G.o_ie_d[x];
-            r.ins_edge_to_host = G.o_ig_h[x]; r.ins_edge_to_dev = G.o_ig_d[x];
-            r.var_kind = G.o_vk[x]; r.after_dev = G.o_ad[x]; r.before_dev = G.o_bd[x];
-            cfgs.push_back(d);
-            res.push_back(r);
-        }
-        rc = run_batch(G, cfgs, res, 0);
-        if (rc) return rc;
-        for (size_t i = 0; i < dirty.size(); ++i)
-            memcpy(&G.sweeps[(size_t)dirty[i] * 6], res[i].sweeps, sizeof res[i].sweeps);
-        // contributions of every solved call to its callee context
         std::vector<int> touched;
-        std::vector<char> is_t(nctx, 0);
         std::vector<ContribItem> cb;
         for (int x : dirty) {
             const int p = st.cproc[x];
@@ -877,47 +1014,96 @@ int contexts(Prog& G)
                 if (cx < 0) continue;
                 if (!is_t[cx]) { is_t[cx] = 1; touched.push_back(cx); }
                 ContribItem I;
-                I.avf_h = G.o_avf_h[x]; I.avf_d = G.o_avf_d[x]; I.nu_h = G.o_nu_h[x]; I.nu_d = G.o_nu_d[x];
+                I.a_h = live ? G.o_nu_h[x] : G.o_ave_h[x];
+                I.a_d = live ? G.o_nu_d[x] : G.o_ave_d[x];
                 I.W = G.W[p]; I.succ_ptr = G.sp[p]; I.succ_idx = G.si[p];
-                I.acc = G.acc[cx];
-                I.c = P->call_block[st.sites[p][k]]; I.wd = st.wd[p]; I.gw = gw; I.G = st.G;
-                I.cnv = P->procs[st.cproc[cx]].n_vars;
+                I.out = G.contrib + (size_t)G.eid[x][k] * 2 * gw;
+                I.c = P->call_block[st.sites[p][k]]; I.wd = st.wd[p]; I.gw = gw; I.G = st.G; I.live = live;
                 cb.push_back(I);
             }
         }
-        // accumulators start at the meet's identity: validity all ones, liveness none
-        acc_init.assign(4 * (size_t)gw, 0);
-        for (int w = 0; w < 2 * gw; ++w) acc_init[w] = ~0ull;
-        for (int cx : touched)
-            CK(hipMemcpyAsync(G.acc[cx], acc_init.data(), 8 * 4 * gw, hipMemcpyHostToDevice, G.s));
         rc = upload_items(cb, k_contrib, 64, G.s, G.arena_items);
         if (rc) return rc;
-        // meet into the boundaries
         int32_t* chg = G.flag + 16;
         CK(hipMemsetAsync(chg, 0, 4 * (size_t)nctx, G.s));
-        std::vector<UpdItem> up;
+        std::vector<MeetItem> mi;
         for (int cx : touched) {
+            is_t[cx] = 0;
             const int q = st.cproc[cx];
-            UpdItem I;
-            I.bnd = G.bnd[cx]; I.acc = G.acc[cx];
-            I.demand = G.demand_new + (size_t)st.cs1[cx] * gw;
-            I.changed = chg + cx;
-            I.wd = st.wd[q]; I.gw = gw; I.G = st.G; I.nv = P->procs[q].n_vars; I.present = present[cx];
-            up.push_back(I);
+            MeetItem I;
+            I.bnd = G.bnd[cx]; I.contrib = G.contrib; I.in_edges = G.in_edges + G.in_ptr[cx];
+            I.changed = chg + cx; I.n_in = G.in_ptr[cx + 1] - G.in_ptr[cx];
+            I.wd = st.wd[q]; I.gw = gw; I.G = st.G; I.nv = P->procs[q].n_vars; I.live = live;
+            mi.push_back(I);
         }
-        rc = upload_items(up, k_update, 64, G.s, G.arena_items);
+        rc = upload_items(mi, k_meet, 64, G.s, G.arena_items);
         if (rc) return rc;
-        std::vector<int32_t> hc(nctx);
         CK(hipMemcpyAsync(hc.data(), chg, 4 * (size_t)nctx, hipMemcpyDeviceToHost, G.s));
         CK(hipStreamSynchronize(G.s));
         dirty.clear();
-        for (int cx : touched) {
-            present[cx] = 1;
+        for (int cx : touched)
             if (hc[cx]) dirty.push_back(cx);
-        }
         std::sort(dirty.begin(), dirty.end());
     }
     return OMPD_OK;
+}
+
+// Contexts of one outer round: fresh initial boundaries, the exit-liveness
+// system, then the entry-validity system with that liveness (its last solve
+// of every context is the context's final solution), then the host-read
+// demands of the globals the contexts leave valid nowhere but read before
+// writing them: each at the call site leading to the context, unless a
+// calling context lacks that global at its own entry; when that leaves no
+// demand at all (a cycle of recursive contexts), every gap is demanded.
+int contexts(Prog& G)
+{
+    const Structure& st = G.st;
+    const ompd_program* P = G.P;
+    const int nctx = (int)st.cproc.size(), gw = st.gw;
+    CK(hipMemsetAsync(G.demand_new, 0, 8 * (size_t)std::max(st.nc, 1) * gw, G.s));
+    std::vector<CopyItem> cp;
+    for (int x = 0; x < nctx; ++x) {
+        CopyItem I;
+        I.dst = G.bnd[x]; I.src = G.bnd0 + G.bnd0_off[x]; I.n = (int32_t)(G.bnd0_off[x + 1] - G.bnd0_off[x]);
+        cp.push_back(I);
+    }
+    int rc = upload_items(cp, k_copy, 64, G.s, G.arena_items);
+    if (rc) return rc;
+    rc = boundary_system(G, 1);
+    if (rc) return rc;
+    rc = boundary_system(G, 0);
+    if (rc) return rc;
+    if (!gw) return OMPD_OK;
+    CK(hipMemsetAsync(G.gaps, 0, 8 * (size_t)nctx * gw, G.s));
+    int32_t* any = G.flag;
+    CK(hipMemsetAsync(any, 0, 8, G.s));
+    std::vector<GapItem> gi;
+    std::vector<OwnItem> oi;
+    for (int x = 0; x < nctx; ++x) {
+        if (st.cs1[x] < 0) continue;
+        const int p = st.cproc[x];
+        GapItem I;
+        I.gap = G.gaps + (size_t)x * gw; I.bnd = G.bnd[x]; I.nu_h = G.o_nu_h[x]; I.nu_d = G.o_nu_d[x];
+        I.any = any; I.entry = P->procs[p].entry; I.wd = st.wd[p]; I.gw = gw; I.G = st.G;
+        gi.push_back(I);
+        OwnItem O;
+        O.gaps = G.gaps; O.callers = G.callers + G.in_ptr[x]; O.demand = G.demand_new + (size_t)st.cs1[x] * gw;
+        O.any = any + 1; O.x = x; O.n_callers = G.in_ptr[x + 1] - G.in_ptr[x]; O.gw = gw; O.all = 0;
+        oi.push_back(O);
+    }
+    rc = upload_items(gi, k_gap, 64, G.s, G.arena_items);
+    if (rc) return rc;
+    int32_t flags[2];
+    CK(hipMemcpyAsync(flags, any, 8, hipMemcpyDeviceToHost, G.s));
+    CK(hipStreamSynchronize(G.s));
+    if (!flags[0]) return OMPD_OK;
+    rc = upload_items(oi, k_own, 64, G.s, G.arena_items);
+    if (rc) return rc;
+    CK(hipMemcpyAsync(flags, any, 8, hipMemcpyDeviceToHost, G.s));
+    CK(hipStreamSynchronize(G.s));
+    if (flags[1]) return OMPD_OK;
+    for (auto& O : oi) O.all = 1;
+    return upload_items(oi, k_own, 64, G.s, G.arena_items);
 }
 
 }  // namespace
