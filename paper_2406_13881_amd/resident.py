@@ -135,6 +135,27 @@ class ResidentBatch:
             out[k] = a
         return out
 
+    def fetch_all(self):
+        """Copy every output of the batch to the host at once (one copy per output) and
+        return a function i -> CFG i's outputs (views, shapes as fetch(i))."""
+        host = {k: self.out[k].cpu().numpy() for k in self.want}
+        nb, ne, nv, wd = self.nb, self.ne, self.nv, self.wd
+
+        def get(i: int) -> Dict[str, np.ndarray]:
+            out = {}
+            for k in self.want:
+                a = host[k]
+                if k.startswith("ins_edge"):
+                    out[k] = a[int(self.o_ew[i]):int(self.o_ew[i + 1])].view(np.uint64).reshape(int(ne[i]), int(wd[i]))
+                elif k == "var_kind":
+                    out[k] = a[int(self.o_var[i]):int(self.o_var[i + 1])]
+                elif k in ("after_dev", "before_dev"):
+                    out[k] = a[int(self.o_blk[i]):int(self.o_blk[i + 1])]
+                else:
+                    out[k] = a[int(self.o_bw[i]):int(self.o_bw[i + 1])].view(np.uint64).reshape(int(nb[i]), int(wd[i]))
+            return out
+        return get
+
     def close(self):
         if getattr(self, "plan", None) is not None:
             self.plan.close()

@@ -303,6 +303,42 @@ def from_edges(blocks: Sequence[Tuple[int, Sequence[int], Sequence[int]]],
                space=space, R=R, W=W), csr_pos
 
 
+def permute_blocks(cfg: CFG, seed: int) -> Tuple[CFG, np.ndarray, np.ndarray]:
+    """The same CFG with its block ids shuffled (ENTRY and EXIT keep theirs).
+
+    Returns (permuted CFG, perm, edge_map): block b of ``cfg`` is block
+    perm[b] of the result, and edge e of ``cfg`` (successor-CSR order) is
+    edge edge_map[e] of the result.  Each block keeps its successors in their
+    order, kinds and accesses; boundaries are carried over."""
+    nb = cfg.n_blocks
+    rng = np.random.Generator(np.random.PCG64(seed))
+    others = np.array([b for b in range(nb) if b not in (cfg.entry, cfg.exit)], dtype=np.int64)
+    perm = np.arange(nb, dtype=np.int64)
+    perm[others] = others[rng.permutation(len(others))]
+    inv = np.empty(nb, dtype=np.int64)
+    inv[perm] = np.arange(nb)
+    sp = np.asarray(cfg.succ_ptr, dtype=np.int64)
+    si = np.asarray(cfg.succ_idx, dtype=np.int64)
+    deg = np.diff(sp)
+    ptr = np.zeros(nb + 1, dtype=np.int64)
+    np.cumsum(deg[inv], out=ptr[1:])
+    succ_idx = np.zeros(si.shape[0], dtype=np.int32)
+    kind = np.zeros(si.shape[0], dtype=np.uint8)
+    edge_map = np.zeros(si.shape[0], dtype=np.int64)
+    for nbk in range(nb):
+        o = int(inv[nbk])
+        a, z = int(sp[o]), int(sp[o + 1])
+        succ_idx[ptr[nbk]:ptr[nbk] + (z - a)] = perm[si[a:z]]
+        kind[ptr[nbk]:ptr[nbk] + (z - a)] = np.asarray(cfg.edge_kind)[a:z]
+        edge_map[a:z] = np.arange(ptr[nbk], ptr[nbk] + (z - a))
+    out = CFG(n_blocks=nb, n_vars=cfg.n_vars, succ_ptr=ptr.astype(np.int32), succ_idx=succ_idx, edge_kind=kind,
+              space=np.ascontiguousarray(np.asarray(cfg.space)[inv]), R=np.ascontiguousarray(np.asarray(cfg.R)[inv]),
+              W=np.ascontiguousarray(np.asarray(cfg.W)[inv]), entry=int(perm[cfg.entry]), exit=int(perm[cfg.exit]),
+              entry_valid_h=cfg.entry_valid_h, entry_valid_d=cfg.entry_valid_d, exit_live_h=cfg.exit_live_h,
+              exit_live_d=cfg.exit_live_d, seed=cfg.seed)
+    return out, perm, edge_map
+
+
 def random_dag(seed: int, n_blocks: int, n_vars: int, p_extra: float = 0.3, p_dev: float = 0.4,
                p_read: float = 0.3, p_write: float = 0.2, p_loop_entry: float = 0.0) -> CFG:
     """Small random acyclic CFG (unstructured).  Every block has a

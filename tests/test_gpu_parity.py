@@ -63,13 +63,48 @@ def test_worked_examples(ctx):
         assert_same(cfg, got[i], oracle.solve(cfg), "example %d" % i)
 
 
+def _oracle_many(cfgs, placement=0):
+    """Oracle results of many CFGs on every host core (the oracle is C; ctypes
+    releases the interpreter lock while it runs)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(lambda c: oracle.solve(c, placement=placement), cfgs))
+
+
 def test_config1_sweep(ctx):
-    """Config 1 shape: 300 seeded CFGs of 64 blocks x 32 variables in one batch."""
-    cfgs = [synth.c1(i) for i in range(300)]
+    """Config 1 shape: 10,000 seeded CFGs of 64 blocks x 32 variables in one batch."""
+    cfgs = [synth.c1(i) for i in range(10_000)]
     _print("c1 sweep: %d CFGs" % len(cfgs))
     got = ctx.analyze_batch(cfgs)
+    refs = _oracle_many(cfgs)
     for i, cfg in enumerate(cfgs):
-        assert_same(cfg, got[i], oracle.solve(cfg), "c1 #%d" % i)
+        assert_same(cfg, got[i], refs[i], "c1 #%d" % i)
+
+
+def test_config1_permuted_ids(ctx):
+    """The config-1 sweep with block ids shuffled (ENTRY and EXIT kept): forward edges now
+    point backwards in id order, so the walk meets neighbours not yet visited in the sweep
+    and steps with two far neighbours.  Every output equals the oracle's on the shuffled CFG."""
+    cfgs = [synth.permute_blocks(synth.c1(i), 50_000 + i)[0] for i in range(2_000)]
+    _print("c1 permuted: %d CFGs" % len(cfgs))
+    got = ctx.analyze_batch(cfgs)
+    refs = _oracle_many(cfgs)
+    for i, cfg in enumerate(cfgs):
+        assert_same(cfg, got[i], refs[i], "c1 permuted #%d" % i)
+
+
+def test_config3_items_permuted_ids(ctx):
+    """Twenty config-3 items (seeded picks of up to 2,048 blocks) with shuffled block ids,
+    solved in one batch: every output equals the oracle's."""
+    nbs, _ = synth.c3_sizes()
+    small = [i for i in range(len(nbs)) if nbs[i] <= 2048]
+    picks = sorted(int(i) for i in np.random.default_rng(4242).choice(small, 20, replace=False))
+    cfgs = [synth.permute_blocks(synth.c3_item(i), 60_000 + i)[0] for i in picks]
+    _print("c3 permuted: items %s, blocks %s" % (picks, [c.n_blocks for c in cfgs]))
+    got = ctx.analyze_batch(cfgs)
+    refs = _oracle_many(cfgs)
+    for i, cfg in enumerate(cfgs):
+        assert_same(cfg, got[i], refs[i], "c3 permuted item %d" % picks[i])
 
 
 @pytest.mark.parametrize("seed", range(4))
@@ -204,22 +239,18 @@ def test_ring_sizes_match_oracle(ctx):
             assert_same(cfg, got[i], refs[i], "ring %d #%d" % (rs, i))
 
 
-def test_config3_batch_resident_sampled(ctx):
+def test_config3_batch_resident_full(ctx):
     """Config 3 at full size in the launch configuration the benchmark times:
     the 4,096-CFG batch resident in device memory under one plan, run twice
     (the second run overwrites the first run's outputs).  Every CFG reports
-    success, and every output of a sample of CFGs (the most blocks, the
-    fewest, the most variables, the fewest, the most block words, and seeded
-    random picks) equals the oracle's."""
+    success and every output of every one of the 4,096 CFGs equals the
+    oracle's (the oracle runs on all host cores)."""
     import torch
+    from concurrent.futures import ThreadPoolExecutor
     from paper_2406_13881_amd.resident import ResidentBatch
     cfgs = synth.c3(4096, threads=8)
     nb = np.array([c.n_blocks for c in cfgs])
-    nv = np.array([c.n_vars for c in cfgs])
-    picks = {int(nb.argmax()), int(nb.argmin()), int(nv.argmax()), int(nv.argmin()),
-             int((nb * ((nv + 63) // 64)).argmax())}
-    picks |= set(int(i) for i in np.random.default_rng(2406).choice(len(cfgs), 8, replace=False))
-    _print("c3 batch: %d CFGs, %d blocks, checking %s" % (len(cfgs), int(nb.sum()), sorted(picks)))
+    _print("c3 batch: %d CFGs, %d blocks" % (len(cfgs), int(nb.sum())))
     rb = ResidentBatch(ctx, cfgs)
     try:
         stream = torch.cuda.current_stream().cuda_stream
@@ -227,8 +258,20 @@ def test_config3_batch_resident_sampled(ctx):
         rb.run(stream)
         torch.cuda.synchronize()
         assert (rb.plan.status() == 0).all()
-        for i in sorted(picks):
-            assert_same(cfgs[i], rb.fetch(i), oracle.solve(cfgs[i]), "c3 #%d" % i)
+        host = rb.fetch_all()
+        _print("c3 batch: outputs on the host, comparing")
+
+        def check(i):
+            assert_same(cfgs[i], host(i), oracle.solve(cfgs[i]), "c3 #%d" % i)
+            return i
+
+        order = np.argsort(-nb)          # largest first, so the pool ends on small ones
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            done = 0
+            for _ in ex.map(check, [int(i) for i in order]):
+                done += 1
+                if done % 1024 == 0:
+                    _print("c3 batch: %d of %d CFGs equal the oracle" % (done, len(cfgs)))
     finally:
         rb.close()
 
@@ -281,3 +324,40 @@ def test_wide_fan_in_and_fan_out(ctx):
     for rs in (8, 64):
         got = ctx.analyze_batch([cfg], flags=ompd.F_RING_SLOTS(rs))[0]
         assert_same(cfg, got, ref, "fan ring %d" % rs)
+
+
+def test_wait_limit_gives_up_and_recovers(ctx):
+    """With a wait bound of one nanosecond every wait of the solve kernels that does not succeed
+    at once gives up: the kernels still end normally, every CFG of a resident plan reports
+    OMPD_E_DEVICE, and the error names the phase, the tile and the counter that did not move.
+    With the default bound restored, a new plan over the same CFGs solves them exactly."""
+    import torch
+    import paper_2406_13881_amd as ompd
+    from paper_2406_13881_amd.resident import ResidentBatch
+    cfgs = [synth.c1(i) for i in range(40)] + [synth.c3_item(i) for i in range(8)]
+    ctx.set_wait_limit(1)
+    try:
+        with pytest.raises(ompd.OmpdError) as ei:
+            ctx.analyze_batch(cfgs[:4])
+        assert ei.value.code == ompd.OMPD_E_DEVICE
+        assert "gave up" in str(ei.value), str(ei.value)
+        _print("give-up message: %s" % ei.value)
+        rb = ResidentBatch(ctx, cfgs)
+        try:
+            rb.run(torch.cuda.current_stream().cuda_stream)
+            torch.cuda.synchronize()
+            st = rb.plan.status()
+            assert (st == ompd.OMPD_E_DEVICE).all(), st.tolist()
+        finally:
+            rb.close()
+    finally:
+        ctx.set_wait_limit(0)
+    rb = ResidentBatch(ctx, cfgs)
+    try:
+        rb.run(torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        assert (rb.plan.status() == 0).all()
+        for i, cfg in enumerate(cfgs):
+            assert_same(cfg, rb.fetch(i), oracle.solve(cfg), "after the bound is restored #%d" % i)
+    finally:
+        rb.close()

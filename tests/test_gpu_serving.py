@@ -31,11 +31,24 @@ def mixed_requests():
     return cfgs
 
 
+def c5_requests():
+    """Config-5 requests: config-2-shaped CFGs (16,384 blocks x 2,048 variables)."""
+    return [synth.c5_request(i) for i in range(8)]
+
+
 def test_serving_mix_matches_alone_and_oracle():
     import paper_2406_13881_amd as ompd
     ctx = ompd.Context(0, budget_bytes=8 << 30)
-    cfgs = mixed_requests()
-    print("serving mix: %d requests" % len(cfgs), flush=True)
+    small = mixed_requests()
+    big = c5_requests()
+    # the config-5 requests arrive interleaved with the others
+    cfgs = []
+    for i, c in enumerate(small):
+        cfgs.append(c)
+        if i % 5 == 2 and big:
+            cfgs.append(big.pop(0))
+    cfgs += big
+    print("serving mix: %d requests (%d config-5)" % (len(cfgs), sum(c.n_blocks > 16_000 for c in cfgs)), flush=True)
     reqs = []
     for i, c in enumerate(cfgs):
         r = ompd.submit(ctx, c)
@@ -45,11 +58,18 @@ def test_serving_mix_matches_alone_and_oracle():
             time.sleep(0.002)          # let some requests start before the next ones arrive
     for r in reqs:
         r.wait(120.0)
+    print("serving mix: all requests done", flush=True)
+    from concurrent.futures import ThreadPoolExecutor
+    import os
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        refs = list(ex.map(oracle.solve, cfgs))
     alone = ctx.analyze_batch(cfgs[:6])
     for i, (c, r) in enumerate(zip(cfgs, reqs)):
-        same(r.out, oracle.solve(c), "request %d vs oracle" % i)
+        same(r.out, refs[i], "request %d vs oracle" % i)
         if i < 6:
             same(r.out, alone[i], "request %d vs alone" % i)
+        if c.n_blocks > 16_000:
+            same(r.out, ctx.analyze_cfg(c), "config-5 request %d vs alone" % i)
     st = ompd.serving_stats(ctx)
     assert st["completed"] == len(cfgs) and st["in_flight"] == 0 and st["bytes_in_use"] == 0
     ctx.close()
