@@ -159,6 +159,18 @@ const char* ompd_last_error(const ompd_ctx* ctx);
 /* Device facts the solver plans with: compute units, LDS bytes a workgroup
  * of the solve kernel may use, and device memory.  Any pointer may be NULL. */
 int ompd_device_info(ompd_ctx* ctx, int32_t* n_cu, int32_t* lds_bytes, int64_t* mem_bytes);
+/* Bound of a wait inside the solve kernels.  The two wavefronts of a solve
+ * workgroup (one computes the steps of the walk, the other feeds it inputs
+ * and stores its results) wait for each other; a wait that sees no progress
+ * for `ns` nanoseconds of the device's wall clock gives up, both wavefronts
+ * stop, the CFG's status becomes OMPD_E_DEVICE, and ompd_last_error names
+ * the phase, the tile and the counter that did not move (a bug in the
+ * library, never a property of the input: a legitimate wait lasts one step
+ * of the other wavefront, microseconds).  Applies to plans built and
+ * requests launched after the call.  ns = 0 restores the default (2 s); ns
+ * < 0 is OMPD_E_INVAL.  A tiny bound makes every wait give up at once (every
+ * kernel still exits normally), which is how the give-up path is tested. */
+int ompd_set_wait_limit(ompd_ctx* ctx, int64_t ns);
 
 /* Solve one CFG; synchronous (returns when the results are in `res`).
  * Errors: OMPD_E_INVAL for a malformed CFG, OMPD_E_NOCONVERGE if a sweep

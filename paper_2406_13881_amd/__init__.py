@@ -139,6 +139,7 @@ def lib():
             L.ompd_last_error.argtypes = [_vp]
             L.ompd_last_error.restype = ctypes.c_char_p
             L.ompd_device_info.argtypes = [_vp, P(_i32), P(_i32), P(ctypes.c_int64)]
+            L.ompd_set_wait_limit.argtypes = [_vp, ctypes.c_int64]
             L.ompd_analyze_cfg.argtypes = [_vp, P(_Cfg), P(_Res), ctypes.c_uint32, _vp]
             L.ompd_analyze_batch.argtypes = [_vp, P(_Cfg), P(_Res), _i32, ctypes.c_uint32, _vp]
             L.ompd_plan_create.argtypes = [_vp, P(_Cfg), P(_Res), _i32, ctypes.c_uint32, P(_vp)]
@@ -329,6 +330,10 @@ class Context:
         cu, lds, mem = _i32(0), _i32(0), ctypes.c_int64(0)
         _check(lib().ompd_device_info(self.h, ctypes.byref(cu), ctypes.byref(lds), ctypes.byref(mem)))
         return {"n_cu": cu.value, "lds_bytes": lds.value, "mem_bytes": mem.value}
+
+    def set_wait_limit(self, ns: int = 0):
+        """ompd_set_wait_limit: bound of a solve kernel's wait without progress (0 = default)."""
+        _check(lib().ompd_set_wait_limit(self.h, int(ns)))
 
     # -- one-shot, host pointers ------------------------------------------------
     def analyze_cfg(self, cfg, flags: int = 0, want: Sequence[str] = OUTPUTS) -> Dict[str, np.ndarray]:
@@ -542,8 +547,9 @@ class Plan:
 
     def status(self) -> np.ndarray:
         per = np.zeros(max(self.n, 1), np.int32)
+        per[:] = 1   # a HIP failure before the per-CFG words are read leaves this (not a status)
         rc = lib().ompd_plan_status(self.h, _vp(per.ctypes.data))
-        if rc not in (0, OMPD_E_INVAL, OMPD_E_NOCONVERGE):
+        if rc not in (0, OMPD_E_INVAL, OMPD_E_NOCONVERGE, OMPD_E_DEVICE) or (per[:self.n] == 1).any():
             _check(rc)
         return per[:self.n]
 

@@ -10,7 +10,20 @@ enum : int32_t {
     INFO_STATUS = 0,      // 0 ok, else an OMPD_E_* code
     INFO_RESERVED = 1,
     INFO_SWEEPS = 2,      // [2..7] max sweeps per phase over the CFG's tiles
+    // the first wait of the CFG's solve that gave up (status OMPD_E_DEVICE): phase + 1 (0 = none),
+    // the tile's index within the CFG, which counter was awaited (WAIT_*), the value last seen,
+    // the value awaited, and the wall-clock ticks waited
+    INFO_PM_PHASE = 8, INFO_PM_TILE = 9, INFO_PM_WHAT = 10, INFO_PM_SEEN = 11, INFO_PM_TARGET = 12,
+    INFO_PM_TICKS = 13,
     INFO_WORDS = 16
+};
+
+// What a wait of a phase workgroup waits for (INFO_PM_WHAT).
+enum : int32_t {
+    WAIT_IN_READY = 1,   // compute: the helper has put a step's inputs in LDS
+    WAIT_CONSUMED = 2,   // compute: the helper has read a ring slot
+    WAIT_FLUSHED = 3,    // compute: the helper's stores of a step's state have completed
+    WAIT_PRODUCED = 4    // helper (idle): the compute wavefront has produced a step
 };
 
 enum : int32_t { PH_NU = 0, PH_AVE = 1, PH_MAYP = 2, PH_LATER = 3, PH_AVF = 4, PH_REACH = 5 };
@@ -27,7 +40,8 @@ enum : int32_t {
 // scratch owned by the plan.
 struct DevCfg {
     int32_t nb, ne, nv, entry, exit, wd;   // wd = 64-bit words per row
-    int32_t n_sums, placement, sweep_cap, pad;   // placement: bit 0 eager, bit 1 summary evaluation
+    int32_t n_sums, placement, sweep_cap;   // placement: bit 0 eager, bit 1 summary evaluation
+    int32_t wait_ticks;   // a wait gives up after this many wall-clock ticks without progress (> 0)
     const int32_t* succ_ptr;
     const int32_t* succ_idx;
     const uint8_t* kind;

@@ -20,6 +20,8 @@ struct ompd_ctx {
     int n_cu = 1;
     int lds_max = 64 * 1024;
     uint64_t budget = 0;
+    int64_t wall_khz = 100000;     // device wall-clock rate (s_memrealtime)
+    int32_t wait_ticks = 0;        // bound of a kernel wait without progress, in wall-clock ticks
     std::mutex mu;                 // serialises API calls
     ServingState* srv = nullptr;   // created on first submit
     std::mutex srv_mu;
@@ -74,13 +76,18 @@ struct ompd_plan {
 };
 
 int ompd_fail(int code, const std::string& msg);
+// The message for CFG i's info words (status, and for OMPD_E_DEVICE which wait gave up).
+std::string ompd_status_message(int i, const int32_t* info);
 
 struct ScratchOff {
     size_t aveout, mayp, later, flg, eag, both, nu, ave, ie, ig, avf, vk, bnd, pp, pi, pe, tmp, recf, recb, stf, stb, info;
 };
 size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o);
 void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const ScratchOff& o, uint32_t flags,
-                      ompd::DevCfg& d, uint64_t* bnd_host, uint64_t* bnd_dev = nullptr);
+                      int32_t wait_ticks, ompd::DevCfg& d, uint64_t* bnd_host, uint64_t* bnd_dev = nullptr);
+// Default bound of a kernel wait without progress (the longest legitimate wait is one step of
+// the other wavefront, microseconds).
+constexpr int64_t OMPD_WAIT_DEFAULT_NS = 2000000000ll;
 // Launch shape of a set of CFGs: tiles (longest first), edge-step items and grids.
 struct Shape {
     std::vector<ompd::Tile> tiles;

@@ -400,7 +400,6 @@ struct Ctl {
 };
 constexpr int CTL_WORDS = CTL_BYTES / 8;   // u64 words reserved for Ctl at the start of the LDS
 static_assert(sizeof(Ctl) <= CTL_BYTES, "coordination words");
-constexpr int SPIN_MAX = 1 << 23;   // bound of every wait (far above any legitimate one)
 
 __device__ __forceinline__ int lds_get(int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
 __device__ __forceinline__ void lds_put(int* p, int v)
@@ -413,16 +412,38 @@ __device__ __forceinline__ void lds_release() { __builtin_amdgcn_fence(__ATOMIC_
 // LDS reads after this point are not moved before the counter read that precedes it
 __device__ __forceinline__ void lds_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local"); }
 
-// Wait (bounded) until *p >= target; false if the wait ran out or the other side gave up.
-__device__ __forceinline__ bool wait_for(int* p, int target, int* abort)
+// The device's constant-rate wall clock (ticks at the rate the host queries as
+// hipDeviceAttributeWallClockRate).
+__device__ __forceinline__ uint64_t wall_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
+// Wait until *p >= target, for at most `limit` wall-clock ticks; false if the wait ran out (then
+// `abort` is set and `seen` / `waited` say what it saw) or the other side gave up first.
+__device__ __forceinline__ bool wait_for(int* p, int target, int* abort, int32_t limit, int& seen, int64_t& waited)
 {
-    for (int k = 0; k < SPIN_MAX; ++k) {
-        if (__builtin_amdgcn_readfirstlane(lds_get(p)) >= target) { lds_acquire(); return true; }
-        if (__builtin_amdgcn_readfirstlane(lds_get(abort))) return false;
+    const uint64_t t0 = wall_ticks();
+    for (;;) {
+        seen = __builtin_amdgcn_readfirstlane(lds_get(p));
+        if (seen >= target) { lds_acquire(); return true; }
+        if (__builtin_amdgcn_readfirstlane(lds_get(abort))) { waited = -1; return false; }
+        waited = (int64_t)(wall_ticks() - t0);
+        if (waited > (int64_t)limit) break;
         __builtin_amdgcn_s_sleep(1);
     }
     lds_put(abort, 1);
     return false;
+}
+
+// First wait of a CFG's solve that gave up: what it waited for (one lane writes).
+__device__ __forceinline__ void post_mortem(int32_t* info, int ph, int tile, int what, int seen, int target,
+                                            int64_t ticks)
+{
+    if ((threadIdx.x & 63) != 0) return;
+    if (atomicCAS(&info[INFO_PM_PHASE], 0, ph + 1) != 0) return;
+    info[INFO_PM_TILE] = tile;
+    info[INFO_PM_WHAT] = what;
+    info[INFO_PM_SEEN] = seen;
+    info[INFO_PM_TARGET] = target;
+    info[INFO_PM_TICKS] = (int32_t)(ticks > 0x7FFFFFFF ? 0x7FFFFFFF : ticks);
 }
 
 // State rows of the iterated vector of one phase, per lane: data lanes
@@ -560,7 +581,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         const hw init = (hw)(hi ? init64 >> 32 : init64);
         int gf = 0, fi = 0;   // next step to store and its index within the sweep
         int pf = 0, pi = 0;   // next step whose inputs are loaded and its index within the sweep
-        int spins = 0;
+        uint64_t idle_since = 0;   // wall clock when the helper last found nothing to do (0: busy)
         // Lane j plans step pf + j (walk position pi + j): its step entry is loaded by the lane
         // after the previous round, so that the load is in flight while the helper waits.
         typedef int v4i __attribute__((ext_vector_type(4)));
@@ -614,15 +635,21 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                     __builtin_amdgcn_readfirstlane(lds_get(&ctl->produced)) == gf)
                     return;
                 if (__builtin_amdgcn_readfirstlane(lds_get(&ctl->abort))) return;
-                // the compute wavefront always ends with `done` or `abort`; this bound only keeps the kernel finite
-                if (++spins > 4 * SPIN_MAX) { lds_put(&ctl->abort, 1); return; }
+                // the compute wavefront always ends with `done` or `abort`; this bound (no step
+                // produced for c.wait_ticks) only keeps the kernel finite
+                const uint64_t now = wall_ticks();
+                if (!idle_since) idle_since = now;
+                else if ((int64_t)(now - idle_since) > (int64_t)c.wait_ticks) {
+                    lds_put(&ctl->abort, 1);
+                    post_mortem(c.info, PH, fslot, WAIT_PRODUCED, prod, gf + 1, (int64_t)(now - idle_since));
+                    return;
+                }
                 // a compute step takes thousands of cycles: poll less once idle, leaving the
                 // issue slots to the other wavefronts of the SIMD
-                if (spins > 1) __builtin_amdgcn_s_sleep(8);
-                else __builtin_amdgcn_s_sleep(1);
+                __builtin_amdgcn_s_sleep(8);
                 continue;
             }
-            spins = 0;
+            idle_since = 0;
             // results of steps gf .. fend - 1 to the rows, eight ring reads in flight at a time
             while (gf < fend) {
                 hw h[8], d[8];
@@ -689,7 +716,15 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         if (seen > g) return;
         seen = __builtin_amdgcn_readfirstlane(lds_get(p));
         if (seen > g) { lds_acquire(); return; }
-        if (!wait_for(p, g + 1, &ctl->abort)) ok = false;
+        int last = 0;
+        int64_t waited = 0;
+        if (!wait_for(p, g + 1, &ctl->abort, c.wait_ticks, last, waited)) {
+            ok = false;
+            if (waited >= 0)
+                post_mortem(c.info, PH, fslot,
+                            p == &ctl->in_ready ? WAIT_IN_READY : p == &ctl->consumed ? WAIT_CONSUMED : WAIT_FLUSHED,
+                            last, g + 1, waited);
+        }
         seen = g + 1;
     };
     // neighbour p at distance d of the block of step g, from the rows: the previous sweep's (or

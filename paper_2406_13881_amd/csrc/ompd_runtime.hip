@@ -73,6 +73,11 @@ extern "C" int ompd_ctx_create(ompd_ctx** out, int device_ordinal, uint64_t budg
         return ompd_fail(OMPD_E_DEVICE, hipGetErrorString(e));
     }
     c->n_cu = c->prop.multiProcessorCount;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device_ordinal) == hipSuccess && khz > 0)
+        c->wall_khz = khz;
+    (void)hipGetLastError();
+    c->wait_ticks = (int32_t)std::min<int64_t>(OMPD_WAIT_DEFAULT_NS / 1000 * c->wall_khz / 1000, INT32_MAX);
     size_t lds_max = c->prop.maxSharedMemoryPerMultiProcessor;
     if (!lds_max) lds_max = c->prop.sharedMemPerBlock;
     lds_max = std::min<size_t>(lds_max ? lds_max : 64 * 1024, 160 * 1024);
@@ -93,6 +98,17 @@ extern "C" int ompd_ctx_create(ompd_ctx** out, int device_ordinal, uint64_t budg
     (void)hipGetLastError();
     c->lds_max = dyn;
     *out = c;
+    return OMPD_OK;
+}
+
+extern "C" int ompd_set_wait_limit(ompd_ctx* c, int64_t ns)
+{
+    if (!c) return ompd_fail(OMPD_E_INVAL, "ctx is NULL");
+    if (ns < 0) return ompd_fail(OMPD_E_INVAL, "wait limit is negative");
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (ns == 0) ns = OMPD_WAIT_DEFAULT_NS;
+    const int64_t t = ns / 1000 * c->wall_khz / 1000 + (ns % 1000) * c->wall_khz / 1000000;
+    c->wait_ticks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(t, INT32_MAX));
     return OMPD_OK;
 }
 
@@ -192,10 +208,11 @@ size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o)
 // ([4*wd] words: entry valid H, D, exit live H, D), to be copied by the
 // caller to bnd_dev (default: base + o.bnd), where the descriptor points.
 void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const ScratchOff& o, uint32_t flags,
-                      DevCfg& d, uint64_t* bnd_host, uint64_t* bnd_dev)
+                      int32_t wait_ticks, DevCfg& d, uint64_t* bnd_host, uint64_t* bnd_dev)
 {
     int wd = (g.n_vars + 63) / 64;
     memset(&d, 0, sizeof d);
+    d.wait_ticks = wait_ticks > 0 ? wait_ticks : 1;
     d.nb = g.n_blocks; d.ne = g.n_edges; d.nv = g.n_vars; d.entry = g.entry; d.exit = g.exit; d.wd = wd;
     d.n_sums = g.call_summary ? g.n_summaries : 0;
     d.placement = ((flags & OMPD_F_PLACEMENT_EAGER) ? 1 : 0) | ((flags & OMPD_F_SUMMARY) ? 2 : 0);
@@ -361,7 +378,7 @@ int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32
     std::vector<uint64_t> bnd(std::max<size_t>(bnd_words, 1), 0);
     uint64_t* bnd_dev = (uint64_t*)(S + bnd_off);
     for (int i = 0; i < n; ++i)
-        ompd_fill_devcfg(cfgs[i], res[i], S + base[i], off[i], flags, p->h_cfgs[i], bnd.data() + boff[i],
+        ompd_fill_devcfg(cfgs[i], res[i], S + base[i], off[i], flags, ctx->wait_ticks, p->h_cfgs[i], bnd.data() + boff[i],
                          bnd_dev + boff[i]);
     if (bnd_words) {
         e = hipMemcpy(bnd_dev, bnd.data(), 8 * bnd_words, hipMemcpyHostToDevice);
@@ -573,6 +590,27 @@ extern "C" int ompd_plan_run(ompd_plan* p, void* stream)
     return ompd_plan_run_locked(p, (hipStream_t)stream);
 }
 
+std::string ompd_status_message(int i, const int32_t* inf)
+{
+    const int st = inf[INFO_STATUS];
+    char buf[320];
+    if (st == OMPD_E_DEVICE && inf[INFO_PM_PHASE] > 0) {
+        static const char* const ph[5] = {"next use", "eager validity", "pending copies", "delayed placement",
+                                          "final validity"};
+        static const char* const what[5] = {"?", "inputs of a step (in_ready)", "a free ring slot (consumed)",
+                                            "stored states (flushed)", "a produced step (produced, helper)"};
+        const int k = inf[INFO_PM_PHASE] - 1, w = inf[INFO_PM_WHAT];
+        snprintf(buf, sizeof buf,
+                 "cfg %d: a kernel wait gave up (phase %s, tile %d of the CFG, waiting for %s: counter at %d, "
+                 "needed %d, after %d wall-clock ticks)",
+                 i, (k >= 0 && k < 5) ? ph[k] : "?", inf[INFO_PM_TILE], (w >= 0 && w < 5) ? what[w] : "?",
+                 inf[INFO_PM_SEEN], inf[INFO_PM_TARGET], inf[INFO_PM_TICKS]);
+    } else
+        snprintf(buf, sizeof buf, "cfg %d: %s", i,
+                 st == OMPD_E_INVAL ? "malformed CFG" : st == OMPD_E_NOCONVERGE ? "sweep cap reached" : "device error");
+    return buf;
+}
+
 int ompd_plan_collect(ompd_plan* p, int32_t* per_cfg)
 {
     CK(hipSetDevice(p->ctx->device));
@@ -591,10 +629,7 @@ int ompd_plan_collect(ompd_plan* p, int32_t* per_cfg)
         for (int k = 0; k < 6; ++k) p->res[i].sweeps[k] = inf[INFO_SWEEPS + k];
         if (st && first == OMPD_OK) {
             first = st;
-            char buf[128];
-            snprintf(buf, sizeof buf, "cfg %d: %s", i,
-                     st == OMPD_E_INVAL ? "malformed CFG" : st == OMPD_E_NOCONVERGE ? "sweep cap reached" : "error");
-            g_err = buf;
+            g_err = ompd_status_message(i, inf);
         }
     }
     return first;
@@ -675,11 +710,12 @@ extern "C" int ompd_plan_describe(ompd_plan* p, char* buf, int32_t len)
     snprintf(buf, len,
              "{\"cfgs\": %d, \"tiles\": %d, \"words\": %ld, \"ring_slots\": %d, \"split\": %d, \"grid_tile\": %d, "
              "\"grid_phases\": [%d, %d, %d, %d, %d], "
-             "\"lds_bytes\": %zu, \"wg_per_cu\": %d, \"graph\": %d, \"scratch_bytes\": %zu}",
+             "\"lds_bytes\": %zu, \"wg_per_cu\": %d, \"graph\": %d, \"graph_captured\": %d, "
+             "\"scratch_bytes\": %zu}",
              p->n, p->n_tiles, lanes, p->dims.ring_slots, (int)p->dims.split, p->dims.grid_tile, p->dims.grid[0],
              p->dims.grid[1], p->dims.grid[2],
              p->dims.grid[3], p->dims.grid[4], p->cfg.lds_bytes, p->cfg.wg_per_cu,
-             p->cfg.use_graph ? 1 : 0, p->scratch_bytes);
+             p->cfg.use_graph ? 1 : 0, p->gx_solve ? 1 : 0, p->scratch_bytes);
     return OMPD_OK;
 }
 
@@ -893,6 +929,7 @@ int ompd_batch_locked(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int
         if (rc) return rc;
         rc = ompd_plan_run_locked(p, s);
         if (rc == OMPD_OK) rc = ompd_plan_collect(p, nullptr);
+        for (int i = 0; i < n; ++i) memcpy(res[i].sweeps, p->res[i].sweeps, sizeof res[i].sweeps);
         ompd_plan_destroy(p);
         return rc;
     }

@@ -2,7 +2,9 @@
 //
 // submit() admits a request when its device footprint (inputs, outputs and
 // solver scratch) fits the context's device-memory budget and its inputs fit
-// the pinned staging pool; otherwise it returns OMPD_E_BUSY.  A launcher
+// the pinned staging pool; otherwise it returns OMPD_E_BUSY.  A step's launch
+// tables live in a fixed region of the stream it runs on, outside both pools,
+// so a free stream can always launch a step, however full the pools are.  A launcher
 // thread groups the admitted requests into steps — everything admitted since
 // the last step — and launches each step (uploads, ingest kernel, persistent
 // solve) on the next of several streams, so requests that arrive while
@@ -20,65 +22,20 @@
 #include <unordered_map>
 
 #include "ompd_internal.h"
+#include "ompd_pool.h"
 
 using namespace ompd;
 
 namespace {
 
-inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+using ompd_pool::a256;
+using ompd_pool::Pool;
 
 int64_t now_ns()
 {
     return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
         .count();
 }
-
-// First-fit allocator over a byte range (256-byte granularity, coalescing).
-struct Pool {
-    char* base = nullptr;
-    size_t size = 0, used = 0;
-    std::map<size_t, size_t> free_;
-    void init(char* b, size_t n)
-    {
-        base = b;
-        size = n;
-        used = 0;
-        free_.clear();
-        if (n) free_[0] = n;
-    }
-    bool alloc(size_t n, size_t& off)
-    {
-        n = a256(std::max<size_t>(n, 1));
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < n) continue;
-            off = it->first;
-            size_t rest = it->second - n, o2 = it->first + n;
-            free_.erase(it);
-            if (rest) free_[o2] = rest;
-            used += n;
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t n)
-    {
-        n = a256(std::max<size_t>(n, 1));
-        used -= n;
-        auto it = free_.emplace(off, n).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-};
 
 struct Back {
     size_t dev_off;
@@ -96,7 +53,9 @@ struct Req {
     ompd_result dres{};
     ScratchOff so{};
     std::vector<Back> back;
+    size_t tab_bytes = 0;   // what the request adds to a step's launch tables
     int status = 0;
+    std::string msg;   // what went wrong, when status != 0
     int state = 0;   // 0 admitted, 1 running, 2 done
     int64_t t_submit = 0, t_done = 0;
 };
@@ -105,9 +64,7 @@ struct Step {
     std::vector<Req*> reqs;
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    size_t tab_off = 0, tab_bytes = 0, pin_off = 0, pin_bytes = 0;
     size_t info_pin_off = 0;
-    bool tables = false;   // tab_off / pin_off hold pool allocations
     int launch_rc = 0;
 };
 
@@ -118,6 +75,10 @@ struct ServingState {
     char* dev_base = nullptr;
     char* pin_base = nullptr;
     Pool dev, pin;
+    // launch tables: one region per stream, device and pinned (outside the pools)
+    static constexpr size_t TAB_REGION = 8u << 20;
+    char* tab_dev = nullptr;
+    char* tab_pin = nullptr;
     std::vector<hipStream_t> streams;
     std::vector<int> stream_busy;
     std::vector<hipEvent_t> events;
@@ -164,9 +125,12 @@ static void launcher_main(ServingState* S)
         for (int i = 0; i < (int)S->stream_busy.size(); ++i)
             if (!S->stream_busy[i]) { si = i; break; }
         if (si < 0) continue;
-        // everything admitted since the last step joins this one
+        // the pending requests, front first, as far as the stream's table region holds them
+        std::deque<size_t> tb;
+        for (size_t i = 0; i < S->pending.size() && (int)i < S->max_step_reqs; ++i) tb.push_back(S->pending[i]->tab_bytes);
+        const int take = ompd_pool::take_step(tb, ServingState::TAB_REGION, S->max_step_reqs);
         Step* st = new Step();
-        while (!S->pending.empty() && (int)st->reqs.size() < S->max_step_reqs) {
+        for (int i = 0; i < take; ++i) {
             st->reqs.push_back(S->pending.front());
             S->pending.pop_front();
         }
@@ -174,44 +138,30 @@ static void launcher_main(ServingState* S)
         std::vector<DevCfg> h(k);
         for (int i = 0; i < k; ++i) {
             Req* r = st->reqs[i];
-            ompd_fill_devcfg(r->dcfg, r->dres, S->dev_base + r->dev_off + r->scratch_off, r->so, r->flags, h[i],
-                             nullptr);
+            ompd_fill_devcfg(r->dcfg, r->dres, S->dev_base + r->dev_off + r->scratch_off, r->so, r->flags,
+                             S->ctx->wait_ticks, h[i], nullptr);
         }
         PlanConfig pc;
         Shape sh;
         int rc = ompd_make_shape(S->ctx, h, pc, sh);
         const std::vector<Tile>& tiles = sh.tiles;
-        size_t cfg_bytes = a256(sizeof(DevCfg) * k), tile_bytes = a256(sizeof(Tile) * std::max<size_t>(tiles.size(), 1));
-        size_t item_bytes = a256(sizeof(EdgeItem) * std::max<size_t>(sh.items.size(), 1));
-        size_t info_bytes = a256(4 * INFO_WORDS * (size_t)k);
-        tile_bytes += item_bytes;   // tiles, then the edge-step items
-        st->tab_bytes = cfg_bytes + tile_bytes + 256;
-        st->pin_bytes = cfg_bytes + tile_bytes + info_bytes;
-        bool ok_mem = (rc == OMPD_OK) && S->dev.alloc(st->tab_bytes, st->tab_off);
-        if (ok_mem && !S->pin.alloc(st->pin_bytes, st->pin_off)) {
-            S->dev.release(st->tab_off, st->tab_bytes);
-            ok_mem = false;
-        }
-        st->tables = ok_mem;
-        if (!ok_mem && rc == OMPD_OK) {
-            // tables do not fit right now: put the requests back and wait for completions
-            for (int i = k - 1; i >= 0; --i) S->pending.push_front(st->reqs[i]);
-            delete st;
-            S->cv_launch.wait_for(lk, std::chrono::milliseconds(1));
-            continue;
-        }
+        const ompd_pool::TableBytes tab = ompd_pool::table_bytes(k, tiles.size(), sh.items.size(), sizeof(DevCfg),
+                                                                 sizeof(Tile), sizeof(EdgeItem), 4 * INFO_WORDS);
+        const size_t cfg_bytes = tab.cfg, tile_bytes = tab.tiles + tab.items, item_bytes = tab.items;
+        if (rc == OMPD_OK && (tab.device() > ServingState::TAB_REGION || tab.pinned() > ServingState::TAB_REGION))
+            rc = ompd_fail(OMPD_E_NOMEM, "serving: step tables exceed their region");   // excluded at submit
         S->stream_busy[si] = 1;
         st->stream = S->streams[si];
         st->done = S->events[si];
         for (Req* r : st->reqs) r->state = 1;
         lk.unlock();
         if (rc == OMPD_OK) {
-            char* pin = S->pin_base + st->pin_off;
+            char* pin = S->tab_pin + (size_t)si * ServingState::TAB_REGION;
             memcpy(pin, h.data(), sizeof(DevCfg) * k);
             if (!tiles.empty()) memcpy(pin + cfg_bytes, tiles.data(), sizeof(Tile) * tiles.size());
             if (!sh.items.empty())
                 memcpy(pin + cfg_bytes + (tile_bytes - item_bytes), sh.items.data(), sizeof(EdgeItem) * sh.items.size());
-            char* dtab = S->dev_base + st->tab_off;
+            char* dtab = S->tab_dev + (size_t)si * ServingState::TAB_REGION;
             hipStream_t s = st->stream;
             hipError_t e = hipSuccess;
             for (Req* r : st->reqs)
@@ -228,9 +178,9 @@ static void launcher_main(ServingState* S)
                                        (const EdgeItem*)(dtab + cfg_bytes + (tile_bytes - item_bytes)),
                                        (int)sh.items.size(), counter, sh.dims, s);
             // per-request status words back to pinned memory
-            st->info_pin_off = st->pin_off + cfg_bytes + tile_bytes;
+            st->info_pin_off = (size_t)si * ServingState::TAB_REGION + cfg_bytes + tile_bytes;
             for (int i = 0; i < k && rc == OMPD_OK; ++i)
-                if (hipMemcpyAsync(S->pin_base + st->info_pin_off + 4 * INFO_WORDS * (size_t)i, h[i].info,
+                if (hipMemcpyAsync(S->tab_pin + st->info_pin_off + 4 * INFO_WORDS * (size_t)i, h[i].info,
                                    4 * INFO_WORDS, hipMemcpyDeviceToHost, s) != hipSuccess)
                     rc = OMPD_E_DEVICE;
             if (hipEventRecord(st->done, s) != hipSuccess && rc == OMPD_OK) rc = OMPD_E_DEVICE;
@@ -267,8 +217,9 @@ static void complete_step(ServingState* S, Step* st)
         Req* r = st->reqs[i];
         int status = st->launch_rc;
         if (status == OMPD_OK) {
-            const int32_t* info = (const int32_t*)(S->pin_base + st->info_pin_off) + INFO_WORDS * i;
+            const int32_t* info = (const int32_t*)(S->tab_pin + st->info_pin_off) + INFO_WORDS * i;
             status = info[INFO_STATUS];
+            if (status) r->msg = "request " + std::to_string(r->id) + ", " + ompd_status_message(0, info);
             if (r->user)
                 for (int k = 0; k < 6; ++k) r->user->sweeps[k] = info[INFO_SWEEPS + k];
             for (const Back& b : r->back)
@@ -287,10 +238,6 @@ static void complete_step(ServingState* S, Step* st)
         r->state = 2;
         r->t_done = t;
         S->completed++;
-    }
-    if (st->tables) {
-        S->dev.release(st->tab_off, st->tab_bytes);
-        S->pin.release(st->pin_off, st->pin_bytes);
     }
     for (size_t i = 0; i < S->streams.size(); ++i)
         if (S->streams[i] == st->stream) S->stream_busy[i] = 0;
@@ -317,8 +264,22 @@ static int serving_init(ompd_ctx* ctx)
         delete S;
         return ompd_fail(OMPD_E_NOMEM, "serving: pinned pool allocation failed");
     }
-    S->dev.init(S->dev_base, dev_bytes);
-    S->pin.init(S->pin_base, pin_bytes);
+    S->dev.init(dev_bytes);
+    S->pin.init(pin_bytes);
+    const size_t tab_total = (size_t)S->max_steps * ServingState::TAB_REGION;
+    if (hipMalloc((void**)&S->tab_dev, tab_total) != hipSuccess) {
+        (void)hipFree(S->dev_base);
+        (void)hipHostFree(S->pin_base);
+        delete S;
+        return ompd_fail(OMPD_E_NOMEM, "serving: table region allocation failed");
+    }
+    if (hipHostMalloc((void**)&S->tab_pin, tab_total, hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(S->tab_dev);
+        (void)hipFree(S->dev_base);
+        (void)hipHostFree(S->pin_base);
+        delete S;
+        return ompd_fail(OMPD_E_NOMEM, "serving: pinned table region allocation failed");
+    }
     S->streams.resize(S->max_steps);
     S->events.resize(S->max_steps);
     S->stream_busy.assign(S->max_steps, 0);
@@ -358,6 +319,8 @@ void ompd_serving_shutdown(ompd_ctx* ctx)
     (void)hipStreamDestroy(S->d2h);
     (void)hipFree(S->dev_base);
     (void)hipHostFree(S->pin_base);
+    (void)hipFree(S->tab_dev);
+    (void)hipHostFree(S->tab_pin);
     for (auto& kv : S->reqs) delete kv.second;
     delete S;
     ctx->srv = nullptr;
@@ -401,6 +364,17 @@ extern "C" int ompd_submit(ompd_ctx* ctx, const ompd_cfg* cfg, ompd_result* res,
     off += ompd_cfg_scratch(g, full, r->so);
     r->dev_bytes = off;
     r->pin_bytes = r->in_bytes;
+    {
+        // its share of a step's launch tables: descriptor, tiles, pass items, status words
+        const size_t tiles = (size_t)tiles_of((int)wd);
+        const size_t items = wd ? ((wd + PASS_WORDS - 1) / PASS_WORDS) * ((nb + 63) / 64) : 0;
+        r->tab_bytes = ompd_pool::request_table_bytes(tiles, items, sizeof(DevCfg), sizeof(Tile), sizeof(EdgeItem),
+                                                      4 * INFO_WORDS);
+        if (r->tab_bytes + ompd_pool::TABLE_SLACK > ServingState::TAB_REGION) {
+            delete r;
+            return ompd_fail(OMPD_E_INVAL, "serving: request too large for a step's launch tables");
+        }
+    }
     {
         std::lock_guard<std::mutex> lk(S->mu);
         if (S->reqs.size() >= S->max_reqs) { delete r; return ompd_fail(OMPD_E_BUSY, "serving: too many requests"); }
@@ -489,6 +463,7 @@ static int poll_locked(ServingState* S, ompd_ticket t, int* done, int64_t* done_
     }
     *done = r->status ? r->status : 1;
     if (done_ns) *done_ns = r->t_done;
+    if (r->status) (void)ompd_fail(r->status, r->msg.empty() ? "request failed" : r->msg);
     S->reqs.erase(it);
     delete r;
     return OMPD_OK;
