@@ -3,9 +3,9 @@ context's outputs, every context boundary, every procedure summary and every
 call site's host-read demand equal the oracle driver's, bit for bit, on
 non-recursive, recursive and external-call programs and on a C4-shaped
 program of 300 procedures.  At the full C4 size (2,000 procedures) the
-oracle would take minutes, so the device result is checked with
-whole-program random walks (no stale read or copy source), which hold for
-any size."""
+oracle takes minutes, so the device result is compared with digests the
+oracle wrote once (tests/golden/c4_digests.json), and checked with
+whole-program random walks (no stale read or copy source)."""
 import sys
 
 import numpy as np
@@ -91,12 +91,32 @@ def test_program_c4_shape(ctx):
     compare(prog, got, "c4-300")
 
 
-def test_program_c4_full_walks(ctx):
+def test_program_c4_full_digests(ctx):
+    """The full whole-program configuration (2,000 procedures, 20,370 contexts): every
+    context's boundaries and 13 outputs, every summary and every demand equal the
+    oracle's, compared through SHA-256 digests that tests/golden/make_c4_digests.py wrote
+    from the oracle alone (one digest per procedure over its contexts).  Whole-program
+    random walks then check that no read or copy source is stale."""
+    import json
+    import os
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from c4_digest import digests
+    want = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c4_digests.json")))
     prog = synth.c4()
     _print("c4: %d procs %d calls" % (len(prog.procs), len(prog.call_proc)))
     got = ctx.analyze_program(prog)
     _print("device: %d contexts, %d rounds, %d solves" % (len(got["contexts"]), got["rounds"], got["solves"]))
-    results = {key: got["results"][k] for k, key in enumerate(got["contexts"])}
+    keys = list(got["contexts"])
+    results = {key: got["results"][k] for k, key in enumerate(keys)}
+    bnds = {key: got["boundaries"][k] for k, key in enumerate(keys)}
+    mine = digests(prog, keys, results, bnds, [got["summaries"][p] for p in range(len(prog.procs))],
+                   [got["demands"][j] for j in range(len(prog.call_proc))])
+    assert mine["n_contexts"] == want["n_contexts"]
+    assert mine["contexts"] == want["contexts"], "context sets differ"
+    assert mine["summaries"] == want["summaries"], "procedure summaries differ"
+    assert mine["demands"] == want["demands"], "host-read demands differ"
+    bad = [p for p in want["procedures"] if mine["procedures"].get(p) != want["procedures"][p]]
+    assert not bad, "contexts of %d procedures differ, first %s" % (len(bad), bad[:5])
     demands = {j: got["demands"][j] for j in range(len(prog.call_proc)) if got["demands"][j].any()}
     errs, cut = simulate_program(prog, None, results, demands, walks=200, seed=7, max_steps=6000)
     assert not errs, errs[:5]

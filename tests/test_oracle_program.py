@@ -311,3 +311,21 @@ def test_every_demand_is_needed():
         if checked >= 40:
             break
     assert programs >= 10 and checked >= 15
+
+
+def test_c4_digest_file_matches_the_generator():
+    """The stored digests of the full whole-program configuration belong to the program the
+    generator builds today: same context count and same sorted context list (the context
+    graph alone, no solves)."""
+    import hashlib
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c4_digests.json")
+    want = json.load(open(path))
+    prog = synth.c4()
+    keys = sorted(ProgramOracle(prog).context_graph(), key=lambda k: (int(k[0]), tuple(int(s) for s in k[1])))
+    h = hashlib.sha256()
+    for key in keys:
+        h.update(repr((int(key[0]), tuple(int(s) for s in key[1]))).encode())
+    assert len(keys) == want["n_contexts"]
+    assert h.hexdigest() == want["contexts"]
