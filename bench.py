@@ -59,6 +59,37 @@ def algorithmic_bytes(cfgs, want):
     return tot
 
 
+def fact_bytes(cfgs, with_ave=True):
+    """Algorithmic bytes of one pass of the path: per fact (user block x
+    variable) the R and W bits in and the next-use, final-validity,
+    copy-before-block (and, when requested, eager-validity) bits out, one
+    bit per space each; per (edge x variable) the two copy-on-edge bits; the
+    successor CSR, edge kinds and block spaces; per variable its map kind
+    and per block its two label facts.  That is the minimum the method moves
+    once, with every iteration on chip (1.325 B per fact, 1.575 B with
+    eager validity, plus the exact CSR and label bytes)."""
+    bits_per_fact = 2 + 2 + 2 + 2 + (2 if with_ave else 0)
+    tot = 0.0
+    for c in cfgs:
+        nb, ne, nv = c.n_blocks, c.n_edges, c.n_vars
+        tot += (nb - 2) * nv * bits_per_fact / 8.0 + ne * nv * 2 / 8.0
+        tot += 4 * (nb + 1) + 4 * ne + ne + nb          # successor CSR, edge kinds, spaces
+        tot += nv + 2 * nb                              # map kinds, label facts
+    return int(tot)
+
+
+def cpu_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count() or 1, "cpu_model": model}
+
+
 TUNED = os.path.join(ROOT, "paper_2406_13881_amd", "tuned.json")
 
 
@@ -180,11 +211,13 @@ def kernel_bytes(cfgs):
     return out
 
 
-def cpu_baseline(cfgs, seconds, threads):
-    """The oracle as it stands, one CFG per thread, on the first CFGs of the
-    batch until `seconds` of wall time have been used."""
+def cpu_baseline(cfgs, seconds, threads, c1=None, c2=None):
+    """The oracle as it stands, one CFG per thread on every host core, on the
+    first CFGs of the batch until `seconds` of wall time have been used; and,
+    single-threaded, its time on the 64-block procedure (median of 50) and on
+    the 16,384-block procedure (one solve)."""
+    import numpy as np
     import oracle
-    done = []
     t0 = time.perf_counter()
     deadline = t0 + seconds
 
@@ -203,8 +236,41 @@ def cpu_baseline(cfgs, seconds, threads):
             facts += r
             n += 1
     dt = time.perf_counter() - t0
-    return {"value": facts / dt, "unit": "facts/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d of %d CFGs of the batch (%d facts, %.1f s wall)" % (n, len(cfgs), facts, dt)}
+    out = {"value": facts / dt, "unit": "facts/s", "cores": threads, "kind": "oracle",
+           "sample": "first %d of %d CFGs of the batch, one per thread (%d facts, %.1f s wall)" % (
+               n, len(cfgs), facts, dt)}
+    out.update(cpu_info())
+    if c1 is not None:
+        ts = []
+        for _ in range(50):
+            t = time.perf_counter()
+            oracle.solve(c1)
+            ts.append(time.perf_counter() - t)
+        out["c1_ms"] = round(1e3 * float(np.median(ts)), 4)
+    if c2 is not None:
+        t = time.perf_counter()
+        oracle.solve(c2)
+        out["c2_ms"] = round(1e3 * (time.perf_counter() - t), 1)
+    return out
+
+
+def c1_leg(out, p1, c1, stream):
+    """The 64-block procedure alone: one plan, graph replays timed one by one."""
+    import numpy as np
+    import torch
+    for _ in range(5):
+        p1.run(stream)
+    torch.cuda.synchronize()
+    lat1 = []
+    for _ in range(50):
+        p1.run(stream)
+        a, _b = p1.plan.last_ms()
+        lat1.append(a)
+    assert (p1.plan.status() == 0).all()
+    out["c1"] = {"workload": "one CFG, 64 user blocks x 32 variables, loop depth <= 3, 30% device",
+                 "ms": round(float(np.median(lat1)), 4), "p99_ms": round(float(np.percentile(lat1, 99)), 4),
+                 "value": c1.facts / (np.median(lat1) * 1e-3), "unit": "facts/s"}
+    log("c1: %.4f ms per solve (median of 50)" % np.median(lat1))
 
 
 def main():
@@ -224,8 +290,13 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory (a device-to-device copy of known size, "
                          "to calibrate the HBM byte counters of a profiler) and exit")
-    ap.add_argument("--serve-requests", type=int, default=300, help="measured requests per offered load")
-    ap.add_argument("--serve-warmup", type=int, default=50)
+    ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per offered load")
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--progress", action="store_true",
+                    help="synchronise and print a line after every timed step (for profiler runs)")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 64-block procedure leg")
+    ap.add_argument("--no-kernel-times", action="store_true",
+                    help="skip the separate pass that times every kernel with events")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -271,44 +342,64 @@ def main():
         c = tuned[key]
         rb.plan.configure(c["lds_bytes"], c["wg_per_cu"])
         log("using the stored autotuner choice %s" % c)
-    plan_desc = json.loads(rb.plan.describe())
     for _ in range(args.warmup):
         rb.run(stream)
         st = rb.plan.status()
         if (st != 0).any():
             raise SystemExit("solve reported errors for %d CFGs" % int((st != 0).sum()))
     torch.cuda.synchronize()
-    rb.plan.profile(True)              # HIP events after every kernel, on the launch stream
-    solve_ms = []
-    total_ms = []
-    per_kernel = []
+    plan_desc = json.loads(rb.plan.describe())
+    if not plan_desc.get("graph_captured"):
+        raise SystemExit("the solve was not captured into a HIP graph: %s" % plan_desc)
+    # timed: K replays of the captured graphs (ingest, then every phase and pass), back to back
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    e0.record()
+    for k in range(args.steps):
         rb.run(stream)
-        a, b = rb.plan.last_ms()       # synchronises on the last event
-        total_ms.append(a)
-        solve_ms.append(b)
-        per_kernel.append(rb.plan.kernel_ms())
+        if args.progress:
+            torch.cuda.synchronize()
+            log("timed step %d of %d done" % (k + 1, args.steps))
+    e1.record()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    dev_ms = e0.elapsed_time(e1) / args.steps
     st = rb.plan.status()
     assert (st == 0).all()
     value = facts * args.steps / dt
     ms_step = 1e3 * dt / args.steps
-    log("batched: %.3f ms/step (device %.3f ms, solve kernel %.3f ms), %.3e facts/s" % (
-        ms_step, np.mean(total_ms), np.mean(solve_ms), value))
-    kms = {k: float(np.mean([d[k] for d in per_kernel])) for k in per_kernel[0]}
-    log("kernel ms: " + ", ".join("%s %.3f" % (k, v) for k, v in kms.items()))
-    dom = max(kms, key=kms.get)
-    kb = kernel_bytes(cfgs)
-    achieved = kb[dom] / (kms[dom] * 1e-3) / 1e9
-    path_bytes = algorithmic_bytes(cfgs, want)
+    log("batched (graph replay): %.3f ms/step (device %.3f ms), %.3e facts/s" % (ms_step, dev_ms, value))
+    # separately: every kernel timed with HIP events recorded after it on the launch stream
+    # (direct launches, not the graph)
+    kms = {}
+    if not args.no_kernel_times:
+        rb.plan.profile(True)
+        per_kernel = []
+        for k in range(3):
+            rb.run(stream)
+            rb.plan.last_ms()
+            per_kernel.append(rb.plan.kernel_ms())
+            log("kernel-timing step %d of 3 done" % (k + 1))
+        rb.plan.profile(False)
+        torch.cuda.synchronize()
+        kms = {k: float(np.mean([d[k] for d in per_kernel])) for k in per_kernel[0]}
+        log("kernel ms: " + ", ".join("%s %.3f" % (k, v) for k, v in kms.items()))
+    path_bytes = fact_bytes(cfgs, with_ave="ave_h" in want)
+    dom = max(kms, key=kms.get) if kms else None
+    dom_ms = kms[dom] if kms else dev_ms
+    achieved = path_bytes / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": measured_traffic(dom),
-                "kernel": dom, "kernel_ms": round(kms[dom], 4), "algorithmic_bytes_per_launch": kb[dom],
+                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": measured_traffic(dom) if dom else None,
+                "kernel": dom, "kernel_ms": round(dom_ms, 4),
+                "algorithmic_bytes_per_launch": path_bytes,
+                "bytes_rule": "1.575 B per fact (R, W in; next use, eager and final validity, copies before "
+                              "blocks out; one bit per space) + 2 bits per edge x variable + exact CSR and "
+                              "label bytes; every phase kernel processes every fact of the batch per launch",
                 "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
-                "path_algorithmic_bytes": path_bytes,
-                "path_frac": round(path_bytes / (np.mean(total_ms) * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)}
+                "kernel_model_bytes": kernel_bytes(cfgs).get(dom) if dom else None,
+                "path_achieved_gbs": round(path_bytes / (dev_ms * 1e-3) / 1e9, 3),
+                "path_frac": round(path_bytes / (dev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)}
     out = {"metric": METRIC, "value": value, "unit": "facts/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u64", "data": "synthetic (seeded structured CFGs)",
@@ -316,11 +407,18 @@ def main():
                                   "log-uniform [32,4096], loop depth <= 3, 30%% device, read p=0.2, write p=0.1"
                                   % len(cfgs),
                       "facts": facts, "global_batch": len(cfgs), "parallelism": "single GPU",
-                      "plan": plan_desc},
+                      "device_ms_per_step": round(dev_ms, 4), "plan": plan_desc},
            "roofline": roofline}
     rb.close()
     del rb
     torch.cuda.empty_cache()
+
+    # the 64-block procedure alone: one plan, graph replays timed one by one
+    c1 = synth.c1(0)
+    p1 = ResidentBatch(ctx, [c1], want=want) if not args.no_c1 else None
+    if p1 is not None:
+        c1_leg(out, p1, c1, stream)
+        p1.close()
 
     if not args.no_plain:
         # the same CFGs, one resident single-CFG plan each, solved back to back on one stream
@@ -394,6 +492,13 @@ def main():
                           "ms": 1e3 * dt, "first_ms": 1e3 * first, "contexts": len(got["contexts"]),
                           "solves": int(got["solves"]), "rounds": int(got["rounds"]), "facts": int(pf),
                           "value": pf / dt, "unit": "facts/s (host arrays in and out)"}
+        try:
+            rec = json.load(open(os.path.join(ROOT, "tests", "golden", "c4_digests.json")))
+            out["program"]["oracle_s"] = rec.get("oracle_seconds")
+            out["program"]["oracle_note"] = ("the interprocedural oracle (one thread) on the same program, timed "
+                                             "when its digests were written (%s)" % rec.get("oracle_host", "?"))
+        except (OSError, ValueError):
+            pass
         log("program c4: %.1f ms (first %.1f ms), %d contexts, %d solves, %d rounds, %.3e facts/s" % (
             1e3 * dt, 1e3 * first, len(got["contexts"]), got["solves"], got["rounds"], pf / dt))
         del got
@@ -405,8 +510,9 @@ def main():
         sctx.close()
 
     if not args.no_cpu:
-        threads = min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(cfgs, args.cpu_seconds, threads)
+        threads = os.cpu_count() or 1
+        out["cpu_baseline"] = cpu_baseline(cfgs, args.cpu_seconds, threads, c1=c1,
+                                           c2=None if args.no_single else synth.c2(0))
         log("cpu baseline: %s" % out["cpu_baseline"])
     ctx.close()
     print(json.dumps(out), flush=True)
