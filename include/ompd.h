@@ -183,6 +183,27 @@ int ompd_analyze_cfg(ompd_ctx* ctx, const ompd_cfg* cfg, ompd_result* res, uint3
 int ompd_analyze_batch(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n,
                        uint32_t flags, void* stream);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, tight serving loops, harnesses that forbid allocation): the
+ * same solve as ompd_analyze_batch with OMPD_F_DEVICE_PTRS, with every byte
+ * of solver scratch and launch tables taken from a static device array of
+ * OMPD_NOALLOC_SCRATCH_MIB MiB that the library holds on each device it
+ * runs on (from the first context on that device until the process ends).
+ * The caller passes inputs and outputs as device pointers (flags must
+ * include OMPD_F_DEVICE_PTRS) and `stream` (NULL = default stream); the call
+ * is synchronous, allocates no device memory and returns OMPD_E_NOMEM,
+ * touching nothing, when the batch needs more scratch than the array holds
+ * (roughly ten words of scratch per block and word of each CFG, so tens of
+ * MiB for a 16,384-block x 2,048-variable procedure).  Every call on one
+ * device shares that device's array, which keeps the last call's contents
+ * (each call rewrites what it reads, so nothing carries over): calls that
+ * overlap on one GPU would race, so the library serialises them, across all
+ * contexts of the process, for the whole call.  Results, errors and sweeps
+ * are those of ompd_analyze_batch. */
+#define OMPD_NOALLOC_SCRATCH_MIB 256
+int ompd_analyze_batch_noalloc(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n,
+                               uint32_t flags, void* stream);
+
 /* Resident batch: ompd_plan_create records the CFGs (device pointers only:
  * OMPD_F_DEVICE_PTRS is required), allocates scratch and chooses tiles;
  * ompd_plan_run enqueues one complete solve (ingest kernels, all phases,

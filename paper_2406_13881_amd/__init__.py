@@ -142,6 +142,7 @@ def lib():
             L.ompd_set_wait_limit.argtypes = [_vp, ctypes.c_int64]
             L.ompd_analyze_cfg.argtypes = [_vp, P(_Cfg), P(_Res), ctypes.c_uint32, _vp]
             L.ompd_analyze_batch.argtypes = [_vp, P(_Cfg), P(_Res), _i32, ctypes.c_uint32, _vp]
+            L.ompd_analyze_batch_noalloc.argtypes = [_vp, P(_Cfg), P(_Res), _i32, ctypes.c_uint32, _vp]
             L.ompd_plan_create.argtypes = [_vp, P(_Cfg), P(_Res), _i32, ctypes.c_uint32, P(_vp)]
             L.ompd_plan_run.argtypes = [_vp, _vp]
             L.ompd_plan_status.argtypes = [_vp, _vp]
@@ -519,6 +520,27 @@ class DeviceResult:
     var_kind: int = 0
     after_dev: int = 0
     before_dev: int = 0
+
+
+def analyze_device(ctx: Context, cfgs: Sequence[DeviceCFG], results: Sequence[DeviceResult], flags: int = 0,
+                   stream: int = 0, noalloc: bool = False) -> np.ndarray:
+    """One synchronous batch solve over device-pointer CFGs and outputs: ompd_analyze_batch
+    with OMPD_F_DEVICE_PTRS, or (noalloc) ompd_analyze_batch_noalloc, which allocates no
+    device memory.  Returns the [n, 6] sweeps per phase."""
+    n = len(cfgs)
+    C = (_Cfg * max(n, 1))()
+    R = (_Res * max(n, 1))()
+    keep: list = []
+    for i in range(n):
+        C[i] = _cfg_struct(cfgs[i], keep)
+        r = _Res()
+        for k, f in _RES_FIELD.items():
+            v = int(getattr(results[i], k))
+            setattr(r, f, v if v else None)
+        R[i] = r
+    fn = lib().ompd_analyze_batch_noalloc if noalloc else lib().ompd_analyze_batch
+    _check(fn(ctx.h, C, R, n, int(flags) | F_DEVICE_PTRS, _vp(stream) if stream else None))
+    return _sweeps_of(R, n)
 
 
 class Plan:

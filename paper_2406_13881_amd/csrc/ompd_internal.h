@@ -22,6 +22,7 @@ struct ompd_ctx {
     uint64_t budget = 0;
     int64_t wall_khz = 100000;     // device wall-clock rate (s_memrealtime)
     int32_t wait_ticks = 0;        // bound of a kernel wait without progress, in wall-clock ticks
+    char* static_scratch = nullptr;   // this device's copy of the allocation-free entry point's scratch
     std::mutex mu;                 // serialises API calls
     ServingState* srv = nullptr;   // created on first submit
     std::mutex srv_mu;

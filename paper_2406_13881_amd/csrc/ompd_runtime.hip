@@ -38,6 +38,15 @@ using namespace ompd;
 
 static thread_local std::string g_err;
 
+// Scratch of the allocation-free batch entry point (ompd_analyze_batch_noalloc):
+// every device the library runs on holds its own copy, from the first context
+// on it until the process ends.  Host code never passes this name to a kernel
+// or a copy: it uses the device address that hipGetSymbolAddress returns for
+// the current device (ompd_ctx::static_scratch).
+constexpr size_t OMPD_STATIC_SCRATCH_BYTES = (size_t)OMPD_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) char scratch[OMPD_STATIC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu[64];   // one caller at a time per device (the scratch is shared)
+
 int ompd_fail(int code, const std::string& msg)
 {
     g_err = msg;
@@ -78,6 +87,14 @@ extern "C" int ompd_ctx_create(ompd_ctx** out, int device_ordinal, uint64_t budg
         c->wall_khz = khz;
     (void)hipGetLastError();
     c->wait_ticks = (int32_t)std::min<int64_t>(OMPD_WAIT_DEFAULT_NS / 1000 * c->wall_khz / 1000, INT32_MAX);
+    // this device's address of the static scratch (the device is current)
+    void* sp = nullptr;
+    e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !sp) {
+        delete c;
+        return ompd_fail(OMPD_E_DEVICE, std::string("static scratch address: ") + hipGetErrorString(e));
+    }
+    c->static_scratch = (char*)sp;
     size_t lds_max = c->prop.maxSharedMemoryPerMultiProcessor;
     if (!lds_max) lds_max = c->prop.sharedMemPerBlock;
     lds_max = std::min<size_t>(lds_max ? lds_max : 64 * 1024, 160 * 1024);
@@ -960,6 +977,94 @@ extern "C" int ompd_analyze_batch(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_resu
     if (!ctx) return ompd_fail(OMPD_E_INVAL, "ctx is NULL");
     std::lock_guard<std::mutex> lk(ctx->mu);
     return ompd_batch_locked(ctx, cfgs, res, n, flags, (hipStream_t)stream);
+}
+
+extern "C" int ompd_analyze_batch_noalloc(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32_t n,
+                                          uint32_t flags, void* stream)
+{
+    if (!ctx) return ompd_fail(OMPD_E_INVAL, "ctx is NULL");
+    if (!(flags & OMPD_F_DEVICE_PTRS)) return ompd_fail(OMPD_E_INVAL, "noalloc: needs OMPD_F_DEVICE_PTRS");
+    if (n < 0 || (n > 0 && (!cfgs || !res))) return ompd_fail(OMPD_E_INVAL, "bad arguments");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    std::lock_guard<std::mutex> sk(g_scratch_mu[ctx->device & 63]);
+    if (!ctx->static_scratch) return ompd_fail(OMPD_E_DEVICE, "noalloc: no static scratch on this device");
+    CK(hipSetDevice(ctx->device));
+    for (int i = 0; i < n; ++i) {
+        int rc = check_cfg_host(cfgs[i], i);
+        if (rc) return rc;
+    }
+    if (n == 0) return OMPD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    PlanConfig pc;
+    pc.use_graph = false;
+    if (flags & OMPD_F_TILE_KERNEL) pc.split = false;
+    if (const uint32_t r = (flags >> 8) & 7u) pc.lds_bytes = (size_t)(4u << r) * STATE_BYTES;
+    // layout of the static scratch: each CFG's solver scratch, the work counters, the default
+    // boundaries, then the launch tables (descriptors, tiles, pass items)
+    char* S = ctx->static_scratch;
+    std::vector<ScratchOff> off(n);
+    std::vector<size_t> base(n), boff(n);
+    size_t total = 0, bnd_words = 0;
+    for (int i = 0; i < n; ++i) {
+        base[i] = total;
+        total += ompd_cfg_scratch(cfgs[i], res[i], off[i]);
+        boff[i] = bnd_words;
+        bnd_words += 4 * (size_t)((cfgs[i].n_vars + 63) / 64);
+    }
+    const size_t counter_off = total;
+    total += 256;
+    const size_t bnd_off = total;
+    total += align256(8 * bnd_words);
+    std::vector<uint64_t> bnd(std::max<size_t>(bnd_words, 1), 0);
+    std::vector<DevCfg> h(n);
+    for (int i = 0; i < n; ++i)
+        ompd_fill_devcfg(cfgs[i], res[i], S + base[i], off[i], flags, ctx->wait_ticks, h[i], bnd.data() + boff[i],
+                         (uint64_t*)(S + bnd_off) + boff[i]);
+    Shape sh;
+    int rc = ompd_make_shape(ctx, h, pc, sh);
+    if (rc) return rc;
+    const size_t cfg_off = total;
+    total += align256(sizeof(DevCfg) * n);
+    const size_t tile_off = total;
+    total += align256(sizeof(Tile) * std::max<size_t>(sh.tiles.size(), 1));
+    const size_t item_off = total;
+    total += align256(sizeof(EdgeItem) * std::max<size_t>(sh.items.size(), 1));
+    if (total > OMPD_STATIC_SCRATCH_BYTES) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "noalloc: the batch needs %zu bytes of scratch, the static scratch holds %zu",
+                 total, OMPD_STATIC_SCRATCH_BYTES);
+        return ompd_fail(OMPD_E_NOMEM, buf);
+    }
+    // nothing here needs zeroed memory: the ingest kernel clears the counters and status words
+    if (bnd_words) CK(hipMemcpyAsync(S + bnd_off, bnd.data(), 8 * bnd_words, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(S + cfg_off, h.data(), sizeof(DevCfg) * n, hipMemcpyHostToDevice, s));
+    if (!sh.tiles.empty())
+        CK(hipMemcpyAsync(S + tile_off, sh.tiles.data(), sizeof(Tile) * sh.tiles.size(), hipMemcpyHostToDevice, s));
+    if (!sh.items.empty())
+        CK(hipMemcpyAsync(S + item_off, sh.items.data(), sizeof(EdgeItem) * sh.items.size(), hipMemcpyHostToDevice,
+                          s));
+    const DevCfg* dc = (const DevCfg*)(S + cfg_off);
+    int32_t* counter = (int32_t*)(S + counter_off);
+    rc = ompd_launch_prep(dc, n, counter, sh.lds_prep, sh.dims.ring_slots, s);
+    if (rc == OMPD_OK)
+        rc = ompd_launch_solve(dc, (const Tile*)(S + tile_off), (int)sh.tiles.size(), (const EdgeItem*)(S + item_off),
+                               (int)sh.items.size(), counter, sh.dims, s);
+    std::vector<int32_t> info((size_t)n * INFO_WORDS, 0);
+    if (rc == OMPD_OK)
+        for (int i = 0; i < n; ++i)
+            CK(hipMemcpyAsync(&info[(size_t)i * INFO_WORDS], h[i].info, 4 * INFO_WORDS, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));   // the host tables above stay alive until the copies are done
+    if (rc) return rc;
+    int first = OMPD_OK;
+    for (int i = 0; i < n; ++i) {
+        const int32_t* inf = &info[(size_t)i * INFO_WORDS];
+        for (int k = 0; k < 6; ++k) res[i].sweeps[k] = inf[INFO_SWEEPS + k];
+        if (inf[INFO_STATUS] && first == OMPD_OK) {
+            first = inf[INFO_STATUS];
+            g_err = ompd_status_message(i, inf);
+        }
+    }
+    return first;
 }
 
 extern "C" int ompd_analyze_cfg(ompd_ctx* ctx, const ompd_cfg* cfg, ompd_result* res, uint32_t flags, void* stream)
