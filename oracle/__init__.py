@@ -128,8 +128,14 @@ def solve(cfg, placement: int = 0, call: Optional[np.ndarray] = None,
         "ins_entry_h": np.zeros((nb, wd), np.uint64), "ins_entry_d": np.zeros((nb, wd), np.uint64),
         "ins_edge_h": np.zeros((max(ne, 1), wd), np.uint64), "ins_edge_d": np.zeros((max(ne, 1), wd), np.uint64),
         "var_kind": np.zeros(max(nv, 1), np.uint8), "after_dev": np.zeros(nb, np.uint8),
-        "before_dev": np.zeros(nb, np.uint8), "visits": np.zeros(6, np.int64),
+        "before_dev": np.zeros(nb, np.uint8), "fp_clause": np.zeros((nb, wd), np.uint64),
+        "visits": np.zeros(6, np.int64),
     }
+    scalar = getattr(cfg, "scalar", None)
+    if scalar is not None:
+        scalar = np.ascontiguousarray(scalar, dtype=np.uint64).reshape(wd)
+        if scalar.size == 0:
+            scalar = None
     # keep buffers of at least one element so every pointer is valid
     evh_, evd_, lxh_, lxd_ = [x if x.size else np.zeros(1, np.uint64) for x in (evh, evd, lxh, lxd)]
     R_ = R if R.size else np.zeros((nb, 1), np.uint64)
@@ -137,11 +143,12 @@ def solve(cfg, placement: int = 0, call: Optional[np.ndarray] = None,
     bufs = {k: (v if v.size else np.zeros(1, v.dtype)) for k, v in out.items()}
     rc = lib.oracle_solve(nb, ne, nv, int(cfg.entry), int(cfg.exit), _p(sp), _p(si), _p(kd), _p(spc),
                           _p(R_), _p(W_), _p(evh_), _p(evd_), _p(lxh_), _p(lxd_), _p(call), _p(sums),
-                          int(placement),
+                          int(placement), _p(scalar),
                           _p(bufs["nu_h"]), _p(bufs["nu_d"]), _p(bufs["ave_h"]), _p(bufs["ave_d"]),
                           _p(bufs["avf_h"]), _p(bufs["avf_d"]), _p(bufs["ins_entry_h"]), _p(bufs["ins_entry_d"]),
                           _p(bufs["ins_edge_h"]), _p(bufs["ins_edge_d"]), _p(bufs["var_kind"]),
-                          _p(bufs["after_dev"]), _p(bufs["before_dev"]), _p(bufs["visits"]))
+                          _p(bufs["after_dev"]), _p(bufs["before_dev"]), _p(bufs["fp_clause"]),
+                          _p(bufs["visits"]))
     if rc != 0:
         raise OracleError(rc)
     out["ins_edge_h"] = out["ins_edge_h"][:ne]

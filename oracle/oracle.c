@@ -32,6 +32,15 @@
  *   labels map(to/from/tofrom/alloc) versus target update (Table II), from
  *        reachability of device blocks (one target data region per function)
  *
+ * firstprivate (section "Data-Flow Analysis", the firstprivate paragraph,
+ * and Table II): a read-only scalar may reach a kernel as a firstprivate
+ * argument initialised from the host copy instead of being mapped.  The
+ * caller marks scalar variables; a marked variable that no DEVICE block
+ * writes is firstprivate.  A DEVICE block's read of it then needs the HOST
+ * copy valid at the kernel launch (a host use, not a device use), and at the
+ * end of that kernel the device copy is no longer valid; the kernel carries
+ * a firstprivate clause for it.
+ *
  * Interprocedural call blocks (section "Interprocedural Analysis") are
  * modelled by exact per-global summaries of the callee passed in by the
  * caller of this function: next use at the callee entry for exit-liveness 0
@@ -71,6 +80,7 @@ typedef struct {
     const uint64_t* ev[2]; const uint64_t* lx[2];
     const int32_t* call; const uint64_t* sums;
     uint64_t lastmask;
+    uint64_t* fp;          /* [wd] firstprivate variables (all zero when no scalar is marked) */
     int summary_mode;
     int32_t* rpo;  /* reverse post-order from ENTRY */
 } G;
@@ -87,11 +97,15 @@ static const uint64_t* sumrow(const G* g, int b, int row)
 static inline int is_call(const G* g, int b) { return g->call && g->call[b] >= 0; }
 
 /* USE_s(b) = R_b when b lies in space s; at EXIT it is the caller-supplied
- * liveness after the region (region-exit liveness). */
+ * liveness after the region (region-exit liveness).  A DEVICE block's read
+ * of a firstprivate variable is a use of the HOST copy (the kernel is
+ * launched with the host value). */
 static inline uint64_t use_s(const G* g, int s, int b, int w)
 {
     if (b == g->exit) return g->lx[s][w];
-    return ((int)g->space[b] == s) ? g->R[ix(g, b, w)] : 0ull;
+    uint64_t r = g->R[ix(g, b, w)];
+    if (g->space[b] == 1) return s == 1 ? (r & ~g->fp[w]) : (r & g->fp[w]);
+    return s == 0 ? r : 0ull;
 }
 
 /* WR_s(b) = W_b when b lies in space s. */
@@ -272,11 +286,14 @@ static int64_t phase_nu(const G* g, uint64_t* nu_h, uint64_t* nu_d)
 /* Validity transfer of one block (shared by AVE and AVF):
  *   block in space s:        out_s = in_s | W   (written here: valid here)
  *   block in the other space: out_s = in_s & ~W (written there: stale here)
+ *   DEVICE block, device copy: also & ~(R & FP) (firstprivate: not valid after the kernel)
  * call block: A1 = the above; out_s = T_s[A1][NUout_s]. */
 static uint64_t valid_out(const G* g, int s, int b, int w, uint64_t in_s, const uint64_t* nu_s)
 {
     uint64_t Wb = g->W[ix(g, b, w)];
     uint64_t a1 = ((int)g->space[b] == s) ? (in_s | Wb) : (in_s & ~Wb);
+    /* after a kernel that reads a firstprivate variable its device copy is no longer valid */
+    if (s == 1 && g->space[b] == 1) a1 &= ~(g->R[ix(g, b, w)] & g->fp[w]);
     if (!is_call(g, b)) return a1;
     uint64_t l = 0;
     for (int e = g->sp[b]; e < g->sp[b + 1]; ++e) l |= nu_s[ix(g, g->si[e], w)];
@@ -482,6 +499,8 @@ static int64_t phase_avf(const G* g, const uint64_t* nu[2], uint64_t* const ins_
  *   lx_h/lx_d  : next use after EXIT (liveness after the region)        [wd]
  *   call       : [n_blocks] summary index for call blocks, -1 otherwise (NULL = no calls)
  *   sums       : [n_summaries][SUM_ROWS][wd]
+ *   scalar     : [wd] variables the front end marks as scalars (NULL = none); those that
+ *                no DEVICE block writes are firstprivate
  *   placement  : bit 0: 0 = delayed placement (LATER), 1 = eager placement only;
  *                bit 8: evaluate a procedure summary — the boundary may leave a
  *                variable valid in neither space (a summary's entry-validity
@@ -490,7 +509,8 @@ static int64_t phase_avf(const G* g, const uint64_t* nu[2], uint64_t* const ins_
  *   nu_*[nb*wd] NUin, ave_*[nb*wd] AVEin, avf_*[nb*wd] AVFin,
  *   ins_entry_*[nb*wd] copy into that space just before block b,
  *   ins_edge_*[ne*wd] copy into that space on edge e,
- *   var_kind[nv] (1 MAP_TO | 2 MAP_FROM | 4 MAP_ALLOC), after_dev[nb], before_dev[nb],
+ *   var_kind[nv] (1 MAP_TO | 2 MAP_FROM | 4 MAP_ALLOC | 8 FIRSTPRIVATE), after_dev[nb], before_dev[nb],
+ *   fp_clause[nb*wd] the firstprivate clause of each DEVICE block (the firstprivate variables it reads),
  *   visits[6] worklist pops per phase (NU, AVE, MAYP, LATER, AVF, labels).
  * Returns 0, -1 (malformed input) or -2 (out of host memory).
  */
@@ -499,10 +519,11 @@ int oracle_solve(int32_t nb, int32_t ne, int32_t nv, int32_t entry, int32_t exit
                  const uint64_t* R, const uint64_t* W,
                  const uint64_t* ev_h, const uint64_t* ev_d, const uint64_t* lx_h, const uint64_t* lx_d,
                  const int32_t* call, const uint64_t* sums, int32_t placement,
+                 const uint64_t* scalar,
                  uint64_t* nu_h, uint64_t* nu_d, uint64_t* ave_h, uint64_t* ave_d,
                  uint64_t* avf_h, uint64_t* avf_d,
                  uint64_t* ins_entry_h, uint64_t* ins_entry_d, uint64_t* ins_edge_h, uint64_t* ins_edge_d,
-                 uint8_t* var_kind, uint8_t* after_dev, uint8_t* before_dev, int64_t* visits)
+                 uint8_t* var_kind, uint8_t* after_dev, uint8_t* before_dev, uint64_t* fp_clause, int64_t* visits)
 {
     G g;
     memset(&g, 0, sizeof(g));
@@ -513,8 +534,18 @@ int oracle_solve(int32_t nb, int32_t ne, int32_t nv, int32_t entry, int32_t exit
     g.lastmask = (nv % 64) ? ((1ull << (nv % 64)) - 1ull) : ~0ull;
     g.summary_mode = (placement >> 8) & 1;
     placement &= 1;
+    g.fp = (uint64_t*)calloc((size_t)(g.wd > 0 ? g.wd : 1), sizeof(uint64_t));
+    if (!g.fp) return OR_ENOMEM;
     int rc = validate_and_prepare(&g);
-    if (rc != OR_OK) { free(g.pp); free(g.pi); free(g.pe); free(g.rpo); return rc; }
+    if (rc != OR_OK) { free(g.pp); free(g.pi); free(g.pe); free(g.rpo); free(g.fp); return rc; }
+    /* firstprivate: marked scalars that no DEVICE block writes */
+    if (scalar) {
+        for (int w = 0; w < g.wd; ++w) {
+            uint64_t dev_w = 0;
+            for (int b = 0; b < nb; ++b) if (space[b] == 1) dev_w |= W[ix(&g, b, w)];
+            g.fp[w] = scalar[w] & ~dev_w & vmask(&g, w);
+        }
+    }
 
     size_t n = (size_t)nb * (size_t)g.wd;
     size_t nedge = (size_t)ne * (size_t)g.wd;
@@ -608,24 +639,30 @@ int oracle_solve(int32_t nb, int32_t ne, int32_t nv, int32_t entry, int32_t exit
             }
         }
         free(stk);
+        /* firstprivate clauses: a kernel reading a firstprivate variable */
+        for (int b = 0; b < nb; ++b)
+            for (int w = 0; w < g.wd; ++w)
+                fp_clause[ix(&g, b, w)] = space[b] == 1 ? (R[ix(&g, b, w)] & g.fp[w]) : 0ull;
         memset(var_kind, 0, (size_t)(nv > 0 ? nv : 0));
         for (int v = 0; v < nv; ++v) {
             int w = v >> 6;
             uint64_t bit = 1ull << (v & 63);
-            int to = 0, from = 0, dev_access = 0;
+            int to = 0, from = 0, dev_access = 0, fp_read = 0;
             for (int q = 0; q < nb; ++q) {
                 int pred_after = 0;
                 for (int k = g.pp[q]; k < g.pp[q + 1]; ++k) pred_after |= after_dev[g.pi[k]];
                 if ((ins_entry_d[ix(&g, q, w)] & bit) && !pred_after) to = 1;
                 if ((ins_entry_h[ix(&g, q, w)] & bit) && !before_dev[q]) from = 1;
-                if (space[q] == 1 && ((R[ix(&g, q, w)] | W[ix(&g, q, w)]) & bit)) dev_access = 1;
+                if (space[q] == 1 && (((R[ix(&g, q, w)] & ~g.fp[w]) | W[ix(&g, q, w)]) & bit)) dev_access = 1;
+                if (space[q] == 1 && (R[ix(&g, q, w)] & g.fp[w] & bit)) fp_read = 1;
                 for (int e = succ_ptr[q]; e < succ_ptr[q + 1]; ++e) {
                     int t = succ_idx[e];
                     if ((ins_edge_d[(size_t)e * g.wd + w] & bit) && !after_dev[q]) to = 1;
                     if ((ins_edge_h[(size_t)e * g.wd + w] & bit) && !before_dev[t]) from = 1;
                 }
             }
-            var_kind[v] = (uint8_t)((to ? 1 : 0) | (from ? 2 : 0) | ((dev_access && !to && !from) ? 4 : 0));
+            var_kind[v] = (uint8_t)((to ? 1 : 0) | (from ? 2 : 0) | ((dev_access && !to && !from) ? 4 : 0) |
+                                    (fp_read ? 8 : 0));
         }
         visits[5] = nb;
     }
@@ -633,6 +670,6 @@ int oracle_solve(int32_t nb, int32_t ne, int32_t nv, int32_t entry, int32_t exit
 done:
     free(aveout_h); free(aveout_d); free(mout_h); free(mout_d);
     free(lin_h); free(lin_d); free(lout_h); free(lout_d); free(avfout_h); free(avfout_d);
-    free(g.pp); free(g.pi); free(g.pe); free(g.rpo);
+    free(g.pp); free(g.pi); free(g.pe); free(g.rpo); free(g.fp);
     return rc;
 }

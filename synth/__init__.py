@@ -142,6 +142,7 @@ class CFG:
     loop_depth: Optional[np.ndarray] = None
     call_blocks: Optional[np.ndarray] = None
     seed: Optional[int] = None
+    scalar: Optional[np.ndarray] = None   # [wd] variables the front end marks as scalars (None = none)
 
     def __post_init__(self):
         if self.exit < 0:
@@ -303,6 +304,29 @@ def from_edges(blocks: Sequence[Tuple[int, Sequence[int], Sequence[int]]],
                space=space, R=R, W=W), csr_pos
 
 
+def mark_scalars(cfg: CFG, seed: int, frac: float = 0.3, read_only_frac: float = 0.5) -> CFG:
+    """Mark a seeded fraction `frac` of the variables as scalars (cfg.scalar).  For
+    `read_only_frac` of the marked ones, device writes are removed from W so that they are
+    read-only on the device (firstprivate candidates the analysis will accept); the others
+    keep their accesses.  Returns the CFG (modified in place)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nv, wd = cfg.n_vars, cfg.wd
+    pick = rng.random(nv) < frac
+    ro = pick & (rng.random(nv) < read_only_frac)
+    sc = np.zeros(wd, np.uint64)
+    rom = np.zeros(wd, np.uint64)
+    for v in np.nonzero(pick)[0]:
+        sc[v >> 6] |= np.uint64(1 << (int(v) & 63))
+    for v in np.nonzero(ro)[0]:
+        rom[v >> 6] |= np.uint64(1 << (int(v) & 63))
+    dev = np.asarray(cfg.space) == 1
+    W = np.array(cfg.W, dtype=np.uint64).reshape(cfg.n_blocks, wd)
+    W[dev] &= ~rom
+    cfg.W = W
+    cfg.scalar = sc
+    return cfg
+
+
 def permute_blocks(cfg: CFG, seed: int) -> Tuple[CFG, np.ndarray, np.ndarray]:
     """The same CFG with its block ids shuffled (ENTRY and EXIT keep theirs).
 
@@ -335,7 +359,7 @@ def permute_blocks(cfg: CFG, seed: int) -> Tuple[CFG, np.ndarray, np.ndarray]:
               space=np.ascontiguousarray(np.asarray(cfg.space)[inv]), R=np.ascontiguousarray(np.asarray(cfg.R)[inv]),
               W=np.ascontiguousarray(np.asarray(cfg.W)[inv]), entry=int(perm[cfg.entry]), exit=int(perm[cfg.exit]),
               entry_valid_h=cfg.entry_valid_h, entry_valid_d=cfg.entry_valid_d, exit_live_h=cfg.exit_live_h,
-              exit_live_d=cfg.exit_live_d, seed=cfg.seed)
+              exit_live_d=cfg.exit_live_d, seed=cfg.seed, scalar=cfg.scalar)
     return out, perm, edge_map
 
 

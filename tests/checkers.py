@@ -50,6 +50,13 @@ class View:
         self.ev = [row_int(evh), row_int(evd)]
         self.lx = [row_int(lxh), row_int(lxd)]
         self.space = [int(x) for x in cfg.space]
+        # firstprivate variables: marked scalars no DEVICE block writes
+        sc = getattr(cfg, "scalar", None)
+        dev_w = 0
+        for b in range(self.nb):
+            if self.space[b] == 1:
+                dev_w |= self.W[b]
+        self.fp = (row_int(np.asarray(sc, dtype=np.uint64)) & ~dev_w & self.full) if sc is not None else 0
         self.succ: List[List[Tuple[int, int]]] = [[] for _ in range(self.nb)]
         for p in range(self.nb):
             for e in range(int(cfg.succ_ptr[p]), int(cfg.succ_ptr[p + 1])):
@@ -57,9 +64,22 @@ class View:
         self.entry, self.exit = cfg.entry, cfg.exit
 
     def use(self, s: int, b: int) -> int:
+        """Reads of b that need the copy in space s (a kernel's read of a firstprivate
+        variable needs the host copy: the kernel is launched with the host value)."""
         if b == self.exit:
             return self.lx[s]
-        return self.R[b] if self.space[b] == s else 0
+        if self.space[b] == 1:
+            return self.R[b] & ~self.fp if s == 1 else self.R[b] & self.fp
+        return self.R[b] if s == 0 else 0
+
+    def after(self, s: int, b: int, val: int) -> int:
+        """Validity of the copy in space s after block b's own accesses (a write makes the
+        other copy stale; a kernel leaves no valid device copy of a firstprivate it reads)."""
+        w = self.W[b]
+        val = (val | w) if self.space[b] == s else (val & ~w)
+        if s == 1 and self.space[b] == 1:
+            val &= ~(self.R[b] & self.fp)
+        return val
 
     def paths_from(self, b: int) -> List[List[Tuple[int, int]]]:
         """All paths b -> EXIT as lists of (block, edge taken from it; -1 at EXIT)."""
@@ -127,8 +147,7 @@ def mop_valid(cfg, gen_entry: Sequence[List[int]], gen_edge: Sequence[Dict[int, 
                         val = val | gen_edge[s].get(e, 0) | gen_entry[s][x]
                     if x == q:
                         break
-                    w = V.W[x]
-                    val = (val | w) if V.space[x] == s else (val & ~w)
+                    val = V.after(s, x, val)
                 res[s][q] &= val
     return res[0], res[1]
 
@@ -172,8 +191,7 @@ def check_invariants(cfg, res) -> List[str]:
           rows_int(res["ins_edge_d"].reshape(-1, wd)) if cfg.n_edges else []]
 
     def out_valid(s, b):
-        w = V.W[b]
-        return (avf[s][b] | w) if V.space[b] == s else (avf[s][b] & ~w)
+        return V.after(s, b, avf[s][b])
 
     preds = cfg.preds()
     for p in range(nb):
@@ -221,6 +239,7 @@ def simulate_paths(cfg, res, walks: int, seed: int, cap_factor: int = 50) -> Tup
 
     R = [bits(x) for x in V.R]
     Wb = [bits(x) for x in V.W]
+    FP = bits(V.fp)
     ie = [[bits(x) for x in rows_int(res["ins_entry_h"])], [bits(x) for x in rows_int(res["ins_entry_d"])]]
     ig = [[bits(x) for x in rows_int(res["ins_edge_h"].reshape(-1, wd))] if cfg.n_edges else [],
           [bits(x) for x in rows_int(res["ins_edge_d"].reshape(-1, wd))] if cfg.n_edges else []]
@@ -269,12 +288,16 @@ def simulate_paths(cfg, res, walks: int, seed: int, cap_factor: int = 50) -> Tup
                         errs.append("walk %d: stale live-out in space %d, vars %s" % (wk, s, np.nonzero(bad)[0][:4].tolist()))
                 break
             x = V.space[b]
-            bad = R[b] & (vs[x] != ver)
+            # a kernel reads a firstprivate variable from the host copy (its launch value)
+            rfp = R[b] & FP if x == 1 else np.zeros(nv, dtype=bool)
+            bad = (R[b] & ~rfp & (vs[x] != ver)) | (rfp & (vs[0] != ver))
             if bad.any():
                 errs.append("walk %d: stale read in block %d space %d, vars %s" % (wk, b, x, np.nonzero(bad)[0][:4].tolist()))
             if Wb[b].any():
                 ver = ver + Wb[b].astype(np.int64)
                 vs[x] = np.where(Wb[b], ver, vs[x])
+            if rfp.any():
+                vs[1] = np.where(rfp, -1, vs[1])   # no valid device copy after the kernel
             steps += 1
             succ = V.succ[b]
             if steps < cap_factor * nb:

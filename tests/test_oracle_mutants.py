@@ -40,6 +40,17 @@ MUTANTS = {
                            "if ((ins_edge_h[(size_t)e * g.wd + w] & bit) && !before_dev[q]) from = 1;"),
     "alloc_always": ("((dev_access && !to && !from) ? 4 : 0)", "(dev_access ? 4 : 0)"),
     "exit_not_live": ("if (b == g->exit) return g->lx[s][w];", "if (b == g->exit) return 0;"),
+    # firstprivate
+    "fp_read_is_device_use": ("if (g->space[b] == 1) return s == 1 ? (r & ~g->fp[w]) : (r & g->fp[w]);",
+                              "if (g->space[b] == 1) return s == 1 ? r : 0ull;"),
+    "fp_no_host_use": ("if (g->space[b] == 1) return s == 1 ? (r & ~g->fp[w]) : (r & g->fp[w]);",
+                       "if (g->space[b] == 1) return s == 1 ? (r & ~g->fp[w]) : 0ull;"),
+    "fp_no_kill": ("if (s == 1 && g->space[b] == 1) a1 &= ~(g->R[ix(g, b, w)] & g->fp[w]);", ""),
+    "fp_device_written": ("g.fp[w] = scalar[w] & ~dev_w & vmask(&g, w);", "g.fp[w] = scalar[w] & vmask(&g, w);"),
+    "fp_clause_on_host": ("fp_clause[ix(&g, b, w)] = space[b] == 1 ? (R[ix(&g, b, w)] & g.fp[w]) : 0ull;",
+                          "fp_clause[ix(&g, b, w)] = R[ix(&g, b, w)] & g.fp[w];"),
+    "fp_alloc_too": ("if (space[q] == 1 && (((R[ix(&g, q, w)] & ~g.fp[w]) | W[ix(&g, q, w)]) & bit)) dev_access = 1;",
+                     "if (space[q] == 1 && ((R[ix(&g, q, w)] | W[ix(&g, q, w)]) & bit)) dev_access = 1;"),
 }
 
 
@@ -62,6 +73,9 @@ def run_pins():
                     return False
             if [int(x) for x in r["var_kind"]] != [VK[x] for x in exp["var_kind"]]:
                 return False
+            for k, want in g.get("expect_words", {}).items():
+                if [int(x) for x in r[k][:, 0]] != want:
+                    return False
         for seed in range(8):
             cfg = synth.random_dag(seed, 9, 65, p_loop_entry=0.3 if seed % 2 else 0.0)
             r = oracle.solve(cfg)
@@ -76,14 +90,33 @@ def run_pins():
                 return False
             if checkers.check_invariants(cfg, r):
                 return False
-        for seed in range(3):
-            cfg = synth.c1(seed)
+        for seed in range(8):
+            # marked scalars (some written on the device) and device-valid entry copies
+            cfg = synth.mark_scalars(synth.random_dag(100 + seed, 9, 65, p_loop_entry=0.3 if seed % 2 else 0.0),
+                                     seed, frac=0.5, read_only_frac=0.6)
+            m = synth.var_mask(cfg.n_vars)
+            rng = np.random.Generator(np.random.PCG64(seed))
+            evd = np.array([int(x) for x in rng.integers(0, 1 << 62, size=cfg.wd)], dtype=np.uint64) & m
+            cfg.entry_valid_d = evd
+            cfg.entry_valid_h = m.copy()
+            cfg.exit_live_d = np.array([int(x) for x in rng.integers(0, 1 << 62, size=cfg.wd)], dtype=np.uint64) & m
             r = oracle.solve(cfg)
+            nu_h, nu_d = checkers.mop_nu(cfg)
+            if checkers.rows_int(r["nu_h"]) != nu_h or checkers.rows_int(r["nu_d"]) != nu_d:
+                return False
+            if (checkers.rows_int(r["ave_h"]), checkers.rows_int(r["ave_d"])) != \
+                    checkers.mop_valid(cfg, [nu_h, nu_d], [{}, {}]):
+                return False
             if checkers.check_invariants(cfg, r):
                 return False
-            errs, _ = checkers.simulate_paths(cfg, r, walks=30, seed=seed)
-            if errs:
-                return False
+        for seed in range(3):
+            for cfg in (synth.c1(seed), synth.mark_scalars(synth.c1(seed), 7 + seed)):
+                r = oracle.solve(cfg)
+                if checkers.check_invariants(cfg, r):
+                    return False
+                errs, _ = checkers.simulate_paths(cfg, r, walks=30, seed=seed)
+                if errs:
+                    return False
     except oracle.OracleError:
         return False
     return True

@@ -23,7 +23,7 @@ import synth
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 SPACE = {"H": 0, "D": 1}
 KIND = {"N": 0, "BACK": 1, "LE": 2}
-VK = {"NONE": 0, "TO": 1, "FROM": 2, "TOFROM": 3, "ALLOC": 4}
+VK = {"NONE": 0, "TO": 1, "FROM": 2, "TOFROM": 3, "ALLOC": 4, "FIRSTPRIVATE": 8}
 
 
 def load_golden(path):
@@ -31,6 +31,11 @@ def load_golden(path):
     blocks = [(SPACE[s], r, w) for (s, r, w) in g["blocks"]]
     edges = [(s, d, KIND[k]) for (s, d, k) in g["edges"]]
     cfg, pos = synth.from_edges(blocks, edges, g["n_vars"])
+    if "scalar" in g:
+        sc = np.zeros(cfg.wd, np.uint64)
+        for v in g["scalar"]:
+            sc[v >> 6] |= np.uint64(1 << (v & 63))
+        cfg.scalar = sc
     return g, cfg, pos
 
 
@@ -46,6 +51,8 @@ def test_worked_example(path):
     for k in ("nu_h", "nu_d", "ave_h", "ave_d", "avf_h", "avf_d"):
         if k in exp:
             assert bits_of(r[k]) == exp[k], k
+    for k, want in g.get("expect_words", {}).items():
+        assert [int(x) for x in r[k][:, 0]] == want, k
     # edge indices in the fixture are positions in its own edge list
     inv = {int(pos[i]): i for i in range(len(pos))}
     for k in ("ins_edge_h", "ins_edge_d"):
