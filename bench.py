@@ -325,7 +325,8 @@ def main():
     cfgs = synth.c3(args.n, threads=min(16, os.cpu_count() or 4))
     facts = sum(c.facts for c in cfgs)
     log("generated %d CFGs, %d facts in %.1f s" % (len(cfgs), facts, time.perf_counter() - t))
-    want = ompd.OUTPUTS
+    # the synthetic CFGs carry no scalar marks: no firstprivate clause to write
+    want = tuple(k for k in ompd.OUTPUTS if k != "fp_clause")
     rb = ResidentBatch(ctx, cfgs, want=want)
     stream = torch.cuda.current_stream().cuda_stream
     tuned = load_tuned()

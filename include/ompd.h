@@ -60,7 +60,7 @@ extern "C" {
 /* ---- enums ----------------------------------------------------------- */
 enum { OMPD_HOST = 0, OMPD_DEVICE = 1 };                                  /* block space */
 enum { OMPD_EDGE_NORMAL = 0, OMPD_EDGE_BACK = 1, OMPD_EDGE_LOOP_ENTRY = 2 };  /* edge kind */
-enum { OMPD_MAP_TO = 1, OMPD_MAP_FROM = 2, OMPD_MAP_ALLOC = 4 };          /* var_kind bits */
+enum { OMPD_MAP_TO = 1, OMPD_MAP_FROM = 2, OMPD_MAP_ALLOC = 4, OMPD_FIRSTPRIVATE = 8 };   /* var_kind bits */
 
 /* ---- flags ----------------------------------------------------------- */
 #define OMPD_F_DEVICE_PTRS (1u << 0)      /* all pointers are device pointers               */
@@ -69,6 +69,14 @@ enum { OMPD_MAP_TO = 1, OMPD_MAP_FROM = 2, OMPD_MAP_ALLOC = 4 };          /* var
                                              leave variables valid in neither space            */
 #define OMPD_F_TILE_KERNEL (1u << 3)      /* one persistent kernel runs every phase of a tile
                                              (same results) instead of one kernel per phase */
+/* Schedule of the sweeps (results do not depend on it).  WALK: one block
+ * after another in block order, the states of recent blocks kept in LDS
+ * (best when a CFG has few blocks per level).  LEVEL: the blocks of a level
+ * (blocks that no chain of edges other than BACK edges orders) in parallel,
+ * a level at a time (best when levels are wide).  Neither flag: the library
+ * picks per CFG from its shape. */
+#define OMPD_F_SCHED_LEVEL (1u << 4)
+#define OMPD_F_SCHED_WALK (1u << 5)
 #define OMPD_F_SWEEP_CAP(n) ((((uint32_t)(n)) & 0xFFFFu) << 16) /* cap sweeps per phase */
 /* Ring of recently solved blocks per solve workgroup, for the one-shot entry
  * points (what ompd_plan_configure sets for a plan): n = 8, 16, 32 or 64
@@ -98,7 +106,15 @@ enum { OMPD_MAP_TO = 1, OMPD_MAP_FROM = 2, OMPD_MAP_ALLOC = 4 };          /* var
  * call_summary[b] of `summaries` (layout [n_summaries][16][wd], rows
  * MAYR_H MAYR_D MAYW_H MAYW_D NU0_H NU0_D NU1_H NU1_D T_H00 T_H01 T_H10
  * T_H11 T_D00 T_D01 T_D10 T_D11, identity for variables the callee cannot
- * see); call blocks must be HOST.  call_summary NULL = no calls.          */
+ * see); call blocks must be HOST.  call_summary NULL = no calls.
+ * firstprivate (section "Data-Flow Analysis", the firstprivate paragraph,
+ * and Table II): scalar [wd] marks the variables the front end knows to be
+ * scalars (NULL = none).  A marked variable that no DEVICE block writes is
+ * firstprivate: a kernel that reads it receives the host value at launch
+ * (its read needs the HOST copy valid, not the device copy), after that
+ * kernel the device copy is not valid, and the kernel carries a
+ * firstprivate clause for it (fp_clause).  ompd_analyze_program ignores the
+ * marks of its procedures (their fp_clause outputs are all zero).          */
 typedef struct {
     int32_t n_blocks, n_edges, n_vars;
     int32_t entry, exit;
@@ -116,6 +132,7 @@ typedef struct {
     const uint64_t* summaries;        /* [n_summaries*16*wd] or NULL */
     int32_t n_summaries;
     int32_t reserved;
+    const uint64_t* scalar;           /* [wd] or NULL */
 } ompd_cfg;
 
 /* Outputs; any pointer may be NULL (not requested).
@@ -125,6 +142,10 @@ typedef struct {
  *   ins_entry_to_dev / _to_host [n_blocks*wd] copy into that space just before block b
  *   ins_edge_to_dev  / _to_host [n_edges*wd]  copy into that space on edge e
  *   var_kind      [n_vars]   OMPD_MAP_TO | OMPD_MAP_FROM (both = tofrom), or OMPD_MAP_ALLOC
+ *                 (a device access that no map clause covers); | OMPD_FIRSTPRIVATE
+ *                 when a kernel reads it as firstprivate
+ *   fp_clause     [n_blocks*wd] the firstprivate clause of each DEVICE block (the
+ *                 firstprivate variables it reads; zero elsewhere)
  *   after_dev     [n_blocks] 1 iff some DEVICE block reaches b (b included)
  *   before_dev    [n_blocks] 1 iff b reaches some DEVICE block (b included)
  * Labels: a copy into the device on edge p->q is map(to) iff !after_dev[p],
@@ -143,6 +164,7 @@ typedef struct {
     uint8_t* var_kind;
     uint8_t* after_dev;
     uint8_t* before_dev;
+    uint64_t* fp_clause;
     int32_t sweeps[6];
 } ompd_result;
 
@@ -215,11 +237,22 @@ int ompd_plan_create(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int3
                      ompd_plan** out);
 int ompd_plan_run(ompd_plan* plan, void* stream);
 int ompd_plan_status(ompd_plan* plan, int32_t* per_cfg);
-/* Autotuner: times each candidate launch configuration (LDS ring bytes per
- * solve workgroup, workgroups per CU) `trials` times on `stream` and keeps
- * the fastest.  Results are bit-identical for every candidate.  best_ms may
- * be NULL. */
+/* Autotuner: first the schedule of each size bucket (below), each bucket's
+ * CFGs timed alone under the walk and the level schedule; then each
+ * candidate launch configuration (LDS ring bytes per solve workgroup,
+ * workgroups per CU) on the whole plan; every candidate is timed `trials`
+ * times on `stream` and the fastest kept.  Results are bit-identical for
+ * every candidate.  best_ms (the whole plan with the choice) may be NULL. */
 int ompd_plan_autotune(ompd_plan* plan, void* stream, int32_t trials, float* best_ms);
+/* Schedule per size bucket (what the autotuner chooses first, then the
+ * launch configuration with that schedule): bucket k holds the CFGs with
+ * fewer than 256, 1,024, 4,096, 16,384 blocks, or more (k = 0..4); per_bucket[k]
+ * is -1 (the library's rule), 0 (walk) or 1 (level); CFGs whose schedule the
+ * plan's flags name, and CFGs too large for the level schedule, keep theirs.
+ * The autotuner times each bucket alone under both schedules.  Results are
+ * bit-identical for every choice.  ompd_plan_describe reports the choice. */
+#define OMPD_SCHED_BUCKETS 5
+int ompd_plan_set_schedule(ompd_plan* plan, const int32_t* per_bucket);
 /* Set the launch configuration by hand (what the autotuner chooses among):
  * LDS bytes per solve workgroup for the ring of recently solved blocks
  * (256 bytes per block; 0 = default, 16 KiB; rounded down to a power of

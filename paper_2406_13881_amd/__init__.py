@@ -39,6 +39,8 @@ OMPD_E_TIMEOUT = -7
 F_DEVICE_PTRS = 1 << 0
 F_PLACEMENT_EAGER = 1 << 1
 F_TILE_KERNEL = 1 << 3
+F_SCHED_LEVEL = 1 << 4
+F_SCHED_WALK = 1 << 5
 
 
 def F_RING_SLOTS(n: int) -> int:
@@ -52,7 +54,7 @@ def F_SWEEP_CAP(n: int) -> int:
 
 
 OUTPUTS = ("nu_h", "nu_d", "ave_h", "ave_d", "avf_h", "avf_d", "ins_entry_h", "ins_entry_d",
-           "ins_edge_h", "ins_edge_d", "var_kind", "after_dev", "before_dev")
+           "ins_edge_h", "ins_edge_d", "var_kind", "after_dev", "before_dev", "fp_clause")
 
 
 def build() -> str:
@@ -86,14 +88,14 @@ class _Cfg(ctypes.Structure):
                 ("read_bits", _vp), ("write_bits", _vp),
                 ("entry_valid_host", _vp), ("entry_valid_dev", _vp), ("exit_live_host", _vp),
                 ("exit_live_dev", _vp), ("call_summary", _vp), ("summaries", _vp),
-                ("n_summaries", _i32), ("reserved", _i32)]
+                ("n_summaries", _i32), ("reserved", _i32), ("scalar", _vp)]
 
 
 class _Res(ctypes.Structure):
     _fields_ = [("nu_host", _vp), ("nu_dev", _vp), ("ave_host", _vp), ("ave_dev", _vp),
                 ("avf_host", _vp), ("avf_dev", _vp), ("ins_entry_to_dev", _vp), ("ins_entry_to_host", _vp),
                 ("ins_edge_to_dev", _vp), ("ins_edge_to_host", _vp), ("var_kind", _vp),
-                ("after_dev", _vp), ("before_dev", _vp), ("sweeps", _i32 * 6)]
+                ("after_dev", _vp), ("before_dev", _vp), ("fp_clause", _vp), ("sweeps", _i32 * 6)]
 
 
 class _Prog(ctypes.Structure):
@@ -110,7 +112,7 @@ _RES_FIELD = {"nu_h": "nu_host", "nu_d": "nu_dev", "ave_h": "ave_host", "ave_d":
               "avf_h": "avf_host", "avf_d": "avf_dev", "ins_entry_h": "ins_entry_to_host",
               "ins_entry_d": "ins_entry_to_dev", "ins_edge_h": "ins_edge_to_host",
               "ins_edge_d": "ins_edge_to_dev", "var_kind": "var_kind", "after_dev": "after_dev",
-              "before_dev": "before_dev"}
+              "before_dev": "before_dev", "fp_clause": "fp_clause"}
 
 _lock = threading.Lock()
 _handle = None
@@ -147,6 +149,7 @@ def lib():
             L.ompd_plan_run.argtypes = [_vp, _vp]
             L.ompd_plan_status.argtypes = [_vp, _vp]
             L.ompd_plan_autotune.argtypes = [_vp, _vp, _i32, P(ctypes.c_float)]
+            L.ompd_plan_set_schedule.argtypes = [_vp, _vp]
             L.ompd_plan_describe.argtypes = [_vp, ctypes.c_char_p, _i32]
             L.ompd_plan_configure.argtypes = [_vp, ctypes.c_int64, _i32]
             L.ompd_plan_profile.argtypes = [_vp, _i32]
@@ -200,6 +203,7 @@ class DeviceCFG:
     call_summary: int = 0
     summaries: int = 0
     n_summaries: int = 0
+    scalar: int = 0
 
 
 def _cfg_struct(cfg, keep: list) -> _Cfg:
@@ -208,7 +212,7 @@ def _cfg_struct(cfg, keep: list) -> _Cfg:
         for f in ("n_blocks", "n_edges", "n_vars", "entry", "exit", "n_summaries"):
             setattr(s, f, int(getattr(cfg, f)))
         for f in ("succ_ptr", "succ_idx", "edge_kind", "space", "read_bits", "write_bits", "entry_valid_host",
-                  "entry_valid_dev", "exit_live_host", "exit_live_dev", "call_summary", "summaries"):
+                  "entry_valid_dev", "exit_live_host", "exit_live_dev", "call_summary", "summaries", "scalar"):
             v = int(getattr(cfg, f))
             setattr(s, f, v if v else None)
         return s
@@ -244,6 +248,9 @@ def _cfg_struct(cfg, keep: list) -> _Cfg:
         s.call_summary = _np_ptr(arr(call, np.int32))
         s.summaries = _np_ptr(sums)
         s.n_summaries = int(sums.size // (16 * max(wd, 1))) if wd else int(getattr(cfg, "n_summaries", 1))
+    sc = getattr(cfg, "scalar", None)
+    if sc is not None:
+        s.scalar = _np_ptr(arr(sc, np.uint64))
     return s
 
 
@@ -392,7 +399,7 @@ def _program_contexts(self, prog) -> List[tuple]:
     return [(int(cp[k]), _sigma(int(c0[k]), int(c1[k]))) for k in range(n.value)]
 
 
-def _analyze_program(self, prog, flags: int = 0, want: Sequence[str] = OUTPUTS) -> Dict:
+def _analyze_program(self, prog, flags: int = 0, want: Sequence[str] = OUTPUTS[:-1]) -> Dict:
     """ompd_analyze_program: per-context results, boundaries, summaries and demands."""
     keys = self.program_contexts(prog)
     keep: list = []
@@ -520,6 +527,7 @@ class DeviceResult:
     var_kind: int = 0
     after_dev: int = 0
     before_dev: int = 0
+    fp_clause: int = 0
 
 
 def analyze_device(ctx: Context, cfgs: Sequence[DeviceCFG], results: Sequence[DeviceResult], flags: int = 0,
@@ -603,6 +611,12 @@ class Plan:
         _check(lib().ompd_plan_kernel_ms(self.h, buf, 16, ctypes.byref(n)))
         names = self.KERNELS if n.value == len(self.KERNELS) else self.KERNELS_TILE
         return {k: float(buf[i]) for i, k in enumerate(names[:n.value])}
+
+    def set_schedule(self, per_bucket):
+        """ompd_plan_set_schedule: -1 (rule), 0 (walk) or 1 (level) per size bucket (5)."""
+        v = np.asarray(list(per_bucket), np.int32)
+        assert v.size == 5
+        _check(lib().ompd_plan_set_schedule(self.h, _vp(v.ctypes.data)))
 
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(1024)

@@ -8,7 +8,7 @@ namespace ompd {
 
 enum : int32_t {
     INFO_STATUS = 0,      // 0 ok, else an OMPD_E_* code
-    INFO_RESERVED = 1,
+    INFO_LEVELS = 1,      // levels of the CFG (level schedule; written by the ingest kernel)
     INFO_SWEEPS = 2,      // [2..7] max sweeps per phase over the CFG's tiles
     // the first wait of the CFG's solve that gave up (status OMPD_E_DEVICE): phase + 1 (0 = none),
     // the tile's index within the CFG, which counter was awaited (WAIT_*), the value last seen,
@@ -42,6 +42,8 @@ struct DevCfg {
     int32_t nb, ne, nv, entry, exit, wd;   // wd = 64-bit words per row
     int32_t n_sums, placement, sweep_cap;   // placement: bit 0 eager, bit 1 summary evaluation
     int32_t wait_ticks;   // a wait gives up after this many wall-clock ticks without progress (> 0)
+    int32_t sched;        // SCHED_WALK or SCHED_LEVEL
+    int32_t sched_rule;   // host side: 1 when the default rule chose sched (a launch may revise it)
     const int32_t* succ_ptr;
     const int32_t* succ_idx;
     const uint8_t* kind;
@@ -54,6 +56,9 @@ struct DevCfg {
     const uint64_t* lx_d;
     const int32_t* call;        // NULL = no call blocks
     const uint64_t* sums;
+    const uint64_t* scalar;     // [wd] variables marked as scalars, or NULL
+    uint64_t* fp;               // [wd] firstprivate variables (ingest: marked, written by no DEVICE block)
+    uint64_t* fpc;              // [nb*wd] output: each DEVICE block's firstprivate clause, or NULL
     uint64_t* nu_h;  uint64_t* nu_d;
     uint64_t* ave_h; uint64_t* ave_d;
     uint64_t* avf_h; uint64_t* avf_d;      // may be NULL
@@ -68,15 +73,23 @@ struct DevCfg {
     uint64_t* eag_h;    uint64_t* eag_d;      // per edge: eager copies
     uint64_t* both;     // per edge: valid in both spaces under the final placement
     uint64_t* flg;      // per tile: [4][nb] words of the flag lane
-    uint64_t* vk_acc;   // [3][wd] map-kind masks (to, from, used on the device); NULL = no map kinds
+    uint64_t* vk_acc;   // [4][wd] map-kind masks (to, from, used on the device, firstprivate read);
+                        // NULL = no map kinds
     int32_t* pred_ptr;  int32_t* pred_idx; int32_t* pred_eid;
     int32_t* tmp;
     int32_t* rec_f;     // [2*nb] int4: block records with predecessors, in block-id order
     int32_t* rec_b;     // [2*nb] int4: block records with successors, in block-id order
     int32_t* step_f;    // [2*nb] int4: step entries of the forward walk, in walk order
     int32_t* step_b;    // [2*nb] int4: step entries of the backward walk, in walk order
+    int32_t* lorder;    // [nb] the blocks by level (level schedule)
+    int32_t* loff;      // [nb + 1] start of each level in lorder
     int32_t* info;
 };
+
+// How a CFG's phases visit its blocks: one block after another along the
+// block order (the walk), or a level at a time with the blocks of a level in
+// parallel.  Results do not depend on it.
+enum : int32_t { SCHED_WALK = 0, SCHED_LEVEL = 1 };
 
 // record meta word: neighbour count | flags
 constexpr uint32_t REC_COUNT = 0x00FFFFFFu;
@@ -124,14 +137,15 @@ constexpr int LDS_FIXED = CTL_BYTES;
 // The helper wavefront refills them in rounds whose fixed cost is spread over the steps it
 // finds free, so a deeper ring means fewer, longer rounds.
 constexpr int in_ring(int ph) { return ph == PH_NU || ph == PH_AVE ? 32 : 16; }
-inline int phase_inputs(int ph) { return 2 + (ph == PH_NU ? 2 : ph == PH_AVE ? 3 : ph == PH_MAYP ? 6 : ph == PH_LATER ? 8 : 7); }
+inline int phase_inputs(int ph) { return 2 + (ph == PH_NU ? 2 : ph == PH_AVE ? 4 : ph == PH_MAYP ? 6 : 8); }
 inline size_t phase_lds(int ph, int ring_slots)
 {
     return LDS_FIXED + (size_t)ring_slots * STATE_BYTES + (size_t)in_ring(ph) * (phase_inputs(ph) * WORD_BYTES + 16) +
            STATE_BYTES;
 }
-// Work counters (int32) of one solve launch: phases 0..4, passes 8..11, map kinds 12.
-constexpr int N_COUNTERS = 16;
+// Work counters (int32) of one solve launch: phases 0..4, passes 8..11, map kinds 12, per-tile
+// kernel 13, level kernels 16..20.
+constexpr int N_COUNTERS = 32;
 // Kernels of one solve launch, in launch order (prep excluded).
 constexpr int N_SOLVE_KERNELS = 10;
 

@@ -38,6 +38,9 @@ struct LaunchDims {
     int grid_edge = 1;
     size_t lds_tile = 0;         // the per-tile kernel: LDS of its largest phase
     int grid_tile = 1;
+    int n_level = 0;             // level tiles: the last n_level entries of the tile array
+    size_t lds_level = 0;        // LDS of a level workgroup (the largest level CFG's column state)
+    int grid_level = 1;
 };
 
 // Tunable launch configuration of a plan; results never depend on it.
@@ -46,7 +49,16 @@ struct PlanConfig {
     int wg_per_cu = 0;      // phase workgroups per CU (0 = as many as fit)
     bool split = true;      // one kernel per phase and pass (else one per-tile kernel)
     bool use_graph = true;  // replay a captured HIP graph
+    // schedule per size bucket (ompd_sched_bucket): -1 the default rule, else SCHED_WALK or
+    // SCHED_LEVEL; CFGs whose schedule the plan's flags name keep it
+    int bucket_sched[OMPD_SCHED_BUCKETS] = {-1, -1, -1, -1, -1};
+    int only_bucket = -1;   // autotuning: solve only the CFGs of this bucket (-1: all)
 };
+// Size bucket of a CFG for the schedule choice: blocks below 256, 1,024, 4,096, 16,384, or more.
+inline int ompd_sched_bucket(int n_blocks)
+{
+    return n_blocks < 256 ? 0 : n_blocks < 1024 ? 1 : n_blocks < 4096 ? 2 : n_blocks < 16384 ? 3 : 4;
+}
 
 struct ompd_plan {
     ompd_ctx* ctx = nullptr;
@@ -81,11 +93,27 @@ int ompd_fail(int code, const std::string& msg);
 std::string ompd_status_message(int i, const int32_t* info);
 
 struct ScratchOff {
-    size_t aveout, mayp, later, flg, eag, both, nu, ave, ie, ig, avf, vk, bnd, pp, pi, pe, tmp, recf, recb, stf, stb, info;
+    size_t aveout, mayp, later, flg, eag, both, nu, ave, ie, ig, avf, vk, bnd, pp, pi, pe, tmp, recf, recb, stf, stb,
+        lorder, loff, fp, info;
 };
 size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o);
 void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const ScratchOff& o, uint32_t flags,
                       int32_t wait_ticks, ompd::DevCfg& d, uint64_t* bnd_host, uint64_t* bnd_dev = nullptr);
+// Blocks from which a CFG takes the level schedule when the caller names none
+// (the walk below: CFGs of a few thousand blocks have too few blocks per level
+// to beat it, measured 62 against 75 ms for an 8,194-block CFG; a
+// 16,386-block one runs 3.6x faster on levels), and the most blocks a CFG on
+// the level schedule may have (its column's state, 8 bytes per block, must
+// fit a workgroup's LDS; larger CFGs take the walk whatever the caller asks).
+constexpr int OMPD_LEVEL_MIN_BLOCKS = 12288;
+constexpr int OMPD_LEVEL_MAX_BLOCKS = 20000;
+int ompd_default_sched(int n_blocks, int n_vars);
+// A level tile keeps a whole column of its CFG in LDS, so a CU runs one at a time: the level
+// schedule has the lower latency per CFG but the lower throughput per CU.  When the CFGs that
+// the default rule put on it have more level tiles than this many rounds of the CUs take, they
+// go back to the walk (the launch is throughput-bound then).
+constexpr int OMPD_LEVEL_ROUNDS = 3;
+void ompd_settle_sched(ompd::DevCfg* h, int n, int n_cu);
 // Default bound of a kernel wait without progress (the longest legitimate wait is one step of
 // the other wavefront, microseconds).
 constexpr int64_t OMPD_WAIT_DEFAULT_NS = 2000000000ll;

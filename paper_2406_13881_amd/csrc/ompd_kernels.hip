@@ -145,7 +145,7 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
     __shared__ int s_err;
     __shared__ int32_t s_scan[16];
     const int ci = blockIdx.x;
-    if (ci == 0 && threadIdx.x < 16) solve_counter[threadIdx.x] = 0;   // work counters of the solve kernels
+    if (ci == 0 && threadIdx.x < N_COUNTERS) solve_counter[threadIdx.x] = 0;   // work counters of the solve kernels
     if (ci >= n_cfgs) return;
     const DevCfg c = cfgs[ci];
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -153,7 +153,8 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
     if (tid == 0) s_err = 0;
     for (int i = tid; i < INFO_WORDS; i += nt) c.info[i] = 0;
     if (c.var_kind)
-        for (int i = tid; i < 3 * wd; i += nt) c.vk_acc[i] = 0;
+        for (int i = tid; i < 4 * wd; i += nt) c.vk_acc[i] = 0;
+    for (int w = tid; w < wd; w += nt) c.fp[w] = 0;
     __syncthreads();
 
     // validation, stage 1: pointers, kinds, spaces
@@ -205,6 +206,25 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
     __syncthreads();
     if (s_err) { if (tid == 0) c.info[INFO_STATUS] = OMPD_E_INVAL_; return; }
 
+    // firstprivate variables: marked scalars that no DEVICE block writes (the OR of the device
+    // blocks' writes gathers in c.fp first)
+    if (c.scalar && wd > 0) {
+        for (size_t i = tid; i < (size_t)nb * wd; i += nt) {
+            const int b = (int)(i / wd), w = (int)(i % wd);
+            if (c.space[b]) {
+                const uint64_t x = c.W[i];
+                if (x) atomicOr((unsigned long long*)&c.fp[w], (unsigned long long)x);
+            }
+        }
+        __syncthreads();
+        const uint64_t last = (c.nv & 63) ? ((1ull << (c.nv & 63)) - 1ull) : ~0ull;
+        for (int w = tid; w < wd; w += nt) {
+            // the atomics above ran in L2: read their result there, past this CU's cache
+            const uint64_t dw = __hip_atomic_load(&c.fp[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            c.fp[w] = c.scalar[w] & ~dw & (w == wd - 1 ? last : ~0ull);
+        }
+        __syncthreads();
+    }
     // predecessor CSR
     int32_t* pp = c.pred_ptr;
     for (int b = tid; b <= nb; b += nt) pp[b] = 0;
@@ -259,6 +279,56 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
         RB[2 * b + 1] = r1;
     }
     __syncthreads();
+    // levels (level schedule only): peel the graph from ENTRY over the edges other than BACK;
+    // the blocks of a round form a level.  Blocks left over (a cycle closed by an edge not marked
+    // BACK, or unreachable ones, which the validity phase rejects) get a level each, in id order.
+    if (c.sched == SCHED_LEVEL) {
+        __shared__ int s_tail;
+        int32_t* deg = c.tmp;
+        for (int b = tid; b < nb; b += nt) {
+            int k = 0;
+            for (int j = pp[b]; j < pp[b + 1]; ++j) k += c.kind[c.pred_eid[j]] != 1;
+            deg[b] = k;
+        }
+        if (tid == 0) { c.lorder[0] = c.entry; s_tail = 1; }
+        __syncthreads();
+        int fa = 0, fb = 1, nl = 0;
+        while (fa < fb) {
+            if (tid == 0) c.loff[nl] = fa;
+            for (int i = fa + tid; i < fb; i += nt) {
+                const int b = c.lorder[i];
+                for (int e = c.succ_ptr[b]; e < c.succ_ptr[b + 1]; ++e) {
+                    if (c.kind[e] == 1) continue;
+                    const int q = c.succ_idx[e];
+                    if (atomicSub(&deg[q], 1) == 1) c.lorder[atomicAdd(&s_tail, 1)] = q;
+                }
+            }
+            __syncthreads();
+            fa = fb;
+            fb = s_tail;
+            ++nl;
+            __syncthreads();
+        }
+        if (fb < nb) {
+            // leftovers: blocks never placed, one level each
+            __shared__ int s_n;
+            for (int i = tid; i < fb; i += nt) deg[c.lorder[i]] = -1;
+            __syncthreads();
+            if (tid == 0) {
+                int n = fb;
+                for (int b = 0; b < nb; ++b)
+                    if (deg[b] != -1) { c.lorder[n] = b; c.loff[nl++] = n; ++n; }
+                s_n = nl;
+            }
+            __syncthreads();
+            nl = s_n;
+        }
+        if (tid == 0) {
+            c.loff[nl] = nb;
+            c.info[INFO_LEVELS] = nl;
+        }
+        __syncthreads();
+    }
     // step entries in walk order: position i is block i forward, block nb - 1 - i backward
     int4* SF = reinterpret_cast<int4*>(c.step_f);
     int4* SB = reinterpret_cast<int4*>(c.step_b);
@@ -332,6 +402,18 @@ __device__ __forceinline__ Rec ldrec(const int32_t* base, int b)
     Rec r;
     r.meta = (uint32_t)q[0]; r.n0 = q[1]; r.n1 = q[2]; r.e0 = (uint32_t)q[3];
     r.e1 = (uint32_t)q[4]; r.ovf = q[5]; r.ci = q[6]; r.pad = q[7];
+    return r;
+}
+
+// Record b of a record array, b per lane.
+__device__ __forceinline__ Rec ldrec_v(const int32_t* base, int b)
+{
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const GAS v4i* q = reinterpret_cast<const GAS v4i*>(G(base)) + 2 * (size_t)b;
+    const v4i x = q[0], y = q[1];
+    Rec r;
+    r.meta = (uint32_t)x.x; r.n0 = x.y; r.n1 = x.z; r.e0 = (uint32_t)x.w;
+    r.e1 = (uint32_t)y.x; r.ovf = y.y; r.ci = y.z; r.pad = y.w;
     return r;
 }
 
@@ -468,9 +550,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
 {
     constexpr bool with_flags = PH == PH_NU || PH == PH_AVE;   // phases with the flag lane
     constexpr bool BWD = PH == PH_NU;
-    constexpr int NX = PH == PH_NU ? 2 : PH == PH_AVE ? 3 : PH == PH_MAYP ? 6 : PH == PH_LATER ? 8 : 7;
+    constexpr int NX = PH == PH_NU ? 2 : PH == PH_AVE ? 4 : PH == PH_MAYP ? 6 : 8;
     // the first input that is a row of the second edge (NX: the phase reads no edge rows)
-    constexpr int NX1 = PH == PH_MAYP ? 4 : PH == PH_LATER ? 5 : PH == PH_AVF ? 5 : NX;
+    constexpr int NX1 = PH == PH_MAYP ? 4 : PH == PH_LATER ? 5 : PH == PH_AVF ? 6 : NX;
     constexpr int NI = NX + 2;        // inputs of a step: the phase's own and the first far neighbour (h, d)
     constexpr int IR = in_ring(PH);   // steps whose inputs the helper keeps ready
     // Lanes 0 .. LANES - 1 of both wavefronts own the tile's words, lanes LANES .. 2 LANES - 1
@@ -504,6 +586,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // valid-variable mask of the lane's word (shadow lanes share word s0's; the flag lane uses bits 0-1)
     const u64 vm64 = flg ? 3ull : ((w == wd - 1 && (c.nv & 63)) ? ((1ull << (c.nv & 63)) - 1ull) : ~0ull);
     const hw vm = (hw)(hi ? vm64 >> 32 : vm64);   // its half
+    // the firstprivate variables of the lane's word (a kernel's read of one is a host use, and the
+    // device copy is not valid after that kernel); none for the flag lane
+    const hw fph = (flg || !wd) ? 0u : ld_half(G(c.fp) + (size_t)w, hi);
     const int cap = c.sweep_cap > 0 ? c.sweep_cap : 2 * nb + 2;
     const int32_t* REC = BWD ? c.rec_b : c.rec_f;
     const CAS int32_t* PI = K(c.pred_idx);
@@ -895,10 +980,10 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     };
     // validity transfer of block b (a call applies the callee's exit-validity
     // tables to the validity after the block's own accesses and the next use after the call)
-    auto valid_out = [&](int b, const Rec& r, hw ih, hw id, hw wr, hw& oh, hw& od) {
+    auto valid_out = [&](int b, const Rec& r, hw ih, hw id, hw wr, hw rr, hw& oh, hw& od) {
         const bool dev = r.meta & REC_DEV;
         hw ah = dev ? (ih & ~wr) : (ih | wr);
-        hw ad = dev ? (id | wr) : (id & ~wr);
+        hw ad = dev ? ((id | wr) & ~(rr & fph)) : (id & ~wr);
         if (r.meta & REC_CALL) {
             hw lh, ld;
             nu_after(b, lh, ld);
@@ -946,15 +1031,15 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 oh = flg ? oh : ch;
                 od = flg ? od : cd;
             }
-            vh = (dev ? 0u : rr) | (~ww & oh);
-            vd = (dev ? rr : 0u) | (~ww & od);
+            vh = (dev ? (rr & fph) : rr) | (~ww & oh);
+            vd = (dev ? (rr & ~fph) : 0u) | (~ww & od);
         };
         auto fast = [&](const hw* x, const hw* nh, const hw* nd, uint32_t fl, hw& vh, hw& vd) {
             const hw dev = fmask(fl, DD_DEV);
             const hw rr = flg ? lo(2) : x[0], ww = flg ? (lo(2) & dev) : x[1];
             const hw oh = nh[0] | nh[1], od = nd[0] | nd[1];
-            vh = (rr & ~dev) | (~ww & oh);
-            vd = (rr & dev) | (~ww & od);
+            vh = (rr & (~dev | fph)) | (~ww & oh);
+            vd = (rr & dev & ~fph) | (~ww & od);
         };
         run_phase(S, 0ull, 0ull, pre, fast, comp);
         return;
@@ -965,11 +1050,13 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     if constexpr (PH == PH_AVE) {
         const Rows S = rows_of(c.aveout_h, c.aveout_d, 2);
         const hw init = vm;
-        // x0/x1 = NU (flag lane: 0), x2 = W (flag lane: 2 at DEVICE blocks), substituted when computed
+        // x0/x1 = NU (flag lane: 0), x2 = W (flag lane: 2 at DEVICE blocks), substituted when computed,
+        // x3 = R (the firstprivate reads of a kernel)
         auto pre = [&](u64 ob, u64, u64, const GAS u64** x) {
             x[0] = rowu(c.nu_h, ob);
             x[1] = rowu(c.nu_d, ob);
             x[2] = rowu(c.W, ob);
+            x[3] = rowu(c.R, ob);
         };
         auto comp = [&](int b, const Rec& r, const hw* x, const hw* nh, const hw* nd, hw ph, hw pd, int sweep,
                         int g, hw& vh, hw& vd) {
@@ -993,14 +1080,14 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 ih = (flg ? 0u : x[0]) | mh;
                 id = (flg ? 0u : x[1]) | md;
             }
-            valid_out(b, r, ih & vm, id & vm, flg ? ((r.meta & REC_DEV) ? lo(2) : 0u) : x[2], vh, vd);
+            valid_out(b, r, ih & vm, id & vm, flg ? ((r.meta & REC_DEV) ? lo(2) : 0u) : x[2], x[3], vh, vd);
         };
         auto fast = [&](const hw* x, const hw* nh, const hw* nd, uint32_t fl, hw& vh, hw& vd) {
             const hw dev = fmask(fl, DD_DEV);
             const hw ih = ((flg ? 0u : x[0]) | (nh[0] & nh[1])) & vm, id = ((flg ? 0u : x[1]) | (nd[0] & nd[1])) & vm;
             const hw wr = flg ? (lo(2) & dev) : x[2];
             vh = ((ih & ~wr & dev) | ((ih | wr) & ~dev)) & vm;
-            vd = (((id | wr) & dev) | (id & ~wr & ~dev)) & vm;
+            vd = (((id | wr) & dev & ~(x[3] & fph)) | (id & ~wr & ~dev)) & vm;
         };
         if (!run_phase(S, vm64, ~0ull, pre, fast, comp)) return;
         if (helper) return;
@@ -1025,8 +1112,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     auto use_wr = [&](int b, const Rec& r, hw rr, hw ww, hw& uh, hw& ud, hw& sh, hw& sd) {
         const bool dev = r.meta & REC_DEV;
         if (r.meta & REC_EXIT) { uh = vec(c.lx_h); ud = vec(c.lx_d); sh = uh; sd = ud; return; }
-        uh = dev ? 0u : rr;
-        ud = dev ? rr : 0u;
+        uh = dev ? (rr & fph) : rr;
+        ud = dev ? (rr & ~fph) : 0u;
         if (r.meta & REC_CALL) {
             const int ci = r.ci;
             hw mw = sum(ci, SUM_MAYW_H) | sum(ci, SUM_MAYW_D);
@@ -1084,9 +1171,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             const hw dev = fmask(fl, DD_DEV), t0 = fmask(fl, DD_A0), t1 = fmask(fl, DD_A1);
             const hw mh = ((x[2] | nh[0]) & t0) | ((x[4] | nh[1]) & t1);
             const hw md = ((x[3] | nd[0]) & t0) | ((x[5] | nd[1]) & t1);
-            const hw st = x[0] | x[1];
-            vh = mh & ~(st & ~dev) & vm;
-            vd = md & ~(st & dev) & vm;
+            const hw sth = ((x[0] | x[1]) & ~dev) | (x[0] & fph & dev), std_ = ((x[0] & ~fph) | x[1]) & dev;
+            vh = mh & ~sth & vm;
+            vd = md & ~std_ & vm;
         };
         run_phase(S, 0ull, 0ull, pre, fast, comp);
         return;
@@ -1138,12 +1225,13 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         };
         // (per edge, (L & ~LE) | N' = L | BOTH whatever LE is; only the OR term skips loop entries)
         auto fast = [&](const hw* x, const hw* nh, const hw* nd, uint32_t fl, hw& vh, hw& vd) {
-            const hw dev = fmask(fl, DD_DEV), a0 = fmask(fl, DD_A0), st = x[0] | x[1];
+            const hw dev = fmask(fl, DD_DEV), a0 = fmask(fl, DD_A0);
+            const hw sth = ((x[0] | x[1]) & ~dev) | (x[0] & fph & dev), std_ = ((x[0] & ~fph) | x[1]) & dev;
             const hw l0h = x[2] | nh[0], l0d = x[3] | nd[0];
             if ((fl & (3u << DD_P0)) == (1u << DD_P0)) {
                 // one predecessor: its term is both the AND and (unless the edge enters a loop) the OR
-                vh = l0h & a0 & vm & ~(st & ~dev);
-                vd = l0d & a0 & vm & ~(st & dev);
+                vh = l0h & a0 & vm & ~sth;
+                vd = l0d & a0 & vm & ~std_;
                 return;
             }
             const hw p0 = fmask(fl, DD_P0), p1 = fmask(fl, DD_P1), a1 = fmask(fl, DD_A1);
@@ -1151,8 +1239,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             const hw allh = (l0h | x[4] | ~p0) & (l1h | x[7] | ~p1);
             const hw alld = (l0d | x[4] | ~p0) & (l1d | x[7] | ~p1);
             const hw anyh = (l0h & a0) | (l1h & a1), anyd = (l0d & a0) | (l1d & a1);
-            vh = allh & anyh & vm & ~(st & ~dev);
-            vd = alld & anyd & vm & ~(st & dev);
+            vh = allh & anyh & vm & ~sth;
+            vd = alld & anyd & vm & ~std_;
         };
         run_phase(S, 0ull, 0ull, pre, fast, comp);
         return;
@@ -1164,11 +1252,11 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     if constexpr (PH == PH_AVF) {
         const Rows S = rows_of(c.aveout_h, c.aveout_d, 2);
         const hw init = vm;
-        // x0/x1 = INS_ENTRY, x2 = W, x3..x6 = INS_EDGE_H/D of the two inline in-edges
+        // x0/x1 = INS_ENTRY, x2 = W, x3 = R, x4..x7 = INS_EDGE_H/D of the two inline in-edges
         auto pre = [&](u64 ob, u64 oe0, u64 oe1, const GAS u64** x) {
-            x[0] = rowu(c.ie_h, ob); x[1] = rowu(c.ie_d, ob); x[2] = rowu(c.W, ob);
-            x[3] = erowu(c.ig_h, oe0); x[4] = erowu(c.ig_d, oe0);
-            x[5] = erowu(c.ig_h, oe1); x[6] = erowu(c.ig_d, oe1);
+            x[0] = rowu(c.ie_h, ob); x[1] = rowu(c.ie_d, ob); x[2] = rowu(c.W, ob); x[3] = rowu(c.R, ob);
+            x[4] = erowu(c.ig_h, oe0); x[5] = erowu(c.ig_d, oe0);
+            x[6] = erowu(c.ig_h, oe1); x[7] = erowu(c.ig_d, oe1);
         };
         auto comp = [&](int b, const Rec& r, const hw* x, const hw* nh, const hw* nd, hw ph, hw pd, int sweep,
                         int g, hw& vh, hw& vd) {
@@ -1182,7 +1270,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                     nbr_f(r, j, p, e);
                     hw gh, gd, sh, sd;
                     if (j < 2) {
-                        gh = j ? x[5] : x[3]; gd = j ? x[6] : x[4]; sh = j ? nh[1] : nh[0]; sd = j ? nd[1] : nd[0];
+                        gh = j ? x[6] : x[4]; gd = j ? x[7] : x[5]; sh = j ? nh[1] : nh[0]; sd = j ? nd[1] : nd[0];
                     }
                     else {
                         gh = settle(erow(c.ig_h, e)); gd = settle(erow(c.ig_d, e));
@@ -1194,19 +1282,296 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 ih = x[0] | mh;
                 id = x[1] | md;
             }
-            valid_out(b, r, ih & vm, id & vm, x[2], vh, vd);
+            valid_out(b, r, ih & vm, id & vm, x[2], x[3], vh, vd);
         };
         auto fast = [&](const hw* x, const hw* nh, const hw* nd, uint32_t fl, hw& vh, hw& vd) {
             const hw dev = fmask(fl, DD_DEV), p0 = fmask(fl, DD_P0), p1 = fmask(fl, DD_P1);
-            const hw mh = (nh[0] | x[3] | ~p0) & (nh[1] | x[5] | ~p1);
-            const hw md = (nd[0] | x[4] | ~p0) & (nd[1] | x[6] | ~p1);
+            const hw mh = (nh[0] | x[4] | ~p0) & (nh[1] | x[6] | ~p1);
+            const hw md = (nd[0] | x[5] | ~p0) & (nd[1] | x[7] | ~p1);
             const hw ih = (x[0] | mh) & vm, id = (x[1] | md) & vm, wr = x[2];
             vh = ((ih & ~wr & dev) | ((ih | wr) & ~dev)) & vm;
-            vd = (((id | wr) & dev) | (id & ~wr & ~dev)) & vm;
+            vd = (((id | wr) & dev & ~(x[3] & fph)) | (id & ~wr & ~dev)) & vm;
         };
         run_phase(S, vm64, ~0ull, pre, fast, comp);
     }
 }
+
+// ---------------------------------------------------------------------------
+// Level schedule: the same phases with the blocks of a level in parallel.
+// The ingest kernel sorts a CFG's blocks into levels (a block's level is one
+// more than the highest level of its predecessors over edges other than
+// BACK, found by peeling the graph from ENTRY); no edge other than BACK joins
+// two blocks of one level, so a sweep visits the levels in order (backward:
+// in reverse) and all blocks of a level at once, each against its
+// neighbours' latest states: Gauss-Seidel across levels, Jacobi within one.
+// A level tile is one 32-bit column of a CFG (half of a 64-bit word: 32
+// variables) or its flag column; one workgroup holds the column's state of
+// every block in LDS (8 bytes per block: host and device halves), so a
+// level costs LDS reads of the neighbours, the blocks' inputs from global
+// memory and a barrier.  At the end of a phase the state goes to the same
+// rows the walk writes, so the passes and later phases read the same arrays
+// whatever schedule produced them.
+constexpr int LV_THREADS = 256;
+
+template <int PH>
+__device__ __forceinline__ void level_phase(const DevCfg& c, int hc, uint32_t* SH, uint32_t* SD)
+{
+    constexpr bool with_flags = PH == PH_NU || PH == PH_AVE;
+    constexpr bool BWD = PH == PH_NU;
+    const bool flg = hc < 0;
+    if (flg && !with_flags) return;
+    if ((PH == PH_MAYP || PH == PH_LATER) && (c.placement & 1)) return;
+    const int nb = c.nb, wd = c.wd, tid = threadIdx.x;
+    const int w = flg ? 0 : hc >> 1;
+    const bool hi = !flg && (hc & 1);
+    const u64 vm64 = (w == wd - 1 && (c.nv & 63)) ? ((1ull << (c.nv & 63)) - 1ull) : ~0ull;
+    const uint32_t vm = flg ? 3u : (uint32_t)(hi ? vm64 >> 32 : vm64);
+    typedef uint32_t hw;
+    const size_t wo = (size_t)w;
+    // the column's half of row b of a block vector / of edge e of an edge vector
+    auto in = [&](const u64* a, int b) -> hw {
+        return reinterpret_cast<const GAS uint32_t*>(G(a) + (size_t)b * wd + wo)[hi ? 1 : 0];
+    };
+    auto vec = [&](const u64* a) -> hw { return reinterpret_cast<const GAS uint32_t*>(G(a) + wo)[hi ? 1 : 0]; };
+    auto sum = [&](int ci, int r) -> hw { return in(c.sums, ci * SUM_ROWS + r); };
+    // the column's firstprivate variables (none for the flag column)
+    const hw fph = (flg || !wd) ? 0u : reinterpret_cast<const GAS uint32_t*>(G(c.fp) + wo)[hi ? 1 : 0];
+    const int32_t* REC = BWD ? c.rec_b : c.rec_f;
+    const int* LO = c.lorder;
+    const int* LF = c.loff;
+    const int nlev = G(c.info)[INFO_LEVELS];
+    GAS u64* FLG = G(c.flg);   // the flag columns of tile slot 0
+    // neighbour j of a record (j >= 2 from the CSR); edge id with LOOP_ENTRY in bit 31
+    auto nbr = [&](const Rec& r, int j, int& p, uint32_t& e) {
+        if (j == 0) { p = r.n0; e = r.e0; return; }
+        if (j == 1) { p = r.n1; e = r.e1; return; }
+        if (BWD) { p = G(c.succ_idx)[r.ovf + j]; e = 0; return; }
+        p = G(c.pred_idx)[r.ovf + j];
+        const int ee = G(c.pred_eid)[r.ovf + j];
+        e = (uint32_t)ee | (G(c.kind)[ee] == 2 ? 0x80000000u : 0u);
+    };
+    auto eid = [&](uint32_t e) -> int { return (int)(e & 0x7FFFFFFFu); };
+    // next use after a call block (OR over its successors; final when validity runs)
+    auto nu_after = [&](int b, hw& lh, hw& ld) {
+        lh = 0; ld = 0;
+        for (int e = G(c.succ_ptr)[b]; e < G(c.succ_ptr)[b + 1]; ++e) {
+            const int q = G(c.succ_idx)[e];
+            lh |= in(c.nu_h, q);
+            ld |= in(c.nu_d, q);
+        }
+    };
+    auto valid_out = [&](int b, const Rec& r, hw ih, hw id, hw wr, hw rr, hw& oh, hw& od) {
+        const bool dev = r.meta & REC_DEV;
+        hw ah = dev ? (ih & ~wr) : (ih | wr);
+        hw ad = dev ? ((id | wr) & ~(rr & fph)) : (id & ~wr);
+        if ((r.meta & REC_CALL) && !flg) {
+            hw lh, ld;
+            nu_after(b, lh, ld);
+            const int ci = r.ci;
+            ah = tsel(ah, lh, sum(ci, SUM_TH + 0), sum(ci, SUM_TH + 1), sum(ci, SUM_TH + 2), sum(ci, SUM_TH + 3));
+            ad = tsel(ad, ld, sum(ci, SUM_TD + 0), sum(ci, SUM_TD + 1), sum(ci, SUM_TD + 2), sum(ci, SUM_TD + 3));
+        }
+        oh = ah & vm;
+        od = ad & vm;
+    };
+    auto stop = [&](int b, const Rec& r, hw rr, hw ww, hw& sh, hw& sd) {
+        if (r.meta & REC_EXIT) { sh = vec(c.lx_h); sd = vec(c.lx_d); return; }
+        const bool dev = r.meta & REC_DEV;
+        hw uh = dev ? (rr & fph) : rr, ud = dev ? (rr & ~fph) : 0u;
+        if (r.meta & REC_CALL) {
+            const int ci = r.ci;
+            const hw mw = sum(ci, SUM_MAYW_H) | sum(ci, SUM_MAYW_D);
+            uh |= sum(ci, SUM_MAYR_H) | mw;
+            ud |= sum(ci, SUM_MAYR_D) | mw;
+        }
+        sh = uh | (dev ? 0u : ww);
+        sd = ud | (dev ? ww : 0u);
+    };
+    // the new state of block b from its neighbours' states in LDS
+    auto transfer = [&](int b, hw& vh, hw& vd) {
+        const Rec r = ldrec_v(REC, b);
+        const int cnt = (int)(r.meta & REC_COUNT);
+        const bool dev = r.meta & REC_DEV;
+        if constexpr (PH == PH_NU) {
+            if (r.meta & REC_EXIT) { vh = flg ? 1u : vec(c.lx_h); vd = flg ? 0u : vec(c.lx_d); return; }
+            hw oh = 0, od = 0;
+            for (int j = 0; j < cnt; ++j) {
+                int q; uint32_t e;
+                nbr(r, j, q, e);
+                oh |= SH[q];
+                od |= SD[q];
+            }
+            const hw rr = flg ? 2u : in(c.R, b), ww = flg ? (dev ? 2u : 0u) : in(c.W, b);
+            if ((r.meta & REC_CALL) && !flg) {
+                oh = sum(r.ci, SUM_NU0_H) | (sum(r.ci, SUM_NU1_H) & oh);
+                od = sum(r.ci, SUM_NU0_D) | (sum(r.ci, SUM_NU1_D) & od);
+            }
+            vh = (dev ? (rr & fph) : rr) | (~ww & oh);
+            vd = (dev ? (rr & ~fph) : 0u) | (~ww & od);
+        } else if constexpr (PH == PH_AVE) {
+            hw ih, id;
+            if (r.meta & REC_ENTRY) { ih = flg ? 2u : vec(c.ev_h); id = flg ? 0u : vec(c.ev_d); }
+            else {
+                hw mh = ~0u, md = ~0u;
+                for (int j = 0; j < cnt; ++j) {
+                    int p; uint32_t e;
+                    nbr(r, j, p, e);
+                    mh &= SH[p];
+                    md &= SD[p];
+                }
+                ih = (flg ? 0u : in(c.nu_h, b)) | mh;
+                id = (flg ? 0u : in(c.nu_d, b)) | md;
+            }
+            valid_out(b, r, ih & vm, id & vm, flg ? (dev ? 2u : 0u) : in(c.W, b), flg ? 0u : in(c.R, b), vh, vd);
+        } else if constexpr (PH == PH_MAYP) {
+            if (r.meta & REC_ENTRY) { vh = 0; vd = 0; return; }
+            hw mh = 0, md = 0;
+            for (int j = 0; j < cnt; ++j) {
+                int p; uint32_t e;
+                nbr(r, j, p, e);
+                if (e & 0x80000000u) continue;   // loop entry: nothing stays pending
+                mh |= in(c.eag_h, eid(e)) | SH[p];
+                md |= in(c.eag_d, eid(e)) | SD[p];
+            }
+            hw sth, std_;
+            stop(b, r, in(c.R, b), in(c.W, b), sth, std_);
+            vh = mh & ~sth & vm;
+            vd = md & ~std_ & vm;
+        } else if constexpr (PH == PH_LATER) {
+            if (r.meta & REC_ENTRY) { vh = 0; vd = 0; return; }
+            hw allh = ~0u, alld = ~0u, anyh = 0, anyd = 0;
+            for (int j = 0; j < cnt; ++j) {
+                int p; uint32_t e;
+                nbr(r, j, p, e);
+                const hw le = (e & 0x80000000u) ? ~0u : 0u;
+                const hw lh = in(c.eag_h, eid(e)) | SH[p], ld = in(c.eag_d, eid(e)) | SD[p];
+                const hw bo = in(c.both, eid(e));
+                allh &= lh | bo;
+                alld &= ld | bo;
+                anyh |= lh & ~le;
+                anyd |= ld & ~le;
+            }
+            hw sth, std_;
+            stop(b, r, in(c.R, b), in(c.W, b), sth, std_);
+            vh = allh & anyh & vm & ~sth;
+            vd = alld & anyd & vm & ~std_;
+        } else {   // PH_AVF
+            hw ih, id;
+            if (r.meta & REC_ENTRY) { ih = vec(c.ev_h); id = vec(c.ev_d); }
+            else {
+                hw mh = ~0u, md = ~0u;
+                for (int j = 0; j < cnt; ++j) {
+                    int p; uint32_t e;
+                    nbr(r, j, p, e);
+                    mh &= SH[p] | in(c.ig_h, eid(e));
+                    md &= SD[p] | in(c.ig_d, eid(e));
+                }
+                ih = in(c.ie_h, b) | mh;
+                id = in(c.ie_d, b) | md;
+            }
+            valid_out(b, r, ih & vm, id & vm, in(c.W, b), in(c.R, b), vh, vd);
+        }
+    };
+    const hw init = (PH == PH_AVE || PH == PH_AVF) ? vm : 0u;
+    for (int b = tid; b < nb; b += LV_THREADS) { SH[b] = init; SD[b] = init; }
+    __syncthreads();
+    const int cap = c.sweep_cap > 0 ? c.sweep_cap : 2 * nb + 2;
+    int sweeps = 0;
+    bool good = true;
+    for (;;) {
+        int chg = 0;
+        for (int li = 0; li < nlev; ++li) {
+            const int lv = BWD ? nlev - 1 - li : li;
+            const int a = LF[lv], z = LF[lv + 1];
+            for (int k = a + tid; k < z; k += LV_THREADS) {
+                const int b = LO[k];
+                hw vh, vd;
+                transfer(b, vh, vd);
+                if (vh != SH[b] || vd != SD[b]) {
+                    SH[b] = vh;
+                    SD[b] = vd;
+                    chg = 1;
+                }
+            }
+            __syncthreads();
+        }
+        ++sweeps;
+        if (!__syncthreads_or(chg)) break;
+        if (sweeps >= cap) {
+            if (tid == 0) set_status(c.info, OMPD_E_NOCONVERGE_);
+            good = false;
+            break;
+        }
+    }
+    if (tid == 0) atomicMax(&c.info[INFO_SWEEPS + PH], sweeps);
+    // the state to the rows of the phase (flag column: tile slot 0's columns)
+    if (flg) {
+        const int fl = PH == PH_NU ? 0 : 2;
+        for (int b = tid; b < nb; b += LV_THREADS) {
+            FLG[(size_t)fl * nb + b] = SH[b];
+            FLG[(size_t)(fl + 1) * nb + b] = SD[b];
+        }
+    } else {
+        u64* h = PH == PH_NU ? c.nu_h : PH == PH_MAYP ? c.mayp_h : PH == PH_LATER ? c.later_h : c.aveout_h;
+        u64* d = PH == PH_NU ? c.nu_d : PH == PH_MAYP ? c.mayp_d : PH == PH_LATER ? c.later_d : c.aveout_d;
+        for (int b = tid; b < nb; b += LV_THREADS) {
+            reinterpret_cast<GAS uint32_t*>(G(h) + (size_t)b * wd + wo)[hi ? 1 : 0] = SH[b];
+            reinterpret_cast<GAS uint32_t*>(G(d) + (size_t)b * wd + wo)[hi ? 1 : 0] = SD[b];
+        }
+    }
+    if constexpr (PH == PH_AVE) {
+        if (!flg || !good) return;
+        // reachability: every block reached from ENTRY and reaching EXIT; the label facts
+        int bad = 0;
+        for (int b = tid; b < nb; b += LV_THREADS) {
+            const u64 fnu = FLG[b], fnud = FLG[(size_t)nb + b];
+            const hw fave = SH[b];
+            if (!(fnu & 1) || (fave & 1)) bad = 1;
+            if (c.after_dev) G(c.after_dev)[b] = (uint8_t)(((fave >> 1) & 1) ^ 1);
+            if (c.before_dev) G(c.before_dev)[b] = (uint8_t)((fnud >> 1) & 1);
+        }
+        if (__syncthreads_or(bad) && tid == 0) set_status(c.info, OMPD_E_INVAL_);
+    }
+}
+
+// One persistent kernel per phase over the level tiles (one workgroup of LV_THREADS per tile,
+// the column's state in dynamic LDS).  A tile (cfg, s0, nw, fslot): s0 = the 32-bit column
+// (word s0 / 2, its high half when s0 is odd) or -1 for the flag column.
+template <int PH>
+__device__ __forceinline__ void level_kernel(const DevCfg* __restrict__ cfgs, const Tile* __restrict__ tiles,
+                                             int n_tiles, int32_t* __restrict__ counter)
+{
+    extern __shared__ __align__(16) u64 lds[];
+    __shared__ int s_tile, s_skip;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(&counter[16 + PH], 1);
+        __syncthreads();
+        const int t = s_tile;
+        __syncthreads();
+        if (t >= n_tiles) break;
+        const Tile tl = tiles[t];
+        const DevCfg c = cfgs[tl.cfg];
+        if (threadIdx.x == 0) s_skip = G(c.info)[INFO_STATUS] != 0;
+        __syncthreads();
+        if (!s_skip) {
+            uint32_t* SH = reinterpret_cast<uint32_t*>(lds);
+            level_phase<PH>(c, tl.s0, SH, SH + c.nb);
+        }
+        __syncthreads();
+    }
+}
+#define OMPD_LEVEL_KERNEL(name, ph)                                                                          \
+    extern "C" __global__ void __launch_bounds__(LV_THREADS) name(const DevCfg* __restrict__ cfgs,          \
+                                                                   const Tile* __restrict__ tiles,           \
+                                                                   int n_tiles, int32_t* __restrict__ counter) \
+    {                                                                                                        \
+        level_kernel<ph>(cfgs, tiles, n_tiles, counter);                                                     \
+    }
+OMPD_LEVEL_KERNEL(ompd_k_lv_nu, PH_NU)
+OMPD_LEVEL_KERNEL(ompd_k_lv_ave, PH_AVE)
+OMPD_LEVEL_KERNEL(ompd_k_lv_mayp, PH_MAYP)
+OMPD_LEVEL_KERNEL(ompd_k_lv_later, PH_LATER)
+OMPD_LEVEL_KERNEL(ompd_k_lv_avf, PH_AVF)
 
 // ---------------------------------------------------------------------------
 // Edge-parallel passes (no iteration): lanes over words, one wavefront per
@@ -1314,9 +1679,9 @@ __device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int f
             u64 uh, ud;
             if (q == c.exit) { uh = G(c.lx_h)[wo]; ud = G(c.lx_d)[wo]; }
             else {
-                const u64 rr = row(c.R, q);
-                uh = dev ? 0ull : rr;
-                ud = dev ? rr : 0ull;
+                const u64 rr = row(c.R, q), fp = G(c.fp)[wo];
+                uh = dev ? (rr & fp) : rr;
+                ud = dev ? (rr & ~fp) : 0ull;
                 const int ci = c.call ? c.call[q] : -1;
                 if (ci >= 0) {
                     const GAS u64* sm = G(c.sums) + (size_t)ci * SUM_ROWS * wd + wo;
@@ -1337,7 +1702,8 @@ __device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int f
         }
     }
     if constexpr (PASS == PASS_AVF) {
-        u64 to = 0, fr = 0, dv = 0;
+        u64 to = 0, fr = 0, dv = 0, fr_read = 0;
+        const u64 fp = G(c.fp)[wo];
         for (int q = b0; q < b1; ++q) {
             const int a = PP[q], z = PP[q + 1];
             const u64 ieh = row(c.ie_h, q), ied = row(c.ie_d, q);
@@ -1361,7 +1727,12 @@ __device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int f
                 to |= ied & none_after;
                 fr |= ieh & not_before;
             }
-            if (c.space[q] && q != c.exit) dv |= row(c.R, q) | row(c.W, q);
+            if (c.space[q] && q != c.exit) {
+                const u64 rr = row(c.R, q);
+                dv |= (rr & ~fp) | row(c.W, q);
+                fr_read |= rr & fp;
+                if (c.fpc) put(c.fpc, q, rr & fp);
+            } else if (c.fpc) put(c.fpc, q, 0);
             if (c.avf_h) { put(c.avf_h, q, ih & vm); put(c.avf_d, q, id & vm); }
         }
         if (c.var_kind) {
@@ -1369,6 +1740,7 @@ __device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int f
             if (to) atomicOr((unsigned long long*)&acc[wo], (unsigned long long)to);
             if (fr) atomicOr((unsigned long long*)&acc[wd + wo], (unsigned long long)fr);
             if (dv) atomicOr((unsigned long long*)&acc[2 * wd + wo], (unsigned long long)dv);
+            if (fr_read) atomicOr((unsigned long long*)&acc[3 * wd + wo], (unsigned long long)fr_read);
         }
     }
 }
@@ -1385,8 +1757,12 @@ __device__ __forceinline__ void tile_phase(const DevCfg& c, const Tile& tl, u64*
         ctl->in_ready = 0;
     }
     __syncthreads();
-    // lanes past 2 LANES hold no word and stay out
-    if (!__builtin_amdgcn_readfirstlane(ctl->skip) && (threadIdx.x & 63) < 2 * LANES)
+    if (__builtin_amdgcn_readfirstlane(ctl->skip)) {
+        __syncthreads();
+        return;
+    }
+    // a CFG on the level schedule is solved by the level kernels; lanes past 2 LANES hold no word
+    if (c.sched != SCHED_LEVEL && (threadIdx.x & 63) < 2 * LANES)
         solve_phase<PH>(c, tl.s0, tl.nw, tl.fslot, lds, ring_slots);
     __syncthreads();
 }
@@ -1468,8 +1844,10 @@ __device__ __forceinline__ void tile_varkind(const DevCfg& c, const Tile& tl, in
         const int v = w * 64 + i;
         if (v >= c.nv) break;
         const u64 t = ld_fresh(acc + w), f = ld_fresh(acc + c.wd + w), d = ld_fresh(acc + 2 * c.wd + w);
+        const u64 fr = ld_fresh(acc + 3 * c.wd + w);
         const uint32_t t1 = (uint32_t)((t >> i) & 1), f1 = (uint32_t)((f >> i) & 1), d1 = (uint32_t)((d >> i) & 1);
-        G(c.var_kind)[v] = (uint8_t)(t1 | (f1 << 1) | ((d1 && !t1 && !f1) ? 4u : 0u));
+        const uint32_t p1 = (uint32_t)((fr >> i) & 1);
+        G(c.var_kind)[v] = (uint8_t)(t1 | (f1 << 1) | ((d1 && !t1 && !f1) ? 4u : 0u) | (p1 << 3));
     }
 }
 

@@ -569,8 +569,8 @@ int run_batch(Prog& G, std::vector<ompd_cfg>& cfgs, std::vector<ompd_result>& re
     PlanConfig pc;
     pc.use_graph = false;   // one-shot plans: capturing a graph would not be replayed
     ompd_plan* plan = nullptr;
-    int rc = ompd_plan_build(G.ctx, cfgs.data(), res.data(), (int32_t)cfgs.size(),
-                             flags | OMPD_F_DEVICE_PTRS | (G.flags & 0xFFFF0000u), pc, &plan);
+    int rc = ompd_plan_build(G.ctx, cfgs.data(), res.data(), (int32_t)cfgs.size(), flags | OMPD_F_DEVICE_PTRS | G.flags,
+                             pc, &plan);
     if (rc) return rc;
     rc = ompd_plan_run_locked(plan, G.s);
     if (rc == OMPD_OK) rc = ompd_plan_collect(plan, nullptr);
@@ -1132,7 +1132,7 @@ extern "C" int ompd_analyze_program(ompd_ctx* ctx, const ompd_program* prog, omp
     Prog G;
     G.ctx = ctx;
     G.P = prog;
-    G.flags = flags & 0xFFFF0000u;
+    G.flags = flags & (0xFFFF0000u | OMPD_F_SCHED_LEVEL | OMPD_F_SCHED_WALK);
     int rc = check_program(prog, G.st);
     if (rc) return rc;
     CK(hipSetDevice(ctx->device));
@@ -1231,6 +1231,7 @@ extern "C" int ompd_analyze_program(ompd_ctx* ctx, const ompd_program* prog, omp
         cp(r.ins_edge_to_host, G.o_ig_h[x], 8 * ev); cp(r.ins_edge_to_dev, G.o_ig_d[x], 8 * ev);
         cp(r.var_kind, G.o_vk[x], (size_t)prog->procs[p].n_vars);
         cp(r.after_dev, G.o_ad[x], nb); cp(r.before_dev, G.o_bd[x], nb);
+        if (r.fp_clause && bv) memset(r.fp_clause, 0, 8 * bv);   // procedures' scalar marks are not used
         memcpy(r.sweeps, &G.sweeps[(size_t)x * 6], sizeof r.sweeps);
     };
     const size_t STAGE = (size_t)64 << 20;

@@ -28,6 +28,15 @@ extern "C" __global__ void ompd_k_post_later(const DevCfg*, const Tile*, const E
 extern "C" __global__ void ompd_k_post_avf(const DevCfg*, const Tile*, const EdgeItem*, int, int32_t*);
 extern "C" __global__ void ompd_k_varkind(const DevCfg*, const Tile*, int, int32_t*);
 extern "C" __global__ void ompd_k_solve(const DevCfg*, const Tile*, int, int32_t*, int);
+extern "C" __global__ void ompd_k_lv_nu(const DevCfg*, const Tile*, int, int32_t*);
+extern "C" __global__ void ompd_k_lv_ave(const DevCfg*, const Tile*, int, int32_t*);
+extern "C" __global__ void ompd_k_lv_mayp(const DevCfg*, const Tile*, int, int32_t*);
+extern "C" __global__ void ompd_k_lv_later(const DevCfg*, const Tile*, int, int32_t*);
+extern "C" __global__ void ompd_k_lv_avf(const DevCfg*, const Tile*, int, int32_t*);
+static const void* const k_levels[5] = {(const void*)ompd_k_lv_nu, (const void*)ompd_k_lv_ave,
+                                        (const void*)ompd_k_lv_mayp, (const void*)ompd_k_lv_later,
+                                        (const void*)ompd_k_lv_avf};
+constexpr int LEVEL_THREADS = 256;
 static const void* const k_phases[5] = {(const void*)ompd_k_nu, (const void*)ompd_k_ave, (const void*)ompd_k_mayp,
                                         (const void*)ompd_k_later, (const void*)ompd_k_avf};
 // threads of a phase workgroup: the compute and the helper wavefront
@@ -101,7 +110,8 @@ extern "C" int ompd_ctx_create(ompd_ctx** out, int device_ordinal, uint64_t budg
     // dynamic LDS limit per kernel = device limit minus the kernel's static LDS
     int dyn = (int)lds_max;
     for (const void* k : {k_phases[0], k_phases[1], k_phases[2], k_phases[3], k_phases[4], (const void*)ompd_k_prep,
-                          (const void*)ompd_k_solve}) {
+                          (const void*)ompd_k_solve, k_levels[0], k_levels[1], k_levels[2], k_levels[3],
+                          k_levels[4]}) {
         hipFuncAttributes fa{};
         int st = 0;
         if (hipFuncGetAttributes(&fa, k) == hipSuccess) st = (int)fa.sharedSizeBytes;
@@ -206,7 +216,8 @@ size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o)
     o.ie = (r.ins_entry_to_host && r.ins_entry_to_dev) ? SIZE_MAX : take(2 * bv);
     o.ig = (r.ins_edge_to_host && r.ins_edge_to_dev) ? SIZE_MAX : take(2 * ev);
     o.avf = (!r.avf_host == !r.avf_dev) ? SIZE_MAX : take(2 * bv);
-    o.vk = r.var_kind ? take(3 * wd * 8) : SIZE_MAX;
+    o.vk = r.var_kind ? take(4 * wd * 8) : SIZE_MAX;
+    o.fp = take(wd * 8 + 8);
     o.bnd = take(4 * wd * 8);
     o.pp = take(4 * ((size_t)g.n_blocks + 1));
     o.pi = take(4 * (size_t)std::max(g.n_edges, 1));
@@ -216,8 +227,29 @@ size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o)
     o.recb = take(32 * (size_t)g.n_blocks);
     o.stf = take(32 * (size_t)g.n_blocks);
     o.stb = take(32 * (size_t)g.n_blocks);
+    o.lorder = take(4 * (size_t)g.n_blocks);
+    o.loff = take(4 * ((size_t)g.n_blocks + 1));
     o.info = take(4 * INFO_WORDS);
     return total;
+}
+
+// The schedule of a CFG when the caller names none: the level schedule for
+// large CFGs, whose levels hold enough blocks to keep a workgroup busy.
+int ompd_default_sched(int n_blocks, int n_vars)
+{
+    (void)n_vars;
+    return n_blocks >= OMPD_LEVEL_MIN_BLOCKS ? SCHED_LEVEL : SCHED_WALK;
+}
+
+void ompd_settle_sched(DevCfg* h, int n, int n_cu)
+{
+    auto by_rule = [&](const DevCfg& d) { return d.sched == SCHED_LEVEL && d.sched_rule; };
+    int64_t tiles = 0;
+    for (int i = 0; i < n; ++i)
+        if (by_rule(h[i])) tiles += 2 * (int64_t)h[i].wd + 1;
+    if (tiles <= (int64_t)OMPD_LEVEL_ROUNDS * n_cu) return;
+    for (int i = 0; i < n; ++i)
+        if (by_rule(h[i])) h[i].sched = SCHED_WALK;
 }
 
 // Fill the kernels' descriptor of one CFG whose scratch starts at `base`.
@@ -234,6 +266,11 @@ void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const
     d.n_sums = g.call_summary ? g.n_summaries : 0;
     d.placement = ((flags & OMPD_F_PLACEMENT_EAGER) ? 1 : 0) | ((flags & OMPD_F_SUMMARY) ? 2 : 0);
     d.sweep_cap = (int)((flags >> 16) & 0xFFFFu);
+    d.sched = (flags & OMPD_F_SCHED_LEVEL) ? SCHED_LEVEL
+            : (flags & OMPD_F_SCHED_WALK) ? SCHED_WALK
+            : ompd_default_sched(g.n_blocks, g.n_vars);
+    d.sched_rule = !(flags & (OMPD_F_SCHED_LEVEL | OMPD_F_SCHED_WALK));
+    if (g.n_blocks > OMPD_LEVEL_MAX_BLOCKS) d.sched = SCHED_WALK;
     d.succ_ptr = g.succ_ptr; d.succ_idx = g.succ_idx; d.kind = g.edge_kind; d.space = g.space;
     d.R = g.read_bits; d.W = g.write_bits;
     uint64_t* bnd = bnd_dev ? bnd_dev : (uint64_t*)(base + o.bnd);
@@ -242,6 +279,9 @@ void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const
     d.lx_h = g.exit_live_host ? g.exit_live_host : bnd + 2 * wd;
     d.lx_d = g.exit_live_dev ? g.exit_live_dev : bnd + 3 * wd;
     d.call = g.call_summary; d.sums = g.summaries;
+    d.scalar = g.scalar;
+    d.fp = (uint64_t*)(base + o.fp);
+    d.fpc = r.fp_clause;
     size_t bvw = (size_t)g.n_blocks * wd, evw = (size_t)g.n_edges * wd;
     auto at = [&](size_t off) { return off == SIZE_MAX ? (uint64_t*)nullptr : (uint64_t*)(base + off); };
     uint64_t *nu = at(o.nu), *ave = at(o.ave), *ie = at(o.ie), *ig = at(o.ig), *avf = at(o.avf);
@@ -270,6 +310,7 @@ void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const
     d.pred_eid = (int32_t*)(base + o.pe); d.tmp = (int32_t*)(base + o.tmp);
     d.rec_f = (int32_t*)(base + o.recf); d.rec_b = (int32_t*)(base + o.recb);
     d.step_f = (int32_t*)(base + o.stf); d.step_b = (int32_t*)(base + o.stb);
+    d.lorder = (int32_t*)(base + o.lorder); d.loff = (int32_t*)(base + o.loff);
     d.info = (int32_t*)(base + o.info);
     if (bnd_host && wd > 0) {
         uint64_t last = (g.n_vars & 63) ? ((1ull << (g.n_vars & 63)) - 1) : ~0ull;
@@ -292,10 +333,25 @@ int ompd_make_shape(ompd_ctx* ctx, const std::vector<DevCfg>& cfgs, const PlanCo
     std::vector<Tile>& tiles = sh.tiles;
     tiles.clear();
     sh.items.clear();
-    for (int i = 0; i < (int)cfgs.size(); ++i) make_tiles(i, cfgs[i].nv, tiles);
+    auto in_plan = [&](int i) { return pc.only_bucket < 0 || ompd_sched_bucket(cfgs[i].nb) == pc.only_bucket; };
+    for (int i = 0; i < (int)cfgs.size(); ++i)
+        if (in_plan(i)) make_tiles(i, cfgs[i].nv, tiles);
     // a tile's work ~ its blocks times the sweeps, which grow with the CFG: longest first
     std::stable_sort(tiles.begin(), tiles.end(),
                      [&](const Tile& a, const Tile& b) { return cfgs[a.cfg].nb > cfgs[b.cfg].nb; });
+    // level tiles (after the walk tiles): each 32-bit column of a CFG on the level schedule, and
+    // its flag column (s0 = -1)
+    std::vector<Tile> lt;
+    int lv_nb = 0;
+    for (int i = 0; i < (int)cfgs.size(); ++i) {
+        if (cfgs[i].sched != SCHED_LEVEL || !in_plan(i)) continue;
+        lv_nb = std::max(lv_nb, cfgs[i].nb);
+        lt.push_back(Tile{i, -1, 0, 0});
+        for (int hc = 0; hc < 2 * cfgs[i].wd; ++hc) lt.push_back(Tile{i, hc, 1, 0});
+    }
+    std::stable_sort(lt.begin(), lt.end(), [&](const Tile& a, const Tile& b) { return cfgs[a.cfg].nb > cfgs[b.cfg].nb; });
+    sh.dims.n_level = (int)lt.size();
+    tiles.insert(tiles.end(), lt.begin(), lt.end());
     // pass items: runs of up to PASS_WORDS words (the passes need no LDS, so a full wavefront of
     // words each), 64-block chunks, longest CFGs first
     {
@@ -304,7 +360,7 @@ int ompd_make_shape(ompd_ctx* ctx, const std::vector<DevCfg>& cfgs, const PlanCo
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cfgs[a].nb > cfgs[b].nb; });
         for (int i : order) {
             const int wd = cfgs[i].wd;
-            if (wd <= 0) continue;
+            if (wd <= 0 || !in_plan(i)) continue;
             const int runs = (wd + PASS_WORDS - 1) / PASS_WORDS;
             for (int r = 0; r < runs; ++r) {
                 const int s0 = (int)((int64_t)wd * r / runs), s1 = (int)((int64_t)wd * (r + 1) / runs);
@@ -339,6 +395,15 @@ int ompd_make_shape(ompd_ctx* ctx, const std::vector<DevCfg>& cfgs, const PlanCo
         if (pc.wg_per_cu > 0) n = std::min(n, pc.wg_per_cu);
         dm.grid_tile = std::max(1, std::min((int)tiles.size(), n * ctx->n_cu));
     }
+    dm.lds_level = align256(8 * (size_t)lv_nb);
+    if (dm.n_level) {
+        if (dm.lds_level > (size_t)ctx->lds_max)
+            return ompd_fail(OMPD_E_INVAL, "a CFG on the level schedule has more blocks than LDS holds");
+        int n = 0;
+        CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_levels[PH_LATER], LEVEL_THREADS, dm.lds_level));
+        dm.grid_level = std::max(1, std::min(dm.n_level, std::max(1, n) * ctx->n_cu));
+    }
+    if (dm.n_level) dm.split = true;   // the per-tile kernel does not run level tiles
     int pe = 1;
     CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pe, (const void*)ompd_k_post_ave, 64, 0));
     dm.grid_edge = std::max(1, std::min((int)std::max<size_t>(sh.items.size(), tiles.size()), std::max(1, pe) * ctx->n_cu));
@@ -420,6 +485,24 @@ int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32
 int ompd_plan_retile(ompd_plan* p, const PlanConfig& pc)
 {
     ompd_ctx* ctx = p->ctx;
+    // the schedule of each CFG the plan's flags leave open: the bucket's choice, else the rule
+    if (!(p->flags & (OMPD_F_SCHED_LEVEL | OMPD_F_SCHED_WALK))) {
+        bool changed = false;
+        for (int i = 0; i < p->n; ++i) {
+            DevCfg& d = p->h_cfgs[i];
+            const int want = pc.bucket_sched[ompd_sched_bucket(d.nb)];
+            int sc = want < 0 ? ompd_default_sched(d.nb, d.nv) : want;
+            if (d.nb > OMPD_LEVEL_MAX_BLOCKS) sc = SCHED_WALK;
+            d.sched_rule = want < 0;
+            if (d.sched != sc) { d.sched = sc; changed = true; }
+        }
+        std::vector<int> before(p->n);
+        for (int i = 0; i < p->n; ++i) before[i] = p->h_cfgs[i].sched;
+        ompd_settle_sched(p->h_cfgs.data(), p->n, ctx->n_cu);
+        for (int i = 0; i < p->n; ++i) changed |= before[i] != p->h_cfgs[i].sched;
+        if (changed && p->d_cfgs)
+            CK(hipMemcpy(p->d_cfgs, p->h_cfgs.data(), sizeof(DevCfg) * p->n, hipMemcpyHostToDevice));
+    }
     Shape sh;
     int rc = ompd_make_shape(ctx, p->h_cfgs, pc, sh);
     if (rc) return rc;
@@ -456,6 +539,10 @@ int ompd_launch_solve(const DevCfg* d_cfgs, const Tile* d_tiles, int n_tiles, co
                       int32_t* d_counter, const LaunchDims& dm, hipStream_t s, hipEvent_t* after)
 {
     if (n_tiles <= 0) return OMPD_OK;
+    // the walk tiles, then the level tiles
+    const int n_level = dm.n_level;
+    n_tiles -= n_level;
+    const Tile* d_ltiles = d_tiles + n_tiles;
     const int rs = dm.ring_slots, grid_edge = dm.grid_edge;
     int k = 0;
     auto mark = [&]() { if (after) (void)hipEventRecord(after[k], s); ++k; };
@@ -472,8 +559,14 @@ int ompd_launch_solve(const DevCfg* d_cfgs, const Tile* d_tiles, int n_tiles, co
     }
     int ph = 0;
     auto phase = [&](const void* fn) {
-        void* args[] = {(void*)&d_cfgs, (void*)&d_tiles, (void*)&n_tiles, (void*)&d_counter, (void*)&rs};
-        (void)hipLaunchKernel(fn, dim3(dm.grid[ph]), dim3(PHASE_THREADS), args, dm.lds[ph], s);
+        if (n_tiles > 0) {
+            void* args[] = {(void*)&d_cfgs, (void*)&d_tiles, (void*)&n_tiles, (void*)&d_counter, (void*)&rs};
+            (void)hipLaunchKernel(fn, dim3(dm.grid[ph]), dim3(PHASE_THREADS), args, dm.lds[ph], s);
+        }
+        if (n_level > 0) {
+            void* args[] = {(void*)&d_cfgs, (void*)&d_ltiles, (void*)&n_level, (void*)&d_counter};
+            (void)hipLaunchKernel(k_levels[ph], dim3(dm.grid_level), dim3(LEVEL_THREADS), args, dm.lds_level, s);
+        }
         ++ph;
         mark();
     };
@@ -723,16 +816,21 @@ extern "C" int ompd_plan_describe(ompd_plan* p, char* buf, int32_t len)
 {
     if (!p || !buf || len <= 0) return ompd_fail(OMPD_E_INVAL, "bad arguments");
     long lanes = 0;
-    for (const Tile& t : p->h_tiles) lanes += t.nw;
+    for (size_t i = 0; i + p->dims.n_level < p->h_tiles.size(); ++i) lanes += p->h_tiles[i].nw;
+    int level_cfgs = 0;
+    for (const DevCfg& d : p->h_cfgs) level_cfgs += d.sched == SCHED_LEVEL;
     snprintf(buf, len,
              "{\"cfgs\": %d, \"tiles\": %d, \"words\": %ld, \"ring_slots\": %d, \"split\": %d, \"grid_tile\": %d, "
              "\"grid_phases\": [%d, %d, %d, %d, %d], "
              "\"lds_bytes\": %zu, \"wg_per_cu\": %d, \"graph\": %d, \"graph_captured\": %d, "
-             "\"scratch_bytes\": %zu}",
-             p->n, p->n_tiles, lanes, p->dims.ring_slots, (int)p->dims.split, p->dims.grid_tile, p->dims.grid[0],
-             p->dims.grid[1], p->dims.grid[2],
+             "\"scratch_bytes\": %zu, \"bucket_sched\": [%d, %d, %d, %d, %d], \"level_cfgs\": %d, "
+             "\"level_tiles\": %d, \"lds_level\": %zu}",
+             p->n, p->n_tiles - p->dims.n_level, lanes, p->dims.ring_slots, (int)p->dims.split, p->dims.grid_tile,
+             p->dims.grid[0], p->dims.grid[1], p->dims.grid[2],
              p->dims.grid[3], p->dims.grid[4], p->cfg.lds_bytes, p->cfg.wg_per_cu,
-             p->cfg.use_graph ? 1 : 0, p->gx_solve ? 1 : 0, p->scratch_bytes);
+             p->cfg.use_graph ? 1 : 0, p->gx_solve ? 1 : 0, p->scratch_bytes, p->cfg.bucket_sched[0],
+             p->cfg.bucket_sched[1], p->cfg.bucket_sched[2], p->cfg.bucket_sched[3], p->cfg.bucket_sched[4],
+             level_cfgs, p->dims.n_level, p->dims.lds_level);
     return OMPD_OK;
 }
 
@@ -757,45 +855,87 @@ extern "C" void ompd_plan_destroy(ompd_plan* p)
 // ---------------------------------------------------------------------------
 // autotuner
 // ---------------------------------------------------------------------------
+// Time the plan under configuration c: `trials` runs after one that warms up the graph.
+static int time_config(ompd_plan* p, const PlanConfig& c, hipStream_t s, int trials, float& avg)
+{
+    int rc = ompd_plan_retile(p, c);
+    if (rc) return rc;
+    float tot = 0;
+    for (int t = 0; t < trials + 1; ++t) {
+        rc = ompd_plan_run_locked(p, s);
+        if (rc) return rc;
+        CK(hipEventSynchronize(p->ev2));
+        float ms = 0;
+        CK(hipEventElapsedTime(&ms, p->ev0, p->ev2));
+        if (t > 0) tot += ms;
+    }
+    avg = tot / trials;
+    return OMPD_OK;
+}
+
 extern "C" int ompd_plan_autotune(ompd_plan* p, void* stream, int32_t trials, float* best_ms)
 {
     if (!p) return ompd_fail(OMPD_E_INVAL, "plan is NULL");
     std::lock_guard<std::mutex> lk(p->ctx->mu);
     hipStream_t s = (hipStream_t)stream;
     trials = std::max(1, trials);
-    std::vector<PlanConfig> cands;
-    for (size_t lds : {(size_t)16 * STATE_BYTES, (size_t)32 * STATE_BYTES, (size_t)64 * STATE_BYTES}) {
-        for (int wpc : {0, 4}) {
-            PlanConfig c = p->cfg;
-            c.lds_bytes = lds;
-            c.wg_per_cu = wpc;
-            cands.push_back(c);
+    PlanConfig base = p->cfg;
+    base.only_bucket = -1;
+    // 1. the schedule of each size bucket, its CFGs timed alone under both schedules
+    if (!(p->flags & (OMPD_F_SCHED_LEVEL | OMPD_F_SCHED_WALK))) {
+        int count[OMPD_SCHED_BUCKETS] = {0}, small[OMPD_SCHED_BUCKETS] = {0};
+        for (const DevCfg& d : p->h_cfgs) {
+            const int b = ompd_sched_bucket(d.nb);
+            ++count[b];
+            small[b] += d.nb <= OMPD_LEVEL_MAX_BLOCKS;
+        }
+        for (int b = 0; b < OMPD_SCHED_BUCKETS; ++b) {
+            if (!count[b]) continue;
+            float best = 1e30f;
+            int pick = SCHED_WALK;
+            for (int sc : {(int)SCHED_WALK, (int)SCHED_LEVEL}) {
+                if (sc == SCHED_LEVEL && small[b] == 0) continue;
+                PlanConfig c = base;
+                c.bucket_sched[b] = sc;
+                c.only_bucket = b;
+                float ms = 0;
+                if (time_config(p, c, s, trials, ms) != OMPD_OK) continue;
+                if (ms < best) { best = ms; pick = sc; }
+            }
+            base.bucket_sched[b] = pick;
         }
     }
-    PlanConfig best = p->cfg;
+    // 2. the launch configuration of the whole plan with those schedules
+    PlanConfig best = base;
     float best_t = 1e30f;
-    for (const PlanConfig& c : cands) {
-        int rc = ompd_plan_retile(p, c);
-        if (rc) continue;
-        float tot = 0;
-        bool ok = true;
-        for (int t = 0; t < trials + 1 && ok; ++t) {
-            if (ompd_plan_run_locked(p, s) != OMPD_OK) { ok = false; break; }
-            if (hipEventSynchronize(p->ev2) != hipSuccess) { ok = false; break; }
+    for (size_t lds : {(size_t)16 * STATE_BYTES, (size_t)32 * STATE_BYTES, (size_t)64 * STATE_BYTES}) {
+        for (int wpc : {0, 4}) {
+            PlanConfig c = base;
+            c.lds_bytes = lds;
+            c.wg_per_cu = wpc;
             float ms = 0;
-            if (hipEventElapsedTime(&ms, p->ev0, p->ev2) != hipSuccess) {
-                return ompd_fail(OMPD_E_DEVICE, "autotune: event timing failed");
-            }
-            if (t > 0) tot += ms;   // first run warms the graph
+            if (time_config(p, c, s, trials, ms) != OMPD_OK) continue;
+            if (ms < best_t) { best_t = ms; best = c; }
         }
-        if (!ok) continue;
-        float avg = tot / trials;
-        if (avg < best_t) { best_t = avg; best = c; }
     }
     int rc = ompd_plan_retile(p, best);
     if (rc) return rc;
+    if (best_t >= 1e30f) return ompd_fail(OMPD_E_DEVICE, "autotune: no configuration ran");
     if (best_ms) *best_ms = best_t;
     return OMPD_OK;
+}
+
+extern "C" int ompd_plan_set_schedule(ompd_plan* p, const int32_t* per_bucket)
+{
+    if (!p || !per_bucket) return ompd_fail(OMPD_E_INVAL, "bad arguments");
+    for (int b = 0; b < OMPD_SCHED_BUCKETS; ++b)
+        if (per_bucket[b] < -1 || per_bucket[b] > 1) return ompd_fail(OMPD_E_INVAL, "schedule must be -1, 0 or 1");
+    std::lock_guard<std::mutex> lk(p->ctx->mu);
+    PlanConfig c = p->cfg;
+    for (int b = 0; b < OMPD_SCHED_BUCKETS; ++b) c.bucket_sched[b] = per_bucket[b];
+    c.only_bucket = -1;
+    c.use_graph = true;
+    return ompd_plan_retile(p, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -820,8 +960,8 @@ static int stage_inputs(const ompd_cfg* cfgs, ompd_result* res, int n, Staged& s
     std::vector<uint8_t> host;
     size_t total = 0;
     auto reserve = [&](size_t bytes) { size_t o = total; total += align256(bytes); return o; };
-    struct In { size_t sp, si, kd, spc, R, W, evh, evd, lxh, lxd, call, sums; };
-    struct OutO { size_t nu_h, nu_d, ave_h, ave_d, avf_h, avf_d, ie_d, ie_h, ig_d, ig_h, vk, ad, bd; };
+    struct In { size_t sp, si, kd, spc, R, W, evh, evd, lxh, lxd, call, sums, sc; };
+    struct OutO { size_t nu_h, nu_d, ave_h, ave_d, avf_h, avf_d, ie_d, ie_h, ig_d, ig_h, vk, ad, bd, fpc; };
     std::vector<In> in(n);
     std::vector<OutO> oo(n);
     for (int i = 0; i < n; ++i) {
@@ -842,6 +982,7 @@ static int stage_inputs(const ompd_cfg* cfgs, ompd_result* res, int n, Staged& s
         a.lxd = g.exit_live_dev ? reserve(wd * 8) : SIZE_MAX;
         a.call = g.call_summary ? reserve(4 * (size_t)g.n_blocks) : SIZE_MAX;
         a.sums = g.call_summary ? reserve((size_t)g.n_summaries * 16 * wd * 8) : SIZE_MAX;
+        a.sc = g.scalar ? reserve(wd * 8) : SIZE_MAX;
         (void)r;
         (void)ev;
     }
@@ -860,6 +1001,7 @@ static int stage_inputs(const ompd_cfg* cfgs, ompd_result* res, int n, Staged& s
         o.ie_d = opt(r.ins_entry_to_dev, bv); o.ie_h = opt(r.ins_entry_to_host, bv);
         o.ig_d = opt(r.ins_edge_to_dev, ev); o.ig_h = opt(r.ins_edge_to_host, ev);
         o.vk = opt(r.var_kind, (size_t)g.n_vars); o.ad = opt(r.after_dev, g.n_blocks); o.bd = opt(r.before_dev, g.n_blocks);
+        o.fpc = opt(r.fp_clause, bv);
     }
     st.bytes = total;
     hipError_t e = hipMalloc(&st.dmem, std::max<size_t>(total, 256));
@@ -887,6 +1029,7 @@ static int stage_inputs(const ompd_cfg* cfgs, ompd_result* res, int n, Staged& s
         if (a.lxd != SIZE_MAX) put(a.lxd, g.exit_live_dev, wd * 8);
         if (a.call != SIZE_MAX) put(a.call, g.call_summary, 4 * (size_t)g.n_blocks);
         if (a.sums != SIZE_MAX) put(a.sums, g.summaries, (size_t)g.n_summaries * 16 * wd * 8);
+        if (a.sc != SIZE_MAX) put(a.sc, g.scalar, wd * 8);
         ompd_cfg d = g;
         d.succ_ptr = (const int32_t*)(D + a.sp);
         d.succ_idx = (const int32_t*)(D + a.si);
@@ -900,6 +1043,7 @@ static int stage_inputs(const ompd_cfg* cfgs, ompd_result* res, int n, Staged& s
         d.exit_live_dev = a.lxd != SIZE_MAX ? (const uint64_t*)(D + a.lxd) : nullptr;
         d.call_summary = a.call != SIZE_MAX ? (const int32_t*)(D + a.call) : nullptr;
         d.summaries = a.sums != SIZE_MAX ? (const uint64_t*)(D + a.sums) : nullptr;
+        d.scalar = a.sc != SIZE_MAX ? (const uint64_t*)(D + a.sc) : nullptr;
         st.dcfg[i] = d;
         const OutO& o = oo[i];
         ompd_result dr;
@@ -922,6 +1066,7 @@ static int stage_inputs(const ompd_cfg* cfgs, ompd_result* res, int n, Staged& s
         dr.var_kind = (uint8_t*)outp(o.vk, r.var_kind, (size_t)g.n_vars);
         dr.after_dev = (uint8_t*)outp(o.ad, r.after_dev, (size_t)g.n_blocks);
         dr.before_dev = (uint8_t*)outp(o.bd, r.before_dev, (size_t)g.n_blocks);
+        dr.fp_clause = (uint64_t*)outp(o.fpc, r.fp_clause, bv);
         st.dres[i] = dr;
     }
     if (in_bytes) CK(hipMemcpyAsync(st.dmem, host.data(), in_bytes, hipMemcpyHostToDevice, s));
@@ -1020,6 +1165,7 @@ extern "C" int ompd_analyze_batch_noalloc(ompd_ctx* ctx, const ompd_cfg* cfgs, o
     for (int i = 0; i < n; ++i)
         ompd_fill_devcfg(cfgs[i], res[i], S + base[i], off[i], flags, ctx->wait_ticks, h[i], bnd.data() + boff[i],
                          (uint64_t*)(S + bnd_off) + boff[i]);
+    ompd_settle_sched(h.data(), n, ctx->n_cu);
     Shape sh;
     int rc = ompd_make_shape(ctx, h, pc, sh);
     if (rc) return rc;

@@ -141,6 +141,7 @@ static void launcher_main(ServingState* S)
             ompd_fill_devcfg(r->dcfg, r->dres, S->dev_base + r->dev_off + r->scratch_off, r->so, r->flags,
                              S->ctx->wait_ticks, h[i], nullptr);
         }
+        ompd_settle_sched(h.data(), k, S->ctx->n_cu);
         PlanConfig pc;
         Shape sh;
         int rc = ompd_make_shape(S->ctx, h, pc, sh);
@@ -351,22 +352,24 @@ extern "C" int ompd_submit(ompd_ctx* ctx, const ompd_cfg* cfg, ompd_result* res,
     size_t o_R = take(bv), o_W = take(bv), o_bnd = take(4 * wd * 8);
     size_t o_call = g.call_summary ? take(4 * nb) : SIZE_MAX;
     size_t o_sums = g.call_summary ? take((size_t)g.n_summaries * 16 * wd * 8) : SIZE_MAX;
+    size_t o_sc = g.scalar ? take(wd * 8) : SIZE_MAX;
     r->in_bytes = off;
-    size_t o_out[13];
-    const size_t out_sz[13] = {bv, bv, bv, bv, bv, bv, bv, bv, ev, ev, nv, nb, nb};
-    for (int i = 0; i < 13; ++i) o_out[i] = take(out_sz[i]);
+    size_t o_out[14];
+    const size_t out_sz[14] = {bv, bv, bv, bv, bv, bv, bv, bv, ev, ev, nv, nb, nb, bv};
+    for (int i = 0; i < 14; ++i) o_out[i] = take(out_sz[i]);
     ompd_result full{};
     uint64_t** op[10] = {&full.nu_host, &full.nu_dev, &full.ave_host, &full.ave_dev, &full.avf_host, &full.avf_dev,
                          &full.ins_entry_to_host, &full.ins_entry_to_dev, &full.ins_edge_to_host, &full.ins_edge_to_dev};
     for (int i = 0; i < 10; ++i) *op[i] = (uint64_t*)1;   // non-NULL: only sizes the scratch here
     full.var_kind = (uint8_t*)1; full.after_dev = (uint8_t*)1; full.before_dev = (uint8_t*)1;
+    full.fp_clause = (uint64_t*)1;
     r->scratch_off = off;
     off += ompd_cfg_scratch(g, full, r->so);
     r->dev_bytes = off;
     r->pin_bytes = r->in_bytes;
     {
         // its share of a step's launch tables: descriptor, tiles, pass items, status words
-        const size_t tiles = (size_t)tiles_of((int)wd);
+        const size_t tiles = (size_t)tiles_of((int)wd) + 2 * wd + 1;   // walk tiles, level tiles
         const size_t items = wd ? ((wd + PASS_WORDS - 1) / PASS_WORDS) * ((nb + 63) / 64) : 0;
         r->tab_bytes = ompd_pool::request_table_bytes(tiles, items, sizeof(DevCfg), sizeof(Tile), sizeof(EdgeItem),
                                                       4 * INFO_WORDS);
@@ -413,6 +416,7 @@ extern "C" int ompd_submit(ompd_ctx* ctx, const ompd_cfg* cfg, ompd_result* res,
         put(o_call, g.call_summary, 4 * nb);
         put(o_sums, g.summaries, (size_t)g.n_summaries * 16 * wd * 8);
     }
+    if (o_sc != SIZE_MAX) put(o_sc, g.scalar, wd * 8);
     char* D = S->dev_base + r->dev_off;
     ompd_cfg d = g;
     d.succ_ptr = (const int32_t*)(D + o_sp);
@@ -427,18 +431,20 @@ extern "C" int ompd_submit(ompd_ctx* ctx, const ompd_cfg* cfg, ompd_result* res,
     d.exit_live_dev = d.entry_valid_host + 3 * wd;
     d.call_summary = o_call != SIZE_MAX ? (const int32_t*)(D + o_call) : nullptr;
     d.summaries = o_sums != SIZE_MAX ? (const uint64_t*)(D + o_sums) : nullptr;
+    d.scalar = o_sc != SIZE_MAX ? (const uint64_t*)(D + o_sc) : nullptr;
     r->dcfg = d;
     ompd_result& dr = r->dres;
-    void* user_ptr[13] = {res->nu_host, res->nu_dev, res->ave_host, res->ave_dev, res->avf_host, res->avf_dev,
+    void* user_ptr[14] = {res->nu_host, res->nu_dev, res->ave_host, res->ave_dev, res->avf_host, res->avf_dev,
                           res->ins_entry_to_host, res->ins_entry_to_dev, res->ins_edge_to_host, res->ins_edge_to_dev,
-                          res->var_kind, res->after_dev, res->before_dev};
+                          res->var_kind, res->after_dev, res->before_dev, res->fp_clause};
     uint64_t** dp[10] = {&dr.nu_host, &dr.nu_dev, &dr.ave_host, &dr.ave_dev, &dr.avf_host, &dr.avf_dev,
                          &dr.ins_entry_to_host, &dr.ins_entry_to_dev, &dr.ins_edge_to_host, &dr.ins_edge_to_dev};
     for (int i = 0; i < 10; ++i) *dp[i] = (uint64_t*)(D + o_out[i]);
     dr.var_kind = (uint8_t*)(D + o_out[10]);
     dr.after_dev = (uint8_t*)(D + o_out[11]);
     dr.before_dev = (uint8_t*)(D + o_out[12]);
-    for (int i = 0; i < 13; ++i)
+    dr.fp_clause = (uint64_t*)(D + o_out[13]);
+    for (int i = 0; i < 14; ++i)
         if (user_ptr[i] && out_sz[i]) r->back.push_back(Back{o_out[i], user_ptr[i], out_sz[i]});
     r->t_submit = now_ns();
     {

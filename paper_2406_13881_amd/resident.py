@@ -70,6 +70,12 @@ class ResidentBatch:
                         full.append(np.asarray(v, dtype=np.uint64))
                     bnd[name] = t(cat(full, np.uint64).view(np.int64))
         self.d_bnd = bnd
+        # scalar marks (firstprivate candidates), zero words for CFGs without marks
+        self.d_sc = None
+        if any(getattr(c, "scalar", None) is not None for c in cfgs):
+            marks = [np.zeros(int(w), np.uint64) if getattr(c, "scalar", None) is None else c.scalar
+                     for c, w in zip(cfgs, wd)]
+            self.d_sc = t(cat(marks, np.uint64).view(np.int64))
         total = {"bw": int(self.o_bw[-1]), "ew": int(self.o_ew[-1]), "var": int(self.o_var[-1]), "blk": int(self.o_blk[-1])}
         self.out = {}
         for k in self.want:
@@ -97,6 +103,8 @@ class ResidentBatch:
                                 ("exit_live_h", "exit_live_host"), ("exit_live_d", "exit_live_dev")):
                 if name in bnd:
                     setattr(g, field, bnd[name].data_ptr() + 8 * int(self.o_w[i]))
+            if self.d_sc is not None and getattr(c, "scalar", None) is not None:
+                g.scalar = self.d_sc.data_ptr() + 8 * int(self.o_w[i])
             self.dcfgs.append(g)
             r = DeviceResult()
             for k in self.want:
