@@ -16,6 +16,10 @@ Parity status per function (pins live in ``tests/``):
   completeness and exclusivity invariants plus random-path simulation;
   beyond those, "parity unpinned" (the definition itself is the reference).
 * labels: pinned by brute-force reachability and the worked examples.
+* placement variants: the loop-entry refinement by a path search for the
+  readers of each loop-entry copy's value (and worked examples P1, P3, P4,
+  P9); pure lazy by the default placement on relabelled loop entries (and
+  the same worked examples).
 """
 from __future__ import annotations
 
@@ -36,6 +40,11 @@ SUM_ROWS = 16
  SUM_TH_00, SUM_TH_01, SUM_TH_10, SUM_TH_11, SUM_TD_00, SUM_TD_01, SUM_TD_10, SUM_TD_11) = range(16)
 
 MAP_TO, MAP_FROM, MAP_ALLOC = 1, 2, 4
+
+# placement variants (the ``placement`` argument of solve)
+PLACEMENT_EAGER = 1     # every eager copy stays where it is made
+PLACEMENT_LAZY = 2      # pure lazy: the delay also enters loops
+PLACEMENT_REFINE = 4    # loop-entry refinement: drop loop-entry copies whose value is never read
 
 
 class OracleError(RuntimeError):

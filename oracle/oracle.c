@@ -32,6 +32,21 @@
  *   labels map(to/from/tofrom/alloc) versus target update (Table II), from
  *        reachability of device blocks (one target data region per function)
  *
+ * Two variants of the placement, selected by the caller:
+ *   pure lazy  the delay without the loop rule: loop-entry edges are
+ *        ordinary edges for MAYP and LATER, so a copy may slide into a loop
+ *        and be made on every trip (the placement the loop rule of
+ *        "Data-Flow Analysis" avoids; for comparison).  The join rule still
+ *        holds, so a copy enters a loop only where every trip around it
+ *        leaves both copies valid again.
+ *   loop-entry refinement  Algorithm 1 puts the update that a loop's
+ *        writes make necessary after the loop nest.  The delay stops at
+ *        loop entries, so a copy owed before a loop stays on its entry edge
+ *        even when every path through the loop copies again before reading.
+ *        LIVE (backward, may) finds whether the value a copy leaves is read
+ *        before a write or another copy into the same space replaces it; a
+ *        copy on a loop-entry edge whose value is never read is dropped.
+ *
  * firstprivate (section "Data-Flow Analysis", the firstprivate paragraph,
  * and Table II): a read-only scalar may reach a kernel as a firstprivate
  * argument initialised from the host copy instead of being mapped.  The
@@ -82,6 +97,7 @@ typedef struct {
     uint64_t lastmask;
     uint64_t* fp;          /* [wd] firstprivate variables (all zero when no scalar is marked) */
     int summary_mode;
+    int lazy;              /* pure lazy: loop-entry edges do not stop the delay */
     int32_t* rpo;  /* reverse post-order from ENTRY */
 } G;
 
@@ -353,7 +369,10 @@ static inline uint64_t eag(const G* g, const uint64_t* nu_s, const uint64_t* ave
     return nu_s[ix(g, q, w)] & ~aveout_s[ix(g, p, w)];
 }
 
-static inline uint64_t le_mask(const G* g, int e) { return g->kind[e] == KIND_LOOP_ENTRY ? ~0ull : 0ull; }
+static inline uint64_t le_mask(const G* g, int e)
+{
+    return (!g->lazy && g->kind[e] == KIND_LOOP_ENTRY) ? ~0ull : 0ull;
+}
 
 /* ------------------------------------------------------------------ */
 /* MAYP: copies that may be pending (forward, may, least f.p.)          */
@@ -449,6 +468,53 @@ static int64_t phase_later(const G* g, const uint64_t* nu[2], const uint64_t* av
 }
 
 /* ------------------------------------------------------------------ */
+/* LIVE: is the value in space s read before it is replaced             */
+/*   (backward, may, least f.p.; o = the other space)                   */
+/*   READ_s(q): a read of the s copy: USE_s(q); a call block reads both */
+/*              copies of every variable (its callee may)               */
+/*   KILL_s(q): WR_s(q), and at a DEVICE block the device copy of a     */
+/*              firstprivate variable it reads (no longer valid after)  */
+/*   A_s(q)   = READ_s(q) | (LO_s(q) & ~KILL_s(q))   after entry copies */
+/*   LI_s(q)  = (A_s(q) & ~IE_s(q)) | IE_o(q)                           */
+/*              a copy into s replaces the s value, a copy into o reads */
+/*              it (every copy that stays reads its source, so a copy   */
+/*              counts as a read whether or not its own value is read)  */
+/*   LO_s(q)  = OR over edges e = q->t of (LI_s(t) & ~IG_s(e)) | IG_o(e) */
+/* ------------------------------------------------------------------ */
+static int64_t phase_live(const G* g, uint64_t* const ie[2], uint64_t* const ig[2], uint64_t* li[2])
+{
+    size_t n = (size_t)g->nb * (size_t)g->wd;
+    memset(li[0], 0, sizeof(uint64_t) * n);
+    memset(li[1], 0, sizeof(uint64_t) * n);
+    WL l; if (wl_init(&l, g->nb)) return -1;
+    for (int i = g->nb - 1; i >= 0; --i) wl_push(&l, g->rpo[i]);
+    int64_t visits = 0;
+    while (l.n > 0) {
+        int q = wl_pop(&l);
+        visits++;
+        int changed = 0;
+        for (int s = 0; s < 2; ++s) {
+            int o = 1 - s;
+            for (int w = 0; w < g->wd; ++w) {
+                uint64_t lo = 0;
+                for (int e = g->sp[q]; e < g->sp[q + 1]; ++e)
+                    lo |= (li[s][ix(g, g->si[e], w)] & ~ig[s][(size_t)e * g->wd + w]) | ig[o][(size_t)e * g->wd + w];
+                uint64_t rd = is_call(g, q) ? ~0ull : use_s(g, s, q, w);
+                uint64_t kill = wr_s(g, s, q, w);
+                if (s == 1 && g->space[q] == 1) kill |= g->R[ix(g, q, w)] & g->fp[w];
+                uint64_t a = rd | (lo & ~kill);
+                uint64_t v = ((a & ~ie[s][ix(g, q, w)]) | ie[o][ix(g, q, w)]) & vmask(g, w);
+                if (v != li[s][ix(g, q, w)]) { li[s][ix(g, q, w)] = v; changed = 1; }
+            }
+        }
+        if (changed)
+            for (int k = g->pp[q]; k < g->pp[q + 1]; ++k) wl_push(&l, g->pi[k]);
+    }
+    wl_free(&l);
+    return visits;
+}
+
+/* ------------------------------------------------------------------ */
 /* AVF: validity after the final placement (forward, must, greatest)    */
 /*   AVFin_s(q) = INS_ENTRY_s(q) | AND_e (AVFout_s(p) | INS_EDGE_s(e))  */
 /* ------------------------------------------------------------------ */
@@ -502,6 +568,8 @@ static int64_t phase_avf(const G* g, const uint64_t* nu[2], uint64_t* const ins_
  *   scalar     : [wd] variables the front end marks as scalars (NULL = none); those that
  *                no DEVICE block writes are firstprivate
  *   placement  : bit 0: 0 = delayed placement (LATER), 1 = eager placement only;
+ *                bit 1: pure lazy: the delay ignores loop entries (with bit 0 clear);
+ *                bit 2: loop-entry refinement of the delayed placement (LIVE);
  *                bit 8: evaluate a procedure summary — the boundary may leave a
  *                variable valid in neither space (a summary's entry-validity
  *                argument ranges over all of {0,1} per space)
@@ -533,6 +601,8 @@ int oracle_solve(int32_t nb, int32_t ne, int32_t nv, int32_t entry, int32_t exit
     g.call = call; g.sums = sums;
     g.lastmask = (nv % 64) ? ((1ull << (nv % 64)) - 1ull) : ~0ull;
     g.summary_mode = (placement >> 8) & 1;
+    g.lazy = !(placement & 1) && ((placement >> 1) & 1);
+    const int refine = !(placement & 1) && !g.lazy && ((placement >> 2) & 1);
     placement &= 1;
     g.fp = (uint64_t*)calloc((size_t)(g.wd > 0 ? g.wd : 1), sizeof(uint64_t));
     if (!g.fp) return OR_ENOMEM;
@@ -602,6 +672,18 @@ int oracle_solve(int32_t nb, int32_t ne, int32_t nv, int32_t entry, int32_t exit
                     for (int e = succ_ptr[p]; e < succ_ptr[p + 1]; ++e)
                         for (int w = 0; w < g.wd; ++w)
                             ig[s][(size_t)e * g.wd + w] = eag(&g, nu[s], aveout[s], p, succ_idx[e], w) & vmask(&g, w);
+            }
+        }
+        if (refine) {
+            /* drop the copies on loop-entry edges whose value no read uses (the AVF
+             * buffers serve as LIVE's state: AVF overwrites them next) */
+            uint64_t* li[2] = { avf_h, avf_d };
+            if (phase_live(&g, ie, ig, li) < 0) { rc = OR_ENOMEM; goto done; }
+            for (int e = 0; e < ne; ++e) {
+                if (kind[e] != KIND_LOOP_ENTRY) continue;
+                int t = succ_idx[e];
+                for (int s = 0; s < 2; ++s)
+                    for (int w = 0; w < g.wd; ++w) ig[s][(size_t)e * g.wd + w] &= li[s][ix(&g, t, w)];
             }
         }
         uint64_t* ain[2] = { avf_h, avf_d };

@@ -11,7 +11,8 @@ import pytest
 import checkers
 import oracle
 import synth
-from test_oracle_pins import GOLDEN, load_golden, bits_of, VK
+from test_oracle_pins import GOLDEN, PLACEMENTS, VK, bits_of, check_expect, load_golden
+from test_oracle_placements import loopy, rows, value_read
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -49,14 +50,81 @@ MUTANTS = {
     "fp_device_written": ("g.fp[w] = scalar[w] & ~dev_w & vmask(&g, w);", "g.fp[w] = scalar[w] & vmask(&g, w);"),
     "fp_clause_on_host": ("fp_clause[ix(&g, b, w)] = space[b] == 1 ? (R[ix(&g, b, w)] & g.fp[w]) : 0ull;",
                           "fp_clause[ix(&g, b, w)] = R[ix(&g, b, w)] & g.fp[w];"),
+    # loop-entry refinement
+    "live_edge_copy_not_a_read": ("lo |= (li[s][ix(g, g->si[e], w)] & ~ig[s][(size_t)e * g->wd + w]) | ig[o][(size_t)e * g->wd + w];",
+                                  "lo |= (li[s][ix(g, g->si[e], w)] & ~ig[s][(size_t)e * g->wd + w]);"),
+    "live_entry_copy_not_a_read": ("uint64_t v = ((a & ~ie[s][ix(g, q, w)]) | ie[o][ix(g, q, w)]) & vmask(g, w);",
+                                   "uint64_t v = (a & ~ie[s][ix(g, q, w)]) & vmask(g, w);"),
+    "live_edge_copy_no_replace": ("lo |= (li[s][ix(g, g->si[e], w)] & ~ig[s][(size_t)e * g->wd + w]) | ig[o][(size_t)e * g->wd + w];",
+                                  "lo |= li[s][ix(g, g->si[e], w)] | ig[o][(size_t)e * g->wd + w];"),
+    "live_entry_copy_no_replace": ("uint64_t v = ((a & ~ie[s][ix(g, q, w)]) | ie[o][ix(g, q, w)]) & vmask(g, w);",
+                                   "uint64_t v = (a | ie[o][ix(g, q, w)]) & vmask(g, w);"),
+    "live_no_kill": ("uint64_t a = rd | (lo & ~kill);", "uint64_t a = rd | lo;"),
+    "live_other_space_read": ("uint64_t rd = is_call(g, q) ? ~0ull : use_s(g, s, q, w);",
+                              "uint64_t rd = is_call(g, q) ? ~0ull : use_s(g, o, q, w);"),
+    "refine_every_edge": ("if (kind[e] != KIND_LOOP_ENTRY) continue;", ""),
+    "refine_wrong_space": ("ig[s][(size_t)e * g.wd + w] &= li[s][ix(&g, t, w)];",
+                           "ig[s][(size_t)e * g.wd + w] &= li[1 - s][ix(&g, t, w)];"),
+    # pure lazy
+    "lazy_ignored": ("return (!g->lazy && g->kind[e] == KIND_LOOP_ENTRY) ? ~0ull : 0ull;",
+                     "return (g->kind[e] == KIND_LOOP_ENTRY) ? ~0ull : 0ull;"),
+    "lazy_mayp_still_stops": ("min |= (eag(g, nu[s], aveout[s], p, q, w) | mout[s][ix(g, p, w)]) & ~le_mask(g, e);",
+                              "min |= (eag(g, nu[s], aveout[s], p, q, w) | mout[s][ix(g, p, w)]) & ~(g->kind[e] == KIND_LOOP_ENTRY ? ~0ull : 0ull);"),
     "fp_alloc_too": ("if (space[q] == 1 && (((R[ix(&g, q, w)] & ~g.fp[w]) | W[ix(&g, q, w)]) & bit)) dev_access = 1;",
                      "if (space[q] == 1 && ((R[ix(&g, q, w)] | W[ix(&g, q, w)]) & bit)) dev_access = 1;"),
 }
 
 
+def run_variant_pins():
+    """The placement variants: hand-derived worked examples, the refinement against the
+    path search, the pure lazy variant against relabelled loop entries."""
+    for path in sorted(glob.glob(os.path.join(GOLDEN, "P*.json"))):
+        g, cfg, pos = load_golden(path)
+        for name, exp in g.get("variants", {}).items():
+            try:
+                check_expect(g, cfg, pos, oracle.solve(cfg, placement=PLACEMENTS[name]), exp)
+            except AssertionError:
+                return False
+    for seed in range(12):
+        cfg = loopy(seed, marks=seed % 2 == 1)
+        base = oracle.solve(cfg)
+        ref = oracle.solve(cfg, placement=oracle.PLACEMENT_REFINE)
+        V = checkers.View(cfg)
+        ie0, ig0 = rows(base, cfg.wd)
+        ie1, ig1 = rows(ref, cfg.wd)
+        if ie1 != ie0:
+            return False
+        for p in range(cfg.n_blocks):
+            for (t, e) in V.succ[p]:
+                for s in (0, 1):
+                    if int(cfg.edge_kind[e]) != 2:
+                        if ig1[s][e] != ig0[s][e]:
+                            return False
+                        continue
+                    for v in range(cfg.n_vars):
+                        if (ig0[s][e] >> v) & 1:
+                            if bool((ig1[s][e] >> v) & 1) != value_read(V, ie0, ig0, s, t, v):
+                                return False
+                        elif (ig1[s][e] >> v) & 1:
+                            return False
+        if checkers.check_invariants(cfg, ref):
+            return False
+        lazy = oracle.solve(cfg, placement=oracle.PLACEMENT_LAZY)
+        plain = synth.CFG(**{f: getattr(cfg, f) for f in cfg.__dataclass_fields__})
+        plain.edge_kind = np.where(np.asarray(cfg.edge_kind) == 2, 0, np.asarray(cfg.edge_kind)).astype(np.uint8)
+        d = oracle.solve(plain)
+        if any(not np.array_equal(lazy[k], d[k]) for k in d):
+            return False
+        if checkers.check_invariants(cfg, lazy):
+            return False
+    return True
+
+
 def run_pins():
     """A compact version of the pin suite; returns True if every pin holds."""
     try:
+        if not run_variant_pins():
+            return False
         for path in sorted(glob.glob(os.path.join(GOLDEN, "P*.json"))):
             g, cfg, pos = load_golden(path)
             r = oracle.solve(cfg)
