@@ -188,9 +188,10 @@ def kernel_bytes(cfgs):
     the kernel must read or write, once (bv = a block vector, ev = an edge
     vector, both in the stored 64-bit word layout).  Iteration traffic (state
     rows revisited by later sweeps) is not algorithmic."""
+    # (the loop-entry refinement, ompd_k_live and ompd_k_post_live, is not requested here: no launch)
     out = dict.fromkeys(("ompd_k_prep", "ompd_k_nu", "ompd_k_ave", "ompd_k_post_ave", "ompd_k_mayp",
-                         "ompd_k_post_mayp", "ompd_k_later", "ompd_k_post_later", "ompd_k_avf",
-                         "ompd_k_post_avf", "ompd_k_varkind"), 0)
+                         "ompd_k_post_mayp", "ompd_k_later", "ompd_k_post_later", "ompd_k_live",
+                         "ompd_k_post_live", "ompd_k_avf", "ompd_k_post_avf", "ompd_k_varkind"), 0)
     for c in cfgs:
         wd = (c.n_vars + 63) // 64
         nb, ne = c.n_blocks, c.n_edges

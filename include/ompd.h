@@ -77,6 +77,19 @@ enum { OMPD_MAP_TO = 1, OMPD_MAP_FROM = 2, OMPD_MAP_ALLOC = 4, OMPD_FIRSTPRIVATE
  * picks per CFG from its shape. */
 #define OMPD_F_SCHED_LEVEL (1u << 4)
 #define OMPD_F_SCHED_WALK (1u << 5)
+/* Placement variants (section "Data-Flow Analysis", the loop rule, and
+ * Algorithm 1).  The default placement makes each copy right after the
+ * producer and then delays it towards the read that needs it, never into a
+ * loop and never across a join where another path holds fresh data in one
+ * space only.  PLACEMENT_LAZY: the delay ignores loop entries (copies may
+ * land inside loops; for comparison).  PLACEMENT_REFINE: the loop-entry
+ * refinement: a copy the delay left on a loop-entry edge is dropped when no
+ * read uses its value (every path re-copies or overwrites it first), which
+ * gives the single update after a writing loop that Algorithm 1 places;
+ * one more backward fixed point and one pass.  EAGER takes precedence over
+ * both, LAZY over REFINE. */
+#define OMPD_F_PLACEMENT_LAZY (1u << 6)
+#define OMPD_F_PLACEMENT_REFINE (1u << 7)
 #define OMPD_F_SWEEP_CAP(n) ((((uint32_t)(n)) & 0xFFFFu) << 16) /* cap sweeps per phase */
 /* Ring of recently solved blocks per solve workgroup, for the one-shot entry
  * points (what ompd_plan_configure sets for a plan): n = 8, 16, 32 or 64
@@ -153,8 +166,8 @@ typedef struct {
  * target update to.  A copy into the host on p->q or before q is map(from)
  * iff !before_dev[q]; otherwise target update from.
  *   sweeps[6]     sweeps used per phase (next use, validity, pending,
- *                 delay, final validity, reachability); host memory, filled
- *                 after completion; informational.                        */
+ *                 delay, final validity, loop-entry refinement); host
+ *                 memory, filled after completion; informational.         */
 typedef struct {
     uint64_t *nu_host, *nu_dev;
     uint64_t *ave_host, *ave_dev;
@@ -264,9 +277,10 @@ int ompd_plan_configure(ompd_plan* plan, int64_t lds_bytes, int32_t wg_per_cu);
  * ompd_plan_kernel_ms then gives the duration (ms) of each kernel of the
  * last run, in launch order: ingest, next use, validity, validity pass
  * (AVEin, eager copies), pending copies, pending pass (valid in both
- * spaces), delayed placement, placement pass (the copies), final
+ * spaces), delayed placement, placement pass (the copies), loop-entry
+ * refinement and its pass (0 ms unless a CFG asks for it), final
  * validity, final pass (AVFin, map-kind masks), map kinds (*n_kernels =
- * 11), or ingest and the per-tile kernel (*n_kernels = 2) after
+ * 13), or ingest and the per-tile kernel (*n_kernels = 2) after
  * ompd_plan_split_kernels(plan, 0).  At most `capacity` are written.
  * OMPD_E_INVAL if profiling is off. */
 int ompd_plan_profile(ompd_plan* plan, int32_t enable);

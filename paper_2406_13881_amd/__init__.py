@@ -41,6 +41,8 @@ F_PLACEMENT_EAGER = 1 << 1
 F_TILE_KERNEL = 1 << 3
 F_SCHED_LEVEL = 1 << 4
 F_SCHED_WALK = 1 << 5
+F_PLACEMENT_LAZY = 1 << 6
+F_PLACEMENT_REFINE = 1 << 7
 
 
 def F_RING_SLOTS(n: int) -> int:
@@ -593,7 +595,8 @@ class Plan:
         _check(lib().ompd_plan_configure(self.h, int(lds_bytes), int(wg_per_cu)))
 
     KERNELS = ("ompd_k_prep", "ompd_k_nu", "ompd_k_ave", "ompd_k_post_ave", "ompd_k_mayp", "ompd_k_post_mayp",
-               "ompd_k_later", "ompd_k_post_later", "ompd_k_avf", "ompd_k_post_avf", "ompd_k_varkind")
+               "ompd_k_later", "ompd_k_post_later", "ompd_k_live", "ompd_k_post_live", "ompd_k_avf",
+               "ompd_k_post_avf", "ompd_k_varkind")
     KERNELS_TILE = ("ompd_k_prep", "ompd_k_solve")
 
     def split_kernels(self, split: bool = True):

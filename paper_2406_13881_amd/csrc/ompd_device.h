@@ -26,7 +26,17 @@ enum : int32_t {
     WAIT_PRODUCED = 4    // helper (idle): the compute wavefront has produced a step
 };
 
-enum : int32_t { PH_NU = 0, PH_AVE = 1, PH_MAYP = 2, PH_LATER = 3, PH_AVF = 4, PH_REACH = 5 };
+// Phases (PH_LIVE: the loop-entry refinement, between the placement and the final validity).
+enum : int32_t { PH_NU = 0, PH_AVE = 1, PH_MAYP = 2, PH_LATER = 3, PH_AVF = 4, PH_LIVE = 5 };
+constexpr int N_PHASES = 6;
+
+// DevCfg::placement bits.
+enum : int32_t {
+    PL_EAGER = 1,     // every eager copy stays where it is made
+    PL_SUMMARY = 2,   // procedure-summary evaluation (the entry boundary may leave gaps)
+    PL_LAZY = 4,      // pure lazy: loop-entry edges do not stop the delay
+    PL_REFINE = 8     // loop-entry refinement of the delayed placement
+};
 
 // Summary rows of a callee, each a word vector over all variables.
 enum : int32_t {
@@ -40,7 +50,7 @@ enum : int32_t {
 // scratch owned by the plan.
 struct DevCfg {
     int32_t nb, ne, nv, entry, exit, wd;   // wd = 64-bit words per row
-    int32_t n_sums, placement, sweep_cap;   // placement: bit 0 eager, bit 1 summary evaluation
+    int32_t n_sums, placement, sweep_cap;   // placement: PL_* bits
     int32_t wait_ticks;   // a wait gives up after this many wall-clock ticks without progress (> 0)
     int32_t sched;        // SCHED_WALK or SCHED_LEVEL
     int32_t sched_rule;   // host side: 1 when the default rule chose sched (a launch may revise it)
@@ -138,15 +148,18 @@ constexpr int LDS_FIXED = CTL_BYTES;
 // finds free, so a deeper ring means fewer, longer rounds.
 constexpr int in_ring(int ph) { return ph == PH_NU || ph == PH_AVE ? 32 : 16; }
 inline int phase_inputs(int ph) { return 2 + (ph == PH_NU ? 2 : ph == PH_AVE ? 4 : ph == PH_MAYP ? 6 : 8); }
+// Does a CFG run the loop-entry refinement (placement bits)?
+constexpr bool refines(int32_t placement) { return (placement & (PL_REFINE | PL_EAGER | PL_LAZY)) == PL_REFINE; }
 inline size_t phase_lds(int ph, int ring_slots)
 {
     return LDS_FIXED + (size_t)ring_slots * STATE_BYTES + (size_t)in_ring(ph) * (phase_inputs(ph) * WORD_BYTES + 16) +
            STATE_BYTES;
 }
-// Work counters (int32) of one solve launch: phases 0..4, passes 8..11, map kinds 12, per-tile
-// kernel 13, level kernels 16..20.
+// Work counters (int32) of one solve launch: phases 0..5, passes 8..11 and 14 (refinement), map
+// kinds 12, per-tile kernel 13, level kernels 16..21.
 constexpr int N_COUNTERS = 32;
-// Kernels of one solve launch, in launch order (prep excluded).
-constexpr int N_SOLVE_KERNELS = 10;
+// Kernels of one solve launch, in launch order (prep excluded; the two of the refinement are
+// launched only when a CFG asks for it, their profile marks always).
+constexpr int N_SOLVE_KERNELS = 12;
 
 }  // namespace ompd

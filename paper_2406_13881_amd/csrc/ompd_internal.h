@@ -33,8 +33,9 @@ struct ompd_ctx {
 struct LaunchDims {
     int ring_slots = 16;
     bool split = true;           // one kernel per phase and pass (else the per-tile kernel)
-    size_t lds[5] = {0, 0, 0, 0, 0};
-    int grid[5] = {1, 1, 1, 1, 1};
+    size_t lds[ompd::N_PHASES] = {0, 0, 0, 0, 0, 0};
+    int grid[ompd::N_PHASES] = {1, 1, 1, 1, 1, 1};
+    bool refine = false;         // some CFG runs the loop-entry refinement (phase and pass launched)
     int grid_edge = 1;
     size_t lds_tile = 0;         // the per-tile kernel: LDS of its largest phase
     int grid_tile = 1;

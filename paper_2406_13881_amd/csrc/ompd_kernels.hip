@@ -73,6 +73,8 @@ constexpr int DD_DEV = 5;                   // the bit of DF_DEV
 static_assert(DF_DEV == 1u << DD_DEV && DF_MASK < 1u << DD_LAST0, "descriptor bits");
 // all ones if bit `bit` of the wave-uniform word fl is set, else zero
 __device__ __forceinline__ uint32_t fmask(uint32_t fl, int bit) { return (uint32_t)((int32_t)(fl << (31 - bit)) >> 31); }
+// Does an edge of kind k stop the delay?  Loop entries do, unless the placement is pure lazy.
+__device__ __forceinline__ bool is_le(const DevCfg& c, uint8_t k) { return k == 2 && !(c.placement & PL_LAZY); }
 // A step entry (two int4, one per walk position): x flags; y the ring distances of neighbours
 // 0 and 1 (bits 0-7, 8-15; flag code 2 only); z the far neighbour; w how many steps before the
 // current one its state was computed (this sweep's or, when SF_BACK, the previous sweep's); then
@@ -191,7 +193,7 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
                 c.R[(size_t)c.exit * wd + w] | c.W[(size_t)c.exit * wd + w]) err = 1;
             uint64_t eh = c.ev_h[w], ed = c.ev_d[w];
             if ((eh | ed | c.lx_h[w] | c.lx_d[w]) & ~m) err = 1;
-            if (!(c.placement & 2) && ((eh | ed) & m) != m) err = 1;   // a summary evaluation may leave gaps
+            if (!(c.placement & PL_SUMMARY) && ((eh | ed) & m) != m) err = 1;   // a summary evaluation may leave gaps
         }
         for (int b = tid; b < nb; b += nt)
             if ((c.R[(size_t)b * wd + wd - 1] | c.W[(size_t)b * wd + wd - 1]) & ~last) err = 1;
@@ -258,8 +260,8 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
         r0.x = (int)((uint32_t)cnt | fl);
         r0.y = cnt > 0 ? c.pred_idx[a] : 0;
         r0.z = cnt > 1 ? c.pred_idx[a + 1] : 0;
-        r0.w = (int)((uint32_t)e0 | ((cnt > 0 && c.kind[e0] == 2) ? 0x80000000u : 0u));
-        r1.x = (int)((uint32_t)e1 | ((cnt > 1 && c.kind[e1] == 2) ? 0x80000000u : 0u));
+        r0.w = (int)((uint32_t)e0 | ((cnt > 0 && is_le(c, c.kind[e0])) ? 0x80000000u : 0u));
+        r1.x = (int)((uint32_t)e1 | ((cnt > 1 && is_le(c, c.kind[e1])) ? 0x80000000u : 0u));
         r1.y = a;
         r1.z = ci;
         r1.w = 0;
@@ -549,10 +551,10 @@ template <int PH>
 __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int fslot, u64* lds, int RS)
 {
     constexpr bool with_flags = PH == PH_NU || PH == PH_AVE;   // phases with the flag lane
-    constexpr bool BWD = PH == PH_NU;
+    constexpr bool BWD = PH == PH_NU || PH == PH_LIVE;
     constexpr int NX = PH == PH_NU ? 2 : PH == PH_AVE ? 4 : PH == PH_MAYP ? 6 : 8;
     // the first input that is a row of the second edge (NX: the phase reads no edge rows)
-    constexpr int NX1 = PH == PH_MAYP ? 4 : PH == PH_LATER ? 5 : PH == PH_AVF ? 6 : NX;
+    constexpr int NX1 = PH == PH_MAYP ? 4 : PH == PH_LATER ? 5 : PH == PH_AVF || PH == PH_LIVE ? 6 : NX;
     constexpr int NI = NX + 2;        // inputs of a step: the phase's own and the first far neighbour (h, d)
     constexpr int IR = in_ring(PH);   // steps whose inputs the helper keeps ready
     // Lanes 0 .. LANES - 1 of both wavefronts own the tile's words, lanes LANES .. 2 LANES - 1
@@ -634,7 +636,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         if (j == 1) { p = r.n1; e = r.e1; return; }
         p = PI[r.ovf + j];
         int ee = PE[r.ovf + j];
-        e = (uint32_t)ee | (KD[ee] == 2 ? 0x80000000u : 0u);
+        e = (uint32_t)ee | (is_le(c, KD[ee]) ? 0x80000000u : 0u);
     };
     auto nbr_b = [&](const Rec& r, int j) -> int {
         if (j == 0) return r.n0;
@@ -1132,7 +1134,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // MAYP_s(e) = (EAG_s(e) | MAYPout_s(p)) & ~LE(e), EAG_s(e=p->q) = NU_s(q) & ~AVEout_s(p);
     // MAYPout_s(q) = OR_e MAYP_s(e) & ~USE'_s(q) & ~WR_s(q)
     if constexpr (PH == PH_MAYP) {
-        if (c.placement & 1) return;
+        if (c.placement & PL_EAGER) return;
         const Rows S = rows_of(c.mayp_h, c.mayp_d, 0);
         // x0 = R, x1 = W, x2..x5 = EAG_H/D of the two inline in-edges
         // (the second edge's rows are not loaded for a block with one neighbour)
@@ -1185,7 +1187,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     // LATERin_s(q) = AND_e (L'_s | N'_s) & OR_e L'_s; LATERout_s(q) = LATERin_s(q) & ~USE'_s(q) & ~WR_s(q)
     // (the copies themselves are materialised after the phase)
     if constexpr (PH == PH_LATER) {
-        if (c.placement & 1) return;
+        if (c.placement & PL_EAGER) return;
         const Rows S = rows_of(c.later_h, c.later_d, 0);
         // x0 = R, x1 = W, x2..x4 / x5..x7 = EAG_H, EAG_D, BOTH of the two inline in-edges
         auto pre = [&](u64 ob, u64 oe0, u64 oe1, const GAS u64** x) {
@@ -1241,6 +1243,69 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             const hw anyh = (l0h & a0) | (l1h & a1), anyd = (l0d & a0) | (l1d & a1);
             vh = allh & anyh & vm & ~sth;
             vd = alld & anyd & vm & ~std_;
+        };
+        run_phase(S, 0ull, 0ull, pre, fast, comp);
+        return;
+    }
+
+    // ------------------------------------------------------------ loop-entry refinement (backward, may)
+    // Is the value in space s at b's entry read before a write or a copy into s replaces it:
+    // A_s(b) = READ_s(b) | (LO_s(b) & ~KILL_s(b)), LI_s(b) = (A_s(b) & ~INS_ENTRY_s(b)) | INS_ENTRY_o(b),
+    // LO_s(b) = OR over out-edges e = b->t of (LI_s(t) & ~INS_EDGE_s(e)) | INS_EDGE_o(e)  (a copy reads
+    // its source); READ at EXIT: the liveness after it, at a call: everything; KILL: a write in s,
+    // and a kernel's firstprivate read for the device copy.  The state uses the pending-copy rows.
+    if constexpr (PH == PH_LIVE) {
+        if (!refines(c.placement)) return;
+        const Rows S = rows_of(c.mayp_h, c.mayp_d, 0);
+        // x0 = R, x1 = W, x2/x3 = INS_ENTRY_H/D, x4..x7 = INS_EDGE_H/D of the first two out-edges
+        auto pre = [&](u64 ob, u64 oe0, u64 oe1, const GAS u64** x) {
+            x[0] = rowu(c.R, ob); x[1] = rowu(c.W, ob); x[2] = rowu(c.ie_h, ob); x[3] = rowu(c.ie_d, ob);
+            x[4] = erowu(c.ig_h, oe0); x[5] = erowu(c.ig_d, oe0);
+            x[6] = erowu(c.ig_h, oe1); x[7] = erowu(c.ig_d, oe1);
+        };
+        auto comp = [&](int b, const Rec& r, const hw* x, const hw* nh, const hw* nd, hw ph, hw pd, int sweep,
+                        int g, hw& vh, hw& vd) {
+            const int cnt = (int)(r.meta & REC_COUNT);
+            hw oh = 0, od = 0;
+            for (int j = 0; j < cnt; ++j) {
+                hw sh, sd, gh, gd;
+                if (j < 2) {
+                    sh = j ? nh[1] : nh[0]; sd = j ? nd[1] : nd[0]; gh = j ? x[6] : x[4]; gd = j ? x[7] : x[5];
+                }
+                else {
+                    const uint32_t e = (uint32_t)(r.ovf + j);
+                    gh = settle(erow(c.ig_h, e)); gd = settle(erow(c.ig_d, e));
+                    extra(S, b, nbr_b(r, j), sweep, g, 0u, ph, pd, sh, sd);
+                }
+                oh |= (sh & ~gh) | gd;
+                od |= (sd & ~gd) | gh;
+            }
+            const bool dev = r.meta & REC_DEV;
+            hw rh, rd, kh = 0u, kd = 0u;
+            if (r.meta & REC_EXIT) { rh = vec(c.lx_h); rd = vec(c.lx_d); }
+            else if (r.meta & REC_CALL) { rh = ~0u; rd = ~0u; }
+            else {
+                const hw rr = x[0], ww = x[1];
+                rh = dev ? (rr & fph) : rr;
+                rd = dev ? (rr & ~fph) : 0u;
+                kh = dev ? 0u : ww;
+                kd = dev ? (ww | (rr & fph)) : 0u;
+            }
+            const hw ah = rh | (oh & ~kh), ad = rd | (od & ~kd);
+            vh = ((ah & ~x[2]) | x[3]) & vm;
+            vd = ((ad & ~x[3]) | x[2]) & vm;
+        };
+        // (a missing second out-edge's rows are not loaded: masked by its presence bit)
+        auto fast = [&](const hw* x, const hw* nh, const hw* nd, uint32_t fl, hw& vh, hw& vd) {
+            const hw dev = fmask(fl, DD_DEV), p0 = fmask(fl, DD_P0), p1 = fmask(fl, DD_P1);
+            const hw oh = (((nh[0] & ~x[4]) | x[5]) & p0) | (((nh[1] & ~x[6]) | x[7]) & p1);
+            const hw od = (((nd[0] & ~x[5]) | x[4]) & p0) | (((nd[1] & ~x[7]) | x[6]) & p1);
+            const hw rr = x[0], ww = x[1];
+            const hw rh = rr & (~dev | fph), rd = rr & dev & ~fph;
+            const hw kh = ww & ~dev, kd = (ww | (rr & fph)) & dev;
+            const hw ah = rh | (oh & ~kh), ad = rd | (od & ~kd);
+            vh = ((ah & ~x[2]) | x[3]) & vm;
+            vd = ((ad & ~x[3]) | x[2]) & vm;
         };
         run_phase(S, 0ull, 0ull, pre, fast, comp);
         return;
@@ -1317,10 +1382,11 @@ template <int PH>
 __device__ __forceinline__ void level_phase(const DevCfg& c, int hc, uint32_t* SH, uint32_t* SD)
 {
     constexpr bool with_flags = PH == PH_NU || PH == PH_AVE;
-    constexpr bool BWD = PH == PH_NU;
+    constexpr bool BWD = PH == PH_NU || PH == PH_LIVE;
     const bool flg = hc < 0;
     if (flg && !with_flags) return;
-    if ((PH == PH_MAYP || PH == PH_LATER) && (c.placement & 1)) return;
+    if ((PH == PH_MAYP || PH == PH_LATER) && (c.placement & PL_EAGER)) return;
+    if (PH == PH_LIVE && !refines(c.placement)) return;
     const int nb = c.nb, wd = c.wd, tid = threadIdx.x;
     const int w = flg ? 0 : hc >> 1;
     const bool hi = !flg && (hc & 1);
@@ -1345,10 +1411,10 @@ __device__ __forceinline__ void level_phase(const DevCfg& c, int hc, uint32_t* S
     auto nbr = [&](const Rec& r, int j, int& p, uint32_t& e) {
         if (j == 0) { p = r.n0; e = r.e0; return; }
         if (j == 1) { p = r.n1; e = r.e1; return; }
-        if (BWD) { p = G(c.succ_idx)[r.ovf + j]; e = 0; return; }
+        if (BWD) { p = G(c.succ_idx)[r.ovf + j]; e = (uint32_t)(r.ovf + j); return; }
         p = G(c.pred_idx)[r.ovf + j];
         const int ee = G(c.pred_eid)[r.ovf + j];
-        e = (uint32_t)ee | (G(c.kind)[ee] == 2 ? 0x80000000u : 0u);
+        e = (uint32_t)ee | (is_le(c, G(c.kind)[ee]) ? 0x80000000u : 0u);
     };
     auto eid = [&](uint32_t e) -> int { return (int)(e & 0x7FFFFFFFu); };
     // next use after a call block (OR over its successors; final when validity runs)
@@ -1455,6 +1521,29 @@ __device__ __forceinline__ void level_phase(const DevCfg& c, int hc, uint32_t* S
             stop(b, r, in(c.R, b), in(c.W, b), sth, std_);
             vh = allh & anyh & vm & ~sth;
             vd = alld & anyd & vm & ~std_;
+        } else if constexpr (PH == PH_LIVE) {
+            hw oh = 0, od = 0;
+            for (int j = 0; j < cnt; ++j) {
+                int q; uint32_t e;
+                nbr(r, j, q, e);
+                const hw gh = in(c.ig_h, eid(e)), gd = in(c.ig_d, eid(e));
+                oh |= (SH[q] & ~gh) | gd;
+                od |= (SD[q] & ~gd) | gh;
+            }
+            hw rh, rd, kh = 0u, kd = 0u;
+            if (r.meta & REC_EXIT) { rh = vec(c.lx_h); rd = vec(c.lx_d); }
+            else if (r.meta & REC_CALL) { rh = ~0u; rd = ~0u; }
+            else {
+                const hw rr = in(c.R, b), ww = in(c.W, b);
+                rh = dev ? (rr & fph) : rr;
+                rd = dev ? (rr & ~fph) : 0u;
+                kh = dev ? 0u : ww;
+                kd = dev ? (ww | (rr & fph)) : 0u;
+            }
+            const hw ih = in(c.ie_h, b), id = in(c.ie_d, b);
+            const hw ah = rh | (oh & ~kh), ad = rd | (od & ~kd);
+            vh = ((ah & ~ih) | id) & vm;
+            vd = ((ad & ~id) | ih) & vm;
         } else {   // PH_AVF
             hw ih, id;
             if (r.meta & REC_ENTRY) { ih = vec(c.ev_h); id = vec(c.ev_d); }
@@ -1512,8 +1601,9 @@ __device__ __forceinline__ void level_phase(const DevCfg& c, int hc, uint32_t* S
             FLG[(size_t)(fl + 1) * nb + b] = SD[b];
         }
     } else {
-        u64* h = PH == PH_NU ? c.nu_h : PH == PH_MAYP ? c.mayp_h : PH == PH_LATER ? c.later_h : c.aveout_h;
-        u64* d = PH == PH_NU ? c.nu_d : PH == PH_MAYP ? c.mayp_d : PH == PH_LATER ? c.later_d : c.aveout_d;
+        // (the refinement keeps its state in the pending-copy rows, free after the placement)
+        u64* h = PH == PH_NU ? c.nu_h : PH == PH_MAYP || PH == PH_LIVE ? c.mayp_h : PH == PH_LATER ? c.later_h : c.aveout_h;
+        u64* d = PH == PH_NU ? c.nu_d : PH == PH_MAYP || PH == PH_LIVE ? c.mayp_d : PH == PH_LATER ? c.later_d : c.aveout_d;
         for (int b = tid; b < nb; b += LV_THREADS) {
             reinterpret_cast<GAS uint32_t*>(G(h) + (size_t)b * wd + wo)[hi ? 1 : 0] = SH[b];
             reinterpret_cast<GAS uint32_t*>(G(d) + (size_t)b * wd + wo)[hi ? 1 : 0] = SD[b];
@@ -1572,6 +1662,7 @@ OMPD_LEVEL_KERNEL(ompd_k_lv_ave, PH_AVE)
 OMPD_LEVEL_KERNEL(ompd_k_lv_mayp, PH_MAYP)
 OMPD_LEVEL_KERNEL(ompd_k_lv_later, PH_LATER)
 OMPD_LEVEL_KERNEL(ompd_k_lv_avf, PH_AVF)
+OMPD_LEVEL_KERNEL(ompd_k_lv_live, PH_LIVE)
 
 // ---------------------------------------------------------------------------
 // Edge-parallel passes (no iteration): lanes over words, one wavefront per
@@ -1588,7 +1679,11 @@ OMPD_LEVEL_KERNEL(ompd_k_lv_avf, PH_AVF)
 //               map(to) = a copy into the device on p->q with no DEVICE block before p, or
 //               before q when no predecessor has one; map(from) = a copy into the host on
 //               p->q or before q when no DEVICE block follows q; alloc = used only on the device
-enum { PASS_AVE = 0, PASS_MAYP = 1, PASS_LATER = 2, PASS_AVF = 3 };
+//   PASS_LIVE : the loop-entry refinement: INS_EDGE_s(e = p->q) &= LI_s(q) on loop-entry edges
+//               (a copy whose value no read uses is dropped)
+enum { PASS_AVE = 0, PASS_MAYP = 1, PASS_LATER = 2, PASS_AVF = 3, PASS_LIVE = 4 };
+// work counter of a pass kernel
+constexpr int pass_counter(int pass) { return pass == PASS_LIVE ? 14 : 8 + pass; }
 
 template <int PASS>
 __device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int fslot, int b0)
@@ -1639,7 +1734,7 @@ __device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int f
             } else {
                 const u64 mph = row(c.mayp_h, b), mpd = row(c.mayp_d, b);
                 for (int e = SP[b]; e < SP[b + 1]; ++e) {
-                    const u64 nle = KD[e] == 2 ? 0ull : ~0ull;
+                    const u64 nle = is_le(c, KD[e]) ? 0ull : ~0ull;
                     const u64 fvh = erow(c.ig_h, e) & ~((erow(c.eag_h, e) | mph) & nle);
                     const u64 fvd = erow(c.ig_d, e) & ~((erow(c.eag_d, e) | mpd) & nle);
                     put(c.both, e, fvh & fvd);
@@ -1648,7 +1743,7 @@ __device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int f
         }
     }
     if constexpr (PASS == PASS_LATER) {
-        const bool eager = c.placement & 1;
+        const bool eager = c.placement & PL_EAGER;
         for (int q = b0; q < b1; ++q) {
             const int a = PP[q], z = PP[q + 1];
             if (eager || q == c.entry) {
@@ -1664,7 +1759,7 @@ __device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int f
             u64 allh = ~0ull, alld = ~0ull, anyh = 0, anyd = 0;
             for (int k = a; k < z; ++k) {
                 const int p = PI[k], e = PE[k];
-                const u64 le = KD[e] == 2 ? ~0ull : 0ull;
+                const u64 le = is_le(c, KD[e]) ? ~0ull : 0ull;
                 const u64 lh = erow(c.eag_h, e) | row(c.later_h, p), ld = erow(c.eag_d, e) | row(c.later_d, p);
                 const u64 bo = erow(c.both, e);
                 const u64 lph = lh & ~le, lpd = ld & ~le;
@@ -1694,10 +1789,21 @@ __device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int f
             put(c.ie_d, q, ind & ud);
             for (int k = a; k < z; ++k) {
                 const int p = PI[k], e = PE[k];
-                const u64 le = KD[e] == 2 ? ~0ull : 0ull;
+                const u64 le = is_le(c, KD[e]) ? ~0ull : 0ull;
                 const u64 lh = erow(c.eag_h, e) | row(c.later_h, p), ld = erow(c.eag_d, e) | row(c.later_d, p);
                 put(c.ig_h, e, lh & (le | ~inh) & vm);
                 put(c.ig_d, e, ld & (le | ~ind) & vm);
+            }
+        }
+    }
+    if constexpr (PASS == PASS_LIVE) {
+        for (int q = b0; q < b1; ++q) {
+            const u64 lh = row(c.mayp_h, q), ld = row(c.mayp_d, q);
+            for (int k = PP[q]; k < PP[q + 1]; ++k) {
+                const int e = PE[k];
+                if (!is_le(c, KD[e])) continue;
+                put(c.ig_h, e, erow(c.ig_h, e) & lh);
+                put(c.ig_d, e, erow(c.ig_d, e) & ld);
             }
         }
     }
@@ -1803,21 +1909,23 @@ OMPD_PHASE_KERNEL(ompd_k_ave, PH_AVE)
 OMPD_PHASE_KERNEL(ompd_k_mayp, PH_MAYP)
 OMPD_PHASE_KERNEL(ompd_k_later, PH_LATER)
 OMPD_PHASE_KERNEL(ompd_k_avf, PH_AVF)
+OMPD_PHASE_KERNEL(ompd_k_live, PH_LIVE)
 
-// Edge-parallel passes over (tile, chunk) items, claimed through counter slots 8..11.
+// Edge-parallel passes over (tile, chunk) items, claimed through counter slots 8..11 and 14.
 template <int PASS>
 __device__ __forceinline__ void pass_kernel(const DevCfg* __restrict__ cfgs, const Tile* __restrict__ tiles,
                                             const EdgeItem* __restrict__ items, int n_items, int32_t* __restrict__ counter)
 {
     for (;;) {
         int it = 0;
-        if (threadIdx.x == 0) it = atomicAdd(&counter[8 + PASS], 1);
+        if (threadIdx.x == 0) it = atomicAdd(&counter[pass_counter(PASS)], 1);
         it = __builtin_amdgcn_readfirstlane(__shfl(it, 0, 64));
         if (it >= n_items) break;
         const EdgeItem item = items[it];
         const DevCfg c = cfgs[item.cfg];
         if (G(c.info)[INFO_STATUS] != 0 || item.nw == 0) continue;
-        if ((PASS == PASS_MAYP) && (c.placement & 1)) continue;   // the eager placement needs no pending copies
+        if ((PASS == PASS_MAYP) && (c.placement & PL_EAGER)) continue;   // the eager placement needs no pending copies
+        if ((PASS == PASS_LIVE) && !refines(c.placement)) continue;
         // every solve tile's flag lane computes the same reachability facts: tile 0's columns
         edge_pass<PASS>(c, item.s0, item.nw, 0, item.b0);
     }
@@ -1834,6 +1942,7 @@ OMPD_PASS_KERNEL(ompd_k_post_ave, PASS_AVE)
 OMPD_PASS_KERNEL(ompd_k_post_mayp, PASS_MAYP)
 OMPD_PASS_KERNEL(ompd_k_post_later, PASS_LATER)
 OMPD_PASS_KERNEL(ompd_k_post_avf, PASS_AVF)
+OMPD_PASS_KERNEL(ompd_k_post_live, PASS_LIVE)
 
 // The map kinds of one tile's variables from its masks; wavefront k takes words s0 + k, s0 + k + waves, ...
 __device__ __forceinline__ void tile_varkind(const DevCfg& c, const Tile& tl, int first, int step)
@@ -1875,7 +1984,8 @@ template <int PASS>
 __device__ __forceinline__ void tile_pass(const DevCfg& c, const Tile& tl)
 {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const bool skip = G(c.info)[INFO_STATUS] != 0 || tl.nw == 0 || (PASS == PASS_MAYP && (c.placement & 1));
+    const bool skip = G(c.info)[INFO_STATUS] != 0 || tl.nw == 0 || (PASS == PASS_MAYP && (c.placement & PL_EAGER)) ||
+                      (PASS == PASS_LIVE && !refines(c.placement));
     if (!skip)
         for (int b0 = 64 * (int)(threadIdx.x >> 6); b0 < c.nb; b0 += 128) edge_pass<PASS>(c, tl.s0, tl.nw, tl.fslot, b0);
     __syncthreads();
@@ -1905,6 +2015,10 @@ extern "C" __global__ void __launch_bounds__(128) ompd_k_solve(const DevCfg* __r
         tile_pass<PASS_MAYP>(c, tl);
         tile_phase<PH_LATER>(c, tl, lds, ring_slots);
         tile_pass<PASS_LATER>(c, tl);
+        if (refines(c.placement)) {
+            tile_phase<PH_LIVE>(c, tl, lds, ring_slots);
+            tile_pass<PASS_LIVE>(c, tl);
+        }
         tile_phase<PH_AVF>(c, tl, lds, ring_slots);
         tile_pass<PASS_AVF>(c, tl);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");

@@ -26,6 +26,9 @@ extern "C" __global__ void ompd_k_post_ave(const DevCfg*, const Tile*, const Edg
 extern "C" __global__ void ompd_k_post_mayp(const DevCfg*, const Tile*, const EdgeItem*, int, int32_t*);
 extern "C" __global__ void ompd_k_post_later(const DevCfg*, const Tile*, const EdgeItem*, int, int32_t*);
 extern "C" __global__ void ompd_k_post_avf(const DevCfg*, const Tile*, const EdgeItem*, int, int32_t*);
+extern "C" __global__ void ompd_k_live(const DevCfg*, const Tile*, int, int32_t*, int);
+extern "C" __global__ void ompd_k_post_live(const DevCfg*, const Tile*, const EdgeItem*, int, int32_t*);
+extern "C" __global__ void ompd_k_lv_live(const DevCfg*, const Tile*, int, int32_t*);
 extern "C" __global__ void ompd_k_varkind(const DevCfg*, const Tile*, int, int32_t*);
 extern "C" __global__ void ompd_k_solve(const DevCfg*, const Tile*, int, int32_t*, int);
 extern "C" __global__ void ompd_k_lv_nu(const DevCfg*, const Tile*, int, int32_t*);
@@ -33,12 +36,13 @@ extern "C" __global__ void ompd_k_lv_ave(const DevCfg*, const Tile*, int, int32_
 extern "C" __global__ void ompd_k_lv_mayp(const DevCfg*, const Tile*, int, int32_t*);
 extern "C" __global__ void ompd_k_lv_later(const DevCfg*, const Tile*, int, int32_t*);
 extern "C" __global__ void ompd_k_lv_avf(const DevCfg*, const Tile*, int, int32_t*);
-static const void* const k_levels[5] = {(const void*)ompd_k_lv_nu, (const void*)ompd_k_lv_ave,
-                                        (const void*)ompd_k_lv_mayp, (const void*)ompd_k_lv_later,
-                                        (const void*)ompd_k_lv_avf};
+static const void* const k_levels[N_PHASES] = {(const void*)ompd_k_lv_nu, (const void*)ompd_k_lv_ave,
+                                               (const void*)ompd_k_lv_mayp, (const void*)ompd_k_lv_later,
+                                               (const void*)ompd_k_lv_avf, (const void*)ompd_k_lv_live};
 constexpr int LEVEL_THREADS = 256;
-static const void* const k_phases[5] = {(const void*)ompd_k_nu, (const void*)ompd_k_ave, (const void*)ompd_k_mayp,
-                                        (const void*)ompd_k_later, (const void*)ompd_k_avf};
+static const void* const k_phases[N_PHASES] = {(const void*)ompd_k_nu, (const void*)ompd_k_ave,
+                                               (const void*)ompd_k_mayp, (const void*)ompd_k_later,
+                                               (const void*)ompd_k_avf, (const void*)ompd_k_live};
 // threads of a phase workgroup: the compute and the helper wavefront
 constexpr int PHASE_THREADS = 128;
 }  // namespace ompd
@@ -109,9 +113,9 @@ extern "C" int ompd_ctx_create(ompd_ctx** out, int device_ordinal, uint64_t budg
     lds_max = std::min<size_t>(lds_max ? lds_max : 64 * 1024, 160 * 1024);
     // dynamic LDS limit per kernel = device limit minus the kernel's static LDS
     int dyn = (int)lds_max;
-    for (const void* k : {k_phases[0], k_phases[1], k_phases[2], k_phases[3], k_phases[4], (const void*)ompd_k_prep,
-                          (const void*)ompd_k_solve, k_levels[0], k_levels[1], k_levels[2], k_levels[3],
-                          k_levels[4]}) {
+    for (const void* k : {k_phases[0], k_phases[1], k_phases[2], k_phases[3], k_phases[4], k_phases[5],
+                          (const void*)ompd_k_prep, (const void*)ompd_k_solve, k_levels[0], k_levels[1], k_levels[2],
+                          k_levels[3], k_levels[4], k_levels[5]}) {
         hipFuncAttributes fa{};
         int st = 0;
         if (hipFuncGetAttributes(&fa, k) == hipSuccess) st = (int)fa.sharedSizeBytes;
@@ -264,7 +268,8 @@ void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const
     d.wait_ticks = wait_ticks > 0 ? wait_ticks : 1;
     d.nb = g.n_blocks; d.ne = g.n_edges; d.nv = g.n_vars; d.entry = g.entry; d.exit = g.exit; d.wd = wd;
     d.n_sums = g.call_summary ? g.n_summaries : 0;
-    d.placement = ((flags & OMPD_F_PLACEMENT_EAGER) ? 1 : 0) | ((flags & OMPD_F_SUMMARY) ? 2 : 0);
+    d.placement = ((flags & OMPD_F_PLACEMENT_EAGER) ? PL_EAGER : 0) | ((flags & OMPD_F_SUMMARY) ? PL_SUMMARY : 0) |
+                  ((flags & OMPD_F_PLACEMENT_LAZY) ? PL_LAZY : 0) | ((flags & OMPD_F_PLACEMENT_REFINE) ? PL_REFINE : 0);
     d.sweep_cap = (int)((flags >> 16) & 0xFFFFu);
     d.sched = (flags & OMPD_F_SCHED_LEVEL) ? SCHED_LEVEL
             : (flags & OMPD_F_SCHED_WALK) ? SCHED_WALK
@@ -377,7 +382,7 @@ int ompd_make_shape(ompd_ctx* ctx, const std::vector<DevCfg>& cfgs, const PlanCo
     dm.ring_slots = rs;
     sh.lds_prep = 0;
     // each phase kernel: as many workgroups as it keeps resident
-    for (int ph = 0; ph < 5; ++ph) {
+    for (int ph = 0; ph < N_PHASES; ++ph) {
         dm.lds[ph] = phase_lds(ph, rs);
         int n = 0;
         CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_phases[ph], PHASE_THREADS, dm.lds[ph]));
@@ -387,7 +392,9 @@ int ompd_make_shape(ompd_ctx* ctx, const std::vector<DevCfg>& cfgs, const PlanCo
     }
     dm.split = pc.split;
     dm.lds_tile = 0;
-    for (int ph = 0; ph < 5; ++ph) dm.lds_tile = std::max(dm.lds_tile, dm.lds[ph]);
+    for (int ph = 0; ph < N_PHASES; ++ph) dm.lds_tile = std::max(dm.lds_tile, dm.lds[ph]);
+    dm.refine = false;
+    for (int i = 0; i < (int)cfgs.size(); ++i) dm.refine |= in_plan(i) && refines(cfgs[i].placement);
     {
         int n = 0;
         CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)ompd_k_solve, PHASE_THREADS, dm.lds_tile));
@@ -557,35 +564,36 @@ int ompd_launch_solve(const DevCfg* d_cfgs, const Tile* d_tiles, int n_tiles, co
                                                 hipGetErrorString(e));
         return OMPD_OK;
     }
-    int ph = 0;
-    auto phase = [&](const void* fn) {
-        if (n_tiles > 0) {
+    // (a phase or pass that no CFG needs is not launched; its profile mark is still taken)
+    auto phase = [&](int ph, bool launch) {
+        if (launch && n_tiles > 0) {
             void* args[] = {(void*)&d_cfgs, (void*)&d_tiles, (void*)&n_tiles, (void*)&d_counter, (void*)&rs};
-            (void)hipLaunchKernel(fn, dim3(dm.grid[ph]), dim3(PHASE_THREADS), args, dm.lds[ph], s);
+            (void)hipLaunchKernel(k_phases[ph], dim3(dm.grid[ph]), dim3(PHASE_THREADS), args, dm.lds[ph], s);
         }
-        if (n_level > 0) {
+        if (launch && n_level > 0) {
             void* args[] = {(void*)&d_cfgs, (void*)&d_ltiles, (void*)&n_level, (void*)&d_counter};
             (void)hipLaunchKernel(k_levels[ph], dim3(dm.grid_level), dim3(LEVEL_THREADS), args, dm.lds_level, s);
         }
-        ++ph;
         mark();
     };
-    auto pass = [&](const void* fn) {
-        if (n_items > 0) {
+    auto pass = [&](const void* fn, bool launch) {
+        if (launch && n_items > 0) {
             void* args[] = {(void*)&d_cfgs, (void*)&d_tiles, (void*)&d_items, (void*)&n_items, (void*)&d_counter};
             (void)hipLaunchKernel(fn, dim3(grid_edge), dim3(64), args, 0, s);
         }
         mark();
     };
-    phase((const void*)ompd_k_nu);
-    phase((const void*)ompd_k_ave);
-    pass((const void*)ompd_k_post_ave);
-    phase((const void*)ompd_k_mayp);
-    pass((const void*)ompd_k_post_mayp);
-    phase((const void*)ompd_k_later);
-    pass((const void*)ompd_k_post_later);
-    phase((const void*)ompd_k_avf);
-    pass((const void*)ompd_k_post_avf);
+    phase(PH_NU, true);
+    phase(PH_AVE, true);
+    pass((const void*)ompd_k_post_ave, true);
+    phase(PH_MAYP, true);
+    pass((const void*)ompd_k_post_mayp, true);
+    phase(PH_LATER, true);
+    pass((const void*)ompd_k_post_later, true);
+    phase(PH_LIVE, dm.refine);
+    pass((const void*)ompd_k_post_live, dm.refine);
+    phase(PH_AVF, true);
+    pass((const void*)ompd_k_post_avf, true);
     hipLaunchKernelGGL(ompd_k_varkind, dim3(grid_edge), dim3(64), 0, s, d_cfgs, d_tiles, n_tiles, d_counter);
     mark();
     hipError_t e = hipGetLastError();
