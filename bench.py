@@ -100,6 +100,13 @@ def load_tuned():
         return {}
 
 
+def apply_tuned(plan, c):
+    """Apply a stored autotuner choice: the schedule per size bucket, then the launch configuration."""
+    if "bucket_sched" in c:
+        plan.set_schedule(c["bucket_sched"])
+    plan.configure(c["lds_bytes"], c["wg_per_cu"])
+
+
 def save_tuned(d):
     with open(TUNED, "w") as f:
         json.dump(d, f, indent=1, sort_keys=True)
@@ -336,14 +343,13 @@ def main():
         t = time.perf_counter()
         best = rb.plan.autotune(stream, trials=2)
         d = json.loads(rb.plan.describe())
-        tuned[key] = {k: d[k] for k in ("lds_bytes", "wg_per_cu")}
+        tuned[key] = {k: d[k] for k in ("lds_bytes", "wg_per_cu", "bucket_sched")}
         tuned[key]["best_ms"] = best
         save_tuned(tuned)
         log("autotune: best %.3f ms in %.1f s -> %s" % (best, time.perf_counter() - t, rb.plan.describe()))
     elif key in tuned:
-        c = tuned[key]
-        rb.plan.configure(c["lds_bytes"], c["wg_per_cu"])
-        log("using the stored autotuner choice %s" % c)
+        apply_tuned(rb.plan, tuned[key])
+        log("using the stored autotuner choice %s" % tuned[key])
     for _ in range(args.warmup):
         rb.run(stream)
         st = rb.plan.status()
@@ -452,14 +458,13 @@ def main():
     if not args.no_single:
         c2 = synth.c2(0)
         sb = ResidentBatch(ctx, [c2], want=want)
-        if "single" in tuned:
-            c = tuned["single"]
-            sb.plan.configure(c["lds_bytes"], c["wg_per_cu"])
-        elif args.autotune:
+        if args.autotune:
             sb.plan.autotune(stream, trials=1)
             d = json.loads(sb.plan.describe())
-            tuned["single"] = {k: d[k] for k in ("lds_bytes", "wg_per_cu")}
+            tuned["single"] = {k: d[k] for k in ("lds_bytes", "wg_per_cu", "bucket_sched")}
             save_tuned(tuned)
+        elif "single" in tuned:
+            apply_tuned(sb.plan, tuned["single"])
         for _ in range(2):
             sb.run(stream)
         torch.cuda.synchronize()

@@ -913,6 +913,16 @@ extern "C" int ompd_plan_autotune(ompd_plan* p, void* stream, int32_t trials, fl
             base.bucket_sched[b] = pick;
         }
     }
+    // the buckets were timed alone, where the lower latency wins; on the whole plan the throughput
+    // may favour the default rule instead: keep whichever runs the plan faster
+    if (!(p->flags & (OMPD_F_SCHED_LEVEL | OMPD_F_SCHED_WALK))) {
+        PlanConfig rule = base;
+        for (int b = 0; b < OMPD_SCHED_BUCKETS; ++b) rule.bucket_sched[b] = -1;
+        float t_pick = 0, t_rule = 0;
+        if (time_config(p, base, s, trials, t_pick) == OMPD_OK && time_config(p, rule, s, trials, t_rule) == OMPD_OK &&
+            t_rule < t_pick)
+            base = rule;
+    }
     // 2. the launch configuration of the whole plan with those schedules
     PlanConfig best = base;
     float best_t = 1e30f;
