@@ -15,6 +15,9 @@ enum : int32_t {
     // the value awaited, and the wall-clock ticks waited
     INFO_PM_PHASE = 8, INFO_PM_TILE = 9, INFO_PM_WHAT = 10, INFO_PM_SEEN = 11, INFO_PM_TARGET = 12,
     INFO_PM_TICKS = 13,
+    // 1: the walk follows the block ids; 0: it follows lorder (positions in loff), written by the
+    // ingest kernel when some edge other than BACK goes from a higher to a lower id
+    INFO_ORDER = 14,
     INFO_WORDS = 16
 };
 
@@ -142,7 +145,10 @@ inline int tiles_of(int wd) { return wd <= 0 ? 1 : (wd + TILE_WORDS - 1) / TILE_
 // steps (phase_inputs(ph) words of WORD_BYTES each), their 16-byte
 // descriptors, then one state of identity words (STATE_BYTES).
 constexpr int CTL_BYTES = 256;
-constexpr int LDS_FIXED = CTL_BYTES;
+// then the blocks of the last BLK_RING planned steps (the helper stores results by them; at least
+// the result ring plus the input ring, so that an entry is not reused before its step is stored)
+constexpr int BLK_RING = 128;
+constexpr int LDS_FIXED = CTL_BYTES + 4 * BLK_RING;
 // steps of inputs kept ready per phase (a power of two; more for the phases with fewer inputs).
 // The helper wavefront refills them in rounds whose fixed cost is spread over the steps it
 // finds free, so a deeper ring means fewer, longer rounds.

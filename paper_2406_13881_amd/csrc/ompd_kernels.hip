@@ -79,10 +79,12 @@ __device__ __forceinline__ bool is_le(const DevCfg& c, uint8_t k) { return k == 
 // 0 and 1 (bits 0-7, 8-15; flag code 2 only); z the far neighbour; w how many steps before the
 // current one its state was computed (this sweep's or, when SF_BACK, the previous sweep's); then
 // the block, the edge ids of neighbours 0 and 1 (0 when missing) and an unused word.
-// The step entry of the block b at walk position i, from its record r0 / r1 (ring of rs slots).
+// The step entry of the block b at walk position i, from its record r0 / r1 (ring of rs slots);
+// pos: each block's position in the forward walk (NULL: its id).
 __device__ __forceinline__ void make_step(const int4& r0, const int4& r1, int b, bool bwd, int nb, int rs,
-                                          int4& t0, int4& t1)
+                                          const int32_t* pos, int4& t0, int4& t1)
 {
+    const int pb = pos ? pos[b] : b;
     const uint32_t meta = (uint32_t)r0.x, e0 = (uint32_t)r0.w, e1 = (uint32_t)r1.x;
     const int cnt = (int)(meta & REC_COUNT);
     uint32_t fl = (cnt > 2 || cnt == 0 || (meta & (REC_ENTRY | REC_EXIT | REC_CALL))) ? DF_SLOW : 0u;
@@ -94,7 +96,8 @@ __device__ __forceinline__ void make_step(const int4& r0, const int4& r1, int b,
     bool far = false;
     for (int j = 0; j < 2 && j < cnt; ++j) {
         const int p = j == 0 ? r0.y : r0.z;
-        const int d = bwd ? p - b : b - p;   // 1: the block just before in the walk
+        const int pp = pos ? pos[p] : p;
+        const int d = bwd ? pp - pb : pb - pp;   // 1: the block just before in the walk
         uint32_t k;
         if (d == 1) k = 1;
         else if (d >= 2 && d <= rs) { k = 2; dd |= d << (8 * j); }
@@ -281,10 +284,27 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
         RB[2 * b + 1] = r1;
     }
     __syncthreads();
-    // levels (level schedule only): peel the graph from ENTRY over the edges other than BACK;
-    // the blocks of a round form a level.  Blocks left over (a cycle closed by an edge not marked
+    // Walk order (walk schedule): the caller's ids when every edge other than BACK goes from a
+    // lower to a higher id (the source order a front end emits; the sweeps then converge in loop
+    // depth + 2), else the order of the peel below, in which every such edge goes forward too;
+    // then lorder[i] is the block at forward walk position i and loff[b] the position of block b.
+    // Levels (level schedule): peel the graph from ENTRY over the edges other than BACK; the
+    // blocks of a round form a level.  Blocks left over (a cycle closed by an edge not marked
     // BACK, or unreachable ones, which the validity phase rejects) get a level each, in id order.
-    if (c.sched == SCHED_LEVEL) {
+    const bool lv = c.sched == SCHED_LEVEL;
+    __shared__ int s_unord;
+    if (tid == 0) s_unord = 0;
+    __syncthreads();
+    if (!lv) {
+        int un = 0;
+        for (int b = tid; b < nb; b += nt)
+            for (int e = c.succ_ptr[b]; e < c.succ_ptr[b + 1]; ++e)
+                if (c.kind[e] != 1 && c.succ_idx[e] <= b) un = 1;
+        if (un) atomicOr(&s_unord, 1);
+        __syncthreads();
+    }
+    const bool unord = s_unord != 0;
+    if (lv || unord) {
         __shared__ int s_tail;
         int32_t* deg = c.tmp;
         for (int b = tid; b < nb; b += nt) {
@@ -296,7 +316,7 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
         __syncthreads();
         int fa = 0, fb = 1, nl = 0;
         while (fa < fb) {
-            if (tid == 0) c.loff[nl] = fa;
+            if (tid == 0 && lv) c.loff[nl] = fa;
             for (int i = fa + tid; i < fb; i += nt) {
                 const int b = c.lorder[i];
                 for (int e = c.succ_ptr[b]; e < c.succ_ptr[b + 1]; ++e) {
@@ -319,28 +339,40 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
             if (tid == 0) {
                 int n = fb;
                 for (int b = 0; b < nb; ++b)
-                    if (deg[b] != -1) { c.lorder[n] = b; c.loff[nl++] = n; ++n; }
+                    if (deg[b] != -1) {
+                        c.lorder[n] = b;
+                        if (lv) c.loff[nl] = n;
+                        ++nl;
+                        ++n;
+                    }
                 s_n = nl;
             }
             __syncthreads();
             nl = s_n;
         }
         if (tid == 0) {
-            c.loff[nl] = nb;
-            c.info[INFO_LEVELS] = nl;
+            if (lv) c.loff[nl] = nb;
+            c.info[INFO_LEVELS] = lv ? nl : 0;
         }
         __syncthreads();
+        if (!lv)
+            for (int i = tid; i < nb; i += nt) c.loff[c.lorder[i]] = i;
+        __syncthreads();
     }
-    // step entries in walk order: position i is block i forward, block nb - 1 - i backward
+    if (tid == 0) c.info[INFO_ORDER] = lv || !unord;
+    // step entries in walk order: forward position i is block i (or lorder[i]), backward position i
+    // the block at forward position nb - 1 - i
     int4* SF = reinterpret_cast<int4*>(c.step_f);
     int4* SB = reinterpret_cast<int4*>(c.step_b);
+    const int32_t* pos = (!lv && unord) ? c.loff : nullptr;
     for (int i = tid; i < nb; i += nt) {
         int4 t0, t1;
-        make_step(RF[2 * i], RF[2 * i + 1], i, false, nb, ring_slots, t0, t1);
+        const int bf = pos ? c.lorder[i] : i;
+        make_step(RF[2 * bf], RF[2 * bf + 1], bf, false, nb, ring_slots, pos, t0, t1);
         SF[2 * i] = t0;
         SF[2 * i + 1] = t1;
-        const int b = nb - 1 - i;
-        make_step(RB[2 * b], RB[2 * b + 1], b, true, nb, ring_slots, t0, t1);
+        const int bb = pos ? c.lorder[nb - 1 - i] : nb - 1 - i;
+        make_step(RB[2 * bb], RB[2 * bb + 1], bb, true, nb, ring_slots, pos, t0, t1);
         SB[2 * i] = t0;
         SB[2 * i + 1] = t1;
     }
@@ -547,7 +579,10 @@ struct Rows {
     }
 };
 
-template <int PH>
+// IDORD: the walk follows the block ids (position = id); else the ingest kernel's order, with the
+// block of each planned step kept in LDS and positions in loff (two instantiations, so that the
+// common case carries nothing extra).
+template <int PH, bool IDORD>
 __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int fslot, u64* lds, int RS)
 {
     constexpr bool with_flags = PH == PH_NU || PH == PH_AVE;   // phases with the flag lane
@@ -580,7 +615,9 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     char* lds8 = reinterpret_cast<char*>(lds);
     // the same as a wave-uniform 32-bit LDS address (scalar registers)
     const uint32_t lds3 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(size_t)(LDS3 char*)lds8);
-    constexpr int RING_OFF = CTL_BYTES;                                   // RS states: the last results
+    static_assert(BLK_RING >= 64 + 32, "block ring: result ring plus input ring");
+    int* blkr = reinterpret_cast<int*>(lds8 + CTL_BYTES);                 // blocks of the last planned steps
+    constexpr int RING_OFF = LDS_FIXED;                                   // RS states: the last results
     const int IN_OFF = RING_OFF + RS * STATE_BYTES;                       // IR steps of NI input words
     const int DESC_OFF = IN_OFF + IR * NI * WORD_BYTES;                   // IR step descriptors
     const int IDENT_OFF = DESC_OFF + IR * 16;                             // one state of identity words
@@ -644,8 +681,12 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
         return SI[r.ovf + j];
     };
     // distance of neighbour p from block b in walk order (1 = the block just before)
-    auto dist = [&](int b, int p) -> int { return BWD ? (p - b) : (b - p); };
-    auto blk = [&](int i) -> int { return BWD ? nb - 1 - i : i; };
+    auto dist = [&](int b, int p) -> int {
+        int pb = b, pp = p;
+        if constexpr (!IDORD) { pb = K(c.loff)[b]; pp = K(c.loff)[p]; }
+        return BWD ? (pp - pb) : (pb - pp);
+    };
+    auto blk = [&](int i) -> int { return BWD ? nb - 1 - i : i; };   // (IDORD)
     // At compute time a neighbour at distance 1 is in registers and one at 2..RS in the ring;
     // the first other one ("far": not yet visited in this sweep, or more than RS steps back)
     // comes with the step's inputs.
@@ -666,7 +707,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     };
     auto helper_loop = [&](const Rows& S, u64 init64, auto&& pre) {
         const hw init = (hw)(hi ? init64 >> 32 : init64);
-        int gf = 0, fi = 0;   // next step to store and its index within the sweep
+        int gf = 0, fi = 0;   // next step to store and its walk position within the sweep
         int pf = 0, pi = 0;   // next step whose inputs are loaded and its index within the sweep
         uint64_t idle_since = 0;   // wall clock when the helper last found nothing to do (0: busy)
         // Lane j plans step pf + j (walk position pi + j): its step entry is loaded by the lane
@@ -704,7 +745,8 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
                 dd |= (k0 == 1 ? 1u << DD_LAST0 : 0u) | (k1 == 1 ? 1u << DD_LAST1 : 0u);
                 dd |= (k0 ? 1u << DD_P0 : 0u) | (k1 ? 1u << DD_P1 : 0u);
                 dd |= (k0 && !(fl & DF_LE0) ? 1u << DD_A0 : 0u) | (k1 && !(fl & DF_LE1) ? 1u << DD_A1 : 0u);
-                dring[st & (IR - 1)] = make_int4((int)dd, loc0, loc1, 0);
+                dring[st & (IR - 1)] = make_int4((int)dd, loc0, loc1, IDORD ? 0 : xv.x);
+                if constexpr (!IDORD) blkr[st & (BLK_RING - 1)] = xv.x;
             }
             // far states from the ring (computed, not stored yet) or the initial value
             for (u64 cm = __ballot(lane < n && (fl & SF_FAR) && (u < 0 || u >= gf0)); cm; cm &= cm - 1) {
@@ -745,7 +787,11 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
                     if (gf < fend) {
-                        if (act) S.st32(blk(fi), hi, h[t], d[t]);
+                        // the block of the step: its walk position, else as planned
+                        int b;
+                        if constexpr (IDORD) b = blk(fi);
+                        else b = __builtin_amdgcn_readfirstlane(blkr[gf & (BLK_RING - 1)]);
+                        if (act) S.st32(b, hi, h[t], d[t]);
                         fi = fi + 1 == nb ? 0 : fi + 1;
                         ++gf;
                     }
@@ -890,7 +936,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             if (!(fl & DF_SLOW)) fast(x, vh_, vd_, fl, vh, vd);
             else {
                 // any block: neighbour values by the general rule, then the full transfer
-                const int b = blk(i);
+                const int b = IDORD ? blk(i) : __builtin_amdgcn_readfirstlane(dring[g & (IR - 1)].w);
                 const Rec r = ldrec(REC, b);
                 const int cnt = (int)(r.meta & REC_COUNT);
                 bool far_used = false;
@@ -1868,8 +1914,13 @@ __device__ __forceinline__ void tile_phase(const DevCfg& c, const Tile& tl, u64*
         return;
     }
     // a CFG on the level schedule is solved by the level kernels; lanes past 2 LANES hold no word
-    if (c.sched != SCHED_LEVEL && (threadIdx.x & 63) < 2 * LANES)
-        solve_phase<PH>(c, tl.s0, tl.nw, tl.fslot, lds, ring_slots);
+    // (the walk order the ingest kernel chose: the block ids, or its own)
+    if (c.sched != SCHED_LEVEL && (threadIdx.x & 63) < 2 * LANES) {
+        if (__builtin_amdgcn_readfirstlane(G(c.info)[INFO_ORDER]))
+            solve_phase<PH, true>(c, tl.s0, tl.nw, tl.fslot, lds, ring_slots);
+        else
+            solve_phase<PH, false>(c, tl.s0, tl.nw, tl.fslot, lds, ring_slots);
+    }
     __syncthreads();
 }
 

@@ -107,6 +107,27 @@ def test_config3_items_permuted_ids(ctx):
         assert_same(cfg, got[i], refs[i], "c3 permuted item %d" % picks[i])
 
 
+def test_permuted_ids_keep_the_sweep_count(ctx):
+    """With shuffled block ids the ingest kernel walks in its own order (every edge other than
+    BACK forward), so the sweeps per phase stay those of the source order instead of growing
+    with the number of blocks; the outputs equal the oracle's.  The largest config-3 items and
+    the config-2 procedure, on the walk."""
+    import paper_2406_13881_amd as ompd
+    nbs, _ = synth.c3_sizes()
+    big = [int(i) for i in np.argsort(nbs)[-3:]]
+    base = [synth.c3_item(i) for i in big] + [synth.c2()]
+    perm = [synth.permute_blocks(c, 70_000 + k)[0] for k, c in enumerate(base)]
+    _print("permuted, walk: blocks %s" % [c.n_blocks for c in base])
+    a = ctx.analyze_batch(base, flags=ompd.F_SCHED_WALK)
+    b = ctx.analyze_batch(perm, flags=ompd.F_SCHED_WALK)
+    refs = _oracle_many(perm)
+    for k, cfg in enumerate(perm):
+        assert_same(cfg, b[k], refs[k], "permuted #%d" % k)
+        sa, sb = np.asarray(a[k]["sweeps"][:5]), np.asarray(b[k]["sweeps"][:5])
+        _print("sweeps in id order %s, shuffled %s" % (sa.tolist(), sb.tolist()))
+        assert (sb <= 2 * sa + 2).all(), (sa.tolist(), sb.tolist())
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_random_dags_with_loop_entries(ctx, seed):
     rng = np.random.Generator(np.random.PCG64(77 + seed))
