@@ -45,6 +45,20 @@ problems of ``oracle.c``:
 External callees (index -1): may read and write every global on the host,
 need every global on the host on entry, leave the host copy valid and the
 device copy stale.
+
+Two refinements of the model (the interprocedural section: accesses on the
+host or the device, and the read-only rule for data behind a pointer to
+``const``):
+
+* A call made inside a kernel (``call_space[j] = 1``, a device function) runs
+  on the device: the call block is a DEVICE block that reads every global
+  the callee may read or write (in either space) and writes every global it
+  may write; such a call gets no context of its own (a device function
+  carries no mapping directives) and no summary table.  An external device
+  function may read and write every global.
+* Globals marked ``const_globals`` are never written: no block may write
+  them, and an external callee neither writes them nor leaves their device
+  copy stale.
 """
 from __future__ import annotations
 
@@ -128,13 +142,15 @@ class Summary:
         self.rows = np.zeros((SUM_ROWS, gw), np.uint64)
 
 
-def external_summary(gm: np.ndarray) -> np.ndarray:
+def external_summary(gm: np.ndarray, const=None) -> np.ndarray:
+    c = np.zeros(gm.size, np.uint64) if const is None else (np.asarray(const, np.uint64)[:gm.size] & gm)
     r = np.zeros((SUM_ROWS, gm.size), np.uint64)
-    for k in (SUM_MAYR_H, SUM_MAYW_H, SUM_NU0_H, SUM_NU1_H, SUM_NU1_D):
+    for k in (SUM_MAYR_H, SUM_NU0_H, SUM_NU1_H, SUM_NU1_D):
         r[k] = gm
+    r[SUM_MAYW_H] = gm & ~c                 # a const global is never written
     for k in range(4):
-        r[SUM_TH_00 + k] = gm       # host copy valid after the call
-        r[SUM_TD_00 + k] = 0        # device copy stale after the call
+        r[SUM_TH_00 + k] = gm               # host copy valid after the call
+        r[SUM_TD_00 + k] = c if k >= 2 else 0   # device copy stale after the call, but a const one kept
     return r
 
 
@@ -146,9 +162,23 @@ class ProgramOracle:
         self.placement = placement
         self.n = len(prog.procs)
         self.G = prog.n_globals
-        self.sites: List[List[int]] = [[] for _ in range(self.n)]      # call-site ids per caller
-        for j in range(len(prog.call_proc)):
-            self.sites[int(prog.call_proc[j])].append(j)
+        gw = (self.G + 63) // 64
+        nc = len(prog.call_proc)
+        cs = getattr(prog, "call_space", None)
+        self.call_space = np.zeros(nc, np.uint8) if cs is None else np.asarray(cs, np.uint8)
+        cg = getattr(prog, "const_globals", None)
+        self.const = np.zeros(gw, np.uint64) if cg is None else (np.asarray(cg, np.uint64)[:gw] & _gmask(self.G, gw))
+        self.sites: List[List[int]] = [[] for _ in range(self.n)]      # host call-site ids per caller
+        self.dsites: List[List[int]] = [[] for _ in range(self.n)]     # device call-site ids per caller
+        for j in range(nc):
+            P, b = int(prog.call_proc[j]), int(prog.call_block[j])
+            dev = bool(self.call_space[j])
+            if int(prog.procs[P].space[b]) != int(dev):
+                raise ValueError("call site %d: its block's space is not the call's" % j)
+            (self.dsites if dev else self.sites)[P].append(j)
+        for P, c in enumerate(prog.procs):
+            if (np.asarray(c.W, np.uint64)[:, :gw] & self.const).any():
+                raise ValueError("procedure %d writes a const global" % P)
         self.demand: Dict[int, np.ndarray] = {}                          # call site -> host-read mask (caller words)
         self.cap: Dict[tuple, Tuple[np.ndarray, np.ndarray]] = {}        # callee context -> (host, device) validity at EXIT
         self.sum_rows: Dict[int, np.ndarray] = {}
@@ -167,7 +197,7 @@ class ProgramOracle:
         for k, j in enumerate(self.sites[P]):
             call[int(self.p.call_block[j])] = k
             q = int(self.p.callee[j])
-            rows = external_summary(_gmask(self.G, gw)) if q < 0 else summaries[q]
+            rows = external_summary(_gmask(self.G, gw), self.const) if q < 0 else summaries[q]
             s = np.zeros((SUM_ROWS, wd), np.uint64)
             s[:, :gw] = rows
             s &= gm
@@ -186,21 +216,35 @@ class ProgramOracle:
             sums[k] = s
         return call, sums
 
-    def _cfg_with_demands(self, P: int):
+    def _cfg_with_demands(self, P: int, S):
+        """P's read and write rows with the host reads demanded at its call blocks and, at each
+        device call block, the callee's may-read and may-write globals (either space)."""
         cfg = self.p.procs[P]
-        R = cfg.R
+        R, W = cfg.R, cfg.W
         dem = [(int(self.p.call_block[j]), self.demand[j]) for j in self.sites[P] if j in self.demand]
-        if dem:
-            R = R.copy()
+        if dem or self.dsites[P]:
+            R, W = R.copy(), W.copy()
             for blk, m in dem:
                 R[blk] |= m
-        return cfg, R
+            gw = (self.G + 63) // 64
+            gm = _gmask(self.G, gw)
+            for j in self.dsites[P]:
+                q, blk = int(self.p.callee[j]), int(self.p.call_block[j])
+                if q < 0:
+                    rd, wr = gm, gm & ~self.const
+                else:
+                    rows = S[q]
+                    wr = rows[SUM_MAYW_H] | rows[SUM_MAYW_D]
+                    rd = rows[SUM_MAYR_H] | rows[SUM_MAYR_D] | wr
+                R[blk, :gw] |= rd & gm
+                W[blk, :gw] |= wr & gm
+        return cfg, R, W
 
     def _solve(self, P, summaries, boundary, summary_mode=False, sigma=None):
-        cfg, R = self._cfg_with_demands(P)
+        cfg, R, W = self._cfg_with_demands(P, summaries)
         call, sums = self._caller_tables(P, summaries, sigma)
         view = type(cfg)(n_blocks=cfg.n_blocks, n_vars=cfg.n_vars, succ_ptr=cfg.succ_ptr, succ_idx=cfg.succ_idx,
-                         edge_kind=cfg.edge_kind, space=cfg.space, R=R, W=cfg.W, entry=cfg.entry, exit=cfg.exit)
+                         edge_kind=cfg.edge_kind, space=cfg.space, R=R, W=W, entry=cfg.entry, exit=cfg.exit)
         self.visits += 1
         res = solve(view, placement=(SUMMARY_MODE if summary_mode else 0) | self.placement,
                     call=call if self.sites[P] else None, sums=sums if self.sites[P] else None,
@@ -217,6 +261,7 @@ class ProgramOracle:
             if q >= 0:
                 succ[int(self.p.call_proc[j])].append(q)
         comps = tarjan(n, succ)
+        # a component is recursive when it has several members or a call to itself
         S: Dict[int, np.ndarray] = {}
         for comp in comps:
             if len(comp) == 1 and comp[0] not in succ[comp[0]]:
@@ -231,7 +276,17 @@ class ProgramOracle:
                     r[SUM_TH_00 + k] = _gmask(G, gw)
                     r[SUM_TD_00 + k] = _gmask(G, gw)
                 S[q] = r
-            # next use from 0, then validity tables from all-ones, then may bits from 0
+            # may bits from 0 (device calls read them into the callers' rows), then next use
+            # from 0, then validity tables from all-ones
+            while True:
+                changed = False
+                for q in comp:
+                    m = self._may(q, S)
+                    if not np.array_equal(S[q][:4], m):
+                        S[q][:4] = m
+                        changed = True
+                if not changed:
+                    break
             for stage in ("nu", "t"):
                 while True:
                     changed = False
@@ -244,15 +299,6 @@ class ProgramOracle:
                             changed = True
                     if not changed:
                         break
-            while True:
-                changed = False
-                for q in comp:
-                    m = self._may(q, S)
-                    if not np.array_equal(S[q][:4], m):
-                        S[q][:4] = m
-                        changed = True
-                if not changed:
-                    break
         self.sum_rows = S
         return S
 
@@ -280,20 +326,20 @@ class ProgramOracle:
         return out
 
     def _may(self, Q: int, S) -> np.ndarray:
-        cfg, R = self._cfg_with_demands(Q)
+        cfg, R, W = self._cfg_with_demands(Q, S)
         gw = (self.G + 63) // 64
         gm = _gmask(self.G, gw)
         m = np.zeros((4, gw), np.uint64)
         dev = np.asarray(cfg.space) == 1
         if (~dev).any():
             m[0] = np.bitwise_or.reduce(R[~dev][:, :gw], axis=0)
-            m[2] = np.bitwise_or.reduce(cfg.W[~dev][:, :gw], axis=0)
+            m[2] = np.bitwise_or.reduce(W[~dev][:, :gw], axis=0)
         if dev.any():
             m[1] = np.bitwise_or.reduce(R[dev][:, :gw], axis=0)
-            m[3] = np.bitwise_or.reduce(cfg.W[dev][:, :gw], axis=0)
+            m[3] = np.bitwise_or.reduce(W[dev][:, :gw], axis=0)
         for j in self.sites[Q]:
             q = int(self.p.callee[j])
-            rows = external_summary(gm) if q < 0 else S[q]
+            rows = external_summary(gm, self.const) if q < 0 else S[q]
             m |= rows[:4]
         return m & gm
 

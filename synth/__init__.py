@@ -414,6 +414,8 @@ class Program:
     call_block: np.ndarray
     callee: np.ndarray
     roots: List[int]
+    call_space: Optional[np.ndarray] = None      # [n_calls] 1: the call runs on the device (None: all host)
+    const_globals: Optional[np.ndarray] = None   # [words of globals] globals never written (None: none)
 
 
 C4 = dict(n_procs=2000, n_globals=256, n_locals=16, blocks=(32, 1024), mean_calls=3.0, max_calls=8,
@@ -424,13 +426,17 @@ def program(seed: int, n_procs: int = 2000, n_globals: int = 256, n_locals: int 
             blocks: Tuple[int, int] = (32, 1024), mean_calls: float = 3.0, max_calls: int = 8,
             scc_procs: int = 100, scc_size: Tuple[int, int] = (2, 8), max_loop_depth: int = 3,
             device_frac: float = 0.30, p_read: float = 0.2, p_write: float = 0.1,
-            external_frac: float = 0.0, threads: int = 0) -> Program:
+            external_frac: float = 0.0, threads: int = 0, device_call_frac: float = 0.0,
+            n_const: int = 0) -> Program:
     """A random call graph: procedure i calls Poisson(mean_calls) (at most
     max_calls) procedures of higher index; then scc_procs procedures are
     grouped into cycles of U{scc_size} members (a call from each member to the
     next), which makes recursive SCCs.  Procedure 0 and every procedure that
-    nobody calls are roots.  Each procedure is a structured CFG whose call
-    sites are distinct host statements."""
+    no host call reaches are roots.  Each procedure is a structured CFG whose
+    call sites are distinct host statements; a seeded fraction
+    device_call_frac of them become calls made inside a kernel (their block
+    turns DEVICE), and n_const seeded globals become const (every write of
+    them is removed)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     calls: List[List[int]] = [[] for _ in range(n_procs)]
     for i in range(n_procs - 1):
@@ -485,10 +491,31 @@ def program(seed: int, n_procs: int = 2000, n_globals: int = 256, n_locals: int 
             cp.append(i)
             cb.append(int(blk))
             ce.append(calls[i][j])
-    called = set(x for x in ce if x >= 0)
+    cs = np.zeros(len(cp), np.uint8)
+    if device_call_frac > 0:
+        pick = rng.random(len(cp)) < device_call_frac
+        for j in np.nonzero(pick)[0]:
+            c = procs[cp[j]]
+            c.space = np.array(c.space, np.uint8)
+            c.space[cb[j]] = 1
+            cs[j] = 1
+    gw = words(n_globals)
+    const = np.zeros(gw, np.uint64)
+    if n_const > 0:
+        for v in rng.choice(n_globals, size=min(n_const, n_globals), replace=False):
+            const[int(v) >> 6] |= np.uint64(1 << (int(v) & 63))
+        for c in procs:
+            W = np.array(c.W, np.uint64).reshape(c.n_blocks, c.wd)
+            W[:, :gw] &= ~const
+            c.W = W
+    # roots: procedure 0 and every procedure no host call reaches (a procedure called only from
+    # kernels is a device function and gets no context of its own)
+    called = set(x for x, d in zip(ce, cs) if x >= 0 and not d)
     roots = sorted(set([0]) | set(i for i in range(n_procs) if i not in called))
     return Program(procs=procs, n_globals=n_globals, call_proc=np.array(cp, np.int32),
-                   call_block=np.array(cb, np.int32), callee=np.array(ce, np.int32), roots=roots)
+                   call_block=np.array(cb, np.int32), callee=np.array(ce, np.int32), roots=roots,
+                   call_space=cs if device_call_frac > 0 else None,
+                   const_globals=const if n_const > 0 else None)
 
 
 def c4(n_procs: int = 2000, **kw) -> Program:

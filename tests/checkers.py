@@ -429,7 +429,11 @@ def simulate_program(prog, ctx, results, demands: Dict[int, np.ndarray], walks: 
     the last two call sites, then the caller takes a successor.  Globals keep
     one version state across frames; locals are per activation and start
     valid on the host.  An external callee reads every global on the host and
-    writes every global there.  Copies placed in the running context fire as
+    writes every global there (but the const globals).  A call made inside a
+    kernel (``prog.call_space``) runs the callee on the device: a walk through
+    it (and whatever it calls) in which every read must see a current device
+    copy and every write makes the device copy the only current one; no copy
+    fires inside it.  Copies placed in the running context fire as
     walked; every read, and every copy's source, must hold the latest
     version; at the program's exit the live copies must be current.  A walk
     that exceeds ``max_steps`` or ``max_depth`` stops where it is (everything
@@ -443,6 +447,10 @@ def simulate_program(prog, ctx, results, demands: Dict[int, np.ndarray], walks: 
     rw: Dict[int, Tuple[list, list]] = {}
     bits: Dict[tuple, _CtxBits] = {}
     dem = {j: _bitset(row_int(m), prog.procs[int(prog.call_proc[j])].n_vars) for j, m in demands.items()}
+    cspace = getattr(prog, "call_space", None)
+    cspace = np.zeros(len(prog.call_proc), np.uint8) if cspace is None else np.asarray(cspace)
+    cg = getattr(prog, "const_globals", None)
+    const = _bitset(row_int(np.asarray(cg, np.uint64)), G) if cg is not None else np.zeros(G, bool)
 
     def view(P):
         if P not in views:
@@ -499,6 +507,36 @@ def simulate_program(prog, ctx, results, demands: Dict[int, np.ndarray], walks: 
                                     % (wk, key, s, where, np.nonzero(bad)[0][:4].tolist()))
                     vs[s] = np.where(mask, ver, vs[s])
 
+            def device_call(q, depth):
+                """The callee q run on the device (its globals only; its locals are its own)."""
+                if q < 0:
+                    bad = vs[1][:G] != ver[:G]
+                    if bad.any():
+                        errs.append("walk %d %s: external device call reads stale device globals %s"
+                                    % (wk, key, np.nonzero(bad)[0][:4].tolist()))
+                    ver[:G] += ~const
+                    vs[1][:G] = ver[:G]
+                    return
+                Vq = view(q)
+                Rq, Wq = rw[q]
+                bq, n = Vq.entry, 0
+                while bq != Vq.exit and n < max_steps and depth < max_depth:
+                    rd = Rq[bq][:G]
+                    bad = rd & (vs[1][:G] != ver[:G])
+                    if bad.any():
+                        errs.append("walk %d %s: device function %d reads stale device globals %s in block %d"
+                                    % (wk, key, q, np.nonzero(bad)[0][:4].tolist(), bq))
+                    w = Wq[bq][:G]
+                    if w.any():
+                        ver[:G] += w
+                        vs[1][:G] = np.where(w, ver[:G], vs[1][:G])
+                    jj = site_at.get((q, bq))
+                    if jj is not None:
+                        device_call(int(prog.callee[jj]), depth + 1)
+                    sq = Vq.succ[bq]
+                    bq = sq[int(rng.integers(len(sq)))][0]
+                    n += 1
+
             if not fr["after"]:
                 for s in (0, 1):
                     copy(cb.ie[s][b], s, "entry of %d" % b)
@@ -523,6 +561,9 @@ def simulate_program(prog, ctx, results, demands: Dict[int, np.ndarray], walks: 
                     ver = ver + Wb[b].astype(np.int64)
                     vs[x] = np.where(Wb[b], ver, vs[x])
                 fr["after"] = True
+                if j is not None and cspace[j]:
+                    device_call(int(prog.callee[j]), len(stack))
+                    j = None
                 if j is not None:
                     q = int(prog.callee[j])
                     if q < 0:
@@ -530,7 +571,7 @@ def simulate_program(prog, ctx, results, demands: Dict[int, np.ndarray], walks: 
                         if bad.any():
                             errs.append("walk %d %s: external call at %d reads stale host globals %s"
                                         % (wk, key, b, np.nonzero(bad)[0][:4].tolist()))
-                        ver[:G] += 1
+                        ver[:G] += ~const
                         vs[0][:G] = ver[:G]
                     else:
                         store()
