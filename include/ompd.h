@@ -332,7 +332,17 @@ int ompd_serving_stats(ompd_ctx* ctx, int64_t* admitted, int64_t* completed, int
  * needs every global current on the host, may read and write every global
  * there, and leaves the device copies stale.  A context is a procedure with
  * the last two call sites of a call string that reaches it from a root;
- * roots are contexts with an empty string.                                 */
+ * roots are contexts with an empty string.
+ * call_space [n_calls] (NULL = all 0): 1 for a call made inside a kernel (a
+ * device function; its block must be a DEVICE block).  It runs on the
+ * device: the call block reads every global the callee may read or write,
+ * in either space, and writes every global it may write (an external
+ * callee: every global), and it leads to no context (a device function
+ * carries no mapping directives).
+ * const_globals [gw] (NULL = none): globals that are never written (the
+ * paper's rule for data behind a pointer to const, per global): a
+ * procedure that writes one is rejected (OMPD_E_INVAL), and an external
+ * callee neither writes them nor leaves their device copy stale.           */
 typedef struct {
     int32_t n_procs, n_globals;
     const ompd_cfg* procs;            /* [n_procs] */
@@ -342,6 +352,8 @@ typedef struct {
     const int32_t* callee;            /* [n_calls] */
     int32_t n_roots;
     const int32_t* roots;             /* [n_roots] */
+    const uint8_t* call_space;        /* [n_calls] or NULL */
+    const uint64_t* const_globals;    /* [gw] or NULL */
 } ompd_program;
 
 /* Enumerate the contexts (breadth first from the roots, call sites in

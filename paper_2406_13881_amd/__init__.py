@@ -102,7 +102,8 @@ class _Res(ctypes.Structure):
 
 class _Prog(ctypes.Structure):
     _fields_ = [("n_procs", _i32), ("n_globals", _i32), ("procs", _vp), ("n_calls", _i32),
-                ("call_proc", _vp), ("call_block", _vp), ("callee", _vp), ("n_roots", _i32), ("roots", _vp)]
+                ("call_proc", _vp), ("call_block", _vp), ("callee", _vp), ("n_roots", _i32), ("roots", _vp),
+                ("call_space", _vp), ("const_globals", _vp)]
 
 
 class _ProgRes(ctypes.Structure):
@@ -380,6 +381,16 @@ def _prog_struct(prog, keep: list) -> _Prog:
     P.n_calls = int(arrs[0].size)
     P.call_proc, P.call_block, P.callee = (_np_ptr(a) if a.size else None for a in arrs[:3])
     P.n_roots, P.roots = int(arrs[3].size), _np_ptr(arrs[3])
+    cs = getattr(prog, "call_space", None)
+    if cs is not None:
+        cs = np.ascontiguousarray(np.asarray(cs, dtype=np.uint8))
+        keep.append(cs)
+        P.call_space = _np_ptr(cs) if cs.size else None
+    cg = getattr(prog, "const_globals", None)
+    if cg is not None:
+        cg = np.ascontiguousarray(np.asarray(cg, dtype=np.uint64))
+        keep.append(cg)
+        P.const_globals = _np_ptr(cg)
     return P
 
 

@@ -75,6 +75,7 @@ struct CallTabItem {
     uint64_t* dst;        // [16][wd]
     const uint64_t* src;  // [16][gw] callee rows, or NULL for an external callee
     const uint64_t* cap;  // [2][gw] host / device caps, or NULL
+    const uint64_t* cmask;   // [gw] const globals (an external callee neither writes nor stales them)
     int32_t wd, gw, G, nv;
 };
 
@@ -89,9 +90,11 @@ __global__ void __launch_bounds__(256) k_calltab(const CallTabItem* __restrict__
             if (w < I.gw) {
                 if (I.src) v = I.src[r * I.gw + w];
                 else {
-                    const bool one = r == SUM_MAYR_H || r == SUM_MAYW_H || r == SUM_NU0_H || r == SUM_NU1_H ||
-                                     r == SUM_NU1_D || (r >= SUM_TH && r < SUM_TH + 4);
+                    const bool one = r == SUM_MAYR_H || r == SUM_NU0_H || r == SUM_NU1_H || r == SUM_NU1_D ||
+                                     (r >= SUM_TH && r < SUM_TH + 4);
                     v = one ? ~0ull : 0ull;
+                    if (r == SUM_MAYW_H) v = ~I.cmask[w];
+                    if (r == SUM_TD + 2 || r == SUM_TD + 3) v = I.cmask[w];   // a const device copy is kept
                 }
                 v &= gm;
                 if (I.cap) {
@@ -149,6 +152,7 @@ struct MayItem {
     const uint8_t* space;
     const int32_t* callees;   // [n_sites], -1 = external
     const uint64_t* Sall;     // rows of every procedure
+    const uint64_t* cmask;    // [gw] const globals
     int32_t nb, wd, gw, G, n_sites;
     int32_t* changed;
 };
@@ -167,7 +171,7 @@ __global__ void __launch_bounds__(64) k_may(const MayItem* __restrict__ items, i
             }
             for (int k = 0; k < I.n_sites; ++k) {
                 const int q = I.callees[k];
-                if (q < 0) { m[SUM_MAYR_H] |= ~0ull; m[SUM_MAYW_H] |= ~0ull; }
+                if (q < 0) { m[SUM_MAYR_H] |= ~0ull; m[SUM_MAYW_H] |= ~I.cmask[w]; }
                 else
                     for (int r = 0; r < 4; ++r) m[r] |= I.Sall[((size_t)q * SUM_ROWS + r) * I.gw + w];
             }
@@ -197,6 +201,37 @@ __global__ void __launch_bounds__(64) k_demand(const DemandItem* __restrict__ it
             uint64_t v = I.R[(size_t)I.block * I.wd + w];
             if (w < I.gw) v |= I.demand[w];
             I.Rd[(size_t)I.block * I.wd + w] = v;
+        }
+    }
+}
+
+// A call made inside a kernel: the call block (a DEVICE block) reads every global the callee
+// may read or write, in either space, and writes every global it may write; an external callee
+// reads every global and writes every one but the const globals.  ORed into the caller's rows
+// (the may sets only grow, so repeating it is harmless).
+struct DevCallItem {
+    uint64_t *Rd, *W;
+    const uint64_t* S;       // [16][gw] callee rows, or NULL for an external callee
+    const uint64_t* cmask;   // [gw]
+    int32_t block, wd, gw, G;
+};
+
+__global__ void __launch_bounds__(64) k_devcall(const DevCallItem* __restrict__ items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const DevCallItem I = items[it];
+        for (int w = threadIdx.x; w < I.gw; w += blockDim.x) {
+            const uint64_t gm = word_mask(I.G, w);
+            uint64_t rd, wr;
+            if (I.S) {
+                wr = I.S[SUM_MAYW_H * I.gw + w] | I.S[SUM_MAYW_D * I.gw + w];
+                rd = I.S[SUM_MAYR_H * I.gw + w] | I.S[SUM_MAYR_D * I.gw + w] | wr;
+            } else {
+                rd = ~0ull;
+                wr = ~I.cmask[w];
+            }
+            I.Rd[(size_t)I.block * I.wd + w] |= rd & gm;
+            I.W[(size_t)I.block * I.wd + w] |= wr & gm;
         }
     }
 }
@@ -377,7 +412,8 @@ static inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Structure {
     int n = 0, G = 0, gw = 0, nc = 0;
     std::vector<int> wd, nb, ne;
-    std::vector<std::vector<int>> sites;   // per procedure: its call sites in order
+    std::vector<std::vector<int>> sites;   // per procedure: its host call sites in order
+    std::vector<std::vector<int>> dsites;  // per procedure: its calls made inside kernels
     std::vector<int> site_k;               // call site -> index among its caller's sites
     // contexts
     std::vector<int> cproc, cs0, cs1;
@@ -404,6 +440,7 @@ int check_program(const ompd_program* P, Structure& st)
     st.nb.resize(st.n);
     st.ne.resize(st.n);
     st.sites.assign(st.n, {});
+    st.dsites.assign(st.n, {});
     for (int i = 0; i < st.n; ++i) {
         const ompd_cfg& g = P->procs[i];
         if (g.n_vars < st.G) return bad("procedure has fewer variables than globals", i);
@@ -420,12 +457,29 @@ int check_program(const ompd_program* P, Structure& st)
         const int p = P->call_proc[j], b = P->call_block[j], q = P->callee[j];
         if (p < 0 || p >= st.n || q < -1 || q >= st.n) return bad("call site out of range", j);
         const ompd_cfg& g = P->procs[p];
-        if (b < 0 || b >= g.n_blocks || b == g.entry || b == g.exit || g.space[b] != 0)
-            return bad("call block is not a host block of its procedure", j);
+        const int dev = P->call_space ? P->call_space[j] : 0;
+        if (dev != 0 && dev != 1) return bad("call space is neither host nor device", j);
+        if (b < 0 || b >= g.n_blocks || b == g.entry || b == g.exit || g.space[b] != dev)
+            return bad("call block is not a block of its procedure in the call's space", j);
         if (seen.count({p, b})) return bad("two calls in one block", j);
         seen[{p, b}] = j;
+        if (dev) { st.dsites[p].push_back(j); continue; }
         st.site_k[j] = (int)st.sites[p].size();
         st.sites[p].push_back(j);
+    }
+    if (P->const_globals && st.G > 0) {
+        // nothing writes a const global
+        for (int i = 0; i < st.n; ++i) {
+            const ompd_cfg& g = P->procs[i];
+            if (!g.write_bits) continue;
+            for (int b = 0; b < g.n_blocks; ++b)
+                for (int w = 0; w < st.gw; ++w) {
+                    const int lo = 64 * w;
+                    const uint64_t gm = st.G >= lo + 64 ? ~0ull : (1ull << (st.G - lo)) - 1ull;
+                    if (g.write_bits[(size_t)b * st.wd[i] + w] & P->const_globals[w] & gm)
+                        return bad("a procedure writes a const global", i);
+                }
+        }
     }
     for (int k = 0; k < P->n_roots; ++k)
         if (P->roots[k] < 0 || P->roots[k] >= st.n) return bad("root out of range", k);
@@ -523,6 +577,7 @@ struct Prog {
     std::vector<int32_t*> callees;           // [n_sites]
     std::vector<uint64_t*> ptab;             // [n_sites][16][wd] call tables of the summary evaluations
     uint64_t* S = nullptr;                   // [n][16][gw]
+    uint64_t* cmask = nullptr;               // [gw] const globals
     uint64_t* demand = nullptr;              // [nc][gw]   (accumulated)
     uint64_t* demand_new = nullptr;          // [nc][gw]   (this outer round)
     uint64_t* caps = nullptr;                // [nctx][2][gw]
@@ -619,6 +674,7 @@ int setup(Prog& G)
         po[i].eout = take(8 * 16 * nb * wd);
     }
     const size_t oS = take(8 * (size_t)n * SUM_ROWS * gw);
+    const size_t oCm = take(8 * (size_t)std::max(gw, 1));
     const size_t oD = take(8 * (size_t)std::max(st.nc, 1) * gw);
     const size_t oDn = take(8 * (size_t)std::max(st.nc, 1) * gw);
     const size_t oC = take(8 * (size_t)nctx * 2 * gw);
@@ -718,6 +774,14 @@ int setup(Prog& G)
         CK(hipStreamSynchronize(G.s));   // host vectors are reused
     }
     G.S = (uint64_t*)(A + oS);
+    G.cmask = (uint64_t*)(A + oCm);
+    {
+        std::vector<uint64_t> cm(std::max(gw, 1), 0);
+        if (P->const_globals)
+            for (int w = 0; w < gw; ++w) cm[w] = P->const_globals[w];
+        CK(hipMemcpyAsync(G.cmask, cm.data(), 8 * cm.size(), hipMemcpyHostToDevice, G.s));
+        CK(hipStreamSynchronize(G.s));
+    }
     G.demand = (uint64_t*)(A + oD);
     G.demand_new = (uint64_t*)(A + oDn);
     G.caps = (uint64_t*)(A + oC);
@@ -802,6 +866,7 @@ void calltab_items(Prog& G, int p, int x, std::vector<CallTabItem>& out)
             const int cx = st.child[x][k];
             if (cx >= 0 && G.cap_valid[cx]) I.cap = G.caps + (size_t)cx * 2 * st.gw;
         }
+        I.cmask = G.cmask;
         I.wd = (int32_t)wd; I.gw = st.gw; I.G = st.G; I.nv = G.P->procs[p].n_vars;
         out.push_back(I);
     }
@@ -883,7 +948,7 @@ int may_rows(Prog& G, const std::vector<int>& procs, int& changed)
         MayItem I;
         I.S = G.S + (size_t)p * SUM_ROWS * st.gw;
         I.R = G.Rd[p]; I.W = G.W[p]; I.space = G.space[p];
-        I.callees = G.callees[p]; I.Sall = G.S;
+        I.callees = G.callees[p]; I.Sall = G.S; I.cmask = G.cmask;
         I.nb = st.nb[p]; I.wd = st.wd[p]; I.gw = st.gw; I.G = st.G; I.n_sites = (int32_t)st.sites[p].size();
         I.changed = G.flag;
         mi.push_back(I);
@@ -895,9 +960,28 @@ int may_rows(Prog& G, const std::vector<int>& procs, int& changed)
     return read_flag(G, G.flag, changed);
 }
 
+// The rows of the calls made inside kernels of a set of procedures, from their callees' current
+// may sets.
+int device_calls(Prog& G, const std::vector<int>& procs)
+{
+    const Structure& st = G.st;
+    std::vector<DevCallItem> it;
+    for (int p : procs)
+        for (int j : st.dsites[p]) {
+            const int q = G.P->callee[j];
+            DevCallItem I;
+            I.Rd = G.Rd[p]; I.W = G.W[p];
+            I.S = q < 0 ? nullptr : G.S + (size_t)q * SUM_ROWS * st.gw;
+            I.cmask = G.cmask;
+            I.block = G.P->call_block[j]; I.wd = st.wd[p]; I.gw = st.gw; I.G = st.G;
+            it.push_back(I);
+        }
+    return upload_items(it, k_devcall, 64, G.s, G.arena_items);
+}
+
 // Bottom-up: components by level; a non-recursive procedure is evaluated
-// once, a recursive component iterates its next-use rows from 0, then its
-// validity tables from all ones, then its may-sets from 0.
+// once, a recursive component iterates its may-sets from 0, then its
+// next-use rows from 0, then its validity tables from all ones.
 int summarize(Prog& G)
 {
     const Structure& st = G.st;
@@ -914,6 +998,7 @@ int summarize(Prog& G)
             bool self = false;
             if (comp.size() == 1)
                 for (int j : st.sites[comp[0]]) self |= G.P->callee[j] == comp[0];
+                for (int j : st.dsites[comp[0]]) self |= G.P->callee[j] == comp[0];
             if (comp.size() == 1 && !self) single.push_back(comp[0]);
             else {
                 recur.push_back(&comp);
@@ -921,7 +1006,10 @@ int summarize(Prog& G)
             }
         }
         int ch = 0;
-        int rc = evaluate(G, single, 3, ch);
+        // calls made inside kernels read their callees' may sets (final below this level)
+        int rc = device_calls(G, single);
+        if (rc) return rc;
+        rc = evaluate(G, single, 3, ch);
         if (rc) return rc;
         rc = may_rows(G, single, ch);
         if (rc) return rc;
@@ -937,16 +1025,20 @@ int summarize(Prog& G)
             CK(hipMemcpyAsync(G.S + ((size_t)p * SUM_ROWS + SUM_TH) * st.gw, row.data(), 8 * row.size(),
                               hipMemcpyHostToDevice, G.s));
         CK(hipStreamSynchronize(G.s));
+        // may sets first (calls made inside kernels feed them into the callers' rows), then next
+        // use from 0, then validity tables from all ones
+        do {
+            rc = device_calls(G, recur_procs);
+            if (rc) return rc;
+            rc = may_rows(G, recur_procs, ch);
+            if (rc) return rc;
+        } while (ch);
         for (int rows : {1, 2}) {
             do {
                 rc = evaluate(G, recur_procs, rows, ch);
                 if (rc) return rc;
             } while (ch);
         }
-        do {
-            rc = may_rows(G, recur_procs, ch);
-            if (rc) return rc;
-        } while (ch);
     }
     return OMPD_OK;
 }

@@ -74,6 +74,32 @@ def test_program_small(ctx, kind):
         compare(prog, got, "%s/%d" % (kind, seed))
 
 
+@pytest.mark.parametrize("kind", ["device", "device_recursive", "all_device", "const_external"])
+def test_program_device_calls_and_const_globals(ctx, kind):
+    """Calls made inside kernels (the callee runs on the device) and const globals, against
+    the oracle driver: every context, boundary, summary and demand."""
+    extra = {"device": dict(device_call_frac=0.4, n_const=3),
+             "device_recursive": dict(device_call_frac=0.4, scc_procs=4, scc_size=(2, 3), mean_calls=1.0),
+             "all_device": dict(device_call_frac=1.0, n_const=2, external_frac=0.2),
+             "const_external": dict(n_procs=8, n_const=4, external_frac=0.4, device_call_frac=0.2)}[kind]
+    for seed in range(5):
+        prm = dict(SMALL)
+        prm.update(extra)
+        prog = synth.program(32_000 + 100 * len(kind) + seed, **prm)
+        _print("program %s seed %d: %d procs %d calls (%d in kernels)"
+               % (kind, seed, len(prog.procs), len(prog.call_proc), int(np.sum(prog.call_space))
+                  if prog.call_space is not None else 0))
+        got = ctx.analyze_program(prog)
+        compare(prog, got, "%s/%d" % (kind, seed))
+
+
+def test_program_c4_shape_device_calls(ctx):
+    prog = synth.c4(n_procs=300, device_call_frac=0.25, n_const=32, external_frac=0.05)
+    _print("c4-shaped with device calls: %d procs %d calls" % (len(prog.procs), len(prog.call_proc)))
+    got = ctx.analyze_program(prog)
+    compare(prog, got, "c4-300-device")
+
+
 def test_program_multiword_globals(ctx):
     # globals spanning words, locals sharing the last global word
     prog = synth.program(4_711, n_procs=10, n_globals=100, n_locals=40, blocks=(6, 30), mean_calls=1.5,
