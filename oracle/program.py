@@ -59,6 +59,24 @@ host or the device, and the read-only rule for data behind a pointer to
 * Globals marked ``const_globals`` are never written: no block may write
   them, and an external callee neither writes them nor leaves their device
   copy stale.
+
+By-reference pointer parameters ("data at the address of pointer
+parameters"): procedure Q's first ``n_params[Q]`` locals (variables
+[G, G + n_params[Q])) are its pointer parameters, and call site j binds them
+to caller variables (``arg_var[arg_ptr[j]:arg_ptr[j + 1]]``).  A procedure's
+summary covers its globals and its parameters (its shared variables); at a
+call site the callee's row of parameter i applies to the caller variable it
+is bound to, combined with any other row that reaches that variable (the
+global's own, another parameter's): may and next-use rows by OR, validity
+tables by AND.  A callee context's boundary takes, for parameter i, the
+caller's facts on the bound variable, and its gaps and caps map back the
+same way.  The callee is solved name by name, so a host call's arguments
+must be distinct locals of the caller (no global, no repeat): then no frame
+sees one datum under two names.  A call made inside a kernel may bind any
+caller variables, repeats and globals included, since only its may rows
+cross it.  An external callee may take arguments too: it reads them on the
+host and writes them there unless the argument is a pointer to const
+(``arg_const``).
 """
 from __future__ import annotations
 
@@ -179,11 +197,53 @@ class ProgramOracle:
         for P, c in enumerate(prog.procs):
             if (np.asarray(c.W, np.uint64)[:, :gw] & self.const).any():
                 raise ValueError("procedure %d writes a const global" % P)
+        npar = getattr(prog, "n_params", None)
+        self.np = [0] * self.n if npar is None else [int(x) for x in npar]
+        ap = getattr(prog, "arg_ptr", None)
+        av = getattr(prog, "arg_var", None)
+        ac = getattr(prog, "arg_const", None)
+        self.args: List[List[Tuple[int, bool]]] = []
+        for j in range(nc):
+            a = [] if ap is None else [(int(av[t]), bool(ac[t]) if ac is not None else False)
+                                       for t in range(int(ap[j]), int(ap[j + 1]))]
+            q, P = int(prog.callee[j]), int(prog.call_proc[j])
+            if q >= 0 and len(a) != self.np[q]:
+                raise ValueError("call site %d binds %d arguments to %d parameters" % (j, len(a), self.np[q]))
+            if any(not (0 <= x < prog.procs[P].n_vars) for x, _ in a):
+                raise ValueError("call site %d: argument is not a caller variable" % j)
+            if q >= 0 and not self.call_space[j] and (len(set(x for x, _ in a)) < len(a)
+                                                      or any(x < self.G for x, _ in a)):
+                raise ValueError("call site %d: a host call's arguments must be distinct locals" % j)
+            self.args.append(a)
+        for P, c in enumerate(prog.procs):
+            if self.G + self.np[P] > c.n_vars:
+                raise ValueError("procedure %d has more parameters than locals" % P)
         self.demand: Dict[int, np.ndarray] = {}                          # call site -> host-read mask (caller words)
         self.cap: Dict[tuple, Tuple[np.ndarray, np.ndarray]] = {}        # callee context -> (host, device) validity at EXIT
         self.sum_rows: Dict[int, np.ndarray] = {}
         self.nowhere: Dict[tuple, np.ndarray] = {}                       # last contexts(): globals valid nowhere
         self.visits = 0
+
+    # -- shared variables and argument bindings ---------------------------------------
+    def shared(self, P: int) -> int:
+        """Number of P's shared variables: the globals, then its pointer parameters."""
+        return self.G + self.np[P]
+
+    def _smask(self, P: int, wd: int) -> np.ndarray:
+        return _vmask(self.shared(P), wd)
+
+    def _rows(self, j: int, q: int, summaries) -> np.ndarray:
+        """The callee side of call site j: q's summary rows over its shared variables, or an
+        external callee's rows over the globals and, past them, its arguments."""
+        if q >= 0:
+            return summaries[q]
+        gw = (self.G + 63) // 64
+        return external_summary(_gmask(self.G, gw), self.const)
+
+    def _sources(self, j: int, q: int):
+        """(caller variable, callee row index or None for an external argument, const) for
+        every argument of call site j."""
+        return [(x, (self.G + i) if q >= 0 else None, c) for i, (x, c) in enumerate(self.args[j])]
 
     # -- call tables in a caller's variable layout ------------------------------------
     def _caller_tables(self, P: int, summaries: Dict[int, np.ndarray], sigma=None):
@@ -191,34 +251,80 @@ class ProgramOracle:
         wd = cfg.wd
         gw = (self.G + 63) // 64
         gm = _gmask(self.G, wd)
-        lm = _vmask(cfg.n_vars, wd) & ~gm
+        vm = _vmask(cfg.n_vars, wd)
         call = np.full(cfg.n_blocks, -1, np.int32)
         sums = np.zeros((max(len(self.sites[P]), 1), SUM_ROWS, wd), np.uint64)
+        OR_ROWS = list(range(SUM_MAYR_H, SUM_NU1_D + 1))
+        T_ROWS = list(range(SUM_TH_00, SUM_TD_00 + 4))
         for k, j in enumerate(self.sites[P]):
             call[int(self.p.call_block[j])] = k
             q = int(self.p.callee[j])
-            rows = external_summary(_gmask(self.G, gw), self.const) if q < 0 else summaries[q]
-            s = np.zeros((SUM_ROWS, wd), np.uint64)
-            s[:, :gw] = rows
-            s &= gm
-            # identity for the caller's locals: NU1 = 1, T[e][l] = e
-            s[SUM_NU1_H] |= lm
-            s[SUM_NU1_D] |= lm
-            for base in (SUM_TH_00, SUM_TD_00):
-                s[base + 2] |= lm
-                s[base + 3] |= lm
+            rows = self._rows(j, q, summaries)
             ckey = None if (sigma is None or q < 0) else (q, (tuple(sigma) + (j,))[-2:])
-            if ckey in self.cap:
-                ch, cd = self.cap[ckey]
+            cap = self.cap.get(ckey)
+            # identity for every caller variable (NU1 = 1, T[e][l] = e), then the globals' rows
+            s = np.zeros((SUM_ROWS, wd), np.uint64)
+            for r in (SUM_NU1_H, SUM_NU1_D, SUM_TH_00 + 2, SUM_TH_00 + 3, SUM_TD_00 + 2, SUM_TD_00 + 3):
+                s[r] = vm & ~gm
+            s[:, :gw] |= rows[:, :gw] & gm[:gw]
+            if cap is not None:
                 for k4 in range(4):
-                    s[SUM_TH_00 + k4, :gw] &= ch | ~gm[:gw]
-                    s[SUM_TD_00 + k4, :gw] &= cd | ~gm[:gw]
+                    s[SUM_TH_00 + k4, :gw] &= cap[0][:gw] | ~gm[:gw]
+                    s[SUM_TD_00 + k4, :gw] &= cap[1][:gw] | ~gm[:gw]
+            # arguments: the row of the parameter (or of an external argument) applies to the bound
+            # caller variable, combined with whatever already reaches it
+            seen = set(range(self.G))
+            for (x, src, const) in self._sources(j, q):
+                col = np.zeros(SUM_ROWS, bool)
+                if src is not None:
+                    for r in range(SUM_ROWS):
+                        col[r] = bool((int(rows[r][src >> 6]) >> (src & 63)) & 1)
+                    if cap is not None:
+                        ch = bool((int(cap[0][src >> 6]) >> (src & 63)) & 1)
+                        cd = bool((int(cap[1][src >> 6]) >> (src & 63)) & 1)
+                        for k4 in range(4):
+                            col[SUM_TH_00 + k4] &= ch
+                            col[SUM_TD_00 + k4] &= cd
+                else:   # an external argument: read on the host, written there unless const
+                    for r in (SUM_MAYR_H, SUM_NU0_H, SUM_NU1_H, SUM_NU1_D):
+                        col[r] = True
+                    col[SUM_MAYW_H] = not const
+                    for k4 in range(4):
+                        col[SUM_TH_00 + k4] = True
+                        col[SUM_TD_00 + k4] = const and k4 >= 2
+                bit = np.uint64(1 << (x & 63))
+                w = x >> 6
+                if x in seen:
+                    for r in OR_ROWS:
+                        if col[r]:
+                            s[r, w] |= bit
+                    for r in T_ROWS:
+                        if not col[r]:
+                            s[r, w] &= ~bit
+                else:
+                    for r in range(SUM_ROWS):
+                        s[r, w] = (s[r, w] | bit) if col[r] else (s[r, w] & ~bit)
+                    seen.add(x)
             sums[k] = s
         return call, sums
 
+    def _to_caller(self, j: int, q: int, row: np.ndarray, P: int) -> np.ndarray:
+        """A row over callee q's shared variables (an external callee: its rows over the
+        globals and arguments) moved to caller P's layout through the bindings of site j
+        (OR where several reach one caller variable)."""
+        cfg = self.p.procs[P]
+        gw = (self.G + 63) // 64
+        out = np.zeros(cfg.wd, np.uint64)
+        out[:gw] = row[:gw] & _gmask(self.G, gw)
+        for (x, src, _) in self._sources(j, q):
+            if src is not None and (int(row[src >> 6]) >> (src & 63)) & 1:
+                out[x >> 6] |= np.uint64(1 << (x & 63))
+        return out
+
     def _cfg_with_demands(self, P: int, S):
         """P's read and write rows with the host reads demanded at its call blocks and, at each
-        device call block, the callee's may-read and may-write globals (either space)."""
+        device call block, the variables the callee may read and write (either space), moved to
+        P's layout (an external device function: every global and its arguments)."""
         cfg = self.p.procs[P]
         R, W = cfg.R, cfg.W
         dem = [(int(self.p.call_block[j]), self.demand[j]) for j in self.sites[P] if j in self.demand]
@@ -231,13 +337,22 @@ class ProgramOracle:
             for j in self.dsites[P]:
                 q, blk = int(self.p.callee[j]), int(self.p.call_block[j])
                 if q < 0:
-                    rd, wr = gm, gm & ~self.const
+                    rd = np.zeros(cfg.wd, np.uint64)
+                    rd[:gw] = gm
+                    wr = rd.copy()
+                    wr[:gw] &= ~self.const
+                    for (x, _, const) in self._sources(j, q):
+                        rd[x >> 6] |= np.uint64(1 << (x & 63))
+                        if not const:
+                            wr[x >> 6] |= np.uint64(1 << (x & 63))
                 else:
                     rows = S[q]
-                    wr = rows[SUM_MAYW_H] | rows[SUM_MAYW_D]
-                    rd = rows[SUM_MAYR_H] | rows[SUM_MAYR_D] | wr
-                R[blk, :gw] |= rd & gm
-                W[blk, :gw] |= wr & gm
+                    w_any = rows[SUM_MAYW_H] | rows[SUM_MAYW_D]
+                    r_any = rows[SUM_MAYR_H] | rows[SUM_MAYR_D] | w_any
+                    rd = self._to_caller(j, q, r_any, P)
+                    wr = self._to_caller(j, q, w_any, P)
+                R[blk] |= rd
+                W[blk] |= wr
         return cfg, R, W
 
     def _solve(self, P, summaries, boundary, summary_mode=False, sigma=None):
@@ -271,10 +386,11 @@ class ProgramOracle:
                 S[q][:4] = self._may(q, S)
                 continue
             for q in comp:
-                r = np.zeros((SUM_ROWS, gw), np.uint64)
+                sw = (self.shared(q) + 63) // 64
+                r = np.zeros((SUM_ROWS, sw), np.uint64)
                 for k in range(4):
-                    r[SUM_TH_00 + k] = _gmask(G, gw)
-                    r[SUM_TD_00 + k] = _gmask(G, gw)
+                    r[SUM_TH_00 + k] = self._smask(q, sw)
+                    r[SUM_TD_00 + k] = self._smask(q, sw)
                 S[q] = r
             # may bits from 0 (device calls read them into the callers' rows), then next use
             # from 0, then validity tables from all-ones
@@ -303,11 +419,12 @@ class ProgramOracle:
         return S
 
     def _evaluate(self, Q: int, S) -> np.ndarray:
-        """NU0/NU1 and the four T tables of Q from four boundary evaluations."""
+        """NU0/NU1 and the four T tables of Q, over its shared variables (globals and
+        parameters), from four boundary evaluations."""
         cfg = self.p.procs[Q]
         wd = cfg.wd
-        gw = (self.G + 63) // 64
-        gm = _gmask(self.G, wd)
+        gw = (self.shared(Q) + 63) // 64
+        gm = self._smask(Q, wd)
         lm = _vmask(cfg.n_vars, wd) & ~gm
         out = np.zeros((SUM_ROWS, gw), np.uint64)
         for eps in (0, 1):
@@ -326,9 +443,12 @@ class ProgramOracle:
         return out
 
     def _may(self, Q: int, S) -> np.ndarray:
+        """May-read / may-write rows of Q over its shared variables: its own blocks (reads
+        including the demanded ones, and device calls' rows) and its host calls' callees,
+        through the argument bindings."""
         cfg, R, W = self._cfg_with_demands(Q, S)
-        gw = (self.G + 63) // 64
-        gm = _gmask(self.G, gw)
+        gw = (self.shared(Q) + 63) // 64
+        gm = self._smask(Q, gw)
         m = np.zeros((4, gw), np.uint64)
         dev = np.asarray(cfg.space) == 1
         if (~dev).any():
@@ -337,10 +457,22 @@ class ProgramOracle:
         if dev.any():
             m[1] = np.bitwise_or.reduce(R[dev][:, :gw], axis=0)
             m[3] = np.bitwise_or.reduce(W[dev][:, :gw], axis=0)
+        G = self.G
+        ggw = (G + 63) // 64
         for j in self.sites[Q]:
             q = int(self.p.callee[j])
-            rows = external_summary(gm, self.const) if q < 0 else S[q]
-            m |= rows[:4]
+            if q < 0:
+                rows = external_summary(_gmask(G, ggw), self.const)
+                m[:, :ggw] |= rows[:4]
+                for (x, _, const) in self._sources(j, q):
+                    if x < self.shared(Q):
+                        b = np.uint64(1 << (x & 63))
+                        m[SUM_MAYR_H, x >> 6] |= b
+                        if not const:
+                            m[SUM_MAYW_H, x >> 6] |= b
+            else:
+                for r in range(4):
+                    m[r] |= self._to_caller(j, q, S[q][r], Q)[:gw]
         return m & gm
 
     # -- top-down -------------------------------------------------------------------
@@ -469,14 +601,22 @@ class ProgramOracle:
 
         def masks(q):
             qc = self.p.procs[q]
-            gq = _gmask(G, qc.wd)
+            gq = self._smask(q, qc.wd)
             return gq, _vmask(qc.n_vars, qc.wd) & ~gq
 
         def to_callee(x, nk):
-            qc = self.p.procs[nk[0]]
+            """A caller-layout row moved to the callee context nk through the bindings of its
+            leading call site: the globals, and parameter i from the bound caller variable."""
+            q, j = nk[0], nk[1][-1]
+            qc = self.p.procs[q]
             m = np.zeros(qc.wd, np.uint64)
             m[:gw] = x[:gw]
-            return m & _gmask(G, qc.wd)
+            m &= _gmask(G, qc.wd)
+            for i, (v, _) in enumerate(self.args[j]):
+                if (int(x[v >> 6]) >> (v & 63)) & 1:
+                    t = G + i
+                    m[t >> 6] |= np.uint64(1 << (t & 63))
+            return m
 
         bnd: Dict[Tuple[int, tuple], List[np.ndarray]] = {}
         for k in keys:
@@ -537,7 +677,8 @@ class ProgramOracle:
             results[k] = res
             if k[1]:
                 qc = self.p.procs[k[0]]
-                caps[k] = (res["avf_h"][qc.exit][:gw].copy(), res["avf_d"][qc.exit][:gw].copy())
+                sm = self._smask(k[0], qc.wd)
+                caps[k] = ((res["avf_h"][qc.exit] & sm).copy(), (res["avf_d"][qc.exit] & sm).copy())
 
         # globals valid nowhere that the context reads before writing them (next
         # use at its ENTRY, which does not depend on entry validity): host-read
@@ -558,19 +699,21 @@ class ProgramOracle:
         new_demand: Dict[int, np.ndarray] = {}
 
         def demand(k, bits):
+            """Gaps of context k (its layout) as host reads of the bound caller variables at its
+            leading call site."""
             jj = k[1][-1]
+            q = k[0]
             P2 = int(self.p.call_proc[jj])
             d = new_demand.get(jj, np.zeros(self.p.procs[P2].wd, np.uint64))
-            d[:gw] |= bits[:gw]
+            d |= self._to_caller(jj, q, bits, P2)
             new_demand[jj] = d
 
         for k, nw in gaps.items():
-            inherited = np.zeros(gw, np.uint64)
+            inherited = np.zeros(self.p.procs[k[0]].wd, np.uint64)
             for x in callers[k]:
                 if x in gaps:
-                    inherited |= gaps[x][:gw]
-            own = nw.copy()
-            own[:gw] &= ~inherited
+                    inherited |= to_callee(gaps[x], k)
+            own = nw & ~inherited
             if own.any():
                 demand(k, own)
         if gaps and not new_demand:
@@ -584,7 +727,6 @@ class ProgramOracle:
         outer rounds (summaries, then contexts) have settled the demands and
         the caps.  ``schedule`` orders the context solves inside a round
         ("rounds", "fifo" or "lifo"); the result does not depend on it."""
-        gm = _gmask(self.G, (self.G + 63) // 64)
         for _ in range(max_rounds):
             S = self.summarize()
             ctx, nd, caps, results = self.contexts(S, schedule)
@@ -595,7 +737,7 @@ class ProgramOracle:
                 if old is None or not np.array_equal(old, cur):
                     self.demand[j] = cur
                     grew = True
-            caps = {k: (ch & gm, cd & gm) for k, (ch, cd) in caps.items()}
+            # (caps are over each callee context's shared variables)
             if caps.keys() != self.cap.keys() or any(
                     not (np.array_equal(caps[k][0], self.cap[k][0]) and np.array_equal(caps[k][1], self.cap[k][1]))
                     for k in caps):

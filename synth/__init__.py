@@ -416,6 +416,10 @@ class Program:
     roots: List[int]
     call_space: Optional[np.ndarray] = None      # [n_calls] 1: the call runs on the device (None: all host)
     const_globals: Optional[np.ndarray] = None   # [words of globals] globals never written (None: none)
+    n_params: Optional[np.ndarray] = None        # [n_procs] pointer parameters: vars [G, G + n_params)
+    arg_ptr: Optional[np.ndarray] = None         # [n_calls + 1] into arg_var / arg_const
+    arg_var: Optional[np.ndarray] = None         # caller variable bound to each argument
+    arg_const: Optional[np.ndarray] = None       # 1: an external callee's pointer-to-const argument
 
 
 C4 = dict(n_procs=2000, n_globals=256, n_locals=16, blocks=(32, 1024), mean_calls=3.0, max_calls=8,
@@ -427,7 +431,7 @@ def program(seed: int, n_procs: int = 2000, n_globals: int = 256, n_locals: int 
             scc_procs: int = 100, scc_size: Tuple[int, int] = (2, 8), max_loop_depth: int = 3,
             device_frac: float = 0.30, p_read: float = 0.2, p_write: float = 0.1,
             external_frac: float = 0.0, threads: int = 0, device_call_frac: float = 0.0,
-            n_const: int = 0) -> Program:
+            n_const: int = 0, max_params: int = 0, max_ext_args: int = 0) -> Program:
     """A random call graph: procedure i calls Poisson(mean_calls) (at most
     max_calls) procedures of higher index; then scc_procs procedures are
     grouped into cycles of U{scc_size} members (a call from each member to the
@@ -436,7 +440,12 @@ def program(seed: int, n_procs: int = 2000, n_globals: int = 256, n_locals: int 
     call sites are distinct host statements; a seeded fraction
     device_call_frac of them become calls made inside a kernel (their block
     turns DEVICE), and n_const seeded globals become const (every write of
-    them is removed)."""
+    them is removed).  With max_params > 0 each procedure gets U{0..max_params}
+    pointer parameters (its first locals) and every call binds them to caller
+    variables: a host call distinct non-global ones (so no frame sees one datum
+    under two names), a call made inside a kernel any, with repeats (globals
+    passed by pointer too).  An external call gets up to max_ext_args
+    arguments, any caller variables, some pointers to const."""
     rng = np.random.Generator(np.random.PCG64(seed))
     calls: List[List[int]] = [[] for _ in range(n_procs)]
     for i in range(n_procs - 1):
@@ -508,6 +517,27 @@ def program(seed: int, n_procs: int = 2000, n_globals: int = 256, n_locals: int 
             W = np.array(c.W, np.uint64).reshape(c.n_blocks, c.wd)
             W[:, :gw] &= ~const
             c.W = W
+    # pointer parameters and their bindings
+    npar = np.zeros(n_procs, np.int32)
+    ap = np.zeros(len(cp) + 1, np.int64)
+    av: List[int] = []
+    acn: List[int] = []
+    if max_params > 0 or max_ext_args > 0:
+        if max_params > 0:
+            npar = rng.integers(0, max_params + 1, size=n_procs).astype(np.int32)
+            npar = np.minimum(npar, n_locals).astype(np.int32)
+        for j in range(len(cp)):
+            P, q = cp[j], ce[j]
+            nv_p = n_globals + n_locals
+            k = int(npar[q]) if q >= 0 else int(rng.integers(0, max_ext_args + 1))
+            if q >= 0 and not cs[j]:
+                pool = np.arange(n_globals, nv_p)
+                pick = rng.choice(pool, size=min(k, pool.size), replace=False)
+            else:
+                pick = rng.integers(0, nv_p, size=k)
+            av.extend(int(x) for x in pick)
+            acn.extend(int(rng.random() < 0.5) if q < 0 else 0 for _ in range(len(pick)))
+            ap[j + 1] = len(av)
     # roots: procedure 0 and every procedure no host call reaches (a procedure called only from
     # kernels is a device function and gets no context of its own)
     called = set(x for x, d in zip(ce, cs) if x >= 0 and not d)
@@ -515,7 +545,11 @@ def program(seed: int, n_procs: int = 2000, n_globals: int = 256, n_locals: int 
     return Program(procs=procs, n_globals=n_globals, call_proc=np.array(cp, np.int32),
                    call_block=np.array(cb, np.int32), callee=np.array(ce, np.int32), roots=roots,
                    call_space=cs if device_call_frac > 0 else None,
-                   const_globals=const if n_const > 0 else None)
+                   const_globals=const if n_const > 0 else None,
+                   n_params=npar if (max_params > 0 or max_ext_args > 0) else None,
+                   arg_ptr=ap if (max_params > 0 or max_ext_args > 0) else None,
+                   arg_var=np.array(av, np.int32) if (max_params > 0 or max_ext_args > 0) else None,
+                   arg_const=np.array(acn, np.uint8) if (max_params > 0 or max_ext_args > 0) else None)
 
 
 def c4(n_procs: int = 2000, **kw) -> Program:

@@ -337,14 +337,19 @@ def inline_program(prog, root: int, demands: Dict[int, np.ndarray], cap_depth: i
     Each call block keeps its own accesses (plus the host reads that
     ``demands`` adds at that call site) and then branches into a fresh copy of
     the callee, whose EXIT branches to the call block's successors.  Globals
-    (the first ``prog.n_globals`` variables) are shared; every inlined copy
-    gets fresh variables for the callee's locals, which are not live after
-    the program.  Returns (cfg, instances, pos) where instances lists
+    (the first ``prog.n_globals`` variables) are shared; a pointer parameter
+    of an inlined copy is the caller variable bound to it at that call site;
+    every other local of the copy is a fresh variable, not live after the
+    program, and a host block that writes them (and reads nothing) precedes
+    the copy's ENTRY: each activation starts with new storage, valid on the
+    host, that no earlier activation's accesses reach (a call in a loop
+    re-enters the same copy).  Returns (cfg, instances, pos) where instances lists
     (procedure, call string, block offset, variable map) in creation order and
     ``pos`` maps an instance block id to its id in the returned CFG.
 
     With ``cap_depth >= 0`` a call made at that nesting depth is not expanded:
-    a host block that writes every global (and reads none) stands in for it,
+    a host block that writes every global and every argument (and reads
+    none) stands in for it,
     so no next use crosses it.  Unrolling recursion this way gives the next
     use of the paths with at most ``cap_depth`` nested calls, a lower bound
     that grows to the exact solution."""
@@ -353,17 +358,23 @@ def inline_program(prog, root: int, demands: Dict[int, np.ndarray], cap_depth: i
     site_at: Dict[Tuple[int, int], int] = {}
     for j in range(len(prog.call_proc)):
         site_at[(int(prog.call_proc[j]), int(prog.call_block[j]))] = j
+    ap, av = getattr(prog, "arg_ptr", None), getattr(prog, "arg_var", None)
+
+    def args(j):
+        return [] if ap is None else [int(av[t]) for t in range(int(ap[j]), int(ap[j + 1]))]
     blocks: List[Tuple[int, List[int], List[int]]] = []
     edges: List[Tuple[int, int, int]] = []
     instances = []
     nvars = [G]
 
-    def add(P: int, sigma: tuple) -> int:
+    def add(P: int, sigma: tuple, bound: List[int]) -> int:
         cfg = prog.procs[P]
         off = len(blocks)
-        vmap = list(range(G)) + list(range(nvars[0], nvars[0] + cfg.n_vars - G))
-        nvars[0] += cfg.n_vars - G
+        nfresh = cfg.n_vars - G - len(bound)
+        vmap = list(range(G)) + list(bound) + list(range(nvars[0], nvars[0] + nfresh))
+        nvars[0] += nfresh
         instances.append((P, sigma, off, vmap))
+        fresh = vmap[G + len(bound):]
         R = cfg.R.reshape(cfg.n_blocks, cfg.wd)
         W = cfg.W.reshape(cfg.n_blocks, cfg.wd)
         for b in range(cfg.n_blocks):
@@ -381,31 +392,35 @@ def inline_program(prog, root: int, demands: Dict[int, np.ndarray], cap_depth: i
                 assert q >= 0, "inlining needs every callee's body"
                 if len(sigma) == cap_depth:
                     cap = len(blocks)
-                    blocks.append((0, [], list(range(G))))
+                    blocks.append((0, [], sorted(set(range(G)) | {vmap[v] for v in args(j)})))
                     edges.append((b + off, cap, 0))
                     for (t, k) in outs:
                         edges.append((cap, t, k))
                     continue
-                qoff = add(q, sigma + (j,))
+                kill = len(blocks)
+                blocks.append((0, [], []))
+                qoff, qfresh = add(q, sigma + (j,), [vmap[v] for v in args(j)])
+                blocks[kill] = (0, [], sorted(qfresh))
                 qc = prog.procs[q]
-                edges.append((b + off, qc.entry + qoff, 0))
+                edges.append((b + off, kill, 0))
+                edges.append((kill, qc.entry + qoff, 0))
                 for (t, k) in outs:
                     edges.append((qc.exit + qoff, t, k))
             else:
                 for (t, k) in outs:
                     edges.append((b + off, t, k))
-        return off
+        return off, fresh
 
-    add(root, ())
+    add(root, (), [])
     rc = prog.procs[root]
     nb = len(blocks)
     order = [rc.entry] + [b for b in range(nb) if b not in (rc.entry, rc.exit)] + [rc.exit]
     pos = {b: i for i, b in enumerate(order)}
     cfg, _ = synth.from_edges([blocks[b] for b in order], [(pos[s], pos[d], k) for (s, d, k) in edges], nvars[0])
     lx = synth.var_mask(nvars[0]).copy()
-    for (_, _, _, vmap) in instances[1:]:
-        for v in vmap[G:]:
-            lx[v >> 6] &= ~np.uint64(1 << (v & 63))
+    nroot = rc.n_vars
+    for v in range(nroot, nvars[0]):
+        lx[v >> 6] &= ~np.uint64(1 << (v & 63))
     cfg.exit_live_h = lx
     return cfg, instances, pos
 
@@ -424,33 +439,46 @@ def simulate_program(prog, ctx, results, demands: Dict[int, np.ndarray], walks: 
                      max_steps: int = 3000, max_depth: int = 30) -> Tuple[List[str], int]:
     """Random walks over a whole program, checking the per-context placements.
 
-    A call block runs its own accesses (and the host reads that ``demands``
-    adds there), then the callee from ENTRY to EXIT in the context named by
-    the last two call sites, then the caller takes a successor.  Globals keep
-    one version state across frames; locals are per activation and start
-    valid on the host.  An external callee reads every global on the host and
-    writes every global there (but the const globals).  A call made inside a
-    kernel (``prog.call_space``) runs the callee on the device: a walk through
-    it (and whatever it calls) in which every read must see a current device
+    Data lives in cells, each with a version and, per memory space, the
+    version its copy holds: the globals' cells are shared by all frames, an
+    activation gets fresh cells for its locals (valid in the space it runs in), and a
+    pointer parameter names the cell of the caller variable bound to it (so
+    one datum may have several names).  A call block runs its own accesses
+    (and the host reads that ``demands`` adds there), then the callee from
+    ENTRY to EXIT in the context named by the last two call sites, then the
+    caller takes a successor.  An external callee reads every global and its
+    arguments on the host and writes them there (but the const globals and
+    the pointer-to-const arguments).  A call made inside a kernel
+    (``prog.call_space``) runs the callee on the device: a walk through it
+    (and whatever it calls) in which every read must see a current device
     copy and every write makes the device copy the only current one; no copy
-    fires inside it.  Copies placed in the running context fire as
-    walked; every read, and every copy's source, must hold the latest
-    version; at the program's exit the live copies must be current.  A walk
-    that exceeds ``max_steps`` or ``max_depth`` stops where it is (everything
-    it did so far was checked).  Returns (violations, walks cut short)."""
+    fires inside it.  Copies placed in the running context fire as walked;
+    every read, and every copy's source, must hold the latest version; at
+    the program's exit the live copies must be current.  A walk that exceeds
+    ``max_steps`` or ``max_depth`` stops where it is (everything it did so
+    far was checked).  Returns (violations, walks cut short)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     G = prog.n_globals
+    nc = len(prog.call_proc)
     site_at: Dict[Tuple[int, int], int] = {}
-    for j in range(len(prog.call_proc)):
+    for j in range(nc):
         site_at[(int(prog.call_proc[j]), int(prog.call_block[j]))] = j
+    cspace = getattr(prog, "call_space", None)
+    cspace = np.zeros(nc, np.uint8) if cspace is None else np.asarray(cspace)
+    cg = getattr(prog, "const_globals", None)
+    const = _bitset(row_int(np.asarray(cg, np.uint64)), G) if cg is not None else np.zeros(G, bool)
+    npar = getattr(prog, "n_params", None)
+    npar = [0] * len(prog.procs) if npar is None else [int(x) for x in npar]
+    ap, av, ac = getattr(prog, "arg_ptr", None), getattr(prog, "arg_var", None), getattr(prog, "arg_const", None)
+
+    def args(j):
+        if ap is None:
+            return []
+        return [(int(av[t]), bool(ac[t]) if ac is not None else False) for t in range(int(ap[j]), int(ap[j + 1]))]
     views: Dict[int, View] = {}
     rw: Dict[int, Tuple[list, list]] = {}
     bits: Dict[tuple, _CtxBits] = {}
     dem = {j: _bitset(row_int(m), prog.procs[int(prog.call_proc[j])].n_vars) for j, m in demands.items()}
-    cspace = getattr(prog, "call_space", None)
-    cspace = np.zeros(len(prog.call_proc), np.uint8) if cspace is None else np.asarray(cspace)
-    cg = getattr(prog, "const_globals", None)
-    const = _bitset(row_int(np.asarray(cg, np.uint64)), G) if cg is not None else np.zeros(G, bool)
 
     def view(P):
         if P not in views:
@@ -471,17 +499,76 @@ def simulate_program(prog, ctx, results, demands: Dict[int, np.ndarray], walks: 
         rv = view(root)
         nv0 = rv.cfg.n_vars
         ev = [_bitset(rv.ev[0], nv0), _bitset(rv.ev[1], nv0)]
-        gver = np.zeros(G, np.int64)
-        gvs = [np.where(ev[s][:G], 0, -1).astype(np.int64) for s in (0, 1)]
+        # cells: version and per space the version held (-1: never valid)
+        ver: List[int] = [0] * G
+        hold = [[0 if ev[s][v] else -1 for v in range(G)] for s in (0, 1)]
+        counter = [1]
 
-        def frame(P, key):
-            L = prog.procs[P].n_vars - G
-            fe = ev if P == root and key == (root, ()) else [np.ones(prog.procs[P].n_vars, bool),
-                                                            np.zeros(prog.procs[P].n_vars, bool)]
-            return dict(P=P, key=key, b=prog.procs[P].entry, after=False, lver=np.zeros(L, np.int64),
-                        lvs=[np.where(fe[s][G:], 0, -1).astype(np.int64) for s in (0, 1)])
+        def new_cell(valid_h: bool, valid_d: bool) -> int:
+            ver.append(0)
+            hold[0].append(0 if valid_h else -1)
+            hold[1].append(0 if valid_d else -1)
+            return len(ver) - 1
 
-        stack = [frame(root, (root, ()))]
+        def frame(P, key, cells_of_params, on_device=False):
+            n = prog.procs[P].n_vars
+            cell = list(range(G)) + [0] * (n - G)
+            for i in range(n - G):
+                if i < len(cells_of_params):
+                    cell[G + i] = cells_of_params[i]
+                elif P == root and key == (root, ()):
+                    cell[G + i] = new_cell(bool(ev[0][G + i]), bool(ev[1][G + i]))
+                else:
+                    cell[G + i] = new_cell(not on_device, on_device)
+            return dict(P=P, key=key, b=prog.procs[P].entry, after=False, cell=cell)
+
+        def bump(c):
+            ver[c] = counter[0]
+            counter[0] += 1
+
+        def read(c, s, what):
+            if hold[s][c] != ver[c]:
+                errs.append("walk %d: stale %s (cell %d, space %d)" % (wk, what, c, s))
+
+        def write(c, s):
+            bump(c)
+            hold[s][c] = ver[c]
+
+        def copy(c, s, what):
+            if hold[1 - s][c] != ver[c]:
+                errs.append("walk %d: stale copy source into space %d at %s (cell %d)" % (wk, s, what, c))
+            hold[s][c] = ver[c]
+
+        def device_call(q, cells_of_args, consts, depth):
+            """The callee q run on the device (an external one: every global and its arguments)."""
+            if q < 0:
+                for c in list(range(G)) + list(cells_of_args):
+                    read(c, 1, "device external read")
+                for c in range(G):
+                    if not const[c]:
+                        write(c, 1)
+                for c, k in zip(cells_of_args, consts):
+                    if not k:
+                        write(c, 1)
+                return
+            Vq = view(q)
+            Rq, Wq = rw[q]
+            fq = frame(q, None, cells_of_args, on_device=True)
+            bq, n = Vq.entry, 0
+            while bq != Vq.exit and n < max_steps and depth < max_depth:
+                for v in np.nonzero(Rq[bq])[0]:
+                    read(fq["cell"][v], 1, "device function %d read in block %d" % (q, bq))
+                for v in np.nonzero(Wq[bq])[0]:
+                    write(fq["cell"][v], 1)
+                jj = site_at.get((q, bq))
+                if jj is not None:
+                    aa = args(jj)
+                    device_call(int(prog.callee[jj]), [fq["cell"][x] for x, _ in aa], [k for _, k in aa], depth + 1)
+                sq = Vq.succ[bq]
+                bq = sq[int(rng.integers(len(sq)))][0]
+                n += 1
+
+        stack = [frame(root, (root, ()), [])]
         steps = 0
         while stack and len(errs) <= 20:
             fr = stack[-1]
@@ -489,96 +576,47 @@ def simulate_program(prog, ctx, results, demands: Dict[int, np.ndarray], walks: 
             V = view(P)
             Rb, Wb = rw[P]
             cb = cbits(key)
-            ver = np.concatenate([gver, fr["lver"]])
-            vs = [np.concatenate([gvs[s], fr["lvs"][s]]) for s in (0, 1)]
-
-            def store():
-                gver[:] = ver[:G]
-                fr["lver"][:] = ver[G:]
-                for s in (0, 1):
-                    gvs[s][:] = vs[s][:G]
-                    fr["lvs"][s][:] = vs[s][G:]
-
-            def copy(mask, s, where):
-                if mask.any():
-                    bad = mask & (vs[1 - s] != ver)
-                    if bad.any():
-                        errs.append("walk %d %s: stale copy source into space %d at %s, vars %s"
-                                    % (wk, key, s, where, np.nonzero(bad)[0][:4].tolist()))
-                    vs[s] = np.where(mask, ver, vs[s])
-
-            def device_call(q, depth):
-                """The callee q run on the device (its globals only; its locals are its own)."""
-                if q < 0:
-                    bad = vs[1][:G] != ver[:G]
-                    if bad.any():
-                        errs.append("walk %d %s: external device call reads stale device globals %s"
-                                    % (wk, key, np.nonzero(bad)[0][:4].tolist()))
-                    ver[:G] += ~const
-                    vs[1][:G] = ver[:G]
-                    return
-                Vq = view(q)
-                Rq, Wq = rw[q]
-                bq, n = Vq.entry, 0
-                while bq != Vq.exit and n < max_steps and depth < max_depth:
-                    rd = Rq[bq][:G]
-                    bad = rd & (vs[1][:G] != ver[:G])
-                    if bad.any():
-                        errs.append("walk %d %s: device function %d reads stale device globals %s in block %d"
-                                    % (wk, key, q, np.nonzero(bad)[0][:4].tolist(), bq))
-                    w = Wq[bq][:G]
-                    if w.any():
-                        ver[:G] += w
-                        vs[1][:G] = np.where(w, ver[:G], vs[1][:G])
-                    jj = site_at.get((q, bq))
-                    if jj is not None:
-                        device_call(int(prog.callee[jj]), depth + 1)
-                    sq = Vq.succ[bq]
-                    bq = sq[int(rng.integers(len(sq)))][0]
-                    n += 1
-
+            cell = fr["cell"]
             if not fr["after"]:
                 for s in (0, 1):
-                    copy(cb.ie[s][b], s, "entry of %d" % b)
+                    for v in np.nonzero(cb.ie[s][b])[0]:
+                        copy(cell[v], s, "%s entry of %d" % (key, b))
                 if b == V.exit:
                     if len(stack) == 1:
                         for s in (0, 1):
-                            bad = _bitset(V.lx[s], V.cfg.n_vars) & (vs[s] != ver)
-                            if bad.any():
-                                errs.append("walk %d: stale live-out in space %d, vars %s"
-                                            % (wk, s, np.nonzero(bad)[0][:4].tolist()))
-                    store()
+                            for v in np.nonzero(_bitset(V.lx[s], V.cfg.n_vars))[0]:
+                                read(cell[v], s, "live-out")
                     stack.pop()
                     continue
                 x = V.space[b]
                 j = site_at.get((P, b))
                 rd = Rb[b] | dem[j] if j is not None and j in dem else Rb[b]
-                bad = rd & (vs[x] != ver)
-                if bad.any():
-                    errs.append("walk %d %s: stale read in block %d (space %d), vars %s"
-                                % (wk, key, b, x, np.nonzero(bad)[0][:4].tolist()))
-                if Wb[b].any():
-                    ver = ver + Wb[b].astype(np.int64)
-                    vs[x] = np.where(Wb[b], ver, vs[x])
+                for v in np.nonzero(rd)[0]:
+                    read(cell[v], x, "%s read in block %d" % (key, b))
+                for v in np.nonzero(Wb[b])[0]:
+                    write(cell[v], x)
                 fr["after"] = True
                 if j is not None and cspace[j]:
-                    device_call(int(prog.callee[j]), len(stack))
+                    aa = args(j)
+                    device_call(int(prog.callee[j]), [cell[v] for v, _ in aa], [k for _, k in aa], len(stack))
                     j = None
                 if j is not None:
                     q = int(prog.callee[j])
+                    aa = args(j)
                     if q < 0:
-                        bad = vs[0][:G] != ver[:G]
-                        if bad.any():
-                            errs.append("walk %d %s: external call at %d reads stale host globals %s"
-                                        % (wk, key, b, np.nonzero(bad)[0][:4].tolist()))
-                        ver[:G] += ~const
-                        vs[0][:G] = ver[:G]
+                        for c in list(range(G)) + [cell[v] for v, _ in aa]:
+                            read(c, 0, "%s external call at %d" % (key, b))
+                        for c in range(G):
+                            if not const[c]:
+                                write(c, 0)
+                        for v, k in aa:
+                            if not k:
+                                write(cell[v], 0)
                     else:
-                        store()
                         if len(stack) >= max_depth or steps >= max_steps:
                             cut += 1
                             break
-                        stack.append(frame(q, (q, (key[1] + (j,))[-2:])))
+                        stack.append(frame(q, (q, (key[1] + (j,))[-2:]), [cell[v] for v, _ in aa]))
                         continue
             steps += 1
             if steps >= max_steps:
@@ -587,8 +625,8 @@ def simulate_program(prog, ctx, results, demands: Dict[int, np.ndarray], walks: 
             succ = V.succ[b]
             t, e = succ[int(rng.integers(len(succ)))]
             for s in (0, 1):
-                copy(cb.ig[s][e], s, "edge %d" % e)
-            store()
+                for v in np.nonzero(cb.ig[s][e])[0]:
+                    copy(cell[v], s, "%s edge %d" % (key, e))
             fr["b"] = t
             fr["after"] = False
     return errs, cut

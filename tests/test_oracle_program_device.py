@@ -197,10 +197,10 @@ def test_external_call_keeps_a_const_global_on_the_device():
 # ---------------------------------------------------------------------------
 # planted mistakes in a copy of the interprocedural driver must be caught
 PROGRAM_MUTANTS = {
-    "device_call_writes_nothing": ("                W[blk, :gw] |= wr & gm\n", ""),
+    "device_call_writes_nothing": ("                W[blk] |= wr\n", ""),
     "device_call_reads_only_device_reads": (
-        "                    rd = rows[SUM_MAYR_H] | rows[SUM_MAYR_D] | wr",
-        "                    rd = rows[SUM_MAYR_D]"),
+        "                    r_any = rows[SUM_MAYR_H] | rows[SUM_MAYR_D] | w_any",
+        "                    r_any = rows[SUM_MAYR_D]"),
     "external_writes_const": ("    r[SUM_MAYW_H] = gm & ~c ", "    r[SUM_MAYW_H] = gm "),
     "external_stales_const": ("        r[SUM_TD_00 + k] = c if k >= 2 else 0 ",
                               "        r[SUM_TD_00 + k] = 0 "),
