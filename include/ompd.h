@@ -342,7 +342,22 @@ int ompd_serving_stats(ompd_ctx* ctx, int64_t* admitted, int64_t* completed, int
  * const_globals [gw] (NULL = none): globals that are never written (the
  * paper's rule for data behind a pointer to const, per global): a
  * procedure that writes one is rejected (OMPD_E_INVAL), and an external
- * callee neither writes them nor leaves their device copy stale.           */
+ * callee neither writes them nor leaves their device copy stale.
+ * n_params [n_procs] (NULL = all 0): procedure i's first n_params[i] locals,
+ * variables [n_globals, n_globals + n_params[i]), are pointer parameters (the
+ * data at the address a caller passes; section "Interprocedural Analysis").
+ * A procedure's shared variables are the globals and then its parameters;
+ * its summary covers them.  arg_ptr [n_calls + 1] (NULL = no arguments,
+ * arg_ptr[0] = 0, non-decreasing) and arg_var [arg_ptr[n_calls]]: call site
+ * j binds argument t (parameter t of the callee) to caller variable
+ * arg_var[arg_ptr[j] + t]; a call to a procedure passes exactly its
+ * n_params.  Each procedure is solved name by name, so a host call to a
+ * procedure (not to an external function) must bind distinct locals of the
+ * caller, none a global (OMPD_E_INVAL otherwise); a call made inside a
+ * kernel and an external call may bind any caller variables.  An external
+ * callee reads its arguments on the host and writes them there, except
+ * those with arg_const [arg_ptr[n_calls]] (NULL = none) set: pointers to
+ * const, never written.                                                    */
 typedef struct {
     int32_t n_procs, n_globals;
     const ompd_cfg* procs;            /* [n_procs] */
@@ -354,6 +369,10 @@ typedef struct {
     const int32_t* roots;             /* [n_roots] */
     const uint8_t* call_space;        /* [n_calls] or NULL */
     const uint64_t* const_globals;    /* [gw] or NULL */
+    const int32_t* n_params;          /* [n_procs] or NULL */
+    const int32_t* arg_ptr;           /* [n_calls + 1] or NULL */
+    const int32_t* arg_var;           /* [arg_ptr[n_calls]] */
+    const uint8_t* arg_const;         /* [arg_ptr[n_calls]] or NULL */
 } ompd_program;
 
 /* Enumerate the contexts (breadth first from the roots, call sites in
@@ -370,11 +389,14 @@ int ompd_program_contexts(ompd_ctx* ctx, const ompd_program* prog, int32_t* n_co
  *   boundaries  per context, in that order, 4*wd words of its procedure:
  *               entry valid host, entry valid device, exit live host, exit
  *               live device (the meet over the contexts' callers)
- *   summaries   [n_procs*16*gw] (gw = ceil(n_globals/64)) summary rows of
- *               each procedure over the globals (row order as above)
- *   demands     [n_calls*gw] globals each call site must make current on
- *               the host (read at the call block) so that the callee's
- *               context has every global valid somewhere
+ *   summaries   [n_procs*16*sw] (sw = ceil((n_globals + max n_params)/64))
+ *               summary rows of each procedure over its shared variables
+ *               (row order as above; bits past them are 0)
+ *   demands     [n_calls*sw] shared variables each call site must make
+ *               current on the host (read at the call block) so that the
+ *               callee's context has every one valid somewhere, in the
+ *               site's layout: bit v < n_globals is global v, bit
+ *               n_globals + t the caller variable bound to argument t
  *   rounds      outer rounds until demands and exit-validity caps settled
  *   solves      CFG solves run on the device                              */
 typedef struct {

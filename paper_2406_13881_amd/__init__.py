@@ -103,7 +103,8 @@ class _Res(ctypes.Structure):
 class _Prog(ctypes.Structure):
     _fields_ = [("n_procs", _i32), ("n_globals", _i32), ("procs", _vp), ("n_calls", _i32),
                 ("call_proc", _vp), ("call_block", _vp), ("callee", _vp), ("n_roots", _i32), ("roots", _vp),
-                ("call_space", _vp), ("const_globals", _vp)]
+                ("call_space", _vp), ("const_globals", _vp), ("n_params", _vp), ("arg_ptr", _vp),
+                ("arg_var", _vp), ("arg_const", _vp)]
 
 
 class _ProgRes(ctypes.Structure):
@@ -391,7 +392,34 @@ def _prog_struct(prog, keep: list) -> _Prog:
         cg = np.ascontiguousarray(np.asarray(cg, dtype=np.uint64))
         keep.append(cg)
         P.const_globals = _np_ptr(cg)
+    for name, dt in (("n_params", np.int32), ("arg_ptr", np.int32), ("arg_var", np.int32), ("arg_const", np.uint8)):
+        a = getattr(prog, name, None)
+        if a is not None:
+            a = np.ascontiguousarray(np.asarray(a, dtype=dt))
+            keep.append(a)
+            setattr(P, name, _np_ptr(a) if a.size else None)
     return P
+
+
+def shared_words(prog) -> int:
+    """Words of a program's summary and demand rows: the globals and the most pointer parameters
+    of any procedure."""
+    npar = getattr(prog, "n_params", None)
+    mx = int(np.max(npar)) if npar is not None and len(npar) else 0
+    return (int(prog.n_globals) + mx + 63) // 64
+
+
+def demand_vars(prog, j: int, row) -> List[int]:
+    """The caller variables a call site's demand row (the site's layout: globals, then one bit
+    per argument) asks to make current on the host."""
+    G = int(prog.n_globals)
+    ap, av = getattr(prog, "arg_ptr", None), getattr(prog, "arg_var", None)
+    args = [] if ap is None else [int(x) for x in av[int(ap[j]):int(ap[j + 1])]]
+    out = set()
+    for v in range(64 * len(row)):
+        if (int(row[v >> 6]) >> (v & 63)) & 1:
+            out.add(v if v < G else args[v - G])
+    return sorted(out)
 
 
 def _sigma(s0: int, s1: int) -> tuple:
@@ -421,10 +449,10 @@ def _analyze_program(self, prog, flags: int = 0, want: Sequence[str] = OUTPUTS[:
     outs = _alloc_outputs_many([prog.procs[p] for (p, _) in keys], want, R)
     wds = [(prog.procs[p].n_vars + 63) // 64 for (p, _) in keys]
     bnd = np.zeros(max(4 * sum(wds), 1), np.uint64)
-    gw = (int(prog.n_globals) + 63) // 64
-    summ = np.zeros((len(prog.procs), 16, gw), np.uint64)
+    sw = shared_words(prog)
+    summ = np.zeros((len(prog.procs), 16, sw), np.uint64)
     nc = int(np.asarray(prog.call_proc).size)
-    dem = np.zeros((nc, gw), np.uint64)
+    dem = np.zeros((nc, sw), np.uint64)
     out = _ProgRes()
     out.per_context = _vp(ctypes.addressof(R))
     out.boundaries = _np_ptr(bnd)

@@ -67,17 +67,43 @@ __device__ __forceinline__ uint64_t word_mask(int nbits, int w)
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
+// Arguments of one call site: caller variable bound to each, and for an external callee whether
+// it is a pointer to const.  A procedure's shared variables are the globals [0, G) and then its
+// pointer parameters [G, G + n_params); parameter t of the callee is the site's argument t.
+struct Args {
+    const int32_t* var;
+    const uint8_t* cst;
+    int32_t n;
+};
+
+__device__ __forceinline__ bool bit_of(const uint64_t* row, int v) { return (row[v >> 6] >> (v & 63)) & 1ull; }
+
 // Call table of one call site in the caller's variable layout: the callee's
 // summary rows on the globals (an external callee's fixed rows), the cap of
 // the callee context on the validity tables, identity for the caller's
-// locals (NU1 = 1, T[e][l] = e).
+// other variables (NU1 = 1, T[e][l] = e); then each argument's column (the
+// callee's parameter row, or an external argument's fixed one: read on the
+// host, written there unless const, the device copy stale unless const) on
+// the bound caller variable, replacing the identity on its first binding and
+// otherwise combined with what reaches it already (a global, an earlier
+// argument): may and next-use rows by OR, validity tables by AND.
 struct CallTabItem {
     uint64_t* dst;        // [16][wd]
-    const uint64_t* src;  // [16][gw] callee rows, or NULL for an external callee
-    const uint64_t* cap;  // [2][gw] host / device caps, or NULL
+    const uint64_t* src;  // [16][sw] callee rows, or NULL for an external callee
+    const uint64_t* cap;  // [2][sw] host / device caps, or NULL
     const uint64_t* cmask;   // [gw] const globals (an external callee neither writes nor stales them)
-    int32_t wd, gw, G, nv;
+    Args a;
+    int32_t wd, gw, sw, G, nv;
 };
+
+__device__ __forceinline__ bool ext_row(int r, bool cst)
+{
+    if (r == SUM_MAYR_H || r == SUM_NU0_H || r == SUM_NU1_H || r == SUM_NU1_D) return true;
+    if (r == SUM_MAYW_H) return !cst;
+    if (r >= SUM_TH && r < SUM_TH + 4) return true;
+    if (r == SUM_TD + 2 || r == SUM_TD + 3) return cst;
+    return false;
+}
 
 __global__ void __launch_bounds__(256) k_calltab(const CallTabItem* __restrict__ items, int n)
 {
@@ -86,9 +112,10 @@ __global__ void __launch_bounds__(256) k_calltab(const CallTabItem* __restrict__
         for (int x = threadIdx.x; x < SUM_ROWS * I.wd; x += blockDim.x) {
             const int r = x / I.wd, w = x % I.wd;
             const uint64_t gm = word_mask(I.G, w), lm = word_mask(I.nv, w) & ~gm;
+            const bool trow = r >= SUM_TH;
             uint64_t v = 0;
             if (w < I.gw) {
-                if (I.src) v = I.src[r * I.gw + w];
+                if (I.src) v = I.src[r * I.sw + w];
                 else {
                     const bool one = r == SUM_MAYR_H || r == SUM_NU0_H || r == SUM_NU1_H || r == SUM_NU1_D ||
                                      (r >= SUM_TH && r < SUM_TH + 4);
@@ -99,12 +126,30 @@ __global__ void __launch_bounds__(256) k_calltab(const CallTabItem* __restrict__
                 v &= gm;
                 if (I.cap) {
                     if (r >= SUM_TH && r < SUM_TH + 4) v &= I.cap[w];
-                    if (r >= SUM_TD && r < SUM_TD + 4) v &= I.cap[I.gw + w];
+                    if (r >= SUM_TD && r < SUM_TD + 4) v &= I.cap[I.sw + w];
                 }
             }
             if (r == SUM_NU1_H || r == SUM_NU1_D || r == SUM_TH + 2 || r == SUM_TH + 3 || r == SUM_TD + 2 ||
                 r == SUM_TD + 3)
                 v |= lm;
+            for (int t = 0; t < I.a.n; ++t) {
+                const int xv = I.a.var[t];
+                if ((xv >> 6) != w) continue;
+                bool col;
+                if (I.src) {
+                    const int y = I.G + t;
+                    col = bit_of(I.src + r * I.sw, y);
+                    if (I.cap && trow) col = col && bit_of(I.cap + (r < SUM_TD ? 0 : I.sw), y);
+                } else {
+                    col = ext_row(r, I.a.cst[t] != 0);
+                }
+                bool seen = xv < I.G;
+                for (int u = 0; u < t && !seen; ++u) seen = I.a.var[u] == xv;
+                const uint64_t bt = 1ull << (xv & 63);
+                if (!seen) v = col ? (v | bt) : (v & ~bt);
+                else if (!trow) { if (col) v |= bt; }
+                else if (!col) v &= ~bt;
+            }
             I.dst[r * I.wd + w] = v;
         }
     }
@@ -113,9 +158,9 @@ __global__ void __launch_bounds__(256) k_calltab(const CallTabItem* __restrict__
 // Summary rows of a procedure from one boundary evaluation (e, l): the next
 // use at its entry (e = 0 only) and the validity at its exit.
 struct SumItem {
-    uint64_t* S;          // [16][gw] rows of the procedure
+    uint64_t* S;          // [16][sw] rows of the procedure
     const uint64_t *nu_h, *nu_d, *ave_h, *ave_d;
-    int32_t entry, exit, wd, gw, G, eps, ell, rows;   // rows: bit 0 next use, bit 1 validity tables
+    int32_t entry, exit, wd, sw, sh, eps, ell, rows;   // sh: shared variables; rows: bit 0 next use, bit 1 tables
     int32_t* changed;
 };
 
@@ -123,37 +168,46 @@ __global__ void __launch_bounds__(64) k_sumgather(const SumItem* __restrict__ it
 {
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const SumItem I = items[it];
-        for (int w = threadIdx.x; w < I.gw; w += blockDim.x) {
-            const uint64_t gm = word_mask(I.G, w);
+        for (int w = threadIdx.x; w < I.sw; w += blockDim.x) {
+            const uint64_t gm = word_mask(I.sh, w);
+            const bool in = w < I.wd;
             bool ch = false;
             auto put = [&](int r, uint64_t v) {
                 v &= gm;
-                if (I.S[r * I.gw + w] != v) { I.S[r * I.gw + w] = v; ch = true; }
+                if (I.S[r * I.sw + w] != v) { I.S[r * I.sw + w] = v; ch = true; }
             };
             if ((I.rows & 1) && I.eps == 0) {
                 const int base = I.ell ? SUM_NU1_H : SUM_NU0_H;
-                put(base, I.nu_h[(size_t)I.entry * I.wd + w]);
-                put(base + 1, I.nu_d[(size_t)I.entry * I.wd + w]);
+                put(base, in ? I.nu_h[(size_t)I.entry * I.wd + w] : 0ull);
+                put(base + 1, in ? I.nu_d[(size_t)I.entry * I.wd + w] : 0ull);
             }
             if (I.rows & 2) {
-                put(SUM_TH + 2 * I.eps + I.ell, I.ave_h[(size_t)I.exit * I.wd + w]);
-                put(SUM_TD + 2 * I.eps + I.ell, I.ave_d[(size_t)I.exit * I.wd + w]);
+                put(SUM_TH + 2 * I.eps + I.ell, in ? I.ave_h[(size_t)I.exit * I.wd + w] : 0ull);
+                put(SUM_TD + 2 * I.eps + I.ell, in ? I.ave_d[(size_t)I.exit * I.wd + w] : 0ull);
             }
             if (ch) atomicOr(I.changed, 1);
         }
     }
 }
 
-// May-read / may-write rows of a procedure: its own host / device blocks
-// (reads including the demanded ones) and every callee.
+// May-read / may-write rows of a procedure over its shared variables: its
+// own host / device blocks (reads including the demanded ones and the calls
+// made inside kernels) and every host call's callee, through the bindings (a
+// callee's parameter row lands on the bound caller variable when that is one
+// of the caller's shared variables); an external callee reads every global
+// and its arguments on the host and writes them there (not the const ones).
 struct MayItem {
     uint64_t* S;
     const uint64_t *R, *W;
     const uint8_t* space;
     const int32_t* callees;   // [n_sites], -1 = external
+    const int32_t* sites;     // [n_sites] call-site ids
+    const int32_t* ap;        // [n_calls + 1] into av / ac
+    const int32_t* av;
+    const uint8_t* ac;
     const uint64_t* Sall;     // rows of every procedure
     const uint64_t* cmask;    // [gw] const globals
-    int32_t nb, wd, gw, G, n_sites;
+    int32_t nb, wd, gw, sw, G, sh, n_sites;
     int32_t* changed;
 };
 
@@ -161,24 +215,39 @@ __global__ void __launch_bounds__(64) k_may(const MayItem* __restrict__ items, i
 {
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const MayItem I = items[it];
-        for (int w = threadIdx.x; w < I.gw; w += blockDim.x) {
-            const uint64_t gm = word_mask(I.G, w);
+        for (int w = threadIdx.x; w < I.sw; w += blockDim.x) {
+            const uint64_t gm = word_mask(I.G, w), sm = word_mask(I.sh, w);
             uint64_t m[4] = {0, 0, 0, 0};
-            for (int b = 0; b < I.nb; ++b) {
-                const int d = I.space[b] ? 1 : 0;
-                m[d] |= I.R[(size_t)b * I.wd + w];
-                m[2 + d] |= I.W[(size_t)b * I.wd + w];
-            }
+            if (w < I.wd)
+                for (int b = 0; b < I.nb; ++b) {
+                    const int d = I.space[b] ? 1 : 0;
+                    m[d] |= I.R[(size_t)b * I.wd + w];
+                    m[2 + d] |= I.W[(size_t)b * I.wd + w];
+                }
             for (int k = 0; k < I.n_sites; ++k) {
-                const int q = I.callees[k];
-                if (q < 0) { m[SUM_MAYR_H] |= ~0ull; m[SUM_MAYW_H] |= ~I.cmask[w]; }
-                else
-                    for (int r = 0; r < 4; ++r) m[r] |= I.Sall[((size_t)q * SUM_ROWS + r) * I.gw + w];
+                const int q = I.callees[k], j = I.sites[k];
+                const int a0 = I.ap[j], na = I.ap[j + 1] - a0;
+                if (q < 0) {
+                    m[SUM_MAYR_H] |= gm;
+                    m[SUM_MAYW_H] |= w < I.gw ? (~I.cmask[w] & gm) : 0ull;
+                } else if (w < I.gw)
+                    for (int r = 0; r < 4; ++r) m[r] |= I.Sall[((size_t)q * SUM_ROWS + r) * I.sw + w] & gm;
+                for (int t = 0; t < na; ++t) {
+                    const int x = I.av[a0 + t];
+                    if ((x >> 6) != w || x >= I.sh) continue;
+                    const uint64_t bt = 1ull << (x & 63);
+                    if (q < 0) {
+                        m[SUM_MAYR_H] |= bt;
+                        if (!I.ac[a0 + t]) m[SUM_MAYW_H] |= bt;
+                    } else
+                        for (int r = 0; r < 4; ++r)
+                            if (bit_of(I.Sall + ((size_t)q * SUM_ROWS + r) * I.sw, I.G + t)) m[r] |= bt;
+                }
             }
             bool ch = false;
             for (int r = 0; r < 4; ++r) {
-                const uint64_t v = m[r] & gm;
-                if (I.S[r * I.gw + w] != v) { I.S[r * I.gw + w] = v; ch = true; }
+                const uint64_t v = m[r] & sm;
+                if (I.S[r * I.sw + w] != v) { I.S[r * I.sw + w] = v; ch = true; }
             }
             if (ch) atomicOr(I.changed, 1);
         }
@@ -186,11 +255,14 @@ __global__ void __launch_bounds__(64) k_may(const MayItem* __restrict__ items, i
 }
 
 // Host reads demanded at call blocks: Rd = R with the demand rows ORed in.
+// A demand is in the call site's layout: bit v < G the global v, bit G + t
+// the caller variable bound to argument t.
 struct DemandItem {
     uint64_t* Rd;
     const uint64_t* R;
-    const uint64_t* demand;   // [gw]
-    int32_t block, wd, gw;
+    const uint64_t* demand;   // [sw]
+    Args a;
+    int32_t block, wd, gw, G;
 };
 
 __global__ void __launch_bounds__(64) k_demand(const DemandItem* __restrict__ items, int n)
@@ -199,92 +271,141 @@ __global__ void __launch_bounds__(64) k_demand(const DemandItem* __restrict__ it
         const DemandItem I = items[it];
         for (int w = threadIdx.x; w < I.wd; w += blockDim.x) {
             uint64_t v = I.R[(size_t)I.block * I.wd + w];
-            if (w < I.gw) v |= I.demand[w];
+            if (w < I.gw) v |= I.demand[w] & word_mask(I.G, w);
+            for (int t = 0; t < I.a.n; ++t) {
+                const int x = I.a.var[t];
+                if ((x >> 6) == w && bit_of(I.demand, I.G + t)) v |= 1ull << (x & 63);
+            }
             I.Rd[(size_t)I.block * I.wd + w] = v;
         }
     }
 }
 
-// A call made inside a kernel: the call block (a DEVICE block) reads every global the callee
-// may read or write, in either space, and writes every global it may write; an external callee
-// reads every global and writes every one but the const globals.  ORed into the caller's rows
-// (the may sets only grow, so repeating it is harmless).
+// A call made inside a kernel: the call block (a DEVICE block) reads every variable the callee
+// may read or write, in either space, and writes every one it may write, through the bindings
+// (the globals, and the caller variable bound to each parameter); an external callee reads
+// every global and its arguments and writes them (not the const ones).  ORed into the caller's
+// rows (the may sets only grow, so repeating it is harmless).
 struct DevCallItem {
     uint64_t *Rd, *W;
-    const uint64_t* S;       // [16][gw] callee rows, or NULL for an external callee
+    const uint64_t* S;       // [16][sw] callee rows, or NULL for an external callee
     const uint64_t* cmask;   // [gw]
-    int32_t block, wd, gw, G;
+    Args a;
+    int32_t block, wd, gw, sw, G;
 };
 
 __global__ void __launch_bounds__(64) k_devcall(const DevCallItem* __restrict__ items, int n)
 {
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const DevCallItem I = items[it];
-        for (int w = threadIdx.x; w < I.gw; w += blockDim.x) {
+        for (int w = threadIdx.x; w < I.wd; w += blockDim.x) {
             const uint64_t gm = word_mask(I.G, w);
-            uint64_t rd, wr;
-            if (I.S) {
-                wr = I.S[SUM_MAYW_H * I.gw + w] | I.S[SUM_MAYW_D * I.gw + w];
-                rd = I.S[SUM_MAYR_H * I.gw + w] | I.S[SUM_MAYR_D * I.gw + w] | wr;
-            } else {
-                rd = ~0ull;
-                wr = ~I.cmask[w];
+            uint64_t rd = 0, wr = 0;
+            if (w < I.gw) {
+                if (I.S) {
+                    wr = I.S[SUM_MAYW_H * I.sw + w] | I.S[SUM_MAYW_D * I.sw + w];
+                    rd = I.S[SUM_MAYR_H * I.sw + w] | I.S[SUM_MAYR_D * I.sw + w] | wr;
+                } else {
+                    rd = ~0ull;
+                    wr = ~I.cmask[w];
+                }
+                rd &= gm;
+                wr &= gm;
             }
-            I.Rd[(size_t)I.block * I.wd + w] |= rd & gm;
-            I.W[(size_t)I.block * I.wd + w] |= wr & gm;
+            for (int t = 0; t < I.a.n; ++t) {
+                const int x = I.a.var[t];
+                if ((x >> 6) != w) continue;
+                const uint64_t bt = 1ull << (x & 63);
+                bool r, wt;
+                if (I.S) {
+                    const int y = I.G + t;
+                    wt = bit_of(I.S + SUM_MAYW_H * I.sw, y) || bit_of(I.S + SUM_MAYW_D * I.sw, y);
+                    r = wt || bit_of(I.S + SUM_MAYR_H * I.sw, y) || bit_of(I.S + SUM_MAYR_D * I.sw, y);
+                } else {
+                    r = true;
+                    wt = !I.a.cst[t];
+                }
+                if (r) rd |= bt;
+                if (wt) wr |= bt;
+            }
+            I.Rd[(size_t)I.block * I.wd + w] |= rd;
+            I.W[(size_t)I.block * I.wd + w] |= wr;
         }
     }
 }
 
-// Contribution of one solved call to the callee context it leads to, on the
-// globals: in the liveness system the caller's next use after the call (the
-// OR of next use over the call block's successors), in the validity system
-// the validity after the call block's own accesses under eager copies.  One
-// slot per call edge of the context graph keeps the latest contribution.
+// Contribution of one solved call to the callee context it leads to, in the
+// callee's shared layout (the globals, then each parameter from the caller
+// variable bound to it): in the liveness system the caller's next use after
+// the call (the OR of next use over the call block's successors), in the
+// validity system the validity after the call block's own accesses under
+// eager copies.  One slot per call edge of the context graph keeps the latest
+// contribution.
 struct ContribItem {
     const uint64_t *a_h, *a_d;   // liveness: next use (H, D); validity: eager validity (H, D)
     const uint64_t* W;
     const int32_t *succ_ptr, *succ_idx;
-    uint64_t* out;               // [2][gw] slot of the call edge
-    int32_t c, wd, gw, G, live;
+    uint64_t* out;               // [2][sw] slot of the call edge
+    Args a;
+    int32_t c, wd, gw, sw, G, live;
 };
 
 __global__ void __launch_bounds__(64) k_contrib(const ContribItem* __restrict__ items, int n)
 {
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const ContribItem I = items[it];
-        for (int w = threadIdx.x; w < I.gw; w += blockDim.x) {
-            const uint64_t gm = word_mask(I.G, w);
-            uint64_t h = 0, d = 0;
+        // the caller's word wc of the two rows
+        auto word = [&](int wc, uint64_t& h, uint64_t& d) {
+            h = 0;
+            d = 0;
             if (I.live) {
                 for (int e = I.succ_ptr[I.c]; e < I.succ_ptr[I.c + 1]; ++e) {
-                    const size_t t = (size_t)I.succ_idx[e] * I.wd + w;
+                    const size_t t = (size_t)I.succ_idx[e] * I.wd + wc;
                     h |= I.a_h[t];
                     d |= I.a_d[t];
                 }
             } else {
-                const size_t cw = (size_t)I.c * I.wd + w;
+                const size_t cw = (size_t)I.c * I.wd + wc;
                 const uint64_t wr = I.W[cw];
                 h = I.a_h[cw] | wr;
                 d = I.a_d[cw] & ~wr;
             }
-            I.out[w] = h & gm;
-            I.out[I.gw + w] = d & gm;
+        };
+        for (int w = threadIdx.x; w < I.sw; w += blockDim.x) {
+            uint64_t h = 0, d = 0;
+            if (w < I.gw) {
+                word(w, h, d);
+                const uint64_t gm = word_mask(I.G, w);
+                h &= gm;
+                d &= gm;
+            }
+            for (int t = 0; t < I.a.n; ++t) {
+                const int y = I.G + t;
+                if ((y >> 6) != w) continue;
+                const int x = I.a.var[t];
+                uint64_t xh, xd;
+                word(x >> 6, xh, xd);
+                const uint64_t bt = 1ull << (y & 63);
+                if ((xh >> (x & 63)) & 1ull) h |= bt;
+                if ((xd >> (x & 63)) & 1ull) d |= bt;
+            }
+            I.out[w] = h;
+            I.out[I.sw + w] = d;
         }
     }
 }
 
 // Meet of the latest contributions of every call edge into a context:
-// liveness by OR (exit liveness; the callee's locals are dead after it),
-// validity by AND (entry validity; the callee's locals are valid on the host
-// at its entry).  The boundary is rewritten, and the context marked, when
-// the meet differs from it.
+// liveness by OR (exit liveness; the callee's other locals are dead after
+// it), validity by AND (entry validity; the callee's other locals are valid
+// on the host at its entry).  The boundary is rewritten, and the context
+// marked, when the meet differs from it.
 struct MeetItem {
     uint64_t* bnd;               // [4][wd] of the context
-    const uint64_t* contrib;     // [n_call_edges][2][gw]
+    const uint64_t* contrib;     // [n_call_edges][2][sw]
     const int32_t* in_edges;     // call edges into the context
     int32_t* changed;
-    int32_t n_in, wd, gw, G, nv, live;
+    int32_t n_in, wd, sw, sh, nv, live;
 };
 
 __global__ void __launch_bounds__(64) k_meet(const MeetItem* __restrict__ items, int n)
@@ -293,13 +414,13 @@ __global__ void __launch_bounds__(64) k_meet(const MeetItem* __restrict__ items,
         const MeetItem I = items[it];
         bool ch = false;
         for (int w = threadIdx.x; w < I.wd; w += blockDim.x) {
-            const uint64_t gm = word_mask(I.G, w), lm = word_mask(I.nv, w) & ~gm;
+            const uint64_t gm = word_mask(I.sh, w), lm = word_mask(I.nv, w) & ~gm;
             uint64_t h = I.live ? 0ull : ~0ull, d = h;
-            if (w < I.gw) {
+            if (w < I.sw) {
                 for (int k = 0; k < I.n_in; ++k) {
-                    const uint64_t* c = I.contrib + (size_t)I.in_edges[k] * 2 * I.gw;
-                    if (I.live) { h |= c[w]; d |= c[I.gw + w]; }
-                    else { h &= c[w]; d &= c[I.gw + w]; }
+                    const uint64_t* c = I.contrib + (size_t)I.in_edges[k] * 2 * I.sw;
+                    if (I.live) { h |= c[w]; d |= c[I.sw + w]; }
+                    else { h &= c[w]; d &= c[I.sw + w]; }
                 }
             }
             const int base = I.live ? 2 : 0;
@@ -313,48 +434,61 @@ __global__ void __launch_bounds__(64) k_meet(const MeetItem* __restrict__ items,
     }
 }
 
-// Globals a context leaves valid in neither space at its entry and reads
-// there before writing them (next use at ENTRY, either space).
+// Shared variables a context leaves valid in neither space at its entry and
+// reads there before writing them (next use at ENTRY, either space).
 struct GapItem {
-    uint64_t* gap;               // [gw] of the context
+    uint64_t* gap;               // [sw] of the context
     const uint64_t *bnd, *nu_h, *nu_d;
     int32_t* any;
-    int32_t entry, wd, gw, G;
+    int32_t entry, wd, sw, sh;
 };
 
 __global__ void __launch_bounds__(64) k_gap(const GapItem* __restrict__ items, int n)
 {
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const GapItem I = items[it];
-        for (int w = threadIdx.x; w < I.gw; w += blockDim.x) {
-            const size_t ew = (size_t)I.entry * I.wd + w;
-            const uint64_t need = I.nu_h[ew] | I.nu_d[ew];
-            const uint64_t v = word_mask(I.G, w) & ~(I.bnd[w] | I.bnd[I.wd + w]) & need;
+        for (int w = threadIdx.x; w < I.sw; w += blockDim.x) {
+            uint64_t v = 0;
+            if (w < I.wd) {
+                const size_t ew = (size_t)I.entry * I.wd + w;
+                const uint64_t need = I.nu_h[ew] | I.nu_d[ew];
+                v = word_mask(I.sh, w) & ~(I.bnd[w] | I.bnd[I.wd + w]) & need;
+            }
             I.gap[w] = v;
             if (v) atomicOr(I.any, 1);
         }
     }
 }
 
-// Host-read demand at the call site leading to a context: its gaps that no
-// calling context lacks at its own entry (or every gap, when `all`).
+// Host-read demand at the call site leading to a context (the site's
+// layout, which is the context's shared layout): its gaps that no calling
+// context lacks at its own entry (a caller's gap on the variable bound to a
+// parameter counts for that parameter), or every gap, when `all`.
 struct OwnItem {
-    const uint64_t* gaps;        // [n_contexts][gw]
+    const uint64_t* gaps;        // [n_contexts][sw]
     const int32_t* callers;      // calling context of each call edge into this one
-    uint64_t* demand;            // [gw] of the leading call site
+    uint64_t* demand;            // [sw] of the leading call site
     int32_t* any;
-    int32_t x, n_callers, gw, all;
+    Args a;
+    int32_t x, n_callers, gw, sw, G, sh_caller, all;
 };
 
 __global__ void __launch_bounds__(64) k_own(const OwnItem* __restrict__ items, int n)
 {
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const OwnItem I = items[it];
-        for (int w = threadIdx.x; w < I.gw; w += blockDim.x) {
+        for (int w = threadIdx.x; w < I.sw; w += blockDim.x) {
             uint64_t inherited = 0;
             if (!I.all)
-                for (int k = 0; k < I.n_callers; ++k) inherited |= I.gaps[(size_t)I.callers[k] * I.gw + w];
-            const uint64_t own = I.gaps[(size_t)I.x * I.gw + w] & ~inherited;
+                for (int k = 0; k < I.n_callers; ++k) {
+                    const uint64_t* cg = I.gaps + (size_t)I.callers[k] * I.sw;
+                    if (w < I.gw) inherited |= cg[w] & word_mask(I.G, w);
+                    for (int t = 0; t < I.a.n; ++t) {
+                        const int y = I.G + t, x = I.a.var[t];
+                        if ((y >> 6) == w && x < I.sh_caller && bit_of(cg, x)) inherited |= 1ull << (y & 63);
+                    }
+                }
+            const uint64_t own = I.gaps[(size_t)I.x * I.sw + w] & ~inherited;
             if (own) {
                 atomicOr((unsigned long long*)&I.demand[w], (unsigned long long)own);
                 atomicOr(I.any, 1);
@@ -378,21 +512,23 @@ __global__ void __launch_bounds__(64) k_copy(const CopyItem* __restrict__ items,
     }
 }
 
-// Validity at EXIT under the final placement of a context (its callers' cap).
+// Validity at EXIT under the final placement of a context, on its shared
+// variables (its callers' cap).
 struct CapItem {
-    uint64_t* cap;            // [2][gw]
+    uint64_t* cap;            // [2][sw]
     const uint64_t *avf_h, *avf_d;
-    int32_t exit, wd, gw, G;
+    int32_t exit, wd, sw, sh;
 };
 
 __global__ void __launch_bounds__(64) k_cap(const CapItem* __restrict__ items, int n)
 {
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const CapItem I = items[it];
-        for (int w = threadIdx.x; w < I.gw; w += blockDim.x) {
-            const uint64_t gm = word_mask(I.G, w);
-            I.cap[w] = I.avf_h[(size_t)I.exit * I.wd + w] & gm;
-            I.cap[I.gw + w] = I.avf_d[(size_t)I.exit * I.wd + w] & gm;
+        for (int w = threadIdx.x; w < I.sw; w += blockDim.x) {
+            const uint64_t gm = word_mask(I.sh, w);
+            const bool in = w < I.wd;
+            I.cap[w] = in ? I.avf_h[(size_t)I.exit * I.wd + w] & gm : 0ull;
+            I.cap[I.sw + w] = in ? I.avf_d[(size_t)I.exit * I.wd + w] & gm : 0ull;
         }
     }
 }
@@ -411,7 +547,10 @@ static inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Structure {
     int n = 0, G = 0, gw = 0, nc = 0;
+    int sw = 0;                            // words of the widest shared layout (globals + parameters)
     std::vector<int> wd, nb, ne;
+    std::vector<int> sh;                   // per procedure: globals + its pointer parameters
+    std::vector<int32_t> ap;               // [nc + 1] arguments of each call site in arg_var
     std::vector<std::vector<int>> sites;   // per procedure: its host call sites in order
     std::vector<std::vector<int>> dsites;  // per procedure: its calls made inside kernels
     std::vector<int> site_k;               // call site -> index among its caller's sites
@@ -450,6 +589,40 @@ int check_program(const ompd_program* P, Structure& st)
         st.wd[i] = (g.n_vars + 63) / 64;
         st.nb[i] = g.n_blocks;
         st.ne[i] = g.n_edges;
+    }
+    // pointer parameters and the arguments bound to them
+    st.sh.assign(st.n, st.G);
+    int maxnp = 0;
+    for (int i = 0; i < st.n; ++i) {
+        const int np = P->n_params ? P->n_params[i] : 0;
+        if (np < 0 || np > P->procs[i].n_vars - st.G) return bad("bad parameter count", i);
+        st.sh[i] = st.G + np;
+        maxnp = std::max(maxnp, np);
+    }
+    st.sw = (st.G + maxnp + 63) / 64;
+    st.ap.assign(st.nc + 1, 0);
+    if (P->arg_ptr) {
+        if (P->arg_ptr[0] != 0) return bad("arg_ptr[0] is not 0", 0);
+        for (int j = 0; j < st.nc; ++j) {
+            if (P->arg_ptr[j + 1] < P->arg_ptr[j]) return bad("arg_ptr decreases", j);
+            st.ap[j + 1] = P->arg_ptr[j + 1];
+        }
+        if (st.ap[st.nc] > 0 && !P->arg_var) return bad("arg_var missing", 0);
+    }
+    for (int j = 0; j < st.nc; ++j) {
+        const int p = P->call_proc[j], q = P->callee[j], a0 = st.ap[j], na = st.ap[j + 1] - a0;
+        if (p < 0 || p >= st.n || q < -1 || q >= st.n) return bad("call site out of range", j);
+        if (q >= 0 && na != st.sh[q] - st.G) return bad("argument count differs from the callee's parameters", j);
+        const bool host_body = q >= 0 && !(P->call_space && P->call_space[j]);
+        for (int t = 0; t < na; ++t) {
+            const int x = P->arg_var[a0 + t];
+            if (x < 0 || x >= P->procs[p].n_vars) return bad("argument is not a caller variable", j);
+            if (host_body) {
+                if (x < st.G) return bad("a host call binds a global to a parameter", j);
+                for (int u = 0; u < t; ++u)
+                    if (P->arg_var[a0 + u] == x) return bad("a host call binds one variable twice", j);
+            }
+        }
     }
     st.site_k.assign(st.nc, -1);
     std::map<std::pair<int, int>, int> seen;
@@ -576,11 +749,14 @@ struct Prog {
     std::vector<uint64_t*> R, Rd, W, sbnd;   // sbnd: [4 evaluations][4][wd] summary boundaries
     std::vector<int32_t*> callees;           // [n_sites]
     std::vector<uint64_t*> ptab;             // [n_sites][16][wd] call tables of the summary evaluations
-    uint64_t* S = nullptr;                   // [n][16][gw]
+    uint64_t* S = nullptr;                   // [n][16][sw]
+    int32_t *d_ap = nullptr, *d_av = nullptr;  // call-site argument offsets and bound caller variables
+    uint8_t* d_ac = nullptr;                 // pointer-to-const flags of the arguments
+    std::vector<int32_t*> sitej;             // per procedure: its host call-site ids
     uint64_t* cmask = nullptr;               // [gw] const globals
-    uint64_t* demand = nullptr;              // [nc][gw]   (accumulated)
-    uint64_t* demand_new = nullptr;          // [nc][gw]   (this outer round)
-    uint64_t* caps = nullptr;                // [nctx][2][gw]
+    uint64_t* demand = nullptr;              // [nc][sw]   (accumulated; call-site layout)
+    uint64_t* demand_new = nullptr;          // [nc][sw]   (this outer round)
+    uint64_t* caps = nullptr;                // [nctx][2][sw]
     int32_t* flag = nullptr;                 // scratch flags
     // per context
     std::vector<uint64_t*> bnd, ctab;
@@ -590,8 +766,8 @@ struct Prog {
     std::vector<int> in_ptr;                 // [nctx+1] into in_edges / callers
     int32_t* in_edges = nullptr;             // call edges into each context
     int32_t* callers = nullptr;              // the calling context of each of those edges
-    uint64_t* contrib = nullptr;             // [n_edges][2][gw] latest contribution per edge
-    uint64_t* gaps = nullptr;                // [nctx][gw]
+    uint64_t* contrib = nullptr;             // [n_edges][2][sw] latest contribution per edge
+    uint64_t* gaps = nullptr;                // [nctx][sw]
     uint64_t* bnd0 = nullptr;                // initial boundaries, contexts back to back
     std::vector<size_t> bnd0_off;
     std::vector<uint64_t*> o_nu_h, o_nu_d, o_ave_h, o_ave_d, o_avf_h, o_avf_d, o_ie_h, o_ie_d, o_ig_h, o_ig_d;
@@ -652,11 +828,11 @@ int setup(Prog& G)
 {
     const Structure& st = G.st;
     const ompd_program* P = G.P;
-    const int n = st.n, gw = st.gw, nctx = (int)st.cproc.size();
+    const int n = st.n, gw = st.gw, sw = st.sw, nctx = (int)st.cproc.size();
     // arena layout
     size_t total = 0;
     auto take = [&](size_t bytes) { size_t x = total; total += a256(std::max<size_t>(bytes, 8)); return x; };
-    struct PO { size_t sp, si, kind, space, R, Rd, W, call, sbnd, callees, ptab, eout; };
+    struct PO { size_t sp, si, kind, space, R, Rd, W, call, sbnd, callees, sitej, ptab, eout; };
     std::vector<PO> po(n);
     for (int i = 0; i < n; ++i) {
         const size_t nb = st.nb[i], ne = st.ne[i], wd = st.wd[i], ns = st.sites[i].size();
@@ -670,14 +846,19 @@ int setup(Prog& G)
         po[i].call = take(4 * nb);
         po[i].sbnd = take(8 * 16 * wd);
         po[i].callees = take(4 * ns);
+        po[i].sitej = take(4 * ns);
         po[i].ptab = take(8 * ns * SUM_ROWS * wd);
         po[i].eout = take(8 * 16 * nb * wd);
     }
-    const size_t oS = take(8 * (size_t)n * SUM_ROWS * gw);
+    const size_t oS = take(8 * (size_t)n * SUM_ROWS * sw);
     const size_t oCm = take(8 * (size_t)std::max(gw, 1));
-    const size_t oD = take(8 * (size_t)std::max(st.nc, 1) * gw);
-    const size_t oDn = take(8 * (size_t)std::max(st.nc, 1) * gw);
-    const size_t oC = take(8 * (size_t)nctx * 2 * gw);
+    const size_t oD = take(8 * (size_t)std::max(st.nc, 1) * sw);
+    const size_t oDn = take(8 * (size_t)std::max(st.nc, 1) * sw);
+    const size_t oC = take(8 * (size_t)nctx * 2 * sw);
+    const size_t nargs = (size_t)st.ap[st.nc];
+    const size_t oAp = take(4 * ((size_t)st.nc + 1));
+    const size_t oAv = take(4 * std::max<size_t>(nargs, 1));
+    const size_t oAc = take(std::max<size_t>(nargs, 1));
     const size_t oF = take(4 * (size_t)(nctx + 16));
     // call edges of the context graph and, per context, the edges into it
     G.eid.assign(nctx, {});
@@ -701,10 +882,10 @@ int setup(Prog& G)
                 h_callers[fill[cx]++] = x;
             }
     }
-    const size_t oCb = take(8 * (size_t)std::max(G.n_edges, 1) * 2 * gw);
+    const size_t oCb = take(8 * (size_t)std::max(G.n_edges, 1) * 2 * sw);
     const size_t oIn = take(4 * h_in.size());
     const size_t oCl = take(4 * h_callers.size());
-    const size_t oGap = take(8 * (size_t)nctx * gw);
+    const size_t oGap = take(8 * (size_t)nctx * sw);
     G.bnd0_off.assign(nctx + 1, 0);
     for (int x = 0; x < nctx; ++x) G.bnd0_off[x + 1] = G.bnd0_off[x] + 4 * (size_t)st.wd[st.cproc[x]];
     const size_t oB0 = take(8 * G.bnd0_off[nctx]);
@@ -723,6 +904,7 @@ int setup(Prog& G)
     char* A = G.arena;
     G.sp.resize(n); G.si.resize(n); G.kind.resize(n); G.space.resize(n); G.R.resize(n); G.Rd.resize(n);
     G.W.resize(n); G.call.resize(n); G.sbnd.resize(n); G.callees.resize(n); G.ptab.resize(n); G.e_out.resize(n);
+    G.sitej.resize(n);
     std::vector<uint64_t> hb;
     for (int i = 0; i < n; ++i) {
         const ompd_cfg& g = P->procs[i];
@@ -732,6 +914,7 @@ int setup(Prog& G)
         G.R[i] = (uint64_t*)(A + po[i].R); G.Rd[i] = (uint64_t*)(A + po[i].Rd); G.W[i] = (uint64_t*)(A + po[i].W);
         G.call[i] = (int32_t*)(A + po[i].call); G.sbnd[i] = (uint64_t*)(A + po[i].sbnd);
         G.callees[i] = (int32_t*)(A + po[i].callees); G.ptab[i] = (uint64_t*)(A + po[i].ptab);
+        G.sitej[i] = (int32_t*)(A + po[i].sitej);
         G.e_out[i] = (uint64_t*)(A + po[i].eout);
         CK(hipMemcpyAsync(G.sp[i], g.succ_ptr, 4 * (nb + 1), hipMemcpyHostToDevice, G.s));
         if (ne) {
@@ -744,15 +927,18 @@ int setup(Prog& G)
             CK(hipMemcpyAsync(G.Rd[i], g.read_bits, 8 * nb * wd, hipMemcpyHostToDevice, G.s));
             CK(hipMemcpyAsync(G.W[i], g.write_bits, 8 * nb * wd, hipMemcpyHostToDevice, G.s));
         }
-        std::vector<int32_t> call(nb, -1), cal(std::max<size_t>(ns, 1), -1);
+        std::vector<int32_t> call(nb, -1), cal(std::max<size_t>(ns, 1), -1), sj(std::max<size_t>(ns, 1), 0);
         for (size_t k = 0; k < ns; ++k) {
             call[P->call_block[st.sites[i][k]]] = (int32_t)k;
             cal[k] = P->callee[st.sites[i][k]];
+            sj[k] = st.sites[i][k];
         }
         CK(hipMemcpyAsync(G.call[i], call.data(), 4 * nb, hipMemcpyHostToDevice, G.s));
         CK(hipMemcpyAsync(G.callees[i], cal.data(), 4 * cal.size(), hipMemcpyHostToDevice, G.s));
-        // summary boundaries, evaluation 2e+l: entry valid (e ? globals : none) on both spaces
-        // plus the locals on the host; globals live after exit in both spaces iff l
+        CK(hipMemcpyAsync(G.sitej[i], sj.data(), 4 * sj.size(), hipMemcpyHostToDevice, G.s));
+        // summary boundaries, evaluation 2e+l: entry valid (e ? shared : none) on both spaces
+        // plus the other locals on the host; the shared variables (globals and parameters) live
+        // after exit in both spaces iff l
         hb.assign(16 * wd, 0);
         for (int ev = 0; ev < 4; ++ev) {
             const int eps = ev >> 1, ell = ev & 1;
@@ -763,7 +949,7 @@ int setup(Prog& G)
                     if (bits <= lo) return 0ull;
                     return (1ull << (bits - lo)) - 1ull;
                 };
-                const uint64_t gm = mask(st.G), lm = mask(g.n_vars) & ~gm;
+                const uint64_t gm = mask(st.sh[i]), lm = mask(g.n_vars) & ~gm;
                 hb[(ev * 4 + 0) * wd + w] = (eps ? gm : 0) | lm;
                 hb[(ev * 4 + 1) * wd + w] = eps ? gm : 0;
                 hb[(ev * 4 + 2) * wd + w] = ell ? gm : 0;
@@ -775,6 +961,21 @@ int setup(Prog& G)
     }
     G.S = (uint64_t*)(A + oS);
     G.cmask = (uint64_t*)(A + oCm);
+    G.d_ap = (int32_t*)(A + oAp);
+    G.d_av = (int32_t*)(A + oAv);
+    G.d_ac = (uint8_t*)(A + oAc);
+    {
+        std::vector<int32_t> av(std::max<size_t>(nargs, 1), 0);
+        std::vector<uint8_t> ac(std::max<size_t>(nargs, 1), 0);
+        for (size_t t = 0; t < nargs; ++t) {
+            av[t] = P->arg_var[t];
+            ac[t] = P->arg_const ? (P->arg_const[t] ? 1 : 0) : 0;
+        }
+        CK(hipMemcpyAsync(G.d_ap, st.ap.data(), 4 * st.ap.size(), hipMemcpyHostToDevice, G.s));
+        CK(hipMemcpyAsync(G.d_av, av.data(), 4 * av.size(), hipMemcpyHostToDevice, G.s));
+        CK(hipMemcpyAsync(G.d_ac, ac.data(), ac.size(), hipMemcpyHostToDevice, G.s));
+        CK(hipStreamSynchronize(G.s));
+    }
     {
         std::vector<uint64_t> cm(std::max(gw, 1), 0);
         if (P->const_globals)
@@ -786,7 +987,7 @@ int setup(Prog& G)
     G.demand_new = (uint64_t*)(A + oDn);
     G.caps = (uint64_t*)(A + oC);
     G.flag = (int32_t*)(A + oF);
-    CK(hipMemsetAsync(G.demand, 0, 8 * (size_t)std::max(st.nc, 1) * gw, G.s));
+    CK(hipMemsetAsync(G.demand, 0, 8 * (size_t)std::max(st.nc, 1) * sw, G.s));
     G.contrib = (uint64_t*)(A + oCb);
     G.in_edges = (int32_t*)(A + oIn);
     G.callers = (int32_t*)(A + oCl);
@@ -795,8 +996,8 @@ int setup(Prog& G)
     CK(hipMemcpyAsync(G.in_edges, h_in.data(), 4 * h_in.size(), hipMemcpyHostToDevice, G.s));
     CK(hipMemcpyAsync(G.callers, h_callers.data(), 4 * h_callers.size(), hipMemcpyHostToDevice, G.s));
     // initial boundaries: a root context its procedure's own (defaults: valid and live on the
-    // host only); any other context valid everywhere on the globals (the top of the validity
-    // meet), its locals valid on the host, nothing live after its exit
+    // host only); any other context valid everywhere on its shared variables (the top of the
+    // validity meet), its other locals valid on the host, nothing live after its exit
     {
         std::vector<uint64_t> b0(std::max<size_t>(G.bnd0_off[nctx], 1), 0);
         for (int x = 0; x < nctx; ++x) {
@@ -811,7 +1012,7 @@ int setup(Prog& G)
                     if (bits <= lo) return 0ull;
                     return (1ull << (bits - lo)) - 1ull;
                 };
-                const uint64_t vm = mask(g.n_vars), gm = mask(st.G);
+                const uint64_t vm = mask(g.n_vars), gm = mask(st.sh[p]);
                 if (st.cs1[x] < 0) {
                     b[w] = g.entry_valid_host ? g.entry_valid_host[w] : vm;
                     b[wd + w] = g.entry_valid_dev ? g.entry_valid_dev[w] : 0;
@@ -850,6 +1051,15 @@ int setup(Prog& G)
     return OMPD_OK;
 }
 
+Args site_args(const Prog& G, int j)
+{
+    Args a;
+    a.var = G.d_av + G.st.ap[j];
+    a.cst = G.d_ac + G.st.ap[j];
+    a.n = G.st.ap[j + 1] - G.st.ap[j];
+    return a;
+}
+
 // Call tables of procedure p for the summary evaluations (no caps) or of
 // context x (caps of the callee contexts when they exist).
 void calltab_items(Prog& G, int p, int x, std::vector<CallTabItem>& out)
@@ -860,14 +1070,15 @@ void calltab_items(Prog& G, int p, int x, std::vector<CallTabItem>& out)
         const int j = st.sites[p][k], q = G.P->callee[j];
         CallTabItem I;
         I.dst = (x < 0 ? G.ptab[p] : G.ctab[x]) + k * SUM_ROWS * wd;
-        I.src = q < 0 ? nullptr : G.S + (size_t)q * SUM_ROWS * st.gw;
+        I.src = q < 0 ? nullptr : G.S + (size_t)q * SUM_ROWS * st.sw;
         I.cap = nullptr;
         if (x >= 0 && q >= 0) {
             const int cx = st.child[x][k];
-            if (cx >= 0 && G.cap_valid[cx]) I.cap = G.caps + (size_t)cx * 2 * st.gw;
+            if (cx >= 0 && G.cap_valid[cx]) I.cap = G.caps + (size_t)cx * 2 * st.sw;
         }
         I.cmask = G.cmask;
-        I.wd = (int32_t)wd; I.gw = st.gw; I.G = st.G; I.nv = G.P->procs[p].n_vars;
+        I.a = site_args(G, j);
+        I.wd = (int32_t)wd; I.gw = st.gw; I.sw = st.sw; I.G = st.G; I.nv = G.P->procs[p].n_vars;
         out.push_back(I);
     }
 }
@@ -925,10 +1136,10 @@ int evaluate(Prog& G, const std::vector<int>& procs, int rows, int& changed)
         for (int ev = 0; ev < 4; ++ev) {
             SumItem I;
             const uint64_t* o = G.e_out[p] + (size_t)ev * 4 * bv;
-            I.S = G.S + (size_t)p * SUM_ROWS * st.gw;
+            I.S = G.S + (size_t)p * SUM_ROWS * st.sw;
             I.nu_h = o; I.nu_d = o + bv; I.ave_h = o + 2 * bv; I.ave_d = o + 3 * bv;
             I.entry = G.P->procs[p].entry; I.exit = G.P->procs[p].exit;
-            I.wd = (int32_t)wd; I.gw = st.gw; I.G = st.G; I.eps = ev >> 1; I.ell = ev & 1; I.rows = rows;
+            I.wd = (int32_t)wd; I.sw = st.sw; I.sh = st.sh[p]; I.eps = ev >> 1; I.ell = ev & 1; I.rows = rows;
             I.changed = G.flag;
             si.push_back(I);
         }
@@ -946,10 +1157,12 @@ int may_rows(Prog& G, const std::vector<int>& procs, int& changed)
     std::vector<MayItem> mi;
     for (int p : procs) {
         MayItem I;
-        I.S = G.S + (size_t)p * SUM_ROWS * st.gw;
+        I.S = G.S + (size_t)p * SUM_ROWS * st.sw;
         I.R = G.Rd[p]; I.W = G.W[p]; I.space = G.space[p];
-        I.callees = G.callees[p]; I.Sall = G.S; I.cmask = G.cmask;
-        I.nb = st.nb[p]; I.wd = st.wd[p]; I.gw = st.gw; I.G = st.G; I.n_sites = (int32_t)st.sites[p].size();
+        I.callees = G.callees[p]; I.sites = G.sitej[p]; I.ap = G.d_ap; I.av = G.d_av; I.ac = G.d_ac;
+        I.Sall = G.S; I.cmask = G.cmask;
+        I.nb = st.nb[p]; I.wd = st.wd[p]; I.gw = st.gw; I.sw = st.sw; I.G = st.G; I.sh = st.sh[p];
+        I.n_sites = (int32_t)st.sites[p].size();
         I.changed = G.flag;
         mi.push_back(I);
     }
@@ -971,9 +1184,10 @@ int device_calls(Prog& G, const std::vector<int>& procs)
             const int q = G.P->callee[j];
             DevCallItem I;
             I.Rd = G.Rd[p]; I.W = G.W[p];
-            I.S = q < 0 ? nullptr : G.S + (size_t)q * SUM_ROWS * st.gw;
+            I.S = q < 0 ? nullptr : G.S + (size_t)q * SUM_ROWS * st.sw;
             I.cmask = G.cmask;
-            I.block = G.P->call_block[j]; I.wd = st.wd[p]; I.gw = st.gw; I.G = st.G;
+            I.a = site_args(G, j);
+            I.block = G.P->call_block[j]; I.wd = st.wd[p]; I.gw = st.gw; I.sw = st.sw; I.G = st.G;
             it.push_back(I);
         }
     return upload_items(it, k_devcall, 64, G.s, G.arena_items);
@@ -985,10 +1199,9 @@ int device_calls(Prog& G, const std::vector<int>& procs)
 int summarize(Prog& G)
 {
     const Structure& st = G.st;
-    CK(hipMemsetAsync(G.S, 0, 8 * (size_t)st.n * SUM_ROWS * st.gw, G.s));
+    CK(hipMemsetAsync(G.S, 0, 8 * (size_t)st.n * SUM_ROWS * st.sw, G.s));
     int max_level = 0;
     for (int l : st.comp_level) max_level = std::max(max_level, l);
-    std::vector<uint64_t> ones(4 * (size_t)st.gw * 2, 0);
     for (int level = 0; level <= max_level; ++level) {
         std::vector<int> single, recur_procs;
         std::vector<const std::vector<int>*> recur;
@@ -1014,16 +1227,19 @@ int summarize(Prog& G)
         rc = may_rows(G, single, ch);
         if (rc) return rc;
         if (recur_procs.empty()) continue;
-        // recursive components: validity tables start at all ones over the globals
-        std::vector<uint64_t> row(8 * (size_t)st.gw);
-        for (int w = 0; w < st.gw; ++w) {
-            const int lo = 64 * w;
-            const uint64_t gm = st.G >= lo + 64 ? ~0ull : (st.G <= lo ? 0ull : (1ull << (st.G - lo)) - 1ull);
-            for (int k = 0; k < 8; ++k) row[(size_t)k * st.gw + w] = gm;
-        }
-        for (int p : recur_procs)
-            CK(hipMemcpyAsync(G.S + ((size_t)p * SUM_ROWS + SUM_TH) * st.gw, row.data(), 8 * row.size(),
+        // recursive components: validity tables start at all ones over the shared variables
+        std::vector<uint64_t> rows(8 * (size_t)st.sw * recur_procs.size());
+        for (size_t i = 0; i < recur_procs.size(); ++i) {
+            const int sh = st.sh[recur_procs[i]];
+            uint64_t* row = rows.data() + 8 * (size_t)st.sw * i;
+            for (int w = 0; w < st.sw; ++w) {
+                const int lo = 64 * w;
+                const uint64_t gm = sh >= lo + 64 ? ~0ull : (sh <= lo ? 0ull : (1ull << (sh - lo)) - 1ull);
+                for (int k = 0; k < 8; ++k) row[(size_t)k * st.sw + w] = gm;
+            }
+            CK(hipMemcpyAsync(G.S + ((size_t)recur_procs[i] * SUM_ROWS + SUM_TH) * st.sw, row, 8 * 8 * (size_t)st.sw,
                               hipMemcpyHostToDevice, G.s));
+        }
         CK(hipStreamSynchronize(G.s));
         // may sets first (calls made inside kernels feed them into the callers' rows), then next
         // use from 0, then validity tables from all ones
@@ -1089,7 +1305,7 @@ int boundary_system(Prog& G, int live)
 {
     const Structure& st = G.st;
     const ompd_program* P = G.P;
-    const int nctx = (int)st.cproc.size(), gw = st.gw;
+    const int nctx = (int)st.cproc.size(), sw = st.sw;
     std::vector<int> dirty(nctx);
     for (int x = 0; x < nctx; ++x) dirty[x] = x;
     std::vector<char> is_t(nctx, 0);
@@ -1109,8 +1325,10 @@ int boundary_system(Prog& G, int live)
                 I.a_h = live ? G.o_nu_h[x] : G.o_ave_h[x];
                 I.a_d = live ? G.o_nu_d[x] : G.o_ave_d[x];
                 I.W = G.W[p]; I.succ_ptr = G.sp[p]; I.succ_idx = G.si[p];
-                I.out = G.contrib + (size_t)G.eid[x][k] * 2 * gw;
-                I.c = P->call_block[st.sites[p][k]]; I.wd = st.wd[p]; I.gw = gw; I.G = st.G; I.live = live;
+                I.out = G.contrib + (size_t)G.eid[x][k] * 2 * sw;
+                I.a = site_args(G, st.sites[p][k]);
+                I.c = P->call_block[st.sites[p][k]]; I.wd = st.wd[p]; I.gw = st.gw; I.sw = sw; I.G = st.G;
+                I.live = live;
                 cb.push_back(I);
             }
         }
@@ -1125,7 +1343,7 @@ int boundary_system(Prog& G, int live)
             MeetItem I;
             I.bnd = G.bnd[cx]; I.contrib = G.contrib; I.in_edges = G.in_edges + G.in_ptr[cx];
             I.changed = chg + cx; I.n_in = G.in_ptr[cx + 1] - G.in_ptr[cx];
-            I.wd = st.wd[q]; I.gw = gw; I.G = st.G; I.nv = P->procs[q].n_vars; I.live = live;
+            I.wd = st.wd[q]; I.sw = sw; I.sh = st.sh[q]; I.nv = P->procs[q].n_vars; I.live = live;
             mi.push_back(I);
         }
         rc = upload_items(mi, k_meet, 64, G.s, G.arena_items);
@@ -1151,8 +1369,8 @@ int contexts(Prog& G)
 {
     const Structure& st = G.st;
     const ompd_program* P = G.P;
-    const int nctx = (int)st.cproc.size(), gw = st.gw;
-    CK(hipMemsetAsync(G.demand_new, 0, 8 * (size_t)std::max(st.nc, 1) * gw, G.s));
+    const int nctx = (int)st.cproc.size(), sw = st.sw;
+    CK(hipMemsetAsync(G.demand_new, 0, 8 * (size_t)std::max(st.nc, 1) * sw, G.s));
     std::vector<CopyItem> cp;
     for (int x = 0; x < nctx; ++x) {
         CopyItem I;
@@ -1165,8 +1383,8 @@ int contexts(Prog& G)
     if (rc) return rc;
     rc = boundary_system(G, 0);
     if (rc) return rc;
-    if (!gw) return OMPD_OK;
-    CK(hipMemsetAsync(G.gaps, 0, 8 * (size_t)nctx * gw, G.s));
+    if (!sw) return OMPD_OK;
+    CK(hipMemsetAsync(G.gaps, 0, 8 * (size_t)nctx * sw, G.s));
     int32_t* any = G.flag;
     CK(hipMemsetAsync(any, 0, 8, G.s));
     std::vector<GapItem> gi;
@@ -1175,12 +1393,14 @@ int contexts(Prog& G)
         if (st.cs1[x] < 0) continue;
         const int p = st.cproc[x];
         GapItem I;
-        I.gap = G.gaps + (size_t)x * gw; I.bnd = G.bnd[x]; I.nu_h = G.o_nu_h[x]; I.nu_d = G.o_nu_d[x];
-        I.any = any; I.entry = P->procs[p].entry; I.wd = st.wd[p]; I.gw = gw; I.G = st.G;
+        I.gap = G.gaps + (size_t)x * sw; I.bnd = G.bnd[x]; I.nu_h = G.o_nu_h[x]; I.nu_d = G.o_nu_d[x];
+        I.any = any; I.entry = P->procs[p].entry; I.wd = st.wd[p]; I.sw = sw; I.sh = st.sh[p];
         gi.push_back(I);
+        const int j = st.cs1[x];
         OwnItem O;
-        O.gaps = G.gaps; O.callers = G.callers + G.in_ptr[x]; O.demand = G.demand_new + (size_t)st.cs1[x] * gw;
-        O.any = any + 1; O.x = x; O.n_callers = G.in_ptr[x + 1] - G.in_ptr[x]; O.gw = gw; O.all = 0;
+        O.gaps = G.gaps; O.callers = G.callers + G.in_ptr[x]; O.demand = G.demand_new + (size_t)j * sw;
+        O.any = any + 1; O.a = site_args(G, j); O.x = x; O.n_callers = G.in_ptr[x + 1] - G.in_ptr[x];
+        O.gw = st.gw; O.sw = sw; O.G = st.G; O.sh_caller = st.sh[P->call_proc[j]]; O.all = 0;
         oi.push_back(O);
     }
     rc = upload_items(gi, k_gap, 64, G.s, G.arena_items);
@@ -1233,9 +1453,9 @@ extern "C" int ompd_analyze_program(ompd_ctx* ctx, const ompd_program* prog, omp
     rc = setup(G);
     if (rc) return rc;
     const Structure& st = G.st;
-    const int nctx = (int)st.cproc.size(), gw = st.gw;
+    const int nctx = (int)st.cproc.size(), sw = st.sw;   // rows over the shared layout
     G.cap_valid.assign(nctx, 0);
-    std::vector<uint64_t> dem((size_t)std::max(st.nc, 1) * gw, 0), dnew(dem.size()), capv((size_t)nctx * 2 * gw),
+    std::vector<uint64_t> dem((size_t)std::max(st.nc, 1) * sw, 0), dnew(dem.size()), capv((size_t)nctx * 2 * sw),
         capn(capv.size());
     int rounds = 0;
     bool settled = false;
@@ -1251,40 +1471,44 @@ extern "C" int ompd_analyze_program(ompd_ctx* ctx, const ompd_program* prog, omp
             if (st.cs1[x] < 0) continue;
             const int p = st.cproc[x];
             CapItem I;
-            I.cap = G.caps + (size_t)x * 2 * gw;
+            I.cap = G.caps + (size_t)x * 2 * sw;
             I.avf_h = G.o_avf_h[x]; I.avf_d = G.o_avf_d[x];
-            I.exit = prog->procs[p].exit; I.wd = st.wd[p]; I.gw = gw; I.G = st.G;
+            I.exit = prog->procs[p].exit; I.wd = st.wd[p]; I.sw = sw; I.sh = st.sh[p];
             ci.push_back(I);
         }
         // previous caps, for the comparison
-        if (gw) CK(hipMemcpyAsync(capv.data(), G.caps, 8 * capv.size(), hipMemcpyDeviceToHost, G.s));
+        if (sw) CK(hipMemcpyAsync(capv.data(), G.caps, 8 * capv.size(), hipMemcpyDeviceToHost, G.s));
         CK(hipStreamSynchronize(G.s));
         rc = upload_items(ci, k_cap, 64, G.s, G.arena_items);
         if (rc) return rc;
-        if (gw) CK(hipMemcpyAsync(capn.data(), G.caps, 8 * capn.size(), hipMemcpyDeviceToHost, G.s));
-        if (st.nc && gw) CK(hipMemcpyAsync(dnew.data(), G.demand_new, 8 * (size_t)st.nc * gw, hipMemcpyDeviceToHost, G.s));
+        if (sw) CK(hipMemcpyAsync(capn.data(), G.caps, 8 * capn.size(), hipMemcpyDeviceToHost, G.s));
+        if (st.nc && sw) CK(hipMemcpyAsync(dnew.data(), G.demand_new, 8 * (size_t)st.nc * sw, hipMemcpyDeviceToHost, G.s));
         CK(hipStreamSynchronize(G.s));
         bool grew = false;
         for (int x = 0; x < nctx; ++x) {
             if (st.cs1[x] < 0) continue;
             bool same = G.cap_valid[x];
-            for (int w = 0; w < 2 * gw && same; ++w) same = capv[(size_t)x * 2 * gw + w] == capn[(size_t)x * 2 * gw + w];
+            for (int w = 0; w < 2 * sw && same; ++w) same = capv[(size_t)x * 2 * sw + w] == capn[(size_t)x * 2 * sw + w];
             if (!same) grew = true;
             G.cap_valid[x] = 1;
         }
-        for (size_t k = 0; k < (size_t)st.nc * gw; ++k) {
+        for (size_t k = 0; k < (size_t)st.nc * sw; ++k) {
             const uint64_t v = dem[k] | dnew[k];
             if (v != dem[k]) { dem[k] = v; grew = true; }
         }
         if (!grew) { settled = true; break; }
         // apply the demands: reads at the call blocks
-        if (st.nc && gw) CK(hipMemcpyAsync(G.demand, dem.data(), 8 * (size_t)st.nc * gw, hipMemcpyHostToDevice, G.s));
+        if (st.nc && sw) CK(hipMemcpyAsync(G.demand, dem.data(), 8 * (size_t)st.nc * sw, hipMemcpyHostToDevice, G.s));
+        // (only a host call to a procedure leads to a context, so only such a site has a demand;
+        // its bit n_globals + t is argument t, t < the callee's parameters)
         std::vector<DemandItem> di;
         for (int j = 0; j < st.nc; ++j) {
+            if (st.site_k[j] < 0 || prog->callee[j] < 0) continue;
             const int p = prog->call_proc[j];
             DemandItem I;
-            I.Rd = G.Rd[p]; I.R = G.R[p]; I.demand = G.demand + (size_t)j * gw;
-            I.block = prog->call_block[j]; I.wd = st.wd[p]; I.gw = gw;
+            I.Rd = G.Rd[p]; I.R = G.R[p]; I.demand = G.demand + (size_t)j * sw;
+            I.a = site_args(G, j);
+            I.block = prog->call_block[j]; I.wd = st.wd[p]; I.gw = st.gw; I.G = st.G;
             di.push_back(I);
         }
         rc = upload_items(di, k_demand, 64, G.s, G.arena_items);
@@ -1294,10 +1518,10 @@ extern "C" int ompd_analyze_program(ompd_ctx* ctx, const ompd_program* prog, omp
     out->solves = G.solves;
     if (!settled) return ompd_fail(OMPD_E_NOCONVERGE, "program: demands and caps did not settle in 64 rounds");
     // results to the host
-    if (out->summaries && gw)
-        CK(hipMemcpyAsync(out->summaries, G.S, 8 * (size_t)st.n * SUM_ROWS * gw, hipMemcpyDeviceToHost, G.s));
-    if (out->demands && st.nc && gw)
-        memcpy(out->demands, dem.data(), 8 * (size_t)st.nc * gw);
+    if (out->summaries && sw)
+        CK(hipMemcpyAsync(out->summaries, G.S, 8 * (size_t)st.n * SUM_ROWS * sw, hipMemcpyDeviceToHost, G.s));
+    if (out->demands && st.nc && sw)
+        memcpy(out->demands, dem.data(), 8 * (size_t)st.nc * sw);
     // Per-context results: each context's region of the arena (boundaries, tables, outputs) is
     // contiguous and the regions follow each other, so runs of contexts go to a pinned staging
     // buffer in one copy and are scattered to the caller's arrays on the host (thousands of

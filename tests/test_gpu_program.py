@@ -14,6 +14,7 @@ import pytest
 import synth
 from checkers import simulate_program
 from oracle.program import ProgramOracle
+from paper_2406_13881_amd import demand_vars
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +38,6 @@ def ctx():
 def compare(prog, got, tag):
     po = ProgramOracle(prog)
     S, ctxb, results = po.analyze()
-    gw = (prog.n_globals + 63) // 64
     keys = got["contexts"]
     assert sorted(keys) == sorted(results.keys()), "%s: context sets differ" % tag
     for k, key in enumerate(keys):
@@ -50,10 +50,13 @@ def compare(prog, got, tag):
             assert np.array_equal(got["boundaries"][k][i], np.asarray(ctxb[key][i])), \
                 "%s: context %s boundary %d differs" % (tag, key, i)
     for p in range(len(prog.procs)):
-        assert np.array_equal(got["summaries"][p], S[p]), "%s: summary of procedure %d differs" % (tag, p)
+        w = S[p].shape[1]
+        assert np.array_equal(got["summaries"][p][:, :w], S[p]), "%s: summary of procedure %d differs" % (tag, p)
+        assert not got["summaries"][p][:, w:].any(), "%s: summary of procedure %d past its width" % (tag, p)
     for j in range(len(prog.call_proc)):
-        want = po.demand[j][:gw] if j in po.demand else np.zeros(gw, np.uint64)
-        assert np.array_equal(got["demands"][j], want), "%s: demand of call site %d differs" % (tag, j)
+        caller = prog.procs[int(prog.call_proc[j])]
+        want = sorted(v for v in range(caller.n_vars) if j in po.demand and (int(po.demand[j][v >> 6]) >> (v & 63)) & 1)
+        assert demand_vars(prog, j, got["demands"][j]) == want, "%s: demand of call site %d differs" % (tag, j)
     return po
 
 
@@ -91,6 +94,57 @@ def test_program_device_calls_and_const_globals(ctx, kind):
                   if prog.call_space is not None else 0))
         got = ctx.analyze_program(prog)
         compare(prog, got, "%s/%d" % (kind, seed))
+
+
+@pytest.mark.parametrize("kind", ["plain", "recursive", "device_external", "multiword"])
+def test_program_pointer_parameters(ctx, kind):
+    """By-reference pointer parameters (host calls bind distinct locals; calls made inside
+    kernels and external calls may bind anything), against the oracle driver: every context,
+    boundary, summary and demand."""
+    extra = {"plain": dict(max_params=3),
+             "recursive": dict(max_params=3, scc_procs=4, scc_size=(2, 3), mean_calls=1.0),
+             "device_external": dict(n_procs=8, max_params=3, max_ext_args=3, external_frac=0.3,
+                                     device_call_frac=0.3, n_const=2, scc_procs=4, scc_size=(2, 3)),
+             "multiword": dict(n_procs=8, n_globals=60, n_locals=30, max_params=12, max_ext_args=4,
+                               external_frac=0.2, device_call_frac=0.2, scc_procs=2, scc_size=(2, 2))}[kind]
+    for seed in range(5):
+        prm = dict(SMALL)
+        prm.update(extra)
+        prog = synth.program(33_000 + 100 * len(kind) + seed, **prm)
+        _print("program params %s seed %d: %d procs %d calls %d arguments"
+               % (kind, seed, len(prog.procs), len(prog.call_proc), int(prog.arg_ptr[-1])))
+        got = ctx.analyze_program(prog)
+        compare(prog, got, "params-%s/%d" % (kind, seed))
+
+
+def test_program_parameter_demands(ctx):
+    """Programs whose merged call strings leave a parameter valid nowhere: the demand (a host
+    read of the caller variable bound to it) and everything else equal the oracle's."""
+    sys.path.insert(0, __import__("os").path.dirname(__file__))
+    from test_oracle_program_params import MERGE_PARAM_SEEDS, merge_params_program
+    for seed in MERGE_PARAM_SEEDS:
+        prog = merge_params_program(27_000 + seed)
+        got = ctx.analyze_program(prog)
+        po = compare(prog, got, "merge-params/%d" % seed)
+        assert demand_vars(prog, 3, got["demands"][3]) and po.demand
+
+
+def test_program_rejects_aliasing_host_calls(ctx):
+    import paper_2406_13881_amd as ompd
+    prog = synth.program(33_999, **dict(SMALL, max_params=3))
+    j = next(j for j in range(len(prog.call_proc)) if int(prog.n_params[int(prog.callee[j])]) >= 2)
+    prog.arg_var = prog.arg_var.copy()
+    prog.arg_var[int(prog.arg_ptr[j]) + 1] = prog.arg_var[int(prog.arg_ptr[j])]
+    with pytest.raises(ompd.OmpdError):
+        ctx.analyze_program(prog)
+
+
+def test_program_c4_shape_parameters(ctx):
+    prog = synth.c4(n_procs=120, max_params=4, max_ext_args=3, device_call_frac=0.1, external_frac=0.05)
+    _print("c4-shaped with parameters: %d procs %d calls %d arguments"
+           % (len(prog.procs), len(prog.call_proc), int(prog.arg_ptr[-1])))
+    got = ctx.analyze_program(prog)
+    compare(prog, got, "c4-120-params")
 
 
 def test_program_c4_shape_device_calls(ctx):

@@ -391,6 +391,70 @@ def test_external_call_through_a_pointer_to_const_does_not_write_the_parameter()
         assert bit(S[1][SUM_MAYW_D], 0) == 0
 
 
+def merge_params_program(seed, n_globals=4):
+    """Root R passes its local x to A at two sites; A passes its parameter on to B, B to C.
+    The call strings (site 0, A->B, B->C) and (site 1, A->B, B->C) meet in C's context, so
+    the two paths into C can leave the parameter fresh in different spaces.  Every other
+    block is a random host or device statement over the globals and the local or parameter
+    (x in R, the parameter in C; A and B only pass it on)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    G = n_globals
+    nv = G + 2
+
+    def stmt(p=0.3, par=True):
+        dev = int(rng.random() < 0.5)
+        pool = list(range(G)) + ([G] if par else [])
+        rd = [v for v in pool if rng.random() < p]
+        wr = [v for v in pool if rng.random() < p]
+        return (dev, rd, wr)
+
+    def chain(body):
+        blocks = [(0, [], [])] + body + [(0, [], [])]
+        edges = [(i, i + 1, 0) for i in range(len(blocks) - 1)]
+        return synth.from_edges(blocks, edges, nv)[0]
+
+    call = (0, [], [])
+    root = chain([stmt(), call, stmt(), stmt(), call, stmt()])          # calls at blocks 2 and 5
+    root.exit_live_h = np.zeros(root.wd, np.uint64)
+    a = chain([stmt(0.1, False), call, stmt(0.1, False)])              # call at block 2
+    b = chain([call, stmt(0.1, False)])                                # call at block 1
+    c = chain([stmt(0.3), stmt(0.3)])
+    return synth.Program(procs=[root, a, b, c], n_globals=G,
+                         call_proc=np.array([0, 0, 1, 2], np.int32), call_block=np.array([2, 5, 2, 1], np.int32),
+                         callee=np.array([1, 1, 2, 3], np.int32), roots=[0],
+                         n_params=np.array([0, 1, 1, 1], np.int32), arg_ptr=np.array([0, 1, 2, 3, 4], np.int32),
+                         arg_var=np.array([G, G, G, G], np.int32), arg_const=np.zeros(4, np.uint8))
+
+
+# seeds (of 1,500 tried) whose program needs a host read of B's parameter at B's call of C
+MERGE_PARAM_SEEDS = (44, 156, 260, 319, 371, 550, 586, 596, 727, 973, 1008, 1085, 1494)
+
+
+def test_parameter_demands_are_needed_and_make_the_program_safe():
+    """A parameter valid nowhere at a merged context's entry is demanded at the leading call
+    site as a host read of the caller variable bound to it; dropping the demand reopens the gap
+    in the callee context; with the demands the walks find nothing stale."""
+    seen = 0
+    for seed in MERGE_PARAM_SEEDS:
+        p = merge_params_program(27_000 + seed)
+        po = ProgramOracle(p)
+        _, ctx, results = po.analyze()
+        G = p.n_globals
+        m = po.demand.get(3)
+        assert m is not None and bit(m, G), seed
+        seen += 1
+        po2 = ProgramOracle(p)
+        po2.demand = {jj: mm.copy() for jj, mm in po.demand.items()}
+        po2.cap = dict(po.cap)
+        po2.demand[3][G >> 6] &= ~np.uint64(1 << (G & 63))
+        S2 = po2.summarize()
+        po2.contexts(S2)
+        assert any(k[0] == 3 and bit(nw, G) for k, nw in po2.nowhere.items()), seed
+        errs, _ = simulate_program(p, ctx, results, po.demand, walks=40, seed=seed)
+        assert not errs, errs[:3]
+    assert seen == len(MERGE_PARAM_SEEDS)
+
+
 # ---------------------------------------------------------------------------
 # planted mistakes in a copy of the interprocedural driver must be caught
 PARAM_MUTANTS = {
@@ -405,6 +469,8 @@ PARAM_MUTANTS = {
                                 "                            s[r, w] &= ~bit",
                                 "                    for r in T_ROWS:\n                        if col[r]:\n"
                                 "                            s[r, w] |= bit"),
+    "demand_kept_on_globals": ("            d |= self._to_caller(jj, q, bits, P2)",
+                               "            d[:gw] |= bits[:gw] & _gmask(G, gw)"),
     "argument_cap_ignored": ("                            col[SUM_TH_00 + k4] &= ch\n                            col[SUM_TD_00 + k4] &= cd\n",
                              "                            pass\n"),
 }
@@ -450,6 +516,16 @@ def _pins_hold(PO):
             po = PO(p)
             _, _, results = po.analyze()
             if exceeds_callee_exit(po, p, results):
+                return False
+        for seed in MERGE_PARAM_SEEDS[:4]:
+            p = merge_params_program(27_000 + seed)
+            po = PO(p)
+            _, ctx, results = po.analyze()
+            m = po.demand.get(3)
+            if m is None or not bit(m, p.n_globals):
+                return False
+            errs, _ = simulate_program(p, ctx, results, po.demand, walks=40, seed=seed)
+            if errs:
                 return False
         from oracle import SUM_MAYW_H
         for const in (False, True):
