@@ -1711,8 +1711,10 @@ OMPD_LEVEL_KERNEL(ompd_k_lv_avf, PH_AVF)
 OMPD_LEVEL_KERNEL(ompd_k_lv_live, PH_LIVE)
 
 // ---------------------------------------------------------------------------
-// Edge-parallel passes (no iteration): lanes over words, one wavefront per
-// (tile, 64-block chunk) item.
+// Edge-parallel passes (no iteration): one wavefront per (tile, 64-block
+// chunk) item; the item's nw words are spread over the lanes 64 / nw times
+// (lane = block slot * nw + word), so that a narrow item keeps that many
+// blocks in flight instead of walking its chunk one block at a time.
 //   PASS_AVE  : AVEin_s(b) (output); per out-edge e = b->q:
 //               EAG_s(e) = NU_s(q) & ~AVEout_s(b), VE_s(e) = AVEout_s(b) | NU_s(q)
 //               (VE is kept in the INS_EDGE rows until the placement overwrites them)
@@ -1735,24 +1737,28 @@ template <int PASS>
 __device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int fslot, int b0)
 {
     const int lane = threadIdx.x & 63;
-    if (lane >= nw) return;
+    if (nw <= 0) return;
+    const int bpw = nw >= 64 ? 1 : 64 / nw;     // blocks in flight per wavefront
+    const int sub = lane / nw;                  // the lane's block slot
+    if (sub >= bpw) return;
     const int nb = c.nb, wd = c.wd;
-    const size_t wo = (size_t)(s0 + lane);
-    const int w = s0 + lane;
+    const int w = s0 + (lane - sub * nw);
+    const size_t wo = (size_t)w;
     const u64 vm = (w == wd - 1 && (c.nv & 63)) ? ((1ull << (c.nv & 63)) - 1ull) : ~0ull;
-    const CAS int32_t* SP = K(c.succ_ptr);
-    const CAS int32_t* SI = K(c.succ_idx);
-    const CAS int32_t* PP = K(c.pred_ptr);
-    const CAS int32_t* PI = K(c.pred_idx);
-    const CAS int32_t* PE = K(c.pred_eid);
-    const CAS uint8_t* KD = K(c.kind);
+    // CSR indices differ between the lanes' blocks: vector loads
+    const GAS int32_t* SP = G(c.succ_ptr);
+    const GAS int32_t* SI = G(c.succ_idx);
+    const GAS int32_t* PP = G(c.pred_ptr);
+    const GAS int32_t* PI = G(c.pred_idx);
+    const GAS int32_t* PE = G(c.pred_eid);
+    const GAS uint8_t* KD = G(c.kind);
     const GAS u64* FLG = G(c.flg) + (size_t)fslot * 4 * nb;
     auto row = [&](const u64* a, int b) -> u64 { return G(a)[(size_t)b * wd + wo]; };
     auto erow = [&](const u64* a, int e) -> u64 { return G(a)[(size_t)e * wd + wo]; };
     auto put = [&](u64* a, size_t r, u64 v) { G(a)[r * wd + wo] = v; };
     const int b1 = min(b0 + 64, nb);
     if constexpr (PASS == PASS_AVE || PASS == PASS_MAYP) {
-        for (int b = b0; b < b1; ++b) {
+        for (int b = b0 + sub; b < b1; b += bpw) {
             const u64 aoh = row(c.aveout_h, b), aod = row(c.aveout_d, b);
             if constexpr (PASS == PASS_AVE) {
                 u64 ih, id;
@@ -1790,7 +1796,7 @@ __device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int f
     }
     if constexpr (PASS == PASS_LATER) {
         const bool eager = c.placement & PL_EAGER;
-        for (int q = b0; q < b1; ++q) {
+        for (int q = b0 + sub; q < b1; q += bpw) {
             const int a = PP[q], z = PP[q + 1];
             if (eager || q == c.entry) {
                 put(c.ie_h, q, 0);
@@ -1843,7 +1849,7 @@ __device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int f
         }
     }
     if constexpr (PASS == PASS_LIVE) {
-        for (int q = b0; q < b1; ++q) {
+        for (int q = b0 + sub; q < b1; q += bpw) {
             const u64 lh = row(c.mayp_h, q), ld = row(c.mayp_d, q);
             for (int k = PP[q]; k < PP[q + 1]; ++k) {
                 const int e = PE[k];
@@ -1856,7 +1862,7 @@ __device__ __forceinline__ void edge_pass(const DevCfg& c, int s0, int nw, int f
     if constexpr (PASS == PASS_AVF) {
         u64 to = 0, fr = 0, dv = 0, fr_read = 0;
         const u64 fp = G(c.fp)[wo];
-        for (int q = b0; q < b1; ++q) {
+        for (int q = b0 + sub; q < b1; q += bpw) {
             const int a = PP[q], z = PP[q + 1];
             const u64 ieh = row(c.ie_h, q), ied = row(c.ie_d, q);
             const u64 not_before = ((FLG[(size_t)nb + q] >> 1) & 1) - 1;   // all ones: no DEVICE block follows q
