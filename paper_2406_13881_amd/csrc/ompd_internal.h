@@ -101,9 +101,8 @@ size_t ompd_cfg_scratch(const ompd_cfg& g, const ompd_result& r, ScratchOff& o);
 void ompd_fill_devcfg(const ompd_cfg& g, const ompd_result& r, char* base, const ScratchOff& o, uint32_t flags,
                       int32_t wait_ticks, ompd::DevCfg& d, uint64_t* bnd_host, uint64_t* bnd_dev = nullptr);
 // Blocks from which a CFG takes the level schedule when the caller names none
-// (the walk below: CFGs of a few thousand blocks have too few blocks per level
-// to beat it, measured 62 against 75 ms for an 8,194-block CFG; a
-// 16,386-block one runs 3.6x faster on levels), and the most blocks a CFG on
+// (in a launch that fills the GPU the walk's throughput wins below this; a
+// 16,386-block CFG runs 3.6x faster on levels), and the most blocks a CFG on
 // the level schedule may have (its column's state, 8 bytes per block, must
 // fit a workgroup's LDS; larger CFGs take the walk whatever the caller asks).
 constexpr int OMPD_LEVEL_MIN_BLOCKS = 12288;
@@ -114,6 +113,11 @@ int ompd_default_sched(int n_blocks, int n_vars);
 // the default rule put on it have more level tiles than this many rounds of the CUs take, they
 // go back to the walk (the launch is throughput-bound then).
 constexpr int OMPD_LEVEL_ROUNDS = 3;
+// ... and a launch with at most n_cu / OMPD_IDLE_FRACTION walk tiles moves the CFGs of at least
+// OMPD_LEVEL_IDLE_MIN_BLOCKS blocks that the rule put on the walk to the level schedule (one round
+// of level tiles at most): alone, such a CFG usually finishes sooner there.
+constexpr int OMPD_IDLE_FRACTION = 4;
+constexpr int OMPD_LEVEL_IDLE_MIN_BLOCKS = 300;
 void ompd_settle_sched(ompd::DevCfg* h, int n, int n_cu);
 // Default bound of a kernel wait without progress (the longest legitimate wait is one step of
 // the other wavefront, microseconds).

@@ -251,9 +251,31 @@ void ompd_settle_sched(DevCfg* h, int n, int n_cu)
     int64_t tiles = 0;
     for (int i = 0; i < n; ++i)
         if (by_rule(h[i])) tiles += 2 * (int64_t)h[i].wd + 1;
-    if (tiles <= (int64_t)OMPD_LEVEL_ROUNDS * n_cu) return;
-    for (int i = 0; i < n; ++i)
-        if (by_rule(h[i])) h[i].sched = SCHED_WALK;
+    if (tiles > (int64_t)OMPD_LEVEL_ROUNDS * n_cu) {
+        for (int i = 0; i < n; ++i)
+            if (by_rule(h[i])) h[i].sched = SCHED_WALK;
+        return;
+    }
+    // A launch whose walk tiles leave most CUs idle is bound by its longest tile's dependent
+    // steps, not by throughput: there the level schedule (a workgroup per 32-bit column, the
+    // blocks of a level in parallel) finishes a CFG of a few hundred blocks or more sooner (C3
+    // CFGs alone: 0.3-0.7x the walk's time for most; below ~300 blocks either may win), so those
+    // the rule put on the walk move to it while one round of level tiles holds them all.
+    int64_t walk = 0, level = 0;
+    for (int i = 0; i < n; ++i) {
+        if (h[i].sched == SCHED_LEVEL) level += 2 * (int64_t)h[i].wd + 1;
+        else walk += tiles_of(h[i].wd);
+    }
+    if (walk == 0 || walk * OMPD_IDLE_FRACTION > n_cu) return;
+    for (int i = 0; i < n; ++i) {
+        if (h[i].sched != SCHED_WALK || !h[i].sched_rule || h[i].nb > OMPD_LEVEL_MAX_BLOCKS ||
+            h[i].nb < OMPD_LEVEL_IDLE_MIN_BLOCKS)
+            continue;
+        const int64_t t = 2 * (int64_t)h[i].wd + 1;
+        if (level + t > n_cu) continue;
+        h[i].sched = SCHED_LEVEL;
+        level += t;
+    }
 }
 
 // Fill the kernels' descriptor of one CFG whose scratch starts at `base`.

@@ -150,3 +150,38 @@ def test_level_programs(ctx):
         for k, key in enumerate(got["contexts"]):
             assert_same(got["results"][k], results[key], "program %d context %s" % (t, key))
         _print("level: program %d, %d contexts equal" % (t, len(got["contexts"])))
+
+
+def test_idle_launch_moves_larger_cfgs_to_levels(ctx):
+    """With no schedule named, a launch whose walk tiles would leave most CUs idle puts its
+    CFGs of 300 blocks or more on the level schedule (smaller ones stay on the walk), and a
+    launch with enough walk tiles to fill the GPU keeps the walk; every output equals the
+    oracle's either way."""
+    import json
+    from paper_2406_13881_amd.resident import ResidentBatch
+    nbs, nvs = synth.c3_sizes()
+    # (few enough words that one round of level tiles holds all three)
+    mid = [int(i) for i in np.nonzero((nbs >= 400) & (nbs <= 3000) & (nvs <= 1280))[0][:3]]
+    tiny = [int(i) for i in np.nonzero(nbs < 200)[0][:3]]
+    cfgs = [synth.c3_item(i) for i in mid + tiny]
+    rb = ResidentBatch(ctx, cfgs)
+    try:
+        d = json.loads(rb.plan.describe())
+        _print("idle launch: blocks %s, plan %s" % ([c.n_blocks for c in cfgs], d))
+        assert d["level_cfgs"] == len(mid), d
+        rb.run()
+        import torch
+        torch.cuda.synchronize()
+        assert (rb.plan.status() == 0).all()
+        refs = _oracle_many(cfgs)
+        for i in range(len(cfgs)):
+            assert_same(rb.fetch(i), refs[i], "idle launch #%d" % i)
+    finally:
+        rb.close()
+    many = [synth.c3_item(i) for i in range(200)]
+    rb = ResidentBatch(ctx, many)
+    try:
+        d = json.loads(rb.plan.describe())
+        assert d["level_cfgs"] == 0, d
+    finally:
+        rb.close()

@@ -24,12 +24,34 @@ KEYS = ("nu_h", "nu_d", "ave_h", "ave_d", "avf_h", "avf_d", "ins_entry_h", "ins_
         "ins_edge_h", "ins_edge_d", "var_kind", "after_dev", "before_dev")
 
 
+class _Walk:
+    """The context, with the walk for every solve that names no schedule: a small launch would
+    otherwise move CFGs of a few hundred blocks or more to the level schedule, which
+    tests/test_gpu_level.py covers."""
+
+    def __init__(self, c):
+        self._c = c
+
+    def __getattr__(self, name):
+        return getattr(self._c, name)
+
+    def _flags(self, flags):
+        import paper_2406_13881_amd as ompd
+        return flags if flags & (ompd.F_SCHED_WALK | ompd.F_SCHED_LEVEL) else flags | ompd.F_SCHED_WALK
+
+    def analyze_batch(self, cfgs, flags=0, **kw):
+        return self._c.analyze_batch(cfgs, flags=self._flags(flags), **kw)
+
+    def analyze_cfg(self, cfg, flags=0, **kw):
+        return self._c.analyze_cfg(cfg, flags=self._flags(flags), **kw)
+
+
 @pytest.fixture(scope="module")
 def ctx():
     import paper_2406_13881_amd as ompd
     c = ompd.Context(0)
     print("device:", c.device_info(), flush=True)
-    yield c
+    yield _Walk(c)
     c.close()
 
 
@@ -363,7 +385,7 @@ def test_wait_limit_gives_up_and_recovers(ctx):
         assert ei.value.code == ompd.OMPD_E_DEVICE
         assert "gave up" in str(ei.value), str(ei.value)
         _print("give-up message: %s" % ei.value)
-        rb = ResidentBatch(ctx, cfgs)
+        rb = ResidentBatch(ctx, cfgs, flags=ompd.F_SCHED_WALK)
         try:
             rb.run(torch.cuda.current_stream().cuda_stream)
             torch.cuda.synchronize()
@@ -373,7 +395,7 @@ def test_wait_limit_gives_up_and_recovers(ctx):
             rb.close()
     finally:
         ctx.set_wait_limit(0)
-    rb = ResidentBatch(ctx, cfgs)
+    rb = ResidentBatch(ctx, cfgs, flags=ompd.F_SCHED_WALK)
     try:
         rb.run(torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
