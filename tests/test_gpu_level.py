@@ -134,14 +134,19 @@ def test_level_wide_fan(ctx):
 
 
 def test_level_programs(ctx):
-    """Call blocks (callee summaries, caps, demands) under the level schedule: the whole
-    interprocedural result equals the oracle's."""
+    """Call blocks (callee summaries, caps, demands, pointer-parameter bindings) under the
+    level schedule: the whole interprocedural result equals the oracle's."""
     import paper_2406_13881_amd as ompd
     from oracle.program import ProgramOracle
     progs = [synth.program(31_500 + s, n_procs=8, n_globals=12, n_locals=5, blocks=(4, 14), mean_calls=1.5,
                            max_calls=3, scc_procs=5, scc_size=(2, 3), external_frac=0.3, max_loop_depth=2,
                            device_frac=0.4, p_read=0.25, p_write=0.15, threads=1) for s in range(4)]
     progs.append(synth.c4(n_procs=60))
+    # pointer parameters bound at host calls, calls inside kernels and external calls with arguments
+    progs += [synth.program(31_600 + s, n_procs=8, n_globals=12, n_locals=6, blocks=(4, 14), mean_calls=1.5,
+                            max_calls=3, scc_procs=4, scc_size=(2, 3), external_frac=0.3, max_loop_depth=2,
+                            device_frac=0.4, p_read=0.25, p_write=0.15, threads=1, max_params=3, max_ext_args=2,
+                            device_call_frac=0.3) for s in range(3)]
     for t, prog in enumerate(progs):
         got = ctx.analyze_program(prog, flags=ompd.F_SCHED_LEVEL)
         po = ProgramOracle(prog)
