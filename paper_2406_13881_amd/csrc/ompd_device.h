@@ -92,8 +92,10 @@ struct DevCfg {
     int32_t* tmp;
     int32_t* rec_f;     // [2*nb] int4: block records with predecessors, in block-id order
     int32_t* rec_b;     // [2*nb] int4: block records with successors, in block-id order
-    int32_t* step_f;    // [2*nb] int4: step entries of the forward walk, in walk order
-    int32_t* step_b;    // [2*nb] int4: step entries of the backward walk, in walk order
+    int32_t* step_f;    // [2*nb] int4: step entries of the forward walk, in walk order (level
+                        // schedule: the forward records in level order, the block in word 7)
+    int32_t* step_b;    // [2*nb] int4: step entries of the backward walk, in walk order (level
+                        // schedule: the backward records in level order)
     int32_t* lorder;    // [nb] the blocks by level (level schedule)
     int32_t* loff;      // [nb + 1] start of each level in lorder
     int32_t* info;
@@ -145,6 +147,8 @@ inline int tiles_of(int wd) { return wd <= 0 ? 1 : (wd + TILE_WORDS - 1) / TILE_
 // steps (phase_inputs(ph) words of WORD_BYTES each), their 16-byte
 // descriptors, then one state of identity words (STATE_BYTES).
 constexpr int CTL_BYTES = 256;
+// Threads of a level-schedule workgroup.
+constexpr int LEVEL_THREADS = 64;
 // then the blocks of the last BLK_RING planned steps (the helper stores results by them; at least
 // the result ring plus the input ring, so that an entry is not reused before its step is stored)
 constexpr int BLK_RING = 128;

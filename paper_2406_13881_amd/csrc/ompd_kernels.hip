@@ -360,11 +360,27 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
         __syncthreads();
     }
     if (tid == 0) c.info[INFO_ORDER] = lv || !unord;
-    // step entries in walk order: forward position i is block i (or lorder[i]), backward position i
-    // the block at forward position nb - 1 - i
     int4* SF = reinterpret_cast<int4*>(c.step_f);
     int4* SB = reinterpret_cast<int4*>(c.step_b);
-    const int32_t* pos = (!lv && unord) ? c.loff : nullptr;
+    if (lv) {
+        // level schedule (no walk steps): the records in level order, the block in the last word,
+        // so that a level's positions lead to their records in one load
+        for (int k = tid; k < nb; k += nt) {
+            const int b = c.lorder[k];
+            int4 t1 = RF[2 * b + 1];
+            t1.w = b;
+            SF[2 * k] = RF[2 * b];
+            SF[2 * k + 1] = t1;
+            t1 = RB[2 * b + 1];
+            t1.w = b;
+            SB[2 * k] = RB[2 * b];
+            SB[2 * k + 1] = t1;
+        }
+        return;
+    }
+    // step entries in walk order: forward position i is block i (or lorder[i]), backward position i
+    // the block at forward position nb - 1 - i
+    const int32_t* pos = unord ? c.loff : nullptr;
     for (int i = tid; i < nb; i += nt) {
         int4 t0, t1;
         const int bf = pos ? c.lorder[i] : i;
@@ -1422,7 +1438,10 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
 // memory and a barrier.  At the end of a phase the state goes to the same
 // rows the walk writes, so the passes and later phases read the same arrays
 // whatever schedule produced them.
-constexpr int LV_THREADS = 256;
+// One wavefront per level tile: a level of a few dozen blocks keeps one wavefront busy, and a
+// barrier inside a single wavefront costs no cross-wave synchronisation (a wider level takes
+// several passes of the wavefront).
+constexpr int LV_THREADS = LEVEL_THREADS;
 
 template <int PH>
 __device__ __forceinline__ void level_phase(const DevCfg& c, int hc, uint32_t* SH, uint32_t* SD)
@@ -1607,28 +1626,240 @@ __device__ __forceinline__ void level_phase(const DevCfg& c, int hc, uint32_t* S
             valid_out(b, r, ih & vm, id & vm, in(c.W, b), in(c.R, b), vh, vd);
         }
     };
+    // The common block (not ENTRY, EXIT or a call) in two halves: its global inputs (rows of the
+    // block and of its first two edges, constant within the phase) into X, and the new state from
+    // X and its neighbours' states in LDS (further neighbours' edge rows loaded there).
+    constexpr int NXL = PH == PH_NU ? 2 : PH == PH_AVE ? 4 : PH == PH_MAYP ? 6 : 8;
+    // (the flag column reads a word of its own flag rows instead, which always exist, and uses
+    // constants: no branch, so that the loads of a round go out together)
+    const GAS uint32_t* safe = reinterpret_cast<const GAS uint32_t*>(FLG);
+    auto at = [&](const u64* a, int i) -> hw {
+        const GAS uint32_t* p = reinterpret_cast<const GAS uint32_t*>(G(a) + (size_t)i * wd + wo) + (hi ? 1 : 0);
+        return *(flg ? safe : p);
+    };
+    auto is_fast = [&](uint32_t meta) { return !(meta & (REC_ENTRY | REC_EXIT | REC_CALL)); };
+    // Neighbours 2 .. cnt-1 of a block with more than two, folded into the accumulators by
+    // `fold(state h, state d, edge row h, edge row d, third edge row, loop entry)`: eight at a
+    // time, first their CSR entries, then their states and edge rows, every slot loaded (past
+    // the last neighbour the last one again: each phase's meet is idempotent).
+    auto extra = [&](const int4& r0, const int4& r1, auto&& fold) {
+        const int cnt = (int)((uint32_t)r0.x & REC_COUNT), ovf = r1.y;
+        for (int j0 = 2; j0 < cnt; j0 += 8) {
+            int pj[8], ej[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int jj = ovf + (j0 + t < cnt ? j0 + t : cnt - 1);
+                if constexpr (BWD) { pj[t] = G(c.succ_idx)[jj]; ej[t] = jj; }
+                else { pj[t] = G(c.pred_idx)[jj]; ej[t] = G(c.pred_eid)[jj]; }
+            }
+            hw g0[8], g1[8], g2[8];
+            bool le[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                le[t] = false;
+                g0[t] = g1[t] = g2[t] = 0u;
+                if constexpr (PH == PH_MAYP || PH == PH_LATER) {
+                    le[t] = is_le(c, G(c.kind)[ej[t]]);
+                    g0[t] = at(c.eag_h, ej[t]);
+                    g1[t] = at(c.eag_d, ej[t]);
+                    if constexpr (PH == PH_LATER) g2[t] = at(c.both, ej[t]);
+                }
+                if constexpr (PH == PH_LIVE || PH == PH_AVF) {
+                    g0[t] = at(c.ig_h, ej[t]);
+                    g1[t] = at(c.ig_d, ej[t]);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) fold(SH[pj[t]], SD[pj[t]], g0[t], g1[t], g2[t], le[t]);
+        }
+    };
+    auto gather = [&](const int4& r0, const int4& r1, hw* X) {
+        // every load is issued whatever the block, at a clamped index (a missing edge reads
+        // edge 0), so that a round issues the same loads every time
+        const int b = r1.w;
+        const int cnt = (int)((uint32_t)r0.x & REC_COUNT);
+        int e0 = r0.w & 0x7FFFFFFF, e1 = r1.x & 0x7FFFFFFF;
+        if (cnt < 1 || e0 >= c.ne) e0 = 0;
+        if (cnt < 2 || e1 >= c.ne) e1 = e0;
+        if constexpr (PH == PH_NU) { X[0] = at(c.R, b); X[1] = at(c.W, b); }
+        if constexpr (PH == PH_AVE) { X[0] = at(c.nu_h, b); X[1] = at(c.nu_d, b); X[2] = at(c.W, b); X[3] = at(c.R, b); }
+        if constexpr (PH == PH_MAYP || PH == PH_LATER) {
+            X[0] = at(c.eag_h, e0); X[1] = at(c.eag_d, e0); X[2] = at(c.eag_h, e1); X[3] = at(c.eag_d, e1);
+        }
+        if constexpr (PH == PH_MAYP) { X[4] = at(c.R, b); X[5] = at(c.W, b); }
+        if constexpr (PH == PH_LATER) { X[4] = at(c.both, e0); X[5] = at(c.both, e1); X[6] = at(c.R, b); X[7] = at(c.W, b); }
+        if constexpr (PH == PH_LIVE || PH == PH_AVF) {
+            X[0] = at(c.ig_h, e0); X[1] = at(c.ig_d, e0); X[2] = at(c.ig_h, e1); X[3] = at(c.ig_d, e1);
+        }
+        if constexpr (PH == PH_LIVE) { X[4] = at(c.R, b); X[5] = at(c.W, b); X[6] = at(c.ie_h, b); X[7] = at(c.ie_d, b); }
+        if constexpr (PH == PH_AVF) { X[4] = at(c.ie_h, b); X[5] = at(c.ie_d, b); X[6] = at(c.W, b); X[7] = at(c.R, b); }
+    };
+    auto apply = [&](const int4& r0, const int4& r1, const hw* X, hw& vh, hw& vd) {
+        const uint32_t meta = (uint32_t)r0.x;
+        const int cnt = (int)(meta & REC_COUNT);
+        const bool dev = meta & REC_DEV;
+        const int nbr0 = r0.y, nbr1 = r0.z;
+        const bool le0 = (uint32_t)r0.w & 0x80000000u, le1 = (uint32_t)r1.x & 0x80000000u;
+        if constexpr (PH == PH_NU) {
+            hw oh = 0, od = 0;
+            if (cnt > 0) { oh |= SH[nbr0]; od |= SD[nbr0]; }
+            if (cnt > 1) { oh |= SH[nbr1]; od |= SD[nbr1]; }
+            if (cnt > 2) extra(r0, r1, [&](hw sh, hw sd, hw, hw, hw, bool) { oh |= sh; od |= sd; });
+            const hw rr = flg ? 2u : X[0], ww = flg ? (dev ? 2u : 0u) : X[1];
+            vh = (dev ? (rr & fph) : rr) | (~ww & oh);
+            vd = (dev ? (rr & ~fph) : 0u) | (~ww & od);
+        } else if constexpr (PH == PH_AVE) {
+            hw mh = ~0u, md = ~0u;
+            if (cnt > 0) { mh &= SH[nbr0]; md &= SD[nbr0]; }
+            if (cnt > 1) { mh &= SH[nbr1]; md &= SD[nbr1]; }
+            if (cnt > 2) extra(r0, r1, [&](hw sh, hw sd, hw, hw, hw, bool) { mh &= sh; md &= sd; });
+            const hw ih = ((flg ? 0u : X[0]) | mh) & vm, id = ((flg ? 0u : X[1]) | md) & vm;
+            const hw wr = flg ? (dev ? 2u : 0u) : X[2], rr = flg ? 0u : X[3];
+            const hw ah = dev ? (ih & ~wr) : (ih | wr);
+            const hw ad = dev ? ((id | wr) & ~(rr & fph)) : (id & ~wr);
+            vh = ah & vm;
+            vd = ad & vm;
+        } else if constexpr (PH == PH_MAYP || PH == PH_LATER) {
+            const hw rr = X[PH == PH_MAYP ? 4 : 6], ww = X[PH == PH_MAYP ? 5 : 7];
+            const hw sth = (dev ? (rr & fph) : rr) | (dev ? 0u : ww);
+            const hw std_ = (dev ? (rr & ~fph) : 0u) | (dev ? ww : 0u);
+            if constexpr (PH == PH_MAYP) {
+                hw mh = 0, md = 0;
+                if (cnt > 0 && !le0) { mh |= X[0] | SH[nbr0]; md |= X[1] | SD[nbr0]; }
+                if (cnt > 1 && !le1) { mh |= X[2] | SH[nbr1]; md |= X[3] | SD[nbr1]; }
+                if (cnt > 2)
+                    extra(r0, r1, [&](hw sh, hw sd, hw gh, hw gd, hw, bool l) {
+                        if (!l) { mh |= gh | sh; md |= gd | sd; }
+                    });
+                vh = mh & ~sth & vm;
+                vd = md & ~std_ & vm;
+            } else {
+                hw allh = ~0u, alld = ~0u, anyh = 0, anyd = 0;
+                if (cnt > 0) {
+                    const hw lh = X[0] | SH[nbr0], ld = X[1] | SD[nbr0];
+                    allh &= lh | X[4];
+                    alld &= ld | X[4];
+                    if (!le0) { anyh |= lh; anyd |= ld; }
+                }
+                if (cnt > 1) {
+                    const hw lh = X[2] | SH[nbr1], ld = X[3] | SD[nbr1];
+                    allh &= lh | X[5];
+                    alld &= ld | X[5];
+                    if (!le1) { anyh |= lh; anyd |= ld; }
+                }
+                if (cnt > 2)
+                    extra(r0, r1, [&](hw sh, hw sd, hw gh, hw gd, hw bo, bool l) {
+                        const hw lh = gh | sh, ld = gd | sd;
+                        allh &= lh | bo;
+                        alld &= ld | bo;
+                        if (!l) { anyh |= lh; anyd |= ld; }
+                    });
+                vh = allh & anyh & vm & ~sth;
+                vd = alld & anyd & vm & ~std_;
+            }
+        } else if constexpr (PH == PH_LIVE) {
+            hw oh = 0, od = 0;
+            if (cnt > 0) { oh |= (SH[nbr0] & ~X[0]) | X[1]; od |= (SD[nbr0] & ~X[1]) | X[0]; }
+            if (cnt > 1) { oh |= (SH[nbr1] & ~X[2]) | X[3]; od |= (SD[nbr1] & ~X[3]) | X[2]; }
+            if (cnt > 2)
+                extra(r0, r1, [&](hw sh, hw sd, hw gh, hw gd, hw, bool) {
+                    oh |= (sh & ~gh) | gd;
+                    od |= (sd & ~gd) | gh;
+                });
+            const hw rr = X[4], ww = X[5];
+            const hw rh = dev ? (rr & fph) : rr, rd = dev ? (rr & ~fph) : 0u;
+            const hw kh = dev ? 0u : ww, kd = dev ? (ww | (rr & fph)) : 0u;
+            const hw ih = X[6], id = X[7];
+            const hw ah = rh | (oh & ~kh), ad = rd | (od & ~kd);
+            vh = ((ah & ~ih) | id) & vm;
+            vd = ((ad & ~id) | ih) & vm;
+        } else {   // PH_AVF
+            hw mh = ~0u, md = ~0u;
+            if (cnt > 0) { mh &= SH[nbr0] | X[0]; md &= SD[nbr0] | X[1]; }
+            if (cnt > 1) { mh &= SH[nbr1] | X[2]; md &= SD[nbr1] | X[3]; }
+            if (cnt > 2) extra(r0, r1, [&](hw sh, hw sd, hw gh, hw gd, hw, bool) { mh &= sh | gh; md &= sd | gd; });
+            const hw ih = (X[4] | mh) & vm, id = (X[5] | md) & vm, wr = X[6], rr = X[7];
+            const hw ah = dev ? (ih & ~wr) : (ih | wr);
+            const hw ad = dev ? ((id | wr) & ~(rr & fph)) : (id & ~wr);
+            vh = ah & vm;
+            vd = ad & vm;
+        }
+    };
     const hw init = (PH == PH_AVE || PH == PH_AVF) ? vm : 0u;
     for (int b = tid; b < nb; b += LV_THREADS) { SH[b] = init; SD[b] = init; }
     __syncthreads();
     const int cap = c.sweep_cap > 0 ? c.sweep_cap : 2 * nb + 2;
     int sweeps = 0;
     bool good = true;
+    // Super-steps of S levels: the loads of S levels go out in three rounds (their bounds, then
+    // the records of the thread's positions in them, in level order with the block in the last
+    // word, then the rows of those blocks and their first two edges), every load issued whatever
+    // the level (indices clamped), so that each round is one latency for S levels; then the S
+    // levels are computed one after another.  Lane tid takes position LF[lv] + tid of each
+    // level (and every LV_THREADS-th one after it, with direct loads, as do calls, ENTRY and
+    // EXIT).
+    constexpr int S = 8;
+    const int4* LR = reinterpret_cast<const int4*>(BWD ? c.step_b : c.step_f);
+    int2 bq[S];
+    int4 r0q[S], r1q[S];
+    hw xq[S][NXL];
+    int chg = 0;
     for (;;) {
-        int chg = 0;
-        for (int li = 0; li < nlev; ++li) {
-            const int lv = BWD ? nlev - 1 - li : li;
-            const int a = LF[lv], z = LF[lv + 1];
-            for (int k = a + tid; k < z; k += LV_THREADS) {
-                const int b = LO[k];
-                hw vh, vd;
-                transfer(b, vh, vd);
-                if (vh != SH[b] || vd != SD[b]) {
-                    SH[b] = vh;
-                    SD[b] = vd;
-                    chg = 1;
+        for (int li0 = 0; li0 < nlev; li0 += S) {
+            const int ns = nlev - li0 < S ? nlev - li0 : S;
+#pragma unroll
+            for (int v = 0; v < S; ++v) {
+                const int li = li0 + v < nlev ? li0 + v : nlev - 1;
+                const int lv = BWD ? nlev - 1 - li : li;
+                bq[v].x = G(LF)[lv];
+                bq[v].y = G(LF)[lv + 1];
+            }
+#pragma unroll
+            for (int v = 0; v < S; ++v) {
+                typedef int v4i __attribute__((ext_vector_type(4)));
+                int k = bq[v].x + tid;
+                if (k >= nb) k = nb - 1;
+                const GAS v4i* p = reinterpret_cast<const GAS v4i*>(G(LR)) + 2 * (size_t)k;
+                const v4i x = p[0], y = p[1];
+                r0q[v] = make_int4(x.x, x.y, x.z, x.w);
+                r1q[v] = make_int4(y.x, y.y, y.z, y.w);
+            }
+#pragma unroll
+            for (int v = 0; v < S; ++v) gather(r0q[v], r1q[v], xq[v]);
+#pragma unroll
+            for (int v = 0; v < S; ++v) {
+                if (v < ns) {
+                    const int2 q = bq[v];
+                    if (q.x + tid < q.y) {
+                        const int4 r0 = r0q[v], r1 = r1q[v];
+                        const int b = r1.w;
+                        hw vh, vd;
+                        if (is_fast((uint32_t)r0.x)) apply(r0, r1, xq[v], vh, vd);
+                        else transfer(b, vh, vd);
+                        if (vh != SH[b] || vd != SD[b]) {
+                            SH[b] = vh;
+                            SD[b] = vd;
+                            chg = 1;
+                        }
+                    }
+                    // positions past the first LV_THREADS of a wide level
+                    for (int k = q.x + tid + LV_THREADS; k < q.y; k += LV_THREADS) {
+                        const int bb = LO[k];
+                        hw vh, vd;
+                        transfer(bb, vh, vd);
+                        if (vh != SH[bb] || vd != SD[bb]) {
+                            SH[bb] = vh;
+                            SD[bb] = vd;
+                            chg = 1;
+                        }
+                    }
+                    // the level's LDS writes before the next level's reads (no wait for the
+                    // loads: none is in flight here)
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                    __builtin_amdgcn_s_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
                 }
             }
-            __syncthreads();
         }
         ++sweeps;
         if (!__syncthreads_or(chg)) break;
@@ -1637,6 +1868,7 @@ __device__ __forceinline__ void level_phase(const DevCfg& c, int hc, uint32_t* S
             good = false;
             break;
         }
+        chg = 0;
     }
     if (tid == 0) atomicMax(&c.info[INFO_SWEEPS + PH], sweeps);
     // the state to the rows of the phase (flag column: tile slot 0's columns)

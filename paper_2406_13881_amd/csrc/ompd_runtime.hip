@@ -39,7 +39,6 @@ extern "C" __global__ void ompd_k_lv_avf(const DevCfg*, const Tile*, int, int32_
 static const void* const k_levels[N_PHASES] = {(const void*)ompd_k_lv_nu, (const void*)ompd_k_lv_ave,
                                                (const void*)ompd_k_lv_mayp, (const void*)ompd_k_lv_later,
                                                (const void*)ompd_k_lv_avf, (const void*)ompd_k_lv_live};
-constexpr int LEVEL_THREADS = 256;
 static const void* const k_phases[N_PHASES] = {(const void*)ompd_k_nu, (const void*)ompd_k_ave,
                                                (const void*)ompd_k_mayp, (const void*)ompd_k_later,
                                                (const void*)ompd_k_avf, (const void*)ompd_k_live};
