@@ -113,11 +113,10 @@ int ompd_default_sched(int n_blocks, int n_vars);
 // the default rule put on it have more level tiles than this many rounds of the CUs take, they
 // go back to the walk (the launch is throughput-bound then).
 constexpr int OMPD_LEVEL_ROUNDS = 3;
-// ... and a launch with at most n_cu / OMPD_IDLE_FRACTION walk tiles moves the CFGs of at least
-// OMPD_LEVEL_IDLE_MIN_BLOCKS blocks that the rule put on the walk to the level schedule (one round
-// of level tiles at most): alone, such a CFG usually finishes sooner there.
+// ... and a launch with at most n_cu / OMPD_IDLE_FRACTION walk tiles moves the CFGs that the rule
+// put on the walk to the level schedule (one round of level tiles at most): alone, a CFG usually
+// finishes sooner there.
 constexpr int OMPD_IDLE_FRACTION = 4;
-constexpr int OMPD_LEVEL_IDLE_MIN_BLOCKS = 300;
 void ompd_settle_sched(ompd::DevCfg* h, int n, int n_cu);
 // Default bound of a kernel wait without progress (the longest legitimate wait is one step of
 // the other wavefront, microseconds).

@@ -256,10 +256,10 @@ void ompd_settle_sched(DevCfg* h, int n, int n_cu)
         return;
     }
     // A launch whose walk tiles leave most CUs idle is bound by its longest tile's dependent
-    // steps, not by throughput: there the level schedule (a workgroup per 32-bit column, the
-    // blocks of a level in parallel) finishes a CFG of a few hundred blocks or more sooner (C3
-    // CFGs alone: 0.3-0.7x the walk's time for most; below ~300 blocks either may win), so those
-    // the rule put on the walk move to it while one round of level tiles holds them all.
+    // steps, not by throughput: there the level schedule (a wavefront per 32-bit column, the
+    // blocks of a level in parallel) usually finishes a CFG sooner (40 C3 CFGs alone: 0.16-0.9x
+    // the walk's time, a few small ones up to 1.1x), so the CFGs the rule put on the walk move to
+    // it while one round of level tiles holds them all.
     int64_t walk = 0, level = 0;
     for (int i = 0; i < n; ++i) {
         if (h[i].sched == SCHED_LEVEL) level += 2 * (int64_t)h[i].wd + 1;
@@ -267,9 +267,7 @@ void ompd_settle_sched(DevCfg* h, int n, int n_cu)
     }
     if (walk == 0 || walk * OMPD_IDLE_FRACTION > n_cu) return;
     for (int i = 0; i < n; ++i) {
-        if (h[i].sched != SCHED_WALK || !h[i].sched_rule || h[i].nb > OMPD_LEVEL_MAX_BLOCKS ||
-            h[i].nb < OMPD_LEVEL_IDLE_MIN_BLOCKS)
-            continue;
+        if (h[i].sched != SCHED_WALK || !h[i].sched_rule || h[i].nb > OMPD_LEVEL_MAX_BLOCKS) continue;
         const int64_t t = 2 * (int64_t)h[i].wd + 1;
         if (level + t > n_cu) continue;
         h[i].sched = SCHED_LEVEL;
