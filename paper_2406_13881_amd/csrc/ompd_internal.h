@@ -111,8 +111,10 @@ int ompd_default_sched(int n_blocks, int n_vars);
 // A level tile keeps a whole column of its CFG in LDS, so a CU runs one at a time: the level
 // schedule has the lower latency per CFG but the lower throughput per CU.  When the CFGs that
 // the default rule put on it have more level tiles than this many rounds of the CUs take, they
-// go back to the walk (the launch is throughput-bound then).
-constexpr int OMPD_LEVEL_ROUNDS = 3;
+// go back to the walk (the launch is throughput-bound then).  Serving C2-shaped requests: 3
+// rounds gave a p50 of 243-453 ms at half load, 5 rounds 189 ms at the same capacity (~146
+// requests/s), 8 rounds 149 ms but a capacity of 133 requests/s.
+constexpr int OMPD_LEVEL_ROUNDS = 5;
 // ... and a launch with at most n_cu / OMPD_IDLE_FRACTION walk tiles moves the CFGs that the rule
 // put on the walk to the level schedule (one round of level tiles at most): alone, a CFG usually
 // finishes sooner there.
