@@ -69,6 +69,7 @@ struct ompd_plan {
     std::vector<ompd::DevCfg> h_cfgs;
     std::vector<ompd_result> res;
     std::vector<int32_t> h_info;
+    int32_t* d_info = nullptr;            // [n][INFO_WORDS]: every CFG's status words, gathered for one copy
     ompd::DevCfg* d_cfgs = nullptr;
     std::vector<ompd::Tile> h_tiles;
     ompd::Tile* d_tiles = nullptr;

@@ -498,6 +498,8 @@ int ompd_plan_build(ompd_ctx* ctx, const ompd_cfg* cfgs, ompd_result* res, int32
         e = hipMemcpy(p->d_cfgs, p->h_cfgs.data(), sizeof(DevCfg) * n, hipMemcpyHostToDevice);
     if (e != hipSuccess) { ompd_plan_destroy(p); return ompd_fail(OMPD_E_DEVICE, hipGetErrorString(e)); }
     p->h_info.assign((size_t)n * INFO_WORDS, 0);
+    e = hipMalloc(&p->d_info, 4 * INFO_WORDS * (size_t)std::max(n, 1));
+    if (e != hipSuccess) { ompd_plan_destroy(p); return ompd_fail(OMPD_E_NOMEM, hipGetErrorString(e)); }
     int rc = ompd_plan_retile(p, p->cfg);
     if (rc) { ompd_plan_destroy(p); return rc; }
     CK(hipEventCreate(&p->ev0));
@@ -748,15 +750,33 @@ std::string ompd_status_message(int i, const int32_t* inf)
     return buf;
 }
 
+// The status words of every CFG of a launch (each in its own scratch) into one array, so that
+// they come back in one copy instead of one per CFG.
+__global__ void __launch_bounds__(256) ompd_k_info(const DevCfg* __restrict__ cfgs, int n, int32_t* __restrict__ out)
+{
+    const int total = n * INFO_WORDS;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x)
+        out[t] = cfgs[t / INFO_WORDS].info[t % INFO_WORDS];
+}
+
+static int gather_info(const DevCfg* d_cfgs, int n, int32_t* d_out, int32_t* h_out, hipStream_t s)
+{
+    if (n <= 0) return OMPD_OK;
+    const int total = n * INFO_WORDS;
+    hipLaunchKernelGGL(ompd_k_info, dim3(std::min((total + 255) / 256, 1024)), dim3(256), 0, s, d_cfgs, n, d_out);
+    CK(hipGetLastError());
+    CK(hipMemcpyAsync(h_out, d_out, 4 * (size_t)total, hipMemcpyDeviceToHost, s));
+    return OMPD_OK;
+}
+
 int ompd_plan_collect(ompd_plan* p, int32_t* per_cfg)
 {
     CK(hipSetDevice(p->ctx->device));
     CK(hipStreamSynchronize(p->last_stream));
     if (p->n == 0) return OMPD_OK;
     // info words live per CFG inside the scratch arena
-    for (int i = 0; i < p->n; ++i)
-        CK(hipMemcpyAsync(&p->h_info[(size_t)i * INFO_WORDS], p->h_cfgs[i].info, 4 * INFO_WORDS,
-                          hipMemcpyDeviceToHost, p->last_stream));
+    int rg = gather_info(p->d_cfgs, p->n, p->d_info, p->h_info.data(), p->last_stream);
+    if (rg) return rg;
     CK(hipStreamSynchronize(p->last_stream));
     int first = OMPD_OK;
     for (int i = 0; i < p->n; ++i) {
@@ -870,6 +890,7 @@ extern "C" void ompd_plan_destroy(ompd_plan* p)
     if (p->d_tiles) (void)hipFree(p->d_tiles);
     if (p->d_items) (void)hipFree(p->d_items);
     if (p->d_cfgs) (void)hipFree(p->d_cfgs);
+    if (p->d_info) (void)hipFree(p->d_info);
     if (p->scratch) (void)hipFree(p->scratch);
     if (p->ev0) (void)hipEventDestroy(p->ev0);
     if (p->ev1) (void)hipEventDestroy(p->ev1);
@@ -1182,7 +1203,8 @@ extern "C" int ompd_analyze_batch_noalloc(ompd_ctx* ctx, const ompd_cfg* cfgs, o
     if (flags & OMPD_F_TILE_KERNEL) pc.split = false;
     if (const uint32_t r = (flags >> 8) & 7u) pc.lds_bytes = (size_t)(4u << r) * STATE_BYTES;
     // layout of the static scratch: each CFG's solver scratch, the work counters, the default
-    // boundaries, then the launch tables (descriptors, tiles, pass items)
+    // boundaries, then the launch tables (descriptors, tiles, pass items) and the gathered
+    // status words
     char* S = ctx->static_scratch;
     std::vector<ScratchOff> off(n);
     std::vector<size_t> base(n), boff(n);
@@ -1212,6 +1234,8 @@ extern "C" int ompd_analyze_batch_noalloc(ompd_ctx* ctx, const ompd_cfg* cfgs, o
     total += align256(sizeof(Tile) * std::max<size_t>(sh.tiles.size(), 1));
     const size_t item_off = total;
     total += align256(sizeof(EdgeItem) * std::max<size_t>(sh.items.size(), 1));
+    const size_t info_off = total;
+    total += align256(4 * INFO_WORDS * (size_t)n);
     if (total > OMPD_STATIC_SCRATCH_BYTES) {
         char buf[200];
         snprintf(buf, sizeof buf, "noalloc: the batch needs %zu bytes of scratch, the static scratch holds %zu",
@@ -1233,9 +1257,7 @@ extern "C" int ompd_analyze_batch_noalloc(ompd_ctx* ctx, const ompd_cfg* cfgs, o
         rc = ompd_launch_solve(dc, (const Tile*)(S + tile_off), (int)sh.tiles.size(), (const EdgeItem*)(S + item_off),
                                (int)sh.items.size(), counter, sh.dims, s);
     std::vector<int32_t> info((size_t)n * INFO_WORDS, 0);
-    if (rc == OMPD_OK)
-        for (int i = 0; i < n; ++i)
-            CK(hipMemcpyAsync(&info[(size_t)i * INFO_WORDS], h[i].info, 4 * INFO_WORDS, hipMemcpyDeviceToHost, s));
+    if (rc == OMPD_OK) rc = gather_info(dc, n, (int32_t*)(S + info_off), info.data(), s);
     CK(hipStreamSynchronize(s));   // the host tables above stay alive until the copies are done
     if (rc) return rc;
     int first = OMPD_OK;
