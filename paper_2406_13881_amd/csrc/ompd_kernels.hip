@@ -78,7 +78,8 @@ __device__ __forceinline__ bool is_le(const DevCfg& c, uint8_t k) { return k == 
 // A step entry (two int4, one per walk position): x flags; y the ring distances of neighbours
 // 0 and 1 (bits 0-7, 8-15; flag code 2 only); z the far neighbour; w how many steps before the
 // current one its state was computed (this sweep's or, when SF_BACK, the previous sweep's); then
-// the block, the edge ids of neighbours 0 and 1 (0 when missing) and an unused word.
+// the block, the edge ids of neighbours 0 and 1 (0 when missing) and a word of the re-check list
+// (entry k's holds the k-th block with a neighbour read before its own visit, -1 past the list).
 // The step entry of the block b at walk position i, from its record r0 / r1 (ring of rs slots);
 // pos: each block's position in the forward walk (NULL: its id).
 __device__ __forceinline__ void make_step(const int4& r0, const int4& r1, int b, bool bwd, int nb, int rs,
@@ -112,7 +113,7 @@ __device__ __forceinline__ void make_step(const int4& r0, const int4& r1, int b,
         fl |= k << (2 * j);
     }
     t0 = make_int4((int)fl, dd, fp, fo);
-    t1 = make_int4(b, cnt > 0 ? (int)(e0 & 0x7FFFFFFFu) : 0, cnt > 1 ? (int)(e1 & 0x7FFFFFFFu) : 0, 0);
+    t1 = make_int4(b, cnt > 0 ? (int)(e0 & 0x7FFFFFFFu) : 0, cnt > 1 ? (int)(e1 & 0x7FFFFFFFu) : 0, -1);
 }
 
 // Inclusive prefix sum of a[0..n) in global memory by one workgroup.
@@ -392,6 +393,48 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
         SB[2 * i] = t0;
         SB[2 * i + 1] = t1;
     }
+    __syncthreads();
+    // Re-check lists, in walk order: the blocks a sweep computes from a neighbour it has not
+    // visited yet in that sweep (the neighbour's walk position is not before the block's own: a
+    // BACK edge into it, or a self loop), that is a predecessor of a forward phase or a successor
+    // of a backward one.  Only through them can the next sweep see states other than this
+    // sweep's.  Entry k's last word takes the k-th such block (make_step left -1 in every one).
+    __shared__ int s_wave[4];
+    const int wv = tid >> 6;
+    for (int dir = 0; dir < 2; ++dir) {
+        int4* S = dir ? SB : SF;
+        int base = 0;
+        for (int i0 = 0; i0 < nb; i0 += nt) {
+            const int i = i0 + tid;
+            int b = -1;
+            bool back = false;
+            if (i < nb) {
+                b = dir ? (pos ? c.lorder[nb - 1 - i] : nb - 1 - i) : (pos ? c.lorder[i] : i);
+                const int pb = pos ? pos[b] : b;
+                if (!dir) {
+                    for (int j = pp[b]; j < pp[b + 1] && !back; ++j) {
+                        const int q = c.pred_idx[j];
+                        back = (pos ? pos[q] : q) >= pb;
+                    }
+                }
+                else {
+                    for (int e = c.succ_ptr[b]; e < c.succ_ptr[b + 1] && !back; ++e) {
+                        const int q = c.succ_idx[e];
+                        back = (pos ? pos[q] : q) <= pb;
+                    }
+                }
+            }
+            const uint64_t m = __ballot(back);
+            if ((tid & 63) == 0) s_wave[wv] = __popcll(m);
+            __syncthreads();
+            int at = base;
+            for (int k = 0; k < wv; ++k) at += s_wave[k];
+            at += __popcll(m & ((1ull << (tid & 63)) - 1ull));
+            if (back) reinterpret_cast<int32_t*>(S + 2 * at + 1)[3] = b;
+            for (int k = 0; k < (nt >> 6); ++k) base += s_wave[k];
+            __syncthreads();
+        }
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -427,7 +470,9 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
 // Every phase is monotone on a finite lattice, so any visiting order reaches
 // the same fixed point, and each block's value only moves one way between
 // sweeps: a sweep changed nothing exactly when the popcount of the state is
-// unchanged.  Outputs derived from the state are written by edge-parallel
+// unchanged.  After a sweep that changed something, re-evaluating the blocks
+// that read a neighbour not yet visited in the sweep tells whether the next
+// sweep would change anything (see `settled`), which saves the confirming sweep.  Outputs derived from the state are written by edge-parallel
 // passes after the phase (no iteration).
 typedef uint64_t u64;
 #define CAS __attribute__((address_space(4)))
@@ -986,12 +1031,59 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             step(i + 1, xb, nhb, ndb, xa, nha, nda);
         }
     };
+    bool recheck = false;   // the transfer functions run for the re-check: every state from the rows
     // a neighbour beyond the first two, at compute time (g = the current step)
     auto extra = [&](const Rows& S, int b, int p, int sweep, int g, hw init, hw ph, hw pd, hw& h, hw& d) {
+        if (recheck) { h = settle(S.ldh32(p, hi)); d = settle(S.ldd32(p, hi)); return; }
         const int dd = dist(b, p);
         if (dd == 1) { h = ph; d = pd; }
         else if (dd >= 2 && dd <= RS) { h = cslot_h(g - dd); d = cslot_d(g - dd); }
         else far_val(S, p, dd, g, sweep, init, h, d);
+    };
+    // After a sweep whose states are all in the rows: would the next sweep change nothing?  It
+    // reads the same states as this one except where a block reads a neighbour it has not yet
+    // visited in the sweep (that neighbour's previous-sweep state); so if every block of the
+    // re-check list, evaluated again from the states this sweep left, keeps its state, then by
+    // induction along the walk the next sweep repeats this one and the states are the fixed
+    // point.  Stops at the first block that would change.
+    auto settled = [&](const Rows& S, auto&& pre, auto&& comp) -> bool {
+        const GAS int32_t* L = reinterpret_cast<const GAS int32_t*>(G(BWD ? c.step_b : c.step_f)) + 7;
+        const u64 rowb = (u64)wd * 8u;
+        bool same = true;
+        recheck = true;
+        // (2 LANES entries at a time: the walk runs on lanes 0 .. 2 LANES - 1 only)
+        for (int j0 = 0; j0 < nb && same; j0 += 2 * LANES) {
+            const int lb = j0 + l32 < nb ? L[8 * (size_t)(j0 + l32)] : -1;
+            // (the list is a prefix of the entries)
+            const int n = __popcll(__ballot(lb >= 0) & ((1ull << (2 * LANES)) - 1ull));
+            for (int k = 0; k < n; ++k) {
+                const int b = __builtin_amdgcn_readlane(lb, k);
+                const Rec r = ldrec(REC, b);
+                const int cnt = (int)(r.meta & REC_COUNT);
+                const GAS u64* a[NX];
+                pre((u64)(uint32_t)b * rowb, cnt > 0 ? (u64)(r.e0 & 0x7FFFFFFFu) * rowb : 0ull,
+                    cnt > 1 ? (u64)(r.e1 & 0x7FFFFFFFu) * rowb : 0ull, a);
+                hw x[NX], nh[2], nd[2];
+#pragma unroll
+                for (int k2 = 0; k2 < NX; ++k2)   // (a block with one neighbour has no second edge)
+                    x[k2] = (k2 < NX1 || cnt > 1)
+                                ? reinterpret_cast<const GAS uint32_t*>(reinterpret_cast<const GAS char*>(a[k2]) + hoff)[0]
+                                : 0u;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int p = j ? r.n1 : r.n0;
+                    nh[j] = j < cnt ? S.ldh32(p, hi) : 0u;
+                    nd[j] = j < cnt ? S.ldd32(p, hi) : 0u;
+                }
+                const hw oh = S.ldh32(b, hi), od = S.ldd32(b, hi);
+                hw vh, vd;
+                comp(b, r, x, nh, nd, 0u, 0u, 1, 0, vh, vd);
+                if (__ballot(act && (vh != oh || vd != od))) { same = false; break; }
+            }
+            if (n < 2 * LANES) break;
+        }
+        recheck = false;
+        return same;
     };
     // Run a phase: the compute wavefront sweeps, the helper feeds and stores; false on an error.
     // (init64: the initial state of the lane's word; ident64: the state of a missing neighbour)
@@ -1017,6 +1109,7 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             const bool ch = act && pc != last;
             last = pc;
             if (__ballot(ch) == 0ull) break;
+            if (settled(S, pre, comp)) break;
             if (sweeps >= cap) {
                 if (lane == 0) set_status(c.info, OMPD_E_NOCONVERGE_);
                 good = false;
