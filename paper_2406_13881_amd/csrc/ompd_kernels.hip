@@ -1049,6 +1049,39 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
     auto settled = [&](const Rows& S, auto&& pre, auto&& comp) -> bool {
         const GAS int32_t* L = reinterpret_cast<const GAS int32_t*>(G(BWD ? c.step_b : c.step_f)) + 7;
         const u64 rowb = (u64)wd * 8u;
+        // a listed block with what its evaluation reads: its record, the phase's input rows, its
+        // first two neighbours' states and its own (the next block's loads are issued before
+        // the current one is evaluated)
+        struct Item { int b; Rec r; hw x[NX], nh[2], nd[2], oh, od; };
+        // (rv: the records of the current entries, one per lane)
+        auto load = [&](int b, const Rec& rv, int k, Item& t) {
+            t.b = b;
+            t.r.meta = (uint32_t)__builtin_amdgcn_readlane((int)rv.meta, k);
+            t.r.n0 = __builtin_amdgcn_readlane(rv.n0, k);
+            t.r.n1 = __builtin_amdgcn_readlane(rv.n1, k);
+            t.r.e0 = (uint32_t)__builtin_amdgcn_readlane((int)rv.e0, k);
+            t.r.e1 = (uint32_t)__builtin_amdgcn_readlane((int)rv.e1, k);
+            t.r.ovf = __builtin_amdgcn_readlane(rv.ovf, k);
+            t.r.ci = __builtin_amdgcn_readlane(rv.ci, k);
+            t.r.pad = 0;
+            const int cnt = (int)(t.r.meta & REC_COUNT);
+            const GAS u64* a[NX];
+            pre((u64)(uint32_t)b * rowb, cnt > 0 ? (u64)(t.r.e0 & 0x7FFFFFFFu) * rowb : 0ull,
+                cnt > 1 ? (u64)(t.r.e1 & 0x7FFFFFFFu) * rowb : 0ull, a);
+#pragma unroll
+            for (int k2 = 0; k2 < NX; ++k2)   // (a block with one neighbour has no second edge)
+                t.x[k2] = (k2 < NX1 || cnt > 1)
+                              ? reinterpret_cast<const GAS uint32_t*>(reinterpret_cast<const GAS char*>(a[k2]) + hoff)[0]
+                              : 0u;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int p = j ? t.r.n1 : t.r.n0;
+                t.nh[j] = j < cnt ? S.ldh32(p, hi) : 0u;
+                t.nd[j] = j < cnt ? S.ldd32(p, hi) : 0u;
+            }
+            t.oh = S.ldh32(b, hi);
+            t.od = S.ldd32(b, hi);
+        };
         bool same = true;
         recheck = true;
         // (2 LANES entries at a time: the walk runs on lanes 0 .. 2 LANES - 1 only)
@@ -1056,29 +1089,23 @@ __device__ __forceinline__ void solve_phase(const DevCfg& c, int s0, int nw, int
             const int lb = j0 + l32 < nb ? L[8 * (size_t)(j0 + l32)] : -1;
             // (the list is a prefix of the entries)
             const int n = __popcll(__ballot(lb >= 0) & ((1ull << (2 * LANES)) - 1ull));
-            for (int k = 0; k < n; ++k) {
-                const int b = __builtin_amdgcn_readlane(lb, k);
-                const Rec r = ldrec(REC, b);
-                const int cnt = (int)(r.meta & REC_COUNT);
-                const GAS u64* a[NX];
-                pre((u64)(uint32_t)b * rowb, cnt > 0 ? (u64)(r.e0 & 0x7FFFFFFFu) * rowb : 0ull,
-                    cnt > 1 ? (u64)(r.e1 & 0x7FFFFFFFu) * rowb : 0ull, a);
-                hw x[NX], nh[2], nd[2];
-#pragma unroll
-                for (int k2 = 0; k2 < NX; ++k2)   // (a block with one neighbour has no second edge)
-                    x[k2] = (k2 < NX1 || cnt > 1)
-                                ? reinterpret_cast<const GAS uint32_t*>(reinterpret_cast<const GAS char*>(a[k2]) + hoff)[0]
-                                : 0u;
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int p = j ? r.n1 : r.n0;
-                    nh[j] = j < cnt ? S.ldh32(p, hi) : 0u;
-                    nd[j] = j < cnt ? S.ldd32(p, hi) : 0u;
-                }
-                const hw oh = S.ldh32(b, hi), od = S.ldd32(b, hi);
+            if (n == 0) break;
+            const Rec rv = ldrec_v(REC, lb >= 0 ? lb : 0);
+            // two items used in turn (two blocks per round, so nothing is copied between them and
+            // the next block's loads stay in flight while the current one is evaluated)
+            auto changes = [&](const Item& t) -> bool {
                 hw vh, vd;
-                comp(b, r, x, nh, nd, 0u, 0u, 1, 0, vh, vd);
-                if (__ballot(act && (vh != oh || vd != od))) { same = false; break; }
+                comp(t.b, t.r, t.x, t.nh, t.nd, 0u, 0u, 1, 0, vh, vd);
+                return __ballot(act && (vh != t.oh || vd != t.od)) != 0ull;
+            };
+            Item ia, ib;
+            load(__builtin_amdgcn_readlane(lb, 0), rv, 0, ia);
+            for (int k = 0; k < n; k += 2) {
+                if (k + 1 < n) load(__builtin_amdgcn_readlane(lb, k + 1), rv, k + 1, ib);
+                if (changes(ia)) { same = false; break; }
+                if (k + 1 >= n) break;
+                if (k + 2 < n) load(__builtin_amdgcn_readlane(lb, k + 2), rv, k + 2, ia);
+                if (changes(ib)) { same = false; break; }
             }
             if (n < 2 * LANES) break;
         }
