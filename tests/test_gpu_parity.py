@@ -167,6 +167,47 @@ def test_random_dags_with_loop_entries(ctx, seed):
         assert_same(cfg, got[i], oracle.solve(cfg), "dag %d/%d" % (seed, i))
 
 
+def test_acyclic_cfg_settles_in_one_sweep(ctx):
+    """Without loops no block reads a neighbour it has not visited in the sweep, so the walk's
+    re-check has nothing to evaluate and every phase ends after its first sweep (in id order and
+    with the ids shuffled); the outputs equal the oracle's."""
+    import paper_2406_13881_amd as ompd
+    cfgs = [synth.random_dag(9_100 + j, 30 + 11 * j, 70 + 40 * j) for j in range(6)]
+    cfgs += [synth.permute_blocks(c, 9_200 + j)[0] for j, c in enumerate(cfgs)]
+    got = ctx.analyze_batch(cfgs, flags=ompd.F_SCHED_WALK)
+    for i, cfg in enumerate(cfgs):
+        assert_same(cfg, got[i], oracle.solve(cfg), "acyclic %d" % i)
+        sw = np.asarray(got[i]["sweeps"][:5])
+        assert (sw == 1).all(), (i, sw.tolist())
+
+
+def _loops_with_self_edges(seed, n_vars):
+    """ENTRY, a host loop whose header has two BACK edges (from a device block with a self loop
+    and from a host latch), entered through a loop-entry edge, then a host block and EXIT; random
+    accesses."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    def acc(p):
+        return [v for v in range(n_vars) if rng.random() < p]
+    blocks = [(0, [], []), (0, acc(0.3), acc(0.1)), (1, acc(0.3), acc(0.2)), (0, acc(0.2), acc(0.3)),
+              (0, acc(0.4), []), (0, [], [])]
+    edges = [(0, 1, 2), (1, 2, 0), (2, 2, 1), (2, 1, 1), (2, 3, 0), (3, 1, 1), (1, 4, 0), (4, 5, 0)]
+    return synth.from_edges(blocks, edges, n_vars)[0]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_recheck_with_self_loops_and_two_back_edges(ctx, seed):
+    """Blocks that read a neighbour not yet visited in the sweep (a self loop, a header with two
+    BACK edges) are re-evaluated after each sweep; the phase ends only when none of them would
+    change.  Bit-exact against the oracle on the walk, in id order and shuffled, over 1-3 words."""
+    import paper_2406_13881_amd as ompd
+    cfgs = [_loops_with_self_edges(9_300 + 10 * seed + k, nv) for k, nv in enumerate((5, 64, 130))]
+    cfgs += [synth.permute_blocks(c, 9_400 + k)[0] for k, c in enumerate(cfgs)]
+    got = ctx.analyze_batch(cfgs, flags=ompd.F_SCHED_WALK)
+    for i, cfg in enumerate(cfgs):
+        assert_same(cfg, got[i], oracle.solve(cfg), "loops %d/%d" % (seed, i))
+    _print("self loops seed %d: sweeps %s" % (seed, [g["sweeps"][:5].tolist() for g in got]))
+
+
 def test_structured_irreducible_multiword(ctx):
     """Mid-size structured CFGs with irreducible loop entries, deep nesting
     and 1..9 words of variables (ragged last word), several tiles each."""
