@@ -364,6 +364,65 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
     int4* SF = reinterpret_cast<int4*>(c.step_f);
     int4* SB = reinterpret_cast<int4*>(c.step_b);
     if (lv) {
+        // Re-check lists of the level schedule (what the walk's step entries carry, for levels):
+        // the blocks that read a neighbour whose level is not below their own (a BACK edge into
+        // them, or a self loop), that is a predecessor of a forward phase or a successor of a
+        // backward one.  Each block's level goes to the spare word of its records first.  The
+        // forward list fills c.tmp from the front, the backward one from the back (entry nb
+        // first), each ended by -1; if the two do not fit in its nb + 1 words, c.tmp[0] = -2 and
+        // the level kernels confirm with a sweep instead.
+        const int nlv = c.info[INFO_LEVELS];
+        for (int l = 0; l < nlv; ++l)
+            for (int k = c.loff[l] + tid; k < c.loff[l + 1]; k += nt) {
+                const int b = c.lorder[k];
+                reinterpret_cast<int32_t*>(RF + 2 * b + 1)[3] = l;
+                reinterpret_cast<int32_t*>(RB + 2 * b + 1)[3] = l;
+            }
+        __syncthreads();
+        auto lev = [&](int b) -> int { return reinterpret_cast<const int32_t*>(RF + 2 * b + 1)[3]; };
+        auto back_in = [&](int b, int dir) -> bool {
+            const int lb = lev(b);
+            if (!dir) {
+                for (int j = pp[b]; j < pp[b + 1]; ++j)
+                    if (lev(c.pred_idx[j]) >= lb) return true;
+            }
+            else {
+                for (int e = c.succ_ptr[b]; e < c.succ_ptr[b + 1]; ++e)
+                    if (lev(c.succ_idx[e]) <= lb) return true;
+            }
+            return false;
+        };
+        __shared__ int s_lw[2][4];
+        const int wv = tid >> 6;
+        int cnt2[2] = {0, 0};
+        for (int pass = 0; pass < 2; ++pass) {   // 0: count, 1: write
+            if (pass == 1 && cnt2[0] + cnt2[1] >= nb) {
+                if (tid == 0) c.tmp[0] = -2;
+                break;
+            }
+            int base[2] = {0, 0};
+            for (int b0 = 0; b0 < nb; b0 += nt) {
+                const int b = b0 + tid;
+                const bool f = b < nb && back_in(b, 0), g = b < nb && back_in(b, 1);
+                const uint64_t mf = __ballot(f), mg = __ballot(g);
+                if ((tid & 63) == 0) { s_lw[0][wv] = __popcll(mf); s_lw[1][wv] = __popcll(mg); }
+                __syncthreads();
+                const uint64_t below = (1ull << (tid & 63)) - 1ull;
+                int af = base[0], ag = base[1];
+                for (int k = 0; k < wv; ++k) { af += s_lw[0][k]; ag += s_lw[1][k]; }
+                af += __popcll(mf & below);
+                ag += __popcll(mg & below);
+                if (pass == 1) {
+                    if (f) c.tmp[af] = b;
+                    if (g) c.tmp[nb - ag] = b;
+                }
+                for (int k = 0; k < (nt >> 6); ++k) { base[0] += s_lw[0][k]; base[1] += s_lw[1][k]; }
+                __syncthreads();
+            }
+            if (pass == 0) { cnt2[0] = base[0]; cnt2[1] = base[1]; }
+            else if (tid == 0) { c.tmp[base[0]] = -1; c.tmp[nb - base[1]] = -1; }
+        }
+        __syncthreads();
         // level schedule (no walk steps): the records in level order, the block in the last word,
         // so that a level's positions lead to their records in one load
         for (int k = tid; k < nb; k += nt) {
@@ -1905,6 +1964,30 @@ __device__ __forceinline__ void level_phase(const DevCfg& c, int hc, uint32_t* S
             vd = ad & vm;
         }
     };
+    // After a sweep that changed something: would the next one change nothing?  Only blocks
+    // that read a neighbour whose level is not below their own can see other states in the
+    // next sweep than in this one; the ingest kernel lists them in c.tmp (forward phases from
+    // the front, backward ones from the back, -1 ends a list, c.tmp[0] = -2: no lists).  If
+    // none of them, evaluated against the states in LDS, changes, then level by level the next
+    // sweep repeats this one and the states are the fixed point.
+    auto settled = [&]() -> bool {
+        const GAS int32_t* LST = G(c.tmp);
+        if (LST[0] == -2) return false;
+        bool diff = false;
+        for (int j0 = 0;; j0 += LV_THREADS) {
+            const int idx = BWD ? nb - (j0 + tid) : j0 + tid;
+            const int b = (idx >= 0 && idx <= nb) ? LST[idx] : -1;
+            const u64 endm = __ballot(b < 0);
+            const int t = endm ? (int)__builtin_ctzll(endm) : LV_THREADS;
+            if (tid < t) {
+                hw vh, vd;
+                transfer(b, vh, vd);
+                if (vh != SH[b] || vd != SD[b]) diff = true;
+            }
+            if (__syncthreads_or(diff) || t < LV_THREADS) break;
+        }
+        return !__syncthreads_or(diff);
+    };
     const hw init = (PH == PH_AVE || PH == PH_AVF) ? vm : 0u;
     for (int b = tid; b < nb; b += LV_THREADS) { SH[b] = init; SD[b] = init; }
     __syncthreads();
@@ -1983,6 +2066,7 @@ __device__ __forceinline__ void level_phase(const DevCfg& c, int hc, uint32_t* S
         }
         ++sweeps;
         if (!__syncthreads_or(chg)) break;
+        if (settled()) break;
         if (sweeps >= cap) {
             if (tid == 0) set_status(c.info, OMPD_E_NOCONVERGE_);
             good = false;
