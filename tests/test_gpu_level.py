@@ -79,6 +79,32 @@ def test_level_small_families(ctx):
     _check(ctx, cfgs, "small")
 
 
+def _self_loops_everywhere(seed, n_user, n_vars):
+    """ENTRY, a chain of user blocks each with a self loop (BACK), EXIT; random accesses, some
+    blocks on the device."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    blocks = [(0, [], [])]
+    for _ in range(n_user):
+        blocks.append((int(rng.random() < 0.4), [v for v in range(n_vars) if rng.random() < 0.2],
+                       [v for v in range(n_vars) if rng.random() < 0.1]))
+    blocks.append((0, [], []))
+    edges = [(b, b + 1, 0) for b in range(n_user + 1)] + [(b, b, 1) for b in range(1, n_user + 1)]
+    return synth.from_edges(blocks, edges, n_vars)[0]
+
+
+def test_level_recheck_lists_that_do_not_fit(ctx):
+    """Every user block reads itself through a self loop, so both re-check lists hold every
+    user block and together do not fit in the CFG's scratch words: the level kernels then
+    confirm the fixed point with a sweep.  Outputs equal the oracle's (also on the walk, whose
+    lists have room for every block)."""
+    import paper_2406_13881_amd as ompd
+    cfgs = [_self_loops_everywhere(9_500 + k, n, nv) for k, (n, nv) in enumerate(((3, 5), (40, 64), (300, 130)))]
+    _check(ctx, cfgs, "self loops everywhere")
+    got = ctx.analyze_batch(cfgs, flags=ompd.F_SCHED_WALK)
+    for i, cfg in enumerate(cfgs):
+        assert_same(got[i], oracle.solve(cfg), "self loops everywhere, walk %d" % i)
+
+
 def test_level_config1_in_order_and_shuffled(ctx):
     cfgs = [synth.c1(i) for i in range(1000)]
     cfgs += [synth.permute_blocks(synth.c1(i), 70_000 + i)[0] for i in range(1000)]
