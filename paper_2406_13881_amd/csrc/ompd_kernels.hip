@@ -286,8 +286,9 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
     }
     __syncthreads();
     // Walk order (walk schedule): the caller's ids when every edge other than BACK goes from a
-    // lower to a higher id (the source order a front end emits; the sweeps then converge in loop
-    // depth + 2), else the order of the peel below, in which every such edge goes forward too;
+    // lower to a higher id (the source order a front end emits; the sweeps then reach the fixed
+    // point in loop depth + 1), else the order of the peel below, in which every such edge goes
+    // forward too;
     // then lorder[i] is the block at forward walk position i and loff[b] the position of block b.
     // Levels (level schedule): peel the graph from ENTRY over the edges other than BACK; the
     // blocks of a round form a level.  Blocks left over (a cycle closed by an edge not marked
@@ -531,8 +532,9 @@ ompd_k_prep(const DevCfg* __restrict__ cfgs, int n_cfgs, int32_t* __restrict__ s
 // sweeps: a sweep changed nothing exactly when the popcount of the state is
 // unchanged.  After a sweep that changed something, re-evaluating the blocks
 // that read a neighbour not yet visited in the sweep tells whether the next
-// sweep would change anything (see `settled`), which saves the confirming sweep.  Outputs derived from the state are written by edge-parallel
-// passes after the phase (no iteration).
+// sweep would change anything (see `settled`), which saves the confirming
+// sweep.  Outputs derived from the state are written by edge-parallel passes
+// after the phase (no iteration).
 typedef uint64_t u64;
 #define CAS __attribute__((address_space(4)))
 
